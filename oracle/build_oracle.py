@@ -1,0 +1,28 @@
+"""Build the CPU oracle shared library (test infrastructure only).
+
+    python oracle/build_oracle.py
+
+gcc, -O2, -ffp-contract=off: no fused multiply-add, every operation rounded as
+written in pcpic_oracle.c.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pcpic_oracle.c")
+LIB = os.path.join(HERE, "libpcpic_oracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wextra", "-o", LIB, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

@@ -1,0 +1,196 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` use this module.  It loads ``oracle/libpcpic_oracle.so`` (built by
+``oracle/build_oracle.py``) and keeps every array in NumPy, owned here.
+
+A tube is described by a plain dict with the keys
+``n_cells, length, radius, dt_over_dz, q_over_m, ppc, rho_kind, rho_amp, kappa,
+r_star, knots, fp_bits, flags, capacity`` (missing keys take the defaults below).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcpic_oracle.so")
+
+RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS = 0, 1, 2
+NO_AUTO_INJECT, FREEZE_FIELDS = 1, 2
+ST_CAPACITY, ST_NONFINITE = 1, 2
+
+DEFAULTS = dict(n_cells=1024, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=-1.0,
+                ppc=4.0, rho_kind=RHO_UNIFORM, rho_amp=1.0, kappa=0.0, r_star=10.0,
+                knots=None, fp_bits=32, flags=0, capacity=1 << 16)
+
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi = ctypes.POINTER(ctypes.c_int64)
+
+
+class OrcCfg(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("length", ctypes.c_double),
+                ("radius", ctypes.c_double), ("dt_over_dz", ctypes.c_double),
+                ("q_over_m", ctypes.c_double), ("ppc", ctypes.c_double),
+                ("rho_kind", ctypes.c_int32), ("n_knots", ctypes.c_int32),
+                ("rho_amp", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("r_star", ctypes.c_double), ("knots", _pd),
+                ("fp_bits", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("capacity", ctypes.c_int64)]
+
+
+class OrcState(ctypes.Structure):
+    _fields_ = [("x", _pd), ("u", _pd), ("rho_gj", _pd), ("ez", _pd), ("er", _pd),
+                ("b", _pd), ("j", _pi), ("k", _pd), ("phi", _pd), ("cp", _pd),
+                ("dp", _pd), ("w", _pi), ("n", ctypes.c_int64), ("step", ctypes.c_int64),
+                ("n_injected", ctypes.c_int64), ("n_exit", ctypes.c_int64),
+                ("n_absorb", ctypes.c_int64), ("w0", ctypes.c_int64),
+                ("last_ninj", ctypes.c_int64), ("status", ctypes.c_int64),
+                ("exit_sum_lo", ctypes.c_uint64), ("exit_sum_hi", ctypes.c_int64),
+                ("e_surf", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load (building first if needed) the oracle library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build_oracle  # noqa: F401  (package-relative when imported as oracle.oracle)
+            build_oracle.build()
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        lib.orc_rho_gj.argtypes = [P(OrcCfg), _pd]
+        lib.orc_weights.argtypes = [P(OrcCfg), _pd, ctypes.c_int64, _pi]
+        lib.orc_init.argtypes = [P(OrcCfg), P(OrcState)]
+        lib.orc_inject.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int64, _pd, _pd]
+        lib.orc_step.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int64]
+        lib.orc_gauss.argtypes = [P(OrcCfg), P(OrcState), _pd, _pd]
+        lib.orc_profile.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int32, _pi,
+                                    P(ctypes.c_uint64), _pi, _pd, _pd]
+        for f in ("orc_rho_gj", "orc_weights", "orc_init", "orc_inject", "orc_step",
+                  "orc_gauss", "orc_profile"):
+            getattr(lib, f).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, t=_pd):
+    return a.ctypes.data_as(t)
+
+
+def i128_to_float(lo, hi):
+    """Value of a two-word 128-bit integer (unsigned low word, signed high word)."""
+    return float((int(hi) << 64) + int(lo))
+
+
+class OracleTube:
+    """One tube advanced by the oracle.  All arrays are NumPy, owned here."""
+
+    def __init__(self, cfg=None, **kw):
+        c = dict(DEFAULTS)
+        c.update(cfg or {})
+        c.update(kw)
+        self.cfg = c
+        self.lib = load()
+        N, cap = int(c["n_cells"]), int(c["capacity"])
+        self.N = N
+        knots = c.get("knots")
+        self._knots = None if knots is None else np.ascontiguousarray(knots, dtype=np.float64)
+        self.ccfg = OrcCfg(N, c["length"], c["radius"], c["dt_over_dz"], c["q_over_m"], c["ppc"],
+                           int(c["rho_kind"]), 0 if self._knots is None else len(self._knots),
+                           c["rho_amp"], c["kappa"], c["r_star"],
+                           None if self._knots is None else _ptr(self._knots),
+                           int(c["fp_bits"]), int(c["flags"]), cap)
+        self._x = np.zeros(cap, np.float64)
+        self._u = np.zeros(cap, np.float64)
+        self.rho_gj = np.zeros(N + 1)
+        self.ez = np.zeros(N)
+        self.er = np.zeros(N + 1)
+        self.b = np.zeros(N)
+        self.j = np.zeros(N, np.int64)
+        self.k = np.zeros(N)
+        self.phi = np.zeros(N + 1)
+        self._cp = np.zeros(N + 1)
+        self._dp = np.zeros(N + 1)
+        self.w = np.zeros(N + 1, np.int64)
+        self.st = OrcState(_ptr(self._x), _ptr(self._u), _ptr(self.rho_gj), _ptr(self.ez),
+                           _ptr(self.er), _ptr(self.b), _ptr(self.j, _pi), _ptr(self.k),
+                           _ptr(self.phi), _ptr(self._cp), _ptr(self._dp), _ptr(self.w, _pi))
+        rc = self.lib.orc_init(ctypes.byref(self.ccfg), ctypes.byref(self.st))
+        if rc != 0:
+            raise ValueError(f"orc_init rejected the configuration (rc={rc})")
+
+    # -- operations ---------------------------------------------------------
+    def inject(self, x, u):
+        x = np.ascontiguousarray(x, np.float64)
+        u = np.ascontiguousarray(u, np.float64)
+        rc = self.lib.orc_inject(ctypes.byref(self.ccfg), ctypes.byref(self.st), len(x),
+                                 _ptr(x), _ptr(u))
+        if rc != 0:
+            raise ValueError(f"orc_inject failed (rc={rc})")
+
+    def step(self, n=1):
+        rc = self.lib.orc_step(ctypes.byref(self.ccfg), ctypes.byref(self.st), int(n))
+        if rc != 0:
+            raise ValueError(f"orc_step failed (rc={rc})")
+
+    def gauss(self):
+        g = np.zeros(self.N + 1)
+        gm = ctypes.c_double(0.0)
+        self.lib.orc_gauss(ctypes.byref(self.ccfg), ctypes.byref(self.st), _ptr(g), ctypes.byref(gm))
+        return g, gm.value
+
+    def weights(self):
+        w = np.zeros(self.N + 1, np.int64)
+        self.lib.orc_weights(ctypes.byref(self.ccfg), _ptr(self._x), self.st.n, _ptr(w, _pi))
+        return w
+
+    def profile(self, nb):
+        cnt = np.zeros(nb, np.int64)
+        lo = np.zeros(nb, np.uint64)
+        hi = np.zeros(nb, np.int64)
+        mn = np.zeros(nb)
+        mx = np.zeros(nb)
+        self.lib.orc_profile(ctypes.byref(self.ccfg), ctypes.byref(self.st), nb, _ptr(cnt, _pi),
+                             lo.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _ptr(hi, _pi),
+                             _ptr(mn), _ptr(mx))
+        return cnt, lo, hi, mn, mx
+
+    def rho_gj_of(self):
+        r = np.zeros(self.N + 1)
+        self.lib.orc_rho_gj(ctypes.byref(self.ccfg), _ptr(r))
+        return r
+
+    # -- state ----------------------------------------------------------------
+    @property
+    def n(self):
+        return self.st.n
+
+    @property
+    def x(self):
+        return self._x[: self.st.n]
+
+    @property
+    def u(self):
+        return self._u[: self.st.n]
+
+    @property
+    def counters(self):
+        s = self.st
+        return dict(step=s.step, n_alive=s.n, n_injected=s.n_injected, n_exit=s.n_exit,
+                    n_absorb=s.n_absorb, w0=s.w0, last_ninj=s.last_ninj, status=s.status,
+                    exit_sum_lo=s.exit_sum_lo, exit_sum_hi=s.exit_sum_hi, e_surf=s.e_surf)
+
+    def exit_gamma_sum(self):
+        return i128_to_float(self.st.exit_sum_lo, self.st.exit_sum_hi) / 2.0 ** 32
+
+    @property
+    def dz(self):
+        return self.cfg["length"] / self.N
+
+    @property
+    def macro_charge(self):
+        return self.rho_gj[0] * self.dz / self.cfg["ppc"]

@@ -1,0 +1,117 @@
+/*
+ * pcpic_oracle.h -- plain FP64 CPU oracle of the 1D polar-cap PIC time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the slow, serial, obviously-correct
+ * definition that the GPU library is checked against.  Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header or constant with the GPU library.
+ *
+ * Method (Barzilay, "Full simulation of the open field lines above pulsar's
+ * polar cap - Part I"): a conducting tube of radius R along the field line,
+ * electrons pushed in E_z by eq. (1), linear weighting between particles and
+ * grid (sec. 2, PIC cycle of Fig. A), the transverse-reduced Maxwell system of
+ * eq. (3) advanced by leap-frog, fields started from the Poisson problem of
+ * eq. (4) with the boundary conditions stated under it, and space-charge-
+ * limited electron injection at the base (sec. 2).  The Goldreich-Julian
+ * background is the flat form of eq. (5) with i = 0, or the frame-dragging
+ * form of eqs. (6)-(7) with alpha = f = H = 1 and the sin(i) term dropped.
+ *
+ * Discretisation (a reading; the paper gives no discrete scheme):
+ *   positions in cell units x = z/dz in [0, N); nodes x = i carry phi, E_r,
+ *   rho_GJ and the integer CIC weight W_i; faces x = i + 1/2 carry E_z, B_phi
+ *   and the integer current J_i.  x and E live at integer time levels, u = gamma*beta,
+ *   B_phi and J at half levels.  Weights are fixed point with P fraction bits.
+ */
+#ifndef PCPIC_ORACLE_H
+#define PCPIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORC_RHO_UNIFORM = 0,    /* rho_GJ = -A                      (eq. 5, i = 0, (R_star/r)^3 dropped) */
+    ORC_RHO_FRAME_DRAG = 1, /* rho_GJ = -A (1 - kappa eta^-3)   (eqs. 6-7, alpha = f = H = 1)    */
+    ORC_RHO_KNOTS = 2       /* rho_GJ = -theta(z) (1 - kappa eta^-3), theta piecewise linear      */
+};
+
+enum {
+    ORC_NO_AUTO_INJECT = 1u, /* skip the SCLF injection                                  */
+    ORC_FREEZE_FIELDS = 2u   /* skip the Maxwell update: fields stay as they are           */
+};
+
+enum {
+    ORC_ST_CAPACITY = 1,     /* injection wanted more particles than the capacity allows */
+    ORC_ST_NONFINITE = 2     /* a momentum or position became non-finite (particle removed) */
+};
+
+typedef struct orc_cfg {
+    int64_t n_cells;      /* N                                                    */
+    double length;        /* L, tube length                                       */
+    double radius;        /* R, tube radius                                       */
+    double dt_over_dz;    /* c dt / dz, must be < 1                                */
+    double q_over_m;      /* electron charge-to-mass ratio (negative)             */
+    double ppc;           /* macro-particles per base cell-charge                 */
+    int32_t rho_kind;     /* ORC_RHO_*                                            */
+    int32_t n_knots;      /* knot count for ORC_RHO_KNOTS (>= 2)                  */
+    double rho_amp;       /* A                                                    */
+    double kappa;         /* frame-dragging strength, omega/Omega at eta = 1      */
+    double r_star;        /* star radius R_*                                      */
+    const double *knots;  /* theta_k, k = 0..n_knots-1, uniform over [0, L]        */
+    int32_t fp_bits;      /* P, fixed-point fraction bits of the weights          */
+    uint32_t flags;       /* ORC_NO_AUTO_INJECT | ORC_FREEZE_FIELDS               */
+    int64_t capacity;     /* particle array capacity                              */
+} orc_cfg;
+
+/* All arrays are owned by the caller; the oracle never allocates them. */
+typedef struct orc_state {
+    double *x;            /* [capacity] positions, cell units                    */
+    double *u;            /* [capacity] momenta u = gamma*beta                    */
+    double *rho_gj;       /* [N+1] background charge density at nodes            */
+    double *ez;           /* [N]   E_z at faces                                  */
+    double *er;           /* [N+1] E_r at nodes                                  */
+    double *b;            /* [N]   B_phi at faces                                */
+    int64_t *j;           /* [N]   fixed-point current of the last step          */
+    double *k;            /* [N]   kick array (q/m) dt E_z                       */
+    double *phi;          /* [N+1] potential (Poisson scratch / output)          */
+    double *cp;           /* [N+1] Thomas scratch                                */
+    double *dp;           /* [N+1] Thomas scratch                                */
+    int64_t *w;           /* [N+1] CIC node weights (Poisson / diagnostics)      */
+    int64_t n;            /* live particles                                      */
+    int64_t step;         /* completed steps                                     */
+    int64_t n_injected;   /* particles injected by the SCLF rule so far          */
+    int64_t n_exit;       /* particles that left through x = N                   */
+    int64_t n_absorb;     /* particles absorbed by the star (x < 0)              */
+    int64_t w0;           /* node-0 weight tally of the last step                */
+    int64_t last_ninj;    /* injected in the last step                           */
+    int64_t status;       /* ORC_ST_* bits                                       */
+    uint64_t exit_sum_lo; /* 128-bit sum of rint(gamma * 2^32) over exits        */
+    int64_t exit_sum_hi;
+    double e_surf;        /* surface field after the last step                   */
+} orc_state;
+
+/* Background charge density at the N+1 nodes. */
+int orc_rho_gj(const orc_cfg *cfg, double *rho_gj);
+/* CIC node weights of the first n particles, w[N+1] overwritten. */
+int orc_weights(const orc_cfg *cfg, const double *x, int64_t n, int64_t *w);
+/* Fill rho_gj and solve eq. (4) with the charge of the live particles; set
+ * E_z, E_r from phi, B_phi = 0, J = 0.  Particles may be preloaded (st->n). */
+int orc_init(const orc_cfg *cfg, orc_state *st);
+/* Append particles; before the first step the fields are solved again. */
+int orc_inject(const orc_cfg *cfg, orc_state *st, int64_t n, const double *x, const double *u);
+/* Advance n_steps PIC cycles. */
+int orc_step(const orc_cfg *cfg, orc_state *st, int64_t n_steps);
+/* Discrete Gauss residual at nodes 1..N-1 into g[N+1] (g[0] = g[N] = 0);
+ * returns max |G_i| / (4 pi max|rho_GJ|) in *gmax. */
+int orc_gauss(const orc_cfg *cfg, orc_state *st, double *g, double *gmax);
+/* Signed-gamma profile: sign(u) gamma binned in x over nb uniform bins.
+ * Sums are 128-bit fixed point in units of 2^-32 (lo/hi words). */
+int orc_profile(const orc_cfg *cfg, const orc_state *st, int32_t nb, int64_t *count,
+                uint64_t *sum_lo, int64_t *sum_hi, double *gmin, double *gmax);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
