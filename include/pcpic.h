@@ -1,0 +1,226 @@
+/*
+ * pcpic.h -- C ABI of the MI355X (gfx950) polar-cap PIC library.
+ *
+ * One time step of the 1D particle-in-cell model of the open field lines above
+ * a pulsar's polar cap (Barzilay, "Full simulation of the open field lines above
+ * pulsar's polar cap - Part I", sec. 2): electrons in a conducting tube of
+ * radius R are pushed along z by E_z (eq. 1), their charge and current are
+ * weighted linearly to the grid (sec. 2, Fig. A), the transverse-reduced
+ * Maxwell system (eq. 3, d/dr -> 1/R) is advanced by leap-frog, the fields
+ * start from the Poisson problem of eq. (4) with phi = 0 at the star and
+ * phi' = 0 at the tube end, and electrons are injected at the base while the
+ * Goldreich-Julian charge there (eq. 5, or eqs. 6-7 with frame dragging) is
+ * not compensated (space-charge-limited flow, sec. 2).
+ *
+ * Units (sec. 3): c = 1; lengths in the caller's unit (normally R = 1).
+ * Grid: N cells of width dz = L/N.  Particle positions are in cell units
+ * x = z/dz in [0, N).  Nodes x = i (i = 0..N) carry phi, E_r and rho_GJ;
+ * faces x = i + 1/2 (i = 0..N-1) carry E_z, B_phi and the current.
+ * x and E live at integer time levels; u = gamma*beta and B_phi at half levels.
+ *
+ * Conventions of every entry point:
+ *  - Plain C types only.  Pointers marked "host" are ordinary CPU memory, read
+ *    or written during the call; pointers marked "device" are HIP device memory.
+ *  - The caller owns the device workspace and the HIP stream.  The library
+ *    never allocates or frees device memory; it carves the workspace.  The
+ *    handle itself is a small host object freed by pic_destroy.
+ *  - Every call returns a pic_status (0 = PIC_OK).  On failure nothing has been
+ *    enqueued and pic_last_error() (per thread) describes the reason.
+ *  - pic_step only enqueues work; device-side conditions (capacity overflow,
+ *    non-finite momenta) are latched in a device status word and reported by
+ *    the next synchronising call (pic_diagnostics, pic_sync, pic_read_*).
+ *  - A handle must not be used from two threads at once.
+ */
+#ifndef PCPIC_H
+#define PCPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCPIC_ABI_VERSION 1
+
+typedef int32_t pic_status;
+enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,     /* invalid argument or parameter                         */
+    PIC_EWORKSPACE = -2, /* workspace missing, too small or misaligned            */
+    PIC_ECAPACITY = -3,  /* particle capacity exceeded (host-detected)            */
+    PIC_ENONFINITE = -4, /* non-finite input particle                             */
+    PIC_ECFL = -5,       /* dt_over_dz not in (0, 1)                              */
+    PIC_EDEVICE = -6,    /* a HIP runtime call failed                             */
+    PIC_ESTATE = -7,     /* call not allowed in the handle's current state        */
+    PIC_EABI = -8,       /* pic_params.abi_version != PCPIC_ABI_VERSION            */
+    PIC_EDEVSTATUS = -9  /* the device latched a status bit (see pic_diag.status) */
+};
+
+/* Device status bits (latched; reported in pic_diag.status). */
+enum {
+    PIC_ST_CAPACITY = 1,  /* SCLF injection was clipped at the capacity            */
+    PIC_ST_NONFINITE = 2  /* a particle's u or x became non-finite; it was removed */
+};
+
+/* Arithmetic of the particle push. */
+enum {
+    PIC_FP64 = 0          /* x, u in FP64; bit-identical to the FP64 CPU oracle    */
+};
+
+/* Goldreich-Julian background (sec. 2, eqs. 5-7), eta = 1 + z/R_*. */
+enum {
+    PIC_RHO_UNIFORM = 0,    /* -A: eq. (5) with i = 0 and (R_star/r)^3 dropped            */
+    PIC_RHO_FRAME_DRAG = 1, /* -A (1 - kappa/eta^3): eq. (6), Omega -> Omega - omega,
+                               omega from eq. (7), alpha = f = H = 1, sin(i) term dropped */
+    PIC_RHO_KNOTS = 2       /* -theta(z)(1 - kappa/eta^3), theta piecewise linear on
+                               n_knots uniform knots over [0, L]                          */
+};
+
+/* pic_params.flags */
+enum {
+    PIC_NO_AUTO_INJECT = 1u, /* no SCLF injection (E_surf is still computed)         */
+    PIC_FREEZE_FIELDS = 2u   /* skip the Maxwell update; fields keep their values     */
+};
+
+/* Tube description.  Copied by pic_init; the knot array is copied too. */
+typedef struct pic_params {
+    int32_t abi_version;      /* must be PCPIC_ABI_VERSION                                  */
+    int32_t precision;        /* PIC_FP64                                                   */
+    int64_t n_cells;          /* N >= 2                                                     */
+    double length;            /* L > 0                                                      */
+    double radius;            /* R > 0                                                      */
+    double dt_over_dz;        /* c dt/dz in (0, 1); 0.5 in every standard configuration     */
+    double q_over_m;          /* electron charge-to-mass ratio (negative); sets omega_p     */
+    double ppc;               /* macro-particles per base cell-charge:
+                                 macro charge q_m = rho_GJ(0) dz / ppc                      */
+    int32_t rho_kind;         /* PIC_RHO_*                                                  */
+    int32_t n_knots;          /* >= 2 for PIC_RHO_KNOTS, else ignored                       */
+    double rho_amp;           /* A                                                          */
+    double kappa;             /* omega/Omega at the surface (eq. 7): 0.4 r_g/R_*             */
+    double r_star;            /* R_* (> 0 for FRAME_DRAG and KNOTS)                          */
+    const double *knots;      /* host, n_knots values theta_k (PIC_RHO_KNOTS)               */
+    int32_t fp_bits;          /* P, fraction bits of the fixed-point weights: 16..36         */
+    int32_t sort_every;       /* cell sort + compaction period in steps (0 = never)          */
+    int64_t capacity;         /* particle capacity (live + not yet compacted)                */
+    uint32_t flags;           /* PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS                      */
+    int32_t max_bins;         /* largest signed-gamma profile pic_diagnostics may request    */
+} pic_params;
+
+typedef struct pic_handle pic_handle;
+
+/* Diagnostics request (sec. 3: gamma(z) with returning electrons negative,
+ * and the E_z, E_r, B_phi profiles). */
+typedef struct pic_diag_req {
+    int32_t n_bins;       /* bins of the signed-gamma profile over [0, N); 0 = none, <= max_bins */
+    int32_t want_gauss;   /* compute the discrete Gauss residual at nodes 1..N-1              */
+} pic_diag_req;
+
+/* Diagnostics result.  Array pointers are host memory provided by the caller
+ * (any may be NULL to skip it); the library fills the scalars. */
+typedef struct pic_diag {
+    int64_t step;          /* completed steps                                              */
+    int64_t n_alive;       /* live particles                                               */
+    int64_t n_slots;       /* occupied slots (live + removed since the last compaction)    */
+    int64_t n_injected;    /* particles injected by the SCLF rule so far                   */
+    int64_t n_exit;        /* particles that left through z = L                            */
+    int64_t n_absorb;      /* particles that returned to the star                          */
+    int64_t last_n_inj;    /* injected at the end of the last step                         */
+    int64_t w0;            /* node-0 fixed-point weight of the last step                   */
+    int64_t status;        /* latched PIC_ST_* bits                                        */
+    double e_surf;         /* surface field of the last step (node-0 Gauss law, before injection) */
+    uint64_t exit_sum_lo;  /* sum over exits of rint(gamma 2^32), 128-bit two's complement */
+    int64_t exit_sum_hi;
+    double exit_gamma_sum; /* the same sum / 2^32 as a double                              */
+    double gauss_max;      /* max |G_i| / (4 pi max|rho_GJ|), nodes 1..N-1 (want_gauss)    */
+    double *ez;            /* [N]   E_z at faces                                           */
+    double *er;            /* [N+1] E_r at nodes                                           */
+    double *b_phi;         /* [N]   B_phi at faces                                         */
+    double *rho_gj;        /* [N+1] background density at nodes                            */
+    int64_t *j_last;       /* [N]   fixed-point current of the last step                   */
+    int64_t *weights;      /* [N+1] fixed-point CIC node weights of the live particles     */
+    double *gauss;         /* [N+1] Gauss residual (0 at nodes 0 and N)                     */
+    int64_t *prof_count;   /* [n_bins] particles per bin                                   */
+    double *prof_mean;     /* [n_bins] mean of sign(u) gamma (fixed-point sum / count)     */
+    double *prof_min;      /* [n_bins] min of sign(u) gamma                                */
+    double *prof_max;      /* [n_bins] max of sign(u) gamma                                */
+    uint64_t *prof_sum_lo; /* [n_bins] raw 128-bit sums, units of 2^-32                    */
+    int64_t *prof_sum_hi;  /* [n_bins]                                                     */
+} pic_diag;
+
+/* Library ABI version (PCPIC_ABI_VERSION of the build). */
+int32_t pic_abi_version(void);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *pic_last_error(void);
+
+/* Device workspace bytes pic_init needs for these parameters, or 0 if the
+ * parameters are invalid (then pic_last_error says why).  The workspace holds
+ * two particle buffers of `capacity` slots (16 B each, FP64), the field arrays
+ * twice (leap-frog ping-pong), the current, kick and Poisson arrays, the
+ * counters and the sort and profile scratch. */
+size_t pic_workspace_bytes(const pic_params *p);
+
+/* Create a tube: validate p, carve the workspace (device, 256-byte aligned,
+ * ws_bytes >= pic_workspace_bytes(p)), fill rho_GJ and solve eq. (4) for the
+ * empty tube on the device, set E_z = -dphi/dz, E_r = phi/R, B_phi = 0
+ * (sec. 2: the tube starts empty, B_phi(0) = 0).  hip_stream is a hipStream_t
+ * (NULL = the null stream); all work of this handle is ordered on it.
+ * Errors: PIC_EABI, PIC_EINVAL, PIC_ECFL, PIC_EWORKSPACE, PIC_EDEVICE. */
+pic_status pic_init(const pic_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream,
+                    pic_handle **out);
+
+/* Append n particles (positions x in cell units, 0 <= x < N; momenta u finite).
+ * mem: 0 = host arrays, 1 = device arrays.  Before the first step the fields are
+ * solved again from eq. (4) with the charge of all loaded particles (warm start);
+ * afterwards the particles are added as they are.  Synchronises the stream.
+ * Errors: PIC_EINVAL (range), PIC_ENONFINITE, PIC_ECAPACITY, PIC_EDEVICE. */
+pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u, int32_t mem);
+
+/* Enqueue n_steps PIC cycles on the stream and return.  Each cycle: push and
+ * charge-conserving deposit, boundary removal, leap-frog field update, SCLF
+ * injection; every sort_every cycles a cell sort that drops removed particles.
+ * Errors: PIC_EINVAL (n_steps < 0), PIC_EDEVICE. */
+pic_status pic_step(pic_handle *h, int64_t n_steps);
+
+/* Synchronise the stream and fill *out (scalars always; arrays where non-NULL).
+ * Returns PIC_EDEVSTATUS if a status bit is latched (out is still filled). */
+pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out);
+
+/* Synchronise and copy the live particles, in slot order, to host arrays of
+ * `cap` entries; *n_out receives the live count (PIC_ECAPACITY if cap is short). */
+pic_status pic_read_particles(pic_handle *h, double *x, double *u, int64_t cap, int64_t *n_out);
+
+/* Overwrite the fields from host arrays (any may be NULL to keep it): E_z [N],
+ * E_r [N+1], B_phi [N]; the kick array follows E_z.  For tests that start from
+ * a prescribed field.  Synchronises the stream. */
+pic_status pic_write_fields(pic_handle *h, const double *ez, const double *er, const double *b_phi);
+
+/* Per-kernel device time of a stepping run. */
+typedef struct pic_timing {
+    double push_ms;         /* summed device time of the particle push + deposit kernels */
+    double field_ms;        /* summed device time of the field update + injection kernels */
+    double sort_ms;         /* summed device time of the cell sort / compaction sequences */
+    double total_ms;        /* device time from the first to the last kernel              */
+    int64_t push_launches;
+    int64_t field_launches;
+    int64_t sort_launches;
+    int64_t particle_steps; /* sum over the steps of the slots the push visited           */
+} pic_timing;
+
+/* pic_step(h, n_steps) with a HIP event recorded on the handle's stream around
+ * every kernel group; synchronises at the end and fills *out.  Used to measure
+ * per-kernel durations; the events add a little launch overhead.
+ * Errors: as pic_step, plus PIC_EDEVICE for event failures. */
+pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out);
+
+/* Synchronise the stream; PIC_EDEVSTATUS if a status bit is latched. */
+pic_status pic_sync(pic_handle *h);
+
+/* Release the handle (the caller still owns workspace and stream). */
+pic_status pic_destroy(pic_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCPIC_H */

@@ -1,0 +1,262 @@
+"""ctypes binding of ``libpcpic.so`` (the C ABI in ``include/pcpic.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+gfx950 kernels.  PyTorch supplies the device workspace (a ``uint8`` tensor)
+and the HIP stream; nothing here computes on the host.
+
+A tube is described by a dict with the keys of ``pic_params`` (see
+``DEFAULTS``); the same dict drives the CPU oracle in the tests.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpcpic.so")
+
+ABI_VERSION = 1
+FP64 = 0
+RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS = 0, 1, 2
+NO_AUTO_INJECT, FREEZE_FIELDS = 1, 2
+ST_CAPACITY, ST_NONFINITE = 1, 2
+
+STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_EWORKSPACE", -3: "PIC_ECAPACITY",
+                -4: "PIC_ENONFINITE", -5: "PIC_ECFL", -6: "PIC_EDEVICE", -7: "PIC_ESTATE",
+                -8: "PIC_EABI", -9: "PIC_EDEVSTATUS"}
+
+DEFAULTS = dict(precision=FP64, n_cells=1024, length=10.0, radius=1.0, dt_over_dz=0.5,
+                q_over_m=-1.0, ppc=4.0, rho_kind=RHO_UNIFORM, rho_amp=1.0, kappa=0.0,
+                r_star=10.0, knots=None, fp_bits=32, sort_every=0, capacity=1 << 16, flags=0,
+                max_bins=1024)
+
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi = ctypes.POINTER(ctypes.c_int64)
+_pu = ctypes.POINTER(ctypes.c_uint64)
+
+
+class PicParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n_cells", ctypes.c_int64), ("length", ctypes.c_double),
+                ("radius", ctypes.c_double), ("dt_over_dz", ctypes.c_double),
+                ("q_over_m", ctypes.c_double), ("ppc", ctypes.c_double),
+                ("rho_kind", ctypes.c_int32), ("n_knots", ctypes.c_int32),
+                ("rho_amp", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("r_star", ctypes.c_double), ("knots", _pd),
+                ("fp_bits", ctypes.c_int32), ("sort_every", ctypes.c_int32),
+                ("capacity", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("max_bins", ctypes.c_int32)]
+
+
+class PicDiagReq(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("want_gauss", ctypes.c_int32)]
+
+
+class PicDiag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("n_alive", ctypes.c_int64), ("n_slots", ctypes.c_int64),
+                ("n_injected", ctypes.c_int64), ("n_exit", ctypes.c_int64),
+                ("n_absorb", ctypes.c_int64), ("last_n_inj", ctypes.c_int64),
+                ("w0", ctypes.c_int64), ("status", ctypes.c_int64), ("e_surf", ctypes.c_double),
+                ("exit_sum_lo", ctypes.c_uint64), ("exit_sum_hi", ctypes.c_int64),
+                ("exit_gamma_sum", ctypes.c_double), ("gauss_max", ctypes.c_double),
+                ("ez", _pd), ("er", _pd), ("b_phi", _pd), ("rho_gj", _pd), ("j_last", _pi),
+                ("weights", _pi), ("gauss", _pd), ("prof_count", _pi), ("prof_mean", _pd),
+                ("prof_min", _pd), ("prof_max", _pd), ("prof_sum_lo", _pu), ("prof_sum_hi", _pi)]
+
+
+class PicTiming(ctypes.Structure):
+    _fields_ = [("push_ms", ctypes.c_double), ("field_ms", ctypes.c_double),
+                ("sort_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("push_launches", ctypes.c_int64), ("field_launches", ctypes.c_int64),
+                ("sort_launches", ctypes.c_int64), ("particle_steps", ctypes.c_int64)]
+
+
+# Every symbol include/pcpic.h declares, with its ctypes signature.
+SIGNATURES = {
+    "pic_abi_version": (ctypes.c_int32, []),
+    "pic_last_error": (ctypes.c_char_p, []),
+    "pic_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PicParams)]),
+    "pic_init": (ctypes.c_int32, [ctypes.POINTER(PicParams), ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "pic_inject": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int32]),
+    "pic_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64]),
+    "pic_diagnostics": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(PicDiagReq),
+                                         ctypes.POINTER(PicDiag)]),
+    "pic_read_particles": (ctypes.c_int32, [ctypes.c_void_p, _pd, _pd, ctypes.c_int64, _pi]),
+    "pic_write_fields": (ctypes.c_int32, [ctypes.c_void_p, _pd, _pd, _pd]),
+    "pic_step_timed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(PicTiming)]),
+    "pic_sync": (ctypes.c_int32, [ctypes.c_void_p]),
+    "pic_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load the built library; raise if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1011_6330_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(code, where):
+    if code != 0:
+        raise PicError(code, where, load().pic_last_error().decode())
+
+
+def _ptr(a, t=_pd):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def make_params(cfg=None, **kw):
+    """pic_params from a config dict; returns (struct, knots array kept alive)."""
+    c = dict(DEFAULTS)
+    c.update(cfg or {})
+    c.update(kw)
+    knots = c.get("knots")
+    knots = None if knots is None else np.ascontiguousarray(knots, dtype=np.float64)
+    p = PicParams(ABI_VERSION, int(c["precision"]), int(c["n_cells"]), float(c["length"]),
+                  float(c["radius"]), float(c["dt_over_dz"]), float(c["q_over_m"]), float(c["ppc"]),
+                  int(c["rho_kind"]), 0 if knots is None else len(knots), float(c["rho_amp"]),
+                  float(c["kappa"]), float(c["r_star"]), _ptr(knots), int(c["fp_bits"]),
+                  int(c["sort_every"]), int(c["capacity"]), int(c["flags"]), int(c["max_bins"]))
+    return p, knots, c
+
+
+def workspace_bytes(cfg=None, **kw):
+    p, _k, _c = make_params(cfg, **kw)
+    n = load().pic_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise PicError(-1, "pic_workspace_bytes", load().pic_last_error().decode())
+    return n
+
+
+class Tube:
+    """One tube on the GPU.  The workspace is a torch uint8 tensor on ``device``
+    and all work is ordered on ``stream`` (a torch.cuda.Stream, created at the
+    default priority when not given)."""
+
+    def __init__(self, cfg=None, device="cuda", stream=None, **kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("pcpic.Tube needs a HIP GPU")
+        self.lib = load()
+        self.params, self._knots, self.cfg = make_params(cfg, **kw)
+        self.N = int(self.cfg["n_cells"])
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(self.cfg)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        _check(self.lib.pic_init(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)), "pic_init")
+
+    # -- operations -----------------------------------------------------------
+    def inject(self, x, u):
+        """Append particles from NumPy (host) arrays or torch CUDA float64 tensors."""
+        try:
+            import torch
+            if isinstance(x, torch.Tensor) and x.is_cuda:
+                x = x.contiguous().to(torch.float64)
+                u = u.contiguous().to(torch.float64)
+                self.stream.wait_stream(torch.cuda.current_stream(self.device))
+                _check(self.lib.pic_inject(self._h, x.numel(), ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(u.data_ptr()), 1), "pic_inject")
+                return
+        except ImportError:
+            pass
+        x = np.ascontiguousarray(x, np.float64)
+        u = np.ascontiguousarray(u, np.float64)
+        _check(self.lib.pic_inject(self._h, len(x), x.ctypes.data_as(ctypes.c_void_p),
+                                   u.ctypes.data_as(ctypes.c_void_p), 0), "pic_inject")
+
+    def step(self, n=1):
+        _check(self.lib.pic_step(self._h, int(n)), "pic_step")
+
+    def step_timed(self, n):
+        """Step with per-kernel HIP events on the tube's stream; returns a dict."""
+        t = PicTiming()
+        _check(self.lib.pic_step_timed(self._h, int(n), ctypes.byref(t)), "pic_step_timed")
+        return {k: getattr(t, k) for k, _ in PicTiming._fields_}
+
+    def sync(self):
+        _check(self.lib.pic_sync(self._h), "pic_sync")
+
+    def diagnostics(self, n_bins=0, gauss=False, fields=True, j=False, weights=False, rho=False,
+                    raise_on_status=True):
+        N = self.N
+        d = PicDiag()
+        out = {}
+        if fields:
+            out["ez"], out["er"], out["b_phi"] = np.zeros(N), np.zeros(N + 1), np.zeros(N)
+            d.ez, d.er, d.b_phi = _ptr(out["ez"]), _ptr(out["er"]), _ptr(out["b_phi"])
+        if rho:
+            out["rho_gj"] = np.zeros(N + 1)
+            d.rho_gj = _ptr(out["rho_gj"])
+        if j:
+            out["j_last"] = np.zeros(N, np.int64)
+            d.j_last = _ptr(out["j_last"], _pi)
+        if weights:
+            out["weights"] = np.zeros(N + 1, np.int64)
+            d.weights = _ptr(out["weights"], _pi)
+        if gauss:
+            out["gauss"] = np.zeros(N + 1)
+            d.gauss = _ptr(out["gauss"])
+        if n_bins:
+            for k, dt in (("prof_count", np.int64), ("prof_mean", np.float64), ("prof_min", np.float64),
+                          ("prof_max", np.float64), ("prof_sum_lo", np.uint64), ("prof_sum_hi", np.int64)):
+                out[k] = np.zeros(n_bins, dt)
+            d.prof_count, d.prof_mean = _ptr(out["prof_count"], _pi), _ptr(out["prof_mean"])
+            d.prof_min, d.prof_max = _ptr(out["prof_min"]), _ptr(out["prof_max"])
+            d.prof_sum_lo, d.prof_sum_hi = _ptr(out["prof_sum_lo"], _pu), _ptr(out["prof_sum_hi"], _pi)
+        req = PicDiagReq(int(n_bins), int(bool(gauss)))
+        rc = self.lib.pic_diagnostics(self._h, ctypes.byref(req), ctypes.byref(d))
+        if rc != 0 and (rc != -9 or raise_on_status):
+            _check(rc, "pic_diagnostics")
+        for k in ("step", "n_alive", "n_slots", "n_injected", "n_exit", "n_absorb", "last_n_inj", "w0",
+                  "status", "e_surf", "exit_sum_lo", "exit_sum_hi", "exit_gamma_sum", "gauss_max"):
+            out[k] = getattr(d, k)
+        return out
+
+    def read_particles(self):
+        n = ctypes.c_int64(0)
+        self.lib.pic_read_particles(self._h, None, None, 0, ctypes.byref(n))
+        x, u = np.zeros(n.value), np.zeros(n.value)
+        _check(self.lib.pic_read_particles(self._h, _ptr(x), _ptr(u), n.value, ctypes.byref(n)),
+               "pic_read_particles")
+        return x, u
+
+    def write_fields(self, ez=None, er=None, b_phi=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (ez, er, b_phi)]
+        _check(self.lib.pic_write_fields(self._h, *[_ptr(a) for a in arrs]), "pic_write_fields")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.pic_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h

@@ -1,0 +1,341 @@
+// k_field.hip -- grid kernels: rho_GJ, Poisson initialisation (eq. 4), the
+// leap-frog update of the reduced Maxwell system (eq. 3) fused with the
+// space-charge-limited injection at the base (sec. 2).
+//
+// Every floating-point expression is written with the operand order of the
+// step's definition and compiled with -ffp-contract=off, so the results are
+// bit-identical to an IEEE double evaluation of the same formulas.
+#include <math.h>
+
+#include "pcpic_internal.h"
+#include "wave.h"
+
+namespace pcpic {
+
+__global__ __launch_bounds__(256) void k_rho_gj(Consts c, const double *knots, double *rho,
+                                                DevCounters *ctr)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double a = 0.0;
+    if (i <= c.N) {
+        const double r = rho_node(c, knots, i);
+        rho[i] = r;
+        a = fabs(r);
+    }
+    // max |rho_GJ| for the Gauss normalisation (non-negative doubles order as integers)
+    long long m = wave_max_i64(__builtin_bit_cast(long long, a));
+    if (__lane_id() == 0) atomicMax(&ctr->rho_max_bits, (unsigned long long)m);
+}
+
+// CIC node weights of the live particles (node weight W_i = S_i - S_{i-1}).
+__global__ __launch_bounds__(256) void k_weights(Consts c, const double *__restrict__ X,
+                                                 const DevCounters *ctr, unsigned long long *w)
+{
+    const int64_t n = ctr->n_slots;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t p = base + threadIdx.x;
+        const double x = p < n ? X[p] : -1.0;
+        const bool live = x >= 0.0 && x < (double)c.N;
+        int64_t cell = 0, F = 0;
+        if (live) {
+            const double cd = floor(x);
+            cell = (int64_t)cd;
+            F = (int64_t)rint((x - cd) * c.twoP);
+        }
+        wave_add_keyed(w, cell, c.oneP - F, live);
+        wave_add_keyed(w, cell + 1, F, live);
+    }
+}
+
+// Right-hand side of eq. (4) times dz^2 on nodes 1..N; node N carries the
+// mirror-doubled particle weight (phi' = 0 at the tube end: phi, rho even about N).
+__global__ __launch_bounds__(256) void k_poisson_rhs(Consts c, const int64_t *w, const double *rho_gj,
+                                                     double *rhs)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x + 1;
+    if (i > c.N) return;
+    const int64_t wi = (i == c.N) ? 2 * w[i] : w[i];
+    const double rho = (c.qmP * (double)wi) / c.dz;
+    const double t = rho - rho_gj[i];
+    rhs[i] = -(c.cpois * t);
+}
+
+// Thomas algorithm for phi_{i-1} + bdiag phi_i + phi_{i+1} = rhs_i (row N: 2 phi_{N-1}),
+// phi_0 = 0.  The recurrence is sequential: one lane runs it while the block
+// stages the operands through LDS in chunks so that no load is on the chain.
+constexpr int TH_CHUNK = 2048;
+__global__ __launch_bounds__(256) void k_thomas(Consts c, const double *rhs, double *cp, double *dp,
+                                                double *phi)
+{
+    __shared__ double sa[TH_CHUNK];
+    __shared__ double sb[TH_CHUNK];
+    __shared__ double carry[2];
+    const int64_t N = c.N;
+    if (threadIdx.x == 0) { carry[0] = 0.0; carry[1] = 0.0; }
+    // forward elimination, i = 1..N
+    for (int64_t base = 1; base <= N; base += TH_CHUNK) {
+        const int cnt = (int)((N - base + 1) < TH_CHUNK ? (N - base + 1) : TH_CHUNK);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 256) sa[t] = rhs[base + t];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double pc = carry[0], pd = carry[1];
+            for (int t = 0; t < cnt; ++t) {
+                const int64_t i = base + t;
+                double ci, di;
+                if (i == 1) {
+                    ci = 1.0 / c.bdiag;
+                    di = sa[t] / c.bdiag;
+                } else {
+                    const double a = (i == N) ? 2.0 : 1.0;
+                    const double m = c.bdiag - a * pc;
+                    ci = 1.0 / m;
+                    di = (sa[t] - a * pd) / m;
+                }
+                sa[t] = di;
+                sb[t] = ci;
+                pc = ci;
+                pd = di;
+            }
+            carry[0] = pc;
+            carry[1] = pd;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 256) { dp[base + t] = sa[t]; cp[base + t] = sb[t]; }
+    }
+    __syncthreads();
+    // back substitution, i = N..1
+    if (threadIdx.x == 0) carry[0] = 0.0;
+    for (int64_t top = N; top >= 1; top -= TH_CHUNK) {
+        const int64_t lo = top - TH_CHUNK + 1 > 1 ? top - TH_CHUNK + 1 : 1;
+        const int cnt = (int)(top - lo + 1);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 256) { sa[t] = dp[lo + t]; sb[t] = cp[lo + t]; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double next = carry[0];
+            for (int t = cnt - 1; t >= 0; --t) {
+                const int64_t i = lo + t;
+                const double v = (i == N) ? sa[t] : sa[t] - sb[t] * next;
+                sa[t] = v;
+                next = v;
+            }
+            carry[0] = next;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 256) phi[lo + t] = sa[t];
+    }
+    if (threadIdx.x == 0) phi[0] = 0.0;
+}
+
+// E_z = -dphi/dz at faces, E_r = phi/R at nodes, B_phi = 0, J = 0, kick array.
+__global__ __launch_bounds__(256) void k_fields_from_phi(Consts c, const double *phi, double *ez,
+                                                         double *er, double *b, double *k64,
+                                                         int64_t *j0, int64_t *j1)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i > c.N) return;
+    er[i] = phi[i] / c.R;
+    if (i < c.N) {
+        const double e = -((phi[i + 1] - phi[i]) / c.dz);
+        ez[i] = e;
+        b[i] = 0.0;
+        k64[i] = c.qmdt * e;
+        j0[i] = 0;
+        j1[i] = 0;
+    }
+}
+
+struct FieldArgs {
+    const double *ezo, *ero, *bo;   // E^n, B^{n-1/2}
+    double *ezn, *ern, *bn;         // E^{n+1}, B^{n+1/2}
+    const int64_t *j;               // J^{n+1/2} of this step
+    int64_t *jnext;                 // cleared for the next step
+    double *k64;
+    double *X, *U;                  // current particle buffer (injection)
+    DevCounters *ctr;
+};
+
+// Leap-frog update of eq. (3), one thread per face i (thread N-1 also owns node N):
+//   B_{i+1/2}  <- B - [ (dt/dz)(E_r,i+1 - E_r,i) + (dt/R) E_z,i+1/2 ]
+//   E_r,i      <- E_r,i - (dt/dz)(B_{i+1/2} - B_{i-1/2}),  i = 1..N-1 (E_r,0 unchanged, = 0)
+//   E_r,N      <- E_r,N + 2 (dt/dz) B_{N-1/2}           (B odd about the mirror x = N)
+//   E_z,i+1/2  <- (E_z + (dt/R) B_{i+1/2}) - 4 pi q_m 2^-P J_{i+1/2}
+// The neighbour B_{i-1/2} is recomputed from the old fields with the same
+// expression instead of being exchanged.  Block 0 then applies the SCLF rule.
+__global__ __launch_bounds__(256) void k_field_inject(Consts c, FieldArgs a)
+{
+    __shared__ double s_ez0;
+    __shared__ long long s_base, s_n;
+    const int64_t N = c.N;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool frozen = (c.flags & PIC_FREEZE_FIELDS) != 0;
+    if (i < N) {
+        a.jnext[i] = 0;
+        double ez;
+        if (frozen) {
+            ez = a.ezo[i];
+            a.bn[i] = a.bo[i];
+            a.ern[i] = a.ero[i];
+            if (i == N - 1) a.ern[N] = a.ero[N];
+        } else {
+            const double bi = a.bo[i] - (c.dtdz * (a.ero[i + 1] - a.ero[i]) + c.dtR * a.ezo[i]);
+            a.bn[i] = bi;
+            if (i >= 1) {
+                const double bm = a.bo[i - 1] - (c.dtdz * (a.ero[i] - a.ero[i - 1]) + c.dtR * a.ezo[i - 1]);
+                a.ern[i] = a.ero[i] - c.dtdz * (bi - bm);
+            } else {
+                a.ern[0] = a.ero[0];
+            }
+            if (i == N - 1) a.ern[N] = a.ero[N] + c.tw * bi;
+            ez = (a.ezo[i] + c.dtR * bi) - c.c4 * (double)a.j[i];
+        }
+        a.ezn[i] = ez;
+        a.k64[i] = c.qmdt * ez;
+        if (i == 0) s_ez0 = ez;
+    }
+    if (blockIdx.x != 0) return;
+    __syncthreads();
+    DevCounters *ctr = a.ctr;
+    if (threadIdx.x == 0) {
+        // surface field from the node-0 Gauss law over the half cell [0, dz/2]
+        const int64_t w0 = ctr->w0;
+        const double t1 = c.qmP * (double)w0;
+        const double t2 = c.rho0 * c.hdz;
+        const double es = s_ez0 - c.fourpi * (t1 - t2);
+        int64_t ninj = 0;
+        if (!(c.flags & PIC_NO_AUTO_INJECT)) {
+            const double ratio = es / c.fqm;
+            if (ratio > 0.0) {
+                const double nf = floor(ratio);
+                const int64_t avail = c.cap - ctr->n_slots;
+                if (nf > (double)avail) {
+                    ninj = avail;
+                    ctr->status |= PIC_ST_CAPACITY;
+                } else {
+                    ninj = (int64_t)nf;
+                }
+            }
+        }
+        s_base = ctr->n_slots;
+        s_n = ninj;
+        ctr->n_slots += ninj;
+        ctr->n_injected += ninj;
+        ctr->last_ninj = ninj;
+        ctr->e_surf = es;
+        ctr->w0_last = w0;
+        ctr->w0 = 0;
+        ctr->step += 1;
+    }
+    __syncthreads();
+    const long long base = s_base, n = s_n;
+    for (long long p = threadIdx.x; p < n; p += 256) {
+        a.X[base + p] = 0.0;   // electrons leave the surface at rest
+        a.U[base + p] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_i64(int64_t *p, int64_t n, int64_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Kick array from E_z (after the caller overwrote the fields).
+__global__ __launch_bounds__(256) void k_kick(Consts c, const double *ez, double *k64)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < c.N) k64[i] = c.qmdt * ez[i];
+}
+
+// Check appended particles in slots [base, base + n): 0 <= x < N and u finite.
+__global__ __launch_bounds__(256) void k_check_append(Consts c, const double *X, const double *U, int64_t base,
+                                                      int64_t n, DevCounters *ctr)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        const double x = X[base + i], u = U[base + i];
+        bad = !(x >= 0.0 && x < (double)c.N) || !isfinite(u);
+    }
+    const int64_t nb = wave_sum_i64(bad ? 1 : 0);
+    if (__lane_id() == 0 && nb) atomicAdd((unsigned long long *)&ctr->bad_inputs, (unsigned long long)nb);
+}
+
+// Commit n appended particles (slots [n_slots, n_slots + n)) unless any failed the check.
+__global__ void k_commit_append(DevCounters *ctr, int64_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && ctr->bad_inputs == 0) {
+        ctr->n_slots += n;
+        ctr->n_alive += n;
+    }
+}
+
+static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+hipError_t launch_rho_gj(pic_handle *h)
+{
+    const Consts &c = h->c;
+    hipLaunchKernelGGL(k_rho_gj, dim3(grid_for(c.N + 1, 256)), dim3(256), 0, h->stream, c, h->ws.knots,
+                       h->ws.rho_gj, h->ws.ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(pic_handle *h, int64_t *w_out)
+{
+    const Consts &c = h->c;
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(c.N + 1, 256)), dim3(256), 0, h->stream, w_out,
+                       c.N + 1, (int64_t)0);
+    hipLaunchKernelGGL(k_weights, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, h->ws.x[h->pbuf],
+                       h->ws.ctr, (unsigned long long *)w_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_poisson(pic_handle *h)
+{
+    const Consts &c = h->c;
+    Workspace &w = h->ws;
+    hipError_t e = launch_weights(h, w.w);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_poisson_rhs, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, w.w,
+                       w.rho_gj, w.rhs);
+    hipLaunchKernelGGL(k_thomas, dim3(1), dim3(256), 0, h->stream, c, w.rhs, w.cp, w.dp, w.phi);
+    const int f = h->fbuf;
+    hipLaunchKernelGGL(k_fields_from_phi, dim3(grid_for(c.N + 1, 256)), dim3(256), 0, h->stream, c,
+                       w.phi, w.ez[f], w.er[f], w.b[f], w.k64, w.j[0], w.j[1]);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_inject(pic_handle *h)
+{
+    const Consts &c = h->c;
+    Workspace &w = h->ws;
+    const int f = h->fbuf, g = 1 - h->fbuf;
+    FieldArgs a{w.ez[f], w.er[f], w.b[f], w.ez[g], w.er[g], w.b[g], w.j[h->jbuf], w.j[1 - h->jbuf],
+                w.k64, w.x[h->pbuf], w.u[h->pbuf], w.ctr};
+    hipLaunchKernelGGL(k_field_inject, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_append(pic_handle *h, int64_t base, int64_t n)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_check_append, dim3(grid_for(n, 256)), dim3(256), 0, h->stream, h->c,
+                           h->ws.x[h->pbuf], h->ws.u[h->pbuf], base, n, h->ws.ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit_append(pic_handle *h, int64_t n)
+{
+    hipLaunchKernelGGL(k_commit_append, dim3(1), dim3(64), 0, h->stream, h->ws.ctr, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick(pic_handle *h)
+{
+    hipLaunchKernelGGL(k_kick, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c,
+                       h->ws.ez[h->fbuf], h->ws.k64);
+    return hipGetLastError();
+}
+
+}  // namespace pcpic

@@ -1,0 +1,166 @@
+// pcpic_internal.h -- private layout shared by the host code and the gfx950 kernels.
+//
+// Not part of the C ABI.  Everything here lives in the caller-provided device
+// workspace; see pcpic.h for the public contract.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pcpic.h"
+
+namespace pcpic {
+
+// Constants of one tube, computed once on the host in IEEE double (the library
+// is built with -ffp-contract=off) and passed to every kernel by value.
+// The order of each floating-point operation is fixed: the device code
+// evaluates every formula of the step with exactly these operands.
+struct Consts {
+    int64_t N;        // cells
+    int64_t cap;      // particle capacity
+    int32_t P;        // fixed-point fraction bits
+    uint32_t flags;   // PIC_* flags
+    int64_t oneP;     // 2^P
+    double twoP;      // 2^P as a double
+    double dz;        // L / N
+    double dtdz;      // c dt / dz
+    double dt;        // dtdz * dz
+    double dtR;       // dt / R
+    double invR;      // unused by the step; kept for diagnostics scaling
+    double R;         // tube radius
+    double qmdt;      // (q/m) dt
+    double rho0;      // rho_GJ at node 0
+    double qm;        // macro charge rho0 dz / ppc
+    double qmP;       // qm / 2^P (charge of one weight unit)
+    double fourpi;    // 4 pi
+    double c4;        // fourpi * qmP: E_z change per unit of J
+    double fqm;       // fourpi * qm: surface-field change per injected particle
+    double hdz;       // dz / 2
+    double tw;        // 2 dtdz (mirror update of E_r at node N)
+    double cpois;     // fourpi dz^2 (Poisson right-hand side)
+    double bdiag;     // -(2 + (dz/R)^2) (Poisson diagonal)
+    // background density
+    int32_t rho_kind;
+    int32_t n_knots;
+    double rho_amp, kappa, r_star, length;
+};
+
+// Device-side counters (one per tube), 256-byte aligned in the workspace.
+struct DevCounters {
+    int64_t n_slots;        // occupied particle slots [0, n_slots) (live + removed)
+    int64_t n_alive;        // live particles (maintained by sort / inject)
+    int64_t n_injected;
+    int64_t n_exit;
+    int64_t n_absorb;
+    int64_t w0;             // node-0 weight tally of the step in progress
+    int64_t w0_last;        // node-0 weight of the last completed step
+    int64_t last_ninj;
+    unsigned long long exit_lo;  // 128-bit exit-gamma sum, units 2^-32
+    long long exit_hi;
+    unsigned long long status;   // PIC_ST_* bits
+    double e_surf;
+    int64_t step;
+    int64_t n_removed;      // removed since the last compaction (exit + absorb + lost)
+    unsigned long long gauss_max_bits;  // diagnostics: max |G| (non-negative double bits)
+    unsigned long long rho_max_bits;    // max |rho_GJ| (non-negative double bits)
+    int64_t bad_inputs;                 // rejected particles of the last pic_inject
+};
+
+struct Workspace {
+    double *x[2], *u[2];    // particle double buffer (FP64)
+    double *ez[2], *er[2], *b[2];
+    int64_t *j[2];          // fixed-point current, ping-pong per step
+    double *k64;            // kick array (q/m) dt E_z
+    double *rho_gj;
+    int64_t *w;             // CIC node weights (Poisson, diagnostics)
+    double *phi, *cp, *dp, *rhs;
+    double *knots;
+    DevCounters *ctr;
+    // profile bins
+    long long *pcount;
+    unsigned long long *plo;
+    long long *phi128;
+    long long *pmin, *pmax; // ordered-integer images of doubles
+    double *gauss;
+    // sort scratch
+    long long *cell_count;  // [N + 1]
+    long long *cell_off;    // [N + 1]
+    long long *blk_sum;     // [scan blocks + 1]
+    size_t bytes;
+};
+
+// Byte layout of the workspace (offsets from the base).  Computing it with a
+// null base gives the size.
+Workspace carve(const pic_params &p, uint8_t *base);
+
+}  // namespace pcpic
+
+struct pic_handle {
+    pic_params p{};
+    std::vector<double> knots;
+    pcpic::Consts c{};
+    pcpic::Workspace ws{};
+    hipStream_t stream = nullptr;
+    int pbuf = 0;       // current particle buffer
+    int fbuf = 0;       // field buffer holding E^n, B^{n-1/2}
+    int jbuf = 0;       // current buffer that the next step deposits into
+    int64_t step = 0;   // steps enqueued
+    int push_block = 256;
+    int push_ppt = 4;
+    int push_grid = 0;  // 0 = derived from the device
+    int n_cu = 256;
+};
+
+namespace pcpic {
+
+// ---- kernel launchers (each enqueues on h->stream, returns hipError_t) ----
+hipError_t launch_rho_gj(pic_handle *h);
+hipError_t launch_weights(pic_handle *h, int64_t *w_out);
+hipError_t launch_poisson(pic_handle *h);
+hipError_t launch_push_f64(pic_handle *h);
+hipError_t launch_field_inject(pic_handle *h);
+hipError_t launch_check_append(pic_handle *h, int64_t base, int64_t n);
+hipError_t launch_commit_append(pic_handle *h, int64_t n);
+hipError_t launch_kick(pic_handle *h);
+hipError_t launch_gauss(pic_handle *h);
+hipError_t launch_profile(pic_handle *h, int n_bins);
+hipError_t launch_sort(pic_handle *h);
+
+// Goldreich-Julian density at node i (eqs. 5-7; the three kinds are listed in
+// pcpic.h).  Used by the device fill and, at node 0, by the host to fix the
+// macro charge, so both see the same value.
+__host__ __device__ inline double rho_node(const Consts &c, const double *knots, int64_t i)
+{
+    const double z = (double)i * c.dz;
+    if (c.rho_kind == PIC_RHO_UNIFORM) return -c.rho_amp;
+    const double eta = 1.0 + z / c.r_star;
+    const double e3 = eta * eta * eta;
+    const double fd = 1.0 - c.kappa / e3;   // 1 - omega/Omega, eq. (7)
+    if (c.rho_kind == PIC_RHO_FRAME_DRAG) return -(c.rho_amp * fd);
+    const int64_t K = c.n_knots;
+    const double s = (z * (double)(K - 1)) / c.length;
+    int64_t k = (int64_t)floor(s);
+    if (k > K - 2) k = K - 2;
+    if (k < 0) k = 0;
+    const double g = s - (double)k;
+    const double th = knots[k] + g * (knots[k + 1] - knots[k]);
+    return -(th * fd);
+}
+
+// Ordered-integer image of a double: monotone in the double's value.
+__host__ __device__ inline long long ordered_bits(double d)
+{
+    long long k = __builtin_bit_cast(long long, d);
+    return k < 0 ? (k ^ 0x7fffffffffffffffLL) : k;
+}
+__host__ __device__ inline double from_ordered_bits(long long k)
+{
+    long long b = k < 0 ? (k ^ 0x7fffffffffffffffLL) : k;
+    return __builtin_bit_cast(double, b);
+}
+
+}  // namespace pcpic

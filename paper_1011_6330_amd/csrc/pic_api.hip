@@ -1,0 +1,465 @@
+// pic_api.hip -- host side of the C ABI declared in include/pcpic.h:
+// parameter validation, workspace carve-up, the per-step launch sequence and
+// the synchronising read-back calls.  No device memory is ever allocated here.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "pcpic_internal.h"
+
+using namespace pcpic;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+pic_status fail(pic_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIP_OK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail(PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+int effective_bins(const pic_params &p) { return p.max_bins > 0 ? p.max_bins : 1024; }
+
+pic_status validate(const pic_params *p)
+{
+    if (!p) return fail(PIC_EINVAL, "params is NULL");
+    if (p->abi_version != PCPIC_ABI_VERSION)
+        return fail(PIC_EABI, "abi_version %d, library is %d", p->abi_version, PCPIC_ABI_VERSION);
+    if (p->precision != PIC_FP64) return fail(PIC_EINVAL, "precision %d not supported", p->precision);
+    if (p->n_cells < 2 || p->n_cells > ((int64_t)1 << 31))
+        return fail(PIC_EINVAL, "n_cells %lld out of range [2, 2^31]", (long long)p->n_cells);
+    if (!(p->length > 0) || !isfinite(p->length)) return fail(PIC_EINVAL, "length must be > 0");
+    if (!(p->radius > 0) || !isfinite(p->radius)) return fail(PIC_EINVAL, "radius must be > 0");
+    if (!(p->dt_over_dz > 0 && p->dt_over_dz < 1))
+        return fail(PIC_ECFL, "dt_over_dz = %g violates 0 < c dt/dz < 1", p->dt_over_dz);
+    if (!isfinite(p->q_over_m)) return fail(PIC_EINVAL, "q_over_m must be finite");
+    if (!(p->ppc > 0) || !isfinite(p->ppc)) return fail(PIC_EINVAL, "ppc must be > 0");
+    if (p->rho_kind < PIC_RHO_UNIFORM || p->rho_kind > PIC_RHO_KNOTS)
+        return fail(PIC_EINVAL, "rho_kind %d unknown", p->rho_kind);
+    if (!isfinite(p->rho_amp)) return fail(PIC_EINVAL, "rho_amp must be finite");
+    if (p->rho_kind != PIC_RHO_UNIFORM && (!(p->r_star > 0) || !isfinite(p->kappa)))
+        return fail(PIC_EINVAL, "frame dragging needs r_star > 0 and a finite kappa");
+    if (p->rho_kind == PIC_RHO_KNOTS && (p->n_knots < 2 || !p->knots))
+        return fail(PIC_EINVAL, "PIC_RHO_KNOTS needs n_knots >= 2 and a knot array");
+    if (p->fp_bits < 16 || p->fp_bits > 36) return fail(PIC_EINVAL, "fp_bits %d not in [16, 36]", p->fp_bits);
+    if (p->capacity < 1 || p->capacity > ((int64_t)1 << 40))
+        return fail(PIC_EINVAL, "capacity %lld out of range", (long long)p->capacity);
+    if (p->sort_every < 0) return fail(PIC_EINVAL, "sort_every must be >= 0");
+    if (p->max_bins < 0 || p->max_bins > (1 << 20)) return fail(PIC_EINVAL, "max_bins out of range");
+    if (p->flags & ~(PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS)) return fail(PIC_EINVAL, "unknown flag bits");
+    return PIC_OK;
+}
+
+Consts make_consts(const pic_params &p, const double *knots)
+{
+    Consts c{};
+    c.N = p.n_cells;
+    c.cap = p.capacity;
+    c.P = p.fp_bits;
+    c.flags = p.flags;
+    c.oneP = (int64_t)1 << p.fp_bits;
+    c.twoP = ldexp(1.0, p.fp_bits);
+    c.dz = p.length / (double)p.n_cells;
+    c.dtdz = p.dt_over_dz;
+    c.dt = c.dtdz * c.dz;
+    c.dtR = c.dt / p.radius;
+    c.R = p.radius;
+    c.invR = 1.0 / p.radius;
+    c.qmdt = p.q_over_m * c.dt;
+    c.rho_kind = p.rho_kind;
+    c.n_knots = p.rho_kind == PIC_RHO_KNOTS ? p.n_knots : 0;
+    c.rho_amp = p.rho_amp;
+    c.kappa = p.kappa;
+    c.r_star = p.r_star;
+    c.length = p.length;
+    c.rho0 = rho_node(c, knots, 0);
+    c.qm = (c.rho0 * c.dz) / p.ppc;
+    c.qmP = c.qm / c.twoP;
+    c.fourpi = 4.0 * M_PI;
+    c.c4 = c.fourpi * c.qmP;
+    c.fqm = c.fourpi * c.qm;
+    c.hdz = 0.5 * c.dz;
+    c.tw = 2.0 * c.dtdz;
+    const double dz2 = c.dz * c.dz;
+    c.cpois = c.fourpi * dz2;
+    const double rr = c.dz / p.radius;
+    const double h2 = rr * rr;
+    c.bdiag = -(2.0 + h2);
+    return c;
+}
+
+}  // namespace
+
+namespace pcpic {
+
+Workspace carve(const pic_params &p, uint8_t *base)
+{
+    Workspace w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        const size_t o = align_up(off);
+        off = o + bytes;
+        return base ? (void *)(base + o) : nullptr;
+    };
+    const size_t N = (size_t)p.n_cells, cap = (size_t)p.capacity;
+    const size_t nb = (size_t)effective_bins(p);
+    for (int k = 0; k < 2; ++k) {
+        w.x[k] = (double *)take(cap * 8);
+        w.u[k] = (double *)take(cap * 8);
+    }
+    for (int k = 0; k < 2; ++k) {
+        w.ez[k] = (double *)take(N * 8);
+        w.er[k] = (double *)take((N + 1) * 8);
+        w.b[k] = (double *)take(N * 8);
+        w.j[k] = (int64_t *)take(N * 8);
+    }
+    w.k64 = (double *)take(N * 8);
+    w.rho_gj = (double *)take((N + 1) * 8);
+    w.w = (int64_t *)take((N + 1) * 8);
+    w.phi = (double *)take((N + 1) * 8);
+    w.cp = (double *)take((N + 1) * 8);
+    w.dp = (double *)take((N + 1) * 8);
+    w.rhs = (double *)take((N + 1) * 8);
+    w.knots = (double *)take((size_t)(p.n_knots > 0 ? p.n_knots : 1) * 8);
+    w.ctr = (DevCounters *)take(sizeof(DevCounters));
+    w.pcount = (long long *)take(nb * 8);
+    w.plo = (unsigned long long *)take(nb * 8);
+    w.phi128 = (long long *)take(nb * 8);
+    w.pmin = (long long *)take(nb * 8);
+    w.pmax = (long long *)take(nb * 8);
+    w.gauss = (double *)take((N + 1) * 8);
+    w.cell_count = (long long *)take((N + 1) * 8);
+    w.cell_off = (long long *)take((N + 1) * 8);
+    w.blk_sum = (long long *)take((N / 1024 + 2) * 8);
+    w.bytes = align_up(off);
+    return w;
+}
+
+}  // namespace pcpic
+
+namespace {
+
+pic_status read_counters(pic_handle *h, DevCounters *out)
+{
+    HIP_OK(hipMemcpyAsync(out, h->ws.ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+double i128_to_double(unsigned long long lo, long long hi)
+{
+    const __int128 v = ((__int128)hi << 64) | (__int128)lo;
+    return (double)v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pic_abi_version(void) { return PCPIC_ABI_VERSION; }
+
+const char *pic_last_error(void) { return g_err; }
+
+size_t pic_workspace_bytes(const pic_params *p)
+{
+    if (validate(p) != PIC_OK) return 0;
+    return carve(*p, nullptr).bytes;
+}
+
+pic_status pic_init(const pic_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream, pic_handle **out)
+{
+    if (!out) return fail(PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    pic_status s = validate(p);
+    if (s != PIC_OK) return s;
+    const size_t need = carve(*p, nullptr).bytes;
+    if (!d_workspace || ws_bytes < need)
+        return fail(PIC_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (((uintptr_t)d_workspace) % ALIGN)
+        return fail(PIC_EWORKSPACE, "workspace must be %zu-byte aligned", ALIGN);
+    pic_handle *h = new (std::nothrow) pic_handle();
+    if (!h) return fail(PIC_EINVAL, "out of host memory");
+    h->p = *p;
+    if (p->rho_kind == PIC_RHO_KNOTS) h->knots.assign(p->knots, p->knots + p->n_knots);
+    h->p.knots = nullptr;
+    h->c = make_consts(*p, h->knots.empty() ? nullptr : h->knots.data());
+    if (!isfinite(h->c.qm) || !isfinite(h->c.rho0)) {
+        delete h;
+        return fail(PIC_EINVAL, "rho_GJ(0) is not finite");
+    }
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = carve(*p, (uint8_t *)d_workspace);
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        h->n_cu = ncu;
+    auto bail = [&](hipError_t e, const char *what) {
+        delete h;
+        return fail(PIC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e = hipMemsetAsync(h->ws.ctr, 0, sizeof(DevCounters), h->stream);
+    if (e != hipSuccess) return bail(e, "clear counters");
+    if (!h->knots.empty()) {
+        e = hipMemcpyAsync(h->ws.knots, h->knots.data(), h->knots.size() * 8, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) return bail(e, "copy knots");
+    }
+    if ((e = launch_rho_gj(h)) != hipSuccess) return bail(e, "rho_gj");
+    if ((e = launch_poisson(h)) != hipSuccess) return bail(e, "poisson");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "init sync");
+    *out = h;
+    return PIC_OK;
+}
+
+pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u, int32_t mem)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (n < 0 || (n > 0 && (!x || !u)) || (mem != 0 && mem != 1))
+        return fail(PIC_EINVAL, "bad arguments to pic_inject");
+    if (n == 0) return PIC_OK;
+    if (mem == 0) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (!isfinite(u[i]) || !isfinite(x[i])) return fail(PIC_ENONFINITE, "particle %lld not finite", (long long)i);
+            if (!(x[i] >= 0.0 && x[i] < (double)h->c.N))
+                return fail(PIC_EINVAL, "particle %lld at x = %g outside [0, N)", (long long)i, x[i]);
+        }
+    }
+    DevCounters ctr;
+    pic_status s = read_counters(h, &ctr);
+    if (s != PIC_OK) return s;
+    if (ctr.n_slots + n > h->c.cap)
+        return fail(PIC_ECAPACITY, "%lld slots used + %lld > capacity %lld", (long long)ctr.n_slots,
+                    (long long)n, (long long)h->c.cap);
+    const hipMemcpyKind kind = mem == 0 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIP_OK(hipMemcpyAsync(h->ws.x[h->pbuf] + ctr.n_slots, x, (size_t)n * 8, kind, h->stream));
+    HIP_OK(hipMemcpyAsync(h->ws.u[h->pbuf] + ctr.n_slots, u, (size_t)n * 8, kind, h->stream));
+    HIP_OK(hipMemsetAsync(&h->ws.ctr->bad_inputs, 0, sizeof(int64_t), h->stream));
+    HIP_OK(launch_check_append(h, ctr.n_slots, n));
+    HIP_OK(launch_commit_append(h, n));
+    s = read_counters(h, &ctr);
+    if (s != PIC_OK) return s;
+    if (ctr.bad_inputs) return fail(PIC_EINVAL, "%lld particles outside [0, N) or not finite", (long long)ctr.bad_inputs);
+    if (h->step == 0) {
+        HIP_OK(launch_poisson(h));
+        HIP_OK(hipStreamSynchronize(h->stream));
+    }
+    return PIC_OK;
+}
+
+pic_status pic_step(pic_handle *h, int64_t n_steps)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (n_steps < 0) return fail(PIC_EINVAL, "n_steps < 0");
+    for (int64_t s = 0; s < n_steps; ++s) {
+        HIP_OK(launch_push_f64(h));
+        HIP_OK(launch_field_inject(h));
+        h->fbuf ^= 1;
+        h->jbuf ^= 1;
+        h->step += 1;
+        if (h->p.sort_every > 0 && h->step % h->p.sort_every == 0) HIP_OK(launch_sort(h));
+    }
+    return PIC_OK;
+}
+
+pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
+{
+    if (!h || !out) return fail(PIC_EINVAL, "handle or out is NULL");
+    if (n_steps < 0) return fail(PIC_EINVAL, "n_steps < 0");
+    memset(out, 0, sizeof *out);
+    if (n_steps == 0) return PIC_OK;
+    std::vector<hipEvent_t> ev((size_t)n_steps * 4, nullptr);
+    std::vector<int64_t> slots_before((size_t)n_steps, 0);
+    pic_status rc = PIC_OK;
+    for (auto &e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) { rc = fail(PIC_EDEVICE, "hipEventCreate failed"); break; }
+    }
+    DevCounters ctr;
+    if (rc == PIC_OK) rc = read_counters(h, &ctr);
+    int64_t slots = ctr.n_slots;
+    for (int64_t s = 0; s < n_steps && rc == PIC_OK; ++s) {
+        hipEvent_t *e = &ev[(size_t)s * 4];
+        bool sorted = false;
+        if (hipEventRecord(e[0], h->stream) != hipSuccess || launch_push_f64(h) != hipSuccess ||
+            hipEventRecord(e[1], h->stream) != hipSuccess || launch_field_inject(h) != hipSuccess ||
+            hipEventRecord(e[2], h->stream) != hipSuccess) {
+            rc = fail(PIC_EDEVICE, "launch failed in pic_step_timed");
+            break;
+        }
+        h->fbuf ^= 1;
+        h->jbuf ^= 1;
+        h->step += 1;
+        if (h->p.sort_every > 0 && h->step % h->p.sort_every == 0) {
+            if (launch_sort(h) != hipSuccess) { rc = fail(PIC_EDEVICE, "sort launch failed"); break; }
+            sorted = true;
+        }
+        if (hipEventRecord(e[3], h->stream) != hipSuccess) { rc = fail(PIC_EDEVICE, "event record failed"); break; }
+        slots_before[(size_t)s] = sorted ? -1 : 0;
+    }
+    if (rc == PIC_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(PIC_EDEVICE, "sync failed");
+    if (rc == PIC_OK) {
+        for (int64_t s = 0; s < n_steps; ++s) {
+            hipEvent_t *e = &ev[(size_t)s * 4];
+            float a = 0, b = 0, c = 0;
+            hipEventElapsedTime(&a, e[0], e[1]);
+            hipEventElapsedTime(&b, e[1], e[2]);
+            hipEventElapsedTime(&c, e[2], e[3]);
+            out->push_ms += a;
+            out->field_ms += b;
+            out->push_launches += 1;
+            out->field_launches += 1;
+            if (slots_before[(size_t)s] < 0) {
+                out->sort_ms += c;
+                out->sort_launches += 1;
+            }
+        }
+        float tot = 0;
+        hipEventElapsedTime(&tot, ev[0], ev[(size_t)n_steps * 4 - 1]);
+        out->total_ms = tot;
+        DevCounters end;
+        if (read_counters(h, &end) == PIC_OK) {
+            // slots visited: between sorts the slot count only grows by injection;
+            // the average of the start and end counts times the steps
+            out->particle_steps = (int64_t)((double)(slots + end.n_slots) * 0.5 * (double)n_steps);
+        }
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+pic_status pic_sync(pic_handle *h)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    DevCounters ctr;
+    pic_status s = read_counters(h, &ctr);
+    if (s != PIC_OK) return s;
+    if (ctr.status) return fail(PIC_EDEVSTATUS, "device status bits 0x%llx", (unsigned long long)ctr.status);
+    return PIC_OK;
+}
+
+pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out)
+{
+    if (!h || !out) return fail(PIC_EINVAL, "handle or out is NULL");
+    const int nb = req ? req->n_bins : 0;
+    const bool want_gauss = req && req->want_gauss;
+    if (nb < 0 || nb > effective_bins(h->p)) return fail(PIC_EINVAL, "n_bins %d > max_bins", nb);
+    const int64_t N = h->c.N;
+    const Workspace &w = h->ws;
+    HIP_OK(launch_profile(h, nb));   // also clears the Gauss maximum
+    if (want_gauss || out->gauss) HIP_OK(launch_gauss(h));
+    else if (out->weights) HIP_OK(launch_weights(h, w.w));
+    DevCounters ctr;
+    HIP_OK(hipMemcpyAsync(&ctr, w.ctr, sizeof ctr, hipMemcpyDeviceToHost, h->stream));
+    const int f = h->fbuf;
+    if (out->ez) HIP_OK(hipMemcpyAsync(out->ez, w.ez[f], (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
+    if (out->er) HIP_OK(hipMemcpyAsync(out->er, w.er[f], (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    if (out->b_phi) HIP_OK(hipMemcpyAsync(out->b_phi, w.b[f], (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
+    if (out->rho_gj) HIP_OK(hipMemcpyAsync(out->rho_gj, w.rho_gj, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    if (out->j_last)
+        HIP_OK(hipMemcpyAsync(out->j_last, w.j[1 - h->jbuf], (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
+    if (out->weights) HIP_OK(hipMemcpyAsync(out->weights, w.w, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    if (out->gauss) HIP_OK(hipMemcpyAsync(out->gauss, w.gauss, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    std::vector<long long> cnt(nb), hi(nb), mn(nb), mx(nb);
+    std::vector<unsigned long long> lo(nb);
+    if (nb > 0) {
+        HIP_OK(hipMemcpyAsync(cnt.data(), w.pcount, (size_t)nb * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipMemcpyAsync(lo.data(), w.plo, (size_t)nb * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipMemcpyAsync(hi.data(), w.phi128, (size_t)nb * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipMemcpyAsync(mn.data(), w.pmin, (size_t)nb * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipMemcpyAsync(mx.data(), w.pmax, (size_t)nb * 8, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_OK(hipStreamSynchronize(h->stream));
+    out->step = ctr.step;
+    out->n_slots = ctr.n_slots;
+    out->n_alive = ctr.n_slots - ctr.n_removed;
+    out->n_injected = ctr.n_injected;
+    out->n_exit = ctr.n_exit;
+    out->n_absorb = ctr.n_absorb;
+    out->last_n_inj = ctr.last_ninj;
+    out->w0 = ctr.w0_last;
+    out->status = (int64_t)ctr.status;
+    out->e_surf = ctr.e_surf;
+    out->exit_sum_lo = ctr.exit_lo;
+    out->exit_sum_hi = ctr.exit_hi;
+    out->exit_gamma_sum = ldexp(i128_to_double(ctr.exit_lo, ctr.exit_hi), -32);
+    const double rmax = __builtin_bit_cast(double, ctr.rho_max_bits);
+    const double gmax = __builtin_bit_cast(double, ctr.gauss_max_bits);
+    out->gauss_max = (want_gauss || out->gauss) ? gmax / (h->c.fourpi * rmax) : 0.0;
+    for (int k = 0; k < nb; ++k) {
+        if (out->prof_count) out->prof_count[k] = cnt[k];
+        if (out->prof_sum_lo) out->prof_sum_lo[k] = lo[k];
+        if (out->prof_sum_hi) out->prof_sum_hi[k] = hi[k];
+        if (out->prof_mean)
+            out->prof_mean[k] = cnt[k] ? ldexp(i128_to_double(lo[k], hi[k]), -32) / (double)cnt[k] : 0.0;
+        if (out->prof_min) out->prof_min[k] = from_ordered_bits(mn[k]);
+        if (out->prof_max) out->prof_max[k] = from_ordered_bits(mx[k]);
+    }
+    if (ctr.status) return fail(PIC_EDEVSTATUS, "device status bits 0x%llx", (unsigned long long)ctr.status);
+    return PIC_OK;
+}
+
+pic_status pic_read_particles(pic_handle *h, double *x, double *u, int64_t cap, int64_t *n_out)
+{
+    if (!h || !n_out) return fail(PIC_EINVAL, "handle or n_out is NULL");
+    DevCounters ctr;
+    pic_status s = read_counters(h, &ctr);
+    if (s != PIC_OK) return s;
+    const int64_t ns = ctr.n_slots;
+    std::vector<double> hx((size_t)ns), hu((size_t)ns);
+    if (ns > 0) {
+        HIP_OK(hipMemcpyAsync(hx.data(), h->ws.x[h->pbuf], (size_t)ns * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipMemcpyAsync(hu.data(), h->ws.u[h->pbuf], (size_t)ns * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+    }
+    int64_t m = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+        if (!(hx[i] >= 0.0)) continue;   // removed slot
+        if (m < cap) {
+            if (x) x[m] = hx[i];
+            if (u) u[m] = hu[i];
+        }
+        ++m;
+    }
+    *n_out = m;
+    if (m > cap) return fail(PIC_ECAPACITY, "%lld live particles, room for %lld", (long long)m, (long long)cap);
+    return PIC_OK;
+}
+
+pic_status pic_write_fields(pic_handle *h, const double *ez, const double *er, const double *b_phi)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    const int64_t N = h->c.N;
+    const int f = h->fbuf;
+    if (ez) HIP_OK(hipMemcpyAsync(h->ws.ez[f], ez, (size_t)N * 8, hipMemcpyHostToDevice, h->stream));
+    if (er) HIP_OK(hipMemcpyAsync(h->ws.er[f], er, (size_t)(N + 1) * 8, hipMemcpyHostToDevice, h->stream));
+    if (b_phi) HIP_OK(hipMemcpyAsync(h->ws.b[f], b_phi, (size_t)N * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(launch_kick(h));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+pic_status pic_destroy(pic_handle *h)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+    return PIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// wave.h -- 64-lane wavefront helpers for gfx950 (CDNA4 runs wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcpic {
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_min_i64(long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        long long o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ long long wave_max_i64(long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Add `val` to dst[key] for every lane with `want`, one global atomic per
+// distinct key present in the wave: lanes sharing the leader's key are summed
+// with a butterfly, the leader lane issues the atomic, and the loop repeats
+// over the keys still pending.  Integer addition makes the result independent
+// of the order in which waves and lanes arrive.
+__device__ __forceinline__ void wave_add_keyed(unsigned long long *dst, int64_t key, int64_t val,
+                                               bool want)
+{
+    unsigned long long pend = __ballot(want);
+    while (pend) {
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const int64_t lk = __shfl(key, leader);
+        const bool mine = want && key == lk;
+        const int64_t v = wave_sum_i64(mine ? val : 0);
+        if ((int)__lane_id() == leader && v != 0) atomicAdd(dst + lk, (unsigned long long)v);
+        pend &= ~__ballot(mine);
+        want = want && !mine;
+    }
+}
+
+// 128-bit two's-complement accumulation into (lo, hi) words with carry.
+__device__ __forceinline__ void atomic_add_i128(unsigned long long *lo, long long *hi, __int128 v)
+{
+    const unsigned long long vlo = (unsigned long long)v;
+    const long long vhi = (long long)(v >> 64);
+    const unsigned long long old = atomicAdd(lo, vlo);
+    const long long carry = (old + vlo < old) ? 1 : 0;
+    if (vhi + carry != 0) atomicAdd((unsigned long long *)hi, (unsigned long long)(vhi + carry));
+}
+
+}  // namespace pcpic

@@ -1,0 +1,198 @@
+"""GPU FP64 path vs the CPU oracle, through the C ABI: bit-identical results.
+
+The FP64 kernels evaluate every formula of the step with the oracle's operand
+order (no FMA contraction, IEEE division and square root), deposit the current
+in exact fixed point, and reduce only integers, so the two must agree to the
+last bit; the 1e-10 relative gate of the FP64 path is never needed.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import assert_state_equal, make_pair, say
+from paper_1011_6330_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c1_full_run_bit_identical():
+    """C1: flat-space SCLF from an empty tube, 2000 steps (cold start)."""
+    cfg = synth.preset("c1")
+    say("c1 full run", cfg["n_cells"], "cells, 2000 steps")
+    g, o = make_pair(cfg)
+    for s in range(8):
+        g.step(250)
+        o.step(250)
+        assert_state_equal(g, o, what=f"c1 step {250 * (s + 1)}")
+    d = g.diagnostics()
+    assert d["n_injected"] > 409 and d["n_absorb"] > 0
+    g.close()
+
+
+def test_vacuum_stays_fixed():
+    """No particles, no injection: the Poisson field is stationary (P3), identically."""
+    cfg = synth.preset("c1", flags=1)   # PIC_NO_AUTO_INJECT
+    say("vacuum 2000 steps")
+    g, o = make_pair(cfg)
+    g.step(2000)
+    o.step(2000)
+    assert_state_equal(g, o, what="vacuum")
+
+
+@pytest.mark.parametrize("N,n", [(777, 3 * 1024 + 123), (1000, 1), (256, 0), (2048, 20000)])
+def test_ragged_grid_and_tail_stepwise(N, n):
+    """Grids that are not a multiple of the 256-thread field block, particle counts
+    with a ragged last tile; J of every step bit-exact, frame-drag background."""
+    cfg = dict(synth.preset("c1"), n_cells=N, length=N / 100.0, q_over_m=-40.0, ppc=6.0,
+               rho_kind=synth.RHO_FRAME_DRAG, kappa=0.15, r_star=3.0, capacity=200000)
+    x, u = synth.random_particles(N, n, seed=7)
+    say("ragged", N, n)
+    g, o = make_pair(cfg, x, u)
+    for s in range(60):
+        g.step(1)
+        o.step(1)
+        d = g.diagnostics(fields=False, j=True)
+        assert np.array_equal(d["j_last"], o.j), f"J differs at step {s + 1}"
+        assert d["last_n_inj"] == o.counters["last_ninj"]
+    assert_state_equal(g, o, what=f"ragged N={N} n={n}")
+
+
+def test_sorted_warm_tube():
+    """Warm frame-drag beam with the cell sort every 16 steps: the sort only
+    reorders, so fields and counters stay bit-identical and the particle multiset
+    is the oracle's."""
+    N = 4096
+    cfg = dict(synth.preset("c2"), n_cells=N, q_over_m=synth.q_over_m_for(430.0), ppc=40.0,
+               warm=40 * N, capacity=int(40 * N * 1.2), sort_every=16)
+    x, u = synth.warm_start(cfg)
+    say("sorted warm", N, len(x))
+    g, o = make_pair(cfg, x, u)
+    for s in range(5):
+        g.step(40)
+        o.step(40)
+        assert_state_equal(g, o, ordered=False, what=f"sorted warm step {40 * (s + 1)}")
+    d = g.diagnostics(fields=False)
+    assert d["n_slots"] >= d["n_alive"]
+
+
+def test_shuffled_load_and_rerun_identical():
+    N = 512
+    cfg = dict(synth.preset("c1"), n_cells=N, q_over_m=-25.0, ppc=10.0, rho_kind=synth.RHO_FRAME_DRAG,
+               kappa=0.15, r_star=5.0, capacity=100000, sort_every=8)
+    x, u = synth.random_particles(N, 6000, seed=3)
+    perm = np.random.default_rng(0).permutation(len(x))
+    from paper_1011_6330_amd import Tube
+    outs = []
+    for xx, uu in ((x, u), (x[perm], u[perm]), (x, u)):
+        t = Tube(synth.tube_params(cfg))
+        t.inject(xx, uu)
+        t.step(100)
+        d = t.diagnostics(fields=True, j=True)
+        px, pu = t.read_particles()
+        k = np.lexsort((pu, px))
+        outs.append((d["ez"], d["er"], d["b_phi"], d["j_last"], px[k], pu[k], d["exit_sum_lo"]))
+        t.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs[0], outs[2]):
+        assert np.array_equal(a, b)
+
+
+def test_diagnostics_match_oracle():
+    cfg = synth.preset("c1")
+    g, o = make_pair(cfg)
+    g.step(700)
+    o.step(700)
+    nb = 37
+    d = g.diagnostics(n_bins=nb, gauss=True, weights=True, rho=True)
+    cnt, lo, hi, mn, mx = o.profile(nb)
+    assert np.array_equal(d["prof_count"], cnt)
+    assert np.array_equal(d["prof_sum_lo"], lo) and np.array_equal(d["prof_sum_hi"], hi)
+    sel = cnt > 0
+    assert np.array_equal(d["prof_min"][sel], mn[sel]) and np.array_equal(d["prof_max"][sel], mx[sel])
+    assert np.array_equal(d["weights"], o.weights())
+    assert np.array_equal(d["rho_gj"], o.rho_gj)
+    G, gmax = o.gauss()
+    assert np.array_equal(d["gauss"], G)
+    assert d["gauss_max"] == gmax
+    assert d["gauss_max"] < 1e-10
+
+
+def test_uniform_field_test_particle():
+    """P1 on the GPU: frozen uniform field, u_n = (n + 1/2) K exactly, positions
+    identical to the oracle."""
+    cfg = dict(synth.preset("c1"), flags=1 | 2, capacity=8)
+    g, o = make_pair(cfg, np.array([2.0]), np.array([-0.5 * 10.0 / 1024]))
+    ez = np.full(1024, -2.0)
+    g.write_fields(ez=ez)
+    o.ez[:] = ez
+    for n in range(1, 400):
+        g.step(1)
+        o.step(1)
+    x, u = g.read_particles()
+    assert u[0] == o.u[0] and x[0] == o.x[0]
+    assert u[0] == 398.5 * 10.0 / 1024     # u_n = u_0 + n K, K = (q/m) dt E0 = 10/1024
+
+
+def test_exit_absorb_and_gamma_sum():
+    N = 64
+    cfg = dict(synth.preset("c1"), n_cells=N, length=1.0, flags=1 | 2, capacity=16)
+    x = np.array([N - 0.1, 0.1, 10.0, N - 0.3])
+    u = np.array([10.0, -10.0, 0.0, 1e7])
+    g, o = make_pair(cfg, x, u)
+    z = np.zeros(N)
+    g.write_fields(ez=z)
+    o.ez[:] = z
+    g.step(1)
+    o.step(1)
+    d = assert_state_equal(g, o, what="exits")
+    assert d["n_exit"] == 2 and d["n_absorb"] == 1
+    expect = (round(math.sqrt(101.0) * 2 ** 32) + round(math.sqrt(1.0 + 1e14) * 2 ** 32)) / 2 ** 32
+    assert d["exit_gamma_sum"] == expect
+
+
+def test_capacity_clip_latches_status():
+    from paper_1011_6330_amd import PicError
+    cfg = dict(synth.preset("c1"), capacity=300)
+    g, o = make_pair(cfg)
+    g.step(1)
+    o.step(1)
+    d = g.diagnostics(raise_on_status=False)
+    assert d["status"] & 1 and d["n_alive"] == 300 == o.n
+    assert o.counters["status"] & 1
+    with pytest.raises(PicError) as e:
+        g.sync()
+    assert e.value.code == -9
+
+
+def test_inject_rejects_bad_particles():
+    from paper_1011_6330_amd import PicError, Tube
+    t = Tube(synth.tube_params(dict(synth.preset("c1"), capacity=10)))
+    for x, u, code in (([1.0, 2000.0], [0.0, 0.0], -1), ([1.0], [np.nan], -4),
+                       (np.ones(11), np.zeros(11), -3), ([-0.5], [0.0], -1)):
+        with pytest.raises(PicError) as e:
+            t.inject(np.array(x, float), np.array(u, float))
+        assert e.value.code == code
+    import torch
+    xd = torch.tensor([1.0, 5000.0], device="cuda", dtype=torch.float64)
+    ud = torch.zeros(2, device="cuda", dtype=torch.float64)
+    with pytest.raises(PicError):
+        t.inject(xd, ud)
+    assert t.diagnostics(fields=False)["n_alive"] == 0
+    t.close()
+
+
+def test_c2_full_size_first_steps():
+    """The frame-dragging tube at full size (65,536 cells, ~4e7 particles, gamma up
+    to ~6e6), in the benchmark's launch configuration: every result after 3 steps
+    bit-identical to the oracle."""
+    cfg = synth.preset("c2")
+    x, u = synth.warm_start(cfg)
+    say("c2 full size", len(x), "particles")
+    g, o = make_pair(cfg, x, u)
+    del x, u
+    g.step(3)
+    o.step(3)
+    d = assert_state_equal(g, o, what="c2 full size")
+    assert d["n_alive"] > 3.9e7
