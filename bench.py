@@ -42,6 +42,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--push", default="256:2", help="push launch shape threads:slots-per-thread")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -62,6 +63,8 @@ def main():
     if len(x):
         tube.inject(x, u)
     log("injected", len(x))
+    pb, pp = (int(v) for v in args.push.split(":"))
+    tube.set_push_config(pb, pp)
     tube.step(args.warmup)
     tube.sync()
     d0 = tube.diagnostics(fields=False)
@@ -95,7 +98,7 @@ def main():
         "data": "synthetic (seeded warm-start beam shaped like the paper's frame-dragging runs)",
         "config": {"workload": WORKLOADS[args.config], "n_cells": int(cfg["n_cells"]),
                    "particles": int(alive_avg), "sort_every": int(cfg["sort_every"]),
-                   "push": "fp64"},
+                   "push": f"fp64 {pb}x{pp}"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_push_f64", "avg_launch_us": push_avg_s * 1e6,

@@ -214,6 +214,12 @@ typedef struct pic_timing {
  * Errors: as pic_step, plus PIC_EDEVICE for event failures. */
 pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out);
 
+/* Launch shape of the particle push: threads per block and consecutive particle
+ * slots per thread.  Supported pairs: (64|128|256|512, 4), (128|256, 8),
+ * (256, 2).  Results do not depend on the choice (integer deposition).
+ * Errors: PIC_EINVAL for an unsupported pair. */
+pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread);
+
 /* Synchronise the stream; PIC_EDEVSTATUS if a status bit is latched. */
 pic_status pic_sync(pic_handle *h);
 

@@ -86,6 +86,7 @@ SIGNATURES = {
     "pic_read_particles": (ctypes.c_int32, [ctypes.c_void_p, _pd, _pd, ctypes.c_int64, _pi]),
     "pic_write_fields": (ctypes.c_int32, [ctypes.c_void_p, _pd, _pd, _pd]),
     "pic_step_timed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(PicTiming)]),
+    "pic_set_push_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "pic_sync": (ctypes.c_int32, [ctypes.c_void_p]),
     "pic_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
 }
@@ -194,6 +195,9 @@ class Tube:
         t = PicTiming()
         _check(self.lib.pic_step_timed(self._h, int(n), ctypes.byref(t)), "pic_step_timed")
         return {k: getattr(t, k) for k, _ in PicTiming._fields_}
+
+    def set_push_config(self, block, per_thread):
+        _check(self.lib.pic_set_push_config(self._h, int(block), int(per_thread)), "pic_set_push_config")
 
     def sync(self):
         _check(self.lib.pic_sync(self._h), "pic_sync")

@@ -110,7 +110,7 @@ struct pic_handle {
     int jbuf = 0;       // current buffer that the next step deposits into
     int64_t step = 0;   // steps enqueued
     int push_block = 256;
-    int push_ppt = 4;
+    int push_ppt = 2;
     int push_grid = 0;  // 0 = derived from the device
     int n_cu = 256;
 };

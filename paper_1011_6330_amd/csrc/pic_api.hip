@@ -316,9 +316,9 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
         for (int64_t s = 0; s < n_steps; ++s) {
             hipEvent_t *e = &ev[(size_t)s * 4];
             float a = 0, b = 0, c = 0;
-            hipEventElapsedTime(&a, e[0], e[1]);
-            hipEventElapsedTime(&b, e[1], e[2]);
-            hipEventElapsedTime(&c, e[2], e[3]);
+            (void)hipEventElapsedTime(&a, e[0], e[1]);
+            (void)hipEventElapsedTime(&b, e[1], e[2]);
+            (void)hipEventElapsedTime(&c, e[2], e[3]);
             out->push_ms += a;
             out->field_ms += b;
             out->push_launches += 1;
@@ -329,7 +329,7 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
             }
         }
         float tot = 0;
-        hipEventElapsedTime(&tot, ev[0], ev[(size_t)n_steps * 4 - 1]);
+        (void)hipEventElapsedTime(&tot, ev[0], ev[(size_t)n_steps * 4 - 1]);
         out->total_ms = tot;
         DevCounters end;
         if (read_counters(h, &end) == PIC_OK) {
@@ -341,6 +341,17 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
     return rc;
+}
+
+pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    const bool ok = (per_thread == 4 && (block == 64 || block == 128 || block == 256 || block == 512)) ||
+                    (per_thread == 8 && (block == 128 || block == 256)) || (per_thread == 2 && block == 256);
+    if (!ok) return fail(PIC_EINVAL, "unsupported push shape (%d threads, %d per thread)", block, per_thread);
+    h->push_block = block;
+    h->push_ppt = per_thread;
+    return PIC_OK;
 }
 
 pic_status pic_sync(pic_handle *h)

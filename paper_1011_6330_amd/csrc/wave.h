@@ -64,3 +64,33 @@ __device__ __forceinline__ void atomic_add_i128(unsigned long long *lo, long lon
 }
 
 }  // namespace pcpic
+
+namespace pcpic {
+
+// DPP move of a double (two 32-bit halves); lanes whose source is outside the
+// pattern read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes, valid in lane 63: inclusive scan inside each row of
+// 16 lanes (row_shr 1, 2, 4, 8), then row 0 -> row 1 and row 2 -> row 3
+// (row_bcast:15), then rows 0-1 -> rows 2-3 (row_bcast:31).  Used on
+// integer-valued doubles below 2^53, where every addition is exact.
+__device__ __forceinline__ double wave_sum_f64_to63(double v)
+{
+    v += dpp_f64<0x111, 0xf>(v);
+    v += dpp_f64<0x112, 0xf>(v);
+    v += dpp_f64<0x114, 0xf>(v);
+    v += dpp_f64<0x118, 0xf>(v);
+    v += dpp_f64<0x142, 0xa>(v);
+    v += dpp_f64<0x143, 0xc>(v);
+    return v;
+}
+
+}  // namespace pcpic

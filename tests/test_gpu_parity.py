@@ -76,6 +76,21 @@ def test_sorted_warm_tube():
     assert d["n_slots"] >= d["n_alive"]
 
 
+@pytest.mark.parametrize("shape", [(64, 4), (128, 4), (256, 2), (256, 4), (512, 4), (128, 8), (256, 8)])
+def test_push_launch_shapes_identical(shape):
+    """Every push launch shape the tuner may pick gives the oracle's state."""
+    N = 2048
+    cfg = dict(synth.preset("c2"), n_cells=N, q_over_m=synth.q_over_m_for(300.0), ppc=30.0,
+               warm=30 * N, capacity=int(30 * N * 1.3), sort_every=16)
+    x, u = synth.warm_start(cfg)
+    say("push shape", shape)
+    g, o = make_pair(cfg, x, u)
+    g.set_push_config(*shape)
+    g.step(50)
+    o.step(50)
+    assert_state_equal(g, o, ordered=False, what=f"shape {shape}")
+
+
 def test_shuffled_load_and_rerun_identical():
     N = 512
     cfg = dict(synth.preset("c1"), n_cells=N, q_over_m=-25.0, ppc=10.0, rho_kind=synth.RHO_FRAME_DRAG,
