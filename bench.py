@@ -42,7 +42,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--push", default="256:2", help="push launch shape threads:slots-per-thread")
+    ap.add_argument("--push", default="64:2:nt", help="push launch shape threads:slots-per-thread[:nt]")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -63,8 +63,9 @@ def main():
     if len(x):
         tube.inject(x, u)
     log("injected", len(x))
-    pb, pp = (int(v) for v in args.push.split(":"))
-    tube.set_push_config(pb, pp)
+    parts = args.push.split(":")
+    pb, pp, pnt = int(parts[0]), int(parts[1]), len(parts) > 2 and parts[2] == "nt"
+    tube.set_push_config(pb, pp, pnt)
     tube.step(args.warmup)
     tube.sync()
     d0 = tube.diagnostics(fields=False)
@@ -98,7 +99,7 @@ def main():
         "data": "synthetic (seeded warm-start beam shaped like the paper's frame-dragging runs)",
         "config": {"workload": WORKLOADS[args.config], "n_cells": int(cfg["n_cells"]),
                    "particles": int(alive_avg), "sort_every": int(cfg["sort_every"]),
-                   "push": f"fp64 {pb}x{pp}"},
+                   "push": f"fp64 {pb}x{pp}{' nt' if pnt else ''}"},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_push_f64", "avg_launch_us": push_avg_s * 1e6,
@@ -109,10 +110,33 @@ def main():
     tube.close()
     del tube
     torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth(torch)
+    result["roofline"]["achievable_copy_gbs"] = copy_gbs
+    result["roofline"]["frac_of_copy"] = achieved_gbs / copy_gbs
+    log(f"copy kernel {copy_gbs:.0f} GB/s; push {achieved_gbs:.0f} GB/s")
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, x, u, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
+    """Achievable HBM bandwidth of a plain device copy (bytes read + written per second)."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / s / 1e9
 
 
 def cpu_baseline(cfg, x, u, seconds):

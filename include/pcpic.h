@@ -65,7 +65,9 @@ enum {
 
 /* Arithmetic of the particle push. */
 enum {
-    PIC_FP64 = 0          /* x, u in FP64; bit-identical to the FP64 CPU oracle    */
+    PIC_FP64 = 0,         /* x, u in FP64; bit-identical to the FP64 CPU oracle            */
+    PIC_FP32_BULK = 1     /* (cell, f32 offset) positions; u in f32 below gamma_fp64 and in
+                             f64 from it on; fields, Gauss residual and E_surf stay FP64    */
 };
 
 /* Goldreich-Julian background (sec. 2, eqs. 5-7), eta = 1 + z/R_*. */
@@ -86,7 +88,7 @@ enum {
 /* Tube description.  Copied by pic_init; the knot array is copied too. */
 typedef struct pic_params {
     int32_t abi_version;      /* must be PCPIC_ABI_VERSION                                  */
-    int32_t precision;        /* PIC_FP64                                                   */
+    int32_t precision;        /* PIC_FP64 or PIC_FP32_BULK                                  */
     int64_t n_cells;          /* N >= 2                                                     */
     double length;            /* L > 0                                                      */
     double radius;            /* R > 0                                                      */
@@ -105,6 +107,7 @@ typedef struct pic_params {
     int64_t capacity;         /* particle capacity (live + not yet compacted)                */
     uint32_t flags;           /* PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS                      */
     int32_t max_bins;         /* largest signed-gamma profile pic_diagnostics may request    */
+    double gamma_fp64;        /* PIC_FP32_BULK: gamma from which u is kept in f64 (0 = 1e6)  */
 } pic_params;
 
 typedef struct pic_handle pic_handle;
@@ -214,11 +217,16 @@ typedef struct pic_timing {
  * Errors: as pic_step, plus PIC_EDEVICE for event failures. */
 pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out);
 
-/* Launch shape of the particle push: threads per block and consecutive particle
- * slots per thread.  Supported pairs: (64|128|256|512, 4), (128|256, 8),
- * (256, 2).  Results do not depend on the choice (integer deposition).
- * Errors: PIC_EINVAL for an unsupported pair. */
-pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread);
+/* pic_set_push_config flags */
+enum {
+    PIC_PUSH_NONTEMPORAL = 1u /* stream particles with nontemporal loads and stores */
+};
+
+/* Launch shape of the particle push: threads per block (64, 128, 256, 512) and
+ * consecutive particle slots per thread (2, or 4 with up to 256 threads).
+ * Results do not depend on the choice (integer deposition); the autotuner
+ * picks the fastest.  Errors: PIC_EINVAL for an unsupported shape or flag. */
+pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread, uint32_t flags);
 
 /* Synchronise the stream; PIC_EDEVSTATUS if a status bit is latched. */
 pic_status pic_sync(pic_handle *h);

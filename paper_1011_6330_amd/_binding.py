@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libpcpic.so")
 
 ABI_VERSION = 1
-FP64 = 0
+FP64, FP32_BULK = 0, 1
 RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS = 0, 1, 2
 NO_AUTO_INJECT, FREEZE_FIELDS = 1, 2
 ST_CAPACITY, ST_NONFINITE = 1, 2
@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_EWORKSPACE", -3: "PIC_EC
 DEFAULTS = dict(precision=FP64, n_cells=1024, length=10.0, radius=1.0, dt_over_dz=0.5,
                 q_over_m=-1.0, ppc=4.0, rho_kind=RHO_UNIFORM, rho_amp=1.0, kappa=0.0,
                 r_star=10.0, knots=None, fp_bits=32, sort_every=0, capacity=1 << 16, flags=0,
-                max_bins=1024)
+                max_bins=1024, gamma_fp64=0.0)
 
 _pd = ctypes.POINTER(ctypes.c_double)
 _pi = ctypes.POINTER(ctypes.c_int64)
@@ -45,7 +45,7 @@ class PicParams(ctypes.Structure):
                 ("r_star", ctypes.c_double), ("knots", _pd),
                 ("fp_bits", ctypes.c_int32), ("sort_every", ctypes.c_int32),
                 ("capacity", ctypes.c_int64), ("flags", ctypes.c_uint32),
-                ("max_bins", ctypes.c_int32)]
+                ("max_bins", ctypes.c_int32), ("gamma_fp64", ctypes.c_double)]
 
 
 class PicDiagReq(ctypes.Structure):
@@ -86,7 +86,8 @@ SIGNATURES = {
     "pic_read_particles": (ctypes.c_int32, [ctypes.c_void_p, _pd, _pd, ctypes.c_int64, _pi]),
     "pic_write_fields": (ctypes.c_int32, [ctypes.c_void_p, _pd, _pd, _pd]),
     "pic_step_timed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(PicTiming)]),
-    "pic_set_push_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "pic_set_push_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_uint32]),
     "pic_sync": (ctypes.c_int32, [ctypes.c_void_p]),
     "pic_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
 }
@@ -135,7 +136,8 @@ def make_params(cfg=None, **kw):
                   float(c["radius"]), float(c["dt_over_dz"]), float(c["q_over_m"]), float(c["ppc"]),
                   int(c["rho_kind"]), 0 if knots is None else len(knots), float(c["rho_amp"]),
                   float(c["kappa"]), float(c["r_star"]), _ptr(knots), int(c["fp_bits"]),
-                  int(c["sort_every"]), int(c["capacity"]), int(c["flags"]), int(c["max_bins"]))
+                  int(c["sort_every"]), int(c["capacity"]), int(c["flags"]), int(c["max_bins"]),
+                  float(c["gamma_fp64"]))
     return p, knots, c
 
 
@@ -196,8 +198,9 @@ class Tube:
         _check(self.lib.pic_step_timed(self._h, int(n), ctypes.byref(t)), "pic_step_timed")
         return {k: getattr(t, k) for k, _ in PicTiming._fields_}
 
-    def set_push_config(self, block, per_thread):
-        _check(self.lib.pic_set_push_config(self._h, int(block), int(per_thread)), "pic_set_push_config")
+    def set_push_config(self, block, per_thread, nontemporal=False):
+        _check(self.lib.pic_set_push_config(self._h, int(block), int(per_thread), 1 if nontemporal else 0),
+               "pic_set_push_config")
 
     def sync(self):
         _check(self.lib.pic_sync(self._h), "pic_sync")

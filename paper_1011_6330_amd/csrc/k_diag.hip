@@ -116,6 +116,7 @@ hipError_t launch_profile(pic_handle *h, int nb)
     const int nbk = nb > 0 ? nb : 1;
     hipLaunchKernelGGL(k_profile_clear, dim3((unsigned)((nbk + 255) / 256)), dim3(256), 0, h->stream, nbk,
                        w.pcount, w.plo, w.phi128, w.pmin, w.pmax, w.ctr);
+    if (nb > 0 && h->p.precision == PIC_FP32_BULK) return launch_profile32(h, nb);
     if (nb > 0)
         hipLaunchKernelGGL(k_profile, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, nb, w.x[h->pbuf],
                            w.u[h->pbuf], w.ctr, w.pcount, w.plo, w.phi128, w.pmin, w.pmax);

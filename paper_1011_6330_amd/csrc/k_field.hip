@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_thomas(Consts c, const double *rhs, dou
 
 // E_z = -dphi/dz at faces, E_r = phi/R at nodes, B_phi = 0, J = 0, kick array.
 __global__ __launch_bounds__(256) void k_fields_from_phi(Consts c, const double *phi, double *ez,
-                                                         double *er, double *b, double *k64,
+                                                         double *er, double *b, double *k64, float *k32,
                                                          int64_t *j0, int64_t *j1)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -140,7 +140,9 @@ __global__ __launch_bounds__(256) void k_fields_from_phi(Consts c, const double 
         const double e = -((phi[i + 1] - phi[i]) / c.dz);
         ez[i] = e;
         b[i] = 0.0;
-        k64[i] = c.qmdt * e;
+        const double kk = c.qmdt * e;
+        k64[i] = kk;
+        if (k32) k32[i] = (float)kk;
         j0[i] = 0;
         j1[i] = 0;
     }
@@ -152,7 +154,10 @@ struct FieldArgs {
     const int64_t *j;               // J^{n+1/2} of this step
     int64_t *jnext;                 // cleared for the next step
     double *k64;
-    double *X, *U;                  // current particle buffer (injection)
+    float *k32;                     // FP32-bulk: f32 kick array (else null)
+    double *X, *U;                  // FP64: current particle buffer (injection)
+    int *CL;                        // FP32-bulk: low stream of the current buffer
+    float *OL, *UL;
     DevCounters *ctr;
 };
 
@@ -191,7 +196,9 @@ __global__ __launch_bounds__(256) void k_field_inject(Consts c, FieldArgs a)
             ez = (a.ezo[i] + c.dtR * bi) - c.c4 * (double)a.j[i];
         }
         a.ezn[i] = ez;
-        a.k64[i] = c.qmdt * ez;
+        const double kk = c.qmdt * ez;
+        a.k64[i] = kk;
+        if (a.k32) a.k32[i] = (float)kk;
         if (i == 0) s_ez0 = ez;
     }
     if (blockIdx.x != 0) return;
@@ -230,8 +237,15 @@ __global__ __launch_bounds__(256) void k_field_inject(Consts c, FieldArgs a)
     __syncthreads();
     const long long base = s_base, n = s_n;
     for (long long p = threadIdx.x; p < n; p += 256) {
-        a.X[base + p] = 0.0;   // electrons leave the surface at rest
-        a.U[base + p] = 0.0;
+        // electrons leave the surface at rest
+        if (a.CL) {
+            a.CL[base + p] = 0;
+            a.OL[base + p] = 0.0f;
+            a.UL[base + p] = 0.0f;
+        } else {
+            a.X[base + p] = 0.0;
+            a.U[base + p] = 0.0;
+        }
     }
 }
 
@@ -242,10 +256,14 @@ __global__ __launch_bounds__(256) void k_fill_i64(int64_t *p, int64_t n, int64_t
 }
 
 // Kick array from E_z (after the caller overwrote the fields).
-__global__ __launch_bounds__(256) void k_kick(Consts c, const double *ez, double *k64)
+__global__ __launch_bounds__(256) void k_kick(Consts c, const double *ez, double *k64, float *k32)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < c.N) k64[i] = c.qmdt * ez[i];
+    if (i < c.N) {
+        const double kk = c.qmdt * ez[i];
+        k64[i] = kk;
+        if (k32) k32[i] = (float)kk;
+    }
 }
 
 // Check appended particles in slots [base, base + n): 0 <= x < N and u finite.
@@ -286,6 +304,7 @@ hipError_t launch_weights(pic_handle *h, int64_t *w_out)
     const Consts &c = h->c;
     hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(c.N + 1, 256)), dim3(256), 0, h->stream, w_out,
                        c.N + 1, (int64_t)0);
+    if (h->p.precision == PIC_FP32_BULK) return launch_weights32(h, w_out);
     hipLaunchKernelGGL(k_weights, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, h->ws.x[h->pbuf],
                        h->ws.ctr, (unsigned long long *)w_out);
     return hipGetLastError();
@@ -302,7 +321,8 @@ hipError_t launch_poisson(pic_handle *h)
     hipLaunchKernelGGL(k_thomas, dim3(1), dim3(256), 0, h->stream, c, w.rhs, w.cp, w.dp, w.phi);
     const int f = h->fbuf;
     hipLaunchKernelGGL(k_fields_from_phi, dim3(grid_for(c.N + 1, 256)), dim3(256), 0, h->stream, c,
-                       w.phi, w.ez[f], w.er[f], w.b[f], w.k64, w.j[0], w.j[1]);
+                       w.phi, w.ez[f], w.er[f], w.b[f], w.k64,
+                       h->p.precision == PIC_FP32_BULK ? w.k32 : nullptr, w.j[0], w.j[1]);
     return hipGetLastError();
 }
 
@@ -311,8 +331,11 @@ hipError_t launch_field_inject(pic_handle *h)
     const Consts &c = h->c;
     Workspace &w = h->ws;
     const int f = h->fbuf, g = 1 - h->fbuf;
+    const bool f32 = h->p.precision == PIC_FP32_BULK;
+    const int b = h->pbuf;
     FieldArgs a{w.ez[f], w.er[f], w.b[f], w.ez[g], w.er[g], w.b[g], w.j[h->jbuf], w.j[1 - h->jbuf],
-                w.k64, w.x[h->pbuf], w.u[h->pbuf], w.ctr};
+                w.k64, f32 ? w.k32 : nullptr, f32 ? nullptr : w.x[b], f32 ? nullptr : w.u[b],
+                f32 ? w.cl[b] : nullptr, f32 ? w.ol[b] : nullptr, f32 ? w.ul[b] : nullptr, w.ctr};
     hipLaunchKernelGGL(k_field_inject, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, a);
     return hipGetLastError();
 }
@@ -334,7 +357,7 @@ hipError_t launch_commit_append(pic_handle *h, int64_t n)
 hipError_t launch_kick(pic_handle *h)
 {
     hipLaunchKernelGGL(k_kick, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c,
-                       h->ws.ez[h->fbuf], h->ws.k64);
+                       h->ws.ez[h->fbuf], h->ws.k64, h->p.precision == PIC_FP32_BULK ? h->ws.k32 : nullptr);
     return hipGetLastError();
 }
 

@@ -7,18 +7,13 @@
 // per live particle and step).  One block owns one tile of BLOCK*PPT
 // consecutive slots and each thread PPT consecutive slots, loaded as 16-byte
 // vectors.  Between cell sorts consecutive slots sit in the same cell, so a
-// thread's current contributions land on three faces (cf-1, cf, cf+1 around
-// the cell cf of its first live particle) and are summed in registers; one
-// DPP reduction per wave and face group then issues a single int64 atomic per
-// face.  Contributions elsewhere go straight to a global atomic.
-//
-// Exactness: every current contribution is an integer below 2^34 held in a
-// double; sums of up to 2^19 of them stay below 2^53, so the register and DPP
-// additions are exact and the int64 atomics make the total order-free.
+// thread's current contributions land on three faces around the cell of its
+// first particle and are summed in registers (DepAcc); one DPP reduction per
+// wave and face group then issues a single int64 atomic per face.
 #include <math.h>
 
 #include "pcpic_internal.h"
-#include "wave.h"
+#include "push_common.h"
 
 namespace pcpic {
 
@@ -30,12 +25,7 @@ struct PushArgs {
     DevCounters *ctr;
 };
 
-__device__ __forceinline__ void atomic_add_face(unsigned long long *J, int f, double v)
-{
-    atomicAdd(J + f, (unsigned long long)(long long)v);
-}
-
-template <int BLOCK, int PPT>
+template <int BLOCK, int PPT, int NT>
 __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
 {
     const int64_t n = a.ctr->n_slots;
@@ -45,13 +35,14 @@ __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
     const int N = (int)c.N;
     const double Nd = (double)c.N, Nm1 = (double)(c.N - 1);
     const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
+    const bool full = p0 + PPT <= n;
 
     double xs[PPT], us[PPT];
-    if (p0 + PPT <= n) {
+    if (full) {
 #pragma unroll
         for (int k = 0; k < PPT; k += 2) {
-            const double2 xv = *reinterpret_cast<const double2 *>(a.X + p0 + k);
-            const double2 uv = *reinterpret_cast<const double2 *>(a.U + p0 + k);
+            const dvec2 xv = ld16<NT, dvec2>(a.X + p0 + k);
+            const dvec2 uv = ld16<NT, dvec2>(a.U + p0 + k);
             xs[k] = xv.x; xs[k + 1] = xv.y;
             us[k] = uv.x; us[k + 1] = uv.y;
         }
@@ -63,11 +54,8 @@ __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
         }
     }
 
-    int cf = -2;                                  // cell of the first live particle
-    double acc_m = 0.0, acc_0 = 0.0, acc_p = 0.0; // faces cf-1, cf, cf+1
-    double w0 = 0.0, nexit = 0.0, nabs = 0.0, nlost = 0.0, g_int = 0.0, g_frac = 0.0;
-    bool bad = false;
-
+    DepAcc acc;
+    acc.init();
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const double x = xs[k], u = us[k];
@@ -88,63 +76,36 @@ __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
         const double v = u1 / gam;
         const double x1 = x + c.dtdz * v;
         if (!isfinite(u1) || !isfinite(x1)) {
-            bad = true;
-            nlost += 1.0;
+            acc.bad = true;
+            acc.nlost += 1.0;
             xs[k] = -1.0;
             continue;
         }
-        // charge-conserving current J_{i+1/2} += S_i(x^n) - S_i(x^{n+1}): nonzero on
-        // the old cell's face and, after a crossing, on the new cell's face
         const double c0d = floor(x);
-        const int c0 = (int)c0d;
         const double F0 = rint((x - c0d) * c.twoP);
         const double c1d = floor(x1);
         const int c1 = (int)c1d;
         const double F1 = rint((x1 - c1d) * c.twoP);
-        double va, vb = 0.0;
-        bool hb = false;
-        if (c1 == c0) {
-            va = F1 - F0;
-        } else if (c1 > c0) {
-            va = c.twoP - F0;
-            if (c1 < N) { vb = F1; hb = true; }
-        } else {
-            va = -F0;
-            if (c1 >= 0) { vb = F1 - c.twoP; hb = true; }
-        }
-        if (cf == -2) cf = c0;
-        if (c0 == cf) {
-            acc_0 += va;
-            if (hb) {
-                if (c1 > c0) acc_p += vb;
-                else acc_m += vb;
-            }
-        } else {
-            if (va != 0.0) atomic_add_face(a.J, c0, va);
-            if (hb && vb != 0.0) atomic_add_face(a.J, c1, vb);
-        }
+        acc.deposit(a.J, N, c.twoP, (int)c0d, F0, c1, F1);
         if (x1 >= Nd) {                          // leaves through z = L
-            nexit += 1.0;
-            const double gi = floor(gam);
-            g_int += gi;
-            g_frac += rint((gam - gi) * 4294967296.0);
+            acc.exit_gamma(gam);
             xs[k] = -1.0;
         } else if (x1 < 0.0) {                   // returns to the star
-            nabs += 1.0;
+            acc.nabs += 1.0;
             xs[k] = -1.0;
         } else {
-            if (c1 == 0) w0 += c.twoP - F1;
+            if (c1 == 0) acc.w0 += c.twoP - F1;
             xs[k] = x1;
             us[k] = u1;
         }
     }
 
     // write back (removed particles get x = -1; their u is left as it was)
-    if (p0 + PPT <= n) {
+    if (full) {
 #pragma unroll
         for (int k = 0; k < PPT; k += 2) {
-            *reinterpret_cast<double2 *>(a.X + p0 + k) = make_double2(xs[k], xs[k + 1]);
-            *reinterpret_cast<double2 *>(a.U + p0 + k) = make_double2(us[k], us[k + 1]);
+            st16<NT, dvec2>(a.X + p0 + k, dvec2{xs[k], xs[k + 1]});
+            st16<NT, dvec2>(a.U + p0 + k, dvec2{us[k], us[k + 1]});
         }
     } else {
 #pragma unroll
@@ -155,73 +116,40 @@ __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
             }
         }
     }
-
-    // one atomic per face group and wave: lanes sharing cf are summed together
-    const int lane = __lane_id();
-    bool want = cf != -2 && (acc_m != 0.0 || acc_0 != 0.0 || acc_p != 0.0);
-    unsigned long long pend = __ballot(want);
-    while (pend) {
-        const int leader = __ffsll(pend) - 1;
-        const int lk = __shfl(cf, leader);
-        const bool mine = want && cf == lk;
-        const double sm = wave_sum_f64_to63(mine ? acc_m : 0.0);
-        const double s0 = wave_sum_f64_to63(mine ? acc_0 : 0.0);
-        const double sp = wave_sum_f64_to63(mine ? acc_p : 0.0);
-        if (lane == 63) {
-            if (sm != 0.0) atomic_add_face(a.J, lk - 1, sm);
-            if (s0 != 0.0) atomic_add_face(a.J, lk, s0);
-            if (sp != 0.0) atomic_add_face(a.J, lk + 1, sp);
-        }
-        pend &= ~__ballot(mine);
-        want = want && !mine;
-    }
-
-    // per-wave tallies
-    DevCounters *ctr = a.ctr;
-    const unsigned long long any = __ballot(w0 != 0.0 || nexit != 0.0 || nabs != 0.0 || nlost != 0.0);
-    if (any) {
-        w0 = wave_sum_f64_to63(w0);
-        nexit = wave_sum_f64_to63(nexit);
-        nabs = wave_sum_f64_to63(nabs);
-        nlost = wave_sum_f64_to63(nlost);
-        g_int = wave_sum_f64_to63(g_int);
-        g_frac = wave_sum_f64_to63(g_frac);
-        if (lane == 63) {
-            if (w0 != 0.0) atomicAdd((unsigned long long *)&ctr->w0, (unsigned long long)(long long)w0);
-            if (nexit != 0.0) {
-                atomicAdd((unsigned long long *)&ctr->n_exit, (unsigned long long)(long long)nexit);
-                const __int128 sum = ((__int128)(long long)g_int << 32) + (__int128)(long long)g_frac;
-                atomic_add_i128(&ctr->exit_lo, &ctr->exit_hi, sum);
-            }
-            if (nabs != 0.0) atomicAdd((unsigned long long *)&ctr->n_absorb, (unsigned long long)(long long)nabs);
-            const double rem = nexit + nabs + nlost;
-            if (rem != 0.0) atomicAdd((unsigned long long *)&ctr->n_removed, (unsigned long long)(long long)rem);
-        }
-    }
-    if (__ballot(bad) && lane == 0) atomicOr(&ctr->status, (unsigned long long)PIC_ST_NONFINITE);
+    acc.flush(a.J, a.ctr);
 }
 
-template <int BLOCK, int PPT>
+template <int BLOCK, int PPT, int NT>
 static hipError_t launch_push_t(pic_handle *h)
 {
     PushArgs a{h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.k64,
                (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr};
     const int64_t tile = (int64_t)BLOCK * PPT;
     const unsigned grid = (unsigned)((h->c.cap + tile - 1) / tile);
-    hipLaunchKernelGGL((k_push_f64<BLOCK, PPT>), dim3(grid), dim3(BLOCK), 0, h->stream, h->c, a);
+    hipLaunchKernelGGL((k_push_f64<BLOCK, PPT, NT>), dim3(grid), dim3(BLOCK), 0, h->stream, h->c, a);
     return hipGetLastError();
 }
 
 hipError_t launch_push_f64(pic_handle *h)
 {
     const int B = h->push_block, P = h->push_ppt;
-    if (B == 256 && P == 4) return launch_push_t<256, 4>(h);
-    if (B == 256 && P == 2) return launch_push_t<256, 2>(h);
-    if (B == 256 && P == 8) return launch_push_t<256, 8>(h);
-    if (B == 128 && P == 4) return launch_push_t<128, 4>(h);
-    if (B == 512 && P == 4) return launch_push_t<512, 4>(h);
-    if (B == 64 && P == 4) return launch_push_t<64, 4>(h);
-    if (B == 128 && P == 8) return launch_push_t<128, 8>(h);
+    if (h->push_nt) {
+        if (B == 256 && P == 2) return launch_push_t<256, 2, 1>(h);
+        if (B == 128 && P == 2) return launch_push_t<128, 2, 1>(h);
+        if (B == 64 && P == 2) return launch_push_t<64, 2, 1>(h);
+        if (B == 512 && P == 2) return launch_push_t<512, 2, 1>(h);
+        if (B == 256 && P == 4) return launch_push_t<256, 4, 1>(h);
+        if (B == 128 && P == 4) return launch_push_t<128, 4, 1>(h);
+        if (B == 64 && P == 4) return launch_push_t<64, 4, 1>(h);
+        return hipErrorInvalidValue;
+    }
+    if (B == 256 && P == 2) return launch_push_t<256, 2, 0>(h);
+    if (B == 128 && P == 2) return launch_push_t<128, 2, 0>(h);
+    if (B == 64 && P == 2) return launch_push_t<64, 2, 0>(h);
+    if (B == 512 && P == 2) return launch_push_t<512, 2, 0>(h);
+    if (B == 256 && P == 4) return launch_push_t<256, 4, 0>(h);
+    if (B == 128 && P == 4) return launch_push_t<128, 4, 0>(h);
+    if (B == 64 && P == 4) return launch_push_t<64, 4, 0>(h);
     return hipErrorInvalidValue;
 }
 

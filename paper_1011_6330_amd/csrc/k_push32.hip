@@ -1,0 +1,542 @@
+// k_push32.hip -- the FP32-bulk particle path.
+//
+// Particles live in two SoA streams, both positioned as (cell i32, offset f32
+// in [0, 1)) so that FP32 keeps its 24 bits of resolution inside a cell of a
+// tube of any length:
+//   low stream  (gamma below the threshold): u = gamma*beta in f32, 12 B/slot;
+//               kick from the f32 kick array, v = u * rsqrt(1 + u^2) (never
+//               formed from gamma, so nothing cancels near v = c);
+//   high stream (gamma at or above the threshold, 1e6 by default): u in f64,
+//               16 B/slot; kick, gamma and v in f64 exactly as the FP64 path.
+// The deposit takes F = rint(2^P offset) of the stored offsets, so charge
+// conservation stays exact.  Fields, the Gauss residual, E_surf and the kick
+// arrays stay FP64.  The cell sort moves particles between the streams.
+#include <math.h>
+
+#include "pcpic_internal.h"
+#include "push_common.h"
+
+namespace pcpic {
+
+struct Push32Args {
+    int *__restrict__ CL;
+    float *__restrict__ OL;
+    float *__restrict__ UL;
+    int *__restrict__ CH;
+    float *__restrict__ OH;
+    double *__restrict__ UH;
+    const float *__restrict__ K32;
+    const double *__restrict__ K64;
+    unsigned long long *__restrict__ J;
+    DevCounters *ctr;
+    unsigned blocks_lo;     // grid blocks [0, blocks_lo) serve the low stream
+};
+
+// Offset update with the carry into the next or previous cell (|move| < 1 cell).
+// An offset that rounds to 1.0f is stored as (cell + 1, 0).
+__device__ __forceinline__ void carry_f32(float &o, int &cell)
+{
+    if (o >= 1.0f) {
+        o -= 1.0f;
+        cell += 1;
+    } else if (o < 0.0f) {
+        o += 1.0f;
+        cell -= 1;
+        if (o >= 1.0f) { o = 0.0f; cell += 1; }
+    }
+}
+
+template <int BLOCK, int NT>
+__global__ __launch_bounds__(BLOCK) void k_push_f32(Consts c, Push32Args a)
+{
+    constexpr int PPT = 4;
+    constexpr int TILE = BLOCK * PPT;
+    const bool hi = blockIdx.x >= a.blocks_lo;
+    const int64_t b = hi ? (int64_t)(blockIdx.x - a.blocks_lo) : (int64_t)blockIdx.x;
+    const int64_t n = hi ? a.ctr->n_slots_hi : a.ctr->n_slots;
+    const int64_t tile0 = b * TILE;
+    if (tile0 >= n) return;                       // whole block idle (uniform)
+    const int N = (int)c.N;
+    const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
+    const bool full = p0 + PPT <= n;
+    int *C = hi ? a.CH : a.CL;
+    float *O = hi ? a.OH : a.OL;
+
+    int cs[PPT];
+    float os[PPT];
+    if (full) {
+        const ivec4 cv = ld16<NT, ivec4>(C + p0);
+        const fvec4 ov = ld16<NT, fvec4>(O + p0);
+        cs[0] = cv.x; cs[1] = cv.y; cs[2] = cv.z; cs[3] = cv.w;
+        os[0] = ov.x; os[1] = ov.y; os[2] = ov.z; os[3] = ov.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            cs[k] = p0 + k < n ? C[p0 + k] : -1;
+            os[k] = p0 + k < n ? O[p0 + k] : 0.0f;
+        }
+    }
+    DepAcc acc;
+    acc.init();
+
+    if (!hi) {
+        // ---------------- low stream: FP32 momentum ----------------
+        float us[PPT];
+        if (full) {
+            const fvec4 uv = ld16<NT, fvec4>(a.UL + p0);
+            us[0] = uv.x; us[1] = uv.y; us[2] = uv.z; us[3] = uv.w;
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) us[k] = p0 + k < n ? a.UL[p0 + k] : 0.0f;
+        }
+        const float dtdz = (float)c.dtdz;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int cell = cs[k];
+            if (cell < 0) continue;              // removed slot or past the end
+            const float off = os[k], u = us[k];
+            // gather between the faces around x = cell + off, clamped at the ends
+            const int j = off < 0.5f ? cell - 1 : cell;
+            const float g = off < 0.5f ? off + 0.5f : off - 0.5f;
+            const int jc = j < 0 ? 0 : (j > N - 2 ? N - 2 : j);
+            const float k0 = a.K32[jc], k1 = a.K32[jc + 1];
+            const float E = j < 0 ? k0 : (j >= N - 1 ? k1 : k0 + g * (k1 - k0));
+            const float u1 = u + E;
+            float t = u1 * u1;
+            t = 1.0f + t;
+            const float v = u1 * __builtin_amdgcn_rsqf(t);
+            float o1 = off + dtdz * v;
+            int c1 = cell;
+            carry_f32(o1, c1);
+            if (!isfinite(u1) || !isfinite(o1)) {
+                acc.bad = true;
+                acc.nlost += 1.0;
+                cs[k] = -1;
+                continue;
+            }
+            const double F0 = rint((double)off * c.twoP);
+            const double F1 = rint((double)o1 * c.twoP);
+            acc.deposit(a.J, N, c.twoP, cell, F0, c1, F1);
+            if (c1 >= N) {
+                const double ud = (double)u1;
+                double tt = ud * ud;
+                tt = 1.0 + tt;
+                acc.exit_gamma(sqrt(tt));
+                cs[k] = -1;
+            } else if (c1 < 0) {
+                acc.nabs += 1.0;
+                cs[k] = -1;
+            } else {
+                if (c1 == 0) acc.w0 += c.twoP - F1;
+                cs[k] = c1;
+                os[k] = o1;
+                us[k] = u1;
+            }
+        }
+        if (full) {
+            st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
+            st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
+            st16<NT, fvec4>(a.UL + p0, fvec4{us[0], us[1], us[2], us[3]});
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UL[p0 + k] = us[k]; }
+        }
+    } else {
+        // ---------------- high stream: FP64 momentum ----------------
+        double us[PPT];
+        if (full) {
+            const dvec2 u01 = ld16<NT, dvec2>(a.UH + p0);
+            const dvec2 u23 = ld16<NT, dvec2>(a.UH + p0 + 2);
+            us[0] = u01.x; us[1] = u01.y; us[2] = u23.x; us[3] = u23.y;
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) us[k] = p0 + k < n ? a.UH[p0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int cell = cs[k];
+            if (cell < 0) continue;
+            const float off = os[k];
+            const double u = us[k];
+            const int j = off < 0.5f ? cell - 1 : cell;
+            const float g = off < 0.5f ? off + 0.5f : off - 0.5f;
+            const int jc = j < 0 ? 0 : (j > N - 2 ? N - 2 : j);
+            const double k0 = a.K64[jc], k1 = a.K64[jc + 1];
+            const double E = j < 0 ? k0 : (j >= N - 1 ? k1 : k0 + (double)g * (k1 - k0));
+            const double u1 = u + E;
+            double tt = u1 * u1;
+            tt = 1.0 + tt;
+            const double gam = sqrt(tt);
+            const double v = u1 / gam;
+            double od = (double)off + c.dtdz * v;
+            int c1 = cell;
+            if (od >= 1.0) {
+                od -= 1.0;
+                c1 += 1;
+            } else if (od < 0.0) {
+                od += 1.0;
+                c1 -= 1;
+            }
+            float o1 = (float)od;
+            if (o1 >= 1.0f) { o1 = 0.0f; c1 += 1; }
+            if (!isfinite(u1) || !isfinite(od)) {
+                acc.bad = true;
+                acc.nlost += 1.0;
+                cs[k] = -1;
+                continue;
+            }
+            const double F0 = rint((double)off * c.twoP);
+            const double F1 = rint((double)o1 * c.twoP);
+            acc.deposit(a.J, N, c.twoP, cell, F0, c1, F1);
+            if (c1 >= N) {
+                acc.exit_gamma(gam);
+                cs[k] = -1;
+            } else if (c1 < 0) {
+                acc.nabs += 1.0;
+                cs[k] = -1;
+            } else {
+                if (c1 == 0) acc.w0 += c.twoP - F1;
+                cs[k] = c1;
+                os[k] = o1;
+                us[k] = u1;
+            }
+        }
+        if (full) {
+            st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
+            st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
+            st16<NT, dvec2>(a.UH + p0, dvec2{us[0], us[1]});
+            st16<NT, dvec2>(a.UH + p0 + 2, dvec2{us[2], us[3]});
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UH[p0 + k] = us[k]; }
+        }
+    }
+    acc.flush(a.J, a.ctr);
+}
+
+// ------------------------------------------------------------------------
+// diagnostics, sort and append for the two streams
+// ------------------------------------------------------------------------
+
+struct Streams {
+    int *CL;
+    float *OL;
+    float *UL;
+    int *CH;
+    float *OH;
+    double *UH;
+};
+
+// Blocks [0, nb_lo) walk the low stream, the rest the high stream, grid-stride.
+__device__ __forceinline__ bool stream_slot(const DevCounters *ctr, unsigned nb_lo, int64_t &first,
+                                            int64_t &stride, int64_t &n)
+{
+    const bool hi = blockIdx.x >= nb_lo;
+    const int64_t b = hi ? blockIdx.x - nb_lo : blockIdx.x;
+    const int64_t nb = hi ? gridDim.x - nb_lo : nb_lo;
+    n = hi ? ctr->n_slots_hi : ctr->n_slots;
+    first = b * 256;
+    stride = nb * 256;
+    return hi;
+}
+
+__global__ __launch_bounds__(256) void k_weights32(Consts c, Streams s, const DevCounters *ctr, unsigned nb_lo,
+                                                   unsigned long long *w)
+{
+    int64_t first, stride, n;
+    const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
+    const int *C = hi ? s.CH : s.CL;
+    const float *O = hi ? s.OH : s.OL;
+    for (int64_t base = first; base < n; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        const int cell = p < n ? C[p] : -1;
+        const bool live = cell >= 0;
+        int64_t F = 0;
+        if (live) F = (int64_t)rint((double)O[p] * c.twoP);
+        wave_add_keyed(w, cell, c.oneP - F, live);
+        wave_add_keyed(w, cell + 1, F, live);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_profile32(Consts c, int nb, Streams s, const DevCounters *ctr,
+                                                   unsigned nb_lo, long long *cnt, unsigned long long *lo,
+                                                   long long *hi128, long long *mn, long long *mx)
+{
+    int64_t first, stride, n;
+    const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
+    const int *C = hi ? s.CH : s.CL;
+    const float *O = hi ? s.OH : s.OL;
+    for (int64_t base = first; base < n; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        const int cell = p < n ? C[p] : -1;
+        bool want = cell >= 0;
+        int64_t bin = 0, gi = 0, gf = 0;
+        long long ob = 0;
+        if (want) {
+            const double u = hi ? s.UH[p] : (double)s.UL[p];
+            const double x = (double)cell + (double)O[p];
+            double t = u * u;
+            t = 1.0 + t;
+            const double gam = sqrt(t);
+            const double sg = u < 0.0 ? -gam : gam;
+            bin = (int64_t)floor((x * (double)nb) / (double)c.N);
+            if (bin < 0) bin = 0;
+            if (bin > nb - 1) bin = nb - 1;
+            const double fl = floor(sg);
+            gi = (int64_t)fl;
+            gf = (int64_t)rint((sg - fl) * 4294967296.0);
+            ob = ordered_bits(sg);
+        }
+        unsigned long long pend = __ballot(want);
+        while (pend) {
+            const int leader = __ffsll(pend) - 1;
+            const int64_t lb = __shfl(bin, leader);
+            const bool mine = want && bin == lb;
+            const int64_t sc = wave_sum_i64(mine ? 1 : 0);
+            const int64_t si = wave_sum_i64(mine ? gi : 0);
+            const int64_t sf = wave_sum_i64(mine ? gf : 0);
+            const long long smin = wave_min_i64(mine ? ob : 0x7fffffffffffffffLL);
+            const long long smax = wave_max_i64(mine ? ob : (long long)0x8000000000000000ULL);
+            if ((int)__lane_id() == leader) {
+                atomicAdd((unsigned long long *)&cnt[lb], (unsigned long long)sc);
+                atomic_add_i128(&lo[lb], &hi128[lb], ((__int128)si << 32) + (__int128)sf);
+                atomicMin(&mn[lb], smin);
+                atomicMax(&mx[lb], smax);
+            }
+            pend &= ~__ballot(mine);
+            want = want && !mine;
+        }
+    }
+}
+
+// Destination stream of a particle: the high stream from |u| >= u_hi on.
+__device__ __forceinline__ bool goes_high(double u, double u_hi) { return fabs(u) >= u_hi; }
+
+// Histogram for the sort: key = cell for the low destination, N + 1 + cell for the high one.
+__global__ __launch_bounds__(256) void k_hist32(Consts c, Streams s, const DevCounters *ctr, unsigned nb_lo,
+                                                double u_hi, unsigned long long *count)
+{
+    int64_t first, stride, n;
+    const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
+    const int *C = hi ? s.CH : s.CL;
+    for (int64_t base = first; base < n; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        const int cell = p < n ? C[p] : -1;
+        const bool live = cell >= 0;
+        int64_t key = 0;
+        if (live) {
+            const double u = hi ? s.UH[p] : (double)s.UL[p];
+            key = goes_high(u, u_hi) ? (int64_t)c.N + 1 + cell : cell;
+        }
+        wave_add_keyed(count, key, 1, live);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter32(Consts c, Streams src, Streams dst, const DevCounters *ctr,
+                                                   unsigned nb_lo, double u_hi, unsigned long long *off,
+                                                   const long long *total_lo)
+{
+    int64_t first, stride, n;
+    const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
+    const int *C = hi ? src.CH : src.CL;
+    const float *O = hi ? src.OH : src.OL;
+    const long long tlo = *total_lo;
+    const int lane = __lane_id();
+    for (int64_t base = first; base < n; base += stride) {
+        const int64_t p = base + threadIdx.x;
+        const int cell = p < n ? C[p] : -1;
+        bool want = cell >= 0;
+        float o = 0.0f;
+        double u = 0.0;
+        int64_t key = 0;
+        if (want) {
+            o = O[p];
+            u = hi ? src.UH[p] : (double)src.UL[p];
+            key = goes_high(u, u_hi) ? (int64_t)c.N + 1 + cell : cell;
+        }
+        unsigned long long pend = __ballot(want);
+        while (pend) {
+            const int leader = __ffsll(pend) - 1;
+            const int64_t lk = __shfl(key, leader);
+            const bool mine = want && key == lk;
+            const unsigned long long grp = __ballot(mine);
+            unsigned long long f0 = 0;
+            if (lane == leader) f0 = atomicAdd(off + lk, (unsigned long long)__popcll(grp));
+            f0 = __shfl(f0, leader);
+            if (mine) {
+                const int64_t d = (int64_t)f0 + __popcll(grp & ((1ull << lane) - 1ull));
+                if (key > (int64_t)c.N) {
+                    const int64_t q = d - tlo;
+                    dst.CH[q] = cell;
+                    dst.OH[q] = o;
+                    dst.UH[q] = u;
+                } else {
+                    dst.CL[d] = cell;
+                    dst.OL[d] = o;
+                    dst.UL[d] = (float)u;
+                }
+            }
+            pend &= ~grp;
+            want = want && !mine;
+        }
+    }
+}
+
+// Low-destination total = exclusive offset of the first high key; copied before
+// the scatter's atomics advance that offset.
+__global__ void k_copy_total(const long long *src, long long *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+__global__ void k_sort32_finish(DevCounters *ctr, const long long *total_lo)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const long long lo = *total_lo;
+        ctr->n_slots_hi = ctr->n_alive - lo;
+        ctr->n_slots = lo;
+        ctr->n_removed = 0;
+    }
+}
+
+// Staged particles (x in cell units, u) -> validity count.
+__global__ __launch_bounds__(256) void k_check_staged(Consts c, const double *X, const double *U, int64_t n,
+                                                      DevCounters *ctr)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool bad = false;
+    if (i < n) bad = !(X[i] >= 0.0 && X[i] < (double)c.N) || !isfinite(U[i]);
+    const int64_t nb = wave_sum_i64(bad ? 1 : 0);
+    if (__lane_id() == 0 && nb) atomicAdd((unsigned long long *)&ctr->bad_inputs, (unsigned long long)nb);
+}
+
+// Staged particles -> (cell, f32 offset) and the stream their gamma selects.
+__global__ __launch_bounds__(256) void k_append_staged(Consts c, const double *X, const double *U, int64_t n,
+                                                       Streams s, double u_hi, DevCounters *ctr)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = __lane_id();
+    bool want = i < n;
+    double x = 0.0, u = 0.0;
+    if (want) { x = X[i]; u = U[i]; }
+    const bool high = want && goes_high(u, u_hi);
+    int cell = 0;
+    float o = 0.0f;
+    if (want) {
+        const double cd = floor(x);
+        cell = (int)cd;
+        o = (float)(x - cd);
+        if (o >= 1.0f) { o = 0.0f; cell += 1; }
+    }
+    for (int sidx = 0; sidx < 2; ++sidx) {
+        const bool mine = want && (high == (sidx == 1));
+        const unsigned long long grp = __ballot(mine);
+        if (!grp) continue;
+        const int leader = __ffsll(grp) - 1;
+        unsigned long long f0 = 0;
+        if (lane == leader)
+            f0 = atomicAdd((unsigned long long *)(sidx ? &ctr->n_slots_hi : &ctr->n_slots),
+                           (unsigned long long)__popcll(grp));
+        f0 = __shfl(f0, leader);
+        if (mine) {
+            const int64_t d = (int64_t)f0 + __popcll(grp & ((1ull << lane) - 1ull));
+            if (sidx) { s.CH[d] = cell; s.OH[d] = o; s.UH[d] = u; }
+            else { s.CL[d] = cell; s.OL[d] = o; s.UL[d] = (float)u; }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+
+static Streams streams_of(pic_handle *h, int b)
+{
+    const Workspace &w = h->ws;
+    return Streams{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b]};
+}
+
+template <int BLOCK, int NT>
+static hipError_t launch_push32_t(pic_handle *h)
+{
+    const Workspace &w = h->ws;
+    const int b = h->pbuf;
+    const int64_t tile = (int64_t)BLOCK * 4;
+    const unsigned nb = (unsigned)((h->c.cap + tile - 1) / tile);
+    Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b], w.k32, w.k64,
+                 (unsigned long long *)w.j[h->jbuf], w.ctr, nb};
+    hipLaunchKernelGGL((k_push_f32<BLOCK, NT>), dim3(2 * nb), dim3(BLOCK), 0, h->stream, h->c, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_f32(pic_handle *h)
+{
+    const int B = h->push_block;
+    if (h->push_nt) {
+        if (B == 64) return launch_push32_t<64, 1>(h);
+        if (B == 128) return launch_push32_t<128, 1>(h);
+        if (B == 256) return launch_push32_t<256, 1>(h);
+        if (B == 512) return launch_push32_t<512, 1>(h);
+    } else {
+        if (B == 64) return launch_push32_t<64, 0>(h);
+        if (B == 128) return launch_push32_t<128, 0>(h);
+        if (B == 256) return launch_push32_t<256, 0>(h);
+        if (B == 512) return launch_push32_t<512, 0>(h);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_weights32(pic_handle *h, int64_t *w_out)
+{
+    const unsigned nb = (unsigned)(h->n_cu * 4);
+    hipLaunchKernelGGL(k_weights32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, streams_of(h, h->pbuf), h->ws.ctr,
+                       nb, (unsigned long long *)w_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile32(pic_handle *h, int nbins)
+{
+    const Workspace &w = h->ws;
+    const unsigned nb = (unsigned)(h->n_cu * 4);
+    hipLaunchKernelGGL(k_profile32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, nbins, streams_of(h, h->pbuf),
+                       w.ctr, nb, w.pcount, w.plo, w.phi128, w.pmin, w.pmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort32_hist(pic_handle *h)
+{
+    const unsigned nb = (unsigned)(h->n_cu * 4);
+    hipLaunchKernelGGL(k_hist32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, streams_of(h, h->pbuf), h->ws.ctr, nb,
+                       h->u_hi, (unsigned long long *)h->ws.cell_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort32_scatter(pic_handle *h)
+{
+    const unsigned nb = (unsigned)(h->n_cu * 4);
+    const int src = h->pbuf, dst = 1 - h->pbuf;
+    hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64), 0, h->stream, (const long long *)(h->ws.cell_off + h->c.N + 1),
+                       h->ws.total_lo);
+    hipLaunchKernelGGL(k_scatter32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, streams_of(h, src),
+                       streams_of(h, dst), h->ws.ctr, nb, h->u_hi, (unsigned long long *)h->ws.cell_off,
+                       (const long long *)h->ws.total_lo);
+    hipLaunchKernelGGL(k_sort32_finish, dim3(1), dim3(64), 0, h->stream, h->ws.ctr,
+                       (const long long *)(h->ws.total_lo));
+    return hipGetLastError();
+}
+
+hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only)
+{
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (check_only)
+        hipLaunchKernelGGL(k_check_staged, dim3(g), dim3(256), 0, h->stream, h->c, h->ws.stage_x, h->ws.stage_u, n,
+                           h->ws.ctr);
+    else
+        hipLaunchKernelGGL(k_append_staged, dim3(g), dim3(256), 0, h->stream, h->c, h->ws.stage_x, h->ws.stage_u, n,
+                           streams_of(h, h->pbuf), h->u_hi, h->ws.ctr);
+    return hipGetLastError();
+}
+
+}  // namespace pcpic

@@ -148,22 +148,40 @@ __global__ void k_sort_finish(DevCounters *ctr)
     }
 }
 
+hipError_t launch_scan(pic_handle *h, int64_t n)
+{
+    Workspace &w = h->ws;
+    const unsigned nblk = (unsigned)((n + SCAN_TILE - 1) / SCAN_TILE);
+    hipLaunchKernelGGL(k_scan_totals, dim3(nblk), dim3(SCAN_BLOCK), 0, h->stream, w.cell_count, n, w.blk_sum);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, h->stream, w.blk_sum, (int64_t)nblk, w.ctr);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(SCAN_BLOCK), 0, h->stream, w.cell_count, n, w.blk_sum,
+                       w.cell_off);
+    return hipGetLastError();
+}
+
+// Counting sort by cell into the other particle buffer, dropping removed slots;
+// in FP32-bulk mode the destination stream follows the particle's gamma.
 hipError_t launch_sort(pic_handle *h)
 {
     const Consts &c = h->c;
     Workspace &w = h->ws;
     const int64_t N = c.N;
-    const unsigned nblk = (unsigned)((N + SCAN_TILE - 1) / SCAN_TILE);
+    const bool f32 = h->p.precision == PIC_FP32_BULK;
+    const int64_t nkeys = f32 ? 2 * (N + 1) : N;
     const int src = h->pbuf, dst = 1 - h->pbuf;
-    hipLaunchKernelGGL(k_fill_ll, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, h->stream, w.cell_count, N);
-    hipLaunchKernelGGL(k_hist, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.ctr, w.cell_count);
-    hipLaunchKernelGGL(k_scan_totals, dim3(nblk), dim3(SCAN_BLOCK), 0, h->stream, w.cell_count, N, w.blk_sum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, h->stream, w.blk_sum, (int64_t)nblk, w.ctr);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(SCAN_BLOCK), 0, h->stream, w.cell_count, N, w.blk_sum,
-                       w.cell_off);
-    hipLaunchKernelGGL(k_scatter, dim3(h->n_cu * 8), dim3(256), 0, h->stream, w.x[src], w.u[src], w.x[dst],
-                       w.u[dst], w.ctr, (unsigned long long *)w.cell_off);
-    hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, h->stream, w.ctr);
+    hipLaunchKernelGGL(k_fill_ll, dim3((unsigned)((nkeys + 255) / 256)), dim3(256), 0, h->stream, w.cell_count, nkeys);
+    hipError_t e;
+    if (f32) {
+        if ((e = launch_sort32_hist(h)) != hipSuccess) return e;
+        if ((e = launch_scan(h, nkeys)) != hipSuccess) return e;
+        if ((e = launch_sort32_scatter(h)) != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_hist, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.ctr, w.cell_count);
+        if ((e = launch_scan(h, nkeys)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_scatter, dim3(h->n_cu * 8), dim3(256), 0, h->stream, w.x[src], w.u[src], w.x[dst],
+                           w.u[dst], w.ctr, (unsigned long long *)w.cell_off);
+        hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, h->stream, w.ctr);
+    }
     h->pbuf = dst;
     return hipGetLastError();
 }

@@ -68,10 +68,21 @@ struct DevCounters {
     unsigned long long gauss_max_bits;  // diagnostics: max |G| (non-negative double bits)
     unsigned long long rho_max_bits;    // max |rho_GJ| (non-negative double bits)
     int64_t bad_inputs;                 // rejected particles of the last pic_inject
+    int64_t n_slots_hi;                 // FP32-bulk: occupied slots of the high-gamma stream
 };
 
 struct Workspace {
     double *x[2], *u[2];    // particle double buffer (FP64)
+    // FP32-bulk streams (double-buffered): low (cell, offset, u f32), high (cell, offset, u f64)
+    int *cl[2];
+    float *ol[2], *ul[2];
+    int *ch[2];
+    float *oh[2];
+    double *uh[2];
+    float *k32;             // f32 kick array (FP32-bulk low stream)
+    double *stage_x, *stage_u;  // FP32-bulk: staging of injected particles
+    int64_t stage_cap;
+    long long *total_lo;    // FP32-bulk sort: low-destination total
     double *ez[2], *er[2], *b[2];
     int64_t *j[2];          // fixed-point current, ping-pong per step
     double *k64;            // kick array (q/m) dt E_z
@@ -109,8 +120,10 @@ struct pic_handle {
     int fbuf = 0;       // field buffer holding E^n, B^{n-1/2}
     int jbuf = 0;       // current buffer that the next step deposits into
     int64_t step = 0;   // steps enqueued
-    int push_block = 256;
+    int push_block = 64;
     int push_ppt = 2;
+    int push_nt = 1;    // nontemporal particle-stream access
+    double u_hi = 0.0;  // FP32-bulk: |u| from which a particle belongs to the FP64 stream
     int push_grid = 0;  // 0 = derived from the device
     int n_cu = 256;
 };
@@ -122,6 +135,13 @@ hipError_t launch_rho_gj(pic_handle *h);
 hipError_t launch_weights(pic_handle *h, int64_t *w_out);
 hipError_t launch_poisson(pic_handle *h);
 hipError_t launch_push_f64(pic_handle *h);
+hipError_t launch_push_f32(pic_handle *h);
+hipError_t launch_weights32(pic_handle *h, int64_t *w_out);
+hipError_t launch_profile32(pic_handle *h, int nbins);
+hipError_t launch_sort32_hist(pic_handle *h);
+hipError_t launch_sort32_scatter(pic_handle *h);
+hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only);
+hipError_t launch_scan(pic_handle *h, int64_t n_keys);
 hipError_t launch_field_inject(pic_handle *h);
 hipError_t launch_check_append(pic_handle *h, int64_t base, int64_t n);
 hipError_t launch_commit_append(pic_handle *h, int64_t n);

@@ -42,7 +42,10 @@ pic_status validate(const pic_params *p)
     if (!p) return fail(PIC_EINVAL, "params is NULL");
     if (p->abi_version != PCPIC_ABI_VERSION)
         return fail(PIC_EABI, "abi_version %d, library is %d", p->abi_version, PCPIC_ABI_VERSION);
-    if (p->precision != PIC_FP64) return fail(PIC_EINVAL, "precision %d not supported", p->precision);
+    if (p->precision != PIC_FP64 && p->precision != PIC_FP32_BULK)
+        return fail(PIC_EINVAL, "precision %d not supported", p->precision);
+    if (!(p->gamma_fp64 == 0.0 || (p->gamma_fp64 >= 1.0 && p->gamma_fp64 < 1e300)))
+        return fail(PIC_EINVAL, "gamma_fp64 must be 0 (default 1e6) or >= 1");
     if (p->n_cells < 2 || p->n_cells > ((int64_t)1 << 31))
         return fail(PIC_EINVAL, "n_cells %lld out of range [2, 2^31]", (long long)p->n_cells);
     if (!(p->length > 0) || !isfinite(p->length)) return fail(PIC_EINVAL, "length must be > 0");
@@ -120,9 +123,28 @@ Workspace carve(const pic_params &p, uint8_t *base)
     };
     const size_t N = (size_t)p.n_cells, cap = (size_t)p.capacity;
     const size_t nb = (size_t)effective_bins(p);
-    for (int k = 0; k < 2; ++k) {
-        w.x[k] = (double *)take(cap * 8);
-        w.u[k] = (double *)take(cap * 8);
+    const bool f32 = p.precision == PIC_FP32_BULK;
+    if (!f32) {
+        for (int k = 0; k < 2; ++k) {
+            w.x[k] = (double *)take(cap * 8);
+            w.u[k] = (double *)take(cap * 8);
+        }
+    } else {
+        // each stream can hold every particle (a tube may sit entirely above or below
+        // the threshold); 16-byte vector access needs 16-byte aligned streams
+        for (int k = 0; k < 2; ++k) {
+            w.cl[k] = (int *)take(cap * 4 + 16);
+            w.ol[k] = (float *)take(cap * 4 + 16);
+            w.ul[k] = (float *)take(cap * 4 + 16);
+            w.ch[k] = (int *)take(cap * 4 + 16);
+            w.oh[k] = (float *)take(cap * 4 + 16);
+            w.uh[k] = (double *)take(cap * 8 + 32);
+        }
+        w.k32 = (float *)take(N * 4);
+        w.stage_cap = (int64_t)(cap < ((size_t)1 << 22) ? cap : ((size_t)1 << 22));
+        w.stage_x = (double *)take((size_t)w.stage_cap * 8);
+        w.stage_u = (double *)take((size_t)w.stage_cap * 8);
+        w.total_lo = (long long *)take(8);
     }
     for (int k = 0; k < 2; ++k) {
         w.ez[k] = (double *)take(N * 8);
@@ -145,9 +167,10 @@ Workspace carve(const pic_params &p, uint8_t *base)
     w.pmin = (long long *)take(nb * 8);
     w.pmax = (long long *)take(nb * 8);
     w.gauss = (double *)take((N + 1) * 8);
-    w.cell_count = (long long *)take((N + 1) * 8);
-    w.cell_off = (long long *)take((N + 1) * 8);
-    w.blk_sum = (long long *)take((N / 1024 + 2) * 8);
+    const size_t nkeys = f32 ? 2 * (N + 1) : N + 1;   // sort keys (FP32-bulk: per destination stream)
+    w.cell_count = (long long *)take(nkeys * 8);
+    w.cell_off = (long long *)take(nkeys * 8);
+    w.blk_sum = (long long *)take((nkeys / 1024 + 2) * 8);
     w.bytes = align_up(off);
     return w;
 }
@@ -155,6 +178,11 @@ Workspace carve(const pic_params &p, uint8_t *base)
 }  // namespace pcpic
 
 namespace {
+
+hipError_t launch_push(pic_handle *h)
+{
+    return h->p.precision == PIC_FP32_BULK ? launch_push_f32(h) : launch_push_f64(h);
+}
 
 pic_status read_counters(pic_handle *h, DevCounters *out)
 {
@@ -206,6 +234,10 @@ pic_status pic_init(const pic_params *p, void *d_workspace, size_t ws_bytes, voi
     }
     h->stream = (hipStream_t)hip_stream;
     h->ws = carve(*p, (uint8_t *)d_workspace);
+    {
+        const double g = p->gamma_fp64 > 0.0 ? p->gamma_fp64 : 1e6;
+        h->u_hi = sqrt(g * g - 1.0);   // gamma >= g  <=>  |u| >= sqrt(g^2 - 1)
+    }
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
@@ -243,6 +275,34 @@ pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u
     DevCounters ctr;
     pic_status s = read_counters(h, &ctr);
     if (s != PIC_OK) return s;
+    if (h->p.precision == PIC_FP32_BULK) {
+        // either stream may receive every particle
+        if (ctr.n_slots + n > h->c.cap || ctr.n_slots_hi + n > h->c.cap)
+            return fail(PIC_ECAPACITY, "%lld + %lld slots used + %lld > capacity %lld", (long long)ctr.n_slots,
+                        (long long)ctr.n_slots_hi, (long long)n, (long long)h->c.cap);
+        const hipMemcpyKind kind = mem == 0 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        const int64_t ch = h->ws.stage_cap;
+        HIP_OK(hipMemsetAsync(&h->ws.ctr->bad_inputs, 0, sizeof(int64_t), h->stream));
+        for (int64_t o = 0; o < n; o += ch) {          // validate everything first
+            const int64_t m = n - o < ch ? n - o : ch;
+            HIP_OK(hipMemcpyAsync(h->ws.stage_x, x + o, (size_t)m * 8, kind, h->stream));
+            HIP_OK(hipMemcpyAsync(h->ws.stage_u, u + o, (size_t)m * 8, kind, h->stream));
+            HIP_OK(launch_append_staged(h, m, true));
+        }
+        s = read_counters(h, &ctr);
+        if (s != PIC_OK) return s;
+        if (ctr.bad_inputs)
+            return fail(PIC_EINVAL, "%lld particles outside [0, N) or not finite", (long long)ctr.bad_inputs);
+        for (int64_t o = 0; o < n; o += ch) {
+            const int64_t m = n - o < ch ? n - o : ch;
+            HIP_OK(hipMemcpyAsync(h->ws.stage_x, x + o, (size_t)m * 8, kind, h->stream));
+            HIP_OK(hipMemcpyAsync(h->ws.stage_u, u + o, (size_t)m * 8, kind, h->stream));
+            HIP_OK(launch_append_staged(h, m, false));
+        }
+        if (h->step == 0) HIP_OK(launch_poisson(h));
+        HIP_OK(hipStreamSynchronize(h->stream));
+        return PIC_OK;
+    }
     if (ctr.n_slots + n > h->c.cap)
         return fail(PIC_ECAPACITY, "%lld slots used + %lld > capacity %lld", (long long)ctr.n_slots,
                     (long long)n, (long long)h->c.cap);
@@ -267,7 +327,7 @@ pic_status pic_step(pic_handle *h, int64_t n_steps)
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
     if (n_steps < 0) return fail(PIC_EINVAL, "n_steps < 0");
     for (int64_t s = 0; s < n_steps; ++s) {
-        HIP_OK(launch_push_f64(h));
+        HIP_OK(launch_push(h));
         HIP_OK(launch_field_inject(h));
         h->fbuf ^= 1;
         h->jbuf ^= 1;
@@ -291,11 +351,11 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
     }
     DevCounters ctr;
     if (rc == PIC_OK) rc = read_counters(h, &ctr);
-    int64_t slots = ctr.n_slots;
+    int64_t slots = ctr.n_slots + ctr.n_slots_hi;
     for (int64_t s = 0; s < n_steps && rc == PIC_OK; ++s) {
         hipEvent_t *e = &ev[(size_t)s * 4];
         bool sorted = false;
-        if (hipEventRecord(e[0], h->stream) != hipSuccess || launch_push_f64(h) != hipSuccess ||
+        if (hipEventRecord(e[0], h->stream) != hipSuccess || launch_push(h) != hipSuccess ||
             hipEventRecord(e[1], h->stream) != hipSuccess || launch_field_inject(h) != hipSuccess ||
             hipEventRecord(e[2], h->stream) != hipSuccess) {
             rc = fail(PIC_EDEVICE, "launch failed in pic_step_timed");
@@ -335,7 +395,7 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
         if (read_counters(h, &end) == PIC_OK) {
             // slots visited: between sorts the slot count only grows by injection;
             // the average of the start and end counts times the steps
-            out->particle_steps = (int64_t)((double)(slots + end.n_slots) * 0.5 * (double)n_steps);
+            out->particle_steps = (int64_t)((double)(slots + end.n_slots + end.n_slots_hi) * 0.5 * (double)n_steps);
         }
     }
     for (auto &e : ev)
@@ -343,14 +403,19 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
     return rc;
 }
 
-pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread)
+pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread, uint32_t flags)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
-    const bool ok = (per_thread == 4 && (block == 64 || block == 128 || block == 256 || block == 512)) ||
-                    (per_thread == 8 && (block == 128 || block == 256)) || (per_thread == 2 && block == 256);
-    if (!ok) return fail(PIC_EINVAL, "unsupported push shape (%d threads, %d per thread)", block, per_thread);
+    const bool bok = block == 64 || block == 128 || block == 256 || block == 512;
+    // FP32-bulk always takes 4 slots per thread (16-byte vectors of 4-byte fields)
+    const bool ok = bok && (h->p.precision == PIC_FP32_BULK ? per_thread == 4
+                                                              : (per_thread == 2 || (per_thread == 4 && block != 512)));
+    if (!ok || (flags & ~PIC_PUSH_NONTEMPORAL))
+        return fail(PIC_EINVAL, "unsupported push shape (%d threads, %d per thread, flags %u)", block, per_thread,
+                    flags);
     h->push_block = block;
     h->push_ppt = per_thread;
+    h->push_nt = (flags & PIC_PUSH_NONTEMPORAL) ? 1 : 0;
     return PIC_OK;
 }
 
@@ -397,8 +462,8 @@ pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out
     }
     HIP_OK(hipStreamSynchronize(h->stream));
     out->step = ctr.step;
-    out->n_slots = ctr.n_slots;
-    out->n_alive = ctr.n_slots - ctr.n_removed;
+    out->n_slots = ctr.n_slots + ctr.n_slots_hi;
+    out->n_alive = ctr.n_slots + ctr.n_slots_hi - ctr.n_removed;
     out->n_injected = ctr.n_injected;
     out->n_exit = ctr.n_exit;
     out->n_absorb = ctr.n_absorb;
@@ -431,6 +496,38 @@ pic_status pic_read_particles(pic_handle *h, double *x, double *u, int64_t cap, 
     DevCounters ctr;
     pic_status s = read_counters(h, &ctr);
     if (s != PIC_OK) return s;
+    if (h->p.precision == PIC_FP32_BULK) {
+        const int b = h->pbuf;
+        int64_t m = 0;
+        for (int st = 0; st < 2; ++st) {
+            const int64_t ns = st ? ctr.n_slots_hi : ctr.n_slots;
+            std::vector<int> hc((size_t)ns);
+            std::vector<float> ho((size_t)ns), hul((size_t)ns);
+            std::vector<double> huh((size_t)ns);
+            if (ns > 0) {
+                HIP_OK(hipMemcpyAsync(hc.data(), st ? h->ws.ch[b] : h->ws.cl[b], (size_t)ns * 4, hipMemcpyDeviceToHost,
+                                      h->stream));
+                HIP_OK(hipMemcpyAsync(ho.data(), st ? h->ws.oh[b] : h->ws.ol[b], (size_t)ns * 4, hipMemcpyDeviceToHost,
+                                      h->stream));
+                if (st)
+                    HIP_OK(hipMemcpyAsync(huh.data(), h->ws.uh[b], (size_t)ns * 8, hipMemcpyDeviceToHost, h->stream));
+                else
+                    HIP_OK(hipMemcpyAsync(hul.data(), h->ws.ul[b], (size_t)ns * 4, hipMemcpyDeviceToHost, h->stream));
+                HIP_OK(hipStreamSynchronize(h->stream));
+            }
+            for (int64_t i = 0; i < ns; ++i) {
+                if (hc[(size_t)i] < 0) continue;   // removed slot
+                if (m < cap) {
+                    if (x) x[m] = (double)hc[(size_t)i] + (double)ho[(size_t)i];
+                    if (u) u[m] = st ? huh[(size_t)i] : (double)hul[(size_t)i];
+                }
+                ++m;
+            }
+        }
+        *n_out = m;
+        if (m > cap) return fail(PIC_ECAPACITY, "%lld live particles, room for %lld", (long long)m, (long long)cap);
+        return PIC_OK;
+    }
     const int64_t ns = ctr.n_slots;
     std::vector<double> hx((size_t)ns), hu((size_t)ns);
     if (ns > 0) {

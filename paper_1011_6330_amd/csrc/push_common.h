@@ -1,0 +1,139 @@
+// push_common.h -- per-thread accumulation of the charge-conserving current and
+// of the boundary tallies, shared by the FP64 and FP32-bulk push kernels.
+//
+// Current contributions are integers below 2^34 held in doubles; every sum
+// below stays under 2^53, so all additions are exact and the int64 atomics
+// make the result independent of the order of particles, lanes and blocks.
+#pragma once
+
+#include <math.h>
+
+#include "pcpic_internal.h"
+#include "wave.h"
+
+namespace pcpic {
+
+__device__ __forceinline__ void atomic_add_face(unsigned long long *J, int f, double v)
+{
+    atomicAdd(J + f, (unsigned long long)(long long)v);
+}
+
+struct DepAcc {
+    int cf;                    // cell of the thread's first deposit (-2 = none yet)
+    double am, a0, ap;         // faces cf-1, cf, cf+1
+    double w0, nexit, nabs, nlost, g_int, g_frac;
+    bool bad;
+
+    __device__ __forceinline__ void init()
+    {
+        cf = -2;
+        am = a0 = ap = 0.0;
+        w0 = nexit = nabs = nlost = g_int = g_frac = 0.0;
+        bad = false;
+    }
+
+    // J_{i+1/2} += S_i(x^n) - S_i(x^{n+1}) for a move from (c0, F0) to (c1, F1),
+    // |c1 - c0| <= 1, with S_i the fixed-point cumulative linear weight left of
+    // face i+1/2 (2^P left of node i, 2^P - F in cell i, 0 right of node i+1).
+    __device__ __forceinline__ void deposit(unsigned long long *J, int N, double twoP, int c0, double F0, int c1,
+                                            double F1)
+    {
+        double va, vb = 0.0;
+        bool hb = false;
+        if (c1 == c0) {
+            va = F1 - F0;
+        } else if (c1 > c0) {
+            va = twoP - F0;
+            if (c1 < N) { vb = F1; hb = true; }
+        } else {
+            va = -F0;
+            if (c1 >= 0) { vb = F1 - twoP; hb = true; }
+        }
+        if (cf == -2) cf = c0;
+        if (c0 == cf) {
+            a0 += va;
+            if (hb) {
+                if (c1 > c0) ap += vb;
+                else am += vb;
+            }
+        } else {
+            if (va != 0.0) atomic_add_face(J, c0, va);
+            if (hb && vb != 0.0) atomic_add_face(J, c1, vb);
+        }
+    }
+
+    // exit-gamma sum in units of 2^-32: integer part and fraction kept apart
+    __device__ __forceinline__ void exit_gamma(double gam)
+    {
+        nexit += 1.0;
+        const double gi = floor(gam);
+        g_int += gi;
+        g_frac += rint((gam - gi) * 4294967296.0);
+    }
+
+    // Wave-collective: must be reached by all 64 lanes of the wave.
+    __device__ __forceinline__ void flush(unsigned long long *J, DevCounters *ctr)
+    {
+        const int lane = __lane_id();
+        bool want = cf != -2 && (am != 0.0 || a0 != 0.0 || ap != 0.0);
+        unsigned long long pend = __ballot(want);
+        while (pend) {
+            const int leader = __ffsll(pend) - 1;
+            const int lk = __shfl(cf, leader);
+            const bool mine = want && cf == lk;
+            const double sm = wave_sum_f64_to63(mine ? am : 0.0);
+            const double s0 = wave_sum_f64_to63(mine ? a0 : 0.0);
+            const double sp = wave_sum_f64_to63(mine ? ap : 0.0);
+            if (lane == 63) {
+                if (sm != 0.0) atomic_add_face(J, lk - 1, sm);
+                if (s0 != 0.0) atomic_add_face(J, lk, s0);
+                if (sp != 0.0) atomic_add_face(J, lk + 1, sp);
+            }
+            pend &= ~__ballot(mine);
+            want = want && !mine;
+        }
+        const unsigned long long any = __ballot(w0 != 0.0 || nexit != 0.0 || nabs != 0.0 || nlost != 0.0);
+        if (any) {
+            const double sw0 = wave_sum_f64_to63(w0);
+            const double sx = wave_sum_f64_to63(nexit);
+            const double sa = wave_sum_f64_to63(nabs);
+            const double sl = wave_sum_f64_to63(nlost);
+            const double gi = wave_sum_f64_to63(g_int);
+            const double gf = wave_sum_f64_to63(g_frac);
+            if (lane == 63) {
+                if (sw0 != 0.0) atomicAdd((unsigned long long *)&ctr->w0, (unsigned long long)(long long)sw0);
+                if (sx != 0.0) {
+                    atomicAdd((unsigned long long *)&ctr->n_exit, (unsigned long long)(long long)sx);
+                    const __int128 sum = ((__int128)(long long)gi << 32) + (__int128)(long long)gf;
+                    atomic_add_i128(&ctr->exit_lo, &ctr->exit_hi, sum);
+                }
+                if (sa != 0.0) atomicAdd((unsigned long long *)&ctr->n_absorb, (unsigned long long)(long long)sa);
+                const double rem = sx + sa + sl;
+                if (rem != 0.0) atomicAdd((unsigned long long *)&ctr->n_removed, (unsigned long long)(long long)rem);
+            }
+        }
+        if (__ballot(bad) && lane == 0) atomicOr(&ctr->status, (unsigned long long)PIC_ST_NONFINITE);
+    }
+};
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef int ivec4 __attribute__((ext_vector_type(4)));
+
+// Particle-stream access of 16 bytes; NT = 1 marks it nontemporal (each value
+// is streamed once per step and should not displace the kick array and the
+// current in L2).
+template <int NT, typename V>
+__device__ __forceinline__ V ld16(const void *p)
+{
+    if (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+    return *reinterpret_cast<const V *>(p);
+}
+template <int NT, typename V>
+__device__ __forceinline__ void st16(void *p, V v)
+{
+    if (NT) __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+    else *reinterpret_cast<V *>(p) = v;
+}
+
+}  // namespace pcpic

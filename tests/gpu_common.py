@@ -14,7 +14,7 @@ def make_pair(cfg, x=None, u=None):
     from paper_1011_6330_amd import Tube
     p = synth.tube_params(cfg)
     g = Tube(p)
-    o = OracleTube({k: v for k, v in p.items() if k not in ("sort_every", "max_bins", "precision")})
+    o = OracleTube({k: v for k, v in p.items() if k not in ("sort_every", "max_bins", "precision", "gamma_fp64")})
     if x is not None and len(x):
         g.inject(x, u)
         o.inject(x, u)

@@ -76,7 +76,8 @@ def test_sorted_warm_tube():
     assert d["n_slots"] >= d["n_alive"]
 
 
-@pytest.mark.parametrize("shape", [(64, 4), (128, 4), (256, 2), (256, 4), (512, 4), (128, 8), (256, 8)])
+@pytest.mark.parametrize("shape", [(64, 4), (128, 4), (256, 2), (256, 4), (512, 2), (128, 2, True),
+                                   (256, 2, True), (64, 4, True)])
 def test_push_launch_shapes_identical(shape):
     """Every push launch shape the tuner may pick gives the oracle's state."""
     N = 2048
