@@ -228,6 +228,47 @@ enum {
  * picks the fastest.  Errors: PIC_EINVAL for an unsupported shape or flag. */
 pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread, uint32_t flags);
 
+/* ---- ensembles: many independent tubes stepped by one persistent launch ----
+ *
+ * A batch holds n_tubes tubes of any sizes (each tube's parameters as for
+ * pic_init; all tubes share the precision and sort_every).  pic_step on the
+ * batch handle advances every tube: one persistent kernel runs the push and
+ * field phases of up to sort_every steps for all tubes (grid barriers between
+ * phases, grid sized from the kernel's occupancy so every block is resident),
+ * followed by a batched cell sort; each such round is captured once in a HIP
+ * graph and replayed.  A tube of a batch computes exactly what it computes when
+ * stepped alone.  pic_step_timed reports the persistent kernel under push_ms.
+ * pic_sync on a batch checks every tube's status and the barrier's abort flag. */
+
+/* Device bytes for a batch (header + every tube's workspace), 0 if invalid. */
+size_t pic_batch_workspace_bytes(const pic_params *tubes, int32_t n_tubes);
+
+/* Create a batch from n_tubes parameter sets (host array), carving the caller's
+ * workspace (device, 256-byte aligned).  Each tube is initialised as by pic_init.
+ * Errors: as pic_init; PIC_EINVAL if precision or sort_every differ. */
+pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_workspace, size_t ws_bytes,
+                          void *hip_stream, pic_handle **out);
+
+/* Borrowed handle of tube t (for pic_inject, pic_diagnostics, pic_read_particles,
+ * pic_write_fields); stepping and release go through the batch handle. */
+pic_status pic_batch_tube(pic_handle *batch, int32_t t, pic_handle **out);
+
+/* pic_batch_set_config flags */
+enum {
+    PIC_BATCH_NO_GRAPH = 1u  /* launch every round directly instead of replaying a captured graph */
+};
+
+/* Launch shape of the persistent kernel: threads per block (64..512), slots per
+ * thread (FP64: 2 or 4; FP32-bulk: 4), blocks per CU (0 = the occupancy limit;
+ * larger values are clipped to it).  Results do not depend on the choice.
+ * Errors: PIC_EINVAL for an unsupported shape. */
+pic_status pic_batch_set_config(pic_handle *batch, int32_t block, int32_t per_thread, int32_t blocks_per_cu,
+                                uint32_t flags);
+
+/* Current launch shape (any pointer may be NULL); grid = CUs x blocks per CU. */
+pic_status pic_batch_get_config(pic_handle *batch, int32_t *block, int32_t *per_thread, int32_t *blocks_per_cu,
+                                int32_t *grid);
+
 /* Synchronise the stream; PIC_EDEVSTATUS if a status bit is latched. */
 pic_status pic_sync(pic_handle *h);
 

@@ -89,6 +89,15 @@ SIGNATURES = {
     "pic_set_push_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_uint32]),
     "pic_sync": (ctypes.c_int32, [ctypes.c_void_p]),
+    "pic_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PicParams), ctypes.c_int32]),
+    "pic_init_batch": (ctypes.c_int32, [ctypes.POINTER(PicParams), ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "pic_batch_tube": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "pic_batch_set_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_uint32]),
+    "pic_batch_get_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]),
     "pic_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
 }
 
@@ -149,26 +158,8 @@ def workspace_bytes(cfg=None, **kw):
     return n
 
 
-class Tube:
-    """One tube on the GPU.  The workspace is a torch uint8 tensor on ``device``
-    and all work is ordered on ``stream`` (a torch.cuda.Stream, created at the
-    default priority when not given)."""
-
-    def __init__(self, cfg=None, device="cuda", stream=None, **kw):
-        import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("pcpic.Tube needs a HIP GPU")
-        self.lib = load()
-        self.params, self._knots, self.cfg = make_params(cfg, **kw)
-        self.N = int(self.cfg["n_cells"])
-        self.device = torch.device(device)
-        nbytes = workspace_bytes(self.cfg)
-        with torch.cuda.device(self.device):
-            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self._h = ctypes.c_void_p()
-        _check(self.lib.pic_init(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
-                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)), "pic_init")
+class _TubeOps:
+    """Per-tube operations shared by a stand-alone Tube and a tube of a Batch."""
 
     # -- operations -----------------------------------------------------------
     def inject(self, x, u):
@@ -188,6 +179,28 @@ class Tube:
         u = np.ascontiguousarray(u, np.float64)
         _check(self.lib.pic_inject(self._h, len(x), x.ctypes.data_as(ctypes.c_void_p),
                                    u.ctypes.data_as(ctypes.c_void_p), 0), "pic_inject")
+
+
+class Tube(_TubeOps):
+    """One tube on the GPU.  The workspace is a torch uint8 tensor on ``device``
+    and all work is ordered on ``stream`` (a torch.cuda.Stream, created at the
+    default priority when not given)."""
+
+    def __init__(self, cfg=None, device="cuda", stream=None, **kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("pcpic.Tube needs a HIP GPU")
+        self.lib = load()
+        self.params, self._knots, self.cfg = make_params(cfg, **kw)
+        self.N = int(self.cfg["n_cells"])
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(self.cfg)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        _check(self.lib.pic_init(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)), "pic_init")
 
     def step(self, n=1):
         _check(self.lib.pic_step(self._h, int(n)), "pic_step")
@@ -267,3 +280,94 @@ class Tube:
     @property
     def handle(self):
         return self._h
+
+
+class _TubeView(Tube):
+    """A tube of a Batch (borrowed handle: no workspace, stepped by the batch)."""
+
+    def __init__(self, batch, t):
+        self.lib = batch.lib
+        self.stream = batch.stream
+        self.device = batch.device
+        self.cfg = batch.cfgs[t]
+        self.N = int(self.cfg["n_cells"])
+        self._h = ctypes.c_void_p()
+        _check(self.lib.pic_batch_tube(batch.handle, int(t), ctypes.byref(self._h)), "pic_batch_tube")
+        self._batch = batch
+
+    def step(self, n=1):
+        raise PicError(-7, "step", "tubes of a batch are stepped through the batch")
+
+    def close(self):
+        self._h = ctypes.c_void_p()   # borrowed; released with the batch
+
+    def __del__(self):
+        pass
+
+
+class Batch:
+    """Many independent tubes of uneven size, stepped together by one persistent
+    HIP launch per round (captured in a graph and replayed)."""
+
+    def __init__(self, cfgs, device="cuda", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("pcpic.Batch needs a HIP GPU")
+        self.lib = load()
+        made = [make_params(c) for c in cfgs]
+        self.cfgs = [m[2] for m in made]
+        self._knots = [m[1] for m in made]
+        arr = (PicParams * len(made))(*[m[0] for m in made])
+        self._params = arr
+        n = self.lib.pic_batch_workspace_bytes(arr, len(made))
+        if n == 0:
+            raise PicError(-1, "pic_batch_workspace_bytes", self.lib.pic_last_error().decode())
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        _check(self.lib.pic_init_batch(arr, len(made), ctypes.c_void_p(self.ws.data_ptr()), n,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)),
+               "pic_init_batch")
+        self.tubes = [_TubeView(self, t) for t in range(len(made))]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return len(self.tubes)
+
+    def step(self, n=1):
+        _check(self.lib.pic_step(self._h, int(n)), "pic_step")
+
+    def step_timed(self, n):
+        t = PicTiming()
+        _check(self.lib.pic_step_timed(self._h, int(n), ctypes.byref(t)), "pic_step_timed")
+        return {k: getattr(t, k) for k, _ in PicTiming._fields_}
+
+    def sync(self):
+        _check(self.lib.pic_sync(self._h), "pic_sync")
+
+    def set_config(self, block, per_thread, blocks_per_cu=0, graph=True):
+        _check(self.lib.pic_batch_set_config(self._h, int(block), int(per_thread), int(blocks_per_cu),
+                                             0 if graph else 1), "pic_batch_set_config")
+
+    def get_config(self):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(self.lib.pic_batch_get_config(self._h, *[ctypes.byref(x) for x in v]), "pic_batch_get_config")
+        return dict(block=v[0].value, per_thread=v[1].value, blocks_per_cu=v[2].value, grid=v[3].value)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            for t in self.tubes:
+                t.close()
+            self.lib.pic_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,6 +9,7 @@
 
 #include "pcpic_internal.h"
 #include "wave.h"
+#include "field_body.h"
 
 namespace pcpic {
 
@@ -148,111 +149,15 @@ __global__ __launch_bounds__(256) void k_fields_from_phi(Consts c, const double 
     }
 }
 
-struct FieldArgs {
-    const double *ezo, *ero, *bo;   // E^n, B^{n-1/2}
-    double *ezn, *ern, *bn;         // E^{n+1}, B^{n+1/2}
-    const int64_t *j;               // J^{n+1/2} of this step
-    int64_t *jnext;                 // cleared for the next step
-    double *k64;
-    float *k32;                     // FP32-bulk: f32 kick array (else null)
-    double *X, *U;                  // FP64: current particle buffer (injection)
-    int *CL;                        // FP32-bulk: low stream of the current buffer
-    float *OL, *UL;
-    DevCounters *ctr;
-};
-
-// Leap-frog update of eq. (3), one thread per face i (thread N-1 also owns node N):
-//   B_{i+1/2}  <- B - [ (dt/dz)(E_r,i+1 - E_r,i) + (dt/R) E_z,i+1/2 ]
-//   E_r,i      <- E_r,i - (dt/dz)(B_{i+1/2} - B_{i-1/2}),  i = 1..N-1 (E_r,0 unchanged, = 0)
-//   E_r,N      <- E_r,N + 2 (dt/dz) B_{N-1/2}           (B odd about the mirror x = N)
-//   E_z,i+1/2  <- (E_z + (dt/R) B_{i+1/2}) - 4 pi q_m 2^-P J_{i+1/2}
-// The neighbour B_{i-1/2} is recomputed from the old fields with the same
-// expression instead of being exchanged.  Block 0 then applies the SCLF rule.
-__global__ __launch_bounds__(256) void k_field_inject(Consts c, FieldArgs a)
-{
-    __shared__ double s_ez0;
-    __shared__ long long s_base, s_n;
-    const int64_t N = c.N;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool frozen = (c.flags & PIC_FREEZE_FIELDS) != 0;
-    if (i < N) {
-        a.jnext[i] = 0;
-        double ez;
-        if (frozen) {
-            ez = a.ezo[i];
-            a.bn[i] = a.bo[i];
-            a.ern[i] = a.ero[i];
-            if (i == N - 1) a.ern[N] = a.ero[N];
-        } else {
-            const double bi = a.bo[i] - (c.dtdz * (a.ero[i + 1] - a.ero[i]) + c.dtR * a.ezo[i]);
-            a.bn[i] = bi;
-            if (i >= 1) {
-                const double bm = a.bo[i - 1] - (c.dtdz * (a.ero[i] - a.ero[i - 1]) + c.dtR * a.ezo[i - 1]);
-                a.ern[i] = a.ero[i] - c.dtdz * (bi - bm);
-            } else {
-                a.ern[0] = a.ero[0];
-            }
-            if (i == N - 1) a.ern[N] = a.ero[N] + c.tw * bi;
-            ez = (a.ezo[i] + c.dtR * bi) - c.c4 * (double)a.j[i];
-        }
-        a.ezn[i] = ez;
-        const double kk = c.qmdt * ez;
-        a.k64[i] = kk;
-        if (a.k32) a.k32[i] = (float)kk;
-        if (i == 0) s_ez0 = ez;
-    }
-    if (blockIdx.x != 0) return;
-    __syncthreads();
-    DevCounters *ctr = a.ctr;
-    if (threadIdx.x == 0) {
-        // surface field from the node-0 Gauss law over the half cell [0, dz/2]
-        const int64_t w0 = ctr->w0;
-        const double t1 = c.qmP * (double)w0;
-        const double t2 = c.rho0 * c.hdz;
-        const double es = s_ez0 - c.fourpi * (t1 - t2);
-        int64_t ninj = 0;
-        if (!(c.flags & PIC_NO_AUTO_INJECT)) {
-            const double ratio = es / c.fqm;
-            if (ratio > 0.0) {
-                const double nf = floor(ratio);
-                const int64_t avail = c.cap - ctr->n_slots;
-                if (nf > (double)avail) {
-                    ninj = avail;
-                    ctr->status |= PIC_ST_CAPACITY;
-                } else {
-                    ninj = (int64_t)nf;
-                }
-            }
-        }
-        s_base = ctr->n_slots;
-        s_n = ninj;
-        ctr->n_slots += ninj;
-        ctr->n_injected += ninj;
-        ctr->last_ninj = ninj;
-        ctr->e_surf = es;
-        ctr->w0_last = w0;
-        ctr->w0 = 0;
-        ctr->step += 1;
-    }
-    __syncthreads();
-    const long long base = s_base, n = s_n;
-    for (long long p = threadIdx.x; p < n; p += 256) {
-        // electrons leave the surface at rest
-        if (a.CL) {
-            a.CL[base + p] = 0;
-            a.OL[base + p] = 0.0f;
-            a.UL[base + p] = 0.0f;
-        } else {
-            a.X[base + p] = 0.0;
-            a.U[base + p] = 0.0;
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void k_fill_i64(int64_t *p, int64_t n, int64_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_field_inject(Consts c, FieldArgs a)
+{
+    field_tile(c, a, blockIdx.x, 256);
 }
 
 // Kick array from E_z (after the caller overwrote the fields).

@@ -14,109 +14,17 @@
 
 #include "pcpic_internal.h"
 #include "push_common.h"
+#include "push_body.h"
 
 namespace pcpic {
-
-struct PushArgs {
-    double *__restrict__ X;
-    double *__restrict__ U;
-    const double *__restrict__ K;
-    unsigned long long *__restrict__ J;
-    DevCounters *ctr;
-};
 
 template <int BLOCK, int PPT, int NT>
 __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
 {
     const int64_t n = a.ctr->n_slots;
-    constexpr int TILE = BLOCK * PPT;
-    const int64_t tile0 = (int64_t)blockIdx.x * TILE;
+    const int64_t tile0 = (int64_t)blockIdx.x * (BLOCK * PPT);
     if (tile0 >= n) return;                       // whole block idle (uniform)
-    const int N = (int)c.N;
-    const double Nd = (double)c.N, Nm1 = (double)(c.N - 1);
-    const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
-    const bool full = p0 + PPT <= n;
-
-    double xs[PPT], us[PPT];
-    if (full) {
-#pragma unroll
-        for (int k = 0; k < PPT; k += 2) {
-            const dvec2 xv = ld16<NT, dvec2>(a.X + p0 + k);
-            const dvec2 uv = ld16<NT, dvec2>(a.U + p0 + k);
-            xs[k] = xv.x; xs[k + 1] = xv.y;
-            us[k] = uv.x; us[k + 1] = uv.y;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            xs[k] = p0 + k < n ? a.X[p0 + k] : -1.0;
-            us[k] = p0 + k < n ? a.U[p0 + k] : 0.0;
-        }
-    }
-
-    DepAcc acc;
-    acc.init();
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const double x = xs[k], u = us[k];
-        if (!(x >= 0.0)) continue;               // removed slot (-1) or past the end
-        // gather: linear interpolation between face values, clamped at the ends
-        const double s = x - 0.5;
-        const int jj = (int)floor(s);
-        const double g = s - (double)jj;
-        const int jc = jj < 0 ? 0 : (jj > N - 2 ? N - 2 : jj);
-        const double k0 = a.K[jc], k1 = a.K[jc + 1];
-        const double Ei = k0 + g * (k1 - k0);
-        const double E = s < 0.0 ? k0 : (s >= Nm1 ? k1 : Ei);
-        // eq. (1): u = gamma v, du/dt = (q/m) E_z, dz/dt = v
-        const double u1 = u + E;
-        double tt = u1 * u1;
-        tt = 1.0 + tt;
-        const double gam = sqrt(tt);
-        const double v = u1 / gam;
-        const double x1 = x + c.dtdz * v;
-        if (!isfinite(u1) || !isfinite(x1)) {
-            acc.bad = true;
-            acc.nlost += 1.0;
-            xs[k] = -1.0;
-            continue;
-        }
-        const double c0d = floor(x);
-        const double F0 = rint((x - c0d) * c.twoP);
-        const double c1d = floor(x1);
-        const int c1 = (int)c1d;
-        const double F1 = rint((x1 - c1d) * c.twoP);
-        acc.deposit(a.J, N, c.twoP, (int)c0d, F0, c1, F1);
-        if (x1 >= Nd) {                          // leaves through z = L
-            acc.exit_gamma(gam);
-            xs[k] = -1.0;
-        } else if (x1 < 0.0) {                   // returns to the star
-            acc.nabs += 1.0;
-            xs[k] = -1.0;
-        } else {
-            if (c1 == 0) acc.w0 += c.twoP - F1;
-            xs[k] = x1;
-            us[k] = u1;
-        }
-    }
-
-    // write back (removed particles get x = -1; their u is left as it was)
-    if (full) {
-#pragma unroll
-        for (int k = 0; k < PPT; k += 2) {
-            st16<NT, dvec2>(a.X + p0 + k, dvec2{xs[k], xs[k + 1]});
-            st16<NT, dvec2>(a.U + p0 + k, dvec2{us[k], us[k + 1]});
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (p0 + k < n) {
-                a.X[p0 + k] = xs[k];
-                a.U[p0 + k] = us[k];
-            }
-        }
-    }
-    acc.flush(a.J, a.ctr);
+    push_tile_f64<BLOCK, PPT, NT>(c, a, n, tile0);
 }
 
 template <int BLOCK, int PPT, int NT>

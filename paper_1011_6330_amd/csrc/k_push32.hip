@@ -15,205 +15,19 @@
 
 #include "pcpic_internal.h"
 #include "push_common.h"
+#include "push_body.h"
 
 namespace pcpic {
-
-struct Push32Args {
-    int *__restrict__ CL;
-    float *__restrict__ OL;
-    float *__restrict__ UL;
-    int *__restrict__ CH;
-    float *__restrict__ OH;
-    double *__restrict__ UH;
-    const float *__restrict__ K32;
-    const double *__restrict__ K64;
-    unsigned long long *__restrict__ J;
-    DevCounters *ctr;
-    unsigned blocks_lo;     // grid blocks [0, blocks_lo) serve the low stream
-};
-
-// Offset update with the carry into the next or previous cell (|move| < 1 cell).
-// An offset that rounds to 1.0f is stored as (cell + 1, 0).
-__device__ __forceinline__ void carry_f32(float &o, int &cell)
-{
-    if (o >= 1.0f) {
-        o -= 1.0f;
-        cell += 1;
-    } else if (o < 0.0f) {
-        o += 1.0f;
-        cell -= 1;
-        if (o >= 1.0f) { o = 0.0f; cell += 1; }
-    }
-}
 
 template <int BLOCK, int NT>
 __global__ __launch_bounds__(BLOCK) void k_push_f32(Consts c, Push32Args a)
 {
-    constexpr int PPT = 4;
-    constexpr int TILE = BLOCK * PPT;
     const bool hi = blockIdx.x >= a.blocks_lo;
     const int64_t b = hi ? (int64_t)(blockIdx.x - a.blocks_lo) : (int64_t)blockIdx.x;
     const int64_t n = hi ? a.ctr->n_slots_hi : a.ctr->n_slots;
-    const int64_t tile0 = b * TILE;
+    const int64_t tile0 = b * (BLOCK * 4);
     if (tile0 >= n) return;                       // whole block idle (uniform)
-    const int N = (int)c.N;
-    const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
-    const bool full = p0 + PPT <= n;
-    int *C = hi ? a.CH : a.CL;
-    float *O = hi ? a.OH : a.OL;
-
-    int cs[PPT];
-    float os[PPT];
-    if (full) {
-        const ivec4 cv = ld16<NT, ivec4>(C + p0);
-        const fvec4 ov = ld16<NT, fvec4>(O + p0);
-        cs[0] = cv.x; cs[1] = cv.y; cs[2] = cv.z; cs[3] = cv.w;
-        os[0] = ov.x; os[1] = ov.y; os[2] = ov.z; os[3] = ov.w;
-    } else {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            cs[k] = p0 + k < n ? C[p0 + k] : -1;
-            os[k] = p0 + k < n ? O[p0 + k] : 0.0f;
-        }
-    }
-    DepAcc acc;
-    acc.init();
-
-    if (!hi) {
-        // ---------------- low stream: FP32 momentum ----------------
-        float us[PPT];
-        if (full) {
-            const fvec4 uv = ld16<NT, fvec4>(a.UL + p0);
-            us[0] = uv.x; us[1] = uv.y; us[2] = uv.z; us[3] = uv.w;
-        } else {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) us[k] = p0 + k < n ? a.UL[p0 + k] : 0.0f;
-        }
-        const float dtdz = (float)c.dtdz;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int cell = cs[k];
-            if (cell < 0) continue;              // removed slot or past the end
-            const float off = os[k], u = us[k];
-            // gather between the faces around x = cell + off, clamped at the ends
-            const int j = off < 0.5f ? cell - 1 : cell;
-            const float g = off < 0.5f ? off + 0.5f : off - 0.5f;
-            const int jc = j < 0 ? 0 : (j > N - 2 ? N - 2 : j);
-            const float k0 = a.K32[jc], k1 = a.K32[jc + 1];
-            const float E = j < 0 ? k0 : (j >= N - 1 ? k1 : k0 + g * (k1 - k0));
-            const float u1 = u + E;
-            float t = u1 * u1;
-            t = 1.0f + t;
-            const float v = u1 * __builtin_amdgcn_rsqf(t);
-            float o1 = off + dtdz * v;
-            int c1 = cell;
-            carry_f32(o1, c1);
-            if (!isfinite(u1) || !isfinite(o1)) {
-                acc.bad = true;
-                acc.nlost += 1.0;
-                cs[k] = -1;
-                continue;
-            }
-            const double F0 = rint((double)off * c.twoP);
-            const double F1 = rint((double)o1 * c.twoP);
-            acc.deposit(a.J, N, c.twoP, cell, F0, c1, F1);
-            if (c1 >= N) {
-                const double ud = (double)u1;
-                double tt = ud * ud;
-                tt = 1.0 + tt;
-                acc.exit_gamma(sqrt(tt));
-                cs[k] = -1;
-            } else if (c1 < 0) {
-                acc.nabs += 1.0;
-                cs[k] = -1;
-            } else {
-                if (c1 == 0) acc.w0 += c.twoP - F1;
-                cs[k] = c1;
-                os[k] = o1;
-                us[k] = u1;
-            }
-        }
-        if (full) {
-            st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
-            st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
-            st16<NT, fvec4>(a.UL + p0, fvec4{us[0], us[1], us[2], us[3]});
-        } else {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UL[p0 + k] = us[k]; }
-        }
-    } else {
-        // ---------------- high stream: FP64 momentum ----------------
-        double us[PPT];
-        if (full) {
-            const dvec2 u01 = ld16<NT, dvec2>(a.UH + p0);
-            const dvec2 u23 = ld16<NT, dvec2>(a.UH + p0 + 2);
-            us[0] = u01.x; us[1] = u01.y; us[2] = u23.x; us[3] = u23.y;
-        } else {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) us[k] = p0 + k < n ? a.UH[p0 + k] : 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int cell = cs[k];
-            if (cell < 0) continue;
-            const float off = os[k];
-            const double u = us[k];
-            const int j = off < 0.5f ? cell - 1 : cell;
-            const float g = off < 0.5f ? off + 0.5f : off - 0.5f;
-            const int jc = j < 0 ? 0 : (j > N - 2 ? N - 2 : j);
-            const double k0 = a.K64[jc], k1 = a.K64[jc + 1];
-            const double E = j < 0 ? k0 : (j >= N - 1 ? k1 : k0 + (double)g * (k1 - k0));
-            const double u1 = u + E;
-            double tt = u1 * u1;
-            tt = 1.0 + tt;
-            const double gam = sqrt(tt);
-            const double v = u1 / gam;
-            double od = (double)off + c.dtdz * v;
-            int c1 = cell;
-            if (od >= 1.0) {
-                od -= 1.0;
-                c1 += 1;
-            } else if (od < 0.0) {
-                od += 1.0;
-                c1 -= 1;
-            }
-            float o1 = (float)od;
-            if (o1 >= 1.0f) { o1 = 0.0f; c1 += 1; }
-            if (!isfinite(u1) || !isfinite(od)) {
-                acc.bad = true;
-                acc.nlost += 1.0;
-                cs[k] = -1;
-                continue;
-            }
-            const double F0 = rint((double)off * c.twoP);
-            const double F1 = rint((double)o1 * c.twoP);
-            acc.deposit(a.J, N, c.twoP, cell, F0, c1, F1);
-            if (c1 >= N) {
-                acc.exit_gamma(gam);
-                cs[k] = -1;
-            } else if (c1 < 0) {
-                acc.nabs += 1.0;
-                cs[k] = -1;
-            } else {
-                if (c1 == 0) acc.w0 += c.twoP - F1;
-                cs[k] = c1;
-                os[k] = o1;
-                us[k] = u1;
-            }
-        }
-        if (full) {
-            st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
-            st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
-            st16<NT, dvec2>(a.UH + p0, dvec2{us[0], us[1]});
-            st16<NT, dvec2>(a.UH + p0 + 2, dvec2{us[2], us[3]});
-        } else {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UH[p0 + k] = us[k]; }
-        }
-    }
-    acc.flush(a.J, a.ctr);
+    push_tile_f32<BLOCK, NT>(c, a, hi, n, tile0);
 }
 
 // ------------------------------------------------------------------------

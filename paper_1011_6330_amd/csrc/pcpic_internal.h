@@ -104,6 +104,36 @@ struct Workspace {
     size_t bytes;
 };
 
+// Device descriptor of one tube of a batch: constants and the base pointers of
+// both parities of every ping-pong array.
+struct TubeDev {
+    Consts c;
+    double *x[2], *u[2];
+    int *cl[2];
+    float *ol[2], *ul[2];
+    int *ch[2];
+    float *oh[2];
+    double *uh[2];
+    double *ez[2], *er[2], *b[2];
+    int64_t *j[2];
+    double *k64;
+    float *k32;
+    DevCounters *ctr;
+    long long *cell_count, *cell_off, *total_lo;
+    double u_hi;
+    int64_t push_tiles;   // push tiles per particle stream at capacity
+    int64_t sort_chunks;  // 256-slot chunks per particle stream at capacity
+    int64_t n_keys;       // sort keys (N, or 2(N+1) in FP32-bulk mode)
+};
+
+// Grid-barrier state of the batched persistent kernel.
+struct BatchState {
+    unsigned bar_count;
+    unsigned bar_gen;
+    unsigned abort;
+    unsigned pad;
+};
+
 // Byte layout of the workspace (offsets from the base).  Computing it with a
 // null base gives the size.
 Workspace carve(const pic_params &p, uint8_t *base);
@@ -126,6 +156,18 @@ struct pic_handle {
     double u_hi = 0.0;  // FP32-bulk: |u| from which a particle belongs to the FP64 stream
     int push_grid = 0;  // 0 = derived from the device
     int n_cu = 256;
+    // batch (ensemble) handles
+    bool is_batch = false;
+    pic_handle *parent = nullptr;               // set on the tubes of a batch
+    std::vector<pic_handle *> tubes;
+    pcpic::TubeDev *d_tubes = nullptr;
+    int64_t *d_push_pref = nullptr, *d_field_pref = nullptr, *d_sort_pref = nullptr, *d_key_pref = nullptr;
+    pcpic::BatchState *d_state = nullptr;
+    int batch_block = 256, batch_ppt = 2, batch_bpc = 0, batch_grid = 0;
+    int64_t batch_push_items = 0, batch_field_items = 0, batch_sort_items = 0, batch_keys = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // one round, keyed by the particle parity
+    int64_t graph_steps = 0;
+    bool use_graph = true;
 };
 
 namespace pcpic {
@@ -142,6 +184,10 @@ hipError_t launch_sort32_hist(pic_handle *h);
 hipError_t launch_sort32_scatter(pic_handle *h);
 hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only);
 hipError_t launch_scan(pic_handle *h, int64_t n_keys);
+hipError_t launch_batch_steps(pic_handle *h, int nsteps);
+hipError_t launch_batch_sort(pic_handle *h);
+int batch_occupancy(pic_handle *h);
+TubeDev tube_dev(pic_handle *t);
 hipError_t launch_field_inject(pic_handle *h);
 hipError_t launch_check_append(pic_handle *h, int64_t base, int64_t n);
 hipError_t launch_commit_append(pic_handle *h, int64_t n);

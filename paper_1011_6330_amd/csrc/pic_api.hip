@@ -211,7 +211,7 @@ size_t pic_workspace_bytes(const pic_params *p)
     return carve(*p, nullptr).bytes;
 }
 
-pic_status pic_init(const pic_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream, pic_handle **out)
+static pic_status init_tube(const pic_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream, pic_handle **out)
 {
     if (!out) return fail(PIC_EINVAL, "out is NULL");
     *out = nullptr;
@@ -254,14 +254,27 @@ pic_status pic_init(const pic_params *p, void *d_workspace, size_t ws_bytes, voi
     }
     if ((e = launch_rho_gj(h)) != hipSuccess) return bail(e, "rho_gj");
     if ((e = launch_poisson(h)) != hipSuccess) return bail(e, "poisson");
-    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return bail(e, "init sync");
     *out = h;
+    return PIC_OK;
+}
+
+pic_status pic_init(const pic_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream, pic_handle **out)
+{
+    pic_status s = init_tube(p, d_workspace, ws_bytes, hip_stream, out);
+    if (s != PIC_OK) return s;
+    hipError_t e = hipStreamSynchronize((*out)->stream);
+    if (e != hipSuccess) {
+        delete *out;
+        *out = nullptr;
+        return fail(PIC_EDEVICE, "init sync: %s", hipGetErrorString(e));
+    }
     return PIC_OK;
 }
 
 pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u, int32_t mem)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (h->is_batch) return fail(PIC_EINVAL, "inject into a tube handle of the batch (pic_batch_tube)");
     if (n < 0 || (n > 0 && (!x || !u)) || (mem != 0 && mem != 1))
         return fail(PIC_EINVAL, "bad arguments to pic_inject");
     if (n == 0) return PIC_OK;
@@ -322,10 +335,16 @@ pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u
     return PIC_OK;
 }
 
+static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t> *ev, pic_timing *tim);
+static pic_status batch_status(pic_handle *h);
+static void free_batch_graphs(pic_handle *h);
+
 pic_status pic_step(pic_handle *h, int64_t n_steps)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
     if (n_steps < 0) return fail(PIC_EINVAL, "n_steps < 0");
+    if (h->parent) return fail(PIC_ESTATE, "a tube of a batch is stepped through its batch handle");
+    if (h->is_batch) return batch_advance(h, n_steps, nullptr, nullptr);
     for (int64_t s = 0; s < n_steps; ++s) {
         HIP_OK(launch_push(h));
         HIP_OK(launch_field_inject(h));
@@ -341,8 +360,37 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
 {
     if (!h || !out) return fail(PIC_EINVAL, "handle or out is NULL");
     if (n_steps < 0) return fail(PIC_EINVAL, "n_steps < 0");
+    if (h->parent) return fail(PIC_ESTATE, "a tube of a batch is stepped through its batch handle");
     memset(out, 0, sizeof *out);
     if (n_steps == 0) return PIC_OK;
+    if (h->is_batch) {
+        std::vector<hipEvent_t> ev;
+        pic_status rc = batch_advance(h, n_steps, &ev, out);
+        if (rc == PIC_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(PIC_EDEVICE, "sync failed");
+        if (rc == PIC_OK) {
+            for (size_t k = 0; k + 2 < ev.size(); k += 3) {
+                float a = 0, b = 0;
+                (void)hipEventElapsedTime(&a, ev[k], ev[k + 1]);
+                (void)hipEventElapsedTime(&b, ev[k + 1], ev[k + 2]);
+                out->push_ms += a;   // persistent kernel: push + field phases of the round
+                out->sort_ms += b;
+            }
+            if (!ev.empty()) {
+                float tot = 0;
+                (void)hipEventElapsedTime(&tot, ev.front(), ev.back());
+                out->total_ms = tot;
+            }
+            int64_t live = 0;
+            for (pic_handle *t : h->tubes) {
+                DevCounters c;
+                if (read_counters(t, &c) == PIC_OK) live += c.n_slots + c.n_slots_hi - c.n_removed;
+            }
+            out->particle_steps = live * n_steps;
+        }
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+        return rc;
+    }
     std::vector<hipEvent_t> ev((size_t)n_steps * 4, nullptr);
     std::vector<int64_t> slots_before((size_t)n_steps, 0);
     pic_status rc = PIC_OK;
@@ -406,6 +454,7 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
 pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread, uint32_t flags)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (h->is_batch || h->parent) return fail(PIC_EINVAL, "batches take pic_batch_set_config");
     const bool bok = block == 64 || block == 128 || block == 256 || block == 512;
     // FP32-bulk always takes 4 slots per thread (16-byte vectors of 4-byte fields)
     const bool ok = bok && (h->p.precision == PIC_FP32_BULK ? per_thread == 4
@@ -422,6 +471,7 @@ pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread,
 pic_status pic_sync(pic_handle *h)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (h->is_batch) return batch_status(h);
     DevCounters ctr;
     pic_status s = read_counters(h, &ctr);
     if (s != PIC_OK) return s;
@@ -432,6 +482,7 @@ pic_status pic_sync(pic_handle *h)
 pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out)
 {
     if (!h || !out) return fail(PIC_EINVAL, "handle or out is NULL");
+    if (h->is_batch) return fail(PIC_EINVAL, "diagnostics are per tube (pic_batch_tube)");
     const int nb = req ? req->n_bins : 0;
     const bool want_gauss = req && req->want_gauss;
     if (nb < 0 || nb > effective_bins(h->p)) return fail(PIC_EINVAL, "n_bins %d > max_bins", nb);
@@ -493,6 +544,7 @@ pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out
 pic_status pic_read_particles(pic_handle *h, double *x, double *u, int64_t cap, int64_t *n_out)
 {
     if (!h || !n_out) return fail(PIC_EINVAL, "handle or n_out is NULL");
+    if (h->is_batch) return fail(PIC_EINVAL, "particles are per tube (pic_batch_tube)");
     DevCounters ctr;
     pic_status s = read_counters(h, &ctr);
     if (s != PIC_OK) return s;
@@ -552,6 +604,7 @@ pic_status pic_read_particles(pic_handle *h, double *x, double *u, int64_t cap, 
 pic_status pic_write_fields(pic_handle *h, const double *ez, const double *er, const double *b_phi)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (h->is_batch) return fail(PIC_EINVAL, "fields are per tube (pic_batch_tube)");
     const int64_t N = h->c.N;
     const int f = h->fbuf;
     if (ez) HIP_OK(hipMemcpyAsync(h->ws.ez[f], ez, (size_t)N * 8, hipMemcpyHostToDevice, h->stream));
@@ -565,8 +618,268 @@ pic_status pic_write_fields(pic_handle *h, const double *ez, const double *er, c
 pic_status pic_destroy(pic_handle *h)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (h->parent) return fail(PIC_ESTATE, "a tube of a batch is released with its batch");
     (void)hipStreamSynchronize(h->stream);
+    if (h->is_batch) {
+        free_batch_graphs(h);
+        for (pic_handle *t : h->tubes) delete t;
+    }
     delete h;
+    return PIC_OK;
+}
+
+// ------------------------------------------------------------------------
+// batches of tubes (ensembles)
+// ------------------------------------------------------------------------
+
+static size_t batch_header_bytes(int n)
+{
+    size_t off = 0;
+    off = align_up(off) + sizeof(TubeDev) * (size_t)n;
+    for (int k = 0; k < 4; ++k) off = align_up(off) + sizeof(int64_t) * (size_t)(n + 1);
+    off = align_up(off) + sizeof(BatchState);
+    return align_up(off);
+}
+
+size_t pic_batch_workspace_bytes(const pic_params *tubes, int32_t n_tubes)
+{
+    if (!tubes || n_tubes < 1) {
+        fail(PIC_EINVAL, "need at least one tube");
+        return 0;
+    }
+    size_t total = batch_header_bytes(n_tubes);
+    for (int t = 0; t < n_tubes; ++t) {
+        if (validate(&tubes[t]) != PIC_OK) return 0;
+        total += carve(tubes[t], nullptr).bytes;
+    }
+    return total;
+}
+
+static void free_batch_graphs(pic_handle *h)
+{
+    for (auto &g : h->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// Push/field work-item tables for the current launch shape, uploaded to the device.
+static pic_status batch_configure(pic_handle *h, int block, int per_thread, int blocks_per_cu)
+{
+    const bool f32 = h->tubes[0]->p.precision == PIC_FP32_BULK;
+    const int ppt = f32 ? 4 : per_thread;
+    const int saved_b = h->batch_block, saved_p = h->batch_ppt;
+    h->batch_block = block;
+    h->batch_ppt = ppt;
+    const int occ = batch_occupancy(h);
+    if (occ <= 0) {
+        h->batch_block = saved_b;
+        h->batch_ppt = saved_p;
+        return fail(PIC_EINVAL, "unsupported batch launch shape (%d threads, %d per thread)", block, per_thread);
+    }
+    const int bpc = blocks_per_cu > 0 ? (blocks_per_cu < occ ? blocks_per_cu : occ) : occ;
+    h->batch_bpc = bpc;
+    h->batch_grid = h->n_cu * bpc;
+    const int n = (int)h->tubes.size();
+    const int64_t tile = (int64_t)block * ppt;
+    std::vector<TubeDev> td((size_t)n);
+    std::vector<int64_t> pp((size_t)n + 1, 0), fp((size_t)n + 1, 0), sp((size_t)n + 1, 0), kp((size_t)n + 1, 0);
+    for (int t = 0; t < n; ++t) {
+        pic_handle *s = h->tubes[(size_t)t];
+        td[(size_t)t] = tube_dev(s);
+        td[(size_t)t].push_tiles = (s->c.cap + tile - 1) / tile;
+        pp[(size_t)t + 1] = pp[(size_t)t] + (f32 ? 2 : 1) * td[(size_t)t].push_tiles;
+        fp[(size_t)t + 1] = fp[(size_t)t] + (s->c.N + block - 1) / block;
+        sp[(size_t)t + 1] = sp[(size_t)t] + (f32 ? 2 : 1) * td[(size_t)t].sort_chunks;
+        kp[(size_t)t + 1] = kp[(size_t)t] + td[(size_t)t].n_keys;
+    }
+    h->batch_push_items = pp[(size_t)n];
+    h->batch_field_items = fp[(size_t)n];
+    h->batch_sort_items = sp[(size_t)n];
+    h->batch_keys = kp[(size_t)n];
+    HIP_OK(hipMemcpyAsync(h->d_tubes, td.data(), sizeof(TubeDev) * (size_t)n, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_push_pref, pp.data(), 8 * pp.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_field_pref, fp.data(), 8 * fp.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_sort_pref, sp.data(), 8 * sp.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_key_pref, kp.data(), 8 * kp.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    free_batch_graphs(h);
+    return PIC_OK;
+}
+
+pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_workspace, size_t ws_bytes,
+                          void *hip_stream, pic_handle **out)
+{
+    if (!out) return fail(PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    const size_t need = pic_batch_workspace_bytes(tubes, n_tubes);
+    if (need == 0) return PIC_EINVAL;
+    for (int t = 1; t < n_tubes; ++t)
+        if (tubes[t].precision != tubes[0].precision || tubes[t].sort_every != tubes[0].sort_every)
+            return fail(PIC_EINVAL, "all tubes of a batch need the same precision and sort_every");
+    if (!d_workspace || ws_bytes < need) return fail(PIC_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (((uintptr_t)d_workspace) % ALIGN) return fail(PIC_EWORKSPACE, "workspace must be %zu-byte aligned", ALIGN);
+    pic_handle *h = new (std::nothrow) pic_handle();
+    if (!h) return fail(PIC_EINVAL, "out of host memory");
+    h->is_batch = true;
+    h->p = tubes[0];
+    h->p.knots = nullptr;
+    h->stream = (hipStream_t)hip_stream;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        h->n_cu = ncu;
+    uint8_t *base = (uint8_t *)d_workspace;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        const size_t o = align_up(off);
+        off = o + bytes;
+        return (void *)(base + o);
+    };
+    h->d_tubes = (TubeDev *)take(sizeof(TubeDev) * (size_t)n_tubes);
+    h->d_push_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
+    h->d_field_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
+    h->d_sort_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
+    h->d_key_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
+    h->d_state = (BatchState *)take(sizeof(BatchState));
+    off = batch_header_bytes(n_tubes);
+    for (int t = 0; t < n_tubes; ++t) {
+        const size_t sz = carve(tubes[t], nullptr).bytes;
+        pic_handle *sub = nullptr;
+        pic_status s = init_tube(&tubes[t], base + off, sz, hip_stream, &sub);
+        if (s != PIC_OK) {
+            pic_destroy(h);
+            return s;
+        }
+        sub->parent = h;
+        h->tubes.push_back(sub);
+        off += sz;
+    }
+    hipError_t e = hipMemsetAsync(h->d_state, 0, sizeof(BatchState), h->stream);
+    if (e != hipSuccess) {
+        pic_destroy(h);
+        return fail(PIC_EDEVICE, "clear batch state: %s", hipGetErrorString(e));
+    }
+    const bool f32 = tubes[0].precision == PIC_FP32_BULK;
+    pic_status s = batch_configure(h, 256, f32 ? 4 : 2, 0);
+    if (s != PIC_OK) {
+        pic_destroy(h);
+        return s;
+    }
+    *out = h;
+    return PIC_OK;
+}
+
+pic_status pic_batch_tube(pic_handle *h, int32_t t, pic_handle **out)
+{
+    if (!h || !out || !h->is_batch) return fail(PIC_EINVAL, "not a batch handle");
+    if (t < 0 || t >= (int32_t)h->tubes.size()) return fail(PIC_EINVAL, "tube %d out of range", t);
+    *out = h->tubes[(size_t)t];
+    return PIC_OK;
+}
+
+pic_status pic_batch_set_config(pic_handle *h, int32_t block, int32_t per_thread, int32_t blocks_per_cu,
+                                uint32_t flags)
+{
+    if (!h || !h->is_batch) return fail(PIC_EINVAL, "not a batch handle");
+    if (blocks_per_cu < 0) return fail(PIC_EINVAL, "blocks_per_cu < 0");
+    if (flags & ~PIC_BATCH_NO_GRAPH) return fail(PIC_EINVAL, "unknown batch flags");
+    pic_status s = batch_configure(h, block, per_thread, blocks_per_cu);
+    if (s == PIC_OK) h->use_graph = !(flags & PIC_BATCH_NO_GRAPH);
+    return s;
+}
+
+pic_status pic_batch_get_config(pic_handle *h, int32_t *block, int32_t *per_thread, int32_t *blocks_per_cu,
+                                int32_t *grid)
+{
+    if (!h || !h->is_batch) return fail(PIC_EINVAL, "not a batch handle");
+    if (block) *block = h->batch_block;
+    if (per_thread) *per_thread = h->batch_ppt;
+    if (blocks_per_cu) *blocks_per_cu = h->batch_bpc;
+    if (grid) *grid = h->batch_grid;
+    return PIC_OK;
+}
+
+// Advance every tube of the batch by n steps in rounds that end at the sort
+// period; a whole round (persistent kernel + batched sort) is replayed from a
+// captured graph.  With `ev`, events bracket each round's kernel and sort.
+static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t> *ev, pic_timing *tim)
+{
+    pic_handle *t0 = h->tubes[0];
+    const int64_t S = t0->p.sort_every;
+    while (n > 0) {
+        int64_t r;
+        if (S > 0) {
+            r = S - (t0->step % S);
+            if (r > n) r = n;
+        } else {
+            r = n < 64 ? n : 64;
+        }
+        const bool to_sort = S > 0 && (t0->step + r) % S == 0;
+        const int key = t0->fbuf | (t0->jbuf << 1) | (t0->pbuf << 2);
+        const bool round = to_sort && r == S && h->use_graph && !ev;
+        if (round && !h->graph[key]) {
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                hipError_t e1 = launch_batch_steps(h, (int)r);
+                hipError_t e2 = launch_batch_sort(h);
+                hipError_t e3 = hipStreamEndCapture(h->stream, &g);
+                if (e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess && g &&
+                    hipGraphInstantiate(&h->graph[key], g, nullptr, nullptr, 0) == hipSuccess) {
+                    h->graph_steps = r;
+                } else {
+                    h->graph[key] = nullptr;
+                    h->use_graph = false;
+                }
+                if (g) (void)hipGraphDestroy(g);
+            } else {
+                (void)hipGetLastError();
+                h->use_graph = false;
+            }
+        }
+        if (round && h->graph[key]) {
+            HIP_OK(hipGraphLaunch(h->graph[key], h->stream));
+        } else {
+            hipEvent_t *e = nullptr;
+            if (ev) {
+                ev->resize(ev->size() + 3, nullptr);
+                e = &(*ev)[ev->size() - 3];
+                for (int k = 0; k < 3; ++k) HIP_OK(hipEventCreate(&e[k]));
+                HIP_OK(hipEventRecord(e[0], h->stream));
+            }
+            HIP_OK(launch_batch_steps(h, (int)r));
+            if (e) HIP_OK(hipEventRecord(e[1], h->stream));
+            if (to_sort) HIP_OK(launch_batch_sort(h));
+            if (e) HIP_OK(hipEventRecord(e[2], h->stream));
+            if (tim) {
+                tim->push_launches += 1;
+                tim->field_launches += r;
+                if (to_sort) tim->sort_launches += 1;
+            }
+        }
+        for (pic_handle *t : h->tubes) {
+            t->fbuf ^= (int)(r & 1);
+            t->jbuf ^= (int)(r & 1);
+            t->step += r;
+            if (to_sort) t->pbuf ^= 1;
+        }
+        n -= r;
+    }
+    return PIC_OK;
+}
+
+static pic_status batch_status(pic_handle *h)
+{
+    BatchState st{};
+    HIP_OK(hipMemcpyAsync(&st, h->d_state, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    if (st.abort) return fail(PIC_EDEVICE, "batched kernel: grid barrier wait exceeded its limit");
+    for (pic_handle *t : h->tubes) {
+        DevCounters c;
+        pic_status s = read_counters(t, &c);
+        if (s != PIC_OK) return s;
+        if (c.status) return fail(PIC_EDEVSTATUS, "a tube latched device status bits 0x%llx", (unsigned long long)c.status);
+    }
     return PIC_OK;
 }
 
