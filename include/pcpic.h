@@ -136,6 +136,7 @@ typedef struct pic_diag {
     int64_t exit_sum_hi;
     double exit_gamma_sum; /* the same sum / 2^32 as a double                              */
     double gauss_max;      /* max |G_i| / (4 pi max|rho_GJ|), nodes 1..N-1 (want_gauss)    */
+    int64_t n_slots_high;  /* PIC_FP32_BULK: occupied slots of the f64-momentum stream      */
     double *ez;            /* [N]   E_z at faces                                           */
     double *er;            /* [N+1] E_r at nodes                                           */
     double *b_phi;         /* [N]   B_phi at faces                                         */

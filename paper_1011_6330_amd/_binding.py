@@ -59,7 +59,7 @@ class PicDiag(ctypes.Structure):
                 ("w0", ctypes.c_int64), ("status", ctypes.c_int64), ("e_surf", ctypes.c_double),
                 ("exit_sum_lo", ctypes.c_uint64), ("exit_sum_hi", ctypes.c_int64),
                 ("exit_gamma_sum", ctypes.c_double), ("gauss_max", ctypes.c_double),
-                ("ez", _pd), ("er", _pd), ("b_phi", _pd), ("rho_gj", _pd), ("j_last", _pi),
+                ("n_slots_high", ctypes.c_int64), ("ez", _pd), ("er", _pd), ("b_phi", _pd), ("rho_gj", _pd), ("j_last", _pi),
                 ("weights", _pi), ("gauss", _pd), ("prof_count", _pi), ("prof_mean", _pd),
                 ("prof_min", _pd), ("prof_max", _pd), ("prof_sum_lo", _pu), ("prof_sum_hi", _pi)]
 
@@ -250,7 +250,8 @@ class Tube(_TubeOps):
         if rc != 0 and (rc != -9 or raise_on_status):
             _check(rc, "pic_diagnostics")
         for k in ("step", "n_alive", "n_slots", "n_injected", "n_exit", "n_absorb", "last_n_inj", "w0",
-                  "status", "e_surf", "exit_sum_lo", "exit_sum_hi", "exit_gamma_sum", "gauss_max"):
+                  "status", "e_surf", "exit_sum_lo", "exit_sum_hi", "exit_gamma_sum", "gauss_max",
+                  "n_slots_high"):
             out[k] = getattr(d, k)
         return out
 

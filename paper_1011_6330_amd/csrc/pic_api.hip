@@ -515,6 +515,7 @@ pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out
     out->step = ctr.step;
     out->n_slots = ctr.n_slots + ctr.n_slots_hi;
     out->n_alive = ctr.n_slots + ctr.n_slots_hi - ctr.n_removed;
+    out->n_slots_high = ctr.n_slots_hi;
     out->n_injected = ctr.n_injected;
     out->n_exit = ctr.n_exit;
     out->n_absorb = ctr.n_absorb;
