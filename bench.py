@@ -1,15 +1,22 @@
 """Throughput of the polar-cap PIC step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+                    [--no-fp32] [--no-ensemble] [--no-cpu-baseline]
 
 A step is one whole PIC cycle of the tube: push + deposit, field update +
 SCLF injection, and the periodic cell sort.  Inputs are seeded synthetic
 tubes shaped like the paper's frame-dragging runs and are resident in HBM
-before the timed region.  Prints one JSON line.
+before the timed region.  Prints one JSON line:
+
+  value          particle-steps/s of the plain FP64 step on the configured tube
+  roofline       of the dominant kernel (the FP64 push), HIP-event timed
+  fp32_bulk      the same tube with the FP32-bulk push (f32 momentum below
+                 gamma = 1e6, f64 above), with its own roofline
+  ensemble       256 tubes of uneven size in one persistent launch per round
+  cpu_baseline   the single-threaded FP64 oracle on the same tube
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -19,14 +26,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/sec + % HBM roofline, FP64 plain vs FP32-bulk; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-BYTES_PER_PARTICLE_FP64 = 32   # x, u read + written per particle-step
+B_FP64 = 32                    # x, u (f64) read + written per particle-step
+B_F32_LOW = 24                 # cell, offset, u (f32)
+B_F32_HIGH = 32                # cell, offset (4 B each), u (f64)
 
 WORKLOADS = {
     "c1": "c1: flat-space SCLF tube, 1024 cells, cold start (~3e3 particles), dt=dz/2",
-    "c2": "c2: frame-dragging tube (kappa=0.15, R*=10R), 65536 cells, ~4.0e7 warm particles, "
+    "c2": "c2: frame-dragging tube (kappa=0.15, R*=10R, a=6878), 65536 cells, ~4.0e7 warm particles, "
           "gamma up to ~6e6, dt=dz/2, cell sort every 16 steps",
     "c4": "c4: 64-knot frame-dragging tube, 4096 cells, ~1e6 warm particles",
-    "c5": "c5: frame-dragging tube, 2^20 cells, L=100R, ~2.5e8 warm particles",
+    "c5": "c5: frame-dragging tube (a=6809), 2^20 cells, L=100R, ~2.5e8 warm particles, sort every 16",
 }
 
 
@@ -34,56 +43,83 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--push", default="64:2:nt", help="push launch shape threads:slots-per-thread[:nt]")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def run_tube(cfg, x, u, precision, steps, warmup, push=None, tune=True):
+    """Warm a tube up (tuning its push shape), then time `steps` steps."""
     import torch
 
-    from paper_1011_6330_amd import Tube, synth
-
-    cfg = synth.preset(args.config)
-    params = synth.tube_params(cfg)
-    log("config", args.config, "cells", cfg["n_cells"], "warm particles", cfg["warm"])
-    x, u = synth.warm_start(cfg)
-    torch.cuda.set_device(0)
-    tube = Tube(params, device="cuda:0")
+    from paper_1011_6330_amd import Tube, autotune, synth
+    tube = Tube(dict(synth.tube_params(cfg), precision=precision), device="cuda:0")
     if len(x):
         tube.inject(x, u)
-    log("injected", len(x))
-    parts = args.push.split(":")
-    pb, pp, pnt = int(parts[0]), int(parts[1]), len(parts) > 2 and parts[2] == "nt"
-    tube.set_push_config(pb, pp, pnt)
-    tube.step(args.warmup)
+    if push is not None:
+        tube.set_push_config(*push)
+        shape = push
+    elif tune:
+        b, p, nt, _ = autotune.tune_tube(tube, steps=max(4, warmup // 4), use_cache=False)
+        shape = (b, p, nt)
+    else:
+        shape = None
+    tube.step(warmup)
     tube.sync()
     d0 = tube.diagnostics(fields=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tim = tube.step_timed(args.steps)
+    tim = tube.step_timed(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     d1 = tube.diagnostics(fields=False)
-    elapsed = t1 - t0
-    alive_avg = 0.5 * (d0["n_alive"] + d1["n_alive"])
-    particle_steps = alive_avg * args.steps
-    value = particle_steps / elapsed
-    push_avg_s = tim["push_ms"] / max(tim["push_launches"], 1) / 1e3
-    achieved_gbs = BYTES_PER_PARTICLE_FP64 * alive_avg / push_avg_s / 1e9
-    log(f"elapsed {elapsed:.4f}s, push avg {push_avg_s * 1e6:.1f} us, field {tim['field_ms'] / args.steps * 1e3:.1f} us/step,"
-        f" sort {tim['sort_ms'] / max(tim['sort_launches'], 1) * 1e3:.1f} us/launch")
+    tube.close()
+    del tube
+    torch.cuda.empty_cache()
+    return d0, d1, tim, t1 - t0, shape
 
+
+def roofline_of(bytes_per_launch, tim, kernel):
+    push_avg_s = tim["push_ms"] / max(tim["push_launches"], 1) / 1e3
+    gbs = bytes_per_launch / push_avg_s / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "kernel": kernel, "avg_launch_us": push_avg_s * 1e6,
+            "bytes_per_launch": bytes_per_launch}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--push", default=None, help="fixed push shape threads:slots[:nt] (default: autotuned)")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(how the step would shard is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1011_6330_amd import synth
+
+    torch.cuda.set_device(0)
+    cfg = synth.preset(args.config)
+    log("config", args.config, "cells", cfg["n_cells"], "warm particles", cfg["warm"])
+    x, u = synth.warm_start(cfg)
+    push = None
+    if args.push:
+        parts = args.push.split(":")
+        push = (int(parts[0]), int(parts[1]), len(parts) > 2 and parts[2] == "nt")
+
+    # ---- plain FP64 step: the headline value ----
+    d0, d1, tim, elapsed, shape = run_tube(cfg, x, u, 0, args.steps, args.warmup, push=push)
+    alive = 0.5 * (d0["n_alive"] + d1["n_alive"])
+    value = alive * args.steps / elapsed
+    roof = roofline_of(B_FP64 * alive, tim, "k_push_f64")
+    log(f"fp64: {elapsed / args.steps * 1e3:.3f} ms/step, push {roof['avg_launch_us']:.1f} us "
+        f"({roof['achieved']:.0f} GB/s), shape {shape}")
     result = {
         "metric": METRIC,
         "value": value,
@@ -97,27 +133,76 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded warm-start beam shaped like the paper's frame-dragging runs)",
-        "config": {"workload": WORKLOADS[args.config], "n_cells": int(cfg["n_cells"]),
-                   "particles": int(alive_avg), "sort_every": int(cfg["sort_every"]),
-                   "push": f"fp64 {pb}x{pp}{' nt' if pnt else ''}"},
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_push_f64", "avg_launch_us": push_avg_s * 1e6,
-                     "bytes_per_launch": BYTES_PER_PARTICLE_FP64 * alive_avg},
+        "config": {"workload": WORKLOADS[args.config], "n_cells": int(cfg["n_cells"]), "particles": int(alive),
+                   "sort_every": int(cfg["sort_every"]), "push_shape": list(shape) if shape else None},
+        "roofline": roof,
         "breakdown_ms_per_step": {"push": tim["push_ms"] / args.steps, "field": tim["field_ms"] / args.steps,
                                   "sort": tim["sort_ms"] / args.steps},
     }
-    tube.close()
-    del tube
-    torch.cuda.empty_cache()
+
+    # ---- FP32-bulk push on the same tube ----
+    if not args.no_fp32:
+        f0, f1, ftim, fel, fshape = run_tube(cfg, x, u, 1, args.steps, args.warmup)
+        falive = 0.5 * (f0["n_alive"] + f1["n_alive"])
+        fhigh = 0.5 * (f0["n_slots_high"] + f1["n_slots_high"])
+        flow = max(falive - fhigh, 0.0)
+        froof = roofline_of(B_F32_LOW * flow + B_F32_HIGH * fhigh, ftim, "k_push_f32")
+        result["fp32_bulk"] = {"value": falive * args.steps / fel, "unit": "particle-steps/s",
+                               "ms_per_step": fel / args.steps * 1e3, "dtype": "f32+f64",
+                               "high_stream_fraction": fhigh / max(falive, 1.0), "push_shape": list(fshape),
+                               "roofline": froof, "vs_fp64": (falive * args.steps / fel) / value}
+        log(f"fp32-bulk: {fel / args.steps * 1e3:.3f} ms/step, push {froof['avg_launch_us']:.1f} us "
+            f"({froof['achieved']:.0f} GB/s), high-stream fraction {fhigh / max(falive, 1):.3f}")
+
+    # ---- ensemble: 256 tubes, one persistent launch per round ----
+    if not args.no_ensemble:
+        result["ensemble"] = run_ensemble(args.ensemble_steps)
+
+    result["adjoint_forward_ratio"] = None   # the hand-written adjoint is not built yet
+
     copy_gbs = copy_bandwidth(torch)
     result["roofline"]["achievable_copy_gbs"] = copy_gbs
-    result["roofline"]["frac_of_copy"] = achieved_gbs / copy_gbs
-    log(f"copy kernel {copy_gbs:.0f} GB/s; push {achieved_gbs:.0f} GB/s")
+    result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / copy_gbs
+    log(f"copy kernel {copy_gbs:.0f} GB/s")
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, x, u, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def run_ensemble(steps):
+    import torch
+
+    from paper_1011_6330_amd import Batch, autotune, synth
+    cfgs = synth.ensemble(n_tubes=256, seed=0, precision=1)
+    b = Batch([synth.tube_params(c) for c in cfgs], device="cuda:0")
+    for t, c in enumerate(cfgs):
+        x, u = synth.warm_start(c, seed=t)
+        b.tubes[t].inject(x, u)
+    log("ensemble loaded")
+    bb, bp, bpc, _ = autotune.tune_batch(b, use_cache=False)
+    b.step(32)
+    b.sync()
+    n0 = sum(t.diagnostics(fields=False)["n_alive"] for t in b.tubes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    b.sync()
+    n1 = sum(t.diagnostics(fields=False)["n_alive"] for t in b.tubes)
+    cfg = b.get_config()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    alive = 0.5 * (n0 + n1)
+    log(f"ensemble: {el / steps * 1e3:.3f} ms/step for {alive:.3g} particles in 256 tubes, shape {cfg}")
+    return {"value": alive * steps / el, "unit": "particle-steps/s", "ms_per_step": el / steps * 1e3,
+            "tubes": 256, "cells": int(sum(c["n_cells"] for c in cfgs)), "particles": int(alive),
+            "dtype": "f32+f64", "launch": cfg, "steps": steps,
+            "workload": "256 frame-dragging tubes, cells log-uniform 2048-65536, particles log-uniform 1e4-1e6, "
+                        "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk, one persistent graph-replayed "
+                        "launch per 16-step round"}
 
 
 def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
@@ -143,7 +228,8 @@ def cpu_baseline(cfg, x, u, seconds):
     """The oracle, as it stands, on the same warm tube for a bounded number of steps."""
     from oracle.oracle import OracleTube
     from paper_1011_6330_amd import synth
-    p = {k: v for k, v in synth.tube_params(cfg).items() if k not in ("sort_every", "max_bins", "precision")}
+    p = {k: v for k, v in synth.tube_params(cfg).items()
+         if k not in ("sort_every", "max_bins", "precision", "gamma_fp64")}
     o = OracleTube(p)
     if len(x):
         o.inject(x, u)
