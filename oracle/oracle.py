@@ -22,7 +22,8 @@ ST_CAPACITY, ST_NONFINITE = 1, 2
 
 DEFAULTS = dict(n_cells=1024, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=-1.0,
                 ppc=4.0, rho_kind=RHO_UNIFORM, rho_amp=1.0, kappa=0.0, r_star=10.0,
-                knots=None, fp_bits=32, flags=0, capacity=1 << 16)
+                knots=None, fp_bits=32, flags=0, capacity=1 << 16, macro_charge=0.0, inj_rate=0.0,
+                schedule=None)
 
 _pd = ctypes.POINTER(ctypes.c_double)
 _pi = ctypes.POINTER(ctypes.c_int64)
@@ -36,7 +37,8 @@ class OrcCfg(ctypes.Structure):
                 ("rho_amp", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("r_star", ctypes.c_double), ("knots", _pd),
                 ("fp_bits", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("capacity", ctypes.c_int64)]
+                ("capacity", ctypes.c_int64), ("macro_charge", ctypes.c_double),
+                ("inj_rate", ctypes.c_double), ("schedule", _pi), ("n_schedule", ctypes.c_int64)]
 
 
 class OrcState(ctypes.Structure):
@@ -47,7 +49,7 @@ class OrcState(ctypes.Structure):
                 ("n_absorb", ctypes.c_int64), ("w0", ctypes.c_int64),
                 ("last_ninj", ctypes.c_int64), ("status", ctypes.c_int64),
                 ("exit_sum_lo", ctypes.c_uint64), ("exit_sum_hi", ctypes.c_int64),
-                ("e_surf", ctypes.c_double)]
+                ("e_surf", ctypes.c_double), ("cls", ctypes.POINTER(ctypes.c_uint8)), ("j_inj", _pi)]
 
 
 _lib = None
@@ -70,6 +72,8 @@ def load():
         lib.orc_gauss.argtypes = [P(OrcCfg), P(OrcState), _pd, _pd]
         lib.orc_profile.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int32, _pi,
                                     P(ctypes.c_uint64), _pi, _pd, _pd]
+        lib.orc_adjoint.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int64, _pd, _pd, _pd, _pi]
+        lib.orc_adjoint.restype = ctypes.c_int
         for f in ("orc_rho_gj", "orc_weights", "orc_init", "orc_inject", "orc_step",
                   "orc_gauss", "orc_profile"):
             getattr(lib, f).restype = ctypes.c_int
@@ -99,11 +103,15 @@ class OracleTube:
         self.N = N
         knots = c.get("knots")
         self._knots = None if knots is None else np.ascontiguousarray(knots, dtype=np.float64)
+        sched = c.get("schedule")
+        self._sched = None if sched is None else np.ascontiguousarray(sched, dtype=np.int64)
         self.ccfg = OrcCfg(N, c["length"], c["radius"], c["dt_over_dz"], c["q_over_m"], c["ppc"],
                            int(c["rho_kind"]), 0 if self._knots is None else len(self._knots),
                            c["rho_amp"], c["kappa"], c["r_star"],
                            None if self._knots is None else _ptr(self._knots),
-                           int(c["fp_bits"]), int(c["flags"]), cap)
+                           int(c["fp_bits"]), int(c["flags"]), cap, float(c["macro_charge"]),
+                           float(c["inj_rate"]), None if self._sched is None else _ptr(self._sched, _pi),
+                           0 if self._sched is None else len(self._sched))
         self._x = np.zeros(cap, np.float64)
         self._u = np.zeros(cap, np.float64)
         self.rho_gj = np.zeros(N + 1)
@@ -116,9 +124,13 @@ class OracleTube:
         self._cp = np.zeros(N + 1)
         self._dp = np.zeros(N + 1)
         self.w = np.zeros(N + 1, np.int64)
+        self._cls = np.zeros(cap, np.uint8)
+        self.j_inj = np.zeros(N, np.int64)
         self.st = OrcState(_ptr(self._x), _ptr(self._u), _ptr(self.rho_gj), _ptr(self.ez),
                            _ptr(self.er), _ptr(self.b), _ptr(self.j, _pi), _ptr(self.k),
                            _ptr(self.phi), _ptr(self._cp), _ptr(self._dp), _ptr(self.w, _pi))
+        self.st.cls = self._cls.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        self.st.j_inj = _ptr(self.j_inj, _pi)
         rc = self.lib.orc_init(ctypes.byref(self.ccfg), ctypes.byref(self.st))
         if rc != 0:
             raise ValueError(f"orc_init rejected the configuration (rc={rc})")
@@ -158,6 +170,23 @@ class OracleTube:
                              lo.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _ptr(hi, _pi),
                              _ptr(mn), _ptr(mx))
         return cnt, lo, hi, mn, mx
+
+    def adjoint(self, n_steps):
+        """Run n_steps recording, then the reverse sweep: returns (loss, n_exit,
+        dL/d rho_GJ at the nodes, dL/d inj_rate)."""
+        g = np.zeros(self.N + 1)
+        gr = ctypes.c_double(0.0)
+        loss = ctypes.c_double(0.0)
+        nex = ctypes.c_int64(0)
+        rc = self.lib.orc_adjoint(ctypes.byref(self.ccfg), ctypes.byref(self.st), int(n_steps), _ptr(g),
+                                  ctypes.byref(gr), ctypes.byref(loss), ctypes.byref(nex))
+        if rc != 0:
+            raise ValueError(f"orc_adjoint failed (rc={rc})")
+        return loss.value, nex.value, g, gr.value
+
+    @property
+    def cls(self):
+        return self._cls[: self.st.n]
 
     def rho_gj_of(self):
         r = np.zeros(self.N + 1)

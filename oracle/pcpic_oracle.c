@@ -77,7 +77,9 @@ static void orc_consts(const orc_cfg *c, const orc_state *st, orc_const *k)
     k->dtR = k->dt / c->radius;
     k->qmdt = c->q_over_m * k->dt;
     k->rho0 = st->rho_gj[0];
-    k->qm = (k->rho0 * k->dz) / c->ppc;          /* macro-particle charge (per unit area) */
+    /* macro-particle charge (per unit area); an explicit value keeps it fixed when
+     * the background is varied (gradients, finite differences) */
+    k->qm = c->macro_charge != 0.0 ? c->macro_charge : (k->rho0 * k->dz) / c->ppc;
     k->twoP = ldexp(1.0, c->fp_bits);
     k->oneP = (int64_t)1 << c->fp_bits;
     k->qmP = k->qm / k->twoP;                      /* charge of one weight unit */
@@ -186,7 +188,11 @@ int orc_inject(const orc_cfg *c, orc_state *st, int64_t n, const double *x, cons
     for (int64_t p = 0; p < n; ++p) {
         if (!(x[p] >= 0.0 && x[p] < (double)c->n_cells) || !isfinite(u[p])) return -1;
     }
-    for (int64_t p = 0; p < n; ++p) { st->x[st->n + p] = x[p]; st->u[st->n + p] = u[p]; }
+    for (int64_t p = 0; p < n; ++p) {
+        st->x[st->n + p] = x[p];
+        st->u[st->n + p] = u[p];
+        if (st->cls) st->cls[st->n + p] = 0;
+    }
     st->n += n;
     if (st->step == 0) orc_solve_fields(c, st);
     return 0;
@@ -212,8 +218,11 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
     /* kick array from the current E_z: K = (q/m) dt E_z */
     for (int64_t i = 0; i < N; ++i) st->k[i] = k.qmdt * st->ez[i];
     for (int64_t i = 0; i < N; ++i) st->j[i] = 0;
+    if (st->j_inj)
+        for (int64_t i = 0; i < N; ++i) st->j_inj[i] = 0;
+    const double rate = c->inj_rate > 0.0 ? c->inj_rate : 1.0;
 
-    int64_t w0 = 0, kept = 0;
+    int64_t w0 = 0, w0_inj = 0, kept = 0;
     for (int64_t p = 0; p < st->n; ++p) {
         double x = st->x[p], u = st->u[p];
         /* gather: linear interpolation of the face values, clamped at the ends */
@@ -243,8 +252,12 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
         int64_t lo = c0 < c1 ? c0 : c1, hi = c0 < c1 ? c1 : c0;
         if (lo < 0) lo = 0;
         if (hi > N - 1) hi = N - 1;
-        for (int64_t i = lo; i <= hi; ++i)
-            st->j[i] += orc_S(i, c0, F0, k.oneP) - orc_S(i, c1, F1, k.oneP);
+        const int injected = st->cls && st->cls[p];
+        for (int64_t i = lo; i <= hi; ++i) {
+            const int64_t d = orc_S(i, c0, F0, k.oneP) - orc_S(i, c1, F1, k.oneP);
+            st->j[i] += d;
+            if (injected && st->j_inj) st->j_inj[i] += d;
+        }
 
         if (x1 >= (double)N) {               /* leaves through the top of the tube */
             st->n_exit += 1;
@@ -255,9 +268,13 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
             st->n_absorb += 1;
             continue;
         }
-        if (c1 == 0) w0 += k.oneP - F1;      /* node-0 weight of the survivors */
+        if (c1 == 0) {                       /* node-0 weight of the survivors */
+            w0 += k.oneP - F1;
+            if (injected) w0_inj += k.oneP - F1;
+        }
         st->x[kept] = x1;
         st->u[kept] = u1;
+        if (st->cls) st->cls[kept] = st->cls[p];
         ++kept;
     }
     st->n = kept;
@@ -272,19 +289,39 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
         for (int64_t i = 1; i < N; ++i)
             st->er[i] = st->er[i] - k.dtdz * (st->b[i] - st->b[i - 1]);
         st->er[N] = st->er[N] + k.tw * st->b[N - 1];
-        for (int64_t i = 0; i < N; ++i)
-            st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) - k.c4 * (double)st->j[i];
+        if (rate == 1.0 || !st->j_inj) {
+            for (int64_t i = 0; i < N; ++i)
+                st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) - k.c4 * (double)st->j[i];
+        } else {
+            /* injected particles carry rate * q_m */
+            for (int64_t i = 0; i < N; ++i) {
+                const double jw = (double)(st->j[i] - st->j_inj[i]) + rate * (double)st->j_inj[i];
+                st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) - k.c4 * jw;
+            }
+        }
     }
 
     /* SCLF injection (sec. 2): the field at the surface from the node-0 Gauss law
      * over the half cell [0, dz/2]; electrons are added at x = 0 with u = 0 until
      * the base charge cancels it (never over-injecting). */
-    double t1 = k.qmP * (double)w0;
+    double t1 = rate == 1.0 ? k.qmP * (double)w0
+                            : k.qmP * ((double)(w0 - w0_inj) + rate * (double)w0_inj);
     double t2 = k.rho0 * k.hdz;
     double es = st->ez[0] - k.fourpi * (t1 - t2);
     st->e_surf = es;
     int64_t ninj = 0;
-    if (!(c->flags & ORC_NO_AUTO_INJECT)) {
+    if (c->schedule) {                       /* frozen injection counts of a recorded run */
+        ninj = st->step < c->n_schedule ? c->schedule[st->step] : 0;
+        int64_t avail = c->capacity - st->n;
+        if (ninj > avail) { ninj = avail; st->status |= ORC_ST_CAPACITY; }
+        for (int64_t p = 0; p < ninj; ++p) {
+            st->x[st->n + p] = 0.0;
+            st->u[st->n + p] = 0.0;
+            if (st->cls) st->cls[st->n + p] = 1;
+        }
+        st->n += ninj;
+        st->n_injected += ninj;
+    } else if (!(c->flags & ORC_NO_AUTO_INJECT)) {
         double ratio = es / k.fqm;
         if (ratio > 0.0) {
             double nf = floor(ratio);
@@ -292,7 +329,11 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
             if (nf > (double)avail) { ninj = avail; st->status |= ORC_ST_CAPACITY; }
             else ninj = (int64_t)nf;
         }
-        for (int64_t p = 0; p < ninj; ++p) { st->x[st->n + p] = 0.0; st->u[st->n + p] = 0.0; }
+        for (int64_t p = 0; p < ninj; ++p) {
+            st->x[st->n + p] = 0.0;
+            st->u[st->n + p] = 0.0;
+            if (st->cls) st->cls[st->n + p] = 1;
+        }
         st->n += ninj;
         st->n_injected += ninj;
     }
@@ -355,5 +396,187 @@ int orc_profile(const orc_cfg *c, const orc_state *st, int32_t nb, int64_t *coun
         if (sg < gmin[b]) gmin[b] = sg;
         if (sg > gmax[b]) gmax[b] = sg;
     }
+    return 0;
+}
+
+/* ---- reverse-mode gradient (test reference) ------------------------------- */
+
+/* Transposed Thomas solve of A^T y = g on nodes 1..N, A the eq. (4) matrix of
+ * orc_solve_fields (rows 1..N-1: 1, bdiag, 1; row N: 2, bdiag).  A^T has the 2
+ * on the super-diagonal of row N-1. */
+static void orc_poisson_transpose(int64_t N, double bdiag, const double *g, double *y, double *cp, double *dp)
+{
+    /* row i of A^T: sub 1 (i >= 2), diag bdiag, super (i == N-1 ? 2 : 1) (i <= N-1) */
+    double sup = (N - 1 == 1) ? 2.0 : 1.0;
+    cp[1] = sup / bdiag;
+    dp[1] = g[1] / bdiag;
+    for (int64_t i = 2; i <= N; ++i) {
+        double m = bdiag - 1.0 * cp[i - 1];
+        double c = (i <= N - 1) ? ((i == N - 1) ? 2.0 : 1.0) : 0.0;
+        cp[i] = c / m;
+        dp[i] = (g[i] - 1.0 * dp[i - 1]) / m;
+    }
+    y[N] = dp[N];
+    for (int64_t i = N - 1; i >= 1; --i) y[i] = dp[i] - cp[i] * y[i + 1];
+}
+
+int orc_adjoint(const orc_cfg *c, orc_state *st, int64_t T, double *g_rho, double *g_rate, double *loss,
+                int64_t *n_exit_out)
+{
+    if (orc_check(c) || !st || T < 1 || !st->cls || !st->j_inj) return -1;
+    if (c->flags & ORC_FREEZE_FIELDS) return -1;
+    orc_const k;
+    orc_consts(c, st, &k);
+    const int64_t N = k.N;
+    const int P = c->fp_bits;
+    const double rate = c->inj_rate > 0.0 ? c->inj_rate : 1.0;
+    const double twoP = k.twoP;
+
+    /* ---- forward, recording every step's starting state ---- */
+    int64_t *n_at = malloc(sizeof(int64_t) * (size_t)(T + 1));
+    double **X = calloc((size_t)T, sizeof(double *)), **U = calloc((size_t)T, sizeof(double *));
+    unsigned char **C = calloc((size_t)T, sizeof(unsigned char *));
+    double *EZ = malloc(sizeof(double) * (size_t)(T * N)), *ER = malloc(sizeof(double) * (size_t)(T * (N + 1)));
+    double *BB = malloc(sizeof(double) * (size_t)(T * N));
+    if (!n_at || !X || !U || !C || !EZ || !ER || !BB) return -2;
+    const int64_t ex0 = st->n_exit;
+    const __int128 s0 = ((__int128)st->exit_sum_hi << 64) | (__int128)st->exit_sum_lo;
+    for (int64_t s = 0; s < T; ++s) {
+        const int64_t n = st->n;
+        n_at[s] = n;
+        X[s] = malloc(sizeof(double) * (size_t)(n + 1));
+        U[s] = malloc(sizeof(double) * (size_t)(n + 1));
+        C[s] = malloc((size_t)(n + 1));
+        if (!X[s] || !U[s] || !C[s]) return -2;
+        memcpy(X[s], st->x, sizeof(double) * (size_t)n);
+        memcpy(U[s], st->u, sizeof(double) * (size_t)n);
+        memcpy(C[s], st->cls, (size_t)n);
+        memcpy(EZ + s * N, st->ez, sizeof(double) * (size_t)N);
+        memcpy(ER + s * (N + 1), st->er, sizeof(double) * (size_t)(N + 1));
+        memcpy(BB + s * N, st->b, sizeof(double) * (size_t)N);
+        orc_one_step(c, st);
+    }
+    n_at[T] = st->n;
+    const int64_t nex = st->n_exit - ex0;
+    const __int128 s1 = ((__int128)st->exit_sum_hi << 64) | (__int128)st->exit_sum_lo;
+    const double L = nex > 0 ? ldexp((double)(s1 - s0), -32) / (double)nex : 0.0;
+    if (loss) *loss = L;
+    if (n_exit_out) *n_exit_out = nex;
+
+    /* ---- reverse sweep ---- */
+    double *lx = calloc((size_t)(n_at[T] + 1), sizeof(double)), *lu = calloc((size_t)(n_at[T] + 1), sizeof(double));
+    double *lez = calloc((size_t)N, sizeof(double)), *ler = calloc((size_t)(N + 1), sizeof(double));
+    double *lb = calloc((size_t)N, sizeof(double)), *lbp = calloc((size_t)N, sizeof(double));
+    double *lk = calloc((size_t)N, sizeof(double)), *kk = calloc((size_t)N, sizeof(double));
+    double grate = 0.0;
+    for (int64_t s = T - 1; s >= 0; --s) {
+        const double *ez = EZ + s * N;
+        for (int64_t i = 0; i < N; ++i) { kk[i] = k.qmdt * ez[i]; lk[i] = 0.0; }
+        /* adjoint of B^{s+1/2}: its own adjoint plus its uses in E_r and E_z of step s */
+        for (int64_t i = 0; i < N; ++i) {
+            double a = lb[i] + k.dtR * lez[i];
+            if (i >= 1 && i <= N - 1) a -= k.dtdz * ler[i];
+            if (i + 1 <= N - 1) a += k.dtdz * ler[i + 1];
+            if (i == N - 1) a += k.tw * ler[N];
+            lbp[i] = a;
+        }
+        /* particles of step s (in order; survivors keep their order at step s+1) */
+        const int64_t n = n_at[s];
+        double *nlx = calloc((size_t)(n + 1), sizeof(double)), *nlu = calloc((size_t)(n + 1), sizeof(double));
+        int64_t jn = 0;
+        for (int64_t p = 0; p < n; ++p) {
+            const double x = X[s][p], u = U[s][p];
+            const double wcls = C[s][p] ? rate : 1.0;
+            const double sx = x - 0.5;
+            int64_t jj = 0;
+            double g = 0.0, dEdx = 0.0;
+            int clamp = 0;
+            if (sx < 0.0) { clamp = 1; }
+            else if (sx >= (double)(N - 1)) { clamp = 2; }
+            else {
+                jj = (int64_t)floor(sx);
+                g = sx - (double)jj;
+                dEdx = kk[jj + 1] - kk[jj];
+            }
+            const double E = clamp == 1 ? kk[0] : (clamp == 2 ? kk[N - 1] : kk[jj] + g * (kk[jj + 1] - kk[jj]));
+            const double u1 = u + E;
+            double t = u1 * u1;
+            t = 1.0 + t;
+            const double gam = sqrt(t);
+            const double v = u1 / gam;
+            const double x1 = x + k.dtdz * v;
+            int64_t c0, F0, c1, F1;
+            orc_cell(x, P, &c0, &F0);
+            orc_cell(x1, P, &c1, &F1);
+            double lx1 = 0.0, lu1 = 0.0;
+            if (x1 >= (double)N) {
+                lu1 = nex > 0 ? (u1 / gam) / (double)nex : 0.0;   /* d gamma / du = u / gamma */
+            } else if (x1 < 0.0) {
+                /* absorbed: no further influence */
+            } else {
+                lx1 = lx[jn];
+                lu1 = lu[jn];
+                ++jn;
+            }
+            /* current: J_i = S_i(x) - S_i(x1), dS_i/dx = -2^P in cell i, scaled by the
+             * particle's charge factor; E_z^{s+1} = ... - c4 * J */
+            if (c1 >= 0 && c1 < N) lx1 += twoP * (-k.c4 * wcls * lez[c1]);
+            const double lx0J = -twoP * (-k.c4 * wcls * lez[c0]);
+            if (C[s][p]) {
+                /* dL/d rate: the particle's deposit times -c4 times the adjoint of E_z^{s+1} */
+                int64_t lo = c0 < c1 ? c0 : c1, hi = c0 < c1 ? c1 : c0;
+                if (lo < 0) lo = 0;
+                if (hi > N - 1) hi = N - 1;
+                for (int64_t i = lo; i <= hi; ++i)
+                    grate += (double)(orc_S(i, c0, F0, k.oneP) - orc_S(i, c1, F1, k.oneP)) * (-k.c4) * lez[i];
+            }
+            /* move: x1 = x + (dt/dz) u1 / gamma(u1), dv/du = 1/gamma^3 */
+            const double lu1t = lu1 + lx1 * k.dtdz / (gam * gam * gam);
+            nlx[p] = lx1 + lx0J + lu1t * dEdx;
+            nlu[p] = lu1t;
+            /* kick: E = K_j (1 - g) + K_{j+1} g */
+            if (clamp == 1) lk[0] += lu1t;
+            else if (clamp == 2) lk[N - 1] += lu1t;
+            else { lk[jj] += lu1t * (1.0 - g); lk[jj + 1] += lu1t * g; }
+        }
+        free(lx);
+        free(lu);
+        lx = nlx;
+        lu = nlu;
+        /* fields of step s: E_z^{s+1} = E_z + dtR B' - c4 J; B' = B - (dtdz (E_r,i+1 - E_r,i) + dtR E_z) */
+        for (int64_t i = 0; i < N; ++i) {
+            const double a = lez[i] - k.dtR * lbp[i] + k.qmdt * lk[i];
+            lez[i] = a;
+        }
+        double *nler = calloc((size_t)(N + 1), sizeof(double));
+        for (int64_t i = 0; i <= N; ++i) {
+            double a = ler[i];
+            if (i <= N - 1) a += k.dtdz * lbp[i];
+            if (i >= 1) a -= k.dtdz * lbp[i - 1];
+            nler[i] = a;
+        }
+        free(ler);
+        ler = nler;
+        for (int64_t i = 0; i < N; ++i) lb[i] = lbp[i];
+    }
+    /* Poisson start (eq. 4): E_z = -dphi/dz, E_r = phi/R, A phi = d, d_i = -cpois (rho_i - rho_GJ,i) */
+    if (g_rho) {
+        double *gphi = calloc((size_t)(N + 1), sizeof(double)), *y = calloc((size_t)(N + 1), sizeof(double));
+        double *cp = calloc((size_t)(N + 1), sizeof(double)), *dp = calloc((size_t)(N + 1), sizeof(double));
+        for (int64_t m = 1; m <= N; ++m) {
+            double a = -lez[m - 1] / k.dz + ler[m] / c->radius;
+            if (m <= N - 1) a += lez[m] / k.dz;
+            gphi[m] = a;
+        }
+        const double rr = k.dz / c->radius;
+        orc_poisson_transpose(N, -(2.0 + rr * rr), gphi, y, cp, dp);
+        g_rho[0] = 0.0;
+        for (int64_t i = 1; i <= N; ++i) g_rho[i] = k.fourpi * (k.dz * k.dz) * y[i];
+        free(gphi); free(y); free(cp); free(dp);
+    }
+    if (g_rate) *g_rate = grate;
+    for (int64_t s = 0; s < T; ++s) { free(X[s]); free(U[s]); free(C[s]); }
+    free(X); free(U); free(C); free(EZ); free(ER); free(BB); free(n_at);
+    free(lx); free(lu); free(lez); free(ler); free(lb); free(lbp); free(lk); free(kk);
     return 0;
 }

@@ -63,6 +63,11 @@ typedef struct orc_cfg {
     int32_t fp_bits;      /* P, fixed-point fraction bits of the weights          */
     uint32_t flags;       /* ORC_NO_AUTO_INJECT | ORC_FREEZE_FIELDS               */
     int64_t capacity;     /* particle array capacity                              */
+    double macro_charge;  /* q_m; 0 = rho_GJ(0) dz / ppc                          */
+    double inj_rate;      /* charge factor of particles injected during the run (0 = 1) */
+    const int64_t *schedule; /* if not NULL: particles injected at step n = schedule[n]
+                                (replaces the SCLF rule; frozen decisions)         */
+    int64_t n_schedule;
 } orc_cfg;
 
 /* All arrays are owned by the caller; the oracle never allocates them. */
@@ -90,6 +95,8 @@ typedef struct orc_state {
     uint64_t exit_sum_lo; /* 128-bit sum of rint(gamma * 2^32) over exits        */
     int64_t exit_sum_hi;
     double e_surf;        /* surface field after the last step                   */
+    unsigned char *cls;   /* [capacity] 0 = loaded before the first step, 1 = injected */
+    int64_t *j_inj;       /* [N] injected-class part of j (in j already)         */
 } orc_state;
 
 /* Background charge density at the N+1 nodes. */
@@ -110,6 +117,19 @@ int orc_gauss(const orc_cfg *cfg, orc_state *st, double *g, double *gmax);
  * Sums are 128-bit fixed point in units of 2^-32 (lo/hi words). */
 int orc_profile(const orc_cfg *cfg, const orc_state *st, int32_t nb, int64_t *count,
                 uint64_t *sum_lo, int64_t *sum_hi, double *gmin, double *gmax);
+
+/* Reverse-mode gradient of the loss L = (sum of gamma over particles leaving
+ * through x = N during n_steps steps) / (their number), with every discrete
+ * decision of the recorded run frozen (injection counts, which particle leaves
+ * or returns, cell crossings; rint taken as the identity).  The run starts from
+ * the state *st0 (fields, particles, counters as after orc_init / orc_inject),
+ * which is advanced in place.  Outputs (each may be NULL):
+ *   g_rho[N+1]  dL/d rho_GJ at the nodes (through the Poisson start of eq. 4),
+ *   g_rate      dL/d inj_rate,
+ *   loss, n_exit.
+ * The particle states of every step are kept in memory (plain and slow). */
+int orc_adjoint(const orc_cfg *cfg, orc_state *st, int64_t n_steps, double *g_rho, double *g_rate,
+                double *loss, int64_t *n_exit);
 
 #ifdef __cplusplus
 }
