@@ -108,6 +108,8 @@ typedef struct pic_params {
     uint32_t flags;           /* PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS                      */
     int32_t max_bins;         /* largest signed-gamma profile pic_diagnostics may request    */
     double gamma_fp64;        /* PIC_FP32_BULK: gamma from which u is kept in f64 (0 = 1e6)  */
+    double macro_charge;      /* q_m (per unit area); 0 = rho_GJ(0) dz / ppc.  A fixed value
+                                 keeps the particle charge independent of rho_GJ (gradients) */
 } pic_params;
 
 typedef struct pic_handle pic_handle;
@@ -269,6 +271,41 @@ pic_status pic_batch_set_config(pic_handle *batch, int32_t block, int32_t per_th
 /* Current launch shape (any pointer may be NULL); grid = CUs x blocks per CU. */
 pic_status pic_batch_get_config(pic_handle *batch, int32_t *block, int32_t *per_thread, int32_t *blocks_per_cu,
                                 int32_t *grid);
+
+/* ---- hand-written adjoint ----
+ *
+ * Loss L = mean Lorentz factor of the electrons that leave through z = L during
+ * n_steps steps.  pic_run_adjoint advances the tube by n_steps (the same steps
+ * pic_step would take) while checkpointing every checkpoint_every steps into
+ * the caller's device tape, then runs the reverse sweep, recomputing each
+ * segment from its checkpoint, and returns dL/d(parameters).  Every discrete
+ * decision of the run is held fixed (injection counts, exits and returns, cell
+ * crossings; the fixed-point rounding is taken as the identity), and the
+ * macro-particle charge is the one pic_params fixes (set macro_charge so that
+ * it does not move with rho_GJ).  rho_GJ enters only through the Poisson start
+ * of eq. (4), whose transpose closes the sweep.  Requirements: PIC_FP64,
+ * sort_every = 0, fields not frozen, a single tube (not a batch).  The device
+ * status word is not changed; the tube ends in the state n_steps steps later. */
+typedef struct pic_adjoint_out {
+    double loss;            /* L                                                        */
+    int64_t n_exit;         /* electrons in the mean                                    */
+    double g_rate;          /* dL/d(charge factor of electrons injected during the run) */
+    double g_kappa;         /* dL/d kappa (PIC_RHO_FRAME_DRAG and PIC_RHO_KNOTS)        */
+    double g_amp;           /* dL/d A (PIC_RHO_UNIFORM and PIC_RHO_FRAME_DRAG)          */
+    double *g_rho;          /* host [N+1] or NULL: dL/d rho_GJ at the nodes             */
+    double *g_knots;        /* host [n_knots] or NULL: dL/d theta_k (PIC_RHO_KNOTS)     */
+    double forward_ms;      /* device time of the checkpointed forward                  */
+    double backward_ms;     /* device time of the recompute + reverse sweep             */
+} pic_adjoint_out;
+
+/* Device bytes of the tape pic_run_adjoint needs (checkpoints, one segment of
+ * recorded steps, adjoint arrays), 0 if the handle cannot run the adjoint. */
+size_t pic_adjoint_tape_bytes(pic_handle *h, int64_t n_steps, int32_t checkpoint_every);
+
+/* Errors: PIC_EINVAL (requirements above), PIC_EWORKSPACE (tape too small or
+ * misaligned), PIC_EDEVICE. */
+pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_every, void *d_tape,
+                           size_t tape_bytes, pic_adjoint_out *out);
 
 /* Synchronise the stream; PIC_EDEVSTATUS if a status bit is latched. */
 pic_status pic_sync(pic_handle *h);

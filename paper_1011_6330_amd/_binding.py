@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_EWORKSPACE", -3: "PIC_EC
 DEFAULTS = dict(precision=FP64, n_cells=1024, length=10.0, radius=1.0, dt_over_dz=0.5,
                 q_over_m=-1.0, ppc=4.0, rho_kind=RHO_UNIFORM, rho_amp=1.0, kappa=0.0,
                 r_star=10.0, knots=None, fp_bits=32, sort_every=0, capacity=1 << 16, flags=0,
-                max_bins=1024, gamma_fp64=0.0)
+                max_bins=1024, gamma_fp64=0.0, macro_charge=0.0)
 
 _pd = ctypes.POINTER(ctypes.c_double)
 _pi = ctypes.POINTER(ctypes.c_int64)
@@ -45,7 +45,8 @@ class PicParams(ctypes.Structure):
                 ("r_star", ctypes.c_double), ("knots", _pd),
                 ("fp_bits", ctypes.c_int32), ("sort_every", ctypes.c_int32),
                 ("capacity", ctypes.c_int64), ("flags", ctypes.c_uint32),
-                ("max_bins", ctypes.c_int32), ("gamma_fp64", ctypes.c_double)]
+                ("max_bins", ctypes.c_int32), ("gamma_fp64", ctypes.c_double),
+                ("macro_charge", ctypes.c_double)]
 
 
 class PicDiagReq(ctypes.Structure):
@@ -71,6 +72,12 @@ class PicTiming(ctypes.Structure):
                 ("sort_launches", ctypes.c_int64), ("particle_steps", ctypes.c_int64)]
 
 
+class PicAdjointOut(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_double), ("n_exit", ctypes.c_int64), ("g_rate", ctypes.c_double),
+                ("g_kappa", ctypes.c_double), ("g_amp", ctypes.c_double), ("g_rho", _pd),
+                ("g_knots", _pd), ("forward_ms", ctypes.c_double), ("backward_ms", ctypes.c_double)]
+
+
 # Every symbol include/pcpic.h declares, with its ctypes signature.
 SIGNATURES = {
     "pic_abi_version": (ctypes.c_int32, []),
@@ -89,6 +96,9 @@ SIGNATURES = {
     "pic_set_push_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_uint32]),
     "pic_sync": (ctypes.c_int32, [ctypes.c_void_p]),
+    "pic_adjoint_tape_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32]),
+    "pic_run_adjoint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.POINTER(PicAdjointOut)]),
     "pic_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PicParams), ctypes.c_int32]),
     "pic_init_batch": (ctypes.c_int32, [ctypes.POINTER(PicParams), ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -146,7 +156,7 @@ def make_params(cfg=None, **kw):
                   int(c["rho_kind"]), 0 if knots is None else len(knots), float(c["rho_amp"]),
                   float(c["kappa"]), float(c["r_star"]), _ptr(knots), int(c["fp_bits"]),
                   int(c["sort_every"]), int(c["capacity"]), int(c["flags"]), int(c["max_bins"]),
-                  float(c["gamma_fp64"]))
+                  float(c["gamma_fp64"]), float(c["macro_charge"]))
     return p, knots, c
 
 
@@ -217,6 +227,30 @@ class Tube(_TubeOps):
 
     def sync(self):
         _check(self.lib.pic_sync(self._h), "pic_sync")
+
+    def run_adjoint(self, n_steps, checkpoint_every=50, tape=None):
+        """Advance n_steps with checkpoints, then the reverse sweep: returns the loss
+        (mean exit gamma), its gradient and the device times.  The tape is a torch
+        uint8 tensor (allocated here when not given)."""
+        import torch
+        nbytes = self.lib.pic_adjoint_tape_bytes(self._h, int(n_steps), int(checkpoint_every))
+        if nbytes == 0:
+            raise PicError(-1, "pic_adjoint_tape_bytes", self.lib.pic_last_error().decode())
+        if tape is None or tape.numel() < nbytes:
+            with torch.cuda.device(self.device):
+                tape = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        out = PicAdjointOut()
+        g_rho = np.zeros(self.N + 1)
+        nk = 0 if self.cfg.get("knots") is None else len(self.cfg["knots"])
+        g_knots = np.zeros(max(nk, 1))
+        out.g_rho = _ptr(g_rho)
+        out.g_knots = _ptr(g_knots)
+        _check(self.lib.pic_run_adjoint(self._h, int(n_steps), int(checkpoint_every),
+                                        ctypes.c_void_p(tape.data_ptr()), nbytes, ctypes.byref(out)),
+               "pic_run_adjoint")
+        return dict(loss=out.loss, n_exit=out.n_exit, g_rate=out.g_rate, g_kappa=out.g_kappa, g_amp=out.g_amp,
+                    g_rho=g_rho, g_knots=g_knots[:nk], forward_ms=out.forward_ms, backward_ms=out.backward_ms,
+                    tape_bytes=nbytes)
 
     def diagnostics(self, n_bins=0, gauss=False, fields=True, j=False, weights=False, rho=False,
                     raise_on_status=True):

@@ -1,0 +1,368 @@
+// k_adjoint.hip -- reverse-mode gradient of the mean exit Lorentz factor
+// through the FP64 PIC step, with every discrete decision frozen (injection
+// counts, exits and returns, cell crossings; rint taken as the identity).
+//
+// One reverse step s, given the adjoints of the state after the step
+// (particles lx, lu per slot; fields lez = dL/dE_z^{s+1}, ler = dL/dE_r^{s+1},
+// lb = dL/dB^{s+1/2}) and the recorded state before it (slots X_s, U_s, fields):
+//   1. lbp = dL/dB^{s+1/2} through its uses in E_r^{s+1} and E_z^{s+1}; clear lk;
+//   2. per slot: recompute the push, route the adjoints through the move, the
+//      gather (into lk, the adjoint of the kick array) and the fixed-point
+//      current (J enters E_z^{s+1} with weight -c4);
+//   3. lez, ler, lb <- adjoints of E^s, B^{s-1/2} (transposed leap-frog of eq. 3).
+// After step 0 the field adjoints go through the transposed Poisson problem of
+// eq. (4) to dL/d rho_GJ.  Slots keep their particle across steps (no sort in an
+// adjoint run), so the particle adjoints are updated in place.
+#include <math.h>
+
+#include "pcpic_internal.h"
+#include "wave.h"
+
+namespace pcpic {
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// dst[key] += val for every lane with `want`, one FP64 atomic per distinct key.
+__device__ __forceinline__ void wave_add_keyed_f64(double *dst, int key, double val, bool want)
+{
+    unsigned long long pend = __ballot(want);
+    while (pend) {
+        const int leader = __ffsll(pend) - 1;
+        const int lk = __shfl(key, leader);
+        const bool mine = want && key == lk;
+        const double v = wave_sum_f64(mine ? val : 0.0);
+        if ((int)__lane_id() == leader && v != 0.0) atomicAdd(dst + lk, v);
+        pend &= ~__ballot(mine);
+        want = want && !mine;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_slots(const double *X, const double *U, double *Xc, double *Uc,
+                                                    const DevCounters *ctr)
+{
+    const int64_t n = ctr->n_slots;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        Xc[i] = X[i];
+        Uc[i] = U[i];
+    }
+}
+
+__global__ void k_record_slots(const DevCounters *ctr, int64_t *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = ctr->n_slots;
+}
+
+__global__ __launch_bounds__(256) void k_fill_f64(double *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0;
+}
+
+// 1. adjoint of B^{s+1/2}: its own adjoint and its uses in E_r^{s+1} (nodes i,
+//    i+1; node N through the mirror term) and in E_z^{s+1}.
+__global__ __launch_bounds__(256) void k_adj_fields1(Consts c, const double *lez, const double *ler,
+                                                     const double *lb, double *lbp, double *lk)
+{
+    const int64_t N = c.N;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    double a = lb[i] + c.dtR * lez[i];
+    if (i >= 1 && i <= N - 1) a -= c.dtdz * ler[i];
+    if (i + 1 <= N - 1) a += c.dtdz * ler[i + 1];
+    if (i == N - 1) a += c.tw * ler[N];
+    lbp[i] = a;
+    lk[i] = 0.0;
+}
+
+struct AdjPartArgs {
+    const double *X, *U;      // slots before the step
+    const double *ez;         // E_z^s (the kick array is (q/m) dt E_z^s)
+    const int64_t *n_s;       // slots before the step
+    const int64_t *n_next;    // slots after the step (injected ones beyond n_s)
+    int64_t n_pre;            // slots loaded before the run (injected class from here on)
+    int64_t n_exit;           // exits of the whole run (loss normalisation)
+    double *lx, *lu;          // slot adjoints, in place
+    const double *lez;        // dL/dE_z^{s+1}
+    double *lk;               // dL/dK^s (accumulated)
+    double *grate;            // dL/d(injection charge factor) (accumulated)
+};
+
+// 2. particles: the forward push recomputed exactly, then its transpose.
+__global__ __launch_bounds__(256) void k_adj_particles(Consts c, AdjPartArgs a)
+{
+    const int64_t ns = *a.n_s, nn = *a.n_next;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int N = (int)c.N;
+    bool live = false;
+    int ka = 0, kb = 0;
+    double va = 0.0, vb = 0.0, gr = 0.0;
+    bool wa = false, wb = false;
+    if (p < ns) {
+        const double x = a.X[p], u = a.U[p];
+        if (x >= 0.0) {
+            live = true;
+            const double s = x - 0.5;
+            int clamp = 0, jj = 0;
+            double g = 0.0, dEdx = 0.0;
+            const double kN1 = c.qmdt * a.ez[N - 1], k0 = c.qmdt * a.ez[0];
+            double kj = 0.0, kj1 = 0.0;
+            if (s < 0.0) {
+                clamp = 1;
+            } else if (s >= (double)(N - 1)) {
+                clamp = 2;
+            } else {
+                jj = (int)floor(s);
+                g = s - (double)jj;
+                kj = c.qmdt * a.ez[jj];
+                kj1 = c.qmdt * a.ez[jj + 1];
+                dEdx = kj1 - kj;
+            }
+            const double E = clamp == 1 ? k0 : (clamp == 2 ? kN1 : kj + g * (kj1 - kj));
+            const double u1 = u + E;
+            double t = u1 * u1;
+            t = 1.0 + t;
+            const double gam = sqrt(t);
+            const double v = u1 / gam;
+            const double x1 = x + c.dtdz * v;
+            const double c0d = floor(x), c1d = floor(x1);
+            const int c0 = (int)c0d, c1 = (int)c1d;
+            double lx1 = 0.0, lu1 = 0.0;
+            if (x1 >= (double)N) {
+                lu1 = a.n_exit > 0 ? (u1 / gam) / (double)a.n_exit : 0.0;   // d gamma/du = u/gamma
+            } else if (x1 >= 0.0) {
+                lx1 = a.lx[p];
+                lu1 = a.lu[p];
+            }
+            // current: J_i = S_i(x) - S_i(x1), dS_i/dx = -2^P in cell i; E_z^{s+1} -= c4 J
+            if (c1 >= 0 && c1 < N) lx1 += c.twoP * (-c.c4 * a.lez[c1]);
+            const double lx0J = -c.twoP * (-c.c4 * a.lez[c0]);
+            if (p >= a.n_pre) {
+                // injected class: its deposit times -c4 times the adjoint of E_z^{s+1}
+                const double F0 = rint((x - c0d) * c.twoP), F1 = rint((x1 - c1d) * c.twoP);
+                double d0, d1 = 0.0;
+                if (c1 == c0) {
+                    d0 = F1 - F0;
+                } else if (c1 > c0) {
+                    d0 = c.twoP - F0;
+                    d1 = c1 < N ? F1 : 0.0;
+                } else {
+                    d0 = -F0;
+                    d1 = c1 >= 0 ? F1 - c.twoP : 0.0;
+                }
+                gr += d0 * (-c.c4) * a.lez[c0];
+                if (d1 != 0.0) gr += d1 * (-c.c4) * a.lez[c1];
+            }
+            // move: x1 = x + (dt/dz) u1/gamma(u1), dv/du = 1/gamma^3
+            const double lu1t = lu1 + lx1 * c.dtdz / (gam * gam * gam);
+            a.lx[p] = lx1 + lx0J + lu1t * dEdx;
+            a.lu[p] = lu1t;
+            // kick: E = K_j (1 - g) + K_{j+1} g
+            if (clamp == 1) { ka = 0; va = lu1t; wa = true; }
+            else if (clamp == 2) { ka = N - 1; va = lu1t; wa = true; }
+            else { ka = jj; va = lu1t * (1.0 - g); kb = jj + 1; vb = lu1t * g; wa = true; wb = true; }
+        }
+    } else if (p < nn) {
+        // injected at the end of step s: created at rest, no dependence
+        a.lx[p] = 0.0;
+        a.lu[p] = 0.0;
+    }
+    (void)live;
+    wave_add_keyed_f64(a.lk, ka, va, wa);
+    wave_add_keyed_f64(a.lk, kb, vb, wb);
+    const double gs = wave_sum_f64(gr);
+    if (__lane_id() == 0 && gs != 0.0) atomicAdd(a.grate, gs);
+}
+
+// 3. transposed leap-frog: adjoints of E_z^s, E_r^s, B^{s-1/2}.
+__global__ __launch_bounds__(256) void k_adj_fields2(Consts c, double *lez, double *ler, double *lb,
+                                                     const double *lbp, const double *lk)
+{
+    const int64_t N = c.N;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < N) {
+        lez[i] = lez[i] - c.dtR * lbp[i] + c.qmdt * lk[i];
+        lb[i] = lbp[i];
+    }
+    if (i <= N) {   // each thread updates only its own node
+        double a = ler[i];
+        if (i <= N - 1) a += c.dtdz * lbp[i];
+        if (i >= 1) a -= c.dtdz * lbp[i - 1];
+        ler[i] = a;
+    }
+}
+
+// dL/dphi_m from E_z = -dphi/dz (faces) and E_r = phi/R (nodes), m = 1..N.
+__global__ __launch_bounds__(256) void k_adj_phi(Consts c, const double *lez, const double *ler, double *g)
+{
+    const int64_t N = c.N;
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x + 1;
+    if (m > N) return;
+    double a = -lez[m - 1] / c.dz + ler[m] / c.R;
+    if (m <= N - 1) a += lez[m] / c.dz;
+    g[m] = a;
+}
+
+// Transposed Thomas solve A^T y = g (A: eq. (4) rows 1..N-1 = 1, bdiag, 1 and
+// row N = 2, bdiag; A^T carries the 2 on the super-diagonal of row N-1), then
+// dL/d rho_GJ,i = 4 pi dz^2 y_i (the right-hand side is -4 pi dz^2 (rho - rho_GJ)).
+constexpr int ADJ_CHUNK = 2048;
+__global__ __launch_bounds__(256) void k_adj_poisson(Consts c, const double *g, double *cp, double *dp,
+                                                     double *g_rho)
+{
+    __shared__ double sa[ADJ_CHUNK];
+    __shared__ double sb[ADJ_CHUNK];
+    __shared__ double carry[2];
+    const int64_t N = c.N;
+    if (threadIdx.x == 0) { carry[0] = 0.0; carry[1] = 0.0; }
+    for (int64_t base = 1; base <= N; base += ADJ_CHUNK) {
+        const int cnt = (int)((N - base + 1) < ADJ_CHUNK ? (N - base + 1) : ADJ_CHUNK);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 256) sa[t] = g[base + t];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double pc = carry[0], pd = carry[1];
+            for (int t = 0; t < cnt; ++t) {
+                const int64_t i = base + t;
+                const double sup = (i <= N - 1) ? ((i == N - 1) ? 2.0 : 1.0) : 0.0;
+                double ci, di;
+                if (i == 1) {
+                    ci = sup / c.bdiag;
+                    di = sa[t] / c.bdiag;
+                } else {
+                    const double m = c.bdiag - pc;
+                    ci = sup / m;
+                    di = (sa[t] - pd) / m;
+                }
+                sa[t] = di;
+                sb[t] = ci;
+                pc = ci;
+                pd = di;
+            }
+            carry[0] = pc;
+            carry[1] = pd;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 256) { dp[base + t] = sa[t]; cp[base + t] = sb[t]; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) carry[0] = 0.0;
+    for (int64_t top = N; top >= 1; top -= ADJ_CHUNK) {
+        const int64_t lo = top - ADJ_CHUNK + 1 > 1 ? top - ADJ_CHUNK + 1 : 1;
+        const int cnt = (int)(top - lo + 1);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += 256) { sa[t] = dp[lo + t]; sb[t] = cp[lo + t]; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double next = carry[0];
+            for (int t = cnt - 1; t >= 0; --t) {
+                const int64_t i = lo + t;
+                const double v = (i == N) ? sa[t] : sa[t] - sb[t] * next;
+                sa[t] = v;
+                next = v;
+            }
+            carry[0] = next;
+        }
+        __syncthreads();
+        const double fac = c.fourpi * (c.dz * c.dz);
+        for (int t = threadIdx.x; t < cnt; t += 256) g_rho[lo + t] = fac * sa[t];
+    }
+    if (threadIdx.x == 0) g_rho[0] = 0.0;
+}
+
+// dL/d(parameters of rho_GJ) from the node gradient: knots (hat weights times
+// -(1 - kappa/eta^3)), kappa (theta(z)/eta^3 per node), amplitude A.
+// One block; out[0] = kappa, out[1] = A, out[2 + k] = knot k.
+__global__ __launch_bounds__(256) void k_adj_params(Consts c, const double *knots, const double *g_rho, double *out)
+{
+    __shared__ double s_red[2][4];
+    const int64_t N = c.N;
+    const int K = c.n_knots;
+    for (int k = threadIdx.x; k < K + 2; k += 256) out[k] = 0.0;
+    __syncthreads();
+    double gk = 0.0, ga = 0.0;
+    for (int64_t i = threadIdx.x; i <= N; i += 256) {
+        const double gr = g_rho[i];
+        const double z = (double)i * c.dz;
+        if (c.rho_kind == PIC_RHO_UNIFORM) {
+            ga += -gr;
+            continue;
+        }
+        const double eta = 1.0 + z / c.r_star;
+        const double e3 = eta * eta * eta;
+        const double fd = 1.0 - c.kappa / e3;
+        if (c.rho_kind == PIC_RHO_FRAME_DRAG) {
+            ga += gr * (-fd);
+            gk += gr * (c.rho_amp / e3);
+        } else {
+            const double s = (z * (double)(K - 1)) / c.length;
+            int kk = (int)floor(s);
+            if (kk > K - 2) kk = K - 2;
+            if (kk < 0) kk = 0;
+            const double g = s - (double)kk;
+            const double th = knots[kk] + g * (knots[kk + 1] - knots[kk]);
+            gk += gr * (th / e3);
+            atomicAdd(&out[2 + kk], gr * (-(1.0 - g) * fd));
+            atomicAdd(&out[2 + kk + 1], gr * (-g * fd));
+        }
+    }
+    gk = wave_sum_f64(gk);
+    ga = wave_sum_f64(ga);
+    if (__lane_id() == 0) {
+        s_red[0][threadIdx.x >> 6] = gk;
+        s_red[1][threadIdx.x >> 6] = ga;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
+        out[1] = s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
+    }
+}
+
+// ---- launchers ----
+
+static inline unsigned gridn(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_copy_slots(pic_handle *h, const double *X, const double *U, double *Xc, double *Uc)
+{
+    hipLaunchKernelGGL(k_copy_slots, dim3(h->n_cu * 8), dim3(256), 0, h->stream, X, U, Xc, Uc, h->ws.ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_record_slots(pic_handle *h, int64_t *dst)
+{
+    hipLaunchKernelGGL(k_record_slots, dim3(1), dim3(64), 0, h->stream, h->ws.ctr, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(pic_handle *h, double *p, int64_t n)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(gridn(n) < 4096 ? gridn(n) : 4096), dim3(256), 0, h->stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_step(pic_handle *h, const AdjStepPtrs &s)
+{
+    const Consts &c = h->c;
+    hipLaunchKernelGGL(k_adj_fields1, dim3(gridn(c.N)), dim3(256), 0, h->stream, c, s.lez, s.ler, s.lb, s.lbp, s.lk);
+    AdjPartArgs a{s.X, s.U, s.ez, s.n_s, s.n_next, s.n_pre, s.n_exit, s.lx, s.lu, s.lez, s.lk, s.grate};
+    hipLaunchKernelGGL(k_adj_particles, dim3(gridn(c.cap)), dim3(256), 0, h->stream, c, a);
+    hipLaunchKernelGGL(k_adj_fields2, dim3(gridn(c.N + 1)), dim3(256), 0, h->stream, c, s.lez, s.ler, s.lb, s.lbp,
+                       s.lk);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_finish(pic_handle *h, const double *lez, const double *ler, double *gphi, double *cp,
+                             double *dp, double *g_rho, double *params)
+{
+    const Consts &c = h->c;
+    hipLaunchKernelGGL(k_adj_phi, dim3(gridn(c.N)), dim3(256), 0, h->stream, c, lez, ler, gphi);
+    hipLaunchKernelGGL(k_adj_poisson, dim3(1), dim3(256), 0, h->stream, c, gphi, cp, dp, g_rho);
+    hipLaunchKernelGGL(k_adj_params, dim3(1), dim3(256), 0, h->stream, c, h->ws.knots, g_rho, params);
+    return hipGetLastError();
+}
+
+}  // namespace pcpic

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_steps(BatchArgs b)
                 const int64_t tile0 = local * TILE;
                 const int64_t n = load_slots(&T.ctr->n_slots);
                 if (tile0 < n) {
-                    PushArgs a{T.x[pb], T.u[pb], T.k64, (unsigned long long *)T.j[jb], T.ctr};
+                    PushArgs a{T.x[pb], T.u[pb], T.x[pb], T.u[pb], T.k64, (unsigned long long *)T.j[jb], T.ctr};
                     push_tile_f64<BLOCK, PPT, NT>(T.c, a, n, tile0);
                 }
             }

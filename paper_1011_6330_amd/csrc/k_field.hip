@@ -245,6 +245,18 @@ hipError_t launch_field_inject(pic_handle *h)
     return hipGetLastError();
 }
 
+// Field update + injection with explicit field buffers and injection target
+// (used by the adjoint recompute; FP64 only).
+hipError_t launch_field_ptrs(pic_handle *h, const double *ezo, const double *ero, const double *bo, double *ezn,
+                             double *ern, double *bn, double *X, double *U)
+{
+    Workspace &w = h->ws;
+    FieldArgs a{ezo, ero, bo, ezn, ern, bn, w.j[h->jbuf], w.j[1 - h->jbuf], w.k64, nullptr, X, U,
+                nullptr, nullptr, nullptr, w.ctr};
+    hipLaunchKernelGGL(k_field_inject, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_check_append(pic_handle *h, int64_t base, int64_t n)
 {
     if (n > 0)
@@ -256,6 +268,20 @@ hipError_t launch_check_append(pic_handle *h, int64_t base, int64_t n)
 hipError_t launch_commit_append(pic_handle *h, int64_t n)
 {
     hipLaunchKernelGGL(k_commit_append, dim3(1), dim3(64), 0, h->stream, h->ws.ctr, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_from(pic_handle *h, const double *ez)
+{
+    hipLaunchKernelGGL(k_kick, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c, ez, h->ws.k64,
+                       h->p.precision == PIC_FP32_BULK ? h->ws.k32 : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i64(pic_handle *h, int64_t *p, int64_t n)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, h->stream, p, n, (int64_t)0);
     return hipGetLastError();
 }
 

@@ -30,12 +30,28 @@ __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
 template <int BLOCK, int PPT, int NT>
 static hipError_t launch_push_t(pic_handle *h)
 {
-    PushArgs a{h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.k64,
+    PushArgs a{h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.k64,
                (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr};
     const int64_t tile = (int64_t)BLOCK * PPT;
     const unsigned grid = (unsigned)((h->c.cap + tile - 1) / tile);
     hipLaunchKernelGGL((k_push_f64<BLOCK, PPT, NT>), dim3(grid), dim3(BLOCK), 0, h->stream, h->c, a);
     return hipGetLastError();
+}
+
+template <int BLOCK, int PPT, int NT>
+static hipError_t launch_push_args_t(pic_handle *h, const PushArgs &a)
+{
+    const int64_t tile = (int64_t)BLOCK * PPT;
+    const unsigned grid = (unsigned)((h->c.cap + tile - 1) / tile);
+    hipLaunchKernelGGL((k_push_f64<BLOCK, PPT, NT>), dim3(grid), dim3(BLOCK), 0, h->stream, h->c, a);
+    return hipGetLastError();
+}
+
+// FP64 push reading (X, U) and writing (Xo, Uo) (used by the adjoint recompute).
+hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U, double *Xo, double *Uo)
+{
+    PushArgs a{X, U, Xo, Uo, h->ws.k64, (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr};
+    return launch_push_args_t<64, 2, 1>(h, a);
 }
 
 hipError_t launch_push_f64(pic_handle *h)

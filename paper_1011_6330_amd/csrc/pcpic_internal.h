@@ -126,6 +126,14 @@ struct TubeDev {
     int64_t n_keys;       // sort keys (N, or 2(N+1) in FP32-bulk mode)
 };
 
+// Pointers of one reverse step of the adjoint (see k_adjoint.hip).
+struct AdjStepPtrs {
+    const double *X, *U, *ez;        // recorded slots and E_z before the step
+    const int64_t *n_s, *n_next;     // slot counts before / after the step (device)
+    int64_t n_pre, n_exit;
+    double *lx, *lu, *lez, *ler, *lb, *lbp, *lk, *grate;
+};
+
 // Grid-barrier state of the batched persistent kernel.
 struct BatchState {
     unsigned bar_count;
@@ -178,6 +186,9 @@ hipError_t launch_weights(pic_handle *h, int64_t *w_out);
 hipError_t launch_poisson(pic_handle *h);
 hipError_t launch_push_f64(pic_handle *h);
 hipError_t launch_push_f32(pic_handle *h);
+hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U, double *Xo, double *Uo);
+hipError_t launch_field_ptrs(pic_handle *h, const double *ezo, const double *ero, const double *bo, double *ezn,
+                             double *ern, double *bn, double *X, double *U);
 hipError_t launch_weights32(pic_handle *h, int64_t *w_out);
 hipError_t launch_profile32(pic_handle *h, int nbins);
 hipError_t launch_sort32_hist(pic_handle *h);
@@ -185,6 +196,14 @@ hipError_t launch_sort32_scatter(pic_handle *h);
 hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only);
 hipError_t launch_scan(pic_handle *h, int64_t n_keys);
 hipError_t launch_batch_steps(pic_handle *h, int nsteps);
+hipError_t launch_copy_slots(pic_handle *h, const double *X, const double *U, double *Xc, double *Uc);
+hipError_t launch_record_slots(pic_handle *h, int64_t *dst);
+hipError_t launch_zero_f64(pic_handle *h, double *p, int64_t n);
+hipError_t launch_adj_step(pic_handle *h, const AdjStepPtrs &s);
+hipError_t launch_adj_finish(pic_handle *h, const double *lez, const double *ler, double *gphi, double *cp,
+                             double *dp, double *g_rho, double *params);
+hipError_t launch_kick_from(pic_handle *h, const double *ez);
+hipError_t launch_zero_i64(pic_handle *h, int64_t *p, int64_t n);
 hipError_t launch_batch_sort(pic_handle *h);
 int batch_occupancy(pic_handle *h);
 TubeDev tube_dev(pic_handle *t);

@@ -44,6 +44,7 @@ pic_status validate(const pic_params *p)
         return fail(PIC_EABI, "abi_version %d, library is %d", p->abi_version, PCPIC_ABI_VERSION);
     if (p->precision != PIC_FP64 && p->precision != PIC_FP32_BULK)
         return fail(PIC_EINVAL, "precision %d not supported", p->precision);
+    if (!isfinite(p->macro_charge)) return fail(PIC_EINVAL, "macro_charge must be finite");
     if (!(p->gamma_fp64 == 0.0 || (p->gamma_fp64 >= 1.0 && p->gamma_fp64 < 1e300)))
         return fail(PIC_EINVAL, "gamma_fp64 must be 0 (default 1e6) or >= 1");
     if (p->n_cells < 2 || p->n_cells > ((int64_t)1 << 31))
@@ -93,7 +94,7 @@ Consts make_consts(const pic_params &p, const double *knots)
     c.r_star = p.r_star;
     c.length = p.length;
     c.rho0 = rho_node(c, knots, 0);
-    c.qm = (c.rho0 * c.dz) / p.ppc;
+    c.qm = p.macro_charge != 0.0 ? p.macro_charge : (c.rho0 * c.dz) / p.ppc;
     c.qmP = c.qm / c.twoP;
     c.fourpi = 4.0 * M_PI;
     c.c4 = c.fourpi * c.qmP;
@@ -882,6 +883,221 @@ static pic_status batch_status(pic_handle *h)
         if (c.status) return fail(PIC_EDEVSTATUS, "a tube latched device status bits 0x%llx", (unsigned long long)c.status);
     }
     return PIC_OK;
+}
+
+// ------------------------------------------------------------------------
+// hand-written adjoint with checkpointing
+// ------------------------------------------------------------------------
+
+namespace {
+
+struct Tape {
+    int64_t T, K, nck, N, cap;
+    std::vector<double *> ck_x, ck_u, ck_ez, ck_er, ck_b;   // checkpoint c: state at step c*K
+    std::vector<DevCounters *> ck_ctr;
+    std::vector<double *> sg_x, sg_u, sg_ez, sg_er, sg_b;   // segment slots 1..K
+    int64_t *nslots;                                        // [T + 1]
+    double *lx, *lu, *lez, *ler, *lb, *lbp, *lk, *grate, *gphi, *cp, *dp, *g_rho, *params;
+    DevCounters *final_ctr;
+    int64_t *final_jlast;
+    size_t bytes;
+};
+
+Tape carve_tape(pic_handle *h, int64_t T, int64_t K, uint8_t *base)
+{
+    Tape t{};
+    t.T = T;
+    t.K = K;
+    t.nck = (T + K - 1) / K;
+    t.N = h->c.N;
+    t.cap = h->c.cap;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        const size_t o = align_up(off);
+        off = o + bytes;
+        return base ? (void *)(base + o) : nullptr;
+    };
+    const size_t N = (size_t)t.N, cap = (size_t)t.cap;
+    for (int64_t c = 0; c < t.nck; ++c) {
+        t.ck_x.push_back((double *)take(cap * 8));
+        t.ck_u.push_back((double *)take(cap * 8));
+        t.ck_ez.push_back((double *)take(N * 8));
+        t.ck_er.push_back((double *)take((N + 1) * 8));
+        t.ck_b.push_back((double *)take(N * 8));
+        t.ck_ctr.push_back((DevCounters *)take(sizeof(DevCounters)));
+    }
+    t.sg_x.push_back(nullptr);   // slot 0 of a segment is its checkpoint
+    t.sg_u.push_back(nullptr);
+    t.sg_ez.push_back(nullptr);
+    t.sg_er.push_back(nullptr);
+    t.sg_b.push_back(nullptr);
+    for (int64_t k = 1; k <= K; ++k) {
+        t.sg_x.push_back((double *)take(cap * 8));
+        t.sg_u.push_back((double *)take(cap * 8));
+        t.sg_ez.push_back((double *)take(N * 8));
+        t.sg_er.push_back((double *)take((N + 1) * 8));
+        t.sg_b.push_back((double *)take(N * 8));
+    }
+    t.nslots = (int64_t *)take((size_t)(T + 1) * 8);
+    t.lx = (double *)take(cap * 8);
+    t.lu = (double *)take(cap * 8);
+    t.lez = (double *)take(N * 8);
+    t.ler = (double *)take((N + 1) * 8);
+    t.lb = (double *)take(N * 8);
+    t.lbp = (double *)take(N * 8);
+    t.lk = (double *)take(N * 8);
+    t.grate = (double *)take(8);
+    t.gphi = (double *)take((N + 1) * 8);
+    t.cp = (double *)take((N + 1) * 8);
+    t.dp = (double *)take((N + 1) * 8);
+    t.g_rho = (double *)take((N + 1) * 8);
+    t.params = (double *)take((size_t)(h->c.n_knots + 2) * 8);
+    t.final_ctr = (DevCounters *)take(sizeof(DevCounters));
+    t.final_jlast = (int64_t *)take(N * 8);
+    t.bytes = align_up(off);
+    return t;
+}
+
+pic_status adjoint_supported(pic_handle *h)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (h->is_batch || h->parent) return fail(PIC_EINVAL, "the adjoint runs on a single tube");
+    if (h->p.precision != PIC_FP64) return fail(PIC_EINVAL, "the adjoint needs PIC_FP64");
+    if (h->p.sort_every != 0) return fail(PIC_EINVAL, "the adjoint needs sort_every = 0");
+    if (h->p.flags & PIC_FREEZE_FIELDS) return fail(PIC_EINVAL, "the adjoint needs evolving fields");
+    return PIC_OK;
+}
+
+}  // namespace
+
+size_t pic_adjoint_tape_bytes(pic_handle *h, int64_t n_steps, int32_t checkpoint_every)
+{
+    if (adjoint_supported(h) != PIC_OK) return 0;
+    if (n_steps < 1 || checkpoint_every < 1) {
+        fail(PIC_EINVAL, "n_steps and checkpoint_every must be >= 1");
+        return 0;
+    }
+    return carve_tape(h, n_steps, checkpoint_every, nullptr).bytes;
+}
+
+pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_every, void *d_tape,
+                           size_t tape_bytes, pic_adjoint_out *out)
+{
+    pic_status s = adjoint_supported(h);
+    if (s != PIC_OK) return s;
+    if (!out || n_steps < 1 || checkpoint_every < 1) return fail(PIC_EINVAL, "bad pic_run_adjoint arguments");
+    const int64_t T = n_steps, K = checkpoint_every;
+    const size_t need = carve_tape(h, T, K, nullptr).bytes;
+    if (!d_tape || tape_bytes < need) return fail(PIC_EWORKSPACE, "tape of %zu bytes, %zu needed", tape_bytes, need);
+    if (((uintptr_t)d_tape) % ALIGN) return fail(PIC_EWORKSPACE, "tape must be %zu-byte aligned", ALIGN);
+    Tape t = carve_tape(h, T, K, (uint8_t *)d_tape);
+    Workspace &w = h->ws;
+    const int64_t N = h->c.N;
+    hipEvent_t ev[4];
+    for (auto &e : ev) HIP_OK(hipEventCreate(&e));
+    auto done = [&](pic_status r) {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        return r;
+    };
+    DevCounters c0;
+    s = read_counters(h, &c0);
+    if (s != PIC_OK) return done(s);
+    const int64_t n_pre = c0.n_slots;
+
+    // ---- forward with checkpoints (the same steps as pic_step) ----
+    HIP_OK(hipEventRecord(ev[0], h->stream));
+    for (int64_t st = 0; st < T; ++st) {
+        if (st % K == 0) {
+            const int64_t ck = st / K;
+            const int f = h->fbuf;
+            HIP_OK(launch_copy_slots(h, w.x[h->pbuf], w.u[h->pbuf], t.ck_x[ck], t.ck_u[ck]));
+            HIP_OK(hipMemcpyAsync(t.ck_ez[ck], w.ez[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+            HIP_OK(hipMemcpyAsync(t.ck_er[ck], w.er[f], (size_t)(N + 1) * 8, hipMemcpyDeviceToDevice, h->stream));
+            HIP_OK(hipMemcpyAsync(t.ck_b[ck], w.b[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+            HIP_OK(hipMemcpyAsync(t.ck_ctr[ck], w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+        }
+        HIP_OK(launch_record_slots(h, t.nslots + st));
+        HIP_OK(launch_push_f64(h));
+        HIP_OK(launch_field_inject(h));
+        h->fbuf ^= 1;
+        h->jbuf ^= 1;
+        h->step += 1;
+    }
+    HIP_OK(launch_record_slots(h, t.nslots + T));
+    HIP_OK(hipEventRecord(ev[1], h->stream));
+    DevCounters c1;
+    s = read_counters(h, &c1);
+    if (s != PIC_OK) return done(s);
+    const int64_t nex = c1.n_exit - c0.n_exit;
+    const __int128 e0 = ((__int128)c0.exit_hi << 64) | (__int128)c0.exit_lo;
+    const __int128 e1 = ((__int128)c1.exit_hi << 64) | (__int128)c1.exit_lo;
+    out->loss = nex > 0 ? ldexp((double)(e1 - e0), -32) / (double)nex : 0.0;
+    out->n_exit = nex;
+    // keep what the recompute overwrites: counters and the last step's current
+    HIP_OK(hipMemcpyAsync(t.final_ctr, w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(t.final_jlast, w.j[1 - h->jbuf], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+    const int jb_final = h->jbuf;
+
+    // ---- reverse sweep, one segment at a time from its checkpoint ----
+    HIP_OK(hipEventRecord(ev[2], h->stream));
+    HIP_OK(launch_zero_f64(h, t.lx, t.cap));
+    HIP_OK(launch_zero_f64(h, t.lu, t.cap));
+    HIP_OK(launch_zero_f64(h, t.lez, N));
+    HIP_OK(launch_zero_f64(h, t.ler, N + 1));
+    HIP_OK(launch_zero_f64(h, t.lb, N));
+    HIP_OK(launch_zero_f64(h, t.grate, 1));
+    for (int64_t ck = t.nck - 1; ck >= 0; --ck) {
+        const int64_t s0 = ck * K, m = (T - s0) < K ? (T - s0) : K;
+        // recompute steps s0 .. s0+m-1 out of place: slot k holds the state before step s0+k
+        HIP_OK(hipMemcpyAsync(w.ctr, t.ck_ctr[ck], sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+        HIP_OK(launch_zero_i64(h, w.j[0], N));
+        HIP_OK(launch_zero_i64(h, w.j[1], N));
+        HIP_OK(launch_kick_from(h, t.ck_ez[ck]));
+        for (int64_t k = 0; k < m; ++k) {
+            const double *xi = k == 0 ? t.ck_x[ck] : t.sg_x[(size_t)k], *ui = k == 0 ? t.ck_u[ck] : t.sg_u[(size_t)k];
+            const double *ezo = k == 0 ? t.ck_ez[ck] : t.sg_ez[(size_t)k];
+            const double *ero = k == 0 ? t.ck_er[ck] : t.sg_er[(size_t)k];
+            const double *bo = k == 0 ? t.ck_b[ck] : t.sg_b[(size_t)k];
+            if (k == m - 1) break;   // the state after the segment's last step is not needed
+            HIP_OK(launch_push_f64_ptrs(h, xi, ui, t.sg_x[(size_t)k + 1], t.sg_u[(size_t)k + 1]));
+            HIP_OK(launch_field_ptrs(h, ezo, ero, bo, t.sg_ez[(size_t)k + 1], t.sg_er[(size_t)k + 1],
+                                     t.sg_b[(size_t)k + 1], t.sg_x[(size_t)k + 1], t.sg_u[(size_t)k + 1]));
+            h->jbuf ^= 1;
+        }
+        for (int64_t k = m - 1; k >= 0; --k) {
+            const int64_t st = s0 + k;
+            AdjStepPtrs a{k == 0 ? t.ck_x[ck] : t.sg_x[(size_t)k], k == 0 ? t.ck_u[ck] : t.sg_u[(size_t)k],
+                          k == 0 ? t.ck_ez[ck] : t.sg_ez[(size_t)k], t.nslots + st, t.nslots + st + 1, n_pre, nex,
+                          t.lx, t.lu, t.lez, t.ler, t.lb, t.lbp, t.lk, t.grate};
+            HIP_OK(launch_adj_step(h, a));
+        }
+    }
+    HIP_OK(launch_adj_finish(h, t.lez, t.ler, t.gphi, t.cp, t.dp, t.g_rho, t.params));
+    HIP_OK(hipEventRecord(ev[3], h->stream));
+    // restore the end state the forward left
+    HIP_OK(hipMemcpyAsync(w.ctr, t.final_ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+    h->jbuf = jb_final;
+    HIP_OK(launch_zero_i64(h, w.j[h->jbuf], N));
+    HIP_OK(hipMemcpyAsync(w.j[1 - h->jbuf], t.final_jlast, (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+    HIP_OK(launch_kick(h));
+    // results
+    std::vector<double> params((size_t)h->c.n_knots + 2);
+    double grate = 0.0;
+    HIP_OK(hipMemcpyAsync(params.data(), t.params, params.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipMemcpyAsync(&grate, t.grate, 8, hipMemcpyDeviceToHost, h->stream));
+    if (out->g_rho) HIP_OK(hipMemcpyAsync(out->g_rho, t.g_rho, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    out->g_rate = grate;
+    out->g_kappa = params[0];
+    out->g_amp = params[1];
+    if (out->g_knots)
+        for (int k = 0; k < h->c.n_knots; ++k) out->g_knots[k] = params[(size_t)k + 2];
+    float fms = 0, bms = 0;
+    (void)hipEventElapsedTime(&fms, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&bms, ev[2], ev[3]);
+    out->forward_ms = fms;
+    out->backward_ms = bms;
+    return done(PIC_OK);
 }
 
 }  // extern "C"

@@ -11,8 +11,10 @@
 namespace pcpic {
 
 struct PushArgs {
-    double *__restrict__ X;
-    double *__restrict__ U;
+    const double *__restrict__ X;   // slots read
+    const double *__restrict__ U;
+    double *__restrict__ Xo;        // slots written (== X, U for an in-place step)
+    double *__restrict__ Uo;
     const double *__restrict__ K;
     unsigned long long *__restrict__ J;
     DevCounters *ctr;
@@ -95,15 +97,15 @@ __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a
     if (full) {
 #pragma unroll
         for (int k = 0; k < PPT; k += 2) {
-            st16<NT, dvec2>(a.X + p0 + k, dvec2{xs[k], xs[k + 1]});
-            st16<NT, dvec2>(a.U + p0 + k, dvec2{us[k], us[k + 1]});
+            st16<NT, dvec2>(a.Xo + p0 + k, dvec2{xs[k], xs[k + 1]});
+            st16<NT, dvec2>(a.Uo + p0 + k, dvec2{us[k], us[k + 1]});
         }
     } else {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             if (p0 + k < n) {
-                a.X[p0 + k] = xs[k];
-                a.U[p0 + k] = us[k];
+                a.Xo[p0 + k] = xs[k];
+                a.Uo[p0 + k] = us[k];
             }
         }
     }

@@ -15,6 +15,7 @@ def make_pair(cfg, x=None, u=None):
     p = synth.tube_params(cfg)
     g = Tube(p)
     o = OracleTube({k: v for k, v in p.items() if k not in ("sort_every", "max_bins", "precision", "gamma_fp64")})
+    # (macro_charge passes through: the oracle takes the same override)
     if x is not None and len(x):
         g.inject(x, u)
         o.inject(x, u)

@@ -1,0 +1,93 @@
+"""The hand-written GPU adjoint against the oracle's reverse-mode gradient
+(itself pinned by finite differences in test_oracle_adjoint.py)."""
+import numpy as np
+import pytest
+
+from gpu_common import assert_state_equal, make_pair, say
+from paper_1011_6330_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _warm_cfg(K=9, N=128, n=2000):
+    cfg = dict(n_cells=N, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=synth.q_over_m_for(0.9 * N / 10.0),
+               ppc=n / N, rho_kind=2, rho_amp=1.0, kappa=0.15, r_star=10.0, knots=np.ones(K),
+               capacity=int(n * 2) + 4096, warm=n, sort_every=0)
+    cfg["macro_charge"] = -(1.0 - cfg["kappa"]) * (cfg["length"] / N) / cfg["ppc"]
+    x, u = synth.warm_start(cfg, seed=0)
+    return cfg, x, u
+
+
+def _cold_cfg():
+    N, L = 256, 3.0
+    cfg = dict(n_cells=N, length=L, radius=1.0, dt_over_dz=0.5, q_over_m=-1.0, ppc=4.0, rho_kind=2, rho_amp=1.0,
+               kappa=0.15, r_star=10.0, knots=np.ones(7), capacity=40000, warm=0, sort_every=0)
+    cfg["macro_charge"] = -(1.0 - cfg["kappa"]) * (L / N) / cfg["ppc"]
+    return cfg, np.zeros(0), np.zeros(0)
+
+
+def _compare(cfg, x, u, T, ckpt):
+    g, o = make_pair(cfg, x, u)
+    r = g.run_adjoint(T, ckpt)
+    L, nex, g_rho, g_rate = o.adjoint(T)
+    assert r["loss"] == L and r["n_exit"] == nex
+    scale = np.abs(g_rho).max()
+    assert scale > 0
+    err = np.abs(r["g_rho"] - g_rho).max() / scale
+    assert err <= 1e-8, err
+    assert abs(r["g_rate"] - g_rate) <= 1e-8 * max(abs(g_rate), 1e-300) or g_rate == r["g_rate"] == 0.0
+    # the tube is left where T plain steps leave it (bit-identical to the oracle)
+    assert_state_equal(g, o, what="after adjoint")
+    return r, g_rho, g_rate
+
+
+@pytest.mark.parametrize("ckpt", [1, 7, 50, 160])
+def test_adjoint_warm_matches_oracle(ckpt):
+    cfg, x, u = _warm_cfg()
+    say("adjoint warm ckpt", ckpt)
+    r, g_rho, _ = _compare(cfg, x, u, 160, ckpt)
+    # knot and kappa gradients from the node gradient (hat weights, eq. 7 factor)
+    N, K = cfg["n_cells"], len(cfg["knots"])
+    z = np.arange(N + 1) * (cfg["length"] / N)
+    W = np.stack([np.interp(z, np.linspace(0, cfg["length"], K), np.eye(K)[k]) for k in range(K)], axis=1)
+    eta = 1 + z / cfg["r_star"]
+    g_theta = -(W * (1 - cfg["kappa"] / eta ** 3)[:, None]).T @ g_rho
+    g_kappa = float(g_rho @ ((W @ cfg["knots"]) / eta ** 3))
+    np.testing.assert_allclose(r["g_knots"], g_theta, rtol=1e-8, atol=1e-10 * np.abs(g_theta).max())
+    assert abs(r["g_kappa"] - g_kappa) <= 1e-8 * abs(g_kappa)
+
+
+def test_adjoint_cold_rate_matches_oracle():
+    cfg, x, u = _cold_cfg()
+    say("adjoint cold")
+    r, _, g_rate = _compare(cfg, x, u, 700, 50)
+    assert abs(g_rate) > 0.1
+
+
+def test_adjoint_autograd_function():
+    import torch
+
+    from paper_1011_6330_amd.adjoint import exit_gamma_loss
+    cfg, x, u = _warm_cfg()
+    knots = torch.ones(9, dtype=torch.float64, requires_grad=True)
+    kappa = torch.tensor(0.15, dtype=torch.float64, requires_grad=True)
+    rate = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    loss = exit_gamma_loss(knots, kappa, rate, synth.tube_params(cfg), x, u, 160, 40)
+    loss.backward()
+    g, o = make_pair(cfg, x, u)
+    L, nex, g_rho, g_rate = o.adjoint(160)
+    assert float(loss) == L
+    N, K = cfg["n_cells"], 9
+    z = np.arange(N + 1) * (cfg["length"] / N)
+    W = np.stack([np.interp(z, np.linspace(0, cfg["length"], K), np.eye(K)[k]) for k in range(K)], axis=1)
+    eta = 1 + z / cfg["r_star"]
+    g_theta = -(W * (1 - 0.15 / eta ** 3)[:, None]).T @ g_rho
+    np.testing.assert_allclose(knots.grad.numpy(), g_theta, rtol=1e-8, atol=1e-10 * np.abs(g_theta).max())
+
+
+def test_adjoint_rejects_sorting_tubes():
+    from paper_1011_6330_amd import PicError, Tube
+    cfg, x, u = _warm_cfg()
+    t = Tube(dict(synth.tube_params(cfg), sort_every=16))
+    with pytest.raises(PicError):
+        t.run_adjoint(10, 5)
