@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=512)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -158,7 +160,10 @@ def main():
     if not args.no_ensemble:
         result["ensemble"] = run_ensemble(args.ensemble_steps)
 
-    result["adjoint_forward_ratio"] = None   # the hand-written adjoint is not built yet
+    if not args.no_adjoint:
+        adj = run_adjoint_leg(args.adjoint_steps)
+        result["adjoint"] = adj
+        result["adjoint_forward_ratio"] = adj["backward_over_plain_forward"]
 
     copy_gbs = copy_bandwidth(torch)
     result["roofline"]["achievable_copy_gbs"] = copy_gbs
@@ -203,6 +208,40 @@ def run_ensemble(steps):
             "workload": "256 frame-dragging tubes, cells log-uniform 2048-65536, particles log-uniform 1e4-1e6, "
                         "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk, one persistent graph-replayed "
                         "launch per 16-step round"}
+
+
+def run_adjoint_leg(steps, ckpt=50):
+    """C4: the hand-written adjoint of `steps` steps (checkpoints every `ckpt`)
+    against a plain forward of the same steps on the same tube."""
+    import torch
+
+    from paper_1011_6330_amd import Tube, synth
+    cfg = synth.preset("c4")
+    x, u = synth.warm_start(cfg)
+    p = synth.tube_params(cfg)
+    t = Tube(p, device="cuda:0")
+    t.inject(x, u)
+    plain = t.step_timed(steps)
+    t.close()
+    t = Tube(p, device="cuda:0")
+    t.inject(x, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = t.run_adjoint(steps, ckpt)
+    el = time.perf_counter() - t0
+    t.close()
+    del t
+    torch.cuda.empty_cache()
+    fwd = plain["total_ms"]
+    log(f"adjoint: plain forward {fwd:.1f} ms, checkpointed forward {r['forward_ms']:.1f} ms, "
+        f"backward {r['backward_ms']:.1f} ms, loss {r['loss']:.6g} over {r['n_exit']} exits")
+    return {"workload": "c4: 64-knot frame-dragging tube, 4096 cells, ~1e6 warm particles, loss = mean exit gamma, "
+                        f"{steps} steps, checkpoint every {ckpt}, FP64",
+            "steps": steps, "checkpoint_every": ckpt, "plain_forward_ms": fwd,
+            "checkpointed_forward_ms": r["forward_ms"], "backward_ms": r["backward_ms"],
+            "backward_over_plain_forward": r["backward_ms"] / fwd if fwd > 0 else None,
+            "loss": r["loss"], "n_exit": r["n_exit"], "tape_bytes": r["tape_bytes"], "wall_s": el,
+            "g_kappa": r["g_kappa"], "g_rate": r["g_rate"]}
 
 
 def copy_bandwidth(torch, nbytes=2 << 30, reps=20):

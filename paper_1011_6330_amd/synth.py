@@ -40,10 +40,11 @@ PRESETS = {
                fp_bits=32, sort_every=16, capacity=int(610 * 65536 * 1.05), flags=0, steps=20000,
                warm=610 * 65536),
     # adjoint workload: 4096 cells, 64 knots, about 1e6 particles
+    # (the macro charge is fixed at its nominal value so that it does not move with the knots)
     "c4": dict(n_cells=4096, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=q_over_m_for(430.0),
                ppc=244.0, rho_kind=RHO_KNOTS, rho_amp=1.0, kappa=0.15, r_star=10.0,
                knots=np.ones(64), fp_bits=32, sort_every=0, capacity=int(244 * 4096 * 1.3),
-               flags=0, steps=1000, warm=244 * 4096),
+               flags=0, steps=1000, warm=244 * 4096, macro_charge=-(1.0 - 0.15) * (10.0 / 4096) / 244.0),
     # large tube: 2^20 cells, L = 100R, the paper's (10317, 0.66) pair: a = 6809, ~2.5e8 particles
     "c5": dict(n_cells=1 << 20, length=100.0, radius=1.0, dt_over_dz=0.5, q_over_m=q_over_m_for(6809.0),
                ppc=238.4, rho_kind=RHO_FRAME_DRAG, rho_amp=1.0, kappa=0.15, r_star=10.0,
