@@ -173,7 +173,7 @@ struct pic_handle {
     pcpic::BatchState *d_state = nullptr;
     int batch_block = 256, batch_ppt = 2, batch_bpc = 0, batch_grid = 0;
     int64_t batch_push_items = 0, batch_field_items = 0, batch_sort_items = 0, batch_keys = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};   // one round, keyed by the particle parity
+    hipGraphExec_t graph[8] = {};   // one round, keyed by the (field, current, particle) buffer parities
     int64_t graph_steps = 0;
     bool use_graph = true;
 };

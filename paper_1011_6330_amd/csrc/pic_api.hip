@@ -889,6 +889,8 @@ static pic_status batch_status(pic_handle *h)
 // hand-written adjoint with checkpointing
 // ------------------------------------------------------------------------
 
+}  // extern "C"
+
 namespace {
 
 struct Tape {
@@ -969,6 +971,8 @@ pic_status adjoint_supported(pic_handle *h)
 }
 
 }  // namespace
+
+extern "C" {
 
 size_t pic_adjoint_tape_bytes(pic_handle *h, int64_t n_steps, int32_t checkpoint_every)
 {
