@@ -12,7 +12,7 @@ before the timed region.  Prints one JSON line:
   roofline       of the dominant kernel (the FP64 push), HIP-event timed
   fp32_bulk      the same tube with the FP32-bulk push (f32 momentum below
                  gamma = 1e6, f64 above), with its own roofline
-  ensemble       256 tubes of uneven size in one persistent launch per round
+  ensemble       256 tubes of uneven size, one graph launch per round
   cpu_baseline   the single-threaded FP64 oracle on the same tube
 """
 import argparse
@@ -156,7 +156,7 @@ def main():
         log(f"fp32-bulk: {fel / args.steps * 1e3:.3f} ms/step, push {froof['avg_launch_us']:.1f} us "
             f"({froof['achieved']:.0f} GB/s), high-stream fraction {fhigh / max(falive, 1):.3f}")
 
-    # ---- ensemble: 256 tubes, one persistent launch per round ----
+    # ---- ensemble: 256 tubes, one graph launch per round ----
     if not args.no_ensemble:
         result["ensemble"] = run_ensemble(args.ensemble_steps)
 
@@ -206,8 +206,8 @@ def run_ensemble(steps):
             "tubes": 256, "cells": int(sum(c["n_cells"] for c in cfgs)), "particles": int(alive),
             "dtype": "f32+f64", "launch": cfg, "steps": steps,
             "workload": "256 frame-dragging tubes, cells log-uniform 2048-65536, particles log-uniform 1e4-1e6, "
-                        "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk, one persistent graph-replayed "
-                        "launch per 16-step round"}
+                        "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk, one graph launch per "
+                        "16-step round"}
 
 
 def run_adjoint_leg(steps, ckpt=50):

@@ -231,17 +231,18 @@ enum {
  * picks the fastest.  Errors: PIC_EINVAL for an unsupported shape or flag. */
 pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread, uint32_t flags);
 
-/* ---- ensembles: many independent tubes stepped by one persistent launch ----
+/* ---- ensembles: many independent tubes stepped by one graph launch per round ----
  *
  * A batch holds n_tubes tubes of any sizes (each tube's parameters as for
  * pic_init; all tubes share the precision and sort_every).  pic_step on the
- * batch handle advances every tube: one persistent kernel runs the push and
- * field phases of up to sort_every steps for all tubes (grid barriers between
- * phases, grid sized from the kernel's occupancy so every block is resident),
- * followed by a batched cell sort; each such round is captured once in a HIP
- * graph and replayed.  A tube of a batch computes exactly what it computes when
- * stepped alone.  pic_step_timed reports the persistent kernel under push_ms.
- * pic_sync on a batch checks every tube's status and the barrier's abort flag. */
+ * batch handle advances every tube.  Each step is two kernels over all tubes:
+ * a push kernel and a field kernel, each a fixed grid of blocks that walks a
+ * device list of (tube, run of tiles) work items.  No block waits for another;
+ * the kernel boundary orders the phases.  Up to sort_every steps plus a batched
+ * cell sort form a round, captured once in a HIP graph and replayed with one
+ * launch.  A tube of a batch computes exactly what it computes when stepped
+ * alone.  pic_step_timed reports the push and field kernels of a round under
+ * push_ms.  pic_sync on a batch checks every tube's status. */
 
 /* Device bytes for a batch (header + every tube's workspace), 0 if invalid. */
 size_t pic_batch_workspace_bytes(const pic_params *tubes, int32_t n_tubes);
@@ -261,9 +262,10 @@ enum {
     PIC_BATCH_NO_GRAPH = 1u  /* launch every round directly instead of replaying a captured graph */
 };
 
-/* Launch shape of the persistent kernel: threads per block (64..512), slots per
- * thread (FP64: 2 or 4; FP32-bulk: 4), blocks per CU (0 = the occupancy limit;
- * larger values are clipped to it).  Results do not depend on the choice.
+/* Launch shape of the batched kernels: threads per block (64..512), slots per
+ * thread (FP64: 2 or 4; FP32-bulk: 4), blocks per CU (0 = the push kernel's
+ * occupancy limit; larger values are clipped to it).  Results do not depend on
+ * the choice.
  * Errors: PIC_EINVAL for an unsupported shape. */
 pic_status pic_batch_set_config(pic_handle *batch, int32_t block, int32_t per_thread, int32_t blocks_per_cu,
                                 uint32_t flags);

@@ -341,8 +341,8 @@ class _TubeView(Tube):
 
 
 class Batch:
-    """Many independent tubes of uneven size, stepped together by one persistent
-    HIP launch per round (captured in a graph and replayed)."""
+    """Many independent tubes of uneven size, stepped together: each round of
+    steps plus the batched sort is captured once in a HIP graph and replayed."""
 
     def __init__(self, cfgs, device="cuda", stream=None):
         import torch

@@ -70,7 +70,7 @@ def tune_tube(tube, steps=16, cache_path=DEFAULT_CACHE, use_cache=True):
 
 
 def tune_batch(batch, steps=None, cache_path=DEFAULT_CACHE, use_cache=True):
-    """Pick the persistent-kernel shape of a Batch; returns (block, per_thread, blocks_per_cu, times)."""
+    """Pick the batched-kernel shape of a Batch; returns (block, per_thread, blocks_per_cu, times)."""
     f32 = int(batch.cfgs[0].get("precision", 0)) == 1
     n = sum(t.diagnostics(fields=False)["n_alive"] for t in batch.tubes)
     se = int(batch.cfgs[0].get("sort_every", 16)) or 16

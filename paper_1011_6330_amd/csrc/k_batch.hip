@@ -1,18 +1,17 @@
-// k_batch.hip -- many independent tubes of uneven size stepped by one
-// persistent kernel launch.
+// k_batch.hip -- many independent tubes of uneven size stepped together.
 //
 // Each tube keeps the exact workspace layout of a single tube; a device table
-// of TubeDev descriptors points at them.  The persistent kernel runs k steps;
-// every step has two phases separated by a grid barrier:
-//   push  -- work items (tube, tile) for every tube's particle tiles at capacity,
-//            statically strided over the grid (tiles past a tube's live count
-//            are skipped); the body is the single-tube push_tile_*;
-//   field -- work items (tube, cell tile); the body is the single-tube
-//            field_tile, whose tile-0 block also injects for its tube.
-// A tube therefore computes bit for bit what it computes when stepped alone.
-// The grid is sized from the kernel's occupancy so every block is resident;
-// the barrier's spin is bounded and latches an abort flag instead of hanging.
-// The cell sort runs as four batched kernels after every round.
+// of TubeDev descriptors points at them.  A step of the whole batch is two
+// kernels, each a fixed grid of resident blocks that walks a device work list:
+//   push  -- items = runs of particle tiles of one tube (both streams in
+//            FP32-bulk mode); the body is the single-tube push_tile_*;
+//   field -- items = runs of cell tiles of one tube; the body is the
+//            single-tube field_tile, whose tile-0 block also injects.
+// The kernel boundary orders the two phases, so no block ever waits for
+// another and nothing depends on how many blocks are resident or on what else
+// shares the GPU.  A round of up to sort_every steps plus the batched cell sort
+// is captured once in a HIP graph and replayed with a single launch.  A tube
+// therefore computes bit for bit what it computes when stepped alone.
 #include <math.h>
 
 #include "field_body.h"
@@ -22,16 +21,14 @@
 
 namespace pcpic {
 
-constexpr unsigned long long BARRIER_SPIN_LIMIT = 1ull << 26;   // ~ seconds of s_sleep
-
 struct BatchArgs {
     const TubeDev *tubes;
     int n_tubes;
-    const int64_t *push_pref;    // [n_tubes + 1] prefix of push items
-    const int64_t *field_pref;   // [n_tubes + 1] prefix of field items
-    BatchState *st;
-    int nsteps;
-    int fb0, jb0, pb;            // parities at the first step
+    const int64_t *push_pref;    // [n_tubes + 1] prefix of push work items
+    const int64_t *field_pref;   // [n_tubes + 1] prefix of field work items
+    int64_t push_chunk;          // particle tiles per push item
+    int64_t field_chunk;         // cell tiles per field item
+    int fb, jb, pb;              // field, current and particle buffer parities of the step
 };
 
 // Last t with pref[t] <= item (pref is non-decreasing, pref[0] = 0).
@@ -46,88 +43,48 @@ __device__ __forceinline__ int find_tube(const int64_t *pref, int n, int64_t ite
     return lo;
 }
 
-// Grid-wide barrier with agent-scope release/acquire.  Returns false if the
-// wait exceeded the spin limit (the abort flag is then set for every block).
-__device__ __forceinline__ bool grid_sync(BatchState *st)
-{
-    __shared__ int s_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const unsigned gen = __hip_atomic_load(&st->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&st->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(&st->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&st->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned long long spins = 0;
-            while (__hip_atomic_load(&st->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > BARRIER_SPIN_LIMIT ||
-                    __hip_atomic_load(&st->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    __hip_atomic_store(&st->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-            }
-        }
-        __threadfence();
-        s_ok = ok;
-    }
-    __syncthreads();
-    return s_ok != 0;
-}
-
-__device__ __forceinline__ int64_t load_slots(const int64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 template <int BLOCK, int PPT, int NT, int F32>
-__global__ __launch_bounds__(BLOCK) void k_batch_steps(BatchArgs b)
+__global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
 {
     constexpr int TILE = BLOCK * (F32 ? 4 : PPT);
-    const int64_t ptot = b.push_pref[b.n_tubes], ftot = b.field_pref[b.n_tubes];
-    for (int s = 0; s < b.nsteps; ++s) {
-        const int fb = b.fb0 ^ (s & 1), jb = b.jb0 ^ (s & 1), pb = b.pb;
-        // ---- push + deposit for every tube ----
-        for (int64_t it = blockIdx.x; it < ptot; it += gridDim.x) {
-            const int t = find_tube(b.push_pref, b.n_tubes, it);
-            const TubeDev &T = b.tubes[t];
-            const int64_t local = it - b.push_pref[t];
-            if (F32) {
-                const bool hi = local >= T.push_tiles;
-                const int64_t tile0 = (hi ? local - T.push_tiles : local) * TILE;
-                const int64_t n = load_slots(hi ? &T.ctr->n_slots_hi : &T.ctr->n_slots);
-                if (tile0 < n) {
-                    Push32Args a{T.cl[pb], T.ol[pb], T.ul[pb], T.ch[pb], T.oh[pb], T.uh[pb], T.k32, T.k64,
-                                 (unsigned long long *)T.j[jb], T.ctr, 0u};
-                    push_tile_f32<BLOCK, NT>(T.c, a, hi, n, tile0);
-                }
-            } else {
-                const int64_t tile0 = local * TILE;
-                const int64_t n = load_slots(&T.ctr->n_slots);
-                if (tile0 < n) {
-                    PushArgs a{T.x[pb], T.u[pb], T.x[pb], T.u[pb], T.k64, (unsigned long long *)T.j[jb], T.ctr};
-                    push_tile_f64<BLOCK, PPT, NT>(T.c, a, n, tile0);
-                }
-            }
+    const int64_t ptot = b.push_pref[b.n_tubes];
+    for (int64_t it = blockIdx.x; it < ptot; it += gridDim.x) {
+        const int t = find_tube(b.push_pref, b.n_tubes, it);
+        const TubeDev &T = b.tubes[t];
+        const int64_t local = it - b.push_pref[t];
+        const int64_t per = (T.push_tiles + b.push_chunk - 1) / b.push_chunk;   // items per stream
+        const bool hi = F32 && local >= per;
+        const int64_t c0 = (hi ? local - per : local) * b.push_chunk;
+        const int64_t c1 = c0 + b.push_chunk < T.push_tiles ? c0 + b.push_chunk : T.push_tiles;
+        if (F32) {
+            const int64_t n = hi ? T.ctr->n_slots_hi : T.ctr->n_slots;
+            Push32Args a{T.cl[b.pb], T.ol[b.pb], T.ul[b.pb], T.ch[b.pb], T.oh[b.pb], T.uh[b.pb], T.k32, T.k64,
+                         (unsigned long long *)T.j[b.jb], T.ctr, 0u};
+            for (int64_t tl = c0; tl < c1 && tl * TILE < n; ++tl) push_tile_f32<BLOCK, NT>(T.c, a, hi, n, tl * TILE);
+        } else {
+            const int64_t n = T.ctr->n_slots;
+            PushArgs a{T.x[b.pb], T.u[b.pb], T.x[b.pb], T.u[b.pb], T.k64, (unsigned long long *)T.j[b.jb], T.ctr};
+            for (int64_t tl = c0; tl < c1 && tl * TILE < n; ++tl) push_tile_f64<BLOCK, PPT, NT>(T.c, a, n, tl * TILE);
         }
-        if (!grid_sync(b.st)) return;
-        // ---- fields + SCLF injection for every tube ----
-        for (int64_t it = blockIdx.x; it < ftot; it += gridDim.x) {
-            const int t = find_tube(b.field_pref, b.n_tubes, it);
-            const TubeDev &T = b.tubes[t];
-            const int64_t local = it - b.field_pref[t];
-            const int g = fb ^ 1;
-            FieldArgs a{T.ez[fb], T.er[fb], T.b[fb], T.ez[g], T.er[g], T.b[g], T.j[jb], T.j[jb ^ 1],
-                        T.k64, F32 ? T.k32 : nullptr, F32 ? nullptr : T.x[pb], F32 ? nullptr : T.u[pb],
-                        F32 ? T.cl[pb] : nullptr, F32 ? T.ol[pb] : nullptr, F32 ? T.ul[pb] : nullptr, T.ctr};
-            field_tile(T.c, a, local, BLOCK);
-        }
-        if (!grid_sync(b.st)) return;
+    }
+}
+
+template <int BLOCK, int F32>
+__global__ __launch_bounds__(BLOCK) void k_batch_field(BatchArgs b)
+{
+    const int64_t ftot = b.field_pref[b.n_tubes];
+    const int fb = b.fb, g = b.fb ^ 1, jb = b.jb, pb = b.pb;
+    for (int64_t it = blockIdx.x; it < ftot; it += gridDim.x) {
+        const int t = find_tube(b.field_pref, b.n_tubes, it);
+        const TubeDev &T = b.tubes[t];
+        const int64_t local = it - b.field_pref[t];
+        const int64_t ftiles = (T.c.N + BLOCK - 1) / BLOCK;
+        const int64_t c0 = local * b.field_chunk;
+        const int64_t c1 = c0 + b.field_chunk < ftiles ? c0 + b.field_chunk : ftiles;
+        FieldArgs a{T.ez[fb], T.er[fb], T.b[fb], T.ez[g], T.er[g], T.b[g], T.j[jb], T.j[jb ^ 1],
+                    T.k64, F32 ? T.k32 : nullptr, F32 ? nullptr : T.x[pb], F32 ? nullptr : T.u[pb],
+                    F32 ? T.cl[pb] : nullptr, F32 ? T.ol[pb] : nullptr, F32 ? T.ul[pb] : nullptr, T.ctr};
+        for (int64_t tl = c0; tl < c1; ++tl) field_tile(T.c, a, tl, BLOCK);
     }
 }
 
@@ -343,50 +300,80 @@ TubeDev tube_dev(pic_handle *t)
 }
 
 template <int BLOCK, int PPT, int NT, int F32>
-static const void *batch_kernel()
+static const void *push_kernel()
 {
-    return reinterpret_cast<const void *>(&k_batch_steps<BLOCK, PPT, NT, F32>);
+    return reinterpret_cast<const void *>(&k_batch_push<BLOCK, PPT, NT, F32>);
 }
 
-static const void *pick_batch_kernel(pic_handle *h)
+template <int BLOCK, int F32>
+static const void *field_kernel()
+{
+    return reinterpret_cast<const void *>(&k_batch_field<BLOCK, F32>);
+}
+
+static const void *pick_push_kernel(pic_handle *h)
 {
     const bool f32 = h->tubes[0]->p.precision == PIC_FP32_BULK;
     const int B = h->batch_block, P = h->batch_ppt;
     if (f32) {
-        if (B == 64) return batch_kernel<64, 4, 1, 1>();
-        if (B == 128) return batch_kernel<128, 4, 1, 1>();
-        if (B == 256) return batch_kernel<256, 4, 1, 1>();
-        if (B == 512) return batch_kernel<512, 4, 1, 1>();
+        if (B == 64) return push_kernel<64, 4, 1, 1>();
+        if (B == 128) return push_kernel<128, 4, 1, 1>();
+        if (B == 256) return push_kernel<256, 4, 1, 1>();
+        if (B == 512) return push_kernel<512, 4, 1, 1>();
     } else {
-        if (B == 64 && P == 2) return batch_kernel<64, 2, 1, 0>();
-        if (B == 128 && P == 2) return batch_kernel<128, 2, 1, 0>();
-        if (B == 256 && P == 2) return batch_kernel<256, 2, 1, 0>();
-        if (B == 512 && P == 2) return batch_kernel<512, 2, 1, 0>();
-        if (B == 64 && P == 4) return batch_kernel<64, 4, 1, 0>();
-        if (B == 128 && P == 4) return batch_kernel<128, 4, 1, 0>();
-        if (B == 256 && P == 4) return batch_kernel<256, 4, 1, 0>();
+        if (B == 64 && P == 2) return push_kernel<64, 2, 1, 0>();
+        if (B == 128 && P == 2) return push_kernel<128, 2, 1, 0>();
+        if (B == 256 && P == 2) return push_kernel<256, 2, 1, 0>();
+        if (B == 512 && P == 2) return push_kernel<512, 2, 1, 0>();
+        if (B == 64 && P == 4) return push_kernel<64, 4, 1, 0>();
+        if (B == 128 && P == 4) return push_kernel<128, 4, 1, 0>();
+        if (B == 256 && P == 4) return push_kernel<256, 4, 1, 0>();
     }
     return nullptr;
 }
 
+static const void *pick_field_kernel(pic_handle *h)
+{
+    const bool f32 = h->tubes[0]->p.precision == PIC_FP32_BULK;
+    switch (h->batch_block) {
+    case 64: return f32 ? field_kernel<64, 1>() : field_kernel<64, 0>();
+    case 128: return f32 ? field_kernel<128, 1>() : field_kernel<128, 0>();
+    case 256: return f32 ? field_kernel<256, 1>() : field_kernel<256, 0>();
+    case 512: return f32 ? field_kernel<512, 1>() : field_kernel<512, 0>();
+    default: return nullptr;
+    }
+}
+
+// Resident blocks per CU of the push kernel for the current shape (0 = unsupported).
 int batch_occupancy(pic_handle *h)
 {
-    const void *k = pick_batch_kernel(h);
-    if (!k) return 0;
+    const void *k = pick_push_kernel(h);
+    const void *kf = pick_field_kernel(h);
+    if (!k || !kf) return 0;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, h->batch_block, 0) != hipSuccess) return 0;
     return per_cu;
 }
 
+// nsteps steps of every tube: a push and a field kernel per step.
 hipError_t launch_batch_steps(pic_handle *h, int nsteps)
 {
-    const void *k = pick_batch_kernel(h);
-    if (!k || h->batch_grid <= 0) return hipErrorInvalidValue;
+    const void *kp = pick_push_kernel(h);
+    const void *kf = pick_field_kernel(h);
+    if (!kp || !kf || h->batch_grid <= 0) return hipErrorInvalidValue;
     pic_handle *t0 = h->tubes[0];
-    BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_push_pref, h->d_field_pref, h->d_state, nsteps,
-                t0->fbuf, t0->jbuf, t0->pbuf};
-    void *args[] = {&a};
-    return hipLaunchKernel(k, dim3(h->batch_grid), dim3(h->batch_block), args, 0, h->stream);
+    const int64_t fitems = h->batch_field_items;
+    const unsigned fgrid = (unsigned)(fitems < h->batch_grid ? fitems : h->batch_grid);
+    for (int s = 0; s < nsteps; ++s) {
+        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_push_pref, h->d_field_pref, h->batch_push_chunk,
+                    h->batch_field_chunk, t0->fbuf ^ (s & 1), t0->jbuf ^ (s & 1), t0->pbuf};
+        void *args[] = {&a};
+        hipError_t e = hipLaunchKernel(kp, dim3(h->batch_grid), dim3(h->batch_block), args, 0, h->stream);
+        if (e != hipSuccess) return e;
+        e = hipLaunchKernel(kf, dim3(fgrid > 0 ? fgrid : 1), dim3(h->batch_block), args, 0, h->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_batch_sort(pic_handle *h)

@@ -134,14 +134,6 @@ struct AdjStepPtrs {
     double *lx, *lu, *lez, *ler, *lb, *lbp, *lk, *grate;
 };
 
-// Grid-barrier state of the batched persistent kernel.
-struct BatchState {
-    unsigned bar_count;
-    unsigned bar_gen;
-    unsigned abort;
-    unsigned pad;
-};
-
 // Byte layout of the workspace (offsets from the base).  Computing it with a
 // null base gives the size.
 Workspace carve(const pic_params &p, uint8_t *base);
@@ -170,9 +162,9 @@ struct pic_handle {
     std::vector<pic_handle *> tubes;
     pcpic::TubeDev *d_tubes = nullptr;
     int64_t *d_push_pref = nullptr, *d_field_pref = nullptr, *d_sort_pref = nullptr, *d_key_pref = nullptr;
-    pcpic::BatchState *d_state = nullptr;
     int batch_block = 256, batch_ppt = 2, batch_bpc = 0, batch_grid = 0;
     int64_t batch_push_items = 0, batch_field_items = 0, batch_sort_items = 0, batch_keys = 0;
+    int64_t batch_push_chunk = 1, batch_field_chunk = 1;   // tiles per work item
     hipGraphExec_t graph[8] = {};   // one round, keyed by the (field, current, particle) buffer parities
     int64_t graph_steps = 0;
     bool use_graph = true;

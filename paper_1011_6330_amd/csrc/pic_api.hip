@@ -373,7 +373,7 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
                 float a = 0, b = 0;
                 (void)hipEventElapsedTime(&a, ev[k], ev[k + 1]);
                 (void)hipEventElapsedTime(&b, ev[k + 1], ev[k + 2]);
-                out->push_ms += a;   // persistent kernel: push + field phases of the round
+                out->push_ms += a;   // push and field kernels of the round
                 out->sort_ms += b;
             }
             if (!ev.empty()) {
@@ -639,7 +639,6 @@ static size_t batch_header_bytes(int n)
     size_t off = 0;
     off = align_up(off) + sizeof(TubeDev) * (size_t)n;
     for (int k = 0; k < 4; ++k) off = align_up(off) + sizeof(int64_t) * (size_t)(n + 1);
-    off = align_up(off) + sizeof(BatchState);
     return align_up(off);
 }
 
@@ -686,12 +685,24 @@ static pic_status batch_configure(pic_handle *h, int block, int per_thread, int 
     const int64_t tile = (int64_t)block * ppt;
     std::vector<TubeDev> td((size_t)n);
     std::vector<int64_t> pp((size_t)n + 1, 0), fp((size_t)n + 1, 0), sp((size_t)n + 1, 0), kp((size_t)n + 1, 0);
+    // Work items of a few tiles each, about four per block and phase: enough
+    // to balance uneven tubes, few enough that the ticket counter stays cheap.
+    int64_t push_tiles = 0, field_tiles = 0;
+    for (int t = 0; t < n; ++t) {
+        pic_handle *s = h->tubes[(size_t)t];
+        push_tiles += (f32 ? 2 : 1) * ((s->c.cap + tile - 1) / tile);
+        field_tiles += (s->c.N + block - 1) / block;
+    }
+    const int64_t target = 4 * (int64_t)h->batch_grid;
+    h->batch_push_chunk = push_tiles > target ? (push_tiles + target - 1) / target : 1;
+    h->batch_field_chunk = field_tiles > target ? (field_tiles + target - 1) / target : 1;
+    const int64_t pc = h->batch_push_chunk, fc = h->batch_field_chunk;
     for (int t = 0; t < n; ++t) {
         pic_handle *s = h->tubes[(size_t)t];
         td[(size_t)t] = tube_dev(s);
         td[(size_t)t].push_tiles = (s->c.cap + tile - 1) / tile;
-        pp[(size_t)t + 1] = pp[(size_t)t] + (f32 ? 2 : 1) * td[(size_t)t].push_tiles;
-        fp[(size_t)t + 1] = fp[(size_t)t] + (s->c.N + block - 1) / block;
+        pp[(size_t)t + 1] = pp[(size_t)t] + (f32 ? 2 : 1) * ((td[(size_t)t].push_tiles + pc - 1) / pc);
+        fp[(size_t)t + 1] = fp[(size_t)t] + ((s->c.N + block - 1) / block + fc - 1) / fc;
         sp[(size_t)t + 1] = sp[(size_t)t] + (f32 ? 2 : 1) * td[(size_t)t].sort_chunks;
         kp[(size_t)t + 1] = kp[(size_t)t] + td[(size_t)t].n_keys;
     }
@@ -743,7 +754,6 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
     h->d_field_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_sort_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_key_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
-    h->d_state = (BatchState *)take(sizeof(BatchState));
     off = batch_header_bytes(n_tubes);
     for (int t = 0; t < n_tubes; ++t) {
         const size_t sz = carve(tubes[t], nullptr).bytes;
@@ -756,11 +766,6 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
         sub->parent = h;
         h->tubes.push_back(sub);
         off += sz;
-    }
-    hipError_t e = hipMemsetAsync(h->d_state, 0, sizeof(BatchState), h->stream);
-    if (e != hipSuccess) {
-        pic_destroy(h);
-        return fail(PIC_EDEVICE, "clear batch state: %s", hipGetErrorString(e));
     }
     const bool f32 = tubes[0].precision == PIC_FP32_BULK;
     pic_status s = batch_configure(h, 256, f32 ? 4 : 2, 0);
@@ -803,8 +808,9 @@ pic_status pic_batch_get_config(pic_handle *h, int32_t *block, int32_t *per_thre
 }
 
 // Advance every tube of the batch by n steps in rounds that end at the sort
-// period; a whole round (persistent kernel + batched sort) is replayed from a
-// captured graph.  With `ev`, events bracket each round's kernel and sort.
+// period; a whole round (push and field kernels of every step, then the batched
+// sort) is replayed from a captured graph.  With `ev`, events bracket each
+// round's step kernels and its sort.
 static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t> *ev, pic_timing *tim)
 {
     pic_handle *t0 = h->tubes[0];
@@ -872,10 +878,6 @@ static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t
 
 static pic_status batch_status(pic_handle *h)
 {
-    BatchState st{};
-    HIP_OK(hipMemcpyAsync(&st, h->d_state, sizeof st, hipMemcpyDeviceToHost, h->stream));
-    HIP_OK(hipStreamSynchronize(h->stream));
-    if (st.abort) return fail(PIC_EDEVICE, "batched kernel: grid barrier wait exceeded its limit");
     for (pic_handle *t : h->tubes) {
         DevCounters c;
         pic_status s = read_counters(t, &c);
