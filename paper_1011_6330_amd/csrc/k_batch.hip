@@ -135,13 +135,13 @@ __global__ __launch_bounds__(256) void k_bsort_hist(BSortArgs a)
                 if (cell >= 0) {
                     const double u = hi ? T.uh[a.src][p] : (double)T.ul[a.src][p];
                     live = true;
-                    key = fabs(u) >= T.u_hi ? T.c.N + 1 + cell : cell;
+                    key = sort_key_f32(T.c, cell, hi ? T.oh[a.src][p] : T.ol[a.src][p], fabs(u) >= T.u_hi);
                 }
             } else {
                 const double x = T.x[a.src][p];
                 if (x >= 0.0) {
                     live = true;
-                    key = (int64_t)floor(x);
+                    key = sort_key_f64(T.c, x);
                 }
             }
         }
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_bsort_scan(BSortArgs a)
     }
     if (threadIdx.x == 0) {
         T.ctr->n_alive = s_carry;
-        if (a.f32) *T.total_lo = T.cell_off[T.c.N + 1];
+        if (a.f32) *T.total_lo = T.cell_off[sort_low_keys(T.c)];
     }
 }
 
@@ -204,14 +204,14 @@ __global__ __launch_bounds__(256) void k_bsort_scatter(BSortArgs a)
                     o = hi ? T.oh[a.src][p] : T.ol[a.src][p];
                     u = hi ? T.uh[a.src][p] : (double)T.ul[a.src][p];
                     want = true;
-                    key = fabs(u) >= T.u_hi ? T.c.N + 1 + cell : cell;
+                    key = sort_key_f32(T.c, cell, o, fabs(u) >= T.u_hi);
                 }
             } else {
                 x = T.x[a.src][p];
                 if (x >= 0.0) {
                     u = T.u[a.src][p];
                     want = true;
-                    key = (int64_t)floor(x);
+                    key = sort_key_f64(T.c, x);
                 }
             }
         }
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_bsort_scatter(BSortArgs a)
             if (mine) {
                 const int64_t d = (int64_t)f0 + __popcll(grp & ((1ull << lane) - 1ull));
                 if (a.f32) {
-                    if (key > T.c.N) {
+                    if (key >= sort_low_keys(T.c)) {
                         const int64_t q = d - tlo;
                         T.ch[a.dst][q] = cell;
                         T.oh[a.dst][q] = o;
@@ -295,7 +295,7 @@ TubeDev tube_dev(pic_handle *t)
     d.total_lo = w.total_lo;
     d.u_hi = t->u_hi;
     d.sort_chunks = (t->c.cap + 255) / 256;
-    d.n_keys = t->p.precision == PIC_FP32_BULK ? 2 * (t->c.N + 1) : t->c.N;
+    d.n_keys = sort_key_count(t->c, t->p.precision == PIC_FP32_BULK);
     return d;
 }
 

@@ -128,13 +128,14 @@ __global__ __launch_bounds__(256) void k_profile32(Consts c, int nb, Streams s, 
 // Destination stream of a particle: the high stream from |u| >= u_hi on.
 __device__ __forceinline__ bool goes_high(double u, double u_hi) { return fabs(u) >= u_hi; }
 
-// Histogram for the sort: key = cell for the low destination, N + 1 + cell for the high one.
+// Histogram for the sort (sort_key_f32: the destination stream's key range).
 __global__ __launch_bounds__(256) void k_hist32(Consts c, Streams s, const DevCounters *ctr, unsigned nb_lo,
                                                 double u_hi, unsigned long long *count)
 {
     int64_t first, stride, n;
     const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
     const int *C = hi ? s.CH : s.CL;
+    const float *O = hi ? s.OH : s.OL;
     for (int64_t base = first; base < n; base += stride) {
         const int64_t p = base + threadIdx.x;
         const int cell = p < n ? C[p] : -1;
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(256) void k_hist32(Consts c, Streams s, const DevCo
         int64_t key = 0;
         if (live) {
             const double u = hi ? s.UH[p] : (double)s.UL[p];
-            key = goes_high(u, u_hi) ? (int64_t)c.N + 1 + cell : cell;
+            key = sort_key_f32(c, cell, O[p], goes_high(u, u_hi));
         }
         wave_add_keyed(count, key, 1, live);
     }
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(256) void k_scatter32(Consts c, Streams src, Stream
         if (want) {
             o = O[p];
             u = hi ? src.UH[p] : (double)src.UL[p];
-            key = goes_high(u, u_hi) ? (int64_t)c.N + 1 + cell : cell;
+            key = sort_key_f32(c, cell, o, goes_high(u, u_hi));
         }
         unsigned long long pend = __ballot(want);
         while (pend) {
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(256) void k_scatter32(Consts c, Streams src, Stream
             f0 = __shfl(f0, leader);
             if (mine) {
                 const int64_t d = (int64_t)f0 + __popcll(grp & ((1ull << lane) - 1ull));
-                if (key > (int64_t)c.N) {
+                if (key >= sort_low_keys(c)) {
                     const int64_t q = d - tlo;
                     dst.CH[q] = cell;
                     dst.OH[q] = o;
@@ -331,7 +332,7 @@ hipError_t launch_sort32_scatter(pic_handle *h)
 {
     const unsigned nb = (unsigned)(h->n_cu * 4);
     const int src = h->pbuf, dst = 1 - h->pbuf;
-    hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64), 0, h->stream, (const long long *)(h->ws.cell_off + h->c.N + 1),
+    hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64), 0, h->stream, (const long long *)(h->ws.cell_off + sort_low_keys(h->c)),
                        h->ws.total_lo);
     hipLaunchKernelGGL(k_scatter32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, streams_of(h, src),
                        streams_of(h, dst), h->ws.ctr, nb, h->u_hi, (unsigned long long *)h->ws.cell_off,

@@ -30,8 +30,8 @@ __global__ __launch_bounds__(256) void k_hist(Consts c, const double *__restrict
         const int64_t p = base + threadIdx.x;
         const double x = p < n ? X[p] : -1.0;
         const bool live = x >= 0.0;
-        const int64_t cell = live ? (int64_t)floor(x) : 0;
-        wave_add_keyed((unsigned long long *)count, cell, 1, live);
+        const int64_t key = live ? sort_key_f64(c, x) : 0;
+        wave_add_keyed((unsigned long long *)count, key, 1, live);
     }
 }
 
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const long long *coun
     }
 }
 
-__global__ __launch_bounds__(256) void k_scatter(const double *__restrict__ X, const double *__restrict__ U,
+__global__ __launch_bounds__(256) void k_scatter(Consts c, const double *__restrict__ X, const double *__restrict__ U,
                                                  double *__restrict__ Xo, double *__restrict__ Uo,
                                                  const DevCounters *ctr, unsigned long long *off)
 {
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_scatter(const double *__restrict__ X, c
         const double x = p < n ? X[p] : -1.0;
         const double u = p < n ? U[p] : 0.0;
         bool want = x >= 0.0;
-        const int64_t cell = want ? (int64_t)floor(x) : 0;
+        const int64_t cell = want ? sort_key_f64(c, x) : 0;
         unsigned long long pend = __ballot(want);
         while (pend) {
             const int leader = __ffsll(pend) - 1;
@@ -165,9 +165,8 @@ hipError_t launch_sort(pic_handle *h)
 {
     const Consts &c = h->c;
     Workspace &w = h->ws;
-    const int64_t N = c.N;
     const bool f32 = h->p.precision == PIC_FP32_BULK;
-    const int64_t nkeys = f32 ? 2 * (N + 1) : N;
+    const int64_t nkeys = sort_key_count(c, f32);
     const int src = h->pbuf, dst = 1 - h->pbuf;
     hipLaunchKernelGGL(k_fill_ll, dim3((unsigned)((nkeys + 255) / 256)), dim3(256), 0, h->stream, w.cell_count, nkeys);
     hipError_t e;
@@ -178,7 +177,7 @@ hipError_t launch_sort(pic_handle *h)
     } else {
         hipLaunchKernelGGL(k_hist, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.ctr, w.cell_count);
         if ((e = launch_scan(h, nkeys)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_scatter, dim3(h->n_cu * 8), dim3(256), 0, h->stream, w.x[src], w.u[src], w.x[dst],
+        hipLaunchKernelGGL(k_scatter, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.u[src], w.x[dst],
                            w.u[dst], w.ctr, (unsigned long long *)w.cell_off);
         hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, h->stream, w.ctr);
     }

@@ -24,6 +24,8 @@ struct Consts {
     int64_t cap;      // particle capacity
     int32_t P;        // fixed-point fraction bits
     uint32_t flags;   // PIC_* flags
+    int32_t sub;      // log2 of the sort key's bins per cell
+    int32_t pad0;
     int64_t oneP;     // 2^P
     double twoP;      // 2^P as a double
     double dz;        // L / N
@@ -48,6 +50,25 @@ struct Consts {
     int32_t n_knots;
     double rho_amp, kappa, r_star, length;
 };
+
+// Cell-sort keys.  A live particle's key is its cell refined into 2^sub bins
+// (so that a wave's particles sit within a small fraction of a cell and cross
+// cell edges together); in FP32-bulk mode the keys of the high stream follow
+// those of the low stream, (N + 1) 2^sub of them.
+__host__ __device__ inline int64_t sort_key_count(const Consts &c, bool f32)
+{
+    return (f32 ? 2 * (c.N + 1) : c.N) << c.sub;
+}
+__host__ __device__ inline int64_t sort_low_keys(const Consts &c) { return (c.N + 1) << c.sub; }
+__device__ inline int64_t sort_key_f64(const Consts &c, double x)
+{
+    return (int64_t)floor(x * (double)(1 << c.sub));   // exact scaling by a power of two
+}
+__device__ inline int64_t sort_key_f32(const Consts &c, int cell, float off, bool high)
+{
+    const int64_t k = ((int64_t)cell << c.sub) + (int64_t)(off * (float)(1 << c.sub));
+    return high ? sort_low_keys(c) + k : k;
+}
 
 // Device-side counters (one per tube), 256-byte aligned in the workspace.
 struct DevCounters {
@@ -137,6 +158,10 @@ struct AdjStepPtrs {
 // Byte layout of the workspace (offsets from the base).  Computing it with a
 // null base gives the size.
 Workspace carve(const pic_params &p, uint8_t *base);
+
+// log2 of the sort key's bins per cell: about 32 particles per bin at the
+// nominal density (ppc per cell), at most 16 bins.
+int sort_sub_log2(const pic_params &p);
 
 }  // namespace pcpic
 

@@ -78,6 +78,7 @@ Consts make_consts(const pic_params &p, const double *knots)
     c.cap = p.capacity;
     c.P = p.fp_bits;
     c.flags = p.flags;
+    c.sub = sort_sub_log2(p);
     c.oneP = (int64_t)1 << p.fp_bits;
     c.twoP = ldexp(1.0, p.fp_bits);
     c.dz = p.length / (double)p.n_cells;
@@ -112,6 +113,13 @@ Consts make_consts(const pic_params &p, const double *knots)
 }  // namespace
 
 namespace pcpic {
+
+int sort_sub_log2(const pic_params &p)
+{
+    int s = 0;
+    while (s < 4 && p.ppc / (double)(1 << s) > 32.0) ++s;
+    return s;
+}
 
 Workspace carve(const pic_params &p, uint8_t *base)
 {
@@ -168,7 +176,7 @@ Workspace carve(const pic_params &p, uint8_t *base)
     w.pmin = (long long *)take(nb * 8);
     w.pmax = (long long *)take(nb * 8);
     w.gauss = (double *)take((N + 1) * 8);
-    const size_t nkeys = f32 ? 2 * (N + 1) : N + 1;   // sort keys (FP32-bulk: per destination stream)
+    const size_t nkeys = (f32 ? 2 * (N + 1) : N + 1) << sort_sub_log2(p);   // sort keys (see sort_key_count)
     w.cell_count = (long long *)take(nkeys * 8);
     w.cell_off = (long long *)take(nkeys * 8);
     w.blk_sum = (long long *)take((nkeys / 1024 + 2) * 8);
