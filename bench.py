@@ -185,7 +185,7 @@ def run_ensemble(steps):
         x, u = synth.warm_start(c, seed=t)
         b.tubes[t].inject(x, u)
     log("ensemble loaded")
-    bb, bp, bpc, _ = autotune.tune_batch(b, use_cache=False)
+    bb, bp, _ = autotune.tune_batch(b, use_cache=False)
     b.step(32)
     b.sync()
     n0 = sum(t.diagnostics(fields=False)["n_alive"] for t in b.tubes)

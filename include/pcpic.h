@@ -236,8 +236,8 @@ pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread,
  * A batch holds n_tubes tubes of any sizes (each tube's parameters as for
  * pic_init; all tubes share the precision and sort_every).  pic_step on the
  * batch handle advances every tube.  Each step is two kernels over all tubes:
- * a push kernel and a field kernel, each a fixed grid of blocks that walks a
- * device list of (tube, run of tiles) work items.  No block waits for another;
+ * a push kernel and a field kernel over a device list of (tube, tile) work
+ * items, one block per item.  No block waits for another;
  * the kernel boundary orders the phases.  Up to sort_every steps plus a batched
  * cell sort form a round, captured once in a HIP graph and replayed with one
  * launch.  A tube of a batch computes exactly what it computes when stepped
@@ -262,17 +262,16 @@ enum {
     PIC_BATCH_NO_GRAPH = 1u  /* launch every round directly instead of replaying a captured graph */
 };
 
-/* Launch shape of the batched kernels: threads per block (64..512), slots per
- * thread (FP64: 2 or 4; FP32-bulk: 4), blocks per CU (0 = the push kernel's
- * occupancy limit; larger values are clipped to it).  Results do not depend on
- * the choice.
- * Errors: PIC_EINVAL for an unsupported shape. */
-pic_status pic_batch_set_config(pic_handle *batch, int32_t block, int32_t per_thread, int32_t blocks_per_cu,
-                                uint32_t flags);
+/* Launch shape of the batched kernels: threads per block (64..512) and slots
+ * per thread (FP64: 2 or 4; FP32-bulk: 4).  Results do not depend on the
+ * choice.  Errors: PIC_EINVAL for an unsupported shape or flag. */
+pic_status pic_batch_set_config(pic_handle *batch, int32_t block, int32_t per_thread, uint32_t flags);
 
-/* Current launch shape (any pointer may be NULL); grid = CUs x blocks per CU. */
-pic_status pic_batch_get_config(pic_handle *batch, int32_t *block, int32_t *per_thread, int32_t *blocks_per_cu,
-                                int32_t *grid);
+/* Current launch shape (any pointer may be NULL): threads per block, slots per
+ * thread, and the blocks of one step's push and field kernels (one per tile of
+ * every tube, particle tiles counted at capacity). */
+pic_status pic_batch_get_config(pic_handle *batch, int32_t *block, int32_t *per_thread, int64_t *push_blocks,
+                                int64_t *field_blocks);
 
 /* ---- hand-written adjoint ----
  *

@@ -103,11 +103,10 @@ SIGNATURES = {
     "pic_init_batch": (ctypes.c_int32, [ctypes.POINTER(PicParams), ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "pic_batch_tube": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
-    "pic_batch_set_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                              ctypes.c_uint32]),
+    "pic_batch_set_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
     "pic_batch_get_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
-                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                              ctypes.POINTER(ctypes.c_int32)]),
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_int64)]),
     "pic_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
 }
 
@@ -385,14 +384,14 @@ class Batch:
     def sync(self):
         _check(self.lib.pic_sync(self._h), "pic_sync")
 
-    def set_config(self, block, per_thread, blocks_per_cu=0, graph=True):
-        _check(self.lib.pic_batch_set_config(self._h, int(block), int(per_thread), int(blocks_per_cu),
-                                             0 if graph else 1), "pic_batch_set_config")
+    def set_config(self, block, per_thread, graph=True):
+        _check(self.lib.pic_batch_set_config(self._h, int(block), int(per_thread), 0 if graph else 1),
+               "pic_batch_set_config")
 
     def get_config(self):
-        v = [ctypes.c_int32() for _ in range(4)]
+        v = [ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()]
         _check(self.lib.pic_batch_get_config(self._h, *[ctypes.byref(x) for x in v]), "pic_batch_get_config")
-        return dict(block=v[0].value, per_thread=v[1].value, blocks_per_cu=v[2].value, grid=v[3].value)
+        return dict(block=v[0].value, per_thread=v[1].value, push_blocks=v[2].value, field_blocks=v[3].value)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -14,8 +14,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pcpic_tune.json
 
 TUBE_SHAPES = [(64, 2, True), (128, 2, True), (256, 2, True), (64, 4, True), (256, 2, False), (128, 4, True)]
 TUBE_SHAPES_F32 = [(64, 4, True), (128, 4, True), (256, 4, True), (512, 4, True), (256, 4, False)]
-BATCH_SHAPES = [(b, p, bpc) for b in (64, 128, 256, 512) for p in (2, 4) for bpc in (0, 1, 2)]
-BATCH_SHAPES_F32 = [(b, 4, bpc) for b in (64, 128, 256, 512) for bpc in (0, 1, 2, 4)]
+BATCH_SHAPES = [(b, p) for b in (64, 128, 256, 512) for p in (2, 4) if (b, p) != (512, 4)]
+BATCH_SHAPES_F32 = [(b, 4) for b in (64, 128, 256, 512)]
 
 
 def _device_key():
@@ -70,7 +70,7 @@ def tune_tube(tube, steps=16, cache_path=DEFAULT_CACHE, use_cache=True):
 
 
 def tune_batch(batch, steps=None, cache_path=DEFAULT_CACHE, use_cache=True):
-    """Pick the batched-kernel shape of a Batch; returns (block, per_thread, blocks_per_cu, times)."""
+    """Pick the batched-kernel shape of a Batch; returns (block, per_thread, times)."""
     f32 = int(batch.cfgs[0].get("precision", 0)) == 1
     n = sum(t.diagnostics(fields=False)["n_alive"] for t in batch.tubes)
     se = int(batch.cfgs[0].get("sort_every", 16)) or 16
@@ -78,17 +78,17 @@ def tune_batch(batch, steps=None, cache_path=DEFAULT_CACHE, use_cache=True):
     key = f"batch/{_device_key()}/{'f32' if f32 else 'f64'}/{len(batch)}/{_bucket(n)}"
     cache = _load(cache_path) if use_cache else {}
     if key in cache:
-        b, p, bpc = cache[key]
-        batch.set_config(b, p, bpc)
-        return b, p, bpc, {}
+        b, p = cache[key]
+        batch.set_config(b, p)
+        return b, p, {}
     times = {}
-    for b, p, bpc in (BATCH_SHAPES_F32 if f32 else BATCH_SHAPES):
+    for b, p in (BATCH_SHAPES_F32 if f32 else BATCH_SHAPES):
         try:
-            batch.set_config(b, p, bpc)
+            batch.set_config(b, p)
         except Exception:
             continue
         t = batch.step_timed(steps)
-        times[(b, p, bpc)] = t["total_ms"] / steps
+        times[(b, p)] = t["total_ms"] / steps
     best = min(times, key=times.get)
     batch.set_config(*best)
     if use_cache:

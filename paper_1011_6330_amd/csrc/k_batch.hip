@@ -2,11 +2,11 @@
 //
 // Each tube keeps the exact workspace layout of a single tube; a device table
 // of TubeDev descriptors points at them.  A step of the whole batch is two
-// kernels, each a fixed grid of resident blocks that walks a device work list:
-//   push  -- items = runs of particle tiles of one tube (both streams in
-//            FP32-bulk mode); the body is the single-tube push_tile_*;
-//   field -- items = runs of cell tiles of one tube; the body is the
-//            single-tube field_tile, whose tile-0 block also injects.
+// kernels over a device work list, one block per item:
+//   push  -- items = particle tiles of every tube (both streams in FP32-bulk
+//            mode); the body is the single-tube push_tile_*;
+//   field -- items = cell tiles of every tube; the body is the single-tube
+//            field_tile, whose tile-0 block also injects.
 // The kernel boundary orders the two phases, so no block ever waits for
 // another and nothing depends on how many blocks are resident or on what else
 // shares the GPU.  A round of up to sort_every steps plus the batched cell sort
@@ -24,10 +24,8 @@ namespace pcpic {
 struct BatchArgs {
     const TubeDev *tubes;
     int n_tubes;
-    const int64_t *push_pref;    // [n_tubes + 1] prefix of push work items
-    const int64_t *field_pref;   // [n_tubes + 1] prefix of field work items
-    int64_t push_chunk;          // particle tiles per push item
-    int64_t field_chunk;         // cell tiles per field item
+    const int64_t *push_pref;    // [n_tubes + 1] prefix of push tiles (at capacity)
+    const int64_t *field_pref;   // [n_tubes + 1] prefix of cell tiles
     int fb, jb, pb;              // field, current and particle buffer parities of the step
 };
 
@@ -47,24 +45,25 @@ template <int BLOCK, int PPT, int NT, int F32>
 __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
 {
     constexpr int TILE = BLOCK * (F32 ? 4 : PPT);
-    const int64_t ptot = b.push_pref[b.n_tubes];
-    for (int64_t it = blockIdx.x; it < ptot; it += gridDim.x) {
+    const int64_t it = blockIdx.x;
+    if (it >= b.push_pref[b.n_tubes]) return;
+    {
         const int t = find_tube(b.push_pref, b.n_tubes, it);
         const TubeDev &T = b.tubes[t];
         const int64_t local = it - b.push_pref[t];
-        const int64_t per = (T.push_tiles + b.push_chunk - 1) / b.push_chunk;   // items per stream
-        const bool hi = F32 && local >= per;
-        const int64_t c0 = (hi ? local - per : local) * b.push_chunk;
-        const int64_t c1 = c0 + b.push_chunk < T.push_tiles ? c0 + b.push_chunk : T.push_tiles;
+        const bool hi = F32 && local >= T.push_tiles;
+        const int64_t tile0 = (hi ? local - T.push_tiles : local) * TILE;
         if (F32) {
             const int64_t n = hi ? T.ctr->n_slots_hi : T.ctr->n_slots;
+            if (tile0 >= n) return;                   // tile past the stream's slots (uniform)
             Push32Args a{T.cl[b.pb], T.ol[b.pb], T.ul[b.pb], T.ch[b.pb], T.oh[b.pb], T.uh[b.pb], T.k32, T.k64,
                          (unsigned long long *)T.j[b.jb], T.ctr, 0u};
-            for (int64_t tl = c0; tl < c1 && tl * TILE < n; ++tl) push_tile_f32<BLOCK, NT>(T.c, a, hi, n, tl * TILE);
+            push_tile_f32<BLOCK, NT>(T.c, a, hi, n, tile0);
         } else {
             const int64_t n = T.ctr->n_slots;
+            if (tile0 >= n) return;
             PushArgs a{T.x[b.pb], T.u[b.pb], T.x[b.pb], T.u[b.pb], T.k64, (unsigned long long *)T.j[b.jb], T.ctr};
-            for (int64_t tl = c0; tl < c1 && tl * TILE < n; ++tl) push_tile_f64<BLOCK, PPT, NT>(T.c, a, n, tl * TILE);
+            push_tile_f64<BLOCK, PPT, NT>(T.c, a, n, tile0);
         }
     }
 }
@@ -72,19 +71,17 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
 template <int BLOCK, int F32>
 __global__ __launch_bounds__(BLOCK) void k_batch_field(BatchArgs b)
 {
-    const int64_t ftot = b.field_pref[b.n_tubes];
     const int fb = b.fb, g = b.fb ^ 1, jb = b.jb, pb = b.pb;
-    for (int64_t it = blockIdx.x; it < ftot; it += gridDim.x) {
+    const int64_t it = blockIdx.x;
+    if (it >= b.field_pref[b.n_tubes]) return;
+    {
         const int t = find_tube(b.field_pref, b.n_tubes, it);
         const TubeDev &T = b.tubes[t];
         const int64_t local = it - b.field_pref[t];
-        const int64_t ftiles = (T.c.N + BLOCK - 1) / BLOCK;
-        const int64_t c0 = local * b.field_chunk;
-        const int64_t c1 = c0 + b.field_chunk < ftiles ? c0 + b.field_chunk : ftiles;
         FieldArgs a{T.ez[fb], T.er[fb], T.b[fb], T.ez[g], T.er[g], T.b[g], T.j[jb], T.j[jb ^ 1],
                     T.k64, F32 ? T.k32 : nullptr, F32 ? nullptr : T.x[pb], F32 ? nullptr : T.u[pb],
                     F32 ? T.cl[pb] : nullptr, F32 ? T.ol[pb] : nullptr, F32 ? T.ul[pb] : nullptr, T.ctr};
-        for (int64_t tl = c0; tl < c1; ++tl) field_tile(T.c, a, tl, BLOCK);
+        field_tile(T.c, a, local, BLOCK);
     }
 }
 
@@ -97,6 +94,7 @@ struct BSortArgs {
     int n_tubes;
     const int64_t *chunk_pref;   // [n_tubes + 1] prefix of 256-slot chunks (both streams)
     const int64_t *key_pref;     // [n_tubes + 1] prefix of sort keys
+    const int64_t *scan_pref;    // [n_tubes + 1] prefix of scan blocks
     int f32;
     int src, dst;                // particle buffer parity before / after
 };
@@ -145,41 +143,90 @@ __global__ __launch_bounds__(256) void k_bsort_hist(BSortArgs a)
                 }
             }
         }
-        wave_add_keyed((unsigned long long *)T.cell_count, key, 1, live);
+        const WaveRun r = wave_runs(key, live);
+        if (live && r.is_head)
+            atomicAdd((unsigned long long *)T.cell_count + key, (unsigned long long)(r.end - (int)__lane_id()));
     }
 }
 
-// One block per tube: exclusive scan of its keys in chunks of 256.
-__global__ __launch_bounds__(256) void k_bsort_scan(BSortArgs a)
+// Exclusive scan of every tube's key counts in three phases over blocks of
+// SORT_SCAN_TILE keys (a block never spans two tubes): block totals, a scan of
+// each tube's block totals (one block per tube), then the offsets.
+__device__ __forceinline__ long long bscan_block_incl(long long v, long long *s_wave)
+{
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) s_wave[wv] = v;
+    __syncthreads();
+    long long add = 0;
+    for (int q = 0; q < wv; ++q) add += s_wave[q];
+    __syncthreads();
+    return v + add;
+}
+
+__global__ __launch_bounds__(256) void k_bscan_totals(BSortArgs a)
+{
+    __shared__ long long s_wave[4];
+    const int t = find_tube(a.scan_pref, a.n_tubes, blockIdx.x);
+    const TubeDev &T = a.tubes[t];
+    const int64_t lb = blockIdx.x - a.scan_pref[t];
+    const int64_t base = lb * SORT_SCAN_TILE + (int64_t)threadIdx.x * 4;
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += base + k < T.n_keys ? T.cell_count[base + k] : 0;
+    const long long inc = bscan_block_incl(s, s_wave);
+    if (threadIdx.x == 255) T.blk_sum[lb] = inc;
+}
+
+__global__ __launch_bounds__(256) void k_bscan_blocks(BSortArgs a)
 {
     __shared__ long long s_wave[4];
     __shared__ long long s_carry;
     const TubeDev &T = a.tubes[blockIdx.x];
-    const int64_t nk = T.n_keys;
+    const int64_t nb = a.scan_pref[blockIdx.x + 1] - a.scan_pref[blockIdx.x];
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    const int lane = __lane_id(), wv = threadIdx.x >> 6;
-    for (int64_t k0 = 0; k0 < nk; k0 += 256) {
-        const int64_t k = k0 + threadIdx.x;
-        const long long v = k < nk ? T.cell_count[k] : 0;
-        long long inc = v;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const long long o = __shfl_up(inc, off);
-            if (lane >= off) inc += o;
-        }
-        if (lane == 63) s_wave[wv] = inc;
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const long long v = i < nb ? T.blk_sum[i] : 0;
+        const long long inc = bscan_block_incl(v, s_wave);
+        const long long carry = s_carry;
+        if (i < nb) T.blk_sum[i] = carry + inc - v;
         __syncthreads();
-        long long add = s_carry;
-        for (int q = 0; q < wv; ++q) add += s_wave[q];
-        if (k < nk) T.cell_off[k] = add + inc - v;
-        __syncthreads();
-        if (threadIdx.x == 255) s_carry = add + inc;
+        if (threadIdx.x == 255) s_carry = carry + inc;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        T.ctr->n_alive = s_carry;
-        if (a.f32) *T.total_lo = T.cell_off[sort_low_keys(T.c)];
+    if (threadIdx.x == 0) T.ctr->n_alive = s_carry;
+}
+
+__global__ __launch_bounds__(256) void k_bscan_apply(BSortArgs a)
+{
+    __shared__ long long s_wave[4];
+    const int t = find_tube(a.scan_pref, a.n_tubes, blockIdx.x);
+    const TubeDev &T = a.tubes[t];
+    const int64_t lb = blockIdx.x - a.scan_pref[t];
+    const int64_t base = lb * SORT_SCAN_TILE + (int64_t)threadIdx.x * 4;
+    long long v[4];
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = base + k < T.n_keys ? T.cell_count[base + k] : 0;
+        s += v[k];
+    }
+    const long long inc = bscan_block_incl(s, s_wave);
+    long long run = T.blk_sum[lb] + inc - s;
+    const int64_t klo = a.f32 ? sort_low_keys(T.c) : -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < T.n_keys) {
+            T.cell_off[base + k] = run;
+            if (base + k == klo) *T.total_lo = run;   // slots of the low destination stream
+        }
+        run += v[k];
     }
 }
 
@@ -216,35 +263,27 @@ __global__ __launch_bounds__(256) void k_bsort_scatter(BSortArgs a)
             }
         }
         const long long tlo = a.f32 ? *T.total_lo : 0;
-        unsigned long long pend = __ballot(want);
-        while (pend) {
-            const int leader = __ffsll(pend) - 1;
-            const int64_t lk = __shfl(key, leader);
-            const bool mine = want && key == lk;
-            const unsigned long long grp = __ballot(mine);
-            unsigned long long f0 = 0;
-            if (lane == leader) f0 = atomicAdd((unsigned long long *)T.cell_off + lk, (unsigned long long)__popcll(grp));
-            f0 = __shfl(f0, leader);
-            if (mine) {
-                const int64_t d = (int64_t)f0 + __popcll(grp & ((1ull << lane) - 1ull));
-                if (a.f32) {
-                    if (key >= sort_low_keys(T.c)) {
-                        const int64_t q = d - tlo;
-                        T.ch[a.dst][q] = cell;
-                        T.oh[a.dst][q] = o;
-                        T.uh[a.dst][q] = u;
-                    } else {
-                        T.cl[a.dst][d] = cell;
-                        T.ol[a.dst][d] = o;
-                        T.ul[a.dst][d] = (float)u;
-                    }
+        const WaveRun r = wave_runs(key, want);
+        unsigned long long f0 = 0;
+        if (want && r.is_head) f0 = atomicAdd((unsigned long long *)T.cell_off + key, (unsigned long long)(r.end - lane));
+        f0 = __shfl(f0, r.head);
+        if (want) {
+            const int64_t d = (int64_t)f0 + r.rank;
+            if (a.f32) {
+                if (key >= sort_low_keys(T.c)) {
+                    const int64_t q = d - tlo;
+                    T.ch[a.dst][q] = cell;
+                    T.oh[a.dst][q] = o;
+                    T.uh[a.dst][q] = u;
                 } else {
-                    T.x[a.dst][d] = x;
-                    T.u[a.dst][d] = u;
+                    T.cl[a.dst][d] = cell;
+                    T.ol[a.dst][d] = o;
+                    T.ul[a.dst][d] = (float)u;
                 }
+            } else {
+                T.x[a.dst][d] = x;
+                T.u[a.dst][d] = u;
             }
-            pend &= ~grp;
-            want = want && !mine;
         }
     }
 }
@@ -293,6 +332,7 @@ TubeDev tube_dev(pic_handle *t)
     d.cell_count = w.cell_count;
     d.cell_off = w.cell_off;
     d.total_lo = w.total_lo;
+    d.blk_sum = w.blk_sum;
     d.u_hi = t->u_hi;
     d.sort_chunks = (t->c.cap + 255) / 256;
     d.n_keys = sort_key_count(t->c, t->p.precision == PIC_FP32_BULK);
@@ -344,33 +384,25 @@ static const void *pick_field_kernel(pic_handle *h)
     }
 }
 
-// Resident blocks per CU of the push kernel for the current shape (0 = unsupported).
-int batch_occupancy(pic_handle *h)
-{
-    const void *k = pick_push_kernel(h);
-    const void *kf = pick_field_kernel(h);
-    if (!k || !kf) return 0;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, h->batch_block, 0) != hipSuccess) return 0;
-    return per_cu;
-}
+bool batch_shape_supported(pic_handle *h) { return pick_push_kernel(h) && pick_field_kernel(h); }
 
 // nsteps steps of every tube: a push and a field kernel per step.
 hipError_t launch_batch_steps(pic_handle *h, int nsteps)
 {
     const void *kp = pick_push_kernel(h);
     const void *kf = pick_field_kernel(h);
-    if (!kp || !kf || h->batch_grid <= 0) return hipErrorInvalidValue;
+    if (!kp || !kf || h->batch_push_items <= 0 || h->batch_field_items <= 0 ||
+        h->batch_push_items > 0x7fffffff || h->batch_field_items > 0x7fffffff)
+        return hipErrorInvalidValue;
     pic_handle *t0 = h->tubes[0];
-    const int64_t fitems = h->batch_field_items;
-    const unsigned fgrid = (unsigned)(fitems < h->batch_grid ? fitems : h->batch_grid);
+    const unsigned pgrid = (unsigned)h->batch_push_items, fgrid = (unsigned)h->batch_field_items;
     for (int s = 0; s < nsteps; ++s) {
-        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_push_pref, h->d_field_pref, h->batch_push_chunk,
-                    h->batch_field_chunk, t0->fbuf ^ (s & 1), t0->jbuf ^ (s & 1), t0->pbuf};
+        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_push_pref, h->d_field_pref, t0->fbuf ^ (s & 1),
+                    t0->jbuf ^ (s & 1), t0->pbuf};
         void *args[] = {&a};
-        hipError_t e = hipLaunchKernel(kp, dim3(h->batch_grid), dim3(h->batch_block), args, 0, h->stream);
+        hipError_t e = hipLaunchKernel(kp, dim3(pgrid), dim3(h->batch_block), args, 0, h->stream);
         if (e != hipSuccess) return e;
-        e = hipLaunchKernel(kf, dim3(fgrid > 0 ? fgrid : 1), dim3(h->batch_block), args, 0, h->stream);
+        e = hipLaunchKernel(kf, dim3(fgrid), dim3(h->batch_block), args, 0, h->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -380,12 +412,16 @@ hipError_t launch_batch_sort(pic_handle *h)
 {
     pic_handle *t0 = h->tubes[0];
     const int nt = (int)h->tubes.size();
-    BSortArgs a{h->d_tubes, nt, h->d_sort_pref, h->d_key_pref, t0->p.precision == PIC_FP32_BULK ? 1 : 0,
-                t0->pbuf, 1 - t0->pbuf};
+    BSortArgs a{h->d_tubes, nt, h->d_sort_pref, h->d_key_pref, h->d_scan_pref,
+                t0->p.precision == PIC_FP32_BULK ? 1 : 0, t0->pbuf, 1 - t0->pbuf};
+    if (h->batch_scan_blocks <= 0 || h->batch_scan_blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const unsigned sb = (unsigned)h->batch_scan_blocks;
     const unsigned g = (unsigned)(h->n_cu * 8);
     hipLaunchKernelGGL(k_bsort_clear, dim3(g), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bsort_hist, dim3(g), dim3(256), 0, h->stream, a);
-    hipLaunchKernelGGL(k_bsort_scan, dim3(nt), dim3(256), 0, h->stream, a);
+    hipLaunchKernelGGL(k_bscan_totals, dim3(sb), dim3(256), 0, h->stream, a);
+    hipLaunchKernelGGL(k_bscan_blocks, dim3(nt), dim3(256), 0, h->stream, a);
+    hipLaunchKernelGGL(k_bscan_apply, dim3(sb), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bsort_scatter, dim3(g), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bsort_finish, dim3((nt + 63) / 64), dim3(64), 0, h->stream, a);
     return hipGetLastError();

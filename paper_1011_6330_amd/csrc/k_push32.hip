@@ -145,7 +145,8 @@ __global__ __launch_bounds__(256) void k_hist32(Consts c, Streams s, const DevCo
             const double u = hi ? s.UH[p] : (double)s.UL[p];
             key = sort_key_f32(c, cell, O[p], goes_high(u, u_hi));
         }
-        wave_add_keyed(count, key, 1, live);
+        const WaveRun r = wave_runs(key, live);
+        if (live && r.is_head) atomicAdd(count + key, (unsigned long long)(r.end - (int)__lane_id()));
     }
 }
 
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(256) void k_scatter32(Consts c, Streams src, Stream
     for (int64_t base = first; base < n; base += stride) {
         const int64_t p = base + threadIdx.x;
         const int cell = p < n ? C[p] : -1;
-        bool want = cell >= 0;
+        const bool want = cell >= 0;
         float o = 0.0f;
         double u = 0.0;
         int64_t key = 0;
@@ -171,30 +172,22 @@ __global__ __launch_bounds__(256) void k_scatter32(Consts c, Streams src, Stream
             u = hi ? src.UH[p] : (double)src.UL[p];
             key = sort_key_f32(c, cell, o, goes_high(u, u_hi));
         }
-        unsigned long long pend = __ballot(want);
-        while (pend) {
-            const int leader = __ffsll(pend) - 1;
-            const int64_t lk = __shfl(key, leader);
-            const bool mine = want && key == lk;
-            const unsigned long long grp = __ballot(mine);
-            unsigned long long f0 = 0;
-            if (lane == leader) f0 = atomicAdd(off + lk, (unsigned long long)__popcll(grp));
-            f0 = __shfl(f0, leader);
-            if (mine) {
-                const int64_t d = (int64_t)f0 + __popcll(grp & ((1ull << lane) - 1ull));
-                if (key >= sort_low_keys(c)) {
-                    const int64_t q = d - tlo;
-                    dst.CH[q] = cell;
-                    dst.OH[q] = o;
-                    dst.UH[q] = u;
-                } else {
-                    dst.CL[d] = cell;
-                    dst.OL[d] = o;
-                    dst.UL[d] = (float)u;
-                }
+        const WaveRun r = wave_runs(key, want);
+        unsigned long long f0 = 0;
+        if (want && r.is_head) f0 = atomicAdd(off + key, (unsigned long long)(r.end - lane));
+        f0 = __shfl(f0, r.head);
+        if (want) {
+            const int64_t d = (int64_t)f0 + r.rank;
+            if (key >= sort_low_keys(c)) {
+                const int64_t q = d - tlo;
+                dst.CH[q] = cell;
+                dst.OH[q] = o;
+                dst.UH[q] = u;
+            } else {
+                dst.CL[d] = cell;
+                dst.OL[d] = o;
+                dst.UL[d] = (float)u;
             }
-            pend &= ~grp;
-            want = want && !mine;
         }
     }
 }

@@ -14,7 +14,8 @@ namespace pcpic {
 
 constexpr int SCAN_ITEMS = 4;
 constexpr int SCAN_BLOCK = 256;
-constexpr int SCAN_TILE = SCAN_ITEMS * SCAN_BLOCK;   // cells per scan block
+constexpr int SCAN_TILE = SCAN_ITEMS * SCAN_BLOCK;   // keys per scan block
+static_assert(SCAN_TILE == SORT_SCAN_TILE, "scan tile and workspace sizing differ");
 
 __global__ __launch_bounds__(256) void k_fill_ll(long long *p, int64_t n)
 {
@@ -31,7 +32,8 @@ __global__ __launch_bounds__(256) void k_hist(Consts c, const double *__restrict
         const double x = p < n ? X[p] : -1.0;
         const bool live = x >= 0.0;
         const int64_t key = live ? sort_key_f64(c, x) : 0;
-        wave_add_keyed((unsigned long long *)count, key, 1, live);
+        const WaveRun r = wave_runs(key, live);
+        if (live && r.is_head) atomicAdd((unsigned long long *)count + key, (unsigned long long)(r.end - (int)__lane_id()));
     }
 }
 
@@ -117,25 +119,16 @@ __global__ __launch_bounds__(256) void k_scatter(Consts c, const double *__restr
         const int64_t p = base + threadIdx.x;
         const double x = p < n ? X[p] : -1.0;
         const double u = p < n ? U[p] : 0.0;
-        bool want = x >= 0.0;
-        const int64_t cell = want ? sort_key_f64(c, x) : 0;
-        unsigned long long pend = __ballot(want);
-        while (pend) {
-            const int leader = __ffsll(pend) - 1;
-            const int64_t lc = __shfl(cell, leader);
-            const bool mine = want && cell == lc;
-            const unsigned long long grp = __ballot(mine);
-            unsigned long long first = 0;
-            if (lane == leader) first = atomicAdd(off + lc, (unsigned long long)__popcll(grp));
-            first = __shfl(first, leader);
-            if (mine) {
-                const unsigned long long below = grp & ((1ull << lane) - 1ull);
-                const int64_t dst = (int64_t)first + __popcll(below);
-                Xo[dst] = x;
-                Uo[dst] = u;
-            }
-            pend &= ~grp;
-            want = want && !mine;
+        const bool want = x >= 0.0;
+        const int64_t key = want ? sort_key_f64(c, x) : 0;
+        const WaveRun r = wave_runs(key, want);
+        unsigned long long first = 0;
+        if (want && r.is_head) first = atomicAdd(off + key, (unsigned long long)(r.end - lane));
+        first = __shfl(first, r.head);
+        if (want) {
+            const int64_t dst = (int64_t)first + r.rank;
+            Xo[dst] = x;
+            Uo[dst] = u;
         }
     }
 }

@@ -60,6 +60,7 @@ __host__ __device__ inline int64_t sort_key_count(const Consts &c, bool f32)
     return (f32 ? 2 * (c.N + 1) : c.N) << c.sub;
 }
 __host__ __device__ inline int64_t sort_low_keys(const Consts &c) { return (c.N + 1) << c.sub; }
+constexpr int SORT_SCAN_TILE = 1024;   // keys per block of the three-phase scan
 __device__ inline int64_t sort_key_f64(const Consts &c, double x)
 {
     return (int64_t)floor(x * (double)(1 << c.sub));   // exact scaling by a power of two
@@ -140,7 +141,7 @@ struct TubeDev {
     double *k64;
     float *k32;
     DevCounters *ctr;
-    long long *cell_count, *cell_off, *total_lo;
+    long long *cell_count, *cell_off, *total_lo, *blk_sum;
     double u_hi;
     int64_t push_tiles;   // push tiles per particle stream at capacity
     int64_t sort_chunks;  // 256-slot chunks per particle stream at capacity
@@ -187,9 +188,9 @@ struct pic_handle {
     std::vector<pic_handle *> tubes;
     pcpic::TubeDev *d_tubes = nullptr;
     int64_t *d_push_pref = nullptr, *d_field_pref = nullptr, *d_sort_pref = nullptr, *d_key_pref = nullptr;
-    int batch_block = 256, batch_ppt = 2, batch_bpc = 0, batch_grid = 0;
-    int64_t batch_push_items = 0, batch_field_items = 0, batch_sort_items = 0, batch_keys = 0;
-    int64_t batch_push_chunk = 1, batch_field_chunk = 1;   // tiles per work item
+    int64_t *d_scan_pref = nullptr;             // [n + 1] prefix of 1024-key scan blocks
+    int batch_block = 256, batch_ppt = 2;
+    int64_t batch_push_items = 0, batch_field_items = 0, batch_sort_items = 0, batch_keys = 0, batch_scan_blocks = 0;
     hipGraphExec_t graph[8] = {};   // one round, keyed by the (field, current, particle) buffer parities
     int64_t graph_steps = 0;
     bool use_graph = true;
@@ -222,7 +223,7 @@ hipError_t launch_adj_finish(pic_handle *h, const double *lez, const double *ler
 hipError_t launch_kick_from(pic_handle *h, const double *ez);
 hipError_t launch_zero_i64(pic_handle *h, int64_t *p, int64_t n);
 hipError_t launch_batch_sort(pic_handle *h);
-int batch_occupancy(pic_handle *h);
+bool batch_shape_supported(pic_handle *h);
 TubeDev tube_dev(pic_handle *t);
 hipError_t launch_field_inject(pic_handle *h);
 hipError_t launch_check_append(pic_handle *h, int64_t base, int64_t n);

@@ -179,7 +179,7 @@ Workspace carve(const pic_params &p, uint8_t *base)
     const size_t nkeys = (f32 ? 2 * (N + 1) : N + 1) << sort_sub_log2(p);   // sort keys (see sort_key_count)
     w.cell_count = (long long *)take(nkeys * 8);
     w.cell_off = (long long *)take(nkeys * 8);
-    w.blk_sum = (long long *)take((nkeys / 1024 + 2) * 8);
+    w.blk_sum = (long long *)take((nkeys / SORT_SCAN_TILE + 2) * 8);
     w.bytes = align_up(off);
     return w;
 }
@@ -646,7 +646,7 @@ static size_t batch_header_bytes(int n)
 {
     size_t off = 0;
     off = align_up(off) + sizeof(TubeDev) * (size_t)n;
-    for (int k = 0; k < 4; ++k) off = align_up(off) + sizeof(int64_t) * (size_t)(n + 1);
+    for (int k = 0; k < 5; ++k) off = align_up(off) + sizeof(int64_t) * (size_t)(n + 1);
     return align_up(off);
 }
 
@@ -673,56 +673,44 @@ static void free_batch_graphs(pic_handle *h)
 }
 
 // Push/field work-item tables for the current launch shape, uploaded to the device.
-static pic_status batch_configure(pic_handle *h, int block, int per_thread, int blocks_per_cu)
+static pic_status batch_configure(pic_handle *h, int block, int per_thread)
 {
     const bool f32 = h->tubes[0]->p.precision == PIC_FP32_BULK;
     const int ppt = f32 ? 4 : per_thread;
     const int saved_b = h->batch_block, saved_p = h->batch_ppt;
     h->batch_block = block;
     h->batch_ppt = ppt;
-    const int occ = batch_occupancy(h);
-    if (occ <= 0) {
+    if (!batch_shape_supported(h)) {
         h->batch_block = saved_b;
         h->batch_ppt = saved_p;
         return fail(PIC_EINVAL, "unsupported batch launch shape (%d threads, %d per thread)", block, per_thread);
     }
-    const int bpc = blocks_per_cu > 0 ? (blocks_per_cu < occ ? blocks_per_cu : occ) : occ;
-    h->batch_bpc = bpc;
-    h->batch_grid = h->n_cu * bpc;
     const int n = (int)h->tubes.size();
     const int64_t tile = (int64_t)block * ppt;
     std::vector<TubeDev> td((size_t)n);
     std::vector<int64_t> pp((size_t)n + 1, 0), fp((size_t)n + 1, 0), sp((size_t)n + 1, 0), kp((size_t)n + 1, 0);
-    // Work items of a few tiles each, about four per block and phase: enough
-    // to balance uneven tubes, few enough that the ticket counter stays cheap.
-    int64_t push_tiles = 0, field_tiles = 0;
-    for (int t = 0; t < n; ++t) {
-        pic_handle *s = h->tubes[(size_t)t];
-        push_tiles += (f32 ? 2 : 1) * ((s->c.cap + tile - 1) / tile);
-        field_tiles += (s->c.N + block - 1) / block;
-    }
-    const int64_t target = 4 * (int64_t)h->batch_grid;
-    h->batch_push_chunk = push_tiles > target ? (push_tiles + target - 1) / target : 1;
-    h->batch_field_chunk = field_tiles > target ? (field_tiles + target - 1) / target : 1;
-    const int64_t pc = h->batch_push_chunk, fc = h->batch_field_chunk;
+    std::vector<int64_t> cp((size_t)n + 1, 0);
     for (int t = 0; t < n; ++t) {
         pic_handle *s = h->tubes[(size_t)t];
         td[(size_t)t] = tube_dev(s);
         td[(size_t)t].push_tiles = (s->c.cap + tile - 1) / tile;
-        pp[(size_t)t + 1] = pp[(size_t)t] + (f32 ? 2 : 1) * ((td[(size_t)t].push_tiles + pc - 1) / pc);
-        fp[(size_t)t + 1] = fp[(size_t)t] + ((s->c.N + block - 1) / block + fc - 1) / fc;
+        pp[(size_t)t + 1] = pp[(size_t)t] + (f32 ? 2 : 1) * td[(size_t)t].push_tiles;
+        fp[(size_t)t + 1] = fp[(size_t)t] + (s->c.N + block - 1) / block;
         sp[(size_t)t + 1] = sp[(size_t)t] + (f32 ? 2 : 1) * td[(size_t)t].sort_chunks;
         kp[(size_t)t + 1] = kp[(size_t)t] + td[(size_t)t].n_keys;
+        cp[(size_t)t + 1] = cp[(size_t)t] + (td[(size_t)t].n_keys + SORT_SCAN_TILE - 1) / SORT_SCAN_TILE;
     }
     h->batch_push_items = pp[(size_t)n];
     h->batch_field_items = fp[(size_t)n];
     h->batch_sort_items = sp[(size_t)n];
     h->batch_keys = kp[(size_t)n];
+    h->batch_scan_blocks = cp[(size_t)n];
     HIP_OK(hipMemcpyAsync(h->d_tubes, td.data(), sizeof(TubeDev) * (size_t)n, hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_push_pref, pp.data(), 8 * pp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_field_pref, fp.data(), 8 * fp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_sort_pref, sp.data(), 8 * sp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_key_pref, kp.data(), 8 * kp.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_scan_pref, cp.data(), 8 * cp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
     free_batch_graphs(h);
     return PIC_OK;
@@ -762,6 +750,7 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
     h->d_field_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_sort_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_key_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
+    h->d_scan_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     off = batch_header_bytes(n_tubes);
     for (int t = 0; t < n_tubes; ++t) {
         const size_t sz = carve(tubes[t], nullptr).bytes;
@@ -776,7 +765,7 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
         off += sz;
     }
     const bool f32 = tubes[0].precision == PIC_FP32_BULK;
-    pic_status s = batch_configure(h, 256, f32 ? 4 : 2, 0);
+    pic_status s = batch_configure(h, 256, f32 ? 4 : 2);
     if (s != PIC_OK) {
         pic_destroy(h);
         return s;
@@ -793,25 +782,23 @@ pic_status pic_batch_tube(pic_handle *h, int32_t t, pic_handle **out)
     return PIC_OK;
 }
 
-pic_status pic_batch_set_config(pic_handle *h, int32_t block, int32_t per_thread, int32_t blocks_per_cu,
-                                uint32_t flags)
+pic_status pic_batch_set_config(pic_handle *h, int32_t block, int32_t per_thread, uint32_t flags)
 {
     if (!h || !h->is_batch) return fail(PIC_EINVAL, "not a batch handle");
-    if (blocks_per_cu < 0) return fail(PIC_EINVAL, "blocks_per_cu < 0");
     if (flags & ~PIC_BATCH_NO_GRAPH) return fail(PIC_EINVAL, "unknown batch flags");
-    pic_status s = batch_configure(h, block, per_thread, blocks_per_cu);
+    pic_status s = batch_configure(h, block, per_thread);
     if (s == PIC_OK) h->use_graph = !(flags & PIC_BATCH_NO_GRAPH);
     return s;
 }
 
-pic_status pic_batch_get_config(pic_handle *h, int32_t *block, int32_t *per_thread, int32_t *blocks_per_cu,
-                                int32_t *grid)
+pic_status pic_batch_get_config(pic_handle *h, int32_t *block, int32_t *per_thread, int64_t *push_blocks,
+                                int64_t *field_blocks)
 {
     if (!h || !h->is_batch) return fail(PIC_EINVAL, "not a batch handle");
     if (block) *block = h->batch_block;
     if (per_thread) *per_thread = h->batch_ppt;
-    if (blocks_per_cu) *blocks_per_cu = h->batch_bpc;
-    if (grid) *grid = h->batch_grid;
+    if (push_blocks) *push_blocks = h->batch_push_items;
+    if (field_blocks) *field_blocks = h->batch_field_items;
     return PIC_OK;
 }
 

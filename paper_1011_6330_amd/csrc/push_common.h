@@ -71,26 +71,23 @@ struct DepAcc {
         g_frac += rint((gam - gi) * 4294967296.0);
     }
 
-    // Wave-collective: must be reached by all 64 lanes of the wave.
+    // Wave-collective: must be reached by all 64 lanes of the wave.  Lanes
+    // with the same first cell in consecutive positions form a run; the run's
+    // head adds the run's sums of the three channels (one atomic per face and
+    // run, however many cells the wave spans).
     __device__ __forceinline__ void flush(unsigned long long *J, DevCounters *ctr)
     {
         const int lane = __lane_id();
-        bool want = cf != -2 && (am != 0.0 || a0 != 0.0 || ap != 0.0);
-        unsigned long long pend = __ballot(want);
-        while (pend) {
-            const int leader = __ffsll(pend) - 1;
-            const int lk = __shfl(cf, leader);
-            const bool mine = want && cf == lk;
-            const double sm = wave_sum_f64_to63(mine ? am : 0.0);
-            const double s0 = wave_sum_f64_to63(mine ? a0 : 0.0);
-            const double sp = wave_sum_f64_to63(mine ? ap : 0.0);
-            if (lane == 63) {
-                if (sm != 0.0) atomic_add_face(J, lk - 1, sm);
-                if (s0 != 0.0) atomic_add_face(J, lk, s0);
-                if (sp != 0.0) atomic_add_face(J, lk + 1, sp);
-            }
-            pend &= ~__ballot(mine);
-            want = want && !mine;
+        const bool has = cf != -2;
+        const WaveRun r = wave_runs(cf, has);
+        double sm = am, s0 = a0, sp = ap;
+        if (__ballot(am != 0.0)) sm = run_sum_to_head(sm, r.end);
+        if (__ballot(a0 != 0.0)) s0 = run_sum_to_head(s0, r.end);
+        if (__ballot(ap != 0.0)) sp = run_sum_to_head(sp, r.end);
+        if (has && r.is_head) {
+            if (sm != 0.0) atomic_add_face(J, cf - 1, sm);
+            if (s0 != 0.0) atomic_add_face(J, cf, s0);
+            if (sp != 0.0) atomic_add_face(J, cf + 1, sp);
         }
         const unsigned long long any = __ballot(w0 != 0.0 || nexit != 0.0 || nabs != 0.0 || nlost != 0.0);
         if (any) {

@@ -33,6 +33,47 @@ __device__ __forceinline__ long long wave_max_i64(long long v)
     return v;
 }
 
+// Runs of equal keys over consecutive lanes of the wave.  A lane without
+// `want` belongs to no run and ends the run before it.  For a lane with `want`:
+// head = first lane of its run, rank = lane - head, end = one past the run's
+// last lane; is_head marks the first lane.  With sorted particles a run is a
+// cell (or sort key), so one atomic per run replaces one per particle.
+struct WaveRun {
+    int head, rank, end;
+    bool is_head;
+};
+
+__device__ __forceinline__ WaveRun wave_runs(long long key, bool want)
+{
+    const int lane = (int)__lane_id();
+    const unsigned long long wm = __ballot(want);
+    const long long kprev = __shfl_up(key, 1u);
+    const bool prev_want = lane > 0 && ((wm >> (lane - 1)) & 1ull);
+    const bool head = want && (!prev_want || kprev != key);
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
+    const unsigned long long brk = (hm | ~wm) & ~upto;                              // breaks above the lane
+    WaveRun r;
+    r.is_head = head;
+    r.head = 63 - __clzll(hm & upto);
+    r.rank = lane - r.head;
+    r.end = brk ? __ffsll(brk) - 1 : 64;
+    return r;
+}
+
+// Sum of v over [lane, end) (Hillis-Steele suffix scan inside contiguous runs);
+// on a run's head lane it is the run total.  Every lane must call it.
+__device__ __forceinline__ double run_sum_to_head(double v, int end)
+{
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_down(v, (unsigned)off);
+        if (lane + off < end) v += t;
+    }
+    return v;
+}
+
 // Add `val` to dst[key] for every lane with `want`, one global atomic per
 // distinct key present in the wave: lanes sharing the leader's key are summed
 // with a butterfly, the leader lane issues the atomic, and the loop repeats

@@ -56,14 +56,14 @@ def test_batch_fp64_matches_oracle_per_tube():
     b.close()
 
 
-@pytest.mark.parametrize("shape", [(64, 2, 1, True), (256, 4, 0, True), (512, 2, 2, False), (128, 2, 0, False)])
+@pytest.mark.parametrize("shape", [(64, 2, True), (256, 4, True), (512, 2, False), (128, 2, False)])
 def test_batch_shapes_and_graph_identical(shape):
     from paper_1011_6330_amd import Batch
     cfgs, loads = _mixed_tubes(precision=0)
     outs = []
-    for cfg_shape in ((256, 2, 0, True), shape):
+    for cfg_shape in ((256, 2, True), shape):
         b = Batch([synth.tube_params(c) for c in cfgs])
-        b.set_config(cfg_shape[0], cfg_shape[1], cfg_shape[2], graph=cfg_shape[3])
+        b.set_config(cfg_shape[0], cfg_shape[1], graph=cfg_shape[2])
         for t, (x, u) in enumerate(loads):
             if len(x):
                 b.tubes[t].inject(x, u)
