@@ -1,7 +1,8 @@
 """Throughput of the polar-cap PIC step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
-                    [--no-fp32] [--no-ensemble] [--no-cpu-baseline]
+                    [--push 256:2:nt] [--push32 256:4:nt] [--tune]
+                    [--no-fp32] [--no-ensemble] [--no-adjoint] [--no-cpu-baseline]
 
 A step is one whole PIC cycle of the tube: push + deposit, field update +
 SCLF injection, and the periodic cell sort.  Inputs are seeded synthetic
@@ -9,7 +10,10 @@ tubes shaped like the paper's frame-dragging runs and are resident in HBM
 before the timed region.  Prints one JSON line:
 
   value          particle-steps/s of the plain FP64 step on the configured tube
-  roofline       of the dominant kernel (the FP64 push), HIP-event timed
+  roofline       of the dominant kernel (the FP64 push), HIP-event timed; its
+                 "traffic" is the counter-measured HBM bytes per launch from
+                 profiles/k_push_f64_c2_hbm_traffic.txt when that summary was
+                 taken on the current push sources and launch shape (else null)
   fp32_bulk      the same tube with the FP32-bulk push (f32 momentum below
                  gamma = 1e6, f64 above), with its own roofline
   ensemble       256 tubes of uneven size, one graph launch per round
@@ -82,13 +86,47 @@ def roofline_of(bytes_per_launch, tim, kernel):
             "bytes_per_launch": bytes_per_launch}
 
 
+PUSH_SOURCES = ("paper_1011_6330_amd/csrc/k_push.hip", "paper_1011_6330_amd/csrc/push_body.h",
+                "paper_1011_6330_amd/csrc/push_common.h", "paper_1011_6330_amd/csrc/wave.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_f64_c2_hbm_traffic.txt")
+
+
+def push_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in PUSH_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(shape):
+    """HBM bytes per launch of the FP64 push from the committed counter summary,
+    if it was taken on the current push sources and this launch shape; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    want = f"{shape[0]}:{shape[1]}:{'nt' if shape[2] else 'plain'}" if shape else None
+    if kv.get("source_sha256") != push_source_hash() or kv.get("push_shape") != want:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--push", default=None, help="fixed push shape threads:slots[:nt] (default: autotuned)")
+    ap.add_argument("--push", default="256:2:nt", help="FP64 push shape threads:slots[:nt]")
+    ap.add_argument("--push32", default="256:4:nt", help="FP32-bulk push shape threads:4[:nt]")
+    ap.add_argument("--tune", action="store_true", help="autotune the push shapes instead")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=512)
@@ -110,16 +148,18 @@ def main():
     cfg = synth.preset(args.config)
     log("config", args.config, "cells", cfg["n_cells"], "warm particles", cfg["warm"])
     x, u = synth.warm_start(cfg)
-    push = None
-    if args.push:
-        parts = args.push.split(":")
-        push = (int(parts[0]), int(parts[1]), len(parts) > 2 and parts[2] == "nt")
+    def shape_of(text):
+        parts = text.split(":")
+        return (int(parts[0]), int(parts[1]), len(parts) > 2 and parts[2] == "nt")
+    push = None if args.tune else shape_of(args.push)
+    push32 = None if args.tune else shape_of(args.push32)
 
     # ---- plain FP64 step: the headline value ----
     d0, d1, tim, elapsed, shape = run_tube(cfg, x, u, 0, args.steps, args.warmup, push=push)
     alive = 0.5 * (d0["n_alive"] + d1["n_alive"])
     value = alive * args.steps / elapsed
     roof = roofline_of(B_FP64 * alive, tim, "k_push_f64")
+    roof["traffic"] = measured_traffic(shape)
     log(f"fp64: {elapsed / args.steps * 1e3:.3f} ms/step, push {roof['avg_launch_us']:.1f} us "
         f"({roof['achieved']:.0f} GB/s), shape {shape}")
     result = {
@@ -144,7 +184,7 @@ def main():
 
     # ---- FP32-bulk push on the same tube ----
     if not args.no_fp32:
-        f0, f1, ftim, fel, fshape = run_tube(cfg, x, u, 1, args.steps, args.warmup)
+        f0, f1, ftim, fel, fshape = run_tube(cfg, x, u, 1, args.steps, args.warmup, push=push32)
         falive = 0.5 * (f0["n_alive"] + f1["n_alive"])
         fhigh = 0.5 * (f0["n_slots_high"] + f1["n_slots_high"])
         flow = max(falive - fhigh, 0.0)
