@@ -14,13 +14,13 @@ SRC = os.path.join(HERE, "pcpic_oracle.c")
 LIB = os.path.join(HERE, "libpcpic_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, src: str = SRC, out: str = LIB) -> str:
     cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-o", LIB, SRC, "-lm"]
+           "-fno-fast-math", "-Wall", "-Wextra", "-I", HERE, "-o", out, src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    return LIB
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    return out
 
 
 if __name__ == "__main__":

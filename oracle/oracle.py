@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpcpic_oracle.so")
+# PCPIC_ORACLE_LIB selects another build of the same source (the planted-mistake
+# tests build mutated copies of it).
+LIB_PATH = os.environ.get("PCPIC_ORACLE_LIB") or os.path.join(HERE, "libpcpic_oracle.so")
 
 RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS = 0, 1, 2
 NO_AUTO_INJECT, FREEZE_FIELDS = 1, 2

@@ -1,0 +1,100 @@
+"""Planted mistakes in the oracle (CPU only): every one must fail a pin.
+
+Each case copies oracle/pcpic_oracle.c, makes one plausible mistake in it (a
+dropped or doubled term, a wrong sign, index or factor, a transposed operand),
+builds the copy and runs the pins against it in a child process.  The pins
+that face the paper and the mathematics (test_oracle_pins.py) must catch every
+mistake in the forward step; the finite-difference pins of the gradient
+(test_oracle_adjoint.py) must catch every mistake in the reverse sweep.  The
+unmodified oracle passes both files in the main run.
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "pcpic_oracle.c")
+
+pytestmark = pytest.mark.slow
+
+# (what is planted, original text, mutated text)
+FORWARD = [
+    ("sign of the E_z term in the B_phi update (eq. 3)",
+     "k.dtR * st->ez[i]);", "-k.dtR * st->ez[i]);"),
+    ("mirror factor 2 dropped in the E_r update at node N",
+     "st->er[N] = st->er[N] + k.tw * st->b[N - 1];", "st->er[N] = st->er[N] + k.dtdz * st->b[N - 1];"),
+    ("mirror-doubled node-N weight dropped in the Poisson right-hand side",
+     "int64_t wi = (i == N) ? 2 * st->w[i] : st->w[i];", "int64_t wi = st->w[i];"),
+    ("mirror row of the Poisson matrix not doubled",
+     "double a = (i == N) ? 2.0 : 1.0;", "double a = 1.0;"),
+    ("gather between nodes instead of faces",
+     "double s = x - 0.5, E;", "double s = x, E;"),
+    ("move with u instead of v = u / gamma",
+     "        double x1 = x + k.dtdz * v;", "        double x1 = x + k.dtdz * u1;"),
+    ("cumulative weight off by one cell",
+     "if (cell > i) return 0;", "if (cell > i + 1) return 0;"),
+    ("sign of the background term of the surface field",
+     "double es = st->ez[0] - k.fourpi * (t1 - t2);", "double es = st->ez[0] - k.fourpi * (t1 + t2);"),
+    ("whole cell instead of half cell in the node-0 Gauss law",
+     "k->hdz = 0.5 * k->dz;", "k->hdz = k->dz;"),
+    ("frame dragging with eta^2 instead of eta^3 (eq. 7)",
+     "double fd = 1.0 - c->kappa / e3;", "double fd = 1.0 - c->kappa / (eta * eta);"),
+    ("sign of the current term of the E_z update",
+     "st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) - k.c4 * (double)st->j[i];",
+     "st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) + k.c4 * (double)st->j[i];"),
+    ("node-0 weight of a particle in cell 0 taken from the wrong side",
+     "            w0 += k.oneP - F1;", "            w0 += F1;"),
+]
+
+REVERSE = [
+    ("d v / d u taken as 1/gamma instead of 1/gamma^3",
+     "const double lu1t = lu1 + lx1 * k.dtdz / (gam * gam * gam);", "const double lu1t = lu1 + lx1 * k.dtdz / gam;"),
+    ("sign of the deposit's position adjoint",
+     "if (c1 >= 0 && c1 < N) lx1 += twoP * (-k.c4 * wcls * lez[c1]);",
+     "if (c1 >= 0 && c1 < N) lx1 -= twoP * (-k.c4 * wcls * lez[c1]);"),
+    ("kick-array adjoint dropped from the E_z adjoint",
+     "const double a = lez[i] - k.dtR * lbp[i] + k.qmdt * lk[i];", "const double a = lez[i] - k.dtR * lbp[i];"),
+    ("mirror factor dropped in the transposed E_r update",
+     "double c = (i <= N - 1) ? ((i == N - 1) ? 2.0 : 1.0) : 0.0;", "double c = (i <= N - 1) ? 1.0 : 0.0;"),
+    ("E_r neighbour term dropped in the B adjoint",
+     "            if (i + 1 <= N - 1) a += k.dtdz * ler[i + 1];", "            if (i + 1 <= N - 1) a += 0.0 * ler[i + 1];"),
+    ("gather-slope term dropped from the position adjoint",
+     "nlx[p] = lx1 + lx0J + lu1t * dEdx;", "nlx[p] = lx1 + lx0J;"),
+    ("loss seed d gamma / d u replaced by 1 / gamma",
+     "lu1 = nex > 0 ? (u1 / gam) / (double)nex : 0.0;", "lu1 = nex > 0 ? (1.0 / gam) / (double)nex : 0.0;"),
+]
+
+
+def _run_case(tmp, idx, old, new, test_file):
+    with open(SRC) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"mutation anchor not unique or missing: {old}"
+    d = os.path.join(tmp, f"m{idx}")
+    os.makedirs(d, exist_ok=True)
+    msrc = os.path.join(d, "pcpic_oracle.c")
+    with open(msrc, "w") as f:
+        f.write(src.replace(old, new))
+    sys.path.insert(0, ROOT)
+    from oracle import build_oracle
+    lib = build_oracle.build(src=msrc, out=os.path.join(d, "liboracle.so"))
+    env = dict(os.environ, PCPIC_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                        os.path.join(ROOT, "tests", test_file)], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    return r.returncode, r.stdout[-400:]
+
+
+@pytest.mark.parametrize("cases,test_file", [(FORWARD, "test_oracle_pins.py"), (REVERSE, "test_oracle_adjoint.py")],
+                         ids=["forward-step", "reverse-sweep"])
+def test_every_planted_mistake_fails_a_pin(tmp_path, cases, test_file):
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        futs = [ex.submit(_run_case, str(tmp_path), k, old, new, test_file) for k, (_, old, new) in enumerate(cases)]
+        results = [f.result() for f in futs]
+    survivors = [(what, out) for (what, _, _), (rc, out) in zip(cases, results) if rc == 0]
+    assert not survivors, "mistakes no pin catches: " + "; ".join(w for w, _ in survivors)
+    # a failure must come from a failing pin, not from a crash of the child run
+    for (what, _, _), (rc, out) in zip(cases, results):
+        assert rc == 1, f"{what}: child pytest exited with {rc}: {out}"
