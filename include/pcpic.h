@@ -311,6 +311,29 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
 /* Synchronise the stream; PIC_EDEVSTATUS if a status bit is latched. */
 pic_status pic_sync(pic_handle *h);
 
+/* Replay recorded SCLF injection counts (the frozen discrete decisions of
+ * finite-difference checks of the adjoint, sec. 2 injection rule): during steps
+ * [first_step, first_step + n) the number injected is d_counts[step - first_step]
+ * (clipped to the free capacity, which latches PIC_ST_CAPACITY) instead of
+ * floor(E_surf / (4 pi q_m)).  d_counts is device memory owned by the caller and
+ * must stay valid while the schedule is set; n = 0 clears it.  Single tubes
+ * only (PIC_ESTATE for a batch or its tubes); pic_run_adjoint honours it too. */
+pic_status pic_set_injection_schedule(pic_handle *h, const int64_t *d_counts, int64_t first_step, int64_t n);
+
+/* Checkpoint of a tube's state in caller-provided host memory: completed steps,
+ * device counters, E_z, E_r, B_phi, the last step's current and the occupied
+ * particle slots.  With buf == NULL only *bytes (the size needed) is set;
+ * otherwise cap must be >= that size.  Synchronises the tube's stream.  A tube of
+ * a batch can be saved through its pic_batch_tube handle. */
+pic_status pic_save(pic_handle *h, void *buf, size_t cap, size_t *bytes);
+
+/* Restore a pic_save state into a single tube created with the same parameters
+ * (capacity may differ if the slots fit).  Stepping afterwards continues
+ * bit for bit as the saved tube would have.  Errors: PIC_EINVAL for another
+ * tube's parameters or a damaged buffer, PIC_ECAPACITY if the slots do not fit,
+ * PIC_ESTATE for a batch or its tubes.  Synchronises the stream. */
+pic_status pic_load(pic_handle *h, const void *buf, size_t bytes);
+
 /* Release the handle (the caller still owns workspace and stream). */
 pic_status pic_destroy(pic_handle *h);
 

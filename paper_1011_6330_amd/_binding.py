@@ -107,6 +107,9 @@ SIGNATURES = {
     "pic_batch_get_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                               ctypes.POINTER(ctypes.c_int64)]),
+    "pic_set_injection_schedule": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]),
+    "pic_save": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "pic_load": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "pic_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
 }
 
@@ -190,6 +193,15 @@ class _TubeOps:
                                    u.ctypes.data_as(ctypes.c_void_p), 0), "pic_inject")
 
 
+    def save(self):
+        """The tube's state as bytes (pic_save)."""
+        n = ctypes.c_size_t(0)
+        _check(self.lib.pic_save(self._h, None, 0, ctypes.byref(n)), "pic_save")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self.lib.pic_save(self._h, buf, n.value, ctypes.byref(n)), "pic_save")
+        return buf.raw[:n.value]
+
+
 class Tube(_TubeOps):
     """One tube on the GPU.  The workspace is a torch uint8 tensor on ``device``
     and all work is ordered on ``stream`` (a torch.cuda.Stream, created at the
@@ -219,6 +231,26 @@ class Tube(_TubeOps):
         t = PicTiming()
         _check(self.lib.pic_step_timed(self._h, int(n), ctypes.byref(t)), "pic_step_timed")
         return {k: getattr(t, k) for k, _ in PicTiming._fields_}
+
+    def load(self, state):
+        """Restore a state from save() into this tube (same parameters)."""
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        _check(self.lib.pic_load(self._h, buf, len(state)), "pic_load")
+
+    def set_injection_schedule(self, counts, first_step=0):
+        """Replay injection counts (host or CUDA int64) from step first_step on;
+        None clears the schedule."""
+        import torch
+        if counts is None or len(counts) == 0:
+            self._sched = None
+            _check(self.lib.pic_set_injection_schedule(self._h, None, 0, 0), "pic_set_injection_schedule")
+            return
+        d = torch.as_tensor(np.asarray(counts, np.int64) if not isinstance(counts, torch.Tensor) else counts,
+                            dtype=torch.int64).to(self.device).contiguous()
+        torch.cuda.synchronize(self.device)
+        self._sched = d                      # keep the device array alive while it is set
+        _check(self.lib.pic_set_injection_schedule(self._h, ctypes.c_void_p(d.data_ptr()), int(first_step),
+                                                   d.numel()), "pic_set_injection_schedule")
 
     def set_push_config(self, block, per_thread, nontemporal=False):
         _check(self.lib.pic_set_push_config(self._h, int(block), int(per_thread), 1 if nontemporal else 0),

@@ -19,6 +19,9 @@ struct FieldArgs {
     int *CL;                        // FP32-bulk: low stream of the current buffer
     float *OL, *UL;
     DevCounters *ctr;
+    const int64_t *sched = nullptr;   // recorded injection counts (device), replayed for
+    int64_t sched_first = 0;          // steps [sched_first, sched_first + sched_n)
+    int64_t sched_n = 0;
 };
 
 // Leap-frog update of eq. (3) for the faces [tile*bs, tile*bs + bs), one thread
@@ -74,7 +77,13 @@ __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, 
         const double t2 = c.rho0 * c.hdz;
         const double es = s_ez0 - c.fourpi * (t1 - t2);
         int64_t ninj = 0;
-        if (!(c.flags & PIC_NO_AUTO_INJECT)) {
+        const int64_t ks = ctr->step - a.sched_first;   // index of this step in a replayed schedule
+        if (a.sched && ks >= 0 && ks < a.sched_n) {
+            const int64_t want = a.sched[ks] > 0 ? a.sched[ks] : 0;
+            const int64_t avail = c.cap - slots;
+            ninj = want > avail ? avail : want;
+            if (want > avail) atomicOr(&ctr->status, (unsigned long long)PIC_ST_CAPACITY);
+        } else if (!(c.flags & PIC_NO_AUTO_INJECT)) {
             const double ratio = es / c.fqm;
             if (ratio > 0.0) {
                 const double nf = floor(ratio);

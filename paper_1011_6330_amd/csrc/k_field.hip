@@ -240,7 +240,8 @@ hipError_t launch_field_inject(pic_handle *h)
     const int b = h->pbuf;
     FieldArgs a{w.ez[f], w.er[f], w.b[f], w.ez[g], w.er[g], w.b[g], w.j[h->jbuf], w.j[1 - h->jbuf],
                 w.k64, f32 ? w.k32 : nullptr, f32 ? nullptr : w.x[b], f32 ? nullptr : w.u[b],
-                f32 ? w.cl[b] : nullptr, f32 ? w.ol[b] : nullptr, f32 ? w.ul[b] : nullptr, w.ctr};
+                f32 ? w.cl[b] : nullptr, f32 ? w.ol[b] : nullptr, f32 ? w.ul[b] : nullptr, w.ctr,
+                h->d_sched, h->sched_first, h->sched_n};
     hipLaunchKernelGGL(k_field_inject, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, a);
     return hipGetLastError();
 }
@@ -252,7 +253,7 @@ hipError_t launch_field_ptrs(pic_handle *h, const double *ezo, const double *ero
 {
     Workspace &w = h->ws;
     FieldArgs a{ezo, ero, bo, ezn, ern, bn, w.j[h->jbuf], w.j[1 - h->jbuf], w.k64, nullptr, X, U,
-                nullptr, nullptr, nullptr, w.ctr};
+                nullptr, nullptr, nullptr, w.ctr, h->d_sched, h->sched_first, h->sched_n};
     hipLaunchKernelGGL(k_field_inject, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c, a);
     return hipGetLastError();
 }

@@ -181,6 +181,8 @@ struct pic_handle {
     int push_nt = 1;    // nontemporal particle-stream access
     double u_hi = 0.0;  // FP32-bulk: |u| from which a particle belongs to the FP64 stream
     int push_grid = 0;  // 0 = derived from the device
+    const int64_t *d_sched = nullptr;   // replayed injection counts (caller's device array)
+    int64_t sched_first = 0, sched_n = 0;
     int n_cu = 256;
     // batch (ensemble) handles
     bool is_batch = false;

@@ -625,6 +625,203 @@ pic_status pic_write_fields(pic_handle *h, const double *ez, const double *er, c
     return PIC_OK;
 }
 
+pic_status pic_set_injection_schedule(pic_handle *h, const int64_t *d_counts, int64_t first_step, int64_t n)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (h->is_batch || h->parent) return fail(PIC_ESTATE, "injection schedules are for single tubes");
+    if (n < 0 || first_step < 0 || (n > 0 && !d_counts)) return fail(PIC_EINVAL, "bad schedule arguments");
+    h->d_sched = n > 0 ? d_counts : nullptr;
+    h->sched_first = first_step;
+    h->sched_n = n;
+    return PIC_OK;
+}
+
+// ---- save / load --------------------------------------------------------
+//
+// Blob: header, knot values, device counters, E_z, E_r, B_phi, last-step J,
+// then the occupied slots of the current particle buffer(s).  Sections are
+// 8-byte aligned.  Loading writes into the target's current buffers, so the
+// blob does not depend on buffer parities.
+
+}  // extern "C"
+
+namespace {
+
+constexpr char SAVE_MAGIC[8] = {'P', 'C', 'P', 'I', 'C', 'S', 'V', '1'};
+
+struct SaveHead {
+    char magic[8];
+    int32_t abi, precision;
+    int64_t n_cells, n_knots, n_lo, n_hi, step, total_bytes;
+    int32_t rho_kind, fp_bits;
+    double length, radius, dt_over_dz, q_over_m, ppc, rho_amp, kappa, r_star, gamma_fp64, macro_charge;
+};
+
+size_t pad8(size_t b) { return (b + 7) & ~(size_t)7; }
+
+struct SaveLayout {
+    size_t knots, ctr, ez, er, b, j, p[6], total;
+};
+
+SaveLayout save_layout(int64_t N, int64_t nk, int64_t nlo, int64_t nhi, bool f32)
+{
+    SaveLayout L{};
+    size_t off = pad8(sizeof(SaveHead));
+    auto take = [&](size_t bytes) { const size_t o = off; off = pad8(off + bytes); return o; };
+    L.knots = take((size_t)nk * 8);
+    L.ctr = take(sizeof(DevCounters));
+    L.ez = take((size_t)N * 8);
+    L.er = take((size_t)(N + 1) * 8);
+    L.b = take((size_t)N * 8);
+    L.j = take((size_t)N * 8);
+    if (!f32) {
+        L.p[0] = take((size_t)nlo * 8);   // x
+        L.p[1] = take((size_t)nlo * 8);   // u
+    } else {
+        L.p[0] = take((size_t)nlo * 4);   // low: cell, offset, u f32
+        L.p[1] = take((size_t)nlo * 4);
+        L.p[2] = take((size_t)nlo * 4);
+        L.p[3] = take((size_t)nhi * 4);   // high: cell, offset, u f64
+        L.p[4] = take((size_t)nhi * 4);
+        L.p[5] = take((size_t)nhi * 8);
+    }
+    L.total = off;
+    return L;
+}
+
+void fill_head(const pic_handle *h, SaveHead *hd)
+{
+    memset(hd, 0, sizeof *hd);
+    memcpy(hd->magic, SAVE_MAGIC, 8);
+    const pic_params &p = h->p;
+    hd->abi = PCPIC_ABI_VERSION;
+    hd->precision = p.precision;
+    hd->n_cells = p.n_cells;
+    hd->n_knots = (int64_t)h->knots.size();
+    hd->rho_kind = p.rho_kind;
+    hd->fp_bits = p.fp_bits;
+    hd->length = p.length;
+    hd->radius = p.radius;
+    hd->dt_over_dz = p.dt_over_dz;
+    hd->q_over_m = p.q_over_m;
+    hd->ppc = p.ppc;
+    hd->rho_amp = p.rho_amp;
+    hd->kappa = p.kappa;
+    hd->r_star = p.r_star;
+    hd->gamma_fp64 = p.gamma_fp64;
+    hd->macro_charge = p.macro_charge;
+}
+
+}  // namespace
+
+extern "C" {
+
+pic_status pic_save(pic_handle *h, void *buf, size_t cap, size_t *bytes)
+{
+    if (!h || !bytes) return fail(PIC_EINVAL, "handle or bytes is NULL");
+    if (h->is_batch) return fail(PIC_EINVAL, "save the tubes of a batch one by one (pic_batch_tube)");
+    DevCounters ctr;
+    pic_status s = read_counters(h, &ctr);
+    if (s != PIC_OK) return s;
+    const bool f32 = h->p.precision == PIC_FP32_BULK;
+    const int64_t N = h->c.N, nlo = ctr.n_slots, nhi = f32 ? ctr.n_slots_hi : 0;
+    const SaveLayout L = save_layout(N, (int64_t)h->knots.size(), nlo, nhi, f32);
+    *bytes = L.total;
+    if (!buf) return PIC_OK;
+    if (cap < L.total) return fail(PIC_EINVAL, "buffer of %zu bytes, %zu needed", cap, L.total);
+    uint8_t *o = (uint8_t *)buf;
+    SaveHead hd;
+    fill_head(h, &hd);
+    hd.n_lo = nlo;
+    hd.n_hi = nhi;
+    hd.step = h->step;
+    hd.total_bytes = (int64_t)L.total;
+    memcpy(o, &hd, sizeof hd);
+    if (!h->knots.empty()) memcpy(o + L.knots, h->knots.data(), h->knots.size() * 8);
+    memcpy(o + L.ctr, &ctr, sizeof ctr);
+    const Workspace &w = h->ws;
+    const int f = h->fbuf, b = h->pbuf;
+    auto d2h = [&](size_t at, const void *src, size_t n) {
+        return n ? hipMemcpyAsync(o + at, src, n, hipMemcpyDeviceToHost, h->stream) : hipSuccess;
+    };
+    HIP_OK(d2h(L.ez, w.ez[f], (size_t)N * 8));
+    HIP_OK(d2h(L.er, w.er[f], (size_t)(N + 1) * 8));
+    HIP_OK(d2h(L.b, w.b[f], (size_t)N * 8));
+    HIP_OK(d2h(L.j, w.j[1 - h->jbuf], (size_t)N * 8));
+    if (!f32) {
+        HIP_OK(d2h(L.p[0], w.x[b], (size_t)nlo * 8));
+        HIP_OK(d2h(L.p[1], w.u[b], (size_t)nlo * 8));
+    } else {
+        HIP_OK(d2h(L.p[0], w.cl[b], (size_t)nlo * 4));
+        HIP_OK(d2h(L.p[1], w.ol[b], (size_t)nlo * 4));
+        HIP_OK(d2h(L.p[2], w.ul[b], (size_t)nlo * 4));
+        HIP_OK(d2h(L.p[3], w.ch[b], (size_t)nhi * 4));
+        HIP_OK(d2h(L.p[4], w.oh[b], (size_t)nhi * 4));
+        HIP_OK(d2h(L.p[5], w.uh[b], (size_t)nhi * 8));
+    }
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+pic_status pic_load(pic_handle *h, const void *buf, size_t bytes)
+{
+    if (!h || !buf) return fail(PIC_EINVAL, "handle or buffer is NULL");
+    if (h->is_batch || h->parent) return fail(PIC_ESTATE, "load into a single tube (not a batch or its tubes)");
+    if (bytes < sizeof(SaveHead)) return fail(PIC_EINVAL, "buffer too small for a saved state");
+    SaveHead hd, mine;
+    memcpy(&hd, buf, sizeof hd);
+    fill_head(h, &mine);
+    if (memcmp(hd.magic, SAVE_MAGIC, 8) != 0) return fail(PIC_EINVAL, "not a saved tube state");
+    if (hd.abi != mine.abi) return fail(PIC_EABI, "saved with ABI version %d", hd.abi);
+    const bool same = hd.precision == mine.precision && hd.n_cells == mine.n_cells && hd.n_knots == mine.n_knots &&
+                      hd.rho_kind == mine.rho_kind && hd.fp_bits == mine.fp_bits && hd.length == mine.length &&
+                      hd.radius == mine.radius && hd.dt_over_dz == mine.dt_over_dz && hd.q_over_m == mine.q_over_m &&
+                      hd.ppc == mine.ppc && hd.rho_amp == mine.rho_amp && hd.kappa == mine.kappa &&
+                      hd.r_star == mine.r_star && hd.gamma_fp64 == mine.gamma_fp64 &&
+                      hd.macro_charge == mine.macro_charge;
+    if (!same) return fail(PIC_EINVAL, "the saved tube has different parameters");
+    const bool f32 = h->p.precision == PIC_FP32_BULK;
+    const int64_t N = h->c.N;
+    if (hd.n_lo < 0 || hd.n_hi < 0 || hd.n_lo > h->c.cap || hd.n_hi > h->c.cap || (!f32 && hd.n_hi != 0))
+        return fail(PIC_ECAPACITY, "saved state holds %lld + %lld slots, capacity %lld", (long long)hd.n_lo,
+                    (long long)hd.n_hi, (long long)h->c.cap);
+    const SaveLayout L = save_layout(N, hd.n_knots, hd.n_lo, hd.n_hi, f32);
+    if ((int64_t)L.total != hd.total_bytes || bytes < L.total) return fail(PIC_EINVAL, "truncated saved state");
+    const uint8_t *in = (const uint8_t *)buf;
+    if (hd.n_knots > 0 && memcmp(in + L.knots, h->knots.data(), (size_t)hd.n_knots * 8) != 0)
+        return fail(PIC_EINVAL, "the saved tube has different knot values");
+    DevCounters ctr;
+    memcpy(&ctr, in + L.ctr, sizeof ctr);
+    if (ctr.n_slots != hd.n_lo || (f32 && ctr.n_slots_hi != hd.n_hi))
+        return fail(PIC_EINVAL, "inconsistent saved state");
+    const Workspace &w = h->ws;
+    const int f = h->fbuf, b = h->pbuf;
+    auto h2d = [&](void *dst, size_t at, size_t n) {
+        return n ? hipMemcpyAsync(dst, in + at, n, hipMemcpyHostToDevice, h->stream) : hipSuccess;
+    };
+    HIP_OK(h2d(w.ez[f], L.ez, (size_t)N * 8));
+    HIP_OK(h2d(w.er[f], L.er, (size_t)(N + 1) * 8));
+    HIP_OK(h2d(w.b[f], L.b, (size_t)N * 8));
+    HIP_OK(h2d(w.j[1 - h->jbuf], L.j, (size_t)N * 8));
+    HIP_OK(launch_zero_i64(h, w.j[h->jbuf], N));        // the next step deposits into a cleared J
+    if (!f32) {
+        HIP_OK(h2d(w.x[b], L.p[0], (size_t)hd.n_lo * 8));
+        HIP_OK(h2d(w.u[b], L.p[1], (size_t)hd.n_lo * 8));
+    } else {
+        HIP_OK(h2d(w.cl[b], L.p[0], (size_t)hd.n_lo * 4));
+        HIP_OK(h2d(w.ol[b], L.p[1], (size_t)hd.n_lo * 4));
+        HIP_OK(h2d(w.ul[b], L.p[2], (size_t)hd.n_lo * 4));
+        HIP_OK(h2d(w.ch[b], L.p[3], (size_t)hd.n_hi * 4));
+        HIP_OK(h2d(w.oh[b], L.p[4], (size_t)hd.n_hi * 4));
+        HIP_OK(h2d(w.uh[b], L.p[5], (size_t)hd.n_hi * 8));
+    }
+    HIP_OK(hipMemcpyAsync(w.ctr, &ctr, sizeof ctr, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(launch_kick(h));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    h->step = hd.step;
+    return PIC_OK;
+}
+
 pic_status pic_destroy(pic_handle *h)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");

@@ -181,3 +181,27 @@ def test_fp32_uniform_field_test_particle():
     assert u[0] == o.u[0] == 398.5 * 10.0 / 1024
     assert abs(x[0] - o.x[0]) <= 1e-6 * o.x[0]
     g.close()
+
+
+def test_fp32_c5_gauss_drift():
+    """The large tube (2^20 cells, 2.5e8 particles) in FP32-bulk for 200 steps:
+    the Gauss residual, evaluated in FP64, stays within the bound of the t = 0
+    solve plus the rounding random walk of the field updates,
+    10 eps (R/dz)^2 + 10 eps (R/dz) sqrt(n)."""
+    from paper_1011_6330_amd import Tube
+    cfg = synth.preset("c5")
+    say("fp32 c5: warm start")
+    x, u = synth.warm_start(cfg)
+    t = Tube(dict(synth.tube_params(cfg), precision=1))
+    t.inject(x, u)
+    del x, u
+    eps = np.finfo(np.float64).eps
+    r_dz = cfg["radius"] / (cfg["length"] / cfg["n_cells"])
+    for n in (100, 200):
+        t.step(100)
+        d = t.diagnostics(fields=False, gauss=True)
+        bound = 10 * eps * r_dz ** 2 + 10 * eps * r_dz * np.sqrt(n)
+        say("fp32 c5 step", n, "gauss", d["gauss_max"], "bound", bound, "high", d["n_slots_high"])
+        assert d["gauss_max"] <= bound
+        assert d["n_alive"] > 2.4e8
+    t.close()

@@ -212,3 +212,55 @@ def test_c2_full_size_first_steps():
     o.step(3)
     d = assert_state_equal(g, o, what="c2 full size")
     assert d["n_alive"] > 3.9e7
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_save_load_resumes_bit_for_bit(precision):
+    """P11: a tube restored from pic_save continues exactly as the saved one
+    (fields, last-step current, counters, particle slots), across sorts."""
+    from paper_1011_6330_amd import PicError, Tube
+    N = 2048
+    cfg = dict(synth.preset("c2"), n_cells=N, q_over_m=synth.q_over_m_for(300.0), ppc=30.0,
+               warm=30 * N, capacity=int(30 * N * 1.3), sort_every=16, precision=precision, gamma_fp64=2000.0)
+    x, u = synth.warm_start(cfg)
+    say("save/load precision", precision)
+    a = Tube(synth.tube_params(cfg))
+    a.inject(x, u)
+    a.step(37)
+    state = a.save()
+    a.step(100)
+    b = Tube(synth.tube_params(dict(cfg, capacity=int(30 * N * 1.5))))   # more room: the slots still fit
+    b.load(state)
+    b.step(100)
+    da, db = a.diagnostics(fields=True, j=True), b.diagnostics(fields=True, j=True)
+    for k in ("ez", "er", "b_phi", "j_last"):
+        assert np.array_equal(da[k], db[k]), k
+    for k in ("step", "n_alive", "n_slots", "n_injected", "n_exit", "n_absorb", "exit_sum_lo", "exit_sum_hi",
+              "e_surf", "w0", "n_slots_high"):
+        assert da[k] == db[k], k
+    xa, ua = a.read_particles()
+    xb, ub = b.read_particles()
+    ka, kb = np.lexsort((ua, xa)), np.lexsort((ub, xb))   # the sort may order equal keys differently
+    assert np.array_equal(xa[ka], xb[kb]) and np.array_equal(ua[ka], ub[kb])
+    # another tube's parameters are refused
+    c = Tube(synth.tube_params(dict(cfg, kappa=0.1)))
+    with pytest.raises(PicError):
+        c.load(state)
+    for t in (a, b, c):
+        t.close()
+
+
+def test_c5_full_size_first_steps():
+    """The large tube at full size (2^20 cells, L = 100R, 2.5e8 particles): two
+    steps bit-identical to the oracle, sorted like the benchmark runs it."""
+    cfg = synth.preset("c5")
+    say("c5: warm start of", cfg["warm"], "particles")
+    x, u = synth.warm_start(cfg)
+    g, o = make_pair(cfg, x, u)
+    del x, u
+    say("c5: stepping")
+    g.step(2)
+    o.step(2)
+    d = assert_state_equal(g, o, what="c5 full size")
+    assert d["n_alive"] > 2.4e8
+    g.close()
