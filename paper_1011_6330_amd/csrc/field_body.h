@@ -22,6 +22,8 @@ struct FieldArgs {
     const int64_t *sched = nullptr;   // recorded injection counts (device), replayed for
     int64_t sched_first = 0;          // steps [sched_first, sched_first + sched_n)
     int64_t sched_n = 0;
+    unsigned long long *hist = nullptr;   // step before a sort: key counts (injected particles added)
+    int64_t inj_key = 0;                  // sort key of a particle injected at x = 0, u = 0
 };
 
 // Leap-frog update of eq. (3) for the faces [tile*bs, tile*bs + bs), one thread
@@ -96,6 +98,7 @@ __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, 
                 }
             }
         }
+        if (a.hist && ninj > 0) atomicAdd(a.hist + a.inj_key, (unsigned long long)ninj);
         s_base = slots;
         s_n = ninj;
         ctr->n_slots = slots + ninj;

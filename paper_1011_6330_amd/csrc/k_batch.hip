@@ -99,12 +99,16 @@ struct BSortArgs {
     int src, dst;                // particle buffer parity before / after
 };
 
+// One block per scan block of SORT_SCAN_TILE keys (a block never spans two tubes).
 __global__ __launch_bounds__(256) void k_bsort_clear(BSortArgs a)
 {
-    const int64_t total = a.key_pref[a.n_tubes];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-        const int t = find_tube(a.key_pref, a.n_tubes, i);
-        a.tubes[t].cell_count[i - a.key_pref[t]] = 0;
+    const int t = find_tube(a.scan_pref, a.n_tubes, blockIdx.x);
+    const TubeDev &T = a.tubes[t];
+    const int64_t base = (blockIdx.x - a.scan_pref[t]) * SORT_SCAN_TILE;
+#pragma unroll
+    for (int k = 0; k < SORT_SCAN_TILE / 256; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        if (i < T.n_keys) T.cell_count[i] = 0;
     }
 }
 
@@ -117,10 +121,11 @@ __device__ __forceinline__ bool chunk_slot(const TubeDev &T, int f32, int64_t lo
     return hi;
 }
 
+// One block per chunk of 256 slots of one stream of one tube.
 __global__ __launch_bounds__(256) void k_bsort_hist(BSortArgs a)
 {
-    const int64_t total = a.chunk_pref[a.n_tubes];
-    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int64_t it = blockIdx.x;
+    {
         const int t = find_tube(a.chunk_pref, a.n_tubes, it);
         const TubeDev &T = a.tubes[t];
         int64_t p, n;
@@ -232,9 +237,9 @@ __global__ __launch_bounds__(256) void k_bscan_apply(BSortArgs a)
 
 __global__ __launch_bounds__(256) void k_bsort_scatter(BSortArgs a)
 {
-    const int64_t total = a.chunk_pref[a.n_tubes];
     const int lane = __lane_id();
-    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int64_t it = blockIdx.x;
+    {
         const int t = find_tube(a.chunk_pref, a.n_tubes, it);
         const TubeDev &T = a.tubes[t];
         int64_t p, n;
@@ -416,8 +421,9 @@ hipError_t launch_batch_sort(pic_handle *h)
                 t0->p.precision == PIC_FP32_BULK ? 1 : 0, t0->pbuf, 1 - t0->pbuf};
     if (h->batch_scan_blocks <= 0 || h->batch_scan_blocks > 0x7fffffff) return hipErrorInvalidValue;
     const unsigned sb = (unsigned)h->batch_scan_blocks;
-    const unsigned g = (unsigned)(h->n_cu * 8);
-    hipLaunchKernelGGL(k_bsort_clear, dim3(g), dim3(256), 0, h->stream, a);
+    if (h->batch_sort_items <= 0 || h->batch_sort_items > 0x7fffffff) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)h->batch_sort_items;   // one block per chunk of 256 slots
+    hipLaunchKernelGGL(k_bsort_clear, dim3(sb), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bsort_hist, dim3(g), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bscan_totals, dim3(sb), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bscan_blocks, dim3(nt), dim3(256), 0, h->stream, a);

@@ -241,7 +241,9 @@ hipError_t launch_field_inject(pic_handle *h)
     FieldArgs a{w.ez[f], w.er[f], w.b[f], w.ez[g], w.er[g], w.b[g], w.j[h->jbuf], w.j[1 - h->jbuf],
                 w.k64, f32 ? w.k32 : nullptr, f32 ? nullptr : w.x[b], f32 ? nullptr : w.u[b],
                 f32 ? w.cl[b] : nullptr, f32 ? w.ol[b] : nullptr, f32 ? w.ul[b] : nullptr, w.ctr,
-                h->d_sched, h->sched_first, h->sched_n};
+                h->d_sched, h->sched_first, h->sched_n,
+                h->hist_on ? (unsigned long long *)w.cell_count : nullptr,
+                f32 && 0.0 >= h->u_hi ? sort_low_keys(c) : 0};
     hipLaunchKernelGGL(k_field_inject, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, a);
     return hipGetLastError();
 }

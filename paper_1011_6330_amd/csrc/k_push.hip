@@ -31,7 +31,8 @@ template <int BLOCK, int PPT, int NT>
 static hipError_t launch_push_t(pic_handle *h)
 {
     PushArgs a{h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.k64,
-               (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr};
+               (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr,
+               h->hist_on ? (unsigned long long *)h->ws.cell_count : nullptr};
     const int64_t tile = (int64_t)BLOCK * PPT;
     const unsigned grid = (unsigned)((h->c.cap + tile - 1) / tile);
     hipLaunchKernelGGL((k_push_f64<BLOCK, PPT, NT>), dim3(grid), dim3(BLOCK), 0, h->stream, h->c, a);

@@ -274,7 +274,8 @@ static hipError_t launch_push32_t(pic_handle *h)
     const int64_t tile = (int64_t)BLOCK * 4;
     const unsigned nb = (unsigned)((h->c.cap + tile - 1) / tile);
     Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b], w.k32, w.k64,
-                 (unsigned long long *)w.j[h->jbuf], w.ctr, nb};
+                 (unsigned long long *)w.j[h->jbuf], w.ctr, nb,
+                 h->hist_on ? (unsigned long long *)w.cell_count : nullptr, h->u_hi};
     hipLaunchKernelGGL((k_push_f32<BLOCK, NT>), dim3(2 * nb), dim3(BLOCK), 0, h->stream, h->c, a);
     return hipGetLastError();
 }

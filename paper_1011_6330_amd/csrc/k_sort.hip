@@ -154,21 +154,31 @@ hipError_t launch_scan(pic_handle *h, int64_t n)
 
 // Counting sort by cell into the other particle buffer, dropping removed slots;
 // in FP32-bulk mode the destination stream follows the particle's gamma.
-hipError_t launch_sort(pic_handle *h)
+// Zero the key counts before a step that accumulates them (the step before a sort).
+hipError_t launch_clear_hist(pic_handle *h)
+{
+    const int64_t nkeys = sort_key_count(h->c, h->p.precision == PIC_FP32_BULK);
+    hipLaunchKernelGGL(k_fill_ll, dim3((unsigned)((nkeys + 255) / 256)), dim3(256), 0, h->stream, h->ws.cell_count,
+                       nkeys);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(pic_handle *h, bool hist_ready)
 {
     const Consts &c = h->c;
     Workspace &w = h->ws;
     const bool f32 = h->p.precision == PIC_FP32_BULK;
     const int64_t nkeys = sort_key_count(c, f32);
     const int src = h->pbuf, dst = 1 - h->pbuf;
-    hipLaunchKernelGGL(k_fill_ll, dim3((unsigned)((nkeys + 255) / 256)), dim3(256), 0, h->stream, w.cell_count, nkeys);
     hipError_t e;
+    if (!hist_ready && (e = launch_clear_hist(h)) != hipSuccess) return e;
     if (f32) {
-        if ((e = launch_sort32_hist(h)) != hipSuccess) return e;
+        if (!hist_ready && (e = launch_sort32_hist(h)) != hipSuccess) return e;
         if ((e = launch_scan(h, nkeys)) != hipSuccess) return e;
         if ((e = launch_sort32_scatter(h)) != hipSuccess) return e;
     } else {
-        hipLaunchKernelGGL(k_hist, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.ctr, w.cell_count);
+        if (!hist_ready)
+            hipLaunchKernelGGL(k_hist, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.ctr, w.cell_count);
         if ((e = launch_scan(h, nkeys)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_scatter, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.u[src], w.x[dst],
                            w.u[dst], w.ctr, (unsigned long long *)w.cell_off);

@@ -183,6 +183,7 @@ struct pic_handle {
     int push_grid = 0;  // 0 = derived from the device
     const int64_t *d_sched = nullptr;   // replayed injection counts (caller's device array)
     int64_t sched_first = 0, sched_n = 0;
+    bool hist_on = false;               // this step also counts the sort keys (a sort follows)
     int n_cu = 256;
     // batch (ensemble) handles
     bool is_batch = false;
@@ -233,7 +234,9 @@ hipError_t launch_commit_append(pic_handle *h, int64_t n);
 hipError_t launch_kick(pic_handle *h);
 hipError_t launch_gauss(pic_handle *h);
 hipError_t launch_profile(pic_handle *h, int n_bins);
-hipError_t launch_sort(pic_handle *h);
+// Counting sort; hist_ready = the key counts were accumulated by the step before.
+hipError_t launch_sort(pic_handle *h, bool hist_ready);
+hipError_t launch_clear_hist(pic_handle *h);
 
 // Goldreich-Julian density at node i (eqs. 5-7; the three kinds are listed in
 // pcpic.h).  Used by the device fill and, at node 0, by the host to fix the

@@ -355,12 +355,17 @@ pic_status pic_step(pic_handle *h, int64_t n_steps)
     if (h->parent) return fail(PIC_ESTATE, "a tube of a batch is stepped through its batch handle");
     if (h->is_batch) return batch_advance(h, n_steps, nullptr, nullptr);
     for (int64_t s = 0; s < n_steps; ++s) {
-        HIP_OK(launch_push(h));
-        HIP_OK(launch_field_inject(h));
+        const bool sort_after = h->p.sort_every > 0 && (h->step + 1) % h->p.sort_every == 0;
+        if (sort_after) HIP_OK(launch_clear_hist(h));
+        h->hist_on = sort_after;            // the step counts the sort keys of its survivors
+        hipError_t e1 = launch_push(h);
+        hipError_t e2 = e1 == hipSuccess ? launch_field_inject(h) : e1;
+        h->hist_on = false;
+        HIP_OK(e2);
         h->fbuf ^= 1;
         h->jbuf ^= 1;
         h->step += 1;
-        if (h->p.sort_every > 0 && h->step % h->p.sort_every == 0) HIP_OK(launch_sort(h));
+        if (sort_after) HIP_OK(launch_sort(h, true));
     }
     return PIC_OK;
 }
@@ -411,20 +416,22 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
     int64_t slots = ctr.n_slots + ctr.n_slots_hi;
     for (int64_t s = 0; s < n_steps && rc == PIC_OK; ++s) {
         hipEvent_t *e = &ev[(size_t)s * 4];
-        bool sorted = false;
-        if (hipEventRecord(e[0], h->stream) != hipSuccess || launch_push(h) != hipSuccess ||
-            hipEventRecord(e[1], h->stream) != hipSuccess || launch_field_inject(h) != hipSuccess ||
-            hipEventRecord(e[2], h->stream) != hipSuccess) {
+        const bool sort_after = h->p.sort_every > 0 && (h->step + 1) % h->p.sort_every == 0;
+        if (sort_after && launch_clear_hist(h) != hipSuccess) { rc = fail(PIC_EDEVICE, "clear launch failed"); break; }
+        h->hist_on = sort_after;
+        const bool ok = hipEventRecord(e[0], h->stream) == hipSuccess && launch_push(h) == hipSuccess &&
+                        hipEventRecord(e[1], h->stream) == hipSuccess && launch_field_inject(h) == hipSuccess &&
+                        hipEventRecord(e[2], h->stream) == hipSuccess;
+        h->hist_on = false;
+        if (!ok) {
             rc = fail(PIC_EDEVICE, "launch failed in pic_step_timed");
             break;
         }
         h->fbuf ^= 1;
         h->jbuf ^= 1;
         h->step += 1;
-        if (h->p.sort_every > 0 && h->step % h->p.sort_every == 0) {
-            if (launch_sort(h) != hipSuccess) { rc = fail(PIC_EDEVICE, "sort launch failed"); break; }
-            sorted = true;
-        }
+        const bool sorted = sort_after;
+        if (sort_after && launch_sort(h, true) != hipSuccess) { rc = fail(PIC_EDEVICE, "sort launch failed"); break; }
         if (hipEventRecord(e[3], h->stream) != hipSuccess) { rc = fail(PIC_EDEVICE, "event record failed"); break; }
         slots_before[(size_t)s] = sorted ? -1 : 0;
     }

@@ -18,7 +18,20 @@ struct PushArgs {
     const double *__restrict__ K;
     unsigned long long *__restrict__ J;
     DevCounters *ctr;
+    unsigned long long *hist;       // non-null on the step before a sort: key counts of the survivors
 };
+
+// Add the sort keys of a tile's surviving particles to hist (one atomic per run
+// of equal keys across the lanes, for each of a thread's PPT slots).
+template <int PPT>
+__device__ __forceinline__ void hist_add(unsigned long long *hist, const int64_t (&key)[PPT], const bool (&live)[PPT])
+{
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const WaveRun r = wave_runs(key[k], live[k]);
+        if (live[k] && r.is_head) atomicAdd(hist + key[k], (unsigned long long)(r.end - (int)__lane_id()));
+    }
+}
 
 // One tile of BLOCK*PPT consecutive slots starting at tile0 (< n).  Called by
 // every thread of a block of BLOCK threads; wave-collective at the end.
@@ -109,6 +122,16 @@ __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a
             }
         }
     }
+    if (a.hist) {
+        int64_t key[PPT];
+        bool live[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            live[k] = xs[k] >= 0.0;
+            key[k] = live[k] ? sort_key_f64(c, xs[k]) : 0;
+        }
+        hist_add<PPT>(a.hist, key, live);
+    }
     acc.flush(a.J, a.ctr);
 }
 
@@ -125,6 +148,8 @@ struct Push32Args {
     unsigned long long *__restrict__ J;
     DevCounters *ctr;
     unsigned blocks_lo;     // grid blocks [0, blocks_lo) serve the low stream
+    unsigned long long *hist = nullptr;   // non-null on the step before a sort: key counts of the survivors
+    double u_hi = 0.0;                    // |u| from which a particle belongs to the high stream
 };
 
 // Offset update with the carry into the next or previous cell (|move| < 1 cell).
@@ -234,6 +259,16 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
             for (int k = 0; k < PPT; ++k)
                 if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UL[p0 + k] = us[k]; }
         }
+        if (a.hist) {
+            int64_t key[PPT];
+            bool live[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                live[k] = cs[k] >= 0;
+                key[k] = live[k] ? sort_key_f32(c, cs[k], os[k], fabs((double)us[k]) >= a.u_hi) : 0;
+            }
+            hist_add<PPT>(a.hist, key, live);
+        }
     } else {
         // ---------------- high stream: FP64 momentum ----------------
         double us[PPT];
@@ -303,6 +338,16 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
                 if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UH[p0 + k] = us[k]; }
+        }
+        if (a.hist) {
+            int64_t key[PPT];
+            bool live[PPT];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                live[k] = cs[k] >= 0;
+                key[k] = live[k] ? sort_key_f32(c, cs[k], os[k], fabs(us[k]) >= a.u_hi) : 0;
+            }
+            hist_add<PPT>(a.hist, key, live);
         }
     }
     acc.flush(a.J, a.ctr);
