@@ -26,20 +26,11 @@ struct BatchArgs {
     int n_tubes;
     const int64_t *push_pref;    // [n_tubes + 1] prefix of push tiles (at capacity)
     const int64_t *field_pref;   // [n_tubes + 1] prefix of cell tiles
+    const int32_t *push_map;     // push tile -> tube
+    const int32_t *field_map;    // cell tile -> tube
     int fb, jb, pb;              // field, current and particle buffer parities of the step
 };
 
-// Last t with pref[t] <= item (pref is non-decreasing, pref[0] = 0).
-__device__ __forceinline__ int find_tube(const int64_t *pref, int n, int64_t item)
-{
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pref[mid] <= item) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 template <int BLOCK, int PPT, int NT, int F32>
 __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
@@ -48,7 +39,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
     const int64_t it = blockIdx.x;
     if (it >= b.push_pref[b.n_tubes]) return;
     {
-        const int t = find_tube(b.push_pref, b.n_tubes, it);
+        const int t = b.push_map[it];
         const TubeDev &T = b.tubes[t];
         const int64_t local = it - b.push_pref[t];
         const bool hi = F32 && local >= T.push_tiles;
@@ -75,7 +66,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_field(BatchArgs b)
     const int64_t it = blockIdx.x;
     if (it >= b.field_pref[b.n_tubes]) return;
     {
-        const int t = find_tube(b.field_pref, b.n_tubes, it);
+        const int t = b.field_map[it];
         const TubeDev &T = b.tubes[t];
         const int64_t local = it - b.field_pref[t];
         FieldArgs a{T.ez[fb], T.er[fb], T.b[fb], T.ez[g], T.er[g], T.b[g], T.j[jb], T.j[jb ^ 1],
@@ -95,6 +86,8 @@ struct BSortArgs {
     const int64_t *chunk_pref;   // [n_tubes + 1] prefix of 256-slot chunks (both streams)
     const int64_t *key_pref;     // [n_tubes + 1] prefix of sort keys
     const int64_t *scan_pref;    // [n_tubes + 1] prefix of scan blocks
+    const int32_t *chunk_map;    // sort chunk -> tube
+    const int32_t *scan_map;     // scan block -> tube
     int f32;
     int src, dst;                // particle buffer parity before / after
 };
@@ -102,7 +95,7 @@ struct BSortArgs {
 // One block per scan block of SORT_SCAN_TILE keys (a block never spans two tubes).
 __global__ __launch_bounds__(256) void k_bsort_clear(BSortArgs a)
 {
-    const int t = find_tube(a.scan_pref, a.n_tubes, blockIdx.x);
+    const int t = a.scan_map[blockIdx.x];
     const TubeDev &T = a.tubes[t];
     const int64_t base = (blockIdx.x - a.scan_pref[t]) * SORT_SCAN_TILE;
 #pragma unroll
@@ -126,7 +119,7 @@ __global__ __launch_bounds__(256) void k_bsort_hist(BSortArgs a)
 {
     const int64_t it = blockIdx.x;
     {
-        const int t = find_tube(a.chunk_pref, a.n_tubes, it);
+        const int t = a.chunk_map[it];
         const TubeDev &T = a.tubes[t];
         int64_t p, n;
         const bool hi = chunk_slot(T, a.f32, it - a.chunk_pref[t], p, n);
@@ -176,7 +169,7 @@ __device__ __forceinline__ long long bscan_block_incl(long long v, long long *s_
 __global__ __launch_bounds__(256) void k_bscan_totals(BSortArgs a)
 {
     __shared__ long long s_wave[4];
-    const int t = find_tube(a.scan_pref, a.n_tubes, blockIdx.x);
+    const int t = a.scan_map[blockIdx.x];
     const TubeDev &T = a.tubes[t];
     const int64_t lb = blockIdx.x - a.scan_pref[t];
     const int64_t base = lb * SORT_SCAN_TILE + (int64_t)threadIdx.x * 4;
@@ -211,7 +204,7 @@ __global__ __launch_bounds__(256) void k_bscan_blocks(BSortArgs a)
 __global__ __launch_bounds__(256) void k_bscan_apply(BSortArgs a)
 {
     __shared__ long long s_wave[4];
-    const int t = find_tube(a.scan_pref, a.n_tubes, blockIdx.x);
+    const int t = a.scan_map[blockIdx.x];
     const TubeDev &T = a.tubes[t];
     const int64_t lb = blockIdx.x - a.scan_pref[t];
     const int64_t base = lb * SORT_SCAN_TILE + (int64_t)threadIdx.x * 4;
@@ -240,7 +233,7 @@ __global__ __launch_bounds__(256) void k_bsort_scatter(BSortArgs a)
     const int lane = __lane_id();
     const int64_t it = blockIdx.x;
     {
-        const int t = find_tube(a.chunk_pref, a.n_tubes, it);
+        const int t = a.chunk_map[it];
         const TubeDev &T = a.tubes[t];
         int64_t p, n;
         const bool hi = chunk_slot(T, a.f32, it - a.chunk_pref[t], p, n);
@@ -338,6 +331,10 @@ TubeDev tube_dev(pic_handle *t)
     d.cell_off = w.cell_off;
     d.total_lo = w.total_lo;
     d.blk_sum = w.blk_sum;
+    d.rhs = w.rhs;
+    d.cp = w.cp;
+    d.dp = w.dp;
+    d.phi = w.phi;
     d.u_hi = t->u_hi;
     d.sort_chunks = (t->c.cap + 255) / 256;
     d.n_keys = sort_key_count(t->c, t->p.precision == PIC_FP32_BULK);
@@ -402,7 +399,8 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps)
     pic_handle *t0 = h->tubes[0];
     const unsigned pgrid = (unsigned)h->batch_push_items, fgrid = (unsigned)h->batch_field_items;
     for (int s = 0; s < nsteps; ++s) {
-        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_push_pref, h->d_field_pref, t0->fbuf ^ (s & 1),
+        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_push_pref, h->d_field_pref, h->d_push_map, h->d_field_map,
+                    t0->fbuf ^ (s & 1),
                     t0->jbuf ^ (s & 1), t0->pbuf};
         void *args[] = {&a};
         hipError_t e = hipLaunchKernel(kp, dim3(pgrid), dim3(h->batch_block), args, 0, h->stream);
@@ -417,7 +415,7 @@ hipError_t launch_batch_sort(pic_handle *h)
 {
     pic_handle *t0 = h->tubes[0];
     const int nt = (int)h->tubes.size();
-    BSortArgs a{h->d_tubes, nt, h->d_sort_pref, h->d_key_pref, h->d_scan_pref,
+    BSortArgs a{h->d_tubes, nt, h->d_sort_pref, h->d_key_pref, h->d_scan_pref, h->d_chunk_map, h->d_scan_map,
                 t0->p.precision == PIC_FP32_BULK ? 1 : 0, t0->pbuf, 1 - t0->pbuf};
     if (h->batch_scan_blocks <= 0 || h->batch_scan_blocks > 0x7fffffff) return hipErrorInvalidValue;
     const unsigned sb = (unsigned)h->batch_scan_blocks;

@@ -65,8 +65,7 @@ __global__ __launch_bounds__(256) void k_poisson_rhs(Consts c, const int64_t *w,
 // phi_0 = 0.  The recurrence is sequential: one lane runs it while the block
 // stages the operands through LDS in chunks so that no load is on the chain.
 constexpr int TH_CHUNK = 2048;
-__global__ __launch_bounds__(256) void k_thomas(Consts c, const double *rhs, double *cp, double *dp,
-                                                double *phi)
+__device__ __forceinline__ void thomas_block(const Consts &c, const double *rhs, double *cp, double *dp, double *phi)
 {
     __shared__ double sa[TH_CHUNK];
     __shared__ double sb[TH_CHUNK];
@@ -127,6 +126,19 @@ __global__ __launch_bounds__(256) void k_thomas(Consts c, const double *rhs, dou
         for (int t = threadIdx.x; t < cnt; t += 256) phi[lo + t] = sa[t];
     }
     if (threadIdx.x == 0) phi[0] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_thomas(Consts c, const double *rhs, double *cp, double *dp,
+                                                double *phi)
+{
+    thomas_block(c, rhs, cp, dp, phi);
+}
+
+// The same solve for many tubes of a batch at once, one block per listed tube.
+__global__ __launch_bounds__(256) void k_thomas_batch(const TubeDev *tubes, const int32_t *list)
+{
+    const TubeDev &T = tubes[list[blockIdx.x]];
+    thomas_block(T.c, T.rhs, T.cp, T.dp, T.phi);
 }
 
 // E_z = -dphi/dz at faces, E_r = phi/R at nodes, B_phi = 0, J = 0, kick array.
@@ -215,7 +227,8 @@ hipError_t launch_weights(pic_handle *h, int64_t *w_out)
     return hipGetLastError();
 }
 
-hipError_t launch_poisson(pic_handle *h)
+// Right-hand side of eq. (4) from the loaded charge (before the solve).
+hipError_t launch_poisson_rhs(pic_handle *h)
 {
     const Consts &c = h->c;
     Workspace &w = h->ws;
@@ -223,11 +236,36 @@ hipError_t launch_poisson(pic_handle *h)
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_poisson_rhs, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, w.w,
                        w.rho_gj, w.rhs);
-    hipLaunchKernelGGL(k_thomas, dim3(1), dim3(256), 0, h->stream, c, w.rhs, w.cp, w.dp, w.phi);
+    return hipGetLastError();
+}
+
+// E_z, E_r, B_phi = 0, cleared J and the kick arrays from the solved phi.
+hipError_t launch_fields_from_phi(pic_handle *h)
+{
+    const Consts &c = h->c;
+    Workspace &w = h->ws;
     const int f = h->fbuf;
     hipLaunchKernelGGL(k_fields_from_phi, dim3(grid_for(c.N + 1, 256)), dim3(256), 0, h->stream, c,
                        w.phi, w.ez[f], w.er[f], w.b[f], w.k64,
                        h->p.precision == PIC_FP32_BULK ? w.k32 : nullptr, w.j[0], w.j[1]);
+    return hipGetLastError();
+}
+
+hipError_t launch_poisson(pic_handle *h)
+{
+    hipError_t e = launch_poisson_rhs(h);
+    if (e != hipSuccess) return e;
+    Workspace &w = h->ws;
+    hipLaunchKernelGGL(k_thomas, dim3(1), dim3(256), 0, h->stream, h->c, w.rhs, w.cp, w.dp, w.phi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_fields_from_phi(h);
+}
+
+// Solve eq. (4) for the listed tubes of a batch together (one Thomas block per tube).
+hipError_t launch_thomas_batch(pic_handle *b, const int32_t *d_list, int n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_thomas_batch, dim3((unsigned)n), dim3(256), 0, b->stream, b->d_tubes, d_list);
     return hipGetLastError();
 }
 

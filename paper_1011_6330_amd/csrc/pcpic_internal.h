@@ -142,6 +142,7 @@ struct TubeDev {
     float *k32;
     DevCounters *ctr;
     long long *cell_count, *cell_off, *total_lo, *blk_sum;
+    double *rhs, *cp, *dp, *phi;   // Poisson solve of eq. (4)
     double u_hi;
     int64_t push_tiles;   // push tiles per particle stream at capacity
     int64_t sort_chunks;  // 256-slot chunks per particle stream at capacity
@@ -184,6 +185,8 @@ struct pic_handle {
     const int64_t *d_sched = nullptr;   // replayed injection counts (caller's device array)
     int64_t sched_first = 0, sched_n = 0;
     bool hist_on = false;               // this step also counts the sort keys (a sort follows)
+    bool poisson_pending = false;       // tube of a batch: eq. (4) to be solved with the batch
+    int32_t *d_pending = nullptr;       // batch: device list of tubes to solve together
     int n_cu = 256;
     // batch (ensemble) handles
     bool is_batch = false;
@@ -192,6 +195,8 @@ struct pic_handle {
     pcpic::TubeDev *d_tubes = nullptr;
     int64_t *d_push_pref = nullptr, *d_field_pref = nullptr, *d_sort_pref = nullptr, *d_key_pref = nullptr;
     int64_t *d_scan_pref = nullptr;             // [n + 1] prefix of 1024-key scan blocks
+    int32_t *d_push_map = nullptr, *d_field_map = nullptr;   // work item -> tube
+    int32_t *d_chunk_map = nullptr, *d_scan_map = nullptr;
     int batch_block = 256, batch_ppt = 2;
     int64_t batch_push_items = 0, batch_field_items = 0, batch_sort_items = 0, batch_keys = 0, batch_scan_blocks = 0;
     hipGraphExec_t graph[8] = {};   // one round, keyed by the (field, current, particle) buffer parities
@@ -205,6 +210,9 @@ namespace pcpic {
 hipError_t launch_rho_gj(pic_handle *h);
 hipError_t launch_weights(pic_handle *h, int64_t *w_out);
 hipError_t launch_poisson(pic_handle *h);
+hipError_t launch_poisson_rhs(pic_handle *h);
+hipError_t launch_fields_from_phi(pic_handle *h);
+hipError_t launch_thomas_batch(pic_handle *b, const int32_t *d_list, int n);
 hipError_t launch_push_f64(pic_handle *h);
 hipError_t launch_push_f32(pic_handle *h);
 hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U, double *Xo, double *Uo);

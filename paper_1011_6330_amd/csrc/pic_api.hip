@@ -220,7 +220,9 @@ size_t pic_workspace_bytes(const pic_params *p)
     return carve(*p, nullptr).bytes;
 }
 
-static pic_status init_tube(const pic_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream, pic_handle **out)
+// defer_poisson: leave the t = 0 solve of eq. (4) to the batch the tube belongs to.
+static pic_status init_tube(const pic_params *p, void *d_workspace, size_t ws_bytes, void *hip_stream, pic_handle **out,
+                            bool defer_poisson = false)
 {
     if (!out) return fail(PIC_EINVAL, "out is NULL");
     *out = nullptr;
@@ -262,7 +264,11 @@ static pic_status init_tube(const pic_params *p, void *d_workspace, size_t ws_by
         if (e != hipSuccess) return bail(e, "copy knots");
     }
     if ((e = launch_rho_gj(h)) != hipSuccess) return bail(e, "rho_gj");
-    if ((e = launch_poisson(h)) != hipSuccess) return bail(e, "poisson");
+    if (defer_poisson) {
+        h->poisson_pending = true;
+    } else if ((e = launch_poisson(h)) != hipSuccess) {
+        return bail(e, "poisson");
+    }
     *out = h;
     return PIC_OK;
 }
@@ -321,7 +327,10 @@ pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u
             HIP_OK(hipMemcpyAsync(h->ws.stage_u, u + o, (size_t)m * 8, kind, h->stream));
             HIP_OK(launch_append_staged(h, m, false));
         }
-        if (h->step == 0) HIP_OK(launch_poisson(h));
+        if (h->step == 0) {
+            if (h->parent) h->poisson_pending = true;   // solved with the batch's other tubes
+            else HIP_OK(launch_poisson(h));
+        }
         HIP_OK(hipStreamSynchronize(h->stream));
         return PIC_OK;
     }
@@ -338,8 +347,12 @@ pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u
     if (s != PIC_OK) return s;
     if (ctr.bad_inputs) return fail(PIC_EINVAL, "%lld particles outside [0, N) or not finite", (long long)ctr.bad_inputs);
     if (h->step == 0) {
-        HIP_OK(launch_poisson(h));
-        HIP_OK(hipStreamSynchronize(h->stream));
+        if (h->parent) {
+            h->poisson_pending = true;                   // solved with the batch's other tubes
+        } else {
+            HIP_OK(launch_poisson(h));
+            HIP_OK(hipStreamSynchronize(h->stream));
+        }
     }
     return PIC_OK;
 }
@@ -495,10 +508,44 @@ pic_status pic_sync(pic_handle *h)
     return PIC_OK;
 }
 
+}  // extern "C"
+
+// A tube of a batch whose t = 0 solve of eq. (4) is still pending (after
+// pic_init_batch or a warm-start pic_inject) gets it now, on its own.
+static pic_status resolve_pending(pic_handle *h)
+{
+    if (!h->poisson_pending) return PIC_OK;
+    HIP_OK(launch_poisson(h));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    h->poisson_pending = false;
+    return PIC_OK;
+}
+
+// Every pending tube of a batch: the right-hand sides, one Thomas block per
+// tube in a single launch, then the fields.  Same kernels and arithmetic as a
+// single tube's solve.
+static pic_status batch_resolve_pending(pic_handle *b)
+{
+    std::vector<int32_t> list;
+    for (size_t t = 0; t < b->tubes.size(); ++t)
+        if (b->tubes[t]->poisson_pending) list.push_back((int32_t)t);
+    if (list.empty()) return PIC_OK;
+    for (int32_t t : list) HIP_OK(launch_poisson_rhs(b->tubes[(size_t)t]));
+    HIP_OK(hipMemcpyAsync(b->d_pending, list.data(), 4 * list.size(), hipMemcpyHostToDevice, b->stream));
+    HIP_OK(launch_thomas_batch(b, b->d_pending, (int)list.size()));
+    for (int32_t t : list) HIP_OK(launch_fields_from_phi(b->tubes[(size_t)t]));
+    HIP_OK(hipStreamSynchronize(b->stream));
+    for (int32_t t : list) b->tubes[(size_t)t]->poisson_pending = false;
+    return PIC_OK;
+}
+
+extern "C" {
+
 pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out)
 {
     if (!h || !out) return fail(PIC_EINVAL, "handle or out is NULL");
     if (h->is_batch) return fail(PIC_EINVAL, "diagnostics are per tube (pic_batch_tube)");
+    if (pic_status sp = resolve_pending(h)) return sp;
     const int nb = req ? req->n_bins : 0;
     const bool want_gauss = req && req->want_gauss;
     if (nb < 0 || nb > effective_bins(h->p)) return fail(PIC_EINVAL, "n_bins %d > max_bins", nb);
@@ -562,6 +609,7 @@ pic_status pic_read_particles(pic_handle *h, double *x, double *u, int64_t cap, 
 {
     if (!h || !n_out) return fail(PIC_EINVAL, "handle or n_out is NULL");
     if (h->is_batch) return fail(PIC_EINVAL, "particles are per tube (pic_batch_tube)");
+    if (pic_status sp = resolve_pending(h)) return sp;
     DevCounters ctr;
     pic_status s = read_counters(h, &ctr);
     if (s != PIC_OK) return s;
@@ -622,6 +670,7 @@ pic_status pic_write_fields(pic_handle *h, const double *ez, const double *er, c
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
     if (h->is_batch) return fail(PIC_EINVAL, "fields are per tube (pic_batch_tube)");
+    if (pic_status sp = resolve_pending(h)) return sp;
     const int64_t N = h->c.N;
     const int f = h->fbuf;
     if (ez) HIP_OK(hipMemcpyAsync(h->ws.ez[f], ez, (size_t)N * 8, hipMemcpyHostToDevice, h->stream));
@@ -727,6 +776,7 @@ pic_status pic_save(pic_handle *h, void *buf, size_t cap, size_t *bytes)
 {
     if (!h || !bytes) return fail(PIC_EINVAL, "handle or bytes is NULL");
     if (h->is_batch) return fail(PIC_EINVAL, "save the tubes of a batch one by one (pic_batch_tube)");
+    if (pic_status sp = resolve_pending(h)) return sp;
     DevCounters ctr;
     pic_status s = read_counters(h, &ctr);
     if (s != PIC_OK) return s;
@@ -846,11 +896,39 @@ pic_status pic_destroy(pic_handle *h)
 // batches of tubes (ensembles)
 // ------------------------------------------------------------------------
 
-static size_t batch_header_bytes(int n)
+// Entries of the work-item -> tube maps, sized for the smallest tiles any
+// launch shape uses (64 threads x 2 slots, or x 4 in FP32-bulk mode; 64 cells).
+struct BatchMapSizes {
+    int64_t push, field, chunk, scan;
+};
+
+static BatchMapSizes batch_map_sizes(const pic_params *tubes, int n)
 {
+    BatchMapSizes m{0, 0, 0, 0};
+    for (int t = 0; t < n; ++t) {
+        const pic_params &p = tubes[t];
+        const bool f32 = p.precision == PIC_FP32_BULK;
+        const int64_t tile = f32 ? 256 : 128;
+        m.push += (f32 ? 2 : 1) * ((p.capacity + tile - 1) / tile);
+        m.field += (p.n_cells + 63) / 64;
+        m.chunk += (f32 ? 2 : 1) * ((p.capacity + 255) / 256);
+        const int64_t keys = (f32 ? 2 * (p.n_cells + 1) : p.n_cells) << sort_sub_log2(p);
+        m.scan += (keys + SORT_SCAN_TILE - 1) / SORT_SCAN_TILE;
+    }
+    return m;
+}
+
+static size_t batch_header_bytes(const pic_params *tubes, int n)
+{
+    const BatchMapSizes m = batch_map_sizes(tubes, n);
     size_t off = 0;
     off = align_up(off) + sizeof(TubeDev) * (size_t)n;
     for (int k = 0; k < 5; ++k) off = align_up(off) + sizeof(int64_t) * (size_t)(n + 1);
+    off = align_up(off) + 4 * (size_t)m.push;
+    off = align_up(off) + 4 * (size_t)m.field;
+    off = align_up(off) + 4 * (size_t)m.chunk;
+    off = align_up(off) + 4 * (size_t)m.scan;
+    off = align_up(off) + 4 * (size_t)n;   // tubes to solve together
     return align_up(off);
 }
 
@@ -860,11 +938,10 @@ size_t pic_batch_workspace_bytes(const pic_params *tubes, int32_t n_tubes)
         fail(PIC_EINVAL, "need at least one tube");
         return 0;
     }
-    size_t total = batch_header_bytes(n_tubes);
-    for (int t = 0; t < n_tubes; ++t) {
+    for (int t = 0; t < n_tubes; ++t)
         if (validate(&tubes[t]) != PIC_OK) return 0;
-        total += carve(tubes[t], nullptr).bytes;
-    }
+    size_t total = batch_header_bytes(tubes, n_tubes);
+    for (int t = 0; t < n_tubes; ++t) total += carve(tubes[t], nullptr).bytes;
     return total;
 }
 
@@ -915,6 +992,19 @@ static pic_status batch_configure(pic_handle *h, int block, int per_thread)
     HIP_OK(hipMemcpyAsync(h->d_sort_pref, sp.data(), 8 * sp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_key_pref, kp.data(), 8 * kp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_scan_pref, cp.data(), 8 * cp.size(), hipMemcpyHostToDevice, h->stream));
+    // work item -> tube maps (one entry per block of the batched kernels)
+    std::vector<int32_t> pm((size_t)pp[(size_t)n]), fm((size_t)fp[(size_t)n]), sm((size_t)sp[(size_t)n]),
+        cm((size_t)cp[(size_t)n]);
+    for (int t = 0; t < n; ++t) {
+        for (int64_t i = pp[(size_t)t]; i < pp[(size_t)t + 1]; ++i) pm[(size_t)i] = t;
+        for (int64_t i = fp[(size_t)t]; i < fp[(size_t)t + 1]; ++i) fm[(size_t)i] = t;
+        for (int64_t i = sp[(size_t)t]; i < sp[(size_t)t + 1]; ++i) sm[(size_t)i] = t;
+        for (int64_t i = cp[(size_t)t]; i < cp[(size_t)t + 1]; ++i) cm[(size_t)i] = t;
+    }
+    HIP_OK(hipMemcpyAsync(h->d_push_map, pm.data(), 4 * pm.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_field_map, fm.data(), 4 * fm.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_chunk_map, sm.data(), 4 * sm.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(h->d_scan_map, cm.data(), 4 * cm.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
     free_batch_graphs(h);
     return PIC_OK;
@@ -955,11 +1045,19 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
     h->d_sort_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_key_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_scan_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
-    off = batch_header_bytes(n_tubes);
+    {
+        const BatchMapSizes m = batch_map_sizes(tubes, n_tubes);
+        h->d_push_map = (int32_t *)take(4 * (size_t)m.push);
+        h->d_field_map = (int32_t *)take(4 * (size_t)m.field);
+        h->d_chunk_map = (int32_t *)take(4 * (size_t)m.chunk);
+        h->d_scan_map = (int32_t *)take(4 * (size_t)m.scan);
+        h->d_pending = (int32_t *)take(4 * (size_t)n_tubes);
+    }
+    off = batch_header_bytes(tubes, n_tubes);
     for (int t = 0; t < n_tubes; ++t) {
         const size_t sz = carve(tubes[t], nullptr).bytes;
         pic_handle *sub = nullptr;
-        pic_status s = init_tube(&tubes[t], base + off, sz, hip_stream, &sub);
+        pic_status s = init_tube(&tubes[t], base + off, sz, hip_stream, &sub, true);
         if (s != PIC_OK) {
             pic_destroy(h);
             return s;
@@ -970,6 +1068,11 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
     }
     const bool f32 = tubes[0].precision == PIC_FP32_BULK;
     pic_status s = batch_configure(h, 256, f32 ? 4 : 2);
+    if (s != PIC_OK) {
+        pic_destroy(h);
+        return s;
+    }
+    s = batch_resolve_pending(h);
     if (s != PIC_OK) {
         pic_destroy(h);
         return s;
@@ -1012,6 +1115,7 @@ pic_status pic_batch_get_config(pic_handle *h, int32_t *block, int32_t *per_thre
 // round's step kernels and its sort.
 static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t> *ev, pic_timing *tim)
 {
+    if (pic_status sp = batch_resolve_pending(h)) return sp;
     pic_handle *t0 = h->tubes[0];
     const int64_t S = t0->p.sort_every;
     while (n > 0) {
