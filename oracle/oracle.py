@@ -18,14 +18,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # tests build mutated copies of it).
 LIB_PATH = os.environ.get("PCPIC_ORACLE_LIB") or os.path.join(HERE, "libpcpic_oracle.so")
 
-RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS = 0, 1, 2
+RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS, RHO_GR = 0, 1, 2, 3
 NO_AUTO_INJECT, FREEZE_FIELDS = 1, 2
 ST_CAPACITY, ST_NONFINITE = 1, 2
 
 DEFAULTS = dict(n_cells=1024, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=-1.0,
                 ppc=4.0, rho_kind=RHO_UNIFORM, rho_amp=1.0, kappa=0.0, r_star=10.0,
                 knots=None, fp_bits=32, flags=0, capacity=1 << 16, macro_charge=0.0, inj_rate=0.0,
-                schedule=None)
+                schedule=None, incl=0.0, theta_star=0.0, cos_phi=1.0, rg_over_rstar=0.0)
 
 _pd = ctypes.POINTER(ctypes.c_double)
 _pi = ctypes.POINTER(ctypes.c_int64)
@@ -40,7 +40,9 @@ class OrcCfg(ctypes.Structure):
                 ("r_star", ctypes.c_double), ("knots", _pd),
                 ("fp_bits", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("capacity", ctypes.c_int64), ("macro_charge", ctypes.c_double),
-                ("inj_rate", ctypes.c_double), ("schedule", _pi), ("n_schedule", ctypes.c_int64)]
+                ("inj_rate", ctypes.c_double), ("schedule", _pi), ("n_schedule", ctypes.c_int64),
+                ("incl", ctypes.c_double), ("theta_star", ctypes.c_double), ("cos_phi", ctypes.c_double),
+                ("rg_over_rstar", ctypes.c_double)]
 
 
 class OrcState(ctypes.Structure):
@@ -113,7 +115,8 @@ class OracleTube:
                            None if self._knots is None else _ptr(self._knots),
                            int(c["fp_bits"]), int(c["flags"]), cap, float(c["macro_charge"]),
                            float(c["inj_rate"]), None if self._sched is None else _ptr(self._sched, _pi),
-                           0 if self._sched is None else len(self._sched))
+                           0 if self._sched is None else len(self._sched), float(c["incl"]),
+                           float(c["theta_star"]), float(c["cos_phi"]), float(c["rg_over_rstar"]))
         self._x = np.zeros(cap, np.float64)
         self._u = np.zeros(cap, np.float64)
         self.rho_gj = np.zeros(N + 1)

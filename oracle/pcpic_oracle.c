@@ -33,6 +33,9 @@ static int orc_check(const orc_cfg *c)
     if (!(c->dt_over_dz > 0 && c->dt_over_dz < 1)) return -1;
     if (!(c->ppc > 0) || c->fp_bits < 8 || c->fp_bits > 40 || c->capacity < 0) return -1;
     if (c->rho_kind == ORC_RHO_KNOTS && (c->n_knots < 2 || !c->knots)) return -1;
+    if (c->rho_kind == ORC_RHO_GR &&
+        (!(c->rg_over_rstar >= 0.0 && c->rg_over_rstar < 1.0) || !(fabs(c->incl) < 1.5) || !(c->r_star > 0)))
+        return -1;
     return 0;
 }
 
@@ -49,6 +52,17 @@ static double orc_rho_node(const orc_cfg *c, double dz, int64_t i)
     double e3 = eta * eta * eta;
     double fd = 1.0 - c->kappa / e3;
     if (c->rho_kind == ORC_RHO_FRAME_DRAG) return -(c->rho_amp * fd);
+    if (c->rho_kind == ORC_RHO_GR) {
+        /* eq. 6 divided by the flat surface density of an inclined rotator, Omega B cos(i) / (2 pi c)
+         * (the paper's n_GJ carries the cos(i)), with (R_star/r)^3 dropped as for eq. 5 and the
+         * curved-space factors f = H = 1 (not given):
+         *   rho_GJ = -A [ (1 - kappa/eta^3) + (3/2) eta^(1/2) theta_* tan(i) cos(varphi) ] / alpha,
+         *   alpha = (1 - r_g / r)^(1/2) = (1 - (r_g/R_*) / eta)^(1/2). */
+        double s = ((1.5 * c->theta_star) * tan(c->incl)) * c->cos_phi;
+        double br = fd + s * sqrt(eta);
+        double al = sqrt(1.0 - c->rg_over_rstar / eta);
+        return -((c->rho_amp * br) / al);
+    }
     /* hat-function interpolation of the knot values */
     int64_t K = c->n_knots;
     double s = (z * (double)(K - 1)) / c->length;

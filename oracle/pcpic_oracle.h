@@ -13,8 +13,9 @@
  * eq. (3) advanced by leap-frog, fields started from the Poisson problem of
  * eq. (4) with the boundary conditions stated under it, and space-charge-
  * limited electron injection at the base (sec. 2).  The Goldreich-Julian
- * background is the flat form of eq. (5) with i = 0, or the frame-dragging
- * form of eqs. (6)-(7) with alpha = f = H = 1 and the sin(i) term dropped.
+ * background is the flat form of eq. (5) with i = 0, the frame-dragging form
+ * of eqs. (6)-(7) with alpha = f = H = 1 and the sin(i) term dropped, or
+ * eq. (6) with the redshift 1/alpha and the sin(i) term (f = H = 1).
  *
  * Discretisation (a reading; the paper gives no discrete scheme):
  *   positions in cell units x = z/dz in [0, N); nodes x = i carry phi, E_r,
@@ -34,7 +35,8 @@ extern "C" {
 enum {
     ORC_RHO_UNIFORM = 0,    /* rho_GJ = -A                      (eq. 5, i = 0, (R_star/r)^3 dropped) */
     ORC_RHO_FRAME_DRAG = 1, /* rho_GJ = -A (1 - kappa eta^-3)   (eqs. 6-7, alpha = f = H = 1)    */
-    ORC_RHO_KNOTS = 2       /* rho_GJ = -theta(z) (1 - kappa eta^-3), theta piecewise linear      */
+    ORC_RHO_KNOTS = 2,      /* rho_GJ = -theta(z) (1 - kappa eta^-3), theta piecewise linear      */
+    ORC_RHO_GR = 3          /* eq. 6 with f = H = 1: redshift 1/alpha and the sin(i) term (below)  */
 };
 
 enum {
@@ -68,6 +70,11 @@ typedef struct orc_cfg {
     const int64_t *schedule; /* if not NULL: particles injected at step n = schedule[n]
                                 (replaces the SCLF rule; frozen decisions)         */
     int64_t n_schedule;
+    /* ORC_RHO_GR only (eq. 6): inclination i (rad), theta_* (rad), cos(varphi) and r_g / R_* */
+    double incl;
+    double theta_star;
+    double cos_phi;
+    double rg_over_rstar;
 } orc_cfg;
 
 /* All arrays are owned by the caller; the oracle never allocates them. */

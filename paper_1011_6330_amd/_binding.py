@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libpcpic.so")
 
 ABI_VERSION = 1
 FP64, FP32_BULK = 0, 1
-RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS = 0, 1, 2
+RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS, RHO_GR = 0, 1, 2, 3
 NO_AUTO_INJECT, FREEZE_FIELDS = 1, 2
 ST_CAPACITY, ST_NONFINITE = 1, 2
 

@@ -16,7 +16,7 @@ import math
 
 import numpy as np
 
-RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS = 0, 1, 2
+RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS, RHO_GR = 0, 1, 2, 3
 
 
 def q_over_m_for(a, amp=1.0, radius=1.0):

@@ -47,6 +47,12 @@ FORWARD = [
      "st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) + k.c4 * (double)st->j[i];"),
     ("node-0 weight of a particle in cell 0 taken from the wrong side",
      "            w0 += k.oneP - F1;", "            w0 += F1;"),
+    ("inclination term of eq. 6 growing as eta instead of eta^(1/2)",
+     "double br = fd + s * sqrt(eta);", "double br = fd + s * eta;"),
+    ("redshift with r_g r instead of r_g / r",
+     "double al = sqrt(1.0 - c->rg_over_rstar / eta);", "double al = sqrt(1.0 - c->rg_over_rstar * eta);"),
+    ("sin(i) instead of tan(i) after dividing eq. 6 by cos(i)",
+     "((1.5 * c->theta_star) * tan(c->incl))", "((1.5 * c->theta_star) * sin(c->incl))"),
 ]
 
 REVERSE = [

@@ -425,6 +425,48 @@ def test_rho_gj_knots(oracle_mod):
     np.testing.assert_allclose(t.rho_gj, -theta * fd, rtol=1e-13)
 
 
+def test_rho_gj_gr_reduces_to_frame_drag(oracle_mod):
+    """Eq. (6) with i = 0 and r_g = 0 (alpha = 1, no sin i term) is the
+    frame-dragging density, bit for bit."""
+    kw = dict(n_cells=128, length=10.0, kappa=0.15, r_star=7.0, rho_amp=1.3)
+    a = _tube(oracle_mod, rho_kind=1, **kw)
+    b = _tube(oracle_mod, rho_kind=3, incl=0.0, theta_star=0.0094, rg_over_rstar=0.0, **kw)
+    assert np.array_equal(a.rho_gj, b.rho_gj)
+
+
+def test_rho_gj_gr_redshift(oracle_mod):
+    """alpha = (1 - r_g/r)^(1/2): with kappa = 0 and i = 0 the density is -A/alpha,
+    so rho^2 (1 - g/eta) = A^2 at every node, and at the surface with
+    r_g/R_* = 0.4 the magnitude is A/sqrt(0.6)."""
+    N, L, Rs, g = 100, 20.0, 5.0, 0.4
+    t = _tube(oracle_mod, n_cells=N, length=L, rho_kind=3, kappa=0.0, r_star=Rs, rho_amp=2.0,
+              incl=0.0, rg_over_rstar=g)
+    eta = 1 + np.arange(N + 1) * (L / N) / Rs
+    np.testing.assert_allclose(t.rho_gj ** 2 * (1 - g / eta), 4.0, rtol=1e-14)
+    assert abs(abs(t.rho_gj[0]) - 2.0 / np.sqrt(0.6)) < 1e-14 * 4
+    assert np.all(np.diff(np.abs(t.rho_gj)) < 0)        # the redshift weakens with height
+
+
+def test_rho_gj_gr_sin_i_term(oracle_mod):
+    """The inclination term of eq. (6) grows as (r/R_*)^(1/2) and scales with
+    theta_* tan(i) cos(varphi); near the star it is much smaller than the cos(i)
+    term for the paper's standard pulsar (theta_p = 0.014, theta_* = 0.67 theta_p,
+    i = 0.5 rad), as the paper states."""
+    N, L, Rs = 64, 30.0, 10.0
+    ts = 0.67 * 0.014
+    kw = dict(n_cells=N, length=L, kappa=0.15, r_star=Rs, rho_amp=1.0, rg_over_rstar=0.0)
+    base = _tube(oracle_mod, rho_kind=3, incl=0.0, theta_star=ts, **kw).rho_gj
+    d5 = _tube(oracle_mod, rho_kind=3, incl=0.5, theta_star=ts, **kw).rho_gj - base
+    d1 = _tube(oracle_mod, rho_kind=3, incl=0.1, theta_star=ts, **kw).rho_gj - base
+    dphi = _tube(oracle_mod, rho_kind=3, incl=0.5, theta_star=ts, cos_phi=-0.5, **kw).rho_gj - base
+    eta = 1 + np.arange(N + 1) * (L / N) / Rs
+    prof = d5 / np.sqrt(eta)
+    np.testing.assert_allclose(prof, prof[0], rtol=1e-9)           # proportional to eta^(1/2)
+    np.testing.assert_allclose(d1 / d5, np.tan(0.1) / np.tan(0.5), rtol=1e-8)
+    np.testing.assert_allclose(dphi / d5, -0.5, rtol=1e-8)
+    assert abs(d5[0] / base[0]) < 0.01                           # sin(i) term << cos(i) term at the surface
+
+
 def test_exit_and_absorb(oracle_mod):
     o = oracle_mod
     N = 32
