@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define PCPIC_ABI_VERSION 1
+#define PCPIC_ABI_VERSION 2
 
 typedef int32_t pic_status;
 enum {
@@ -75,8 +75,12 @@ enum {
     PIC_RHO_UNIFORM = 0,    /* -A: eq. (5) with i = 0 and (R_star/r)^3 dropped            */
     PIC_RHO_FRAME_DRAG = 1, /* -A (1 - kappa/eta^3): eq. (6), Omega -> Omega - omega,
                                omega from eq. (7), alpha = f = H = 1, sin(i) term dropped */
-    PIC_RHO_KNOTS = 2       /* -theta(z)(1 - kappa/eta^3), theta piecewise linear on
+    PIC_RHO_KNOTS = 2,      /* -theta(z)(1 - kappa/eta^3), theta piecewise linear on
                                n_knots uniform knots over [0, L]                          */
+    PIC_RHO_GR = 3          /* eq. (6) with f = H = 1, in units of the flat surface density
+                               Omega B cos(i)/(2 pi c), (R_star/r)^3 dropped:
+                               -A [(1 - kappa/eta^3) + (3/2) eta^(1/2) theta_* tan(i) cos(varphi)]
+                               / alpha, alpha = (1 - (r_g/R_*)/eta)^(1/2)                   */
 };
 
 /* pic_params.flags */
@@ -110,6 +114,11 @@ typedef struct pic_params {
     double gamma_fp64;        /* PIC_FP32_BULK: gamma from which u is kept in f64 (0 = 1e6)  */
     double macro_charge;      /* q_m (per unit area); 0 = rho_GJ(0) dz / ppc.  A fixed value
                                  keeps the particle charge independent of rho_GJ (gradients) */
+    /* PIC_RHO_GR only (eq. 6): */
+    double incl;              /* inclination i (rad), |i| < 1.5                              */
+    double theta_star;        /* magnetic colatitude theta_* of the field line (rad)         */
+    double cos_phi;           /* cos(varphi) of the field line's azimuth (1 for varphi = 0)  */
+    double rg_over_rstar;     /* r_g / R_* in [0, 1): alpha = (1 - r_g/r)^(1/2)              */
 } pic_params;
 
 typedef struct pic_handle pic_handle;
@@ -291,8 +300,8 @@ typedef struct pic_adjoint_out {
     double loss;            /* L                                                        */
     int64_t n_exit;         /* electrons in the mean                                    */
     double g_rate;          /* dL/d(charge factor of electrons injected during the run) */
-    double g_kappa;         /* dL/d kappa (PIC_RHO_FRAME_DRAG and PIC_RHO_KNOTS)        */
-    double g_amp;           /* dL/d A (PIC_RHO_UNIFORM and PIC_RHO_FRAME_DRAG)          */
+    double g_kappa;         /* dL/d kappa (PIC_RHO_FRAME_DRAG, PIC_RHO_KNOTS, PIC_RHO_GR) */
+    double g_amp;           /* dL/d A (PIC_RHO_UNIFORM, PIC_RHO_FRAME_DRAG, PIC_RHO_GR)  */
     double *g_rho;          /* host [N+1] or NULL: dL/d rho_GJ at the nodes             */
     double *g_knots;        /* host [n_knots] or NULL: dL/d theta_k (PIC_RHO_KNOTS)     */
     double forward_ms;      /* device time of the checkpointed forward                  */

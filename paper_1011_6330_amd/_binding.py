@@ -15,7 +15,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libpcpic.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 FP64, FP32_BULK = 0, 1
 RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS, RHO_GR = 0, 1, 2, 3
 NO_AUTO_INJECT, FREEZE_FIELDS = 1, 2
@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_EWORKSPACE", -3: "PIC_EC
 DEFAULTS = dict(precision=FP64, n_cells=1024, length=10.0, radius=1.0, dt_over_dz=0.5,
                 q_over_m=-1.0, ppc=4.0, rho_kind=RHO_UNIFORM, rho_amp=1.0, kappa=0.0,
                 r_star=10.0, knots=None, fp_bits=32, sort_every=0, capacity=1 << 16, flags=0,
-                max_bins=1024, gamma_fp64=0.0, macro_charge=0.0)
+                max_bins=1024, gamma_fp64=0.0, macro_charge=0.0, incl=0.0, theta_star=0.0, cos_phi=1.0,
+                rg_over_rstar=0.0)
 
 _pd = ctypes.POINTER(ctypes.c_double)
 _pi = ctypes.POINTER(ctypes.c_int64)
@@ -46,7 +47,8 @@ class PicParams(ctypes.Structure):
                 ("fp_bits", ctypes.c_int32), ("sort_every", ctypes.c_int32),
                 ("capacity", ctypes.c_int64), ("flags", ctypes.c_uint32),
                 ("max_bins", ctypes.c_int32), ("gamma_fp64", ctypes.c_double),
-                ("macro_charge", ctypes.c_double)]
+                ("macro_charge", ctypes.c_double), ("incl", ctypes.c_double), ("theta_star", ctypes.c_double),
+                ("cos_phi", ctypes.c_double), ("rg_over_rstar", ctypes.c_double)]
 
 
 class PicDiagReq(ctypes.Structure):
@@ -158,7 +160,8 @@ def make_params(cfg=None, **kw):
                   int(c["rho_kind"]), 0 if knots is None else len(knots), float(c["rho_amp"]),
                   float(c["kappa"]), float(c["r_star"]), _ptr(knots), int(c["fp_bits"]),
                   int(c["sort_every"]), int(c["capacity"]), int(c["flags"]), int(c["max_bins"]),
-                  float(c["gamma_fp64"]), float(c["macro_charge"]))
+                  float(c["gamma_fp64"]), float(c["macro_charge"]), float(c["incl"]),
+                  float(c["theta_star"]), float(c["cos_phi"]), float(c["rg_over_rstar"]))
     return p, knots, c
 
 

@@ -297,6 +297,11 @@ __global__ __launch_bounds__(256) void k_adj_params(Consts c, const double *knot
         if (c.rho_kind == PIC_RHO_FRAME_DRAG) {
             ga += gr * (-fd);
             gk += gr * (c.rho_amp / e3);
+        } else if (c.rho_kind == PIC_RHO_GR) {
+            const double br = fd + c.gr_s * sqrt(eta);
+            const double al = sqrt(1.0 - c.gr_g / eta);
+            ga += gr * (-(br / al));
+            gk += gr * (c.rho_amp / (e3 * al));
         } else {
             const double s = (z * (double)(K - 1)) / c.length;
             int kk = (int)floor(s);

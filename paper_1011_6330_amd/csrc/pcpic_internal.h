@@ -49,6 +49,8 @@ struct Consts {
     int32_t rho_kind;
     int32_t n_knots;
     double rho_amp, kappa, r_star, length;
+    double gr_s;      // PIC_RHO_GR: (3/2) theta_* tan(i) cos(varphi)
+    double gr_g;      // PIC_RHO_GR: r_g / R_*
 };
 
 // Cell-sort keys.  A live particle's key is its cell refined into 2^sub bins
@@ -257,6 +259,12 @@ __host__ __device__ inline double rho_node(const Consts &c, const double *knots,
     const double e3 = eta * eta * eta;
     const double fd = 1.0 - c.kappa / e3;   // 1 - omega/Omega, eq. (7)
     if (c.rho_kind == PIC_RHO_FRAME_DRAG) return -(c.rho_amp * fd);
+    if (c.rho_kind == PIC_RHO_GR) {
+        // eq. (6): inclination term growing as eta^(1/2), gravitational redshift 1/alpha
+        const double br = fd + c.gr_s * sqrt(eta);
+        const double al = sqrt(1.0 - c.gr_g / eta);
+        return -((c.rho_amp * br) / al);
+    }
     const int64_t K = c.n_knots;
     const double s = (z * (double)(K - 1)) / c.length;
     int64_t k = (int64_t)floor(s);

@@ -55,13 +55,17 @@ pic_status validate(const pic_params *p)
         return fail(PIC_ECFL, "dt_over_dz = %g violates 0 < c dt/dz < 1", p->dt_over_dz);
     if (!isfinite(p->q_over_m)) return fail(PIC_EINVAL, "q_over_m must be finite");
     if (!(p->ppc > 0) || !isfinite(p->ppc)) return fail(PIC_EINVAL, "ppc must be > 0");
-    if (p->rho_kind < PIC_RHO_UNIFORM || p->rho_kind > PIC_RHO_KNOTS)
+    if (p->rho_kind < PIC_RHO_UNIFORM || p->rho_kind > PIC_RHO_GR)
         return fail(PIC_EINVAL, "rho_kind %d unknown", p->rho_kind);
     if (!isfinite(p->rho_amp)) return fail(PIC_EINVAL, "rho_amp must be finite");
     if (p->rho_kind != PIC_RHO_UNIFORM && (!(p->r_star > 0) || !isfinite(p->kappa)))
         return fail(PIC_EINVAL, "frame dragging needs r_star > 0 and a finite kappa");
     if (p->rho_kind == PIC_RHO_KNOTS && (p->n_knots < 2 || !p->knots))
         return fail(PIC_EINVAL, "PIC_RHO_KNOTS needs n_knots >= 2 and a knot array");
+    if (p->rho_kind == PIC_RHO_GR &&
+        (!(p->rg_over_rstar >= 0.0 && p->rg_over_rstar < 1.0) || !(fabs(p->incl) < 1.5) ||
+         !isfinite(p->theta_star) || !isfinite(p->cos_phi)))
+        return fail(PIC_EINVAL, "PIC_RHO_GR needs r_g/R_* in [0, 1), |i| < 1.5 and finite theta_*, cos(varphi)");
     if (p->fp_bits < 16 || p->fp_bits > 36) return fail(PIC_EINVAL, "fp_bits %d not in [16, 36]", p->fp_bits);
     if (p->capacity < 1 || p->capacity > ((int64_t)1 << 40))
         return fail(PIC_EINVAL, "capacity %lld out of range", (long long)p->capacity);
@@ -94,6 +98,8 @@ Consts make_consts(const pic_params &p, const double *knots)
     c.kappa = p.kappa;
     c.r_star = p.r_star;
     c.length = p.length;
+    c.gr_s = p.rho_kind == PIC_RHO_GR ? ((1.5 * p.theta_star) * tan(p.incl)) * p.cos_phi : 0.0;
+    c.gr_g = p.rho_kind == PIC_RHO_GR ? p.rg_over_rstar : 0.0;
     c.rho0 = rho_node(c, knots, 0);
     c.qm = p.macro_charge != 0.0 ? p.macro_charge : (c.rho0 * c.dz) / p.ppc;
     c.qmP = c.qm / c.twoP;
@@ -703,7 +709,7 @@ pic_status pic_set_injection_schedule(pic_handle *h, const int64_t *d_counts, in
 
 namespace {
 
-constexpr char SAVE_MAGIC[8] = {'P', 'C', 'P', 'I', 'C', 'S', 'V', '1'};
+constexpr char SAVE_MAGIC[8] = {'P', 'C', 'P', 'I', 'C', 'S', 'V', '2'};
 
 struct SaveHead {
     char magic[8];
@@ -711,6 +717,7 @@ struct SaveHead {
     int64_t n_cells, n_knots, n_lo, n_hi, step, total_bytes;
     int32_t rho_kind, fp_bits;
     double length, radius, dt_over_dz, q_over_m, ppc, rho_amp, kappa, r_star, gamma_fp64, macro_charge;
+    double incl, theta_star, cos_phi, rg_over_rstar;
 };
 
 size_t pad8(size_t b) { return (b + 7) & ~(size_t)7; }
@@ -766,6 +773,10 @@ void fill_head(const pic_handle *h, SaveHead *hd)
     hd->r_star = p.r_star;
     hd->gamma_fp64 = p.gamma_fp64;
     hd->macro_charge = p.macro_charge;
+    hd->incl = p.incl;
+    hd->theta_star = p.theta_star;
+    hd->cos_phi = p.cos_phi;
+    hd->rg_over_rstar = p.rg_over_rstar;
 }
 
 }  // namespace
@@ -835,7 +846,9 @@ pic_status pic_load(pic_handle *h, const void *buf, size_t bytes)
                       hd.radius == mine.radius && hd.dt_over_dz == mine.dt_over_dz && hd.q_over_m == mine.q_over_m &&
                       hd.ppc == mine.ppc && hd.rho_amp == mine.rho_amp && hd.kappa == mine.kappa &&
                       hd.r_star == mine.r_star && hd.gamma_fp64 == mine.gamma_fp64 &&
-                      hd.macro_charge == mine.macro_charge;
+                      hd.macro_charge == mine.macro_charge && hd.incl == mine.incl &&
+                      hd.theta_star == mine.theta_star && hd.cos_phi == mine.cos_phi &&
+                      hd.rg_over_rstar == mine.rg_over_rstar;
     if (!same) return fail(PIC_EINVAL, "the saved tube has different parameters");
     const bool f32 = h->p.precision == PIC_FP32_BULK;
     const int64_t N = h->c.N;

@@ -39,6 +39,14 @@ PRESETS = {
                ppc=610.0, rho_kind=RHO_FRAME_DRAG, rho_amp=1.0, kappa=0.15, r_star=10.0,
                fp_bits=32, sort_every=16, capacity=int(610 * 65536 * 1.05), flags=0, steps=20000,
                warm=610 * 65536),
+    # the frame-dragging tube with the whole of eq. (6): redshift (r_g/R_* = 0.4) and the
+    # inclination term of the paper's standard pulsar (i = 0.5 rad, theta_* = 0.67 theta_p,
+    # theta_p = 0.014, varphi = 0)
+    "c2gr": dict(n_cells=65536, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=q_over_m_for(6878.0),
+                 ppc=610.0, rho_kind=RHO_GR, rho_amp=1.0, kappa=0.15, r_star=10.0, incl=0.5,
+                 theta_star=0.67 * 0.014, cos_phi=1.0, rg_over_rstar=0.4,
+                 fp_bits=32, sort_every=16, capacity=int(610 * 65536 * 1.05), flags=0, steps=20000,
+                 warm=610 * 65536),
     # adjoint workload: 4096 cells, 64 knots, about 1e6 particles
     # (the macro charge is fixed at its nominal value so that it does not move with the knots)
     "c4": dict(n_cells=4096, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=q_over_m_for(430.0),

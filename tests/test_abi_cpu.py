@@ -41,7 +41,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.pic_abi_version() == 1
+    assert lib.pic_abi_version() == 2
 
 
 def _params(**kw):
@@ -81,7 +81,7 @@ def test_init_rejects_bad_abi_and_workspace(lib):
     p.abi_version = 99
     h = ctypes.c_void_p()
     assert lib.pic_init(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == -8     # PIC_EABI
-    p.abi_version = 1
+    p.abi_version = 2
     assert lib.pic_init(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == -2     # PIC_EWORKSPACE
     assert lib.pic_init(ctypes.byref(p), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(h)) == -2  # misaligned
     assert b"aligned" in lib.pic_last_error()

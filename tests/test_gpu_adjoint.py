@@ -189,3 +189,22 @@ def test_adjoint_c4_vs_finite_differences():
         assert abs(fd - g) <= 2e-4 * ref, (name, k, fd, g)
         checked += 1
     assert checked == 5
+
+
+def test_adjoint_gr_background_params():
+    """The eq. (6) background: node gradient as the oracle's, and dL/dkappa, dL/dA
+    mapped through rho = -A [(1 - kappa/eta^3) + s eta^(1/2)] / alpha."""
+    cfg, x, u = _warm_cfg()
+    cfg = dict(cfg, rho_kind=synth.RHO_GR, incl=0.5, theta_star=0.67 * 0.014, rg_over_rstar=0.4, knots=None)
+    say("adjoint gr background")
+    r, g_rho, _ = _compare(cfg, x, u, 160, 50)
+    N = cfg["n_cells"]
+    z = np.arange(N + 1) * (cfg["length"] / N)
+    eta = 1 + z / cfg["r_star"]
+    s = 1.5 * cfg["theta_star"] * np.tan(cfg["incl"])
+    al = np.sqrt(1 - cfg["rg_over_rstar"] / eta)
+    br = (1 - cfg["kappa"] / eta ** 3) + s * np.sqrt(eta)
+    g_amp = float(g_rho @ (-br / al))
+    g_kappa = float(g_rho @ (cfg["rho_amp"] / (eta ** 3 * al)))
+    assert abs(r["g_amp"] - g_amp) <= 1e-8 * abs(g_amp)
+    assert abs(r["g_kappa"] - g_kappa) <= 1e-8 * abs(g_kappa)

@@ -264,3 +264,23 @@ def test_c5_full_size_first_steps():
     d = assert_state_equal(g, o, what="c5 full size")
     assert d["n_alive"] > 2.4e8
     g.close()
+
+
+def test_gr_background_bit_identical():
+    """Eq. (6) background with the redshift and the inclination term
+    (i = 0.5 rad, theta_* = 0.67 theta_p, r_g/R_* = 0.4): background, start and
+    100 sorted steps of a warm beam bit-identical to the oracle."""
+    N = 2048
+    cfg = dict(synth.preset("c2"), n_cells=N, q_over_m=synth.q_over_m_for(300.0), ppc=30.0,
+               warm=30 * N, capacity=int(30 * N * 1.3), sort_every=16, rho_kind=synth.RHO_GR, incl=0.5,
+               theta_star=0.67 * 0.014, rg_over_rstar=0.4)
+    x, u = synth.warm_start(cfg)
+    say("gr background", N, len(x))
+    g, o = make_pair(cfg, x, u)
+    d = g.diagnostics(rho=True)
+    assert np.array_equal(d["rho_gj"], o.rho_gj)
+    assert np.array_equal(d["ez"], o.ez)
+    g.step(100)
+    o.step(100)
+    assert_state_equal(g, o, ordered=False, what="gr background")
+    g.close()
