@@ -17,6 +17,8 @@ before the timed region.  Prints one JSON line:
   fp32_bulk      the same tube with the FP32-bulk push (f32 momentum below
                  gamma = 1e6, f64 above), with its own roofline
   ensemble       256 tubes of uneven size, one graph launch per round
+  plausibility   flat-space SCLF over a = omega_p R / c (sec. 3, Table 2): gamma
+                 behind the front and the oscillation amplitude per a
   cpu_baseline   the single-threaded FP64 oracle on the same tube
 """
 import argparse
@@ -133,6 +135,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -209,6 +212,17 @@ def main():
     result["roofline"]["achievable_copy_gbs"] = copy_gbs
     result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / copy_gbs
     log(f"copy kernel {copy_gbs:.0f} GB/s")
+
+    if not args.no_sweep:
+        from paper_1011_6330_amd import sweep
+        rows = sweep.run_sweep([3.5, 5.5, 11.0, 30.0])
+        result["plausibility"] = {"workload": "flat-space SCLF from empty tubes, L = 40R, one grid for all a, "
+                                              "profiles read when the front reaches 30R",
+                                  "rows": [{k: r[k] for k in ("a", "gamma_plateau", "gamma_peak", "gamma_sclf",
+                                                              "gamma_paper", "amplitude", "returning",
+                                                              "e_surf_ratio")} for r in rows]}
+        log("plausibility: " + "; ".join(f"a={r['a']:g}: peak {r['gamma_peak']:.2f} vs sqrt2 a {r['gamma_paper']:.2f}, "
+                                           f"ampl {r['amplitude']:.2f}" for r in rows))
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, x, u, args.cpu_seconds)

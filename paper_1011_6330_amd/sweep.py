@@ -1,0 +1,117 @@
+"""Plausibility sweep over a = omega_p R / c on a batch of tubes (sec. 3).
+
+The paper's flat-space runs (Table 2 and Fig. 3) keep omega_p fixed and widen
+the tube, so a = omega_p R / c grows from about 3.5 to 11 and beyond; gamma
+behind the front rises with a and the profile becomes more oscillatory until
+an instability sets in (sec. 4).  This module runs such a sweep as one batch
+of cold-start SCLF tubes (uniform rho_GJ = -1, empty tube, injection from
+step 1), one tube per value of a, on one grid fine enough that the plasma
+wavelength 2 pi R / a of the largest a stays resolved, and reads the profiles
+when the front has reached 30R in every tube, as the paper does.  Per tube:
+
+  gamma_plateau   mean Lorentz factor behind the front (5R <= z <= front - 5R)
+  gamma_peak      largest binned mean Lorentz factor over the same range
+  gamma_sclf      (sqrt(9 + 8 a^2) - 1) / 2, the steady flat-space SCLF value of
+                  the reduced model (its large-a limit is the paper's sqrt(2) a)
+  amplitude       relative spread (std / mean) of the binned mean gamma over
+                  the same range: the oscillation amplitude
+  returning       fraction of electrons above z = R moving back to the star
+  e_surf_ratio    surface field E_z(dz/2) over its value at t = 0 (SCLF drives
+                  it towards 0)
+
+    python -m paper_1011_6330_amd.sweep --a 3.5 5.5 11 30
+
+Every number comes from the GPU library; nothing here computes the method.
+"""
+import argparse
+import json
+import math
+import sys
+
+import numpy as np
+
+from . import synth
+
+
+def gamma_sclf(a):
+    """Steady SCLF Lorentz factor of the reduced flat-space model (large a: sqrt(2) a - 1/2)."""
+    return (math.sqrt(9.0 + 8.0 * a * a) - 1.0) / 2.0
+
+
+def sclf_tube(a, cells_per_r, length=10.0, ppc=4.0, sort_every=16):
+    """A cold-start flat-space tube of strength a (R = 1, rho_GJ = -1)."""
+    n = int(round(cells_per_r * length))
+    return dict(n_cells=n, length=length, radius=1.0, dt_over_dz=0.5, q_over_m=-a * a / (4.0 * math.pi),
+                ppc=ppc, rho_kind=synth.RHO_UNIFORM, rho_amp=1.0, kappa=0.0, r_star=10.0, fp_bits=32,
+                sort_every=sort_every, capacity=int(12 * ppc * n) + 8192, flags=0, precision=0)
+
+
+def run_sweep(a_values, cells_per_lambda=24.0, min_cells_per_r=50.0, front=30.0, length=40.0, n_bins=200,
+              chunk=512, max_steps=200000, device="cuda"):
+    """Run the batch until the front has crossed `front` radii in every tube
+    (the paper reads its profiles when the front reaches 30R); all tubes share
+    one grid (the finest the largest a needs), so they share the time step.
+    Returns one dict of results per value of a."""
+    from . import Batch
+    cpr = max(min_cells_per_r, cells_per_lambda * max(a_values) / (2.0 * math.pi))
+    cfgs = [sclf_tube(a, cpr, length=length) for a in a_values]
+    N = cfgs[0]["n_cells"]
+    b = Batch([synth.tube_params(c) for c in cfgs], device=device)
+    ez0 = [t.diagnostics(fields=True)["ez"][0] for t in b.tubes]
+    bin_r = length / n_bins
+    steps = 0
+    while steps < max_steps:
+        b.step(chunk)
+        steps += chunk
+        fronts = []
+        for t in b.tubes:
+            cnt = t.diagnostics(n_bins=n_bins, fields=False)["prof_count"]
+            nz = np.flatnonzero(cnt)
+            fronts.append((nz[-1] + 1) * bin_r if len(nz) else 0.0)
+        if min(fronts) >= front:
+            break
+    b.sync()
+    out = []
+    for a, c, t, e0 in zip(a_values, cfgs, b.tubes, ez0):
+        d = t.diagnostics(n_bins=n_bins, fields=True)
+        x, u = t.read_particles()
+        z = x / (N / c["length"])
+        zf = float(np.quantile(z, 0.999)) if len(z) else 0.0
+        centers = (np.arange(n_bins) + 0.5) * bin_r
+        sel = (centers >= 5.0) & (centers <= zf - 5.0) & (d["prof_count"] > 0)
+        gam = np.abs(d["prof_mean"][sel])
+        plateau = float(np.average(gam, weights=d["prof_count"][sel])) if sel.any() else float("nan")
+        peak = float(gam.max()) if sel.any() else float("nan")
+        amp = float(gam.std() / gam.mean()) if sel.sum() > 2 else float("nan")
+        above = z > 1.0
+        ret = float((u[above] < 0).sum() / max(above.sum(), 1))
+        out.append(dict(a=float(a), n_cells=N, steps=steps, time=steps * 0.5 * c["length"] / N,
+                        particles=int(d["n_alive"]), front=zf, gamma_plateau=plateau, gamma_peak=peak,
+                        gamma_sclf=gamma_sclf(a),
+                        gamma_paper=math.sqrt(2.0) * a, amplitude=amp, returning=ret,
+                        e_surf_ratio=float(d["ez"][0] / e0) if e0 != 0 else float("nan")))
+    b.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--a", type=float, nargs="+", default=[3.5, 5.5, 11.0, 30.0])
+    ap.add_argument("--front", type=float, default=30.0, help="radii the front must cross")
+    ap.add_argument("--json", action="store_true")
+    args = ap.parse_args(argv)
+    rows = run_sweep(args.a, front=args.front)
+    if args.json:
+        print(json.dumps(rows))
+        return 0
+    print(f"{'a':>7} {'cells':>6} {'steps':>6} {'front/R':>8} {'gamma':>9} {'peak':>9} {'gamma*':>8} "
+          f"{'sqrt2 a':>8} {'ampl':>7} {'return':>7} {'E(0)/E0':>8}")
+    for r in rows:
+        print(f"{r['a']:7.2f} {r['n_cells']:6d} {r['steps']:6d} {r['front']:8.2f} {r['gamma_plateau']:9.3f} "
+              f"{r['gamma_peak']:9.3f} {r['gamma_sclf']:8.3f} {r['gamma_paper']:8.3f} {r['amplitude']:7.3f} "
+              f"{r['returning']:7.4f} {r['e_surf_ratio']:8.4f}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
