@@ -181,6 +181,31 @@ static void orc_solve_fields(const orc_cfg *c, orc_state *st)
     for (int64_t i = 0; i < N; ++i) st->ez[i] = -((st->phi[i + 1] - st->phi[i]) / k.dz);
     for (int64_t i = 0; i <= N; ++i) st->er[i] = st->phi[i] / c->radius;
     for (int64_t i = 0; i < N; ++i) { st->b[i] = 0.0; st->j[i] = 0; st->k[i] = k.qmdt * st->ez[i]; }
+    if (c->flags & ORC_B_STEADY_INIT) {
+        /* Steady start of eq. (3): with dE_z/dt = 0 the E_z update gives B_phi = 4 pi R j.
+         * j is the current the loaded beam carries: the charge-conserving current of one
+         * drift step with the particles' own velocities and no kick.  In the update's units,
+         * (dt/R) B = 4 pi q_m 2^-P J. */
+        for (int64_t p = 0; p < st->n; ++p) {
+            double x = st->x[p], u = st->u[p];
+            double t = u * u;
+            t = 1.0 + t;
+            double gam = sqrt(t);
+            double v = u / gam;
+            double x1 = x + k.dtdz * v;
+            int64_t c0, F0, c1, F1;
+            orc_cell(x, c->fp_bits, &c0, &F0);
+            orc_cell(x1, c->fp_bits, &c1, &F1);
+            int64_t lo = c0 < c1 ? c0 : c1, hi = c0 < c1 ? c1 : c0;
+            if (lo < 0) lo = 0;
+            if (hi > N - 1) hi = N - 1;
+            for (int64_t i = lo; i <= hi; ++i) st->j[i] += orc_S(i, c0, F0, k.oneP) - orc_S(i, c1, F1, k.oneP);
+        }
+        for (int64_t i = 0; i < N; ++i) {
+            st->b[i] = (k.c4 * (double)st->j[i]) / k.dtR;
+            st->j[i] = 0;
+        }
+    }
 }
 
 int orc_init(const orc_cfg *c, orc_state *st)

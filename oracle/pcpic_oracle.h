@@ -41,7 +41,8 @@ enum {
 
 enum {
     ORC_NO_AUTO_INJECT = 1u, /* skip the SCLF injection                                  */
-    ORC_FREEZE_FIELDS = 2u   /* skip the Maxwell update: fields stay as they are           */
+    ORC_FREEZE_FIELDS = 2u,  /* skip the Maxwell update: fields stay as they are           */
+    ORC_B_STEADY_INIT = 4u   /* start B_phi = 4 pi R j of the loaded beam (steady E_z)     */
 };
 
 enum {

@@ -33,7 +33,7 @@ FORWARD = [
     ("gather between nodes instead of faces",
      "double s = x - 0.5, E;", "double s = x, E;"),
     ("move with u instead of v = u / gamma",
-     "        double x1 = x + k.dtdz * v;", "        double x1 = x + k.dtdz * u1;"),
+     "double v = u1 / gam;\n        double x1 = x + k.dtdz * v;", "double v = u1 / gam;\n        double x1 = x + k.dtdz * u1;"),
     ("cumulative weight off by one cell",
      "if (cell > i) return 0;", "if (cell > i + 1) return 0;"),
     ("sign of the background term of the surface field",
@@ -51,6 +51,10 @@ FORWARD = [
      "double br = fd + s * sqrt(eta);", "double br = fd + s * eta;"),
     ("redshift with r_g r instead of r_g / r",
      "double al = sqrt(1.0 - c->rg_over_rstar / eta);", "double al = sqrt(1.0 - c->rg_over_rstar * eta);"),
+    ("steady start drifting with u instead of v",
+     "double v = u / gam;\n            double x1 = x + k.dtdz * v;", "double v = u / gam;\n            double x1 = x + k.dtdz * u;"),
+    ("steady start B = J / (R dt) without the 4 pi q_m 2^-P factor",
+     "st->b[i] = (k.c4 * (double)st->j[i]) / k.dtR;", "st->b[i] = ((double)st->j[i]) / k.dtR;"),
     ("sin(i) instead of tan(i) after dividing eq. 6 by cos(i)",
      "((1.5 * c->theta_star) * tan(c->incl))", "((1.5 * c->theta_star) * sin(c->incl))"),
 ]

@@ -467,6 +467,48 @@ def test_rho_gj_gr_sin_i_term(oracle_mod):
     assert abs(d5[0] / base[0]) < 0.01                           # sin(i) term << cos(i) term at the surface
 
 
+def _uniform_beam(N, n_per_cell, u0):
+    x = (np.arange(N * n_per_cell) + 0.5) / n_per_cell
+    return x, np.full(len(x), u0)
+
+
+def test_b_steady_init_equals_4pi_r_j(oracle_mod):
+    """Steady start of eq. (3): dE_z/dt = B/R - 4 pi j = 0 gives B_phi = 4 pi R j.
+    A uniform beam of n electrons per cell at u0 carries j = rho v with
+    rho = q_m n / dz and v = u0 / sqrt(1 + u0^2)."""
+    o = oracle_mod
+    N, n, u0, R = 64, 8, 3.0, 0.7
+    kw = dict(n_cells=N, length=N / 50.0, radius=R, q_over_m=-40.0, ppc=8.0, capacity=N * n + 16,
+              flags=o.NO_AUTO_INJECT)
+    t = _tube(oracle_mod, flags=o.NO_AUTO_INJECT | o.B_STEADY_INIT, **{k: v for k, v in kw.items() if k != "flags"})
+    x, u = _uniform_beam(N, n, u0)
+    t.inject(x, u)
+    dz = kw["length"] / N
+    qm = -1.0 * dz / kw["ppc"]                   # rho_GJ(0) dz / ppc with rho_GJ = -1
+    v = u0 / np.sqrt(1 + u0 * u0)
+    want = 4 * np.pi * R * (qm * n / dz) * v
+    inner = t.b[2:N - 2]
+    np.testing.assert_allclose(inner, want, rtol=1e-8)
+    assert np.all(t.j == 0)
+
+
+def test_b_steady_init_starts_steady(oracle_mod):
+    """With the steady B the first step leaves E_z nearly unchanged in the
+    interior; without it the beam's current drives E_z at once."""
+    o = oracle_mod
+    N, n = 128, 8
+    x, u = _uniform_beam(N, n, 20.0)
+    dez = []
+    for flags in (o.NO_AUTO_INJECT, o.NO_AUTO_INJECT | o.B_STEADY_INIT):
+        t = _tube(oracle_mod, n_cells=N, length=N / 50.0, q_over_m=-40.0, ppc=8.0, capacity=N * n + 16,
+                  flags=flags)
+        t.inject(x, u)
+        e0 = t.ez.copy()
+        t.step(1)
+        dez.append(np.abs(t.ez - e0)[4:N - 4].max())
+    assert dez[1] < 1e-3 * dez[0], dez
+
+
 def test_exit_and_absorb(oracle_mod):
     o = oracle_mod
     N = 32
