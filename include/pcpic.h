@@ -86,7 +86,10 @@ enum {
 /* pic_params.flags */
 enum {
     PIC_NO_AUTO_INJECT = 1u, /* no SCLF injection (E_surf is still computed)         */
-    PIC_FREEZE_FIELDS = 2u   /* skip the Maxwell update; fields keep their values     */
+    PIC_FREEZE_FIELDS = 2u,  /* skip the Maxwell update; fields keep their values     */
+    PIC_B_STEADY_INIT = 4u   /* warm start: B_phi = 4 pi R j of the loaded beam, so that
+                                dE_z/dt = 0 at t = 0 (eq. 3); j is the current of one
+                                drift step at the particles' velocities, without a kick */
 };
 
 /* Tube description.  Copied by pic_init; the knot array is copied too. */
@@ -109,7 +112,7 @@ typedef struct pic_params {
     int32_t fp_bits;          /* P, fraction bits of the fixed-point weights: 16..36         */
     int32_t sort_every;       /* cell sort + compaction period in steps (0 = never)          */
     int64_t capacity;         /* particle capacity (live + not yet compacted)                */
-    uint32_t flags;           /* PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS                      */
+    uint32_t flags;           /* PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS | PIC_B_STEADY_INIT  */
     int32_t max_bins;         /* largest signed-gamma profile pic_diagnostics may request    */
     double gamma_fp64;        /* PIC_FP32_BULK: gamma from which u is kept in f64 (0 = 1e6)  */
     double macro_charge;      /* q_m (per unit area); 0 = rho_GJ(0) dz / ppc.  A fixed value

@@ -141,6 +141,70 @@ __global__ __launch_bounds__(256) void k_thomas_batch(const TubeDev *tubes, cons
     thomas_block(T.c, T.rhs, T.cp, T.dp, T.phi);
 }
 
+// Current of one drift step of the loaded beam, no kick (steady start,
+// PIC_B_STEADY_INIT): J_{i+1/2} += S_i(x) - S_i(x + (dt/dz) v), v = u / sqrt(1 + u^2),
+// in the push's fixed point.  One atomic per touched face (once per run).
+__device__ __forceinline__ void drift_current(const Consts &c, double x, double u, unsigned long long *J)
+{
+    const int64_t N = c.N;
+    double t = u * u;
+    t = 1.0 + t;
+    const double gam = sqrt(t);
+    const double v = u / gam;
+    const double x1 = x + c.dtdz * v;
+    const double c0d = floor(x), c1d = floor(x1);
+    const int64_t c0 = (int64_t)c0d, c1 = (int64_t)c1d;
+    const double F0 = rint((x - c0d) * c.twoP), F1 = rint((x1 - c1d) * c.twoP);
+    double va, vb = 0.0;
+    bool hb = false;
+    if (c1 == c0) {
+        va = F1 - F0;
+    } else if (c1 > c0) {
+        va = c.twoP - F0;
+        if (c1 < N) { vb = F1; hb = true; }
+    } else {
+        va = -F0;
+        if (c1 >= 0) { vb = F1 - c.twoP; hb = true; }
+    }
+    if (va != 0.0) atomicAdd(J + c0, (unsigned long long)(long long)va);
+    if (hb && vb != 0.0) atomicAdd(J + c1, (unsigned long long)(long long)vb);
+}
+
+__global__ __launch_bounds__(256) void k_drift_current_f64(Consts c, const double *X, const double *U,
+                                                           const DevCounters *ctr, unsigned long long *J)
+{
+    const int64_t n = ctr->n_slots;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const double x = X[p];
+        if (x >= 0.0) drift_current(c, x, U[p], J);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_drift_current_f32(Consts c, const int *CL, const float *OL, const float *UL,
+                                                           const int *CH, const float *OH, const double *UH,
+                                                           const DevCounters *ctr, unsigned long long *J)
+{
+    const int64_t nl = ctr->n_slots, nh = ctr->n_slots_hi;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nl + nh; p += (int64_t)gridDim.x * 256) {
+        const bool hi = p >= nl;
+        const int64_t q = hi ? p - nl : p;
+        const int cell = hi ? CH[q] : CL[q];
+        if (cell < 0) continue;
+        const double x = (double)cell + (double)(hi ? OH[q] : OL[q]);
+        drift_current(c, x, hi ? UH[q] : (double)UL[q], J);
+    }
+}
+
+// B_phi = 4 pi R j: (dt/R) B = 4 pi q_m 2^-P J, then J is cleared.
+__global__ __launch_bounds__(256) void k_b_from_current(Consts c, int64_t *J, double *b)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < c.N) {
+        b[i] = (c.c4 * (double)J[i]) / c.dtR;
+        J[i] = 0;
+    }
+}
+
 // E_z = -dphi/dz at faces, E_r = phi/R at nodes, B_phi = 0, J = 0, kick array.
 __global__ __launch_bounds__(256) void k_fields_from_phi(Consts c, const double *phi, double *ez,
                                                          double *er, double *b, double *k64, float *k32,
@@ -248,6 +312,19 @@ hipError_t launch_fields_from_phi(pic_handle *h)
     hipLaunchKernelGGL(k_fields_from_phi, dim3(grid_for(c.N + 1, 256)), dim3(256), 0, h->stream, c,
                        w.phi, w.ez[f], w.er[f], w.b[f], w.k64,
                        h->p.precision == PIC_FP32_BULK ? w.k32 : nullptr, w.j[0], w.j[1]);
+    if (c.flags & PIC_B_STEADY_INIT) {
+        // steady start: B_phi from the current the loaded beam carries (J is clear here)
+        unsigned long long *J = (unsigned long long *)w.j[h->jbuf];
+        const unsigned g = (unsigned)(h->n_cu * 8);
+        const int b = h->pbuf;
+        if (h->p.precision == PIC_FP32_BULK)
+            hipLaunchKernelGGL(k_drift_current_f32, dim3(g), dim3(256), 0, h->stream, c, w.cl[b], w.ol[b], w.ul[b],
+                               w.ch[b], w.oh[b], w.uh[b], w.ctr, J);
+        else
+            hipLaunchKernelGGL(k_drift_current_f64, dim3(g), dim3(256), 0, h->stream, c, w.x[b], w.u[b], w.ctr, J);
+        hipLaunchKernelGGL(k_b_from_current, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, w.j[h->jbuf],
+                           w.b[f]);
+    }
     return hipGetLastError();
 }
 

@@ -71,7 +71,8 @@ pic_status validate(const pic_params *p)
         return fail(PIC_EINVAL, "capacity %lld out of range", (long long)p->capacity);
     if (p->sort_every < 0) return fail(PIC_EINVAL, "sort_every must be >= 0");
     if (p->max_bins < 0 || p->max_bins > (1 << 20)) return fail(PIC_EINVAL, "max_bins out of range");
-    if (p->flags & ~(PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS)) return fail(PIC_EINVAL, "unknown flag bits");
+    if (p->flags & ~(PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS | PIC_B_STEADY_INIT))
+        return fail(PIC_EINVAL, "unknown flag bits");
     return PIC_OK;
 }
 

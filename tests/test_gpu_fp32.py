@@ -205,3 +205,19 @@ def test_fp32_c5_gauss_drift():
         assert d["gauss_max"] <= bound
         assert d["n_alive"] > 2.4e8
     t.close()
+
+
+def test_fp32_b_steady_init():
+    """The steady start from the FP32-bulk streams: B_phi of the loaded beam
+    within f32 position rounding of the oracle's, and the first steps per result."""
+    cfg = _warm_beam(flags=4, gamma_fp64=1000.0)
+    x, u = synth.warm_start(cfg)
+    g, o = _pair(cfg, x, u)
+    d = g.diagnostics()
+    rel = np.linalg.norm(d["b_phi"] - o.b) / np.linalg.norm(o.b)
+    say("fp32 steady B normwise", rel)
+    assert rel <= 1e-6
+    g.step(50)
+    o.step(50)
+    _gate(_errors(g, o), "fp32 steady start step 50")
+    g.close()

@@ -284,3 +284,21 @@ def test_gr_background_bit_identical():
     o.step(100)
     assert_state_equal(g, o, ordered=False, what="gr background")
     g.close()
+
+
+def test_b_steady_init_bit_identical():
+    """Warm start with B_phi = 4 pi R j of the loaded beam (PIC_B_STEADY_INIT):
+    the starting fields and 60 sorted steps bit-identical to the oracle."""
+    N = 2048
+    cfg = dict(synth.preset("c2"), n_cells=N, q_over_m=synth.q_over_m_for(300.0), ppc=30.0,
+               warm=30 * N, capacity=int(30 * N * 1.3), sort_every=16, flags=4)
+    x, u = synth.warm_start(cfg)
+    say("b steady init", N, len(x))
+    g, o = make_pair(cfg, x, u)
+    d = g.diagnostics()
+    assert np.array_equal(d["b_phi"], o.b) and np.abs(o.b).max() > 0
+    assert np.array_equal(d["ez"], o.ez) and np.array_equal(d["er"], o.er)
+    g.step(60)
+    o.step(60)
+    assert_state_equal(g, o, ordered=False, what="b steady init")
+    g.close()
