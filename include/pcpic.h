@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define PCPIC_ABI_VERSION 2
+#define PCPIC_ABI_VERSION 3
 
 typedef int32_t pic_status;
 enum {
@@ -151,6 +151,7 @@ typedef struct pic_diag {
     double exit_gamma_sum; /* the same sum / 2^32 as a double                              */
     double gauss_max;      /* max |G_i| / (4 pi max|rho_GJ|), nodes 1..N-1 (want_gauss)    */
     int64_t n_slots_high;  /* PIC_FP32_BULK: occupied slots of the f64-momentum stream      */
+    double gauss_l2;       /* sqrt(mean over nodes 1..N-1 of G_i^2) / (4 pi max|rho_GJ|) (want_gauss) */
     double *ez;            /* [N]   E_z at faces                                           */
     double *er;            /* [N+1] E_r at nodes                                           */
     double *b_phi;         /* [N]   B_phi at faces                                         */

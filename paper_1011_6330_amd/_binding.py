@@ -15,7 +15,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libpcpic.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 FP64, FP32_BULK = 0, 1
 RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS, RHO_GR = 0, 1, 2, 3
 NO_AUTO_INJECT, FREEZE_FIELDS, B_STEADY_INIT = 1, 2, 4
@@ -62,7 +62,7 @@ class PicDiag(ctypes.Structure):
                 ("w0", ctypes.c_int64), ("status", ctypes.c_int64), ("e_surf", ctypes.c_double),
                 ("exit_sum_lo", ctypes.c_uint64), ("exit_sum_hi", ctypes.c_int64),
                 ("exit_gamma_sum", ctypes.c_double), ("gauss_max", ctypes.c_double),
-                ("n_slots_high", ctypes.c_int64), ("ez", _pd), ("er", _pd), ("b_phi", _pd), ("rho_gj", _pd), ("j_last", _pi),
+                ("n_slots_high", ctypes.c_int64), ("gauss_l2", ctypes.c_double), ("ez", _pd), ("er", _pd), ("b_phi", _pd), ("rho_gj", _pd), ("j_last", _pi),
                 ("weights", _pi), ("gauss", _pd), ("prof_count", _pi), ("prof_mean", _pd),
                 ("prof_min", _pd), ("prof_max", _pd), ("prof_sum_lo", _pu), ("prof_sum_hi", _pi)]
 
@@ -319,7 +319,7 @@ class Tube(_TubeOps):
             _check(rc, "pic_diagnostics")
         for k in ("step", "n_alive", "n_slots", "n_injected", "n_exit", "n_absorb", "last_n_inj", "w0",
                   "status", "e_surf", "exit_sum_lo", "exit_sum_hi", "exit_gamma_sum", "gauss_max",
-                  "n_slots_high"):
+                  "gauss_l2", "n_slots_high"):
             out[k] = getattr(d, k)
         return out
 

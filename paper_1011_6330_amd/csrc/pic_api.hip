@@ -571,7 +571,15 @@ pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out
     if (out->j_last)
         HIP_OK(hipMemcpyAsync(out->j_last, w.j[1 - h->jbuf], (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
     if (out->weights) HIP_OK(hipMemcpyAsync(out->weights, w.w, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
-    if (out->gauss) HIP_OK(hipMemcpyAsync(out->gauss, w.gauss, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    // The L2 norm of the residual is summed on the host in node order, so it
+    // does not depend on a device reduction order.
+    std::vector<double> gtmp;
+    double *gdst = out->gauss;
+    if (want_gauss && !gdst) {
+        gtmp.resize((size_t)(N + 1));
+        gdst = gtmp.data();
+    }
+    if (gdst) HIP_OK(hipMemcpyAsync(gdst, w.gauss, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
     std::vector<long long> cnt(nb), hi(nb), mn(nb), mx(nb);
     std::vector<unsigned long long> lo(nb);
     if (nb > 0) {
@@ -599,6 +607,12 @@ pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out
     const double rmax = __builtin_bit_cast(double, ctr.rho_max_bits);
     const double gmax = __builtin_bit_cast(double, ctr.gauss_max_bits);
     out->gauss_max = (want_gauss || out->gauss) ? gmax / (h->c.fourpi * rmax) : 0.0;
+    out->gauss_l2 = 0.0;
+    if (gdst && N > 1) {
+        double ss = 0.0;
+        for (int64_t i = 1; i < N; ++i) ss += gdst[i] * gdst[i];
+        out->gauss_l2 = sqrt(ss / (double)(N - 1)) / (h->c.fourpi * rmax);
+    }
     for (int k = 0; k < nb; ++k) {
         if (out->prof_count) out->prof_count[k] = cnt[k];
         if (out->prof_sum_lo) out->prof_sum_lo[k] = lo[k];

@@ -41,7 +41,9 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.pic_abi_version() == 2
+    from paper_1011_6330_amd import _binding
+    m = re.search(r"#define PCPIC_ABI_VERSION (\d+)", open(os.path.join(ROOT, "include", "pcpic.h")).read())
+    assert lib.pic_abi_version() == int(m.group(1)) == _binding.ABI_VERSION == 3
 
 
 def _params(**kw):
@@ -81,7 +83,7 @@ def test_init_rejects_bad_abi_and_workspace(lib):
     p.abi_version = 99
     h = ctypes.c_void_p()
     assert lib.pic_init(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == -8     # PIC_EABI
-    p.abi_version = 2
+    p.abi_version = lib.pic_abi_version()
     assert lib.pic_init(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == -2     # PIC_EWORKSPACE
     assert lib.pic_init(ctypes.byref(p), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(h)) == -2  # misaligned
     assert b"aligned" in lib.pic_last_error()

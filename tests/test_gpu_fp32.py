@@ -201,7 +201,8 @@ def test_fp32_c5_gauss_drift():
         t.step(100)
         d = t.diagnostics(fields=False, gauss=True)
         bound = 10 * eps * r_dz ** 2 + 10 * eps * r_dz * np.sqrt(n)
-        say("fp32 c5 step", n, "gauss", d["gauss_max"], "bound", bound, "high", d["n_slots_high"])
+        say("fp32 c5 step", n, "gauss max", d["gauss_max"], "L2", d["gauss_l2"], "bound", bound,
+            "high", d["n_slots_high"])
         assert d["gauss_max"] <= bound
         assert d["n_alive"] > 2.4e8
     t.close()
