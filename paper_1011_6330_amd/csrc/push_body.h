@@ -33,93 +33,114 @@ __device__ __forceinline__ void hist_add(unsigned long long *hist, const int64_t
     }
 }
 
-// One tile of BLOCK*PPT consecutive slots starting at tile0 (< n).  Called by
-// every thread of a block of BLOCK threads; wave-collective at the end.
+// Kick at x: linear interpolation between face values, clamped at the ends.
+// Also called for an empty slot (x = -1), whose face index clamps to 0, so the
+// loads of every slot can be issued together before any particle is pushed.
+__device__ __forceinline__ double gather_f64(const Consts &c, const double *__restrict__ K, double x)
+{
+    const int N = (int)c.N;
+    const double Nm1 = (double)(c.N - 1);
+    const double s = x - 0.5;
+    const int jj = (int)floor(s);
+    const double g = s - (double)jj;
+    const int jc = jj < 0 ? 0 : (jj > N - 2 ? N - 2 : jj);
+    const double k0 = K[jc], k1 = K[jc + 1];
+    const double Ei = k0 + g * (k1 - k0);
+    const double lo = s < 0.0 ? k0 : Ei;
+    return s >= Nm1 ? k1 : lo;
+}
+
+// Push of one particle (x, u) in place with the gathered kick E: kick and move
+// (eq. 1), current deposit, removal at the ends (x = -1) and the node-0 tally.
+// x < 0 marks an empty slot and is left alone.
+__device__ __forceinline__ void push_one_f64(const Consts &c, const PushArgs &a, double E, double &xr, double &ur,
+                                             DepAcc &acc)
+{
+    const int N = (int)c.N;
+    const double Nd = (double)c.N;
+    const double x = xr, u = ur;
+    if (!(x >= 0.0)) return;                     // removed slot (-1) or past the end
+    // eq. (1): u = gamma v, du/dt = (q/m) E_z, dz/dt = v
+    const double u1 = u + E;
+    double tt = u1 * u1;
+    tt = 1.0 + tt;
+    const double gam = sqrt(tt);
+    const double v = u1 / gam;
+    const double x1 = x + c.dtdz * v;
+    if (!isfinite(u1) || !isfinite(x1)) {
+        acc.bad = true;
+        acc.nlost += 1.0;
+        xr = -1.0;
+        return;
+    }
+    const double c0d = floor(x);
+    const double F0 = rint((x - c0d) * c.twoP);
+    const double c1d = floor(x1);
+    const int c1 = (int)c1d;
+    const double F1 = rint((x1 - c1d) * c.twoP);
+    acc.deposit(a.J, N, c.twoP, (int)c0d, F0, c1, F1);
+    if (x1 >= Nd) {                              // leaves through z = L
+        acc.exit_gamma(gam);
+        xr = -1.0;
+    } else if (x1 < 0.0) {                       // returns to the star
+        acc.nabs += 1.0;
+        xr = -1.0;
+    } else {
+        if (c1 == 0) acc.w0 += c.twoP - F1;
+        xr = x1;
+        ur = u1;
+    }
+}
+
+// One tile of BLOCK*PPT consecutive slots starting at tile0 (< n).  Thread t
+// takes PPT/2 pairs of consecutive slots, pair v at tile0 + 2 (v BLOCK + t), so
+// each pair is one 16-byte vector per stream and a wave's pair v covers 128
+// consecutive slots.  Every pair of the thread is loaded before the first is
+// pushed (PPT/2 vectors per stream in flight); the current of pair v is
+// flushed before pair v+1 is pushed, so a flush sees the few cells 128
+// consecutive slots span.  Called by every thread of a block of BLOCK threads;
+// wave-collective.
 template <int BLOCK, int PPT, int NT>
 __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a, int64_t n, int64_t tile0)
 {
-    const int N = (int)c.N;
-    const double Nd = (double)c.N, Nm1 = (double)(c.N - 1);
-    const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
-    const bool full = p0 + PPT <= n;
-
+    static_assert(PPT % 2 == 0, "slots are taken in pairs");
+    constexpr int V = PPT / 2;
     double xs[PPT], us[PPT];
-    if (full) {
 #pragma unroll
-        for (int k = 0; k < PPT; k += 2) {
-            const dvec2 xv = ld16<NT, dvec2>(a.X + p0 + k);
-            const dvec2 uv = ld16<NT, dvec2>(a.U + p0 + k);
-            xs[k] = xv.x; xs[k + 1] = xv.y;
-            us[k] = uv.x; us[k + 1] = uv.y;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            xs[k] = p0 + k < n ? a.X[p0 + k] : -1.0;
-            us[k] = p0 + k < n ? a.U[p0 + k] : 0.0;
+    for (int v = 0; v < V; ++v) {
+        const int64_t e = tile0 + 2 * ((int64_t)v * BLOCK + threadIdx.x);
+        if (e + 2 <= n) {
+            const dvec2 xv = ld16<NT, dvec2>(a.X + e);
+            const dvec2 uv = ld16<NT, dvec2>(a.U + e);
+            xs[2 * v] = xv.x; xs[2 * v + 1] = xv.y;
+            us[2 * v] = uv.x; us[2 * v + 1] = uv.y;
+        } else {
+            xs[2 * v] = e < n ? a.X[e] : -1.0;
+            us[2 * v] = e < n ? a.U[e] : 0.0;
+            xs[2 * v + 1] = e + 1 < n ? a.X[e + 1] : -1.0;
+            us[2 * v + 1] = e + 1 < n ? a.U[e + 1] : 0.0;
         }
     }
+
+    double E[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) E[k] = gather_f64(c, a.K, xs[k]);
 
     DepAcc acc;
     acc.init();
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const double x = xs[k], u = us[k];
-        if (!(x >= 0.0)) continue;               // removed slot (-1) or past the end
-        // gather: linear interpolation between face values, clamped at the ends
-        const double s = x - 0.5;
-        const int jj = (int)floor(s);
-        const double g = s - (double)jj;
-        const int jc = jj < 0 ? 0 : (jj > N - 2 ? N - 2 : jj);
-        const double k0 = a.K[jc], k1 = a.K[jc + 1];
-        const double Ei = k0 + g * (k1 - k0);
-        const double E = s < 0.0 ? k0 : (s >= Nm1 ? k1 : Ei);
-        // eq. (1): u = gamma v, du/dt = (q/m) E_z, dz/dt = v
-        const double u1 = u + E;
-        double tt = u1 * u1;
-        tt = 1.0 + tt;
-        const double gam = sqrt(tt);
-        const double v = u1 / gam;
-        const double x1 = x + c.dtdz * v;
-        if (!isfinite(u1) || !isfinite(x1)) {
-            acc.bad = true;
-            acc.nlost += 1.0;
-            xs[k] = -1.0;
-            continue;
-        }
-        const double c0d = floor(x);
-        const double F0 = rint((x - c0d) * c.twoP);
-        const double c1d = floor(x1);
-        const int c1 = (int)c1d;
-        const double F1 = rint((x1 - c1d) * c.twoP);
-        acc.deposit(a.J, N, c.twoP, (int)c0d, F0, c1, F1);
-        if (x1 >= Nd) {                          // leaves through z = L
-            acc.exit_gamma(gam);
-            xs[k] = -1.0;
-        } else if (x1 < 0.0) {                   // returns to the star
-            acc.nabs += 1.0;
-            xs[k] = -1.0;
+    for (int v = 0; v < V; ++v) {
+        push_one_f64(c, a, E[2 * v], xs[2 * v], us[2 * v], acc);
+        push_one_f64(c, a, E[2 * v + 1], xs[2 * v + 1], us[2 * v + 1], acc);
+        acc.flush_current(a.J);
+        // write back (removed particles get x = -1; their u is left as it was)
+        const int64_t e = tile0 + 2 * ((int64_t)v * BLOCK + threadIdx.x);
+        if (e + 2 <= n) {
+            st16<NT, dvec2>(a.Xo + e, dvec2{xs[2 * v], xs[2 * v + 1]});
+            st16<NT, dvec2>(a.Uo + e, dvec2{us[2 * v], us[2 * v + 1]});
         } else {
-            if (c1 == 0) acc.w0 += c.twoP - F1;
-            xs[k] = x1;
-            us[k] = u1;
-        }
-    }
-
-    // write back (removed particles get x = -1; their u is left as it was)
-    if (full) {
-#pragma unroll
-        for (int k = 0; k < PPT; k += 2) {
-            st16<NT, dvec2>(a.Xo + p0 + k, dvec2{xs[k], xs[k + 1]});
-            st16<NT, dvec2>(a.Uo + p0 + k, dvec2{us[k], us[k + 1]});
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (p0 + k < n) {
-                a.Xo[p0 + k] = xs[k];
-                a.Uo[p0 + k] = us[k];
-            }
+            if (e < n) { a.Xo[e] = xs[2 * v]; a.Uo[e] = us[2 * v]; }
+            if (e + 1 < n) { a.Xo[e + 1] = xs[2 * v + 1]; a.Uo[e + 1] = us[2 * v + 1]; }
         }
     }
     if (a.hist) {
@@ -132,7 +153,7 @@ __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a
         }
         hist_add<PPT>(a.hist, key, live);
     }
-    acc.flush(a.J, a.ctr);
+    acc.flush_tallies(a.ctr);
 }
 
 

@@ -73,22 +73,42 @@ struct DepAcc {
 
     // Wave-collective: must be reached by all 64 lanes of the wave.  Lanes
     // with the same first cell in consecutive positions form a run; the run's
-    // head adds the run's sums of the three channels (one atomic per face and
-    // run, however many cells the wave spans).
-    __device__ __forceinline__ void flush(unsigned long long *J, DevCounters *ctr)
+    // last lane adds the run's sums of the three channels (one atomic per face
+    // and run, however many cells the wave spans).  A wave that is one run
+    // (the common case between sorts) takes plain wave sums.  The channels
+    // start afresh.
+    __device__ __forceinline__ void flush_current(unsigned long long *J)
     {
-        const int lane = __lane_id();
         const bool has = cf != -2;
-        const WaveRun r = wave_runs(cf, has);
+        const int lane = (int)__lane_id();
+        const WaveRun r = wave_runs_i32(cf, has);
         double sm = am, s0 = a0, sp = ap;
-        if (__ballot(am != 0.0)) sm = run_sum_to_head(sm, r.end);
-        if (__ballot(a0 != 0.0)) s0 = run_sum_to_head(s0, r.end);
-        if (__ballot(ap != 0.0)) sp = run_sum_to_head(sp, r.end);
-        if (has && r.is_head) {
+        const bool one_run = __ballot(r.is_head) == 1ull && __ballot(has) == ~0ull;
+        bool tail;
+        if (one_run) {
+            if (__ballot(am != 0.0)) sm = wave_sum_f64_to63(sm);
+            if (__ballot(a0 != 0.0)) s0 = wave_sum_f64_to63(s0);
+            if (__ballot(ap != 0.0)) sp = wave_sum_f64_to63(sp);
+            tail = lane == 63;
+        } else {
+            if (__ballot(am != 0.0)) sm = run_sum_to_tail(sm, r.rank);
+            if (__ballot(a0 != 0.0)) s0 = run_sum_to_tail(s0, r.rank);
+            if (__ballot(ap != 0.0)) sp = run_sum_to_tail(sp, r.rank);
+            tail = has && lane == r.end - 1;
+        }
+        if (tail) {
             if (sm != 0.0) atomic_add_face(J, cf - 1, sm);
             if (s0 != 0.0) atomic_add_face(J, cf, s0);
             if (sp != 0.0) atomic_add_face(J, cf + 1, sp);
         }
+        cf = -2;
+        am = a0 = ap = 0.0;
+    }
+
+    // Wave-collective: the boundary tallies of the wave, one atomic each.
+    __device__ __forceinline__ void flush_tallies(DevCounters *ctr)
+    {
+        const int lane = __lane_id();
         const unsigned long long any = __ballot(w0 != 0.0 || nexit != 0.0 || nabs != 0.0 || nlost != 0.0);
         if (any) {
             const double sw0 = wave_sum_f64_to63(w0);
@@ -110,6 +130,12 @@ struct DepAcc {
             }
         }
         if (__ballot(bad) && lane == 0) atomicOr(&ctr->status, (unsigned long long)PIC_ST_NONFINITE);
+    }
+
+    __device__ __forceinline__ void flush(unsigned long long *J, DevCounters *ctr)
+    {
+        flush_current(J);
+        flush_tallies(ctr);
     }
 };
 

@@ -134,4 +134,56 @@ __device__ __forceinline__ double wave_sum_f64_to63(double v)
     return v;
 }
 
+// Value of lane - 1 (lane 0 reads 0): DPP wave_shr:1.
+__device__ __forceinline__ int wave_shr1_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+
+// Runs of equal int keys over consecutive lanes, as wave_runs, with the lane
+// shift done by DPP instead of a cross-lane permute through LDS.
+__device__ __forceinline__ WaveRun wave_runs_i32(int key, bool want)
+{
+    const int lane = (int)__lane_id();
+    const unsigned long long wm = __ballot(want);
+    const int kprev = wave_shr1_i32(key);
+    const bool prev_want = lane > 0 && ((wm >> (lane - 1)) & 1ull);
+    const bool head = want && (!prev_want || kprev != key);
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0..lane
+    const unsigned long long brk = (hm | ~wm) & ~upto;                              // breaks above the lane
+    WaveRun r;
+    r.is_head = head;
+    r.head = 63 - __clzll(hm & upto);
+    r.rank = lane - r.head;
+    r.end = brk ? __ffsll(brk) - 1 : 64;
+    return r;
+}
+
+// Sum of v over [head, lane] inside the lane's run (head = lane - rank): a
+// segmented inclusive scan on DPP, row_shr 1, 2, 4, 8 inside each row of 16
+// lanes, then row_bcast:15 (rows 0 -> 1, 2 -> 3) and row_bcast:31 (row 1 ->
+// rows 2, 3), each step taken only where the source lane lies in the same run.
+// On a run's last lane it is the run total.  Every lane must call it; values
+// are integer-valued doubles below 2^53, so every addition is exact.
+__device__ __forceinline__ double run_sum_to_tail(double v, int rank)
+{
+    const int lane = (int)__lane_id();
+    const int head = lane - rank;
+    double t;
+    t = dpp_f64<0x111, 0xf>(v);
+    if (rank >= 1) v += t;
+    t = dpp_f64<0x112, 0xf>(v);
+    if (rank >= 2) v += t;
+    t = dpp_f64<0x114, 0xf>(v);
+    if (rank >= 4) v += t;
+    t = dpp_f64<0x118, 0xf>(v);
+    if (rank >= 8) v += t;
+    t = dpp_f64<0x142, 0xa>(v);                 // lane 15 -> row 1, lane 47 -> row 3; rows 0, 2 read 0
+    if (head < (lane & ~15)) v += t;
+    t = dpp_f64<0x143, 0xc>(v);                 // lane 31 -> rows 2, 3; rows 0, 1 read 0
+    if (head < 32) v += t;
+    return v;
+}
+
 }  // namespace pcpic
