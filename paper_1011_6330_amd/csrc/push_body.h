@@ -52,44 +52,42 @@ __device__ __forceinline__ double gather_f64(const Consts &c, const double *__re
 
 // Push of one particle (x, u) in place with the gathered kick E: kick and move
 // (eq. 1), current deposit, removal at the ends (x = -1) and the node-0 tally.
-// x < 0 marks an empty slot and is left alone.
+// x < 0 marks an empty slot and is left alone.  Straight-line code with
+// selects: every lane computes the step, and the flags say what is kept.
 __device__ __forceinline__ void push_one_f64(const Consts &c, const PushArgs &a, double E, double &xr, double &ur,
                                              DepAcc &acc)
 {
     const int N = (int)c.N;
-    const double Nd = (double)c.N;
+    const double Nd = (double)N;
     const double x = xr, u = ur;
-    if (!(x >= 0.0)) return;                     // removed slot (-1) or past the end
+    const bool live = x >= 0.0;                  // not a removed slot (-1) or past the end
     // eq. (1): u = gamma v, du/dt = (q/m) E_z, dz/dt = v
     const double u1 = u + E;
     double tt = u1 * u1;
     tt = 1.0 + tt;
-    const double gam = sqrt(tt);
-    const double v = u1 / gam;
+    double gam, v;
+    gamma_velocity(u1, tt, gam, v);
     const double x1 = x + c.dtdz * v;
-    if (!isfinite(u1) || !isfinite(x1)) {
-        acc.bad = true;
-        acc.nlost += 1.0;
-        xr = -1.0;
-        return;
-    }
+    const bool fin = isfinite(u1) && isfinite(x1);
+    const bool ok = live && fin;
     const double c0d = floor(x);
     const double F0 = rint((x - c0d) * c.twoP);
     const double c1d = floor(x1);
     const int c1 = (int)c1d;
     const double F1 = rint((x1 - c1d) * c.twoP);
-    acc.deposit(a.J, N, c.twoP, (int)c0d, F0, c1, F1);
-    if (x1 >= Nd) {                              // leaves through z = L
-        acc.exit_gamma(gam);
-        xr = -1.0;
-    } else if (x1 < 0.0) {                       // returns to the star
-        acc.nabs += 1.0;
-        xr = -1.0;
-    } else {
-        if (c1 == 0) acc.w0 += c.twoP - F1;
-        xr = x1;
-        ur = u1;
+    acc.deposit_sel(a.J, N, c.twoP, ok, (int)c0d, F0, c1, F1);
+    const bool exits = ok && x1 >= Nd;           // leaves through z = L
+    const bool absorbed = ok && x1 < 0.0;        // returns to the star
+    const bool stays = ok && !exits && !absorbed;
+    if (exits) acc.exit_gamma(gam);
+    acc.nabs += absorbed ? 1.0 : 0.0;
+    acc.w0 += (stays && c1 == 0) ? c.twoP - F1 : 0.0;
+    if (live && !fin) {
+        acc.bad = true;
+        acc.nlost += 1.0;
     }
+    xr = stays ? x1 : (live ? -1.0 : x);
+    ur = stays ? u1 : u;
 }
 
 // One tile of BLOCK*PPT consecutive slots starting at tile0 (< n).  Thread t
@@ -315,8 +313,8 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
             const double u1 = u + E;
             double tt = u1 * u1;
             tt = 1.0 + tt;
-            const double gam = sqrt(tt);
-            const double v = u1 / gam;
+            double gam, v;
+            gamma_velocity(u1, tt, gam, v);
             double od = (double)off + c.dtdz * v;
             int c1 = cell;
             if (od >= 1.0) {

@@ -62,6 +62,27 @@ struct DepAcc {
         }
     }
 
+    // The same deposit written with selects for a lane that may have nothing
+    // to deposit (ok = false): lanes of a wave split between staying in their
+    // cell and crossing a face, and selects keep them on one path.
+    __device__ __forceinline__ void deposit_sel(unsigned long long *J, int N, double twoP, bool ok, int c0, double F0,
+                                                int c1, double F1)
+    {
+        const bool right = c1 > c0, left = c1 < c0;
+        const double va = (right ? twoP : (left ? 0.0 : F1)) - F0;
+        const double vb = left ? F1 - twoP : F1;
+        const bool hb = (right && c1 < N) || (left && c1 >= 0);
+        if (ok && cf == -2) cf = c0;
+        const bool mine = ok && c0 == cf;
+        a0 += mine ? va : 0.0;
+        ap += (mine && hb && right) ? vb : 0.0;
+        am += (mine && hb && left) ? vb : 0.0;
+        if (ok && !mine) {
+            if (va != 0.0) atomic_add_face(J, c0, va);
+            if (hb && vb != 0.0) atomic_add_face(J, c1, vb);
+        }
+    }
+
     // exit-gamma sum in units of 2^-32: integer part and fraction kept apart
     __device__ __forceinline__ void exit_gamma(double gam)
     {
@@ -138,6 +159,44 @@ struct DepAcc {
         flush_tallies(ctr);
     }
 };
+
+// gamma = sqrt(tt) and v = u / gamma for tt = 1 + u^2, both correctly rounded.
+// Square root: Goldschmidt iteration from the hardware reciprocal square root
+// estimate y (g = tt y, h = y/2, one joint correction, then two residual
+// corrections g += (tt - g^2) h).  Quotient: Newton-Raphson reciprocal from the
+// hardware estimate (two steps), q = u r, and one residual correction
+// q += (u - gamma q) r (Markstein).  These are the operations, in order, that
+// the general correctly rounded double-precision square root and division
+// perform when their range scaling does not apply, which holds for tt >= 1 and
+// 2^-400 <= |u| <= 2^400; outside that range (u = 0 included) the general
+// routines are called.  Skipping the scaling and special-case steps saves
+// about a dozen instructions per particle.
+__device__ __forceinline__ void gamma_velocity(double u, double tt, double &gam, double &v)
+{
+    const double y = __builtin_amdgcn_rsq(tt);
+    double g = tt * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, tt);
+    g = fma(d, h, g);
+    d = fma(-g, g, tt);
+    g = fma(d, h, g);
+    double rc = __builtin_amdgcn_rcp(g);
+    double e = fma(-g, rc, 1.0);
+    rc = fma(rc, e, rc);
+    e = fma(-g, rc, 1.0);
+    rc = fma(rc, e, rc);
+    const double q = u * rc;
+    const double rem = fma(-g, q, u);
+    gam = g;
+    v = fma(rem, rc, q);
+    const double au = fabs(u);
+    if (!(au >= 0x1p-400 && au <= 0x1p+400)) {
+        gam = sqrt(tt);
+        v = u / gam;
+    }
+}
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec4 __attribute__((ext_vector_type(4)));
