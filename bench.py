@@ -1,7 +1,7 @@
 """Throughput of the polar-cap PIC step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
-                    [--push 256:2:nt] [--push32 256:4:nt] [--tune]
+                    [--push 128:2:nt] [--push32 256:4:nt] [--tune]
                     [--no-fp32] [--no-ensemble] [--no-adjoint] [--no-cpu-baseline]
 
 A step is one whole PIC cycle of the tube: push + deposit, field update +
@@ -126,7 +126,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--push", default="256:2:nt", help="FP64 push shape threads:slots[:nt]")
+    ap.add_argument("--push", default="128:2:nt", help="FP64 push shape threads:slots[:nt]")
     ap.add_argument("--push32", default="256:4:nt", help="FP32-bulk push shape threads:4[:nt]")
     ap.add_argument("--tune", action="store_true", help="autotune the push shapes instead")
     ap.add_argument("--no-fp32", action="store_true")

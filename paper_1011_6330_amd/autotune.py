@@ -12,10 +12,9 @@ import os
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pcpic_tune.json")
 
-TUBE_SHAPES = [(64, 2, True), (128, 2, True), (256, 2, True), (64, 4, True), (256, 2, False), (128, 4, True),
-               (64, 8, True), (128, 8, True), (256, 8, True)]
+TUBE_SHAPES = [(64, 2, True), (128, 2, True), (256, 2, True), (64, 4, True), (256, 2, False), (128, 4, True)]
 TUBE_SHAPES_F32 = [(64, 4, True), (128, 4, True), (256, 4, True), (512, 4, True), (256, 4, False)]
-BATCH_SHAPES = [(b, p) for b in (64, 128, 256, 512) for p in (2, 4, 8) if b < 512 or p == 2]
+BATCH_SHAPES = [(b, p) for b in (64, 128, 256, 512) for p in (2, 4) if (b, p) != (512, 4)]
 BATCH_SHAPES_F32 = [(b, 4) for b in (64, 128, 256, 512)]
 
 

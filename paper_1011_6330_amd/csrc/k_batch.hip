@@ -370,9 +370,6 @@ static const void *pick_push_kernel(pic_handle *h)
         if (B == 64 && P == 4) return push_kernel<64, 4, 1, 0>();
         if (B == 128 && P == 4) return push_kernel<128, 4, 1, 0>();
         if (B == 256 && P == 4) return push_kernel<256, 4, 1, 0>();
-        if (B == 64 && P == 8) return push_kernel<64, 8, 1, 0>();
-        if (B == 128 && P == 8) return push_kernel<128, 8, 1, 0>();
-        if (B == 256 && P == 8) return push_kernel<256, 8, 1, 0>();
     }
     return nullptr;
 }

@@ -80,67 +80,74 @@ __device__ __forceinline__ void push_one_f64(const Consts &c, const PushArgs &a,
     const bool absorbed = ok && x1 < 0.0;        // returns to the star
     const bool stays = ok && !exits && !absorbed;
     if (exits) acc.exit_gamma(gam);
-    acc.nabs += absorbed ? 1.0 : 0.0;
-    acc.w0 += (stays && c1 == 0) ? c.twoP - F1 : 0.0;
-    if (live && !fin) {
-        acc.bad = true;
-        acc.nlost += 1.0;
-    }
+    if (absorbed) acc.absorb();
+    if (stays && c1 == 0) acc.node0(c.twoP - F1);
+    if (live && !fin) acc.lost();
     xr = stays ? x1 : (live ? -1.0 : x);
     ur = stays ? u1 : u;
 }
 
 // One tile of BLOCK*PPT consecutive slots starting at tile0 (< n).  Thread t
-// takes PPT/2 pairs of consecutive slots, pair v at tile0 + 2 (v BLOCK + t), so
-// each pair is one 16-byte vector per stream and a wave's pair v covers 128
-// consecutive slots.  Every pair of the thread is loaded before the first is
-// pushed (PPT/2 vectors per stream in flight); the current of pair v is
-// flushed before pair v+1 is pushed, so a flush sees the few cells 128
-// consecutive slots span.  Called by every thread of a block of BLOCK threads;
-// wave-collective.
+// takes the PPT consecutive slots from tile0 + PPT t, loaded as PPT/2 16-byte
+// vectors per stream; every gather is issued before the first kick, and the
+// particles are pushed two at a time (more in flight would cost occupancy).
+// Between cell sorts a thread's slots sit in one or two cells, so its current
+// lands on the three faces around the cell of its first particle (one
+// register channel each) and the wave flushes once.  Called by every thread of
+// a block of BLOCK threads; wave-collective.
 template <int BLOCK, int PPT, int NT>
 __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a, int64_t n, int64_t tile0)
 {
-    static_assert(PPT % 2 == 0, "slots are taken in pairs");
-    constexpr int V = PPT / 2;
+    static_assert(PPT % 2 == 0, "slots are loaded in pairs");
+    const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
+    const bool full = p0 + PPT <= n;
     double xs[PPT], us[PPT];
+    if (full) {
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const int64_t e = tile0 + 2 * ((int64_t)v * BLOCK + threadIdx.x);
-        if (e + 2 <= n) {
-            const dvec2 xv = ld16<NT, dvec2>(a.X + e);
-            const dvec2 uv = ld16<NT, dvec2>(a.U + e);
-            xs[2 * v] = xv.x; xs[2 * v + 1] = xv.y;
-            us[2 * v] = uv.x; us[2 * v + 1] = uv.y;
-        } else {
-            xs[2 * v] = e < n ? a.X[e] : -1.0;
-            us[2 * v] = e < n ? a.U[e] : 0.0;
-            xs[2 * v + 1] = e + 1 < n ? a.X[e + 1] : -1.0;
-            us[2 * v + 1] = e + 1 < n ? a.U[e + 1] : 0.0;
+        for (int k = 0; k < PPT; k += 2) {
+            const dvec2 xv = ld16<NT, dvec2>(a.X + p0 + k);
+            const dvec2 uv = ld16<NT, dvec2>(a.U + p0 + k);
+            xs[k] = xv.x; xs[k + 1] = xv.y;
+            us[k] = uv.x; us[k + 1] = uv.y;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            xs[k] = p0 + k < n ? a.X[p0 + k] : -1.0;
+            us[k] = p0 + k < n ? a.U[p0 + k] : 0.0;
         }
     }
-
     double E[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) E[k] = gather_f64(c, a.K, xs[k]);
 
     DepAcc acc;
-    acc.init();
+    acc.init(a.ctr);
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-        push_one_f64(c, a, E[2 * v], xs[2 * v], us[2 * v], acc);
-        push_one_f64(c, a, E[2 * v + 1], xs[2 * v + 1], us[2 * v + 1], acc);
-        acc.flush_current(a.J);
-        // write back (removed particles get x = -1; their u is left as it was)
-        const int64_t e = tile0 + 2 * ((int64_t)v * BLOCK + threadIdx.x);
-        if (e + 2 <= n) {
-            st16<NT, dvec2>(a.Xo + e, dvec2{xs[2 * v], xs[2 * v + 1]});
-            st16<NT, dvec2>(a.Uo + e, dvec2{us[2 * v], us[2 * v + 1]});
-        } else {
-            if (e < n) { a.Xo[e] = xs[2 * v]; a.Uo[e] = us[2 * v]; }
-            if (e + 1 < n) { a.Xo[e + 1] = xs[2 * v + 1]; a.Uo[e + 1] = us[2 * v + 1]; }
+    for (int k = 0; k < PPT; k += 2) {
+        push_one_f64(c, a, E[k], xs[k], us[k], acc);
+        push_one_f64(c, a, E[k + 1], xs[k + 1], us[k + 1], acc);
+        if (k + 2 < PPT) __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // write back (removed particles get x = -1; their u is left as it was);
+    // a lane's vectors go out back to back so that every line is written whole
+    if (full) {
+#pragma unroll
+        for (int k = 0; k < PPT; k += 2) {
+            st16<NT, dvec2>(a.Xo + p0 + k, dvec2{xs[k], xs[k + 1]});
+            st16<NT, dvec2>(a.Uo + p0 + k, dvec2{us[k], us[k + 1]});
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (p0 + k < n) {
+                a.Xo[p0 + k] = xs[k];
+                a.Uo[p0 + k] = us[k];
+            }
         }
     }
+    acc.flush_current(a.J);
     if (a.hist) {
         int64_t key[PPT];
         bool live[PPT];
@@ -151,7 +158,6 @@ __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a
         }
         hist_add<PPT>(a.hist, key, live);
     }
-    acc.flush_tallies(a.ctr);
 }
 
 
@@ -213,7 +219,7 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
         }
     }
     DepAcc acc;
-    acc.init();
+    acc.init(a.ctr);
 
     if (!hi) {
         // ---------------- low stream: FP32 momentum ----------------
@@ -245,8 +251,7 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
             int c1 = cell;
             carry_f32(o1, c1);
             if (!isfinite(u1) || !isfinite(o1)) {
-                acc.bad = true;
-                acc.nlost += 1.0;
+                acc.lost();
                 cs[k] = -1;
                 continue;
             }
@@ -260,10 +265,10 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
                 acc.exit_gamma(sqrt(tt));
                 cs[k] = -1;
             } else if (c1 < 0) {
-                acc.nabs += 1.0;
+                acc.absorb();
                 cs[k] = -1;
             } else {
-                if (c1 == 0) acc.w0 += c.twoP - F1;
+                if (c1 == 0) acc.node0(c.twoP - F1);
                 cs[k] = c1;
                 os[k] = o1;
                 us[k] = u1;
@@ -327,8 +332,7 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
             float o1 = (float)od;
             if (o1 >= 1.0f) { o1 = 0.0f; c1 += 1; }
             if (!isfinite(u1) || !isfinite(od)) {
-                acc.bad = true;
-                acc.nlost += 1.0;
+                acc.lost();
                 cs[k] = -1;
                 continue;
             }
@@ -339,10 +343,10 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
                 acc.exit_gamma(gam);
                 cs[k] = -1;
             } else if (c1 < 0) {
-                acc.nabs += 1.0;
+                acc.absorb();
                 cs[k] = -1;
             } else {
-                if (c1 == 0) acc.w0 += c.twoP - F1;
+                if (c1 == 0) acc.node0(c.twoP - F1);
                 cs[k] = c1;
                 os[k] = o1;
                 us[k] = u1;
@@ -369,7 +373,7 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
             hist_add<PPT>(a.hist, key, live);
         }
     }
-    acc.flush(a.J, a.ctr);
+    acc.flush_current(a.J);
 }
 
 }  // namespace pcpic

@@ -21,15 +21,41 @@ __device__ __forceinline__ void atomic_add_face(unsigned long long *J, int f, do
 struct DepAcc {
     int cf;                    // cell of the thread's first deposit (-2 = none yet)
     double am, a0, ap;         // faces cf-1, cf, cf+1
-    double w0, nexit, nabs, nlost, g_int, g_frac;
-    bool bad;
+    DevCounters *ctr;          // the boundary tallies go straight to the counters
 
-    __device__ __forceinline__ void init()
+    __device__ __forceinline__ void init(DevCounters *counters)
     {
         cf = -2;
         am = a0 = ap = 0.0;
-        w0 = nexit = nabs = nlost = g_int = g_frac = 0.0;
-        bad = false;
+        ctr = counters;
+    }
+
+    // Boundary events are rare (a few hundred particles per step leave or
+    // return; only cell 0 feeds the node-0 tally), so each lane adds its own
+    // with integer atomics, which keeps the sums independent of order.
+    __device__ __forceinline__ void exit_gamma(double gam)
+    {
+        // exit-gamma sum in units of 2^-32: integer part and fraction kept apart
+        const double gi = floor(gam);
+        const double gf = rint((gam - gi) * 4294967296.0);
+        const __int128 sum = ((__int128)(long long)gi << 32) + (__int128)(long long)gf;
+        atomicAdd((unsigned long long *)&ctr->n_exit, 1ull);
+        atomicAdd((unsigned long long *)&ctr->n_removed, 1ull);
+        atomic_add_i128(&ctr->exit_lo, &ctr->exit_hi, sum);
+    }
+    __device__ __forceinline__ void absorb()
+    {
+        atomicAdd((unsigned long long *)&ctr->n_absorb, 1ull);
+        atomicAdd((unsigned long long *)&ctr->n_removed, 1ull);
+    }
+    __device__ __forceinline__ void lost()
+    {
+        atomicAdd((unsigned long long *)&ctr->n_removed, 1ull);
+        atomicOr(&ctr->status, (unsigned long long)PIC_ST_NONFINITE);
+    }
+    __device__ __forceinline__ void node0(double w)
+    {
+        atomicAdd((unsigned long long *)&ctr->w0, (unsigned long long)(long long)w);
     }
 
     // J_{i+1/2} += S_i(x^n) - S_i(x^{n+1}) for a move from (c0, F0) to (c1, F1),
@@ -83,15 +109,6 @@ struct DepAcc {
         }
     }
 
-    // exit-gamma sum in units of 2^-32: integer part and fraction kept apart
-    __device__ __forceinline__ void exit_gamma(double gam)
-    {
-        nexit += 1.0;
-        const double gi = floor(gam);
-        g_int += gi;
-        g_frac += rint((gam - gi) * 4294967296.0);
-    }
-
     // Wave-collective: must be reached by all 64 lanes of the wave.  Lanes
     // with the same first cell in consecutive positions form a run; the run's
     // last lane adds the run's sums of the three channels (one atomic per face
@@ -124,39 +141,6 @@ struct DepAcc {
         }
         cf = -2;
         am = a0 = ap = 0.0;
-    }
-
-    // Wave-collective: the boundary tallies of the wave, one atomic each.
-    __device__ __forceinline__ void flush_tallies(DevCounters *ctr)
-    {
-        const int lane = __lane_id();
-        const unsigned long long any = __ballot(w0 != 0.0 || nexit != 0.0 || nabs != 0.0 || nlost != 0.0);
-        if (any) {
-            const double sw0 = wave_sum_f64_to63(w0);
-            const double sx = wave_sum_f64_to63(nexit);
-            const double sa = wave_sum_f64_to63(nabs);
-            const double sl = wave_sum_f64_to63(nlost);
-            const double gi = wave_sum_f64_to63(g_int);
-            const double gf = wave_sum_f64_to63(g_frac);
-            if (lane == 63) {
-                if (sw0 != 0.0) atomicAdd((unsigned long long *)&ctr->w0, (unsigned long long)(long long)sw0);
-                if (sx != 0.0) {
-                    atomicAdd((unsigned long long *)&ctr->n_exit, (unsigned long long)(long long)sx);
-                    const __int128 sum = ((__int128)(long long)gi << 32) + (__int128)(long long)gf;
-                    atomic_add_i128(&ctr->exit_lo, &ctr->exit_hi, sum);
-                }
-                if (sa != 0.0) atomicAdd((unsigned long long *)&ctr->n_absorb, (unsigned long long)(long long)sa);
-                const double rem = sx + sa + sl;
-                if (rem != 0.0) atomicAdd((unsigned long long *)&ctr->n_removed, (unsigned long long)(long long)rem);
-            }
-        }
-        if (__ballot(bad) && lane == 0) atomicOr(&ctr->status, (unsigned long long)PIC_ST_NONFINITE);
-    }
-
-    __device__ __forceinline__ void flush(unsigned long long *J, DevCounters *ctr)
-    {
-        flush_current(J);
-        flush_tallies(ctr);
     }
 };
 
