@@ -7,7 +7,10 @@
 A step is one whole PIC cycle of the tube: push + deposit, field update +
 SCLF injection, and the periodic cell sort.  Inputs are seeded synthetic
 tubes shaped like the paper's frame-dragging runs and are resident in HBM
-before the timed region.  Prints one JSON line:
+before the timed region.  The throughput is timed over K plain steps (no
+events between the kernels); the per-kernel durations come from K further
+steps of the same tube with HIP events around every push, field update and
+sort on the tube's stream.  Prints one JSON line:
 
   value          particle-steps/s of the plain FP64 step on the configured tube
   roofline       of the dominant kernel (the FP64 push), HIP-event timed; its
@@ -68,12 +71,19 @@ def run_tube(cfg, x, u, precision, steps, warmup, push=None, tune=True):
     tube.step(warmup)
     tube.sync()
     d0 = tube.diagnostics(fields=False)
+    # throughput: `steps` plain steps, nothing recorded between the kernels
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tim = tube.step_timed(steps)
+    tube.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     d1 = tube.diagnostics(fields=False)
+    # kernel durations: `steps` more steps with HIP events around every push,
+    # field update and sort, on the tube's own stream
+    tim = tube.step_timed(steps)
+    d2 = tube.diagnostics(fields=False)
+    tim["alive"] = 0.5 * (d1["n_alive"] + d2["n_alive"])
+    tim["alive_high"] = 0.5 * (d1["n_slots_high"] + d2["n_slots_high"])
     tube.close()
     del tube
     torch.cuda.empty_cache()
@@ -161,7 +171,7 @@ def main():
     d0, d1, tim, elapsed, shape = run_tube(cfg, x, u, 0, args.steps, args.warmup, push=push)
     alive = 0.5 * (d0["n_alive"] + d1["n_alive"])
     value = alive * args.steps / elapsed
-    roof = roofline_of(B_FP64 * alive, tim, "k_push_f64")
+    roof = roofline_of(B_FP64 * tim["alive"], tim, "k_push_f64")
     roof["traffic"] = measured_traffic(shape)
     log(f"fp64: {elapsed / args.steps * 1e3:.3f} ms/step, push {roof['avg_launch_us']:.1f} us "
         f"({roof['achieved']:.0f} GB/s), shape {shape}")
@@ -190,8 +200,8 @@ def main():
         f0, f1, ftim, fel, fshape = run_tube(cfg, x, u, 1, args.steps, args.warmup, push=push32)
         falive = 0.5 * (f0["n_alive"] + f1["n_alive"])
         fhigh = 0.5 * (f0["n_slots_high"] + f1["n_slots_high"])
-        flow = max(falive - fhigh, 0.0)
-        froof = roofline_of(B_F32_LOW * flow + B_F32_HIGH * fhigh, ftim, "k_push_f32")
+        froof = roofline_of(B_F32_LOW * max(ftim["alive"] - ftim["alive_high"], 0.0) + B_F32_HIGH * ftim["alive_high"],
+                            ftim, "k_push_f32")
         result["fp32_bulk"] = {"value": falive * args.steps / fel, "unit": "particle-steps/s",
                                "ms_per_step": fel / args.steps * 1e3, "dtype": "f32+f64",
                                "high_stream_fraction": fhigh / max(falive, 1.0), "push_shape": list(fshape),

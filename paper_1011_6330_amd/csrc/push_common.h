@@ -120,24 +120,27 @@ struct DepAcc {
         const bool has = cf != -2;
         const int lane = (int)__lane_id();
         const WaveRun r = wave_runs_i32(cf, has);
-        double sm = am, s0 = a0, sp = ap;
         const bool one_run = __ballot(r.is_head) == 1ull && __ballot(has) == ~0ull;
-        bool tail;
         if (one_run) {
-            if (__ballot(am != 0.0)) sm = wave_sum_f64_to63(sm);
-            if (__ballot(a0 != 0.0)) s0 = wave_sum_f64_to63(s0);
-            if (__ballot(ap != 0.0)) sp = wave_sum_f64_to63(sp);
-            tail = lane == 63;
+            long long sm = 0, s0 = 0, sp = 0;
+            if (__ballot(am != 0.0)) sm = wave_sum_int_f64_to63(am);
+            if (__ballot(a0 != 0.0)) s0 = wave_sum_int_f64_to63(a0);
+            if (__ballot(ap != 0.0)) sp = wave_sum_int_f64_to63(ap);
+            if (lane == 63) {
+                if (sm != 0) atomicAdd(J + cf - 1, (unsigned long long)sm);
+                if (s0 != 0) atomicAdd(J + cf, (unsigned long long)s0);
+                if (sp != 0) atomicAdd(J + cf + 1, (unsigned long long)sp);
+            }
         } else {
+            double sm = am, s0 = a0, sp = ap;
             if (__ballot(am != 0.0)) sm = run_sum_to_tail(sm, r.rank);
             if (__ballot(a0 != 0.0)) s0 = run_sum_to_tail(s0, r.rank);
             if (__ballot(ap != 0.0)) sp = run_sum_to_tail(sp, r.rank);
-            tail = has && lane == r.end - 1;
-        }
-        if (tail) {
-            if (sm != 0.0) atomic_add_face(J, cf - 1, sm);
-            if (s0 != 0.0) atomic_add_face(J, cf, s0);
-            if (sp != 0.0) atomic_add_face(J, cf + 1, sp);
+            if (has && lane == r.end - 1) {
+                if (sm != 0.0) atomic_add_face(J, cf - 1, sm);
+                if (s0 != 0.0) atomic_add_face(J, cf, s0);
+                if (sp != 0.0) atomic_add_face(J, cf + 1, sp);
+            }
         }
         cf = -2;
         am = a0 = ap = 0.0;

@@ -134,6 +134,33 @@ __device__ __forceinline__ double wave_sum_f64_to63(double v)
     return v;
 }
 
+// Sum over the 64 lanes of an int32, valid in lane 63, with the same DPP
+// pattern as wave_sum_f64_to63; each step is one add with a DPP operand.
+__device__ __forceinline__ int wave_sum_i32_to63(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
+// Sum over the 64 lanes of integer-valued doubles with |v| < 2^40, exact,
+// valid in lane 63: each value is split into 2^16 v_hi + v_lo with
+// 0 <= v_lo < 2^16, and the two int32 parts are summed apart (no part sum can
+// reach 2^31), which is cheaper than summing the doubles.
+__device__ __forceinline__ long long wave_sum_int_f64_to63(double v)
+{
+    const double hd = floor(v * 0x1p-16);
+    const int hi = (int)hd;
+    const int lo = (int)fma(hd, -65536.0, v);
+    const int hs = wave_sum_i32_to63(hi);
+    const int ls = wave_sum_i32_to63(lo);
+    return (long long)hs * 65536 + (long long)ls;
+}
+
 // Value of lane - 1 (lane 0 reads 0): DPP wave_shr:1.
 __device__ __forceinline__ int wave_shr1_i32(int v)
 {
