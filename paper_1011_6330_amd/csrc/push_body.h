@@ -177,22 +177,107 @@ struct Push32Args {
     double u_hi = 0.0;                    // |u| from which a particle belongs to the high stream
 };
 
-// Offset update with the carry into the next or previous cell (|move| < 1 cell).
-// An offset that rounds to 1.0f is stored as (cell + 1, 0).
+// Offset update with the carry into the next or previous cell (|move| < 1 cell),
+// with selects.  An offset that rounds to 1.0f is stored as (cell + 1, 0).
 __device__ __forceinline__ void carry_f32(float &o, int &cell)
 {
-    if (o >= 1.0f) {
-        o -= 1.0f;
-        cell += 1;
-    } else if (o < 0.0f) {
-        o += 1.0f;
-        cell -= 1;
-        if (o >= 1.0f) { o = 0.0f; cell += 1; }
+    const bool up = o >= 1.0f, dn = o < 0.0f;
+    const float om = o + 1.0f;
+    const bool dn_full = dn && om >= 1.0f;       // -tiny + 1 rounds to 1: stays in the cell at 0
+    o = up ? o - 1.0f : (dn ? (dn_full ? 0.0f : om) : o);
+    cell += up ? 1 : ((dn && !dn_full) ? -1 : 0);
+}
+
+// Face values around x = cell + off (linear interpolation between faces, clamped
+// at the ends): the lower face index, clamped, and the weight of the upper one.
+// An empty slot (cell = -1) clamps to face 0, so every slot may load.
+__device__ __forceinline__ int gather_face_f32(int N, int cell, float off, float &g, int &j)
+{
+    j = off < 0.5f ? cell - 1 : cell;
+    g = off < 0.5f ? off + 0.5f : off - 0.5f;
+    return j < 0 ? 0 : (j > N - 2 ? N - 2 : j);
+}
+
+// One particle of the low stream (f32 momentum) with its gathered kick E, in
+// place; straight-line code with selects, as push_one_f64.
+__device__ __forceinline__ void push_one_lo(const Consts &c, const Push32Args &a, float E, int &cr, float &orf,
+                                            float &ur, DepAcc &acc)
+{
+    const int N = (int)c.N;
+    const int cell = cr;
+    const float off = orf, u = ur;
+    const bool live = cell >= 0;
+    const float u1 = u + E;
+    float t = u1 * u1;
+    t = 1.0f + t;
+    const float v = u1 * __builtin_amdgcn_rsqf(t);
+    float o1 = off + (float)c.dtdz * v;
+    int c1 = cell;
+    carry_f32(o1, c1);
+    const bool fin = isfinite(u1) && isfinite(o1);
+    const bool ok = live && fin;
+    const double F0 = rint((double)off * c.twoP);
+    const double F1 = rint((double)o1 * c.twoP);
+    acc.deposit_sel(a.J, N, c.twoP, ok, cell, F0, c1, F1);
+    const bool exits = ok && c1 >= N, absorbed = ok && c1 < 0;
+    const bool stays = ok && !exits && !absorbed;
+    if (exits) {
+        const double ud = (double)u1;
+        double tt = ud * ud;
+        tt = 1.0 + tt;
+        acc.exit_gamma(sqrt(tt));
     }
+    if (absorbed) acc.absorb();
+    if (stays && c1 == 0) acc.node0(c.twoP - F1);
+    if (live && !fin) acc.lost();
+    cr = stays ? c1 : (live ? -1 : cell);
+    orf = stays ? o1 : off;
+    ur = stays ? u1 : u;
+}
+
+// One particle of the high stream (f64 momentum, f32 offset).
+__device__ __forceinline__ void push_one_hi(const Consts &c, const Push32Args &a, double E, int &cr, float &orf,
+                                            double &ur, DepAcc &acc)
+{
+    const int N = (int)c.N;
+    const int cell = cr;
+    const float off = orf;
+    const double u = ur;
+    const bool live = cell >= 0;
+    const double u1 = u + E;
+    double tt = u1 * u1;
+    tt = 1.0 + tt;
+    double gam, v;
+    gamma_velocity(u1, tt, gam, v);
+    const double od = (double)off + c.dtdz * v;
+    const bool up = od >= 1.0, dn = od < 0.0;
+    const double od1 = up ? od - 1.0 : (dn ? od + 1.0 : od);
+    int c1 = cell + (up ? 1 : (dn ? -1 : 0));
+    float o1 = (float)od1;
+    if (o1 >= 1.0f) {                            // rounds up to the next cell
+        o1 = 0.0f;
+        c1 += 1;
+    }
+    const bool fin = isfinite(u1) && isfinite(od);
+    const bool ok = live && fin;
+    const double F0 = rint((double)off * c.twoP);
+    const double F1 = rint((double)o1 * c.twoP);
+    acc.deposit_sel(a.J, N, c.twoP, ok, cell, F0, c1, F1);
+    const bool exits = ok && c1 >= N, absorbed = ok && c1 < 0;
+    const bool stays = ok && !exits && !absorbed;
+    if (exits) acc.exit_gamma(gam);
+    if (absorbed) acc.absorb();
+    if (stays && c1 == 0) acc.node0(c.twoP - F1);
+    if (live && !fin) acc.lost();
+    cr = stays ? c1 : (live ? -1 : cell);
+    orf = stays ? o1 : off;
+    ur = stays ? u1 : u;
 }
 
 // One tile of BLOCK*4 consecutive slots of the low (hi = false) or high stream,
-// starting at tile0 (< n).  Called by every thread of the block.
+// starting at tile0 (< n): each thread 4 consecutive slots (16-byte vectors of
+// the 4-byte fields), gathers issued before the first kick, one current flush.
+// Called by every thread of the block; wave-collective.
 template <int BLOCK, int NT>
 __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args &a, bool hi, int64_t n,
                                               int64_t tile0)
@@ -231,49 +316,19 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
 #pragma unroll
             for (int k = 0; k < PPT; ++k) us[k] = p0 + k < n ? a.UL[p0 + k] : 0.0f;
         }
-        const float dtdz = (float)c.dtdz;
+        float E[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int cell = cs[k];
-            if (cell < 0) continue;              // removed slot or past the end
-            const float off = os[k], u = us[k];
-            // gather between the faces around x = cell + off, clamped at the ends
-            const int j = off < 0.5f ? cell - 1 : cell;
-            const float g = off < 0.5f ? off + 0.5f : off - 0.5f;
-            const int jc = j < 0 ? 0 : (j > N - 2 ? N - 2 : j);
+            float g;
+            int j;
+            const int jc = gather_face_f32(N, cs[k], os[k], g, j);
             const float k0 = a.K32[jc], k1 = a.K32[jc + 1];
-            const float E = j < 0 ? k0 : (j >= N - 1 ? k1 : k0 + g * (k1 - k0));
-            const float u1 = u + E;
-            float t = u1 * u1;
-            t = 1.0f + t;
-            const float v = u1 * __builtin_amdgcn_rsqf(t);
-            float o1 = off + dtdz * v;
-            int c1 = cell;
-            carry_f32(o1, c1);
-            if (!isfinite(u1) || !isfinite(o1)) {
-                acc.lost();
-                cs[k] = -1;
-                continue;
-            }
-            const double F0 = rint((double)off * c.twoP);
-            const double F1 = rint((double)o1 * c.twoP);
-            acc.deposit(a.J, N, c.twoP, cell, F0, c1, F1);
-            if (c1 >= N) {
-                const double ud = (double)u1;
-                double tt = ud * ud;
-                tt = 1.0 + tt;
-                acc.exit_gamma(sqrt(tt));
-                cs[k] = -1;
-            } else if (c1 < 0) {
-                acc.absorb();
-                cs[k] = -1;
-            } else {
-                if (c1 == 0) acc.node0(c.twoP - F1);
-                cs[k] = c1;
-                os[k] = o1;
-                us[k] = u1;
-            }
+            const float Ei = k0 + g * (k1 - k0);
+            const float lo = j < 0 ? k0 : Ei;
+            E[k] = j >= N - 1 ? k1 : lo;
         }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) push_one_lo(c, a, E[k], cs[k], os[k], us[k], acc);
         if (full) {
             st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
             st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
@@ -283,6 +338,7 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
             for (int k = 0; k < PPT; ++k)
                 if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UL[p0 + k] = us[k]; }
         }
+        acc.flush_current(a.J);
         if (a.hist) {
             int64_t key[PPT];
             bool live[PPT];
@@ -304,53 +360,21 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
 #pragma unroll
             for (int k = 0; k < PPT; ++k) us[k] = p0 + k < n ? a.UH[p0 + k] : 0.0;
         }
+        double E[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int cell = cs[k];
-            if (cell < 0) continue;
-            const float off = os[k];
-            const double u = us[k];
-            const int j = off < 0.5f ? cell - 1 : cell;
-            const float g = off < 0.5f ? off + 0.5f : off - 0.5f;
-            const int jc = j < 0 ? 0 : (j > N - 2 ? N - 2 : j);
+            float g;
+            int j;
+            const int jc = gather_face_f32(N, cs[k], os[k], g, j);
             const double k0 = a.K64[jc], k1 = a.K64[jc + 1];
-            const double E = j < 0 ? k0 : (j >= N - 1 ? k1 : k0 + (double)g * (k1 - k0));
-            const double u1 = u + E;
-            double tt = u1 * u1;
-            tt = 1.0 + tt;
-            double gam, v;
-            gamma_velocity(u1, tt, gam, v);
-            double od = (double)off + c.dtdz * v;
-            int c1 = cell;
-            if (od >= 1.0) {
-                od -= 1.0;
-                c1 += 1;
-            } else if (od < 0.0) {
-                od += 1.0;
-                c1 -= 1;
-            }
-            float o1 = (float)od;
-            if (o1 >= 1.0f) { o1 = 0.0f; c1 += 1; }
-            if (!isfinite(u1) || !isfinite(od)) {
-                acc.lost();
-                cs[k] = -1;
-                continue;
-            }
-            const double F0 = rint((double)off * c.twoP);
-            const double F1 = rint((double)o1 * c.twoP);
-            acc.deposit(a.J, N, c.twoP, cell, F0, c1, F1);
-            if (c1 >= N) {
-                acc.exit_gamma(gam);
-                cs[k] = -1;
-            } else if (c1 < 0) {
-                acc.absorb();
-                cs[k] = -1;
-            } else {
-                if (c1 == 0) acc.node0(c.twoP - F1);
-                cs[k] = c1;
-                os[k] = o1;
-                us[k] = u1;
-            }
+            const double Ei = k0 + (double)g * (k1 - k0);
+            const double lo = j < 0 ? k0 : Ei;
+            E[k] = j >= N - 1 ? k1 : lo;
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            push_one_hi(c, a, E[k], cs[k], os[k], us[k], acc);
+            if (k == 1) __builtin_amdgcn_sched_barrier(0);
         }
         if (full) {
             st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
@@ -362,6 +386,7 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
             for (int k = 0; k < PPT; ++k)
                 if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UH[p0 + k] = us[k]; }
         }
+        acc.flush_current(a.J);
         if (a.hist) {
             int64_t key[PPT];
             bool live[PPT];
@@ -373,7 +398,6 @@ __device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args 
             hist_add<PPT>(a.hist, key, live);
         }
     }
-    acc.flush_current(a.J);
 }
 
 }  // namespace pcpic
