@@ -239,8 +239,9 @@ enum {
 };
 
 /* Launch shape of the particle push: threads per block (64, 128, 256, 512) and
- * consecutive particle slots per thread: FP64 2, or 4 with up to 256 threads;
- * FP32-bulk 4.
+ * particle slots per thread.  FP64: 2, 4 (up to 256 threads) or 8 (up to 128
+ * threads); a thread takes per_thread/2 pairs of consecutive slots, 2*block
+ * slots apart.  FP32-bulk: 4 consecutive slots.
  * Results do not depend on the choice (integer deposition); the autotuner
  * picks the fastest.  Errors: PIC_EINVAL for an unsupported shape or flag. */
 pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread, uint32_t flags);

@@ -5,15 +5,17 @@
 //
 // Layout and mapping: x and u are SoA FP64 streams (16 B read + 16 B written
 // per live particle and step).  One block owns one tile of BLOCK*PPT
-// consecutive slots and each thread PPT consecutive slots, loaded as 16-byte
-// vectors.  Between cell sorts consecutive slots sit in the same cell, so a
+// consecutive slots; each thread takes PPT/2 pairs of consecutive slots, a
+// wave's pair v being 128 consecutive slots, each pair one 16-byte vector per
+// stream.  Between cell sorts consecutive slots sit in the same cell, so a
 // thread's current contributions land on three faces around the cell of its
-// first particle and are summed in registers (DepAcc); one segmented DPP
-// reduction per wave then issues a single int64 atomic per face and run of
-// lanes in the same cell.  The particle arithmetic is straight-line code with
-// selects, so lanes that stay in their cell and lanes that cross a face share
-// one instruction stream; the rare boundary events (exit, return, node-0
-// tally) are added by the lanes that have them.
+// pair and are summed in registers (DepAcc); one DPP reduction per wave and
+// pair (segmented when the wave spans several cells) then issues a single
+// int64 atomic per face and run of lanes in the same cell.  The particle
+// arithmetic is straight-line code with selects, so lanes that stay in their
+// cell and lanes that cross a face share one instruction stream; the rare
+// boundary events (exit, return, node-0 tally) are added by the lanes that
+// have them.
 #include <math.h>
 
 #include "pcpic_internal.h"
@@ -70,6 +72,8 @@ hipError_t launch_push_f64(pic_handle *h)
         if (B == 256 && P == 4) return launch_push_t<256, 4, 1>(h);
         if (B == 128 && P == 4) return launch_push_t<128, 4, 1>(h);
         if (B == 64 && P == 4) return launch_push_t<64, 4, 1>(h);
+        if (B == 128 && P == 8) return launch_push_t<128, 8, 1>(h);
+        if (B == 64 && P == 8) return launch_push_t<64, 8, 1>(h);
         return hipErrorInvalidValue;
     }
     if (B == 256 && P == 2) return launch_push_t<256, 2, 0>(h);
@@ -79,6 +83,8 @@ hipError_t launch_push_f64(pic_handle *h)
     if (B == 256 && P == 4) return launch_push_t<256, 4, 0>(h);
     if (B == 128 && P == 4) return launch_push_t<128, 4, 0>(h);
     if (B == 64 && P == 4) return launch_push_t<64, 4, 0>(h);
+    if (B == 128 && P == 8) return launch_push_t<128, 8, 0>(h);
+    if (B == 64 && P == 8) return launch_push_t<64, 8, 0>(h);
     return hipErrorInvalidValue;
 }
 

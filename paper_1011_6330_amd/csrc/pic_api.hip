@@ -494,7 +494,8 @@ pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread,
     const bool bok = block == 64 || block == 128 || block == 256 || block == 512;
     // FP32-bulk always takes 4 slots per thread (16-byte vectors of 4-byte fields)
     const bool ok = bok && (h->p.precision == PIC_FP32_BULK ? per_thread == 4
-                                                              : (per_thread == 2 || (per_thread == 4 && block != 512)));
+                                                              : (per_thread == 2 || (per_thread == 4 && block != 512) ||
+                                                                 (per_thread == 8 && block <= 128)));
     if (!ok || (flags & ~PIC_PUSH_NONTEMPORAL))
         return fail(PIC_EINVAL, "unsupported push shape (%d threads, %d per thread, flags %u)", block, per_thread,
                     flags);

@@ -88,33 +88,32 @@ __device__ __forceinline__ void push_one_f64(const Consts &c, const PushArgs &a,
 }
 
 // One tile of BLOCK*PPT consecutive slots starting at tile0 (< n).  Thread t
-// takes the PPT consecutive slots from tile0 + PPT t, loaded as PPT/2 16-byte
-// vectors per stream; every gather is issued before the first kick, and the
-// particles are pushed two at a time (more in flight would cost occupancy).
-// Between cell sorts a thread's slots sit in one or two cells, so its current
-// lands on the three faces around the cell of its first particle (one
-// register channel each) and the wave flushes once.  Called by every thread of
-// a block of BLOCK threads; wave-collective.
+// takes PPT/2 pairs of consecutive slots, pair v at tile0 + 2 (v BLOCK + t), so
+// each pair is one 16-byte vector per stream and a wave's pair v covers 128
+// consecutive slots (PPT = 2: the thread's two slots).  Every pair of the
+// thread is loaded, and every gather issued, before the first kick.  The
+// current of pair v is flushed before pair v+1 is pushed, so a flush sees the
+// few cells 128 consecutive slots span.  Called by every thread of a block of
+// BLOCK threads; wave-collective.
 template <int BLOCK, int PPT, int NT>
 __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a, int64_t n, int64_t tile0)
 {
-    static_assert(PPT % 2 == 0, "slots are loaded in pairs");
-    const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
-    const bool full = p0 + PPT <= n;
+    static_assert(PPT % 2 == 0, "slots are taken in pairs");
+    constexpr int V = PPT / 2;
     double xs[PPT], us[PPT];
-    if (full) {
 #pragma unroll
-        for (int k = 0; k < PPT; k += 2) {
-            const dvec2 xv = ld16<NT, dvec2>(a.X + p0 + k);
-            const dvec2 uv = ld16<NT, dvec2>(a.U + p0 + k);
-            xs[k] = xv.x; xs[k + 1] = xv.y;
-            us[k] = uv.x; us[k + 1] = uv.y;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            xs[k] = p0 + k < n ? a.X[p0 + k] : -1.0;
-            us[k] = p0 + k < n ? a.U[p0 + k] : 0.0;
+    for (int v = 0; v < V; ++v) {
+        const int64_t e = tile0 + 2 * ((int64_t)v * BLOCK + threadIdx.x);
+        if (e + 2 <= n) {
+            const dvec2 xv = ld16<NT, dvec2>(a.X + e);
+            const dvec2 uv = ld16<NT, dvec2>(a.U + e);
+            xs[2 * v] = xv.x; xs[2 * v + 1] = xv.y;
+            us[2 * v] = uv.x; us[2 * v + 1] = uv.y;
+        } else {
+            xs[2 * v] = e < n ? a.X[e] : -1.0;
+            us[2 * v] = e < n ? a.U[e] : 0.0;
+            xs[2 * v + 1] = e + 1 < n ? a.X[e + 1] : -1.0;
+            us[2 * v + 1] = e + 1 < n ? a.U[e + 1] : 0.0;
         }
     }
     double E[PPT];
@@ -124,39 +123,31 @@ __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a
     DepAcc acc;
     acc.init(a.ctr);
 #pragma unroll
-    for (int k = 0; k < PPT; k += 2) {
-        push_one_f64(c, a, E[k], xs[k], us[k], acc);
-        push_one_f64(c, a, E[k + 1], xs[k + 1], us[k + 1], acc);
-        if (k + 2 < PPT) __builtin_amdgcn_sched_barrier(0);
-    }
-
-    // write back (removed particles get x = -1; their u is left as it was);
-    // a lane's vectors go out back to back so that every line is written whole
-    if (full) {
-#pragma unroll
-        for (int k = 0; k < PPT; k += 2) {
-            st16<NT, dvec2>(a.Xo + p0 + k, dvec2{xs[k], xs[k + 1]});
-            st16<NT, dvec2>(a.Uo + p0 + k, dvec2{us[k], us[k + 1]});
+    for (int v = 0; v < V; ++v) {
+        push_one_f64(c, a, E[2 * v], xs[2 * v], us[2 * v], acc);
+        push_one_f64(c, a, E[2 * v + 1], xs[2 * v + 1], us[2 * v + 1], acc);
+        // write back (removed particles get x = -1; their u is left as it was)
+        const int64_t e = tile0 + 2 * ((int64_t)v * BLOCK + threadIdx.x);
+        if (e + 2 <= n) {
+            st16<NT, dvec2>(a.Xo + e, dvec2{xs[2 * v], xs[2 * v + 1]});
+            st16<NT, dvec2>(a.Uo + e, dvec2{us[2 * v], us[2 * v + 1]});
+        } else {
+            if (e < n) { a.Xo[e] = xs[2 * v]; a.Uo[e] = us[2 * v]; }
+            if (e + 1 < n) { a.Xo[e + 1] = xs[2 * v + 1]; a.Uo[e + 1] = us[2 * v + 1]; }
         }
-    } else {
+        acc.flush_current(a.J);
+        if (a.hist) {
+            int64_t key[2];
+            bool live[2];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            if (p0 + k < n) {
-                a.Xo[p0 + k] = xs[k];
-                a.Uo[p0 + k] = us[k];
+            for (int j = 0; j < 2; ++j) {
+                live[j] = xs[2 * v + j] >= 0.0;
+                key[j] = live[j] ? sort_key_f64(c, xs[2 * v + j]) : 0;
             }
+            hist_add<2>(a.hist, key, live);
         }
-    }
-    acc.flush_current(a.J);
-    if (a.hist) {
-        int64_t key[PPT];
-        bool live[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            live[k] = xs[k] >= 0.0;
-            key[k] = live[k] ? sort_key_f64(c, xs[k]) : 0;
-        }
-        hist_add<PPT>(a.hist, key, live);
+        // one pair at a time: interleaving pairs would cost registers and occupancy
+        if (v + 1 < V) __builtin_amdgcn_sched_barrier(0);
     }
 }
 

@@ -77,7 +77,7 @@ def test_sorted_warm_tube():
 
 
 @pytest.mark.parametrize("shape", [(64, 4), (128, 4), (256, 2), (256, 4), (512, 2), (128, 2, True),
-                                   (256, 2, True), (64, 4, True)])
+                                   (256, 2, True), (64, 4, True), (64, 8, True), (128, 8)])
 def test_push_launch_shapes_identical(shape):
     """Every push launch shape the tuner may pick gives the oracle's state."""
     N = 2048
