@@ -29,6 +29,8 @@ struct BatchArgs {
     const int32_t *push_map;     // push tile -> tube
     const int32_t *field_map;    // cell tile -> tube
     int fb, jb, pb;              // field, current and particle buffer parities of the step
+    int hist;                    // the step before a sort: the push counts its survivors' sort keys
+                                 // and the injection adds the injected particles' key
 };
 
 
@@ -48,12 +50,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
             const int64_t n = hi ? T.ctr->n_slots_hi : T.ctr->n_slots;
             if (tile0 >= n) return;                   // tile past the stream's slots (uniform)
             Push32Args a{T.cl[b.pb], T.ol[b.pb], T.ul[b.pb], T.ch[b.pb], T.oh[b.pb], T.uh[b.pb], T.k32, T.k64,
-                         (unsigned long long *)T.j[b.jb], T.ctr, 0u};
+                         (unsigned long long *)T.j[b.jb], T.ctr, 0u,
+                         b.hist ? (unsigned long long *)T.cell_count : nullptr, T.u_hi};
             push_tile_f32<BLOCK, NT>(T.c, a, hi, n, tile0);
         } else {
             const int64_t n = T.ctr->n_slots;
             if (tile0 >= n) return;
-            PushArgs a{T.x[b.pb], T.u[b.pb], T.x[b.pb], T.u[b.pb], T.k64, (unsigned long long *)T.j[b.jb], T.ctr};
+            PushArgs a{T.x[b.pb], T.u[b.pb], T.x[b.pb], T.u[b.pb], T.k64, (unsigned long long *)T.j[b.jb], T.ctr,
+                       b.hist ? (unsigned long long *)T.cell_count : nullptr};
             push_tile_f64<BLOCK, PPT, NT>(T.c, a, n, tile0);
         }
     }
@@ -71,7 +75,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_field(BatchArgs b)
         const int64_t local = it - b.field_pref[t];
         FieldArgs a{T.ez[fb], T.er[fb], T.b[fb], T.ez[g], T.er[g], T.b[g], T.j[jb], T.j[jb ^ 1],
                     T.k64, F32 ? T.k32 : nullptr, F32 ? nullptr : T.x[pb], F32 ? nullptr : T.u[pb],
-                    F32 ? T.cl[pb] : nullptr, F32 ? T.ol[pb] : nullptr, F32 ? T.ul[pb] : nullptr, T.ctr};
+                    F32 ? T.cl[pb] : nullptr, F32 ? T.ol[pb] : nullptr, F32 ? T.ul[pb] : nullptr, T.ctr,
+                    nullptr, 0, 0, b.hist ? (unsigned long long *)T.cell_count : nullptr,
+                    (F32 && 0.0 >= T.u_hi) ? sort_low_keys(T.c) : 0};
         field_tile(T.c, a, local, BLOCK);
     }
 }
@@ -388,8 +394,18 @@ static const void *pick_field_kernel(pic_handle *h)
 
 bool batch_shape_supported(pic_handle *h) { return pick_push_kernel(h) && pick_field_kernel(h); }
 
-// nsteps steps of every tube: a push and a field kernel per step.
-hipError_t launch_batch_steps(pic_handle *h, int nsteps)
+static BSortArgs bsort_args(pic_handle *h)
+{
+    pic_handle *t0 = h->tubes[0];
+    return BSortArgs{h->d_tubes, (int)h->tubes.size(), h->d_sort_pref, h->d_key_pref, h->d_scan_pref,
+                     h->d_chunk_map, h->d_scan_map, t0->p.precision == PIC_FP32_BULK ? 1 : 0, t0->pbuf,
+                     1 - t0->pbuf};
+}
+
+// nsteps steps of every tube: a push and a field kernel per step.  With
+// hist_last, the key counts are cleared first and the last step's push counts
+// the sort keys of its survivors (the sort that follows skips its histogram).
+hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last)
 {
     const void *kp = pick_push_kernel(h);
     const void *kf = pick_field_kernel(h);
@@ -398,10 +414,15 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps)
         return hipErrorInvalidValue;
     pic_handle *t0 = h->tubes[0];
     const unsigned pgrid = (unsigned)h->batch_push_items, fgrid = (unsigned)h->batch_field_items;
+    if (hist_last) {
+        if (h->batch_scan_blocks <= 0 || h->batch_scan_blocks > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_bsort_clear, dim3((unsigned)h->batch_scan_blocks), dim3(256), 0, h->stream,
+                           bsort_args(h));
+    }
     for (int s = 0; s < nsteps; ++s) {
         BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_push_pref, h->d_field_pref, h->d_push_map, h->d_field_map,
                     t0->fbuf ^ (s & 1),
-                    t0->jbuf ^ (s & 1), t0->pbuf};
+                    t0->jbuf ^ (s & 1), t0->pbuf, (hist_last && s == nsteps - 1) ? 1 : 0};
         void *args[] = {&a};
         hipError_t e = hipLaunchKernel(kp, dim3(pgrid), dim3(h->batch_block), args, 0, h->stream);
         if (e != hipSuccess) return e;
@@ -411,18 +432,19 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps)
     return hipSuccess;
 }
 
-hipError_t launch_batch_sort(pic_handle *h)
+// The batched sort; hist_ready: the key counts were taken by the last push.
+hipError_t launch_batch_sort(pic_handle *h, bool hist_ready)
 {
-    pic_handle *t0 = h->tubes[0];
     const int nt = (int)h->tubes.size();
-    BSortArgs a{h->d_tubes, nt, h->d_sort_pref, h->d_key_pref, h->d_scan_pref, h->d_chunk_map, h->d_scan_map,
-                t0->p.precision == PIC_FP32_BULK ? 1 : 0, t0->pbuf, 1 - t0->pbuf};
+    const BSortArgs a = bsort_args(h);
     if (h->batch_scan_blocks <= 0 || h->batch_scan_blocks > 0x7fffffff) return hipErrorInvalidValue;
     const unsigned sb = (unsigned)h->batch_scan_blocks;
     if (h->batch_sort_items <= 0 || h->batch_sort_items > 0x7fffffff) return hipErrorInvalidValue;
     const unsigned g = (unsigned)h->batch_sort_items;   // one block per chunk of 256 slots
-    hipLaunchKernelGGL(k_bsort_clear, dim3(sb), dim3(256), 0, h->stream, a);
-    hipLaunchKernelGGL(k_bsort_hist, dim3(g), dim3(256), 0, h->stream, a);
+    if (!hist_ready) {
+        hipLaunchKernelGGL(k_bsort_clear, dim3(sb), dim3(256), 0, h->stream, a);
+        hipLaunchKernelGGL(k_bsort_hist, dim3(g), dim3(256), 0, h->stream, a);
+    }
     hipLaunchKernelGGL(k_bscan_totals, dim3(sb), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bscan_blocks, dim3(nt), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bscan_apply, dim3(sb), dim3(256), 0, h->stream, a);

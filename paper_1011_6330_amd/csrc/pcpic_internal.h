@@ -226,7 +226,7 @@ hipError_t launch_sort32_hist(pic_handle *h);
 hipError_t launch_sort32_scatter(pic_handle *h);
 hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only);
 hipError_t launch_scan(pic_handle *h, int64_t n_keys);
-hipError_t launch_batch_steps(pic_handle *h, int nsteps);
+hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last);
 hipError_t launch_copy_slots(pic_handle *h, const double *X, const double *U, double *Xc, double *Uc);
 hipError_t launch_record_slots(pic_handle *h, int64_t *dst);
 hipError_t launch_zero_f64(pic_handle *h, double *p, int64_t n);
@@ -235,7 +235,7 @@ hipError_t launch_adj_finish(pic_handle *h, const double *lez, const double *ler
                              double *dp, double *g_rho, double *params);
 hipError_t launch_kick_from(pic_handle *h, const double *ez);
 hipError_t launch_zero_i64(pic_handle *h, int64_t *p, int64_t n);
-hipError_t launch_batch_sort(pic_handle *h);
+hipError_t launch_batch_sort(pic_handle *h, bool hist_ready);
 bool batch_shape_supported(pic_handle *h);
 TubeDev tube_dev(pic_handle *t);
 hipError_t launch_field_inject(pic_handle *h);

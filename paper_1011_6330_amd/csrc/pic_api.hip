@@ -1161,8 +1161,8 @@ static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t
         if (round && !h->graph[key]) {
             hipGraph_t g = nullptr;
             if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-                hipError_t e1 = launch_batch_steps(h, (int)r);
-                hipError_t e2 = launch_batch_sort(h);
+                hipError_t e1 = launch_batch_steps(h, (int)r, true);
+                hipError_t e2 = launch_batch_sort(h, true);
                 hipError_t e3 = hipStreamEndCapture(h->stream, &g);
                 if (e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess && g &&
                     hipGraphInstantiate(&h->graph[key], g, nullptr, nullptr, 0) == hipSuccess) {
@@ -1187,9 +1187,9 @@ static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t
                 for (int k = 0; k < 3; ++k) HIP_OK(hipEventCreate(&e[k]));
                 HIP_OK(hipEventRecord(e[0], h->stream));
             }
-            HIP_OK(launch_batch_steps(h, (int)r));
+            HIP_OK(launch_batch_steps(h, (int)r, to_sort));
             if (e) HIP_OK(hipEventRecord(e[1], h->stream));
-            if (to_sort) HIP_OK(launch_batch_sort(h));
+            if (to_sort) HIP_OK(launch_batch_sort(h, true));
             if (e) HIP_OK(hipEventRecord(e[2], h->stream));
             if (tim) {
                 tim->push_launches += 1;
