@@ -8,14 +8,14 @@
 // consecutive slots; each thread takes PPT/2 pairs of consecutive slots, a
 // wave's pair v being 128 consecutive slots, each pair one 16-byte vector per
 // stream.  Between cell sorts consecutive slots sit in the same cell, so a
-// thread's current contributions land on three faces around the cell of its
-// pair and are summed in registers (DepAcc); one DPP reduction per wave and
-// pair (segmented when the wave spans several cells) then issues a single
-// int64 atomic per face and run of lanes in the same cell.  The particle
-// arithmetic is straight-line code with selects, so lanes that stay in their
-// cell and lanes that cross a face share one instruction stream; the rare
-// boundary events (exit, return, node-0 tally) are added by the lanes that
-// have them.
+// thread's current contributions land on the faces around the one or two
+// cells of its pair and are summed in four register channels (DepAcc); one
+// DPP reduction per wave and pair (segmented when the wave spans several
+// cells) then issues a single int64 atomic per face and run of lanes in the
+// same cell.  The particle arithmetic is straight-line code with selects, so
+// lanes that stay in their cell and lanes that cross a face share one
+// instruction stream; the rare boundary events (exit, return, node-0 tally)
+// are added by the lanes that have them.
 #include <math.h>
 
 #include "pcpic_internal.h"

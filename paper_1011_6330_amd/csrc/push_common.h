@@ -20,13 +20,13 @@ __device__ __forceinline__ void atomic_add_face(unsigned long long *J, int f, do
 
 struct DepAcc {
     int cf;                    // cell of the thread's first deposit (-2 = none yet)
-    double am, a0, ap;         // faces cf-1, cf, cf+1
+    double am, a0, ap, a2;     // faces cf-1, cf, cf+1, cf+2 (particles starting in cf or cf+1)
     DevCounters *ctr;          // the boundary tallies go straight to the counters
 
     __device__ __forceinline__ void init(DevCounters *counters)
     {
         cf = -2;
-        am = a0 = ap = 0.0;
+        am = a0 = ap = a2 = 0.0;
         ctr = counters;
     }
 
@@ -60,37 +60,14 @@ struct DepAcc {
 
     // J_{i+1/2} += S_i(x^n) - S_i(x^{n+1}) for a move from (c0, F0) to (c1, F1),
     // |c1 - c0| <= 1, with S_i the fixed-point cumulative linear weight left of
-    // face i+1/2 (2^P left of node i, 2^P - F in cell i, 0 right of node i+1).
-    __device__ __forceinline__ void deposit(unsigned long long *J, int N, double twoP, int c0, double F0, int c1,
-                                            double F1)
-    {
-        double va, vb = 0.0;
-        bool hb = false;
-        if (c1 == c0) {
-            va = F1 - F0;
-        } else if (c1 > c0) {
-            va = twoP - F0;
-            if (c1 < N) { vb = F1; hb = true; }
-        } else {
-            va = -F0;
-            if (c1 >= 0) { vb = F1 - twoP; hb = true; }
-        }
-        if (cf == -2) cf = c0;
-        if (c0 == cf) {
-            a0 += va;
-            if (hb) {
-                if (c1 > c0) ap += vb;
-                else am += vb;
-            }
-        } else {
-            if (va != 0.0) atomic_add_face(J, c0, va);
-            if (hb && vb != 0.0) atomic_add_face(J, c1, vb);
-        }
-    }
-
-    // The same deposit written with selects for a lane that may have nothing
-    // to deposit (ok = false): lanes of a wave split between staying in their
-    // cell and crossing a face, and selects keep them on one path.
+    // face i+1/2 (2^P left of node i, 2^P - F in cell i, 0 right of node i+1):
+    // face c0 gets (2^P if c1 > c0, 0 if c1 < c0, F1 if c1 = c0) - F0, and a
+    // crossed face c1 inside the tube gets F1 (moving right) or F1 - 2^P (left).
+    // Written with selects for a lane that may have nothing to deposit
+    // (ok = false): lanes of a wave split between staying in their cell and
+    // crossing a face, and selects keep them on one path.  A particle starting
+    // in cf or cf+1 lands in the four channels; any other (a thread whose slots
+    // span more than two cells) adds its own atomics.
     __device__ __forceinline__ void deposit_sel(unsigned long long *J, int N, double twoP, bool ok, int c0, double F0,
                                                 int c1, double F1)
     {
@@ -99,11 +76,13 @@ struct DepAcc {
         const double vb = left ? F1 - twoP : F1;
         const bool hb = (right && c1 < N) || (left && c1 >= 0);
         if (ok && cf == -2) cf = c0;
-        const bool mine = ok && c0 == cf;
-        a0 += mine ? va : 0.0;
-        ap += (mine && hb && right) ? vb : 0.0;
-        am += (mine && hb && left) ? vb : 0.0;
-        if (ok && !mine) {
+        const bool in0 = ok && c0 == cf, in1 = ok && c0 == cf + 1;
+        const double vl = (hb && left) ? vb : 0.0, vr = (hb && right) ? vb : 0.0;
+        am += in0 ? vl : 0.0;
+        a0 += in0 ? va : (in1 ? vl : 0.0);
+        ap += in0 ? vr : (in1 ? va : 0.0);
+        a2 += in1 ? vr : 0.0;
+        if (ok && !in0 && !in1) {
             if (va != 0.0) atomic_add_face(J, c0, va);
             if (hb && vb != 0.0) atomic_add_face(J, c1, vb);
         }
@@ -122,28 +101,32 @@ struct DepAcc {
         const WaveRun r = wave_runs_i32(cf, has);
         const bool one_run = __ballot(r.is_head) == 1ull && __ballot(has) == ~0ull;
         if (one_run) {
-            long long sm = 0, s0 = 0, sp = 0;
+            long long sm = 0, s0 = 0, sp = 0, s2 = 0;
             if (__ballot(am != 0.0)) sm = wave_sum_int_f64_to63(am);
             if (__ballot(a0 != 0.0)) s0 = wave_sum_int_f64_to63(a0);
             if (__ballot(ap != 0.0)) sp = wave_sum_int_f64_to63(ap);
+            if (__ballot(a2 != 0.0)) s2 = wave_sum_int_f64_to63(a2);
             if (lane == 63) {
                 if (sm != 0) atomicAdd(J + cf - 1, (unsigned long long)sm);
                 if (s0 != 0) atomicAdd(J + cf, (unsigned long long)s0);
                 if (sp != 0) atomicAdd(J + cf + 1, (unsigned long long)sp);
+                if (s2 != 0) atomicAdd(J + cf + 2, (unsigned long long)s2);
             }
         } else {
-            double sm = am, s0 = a0, sp = ap;
+            double sm = am, s0 = a0, sp = ap, s2 = a2;
             if (__ballot(am != 0.0)) sm = run_sum_to_tail(sm, r.rank);
             if (__ballot(a0 != 0.0)) s0 = run_sum_to_tail(s0, r.rank);
             if (__ballot(ap != 0.0)) sp = run_sum_to_tail(sp, r.rank);
+            if (__ballot(a2 != 0.0)) s2 = run_sum_to_tail(s2, r.rank);
             if (has && lane == r.end - 1) {
                 if (sm != 0.0) atomic_add_face(J, cf - 1, sm);
                 if (s0 != 0.0) atomic_add_face(J, cf, s0);
                 if (sp != 0.0) atomic_add_face(J, cf + 1, sp);
+                if (s2 != 0.0) atomic_add_face(J, cf + 2, s2);
             }
         }
         cf = -2;
-        am = a0 = ap = 0.0;
+        am = a0 = ap = a2 = 0.0;
     }
 };
 
