@@ -18,8 +18,10 @@ sort on the tube's stream.  Prints one JSON line:
                  profiles/k_push_f64_c2_hbm_traffic.txt when that summary was
                  taken on the current push sources and launch shape (else null)
   fp32_bulk      the same tube with the FP32-bulk push (f32 momentum below
-                 gamma = 1e6, f64 above), with its own roofline
-  ensemble       256 tubes of uneven size, one graph launch per round
+                 gamma = 1e6, f64 above), with its own roofline; low_gamma: the
+                 same geometry with a beam below 1e6, FP64 against FP32-bulk
+  ensemble       256 tubes of uneven size, one graph launch per round (FP32-bulk;
+                 fp64: the same tubes in FP64)
   plausibility   flat-space SCLF over a = omega_p R / c (sec. 3, Table 2): gamma
                  behind the front and the oscillation amplitude per a
   cpu_baseline   the single-threaded FP64 oracle on the same tube
@@ -209,9 +211,33 @@ def main():
         log(f"fp32-bulk: {fel / args.steps * 1e3:.3f} ms/step, push {froof['avg_launch_us']:.1f} us "
             f"({froof['achieved']:.0f} GB/s), high-stream fraction {fhigh / max(falive, 1):.3f}")
 
+        # the same geometry with a beam below gamma_fp64 (a = 430, gamma up to ~3e4):
+        # every particle in the f32-momentum stream, 24 B per particle-step
+        lcfg = dict(cfg, q_over_m=synth.q_over_m_for(430.0))
+        lx, lu = synth.warm_start(lcfg)
+        l0, l1, ltim, lel, _ = run_tube(lcfg, lx, lu, 0, args.steps, args.warmup, push=push)
+        m0, m1, mtim, mel, _ = run_tube(lcfg, lx, lu, 1, args.steps, args.warmup, push=push32)
+        del lx, lu
+        lval = 0.5 * (l0["n_alive"] + l1["n_alive"]) * args.steps / lel
+        mval = 0.5 * (m0["n_alive"] + m1["n_alive"]) * args.steps / mel
+        mroof = roofline_of(B_F32_LOW * max(mtim["alive"] - mtim["alive_high"], 0.0) + B_F32_HIGH * mtim["alive_high"],
+                            mtim, "k_push_f32")
+        result["fp32_bulk"]["low_gamma"] = {
+            "workload": "the c2 tube geometry with a = 430 (q/m = -a^2/4pi): gamma up to ~3e4, all particles "
+                        "in the f32-momentum stream",
+            "fp64": {"value": lval, "ms_per_step": lel / args.steps * 1e3,
+                     "push_us": ltim["push_ms"] / max(ltim["push_launches"], 1) * 1e3},
+            "fp32_bulk": {"value": mval, "ms_per_step": mel / args.steps * 1e3, "roofline": mroof,
+                          "high_stream_fraction": mtim["alive_high"] / max(mtim["alive"], 1.0)},
+            "fp32_over_fp64": mval / lval}
+        log(f"fp32-bulk, low gamma: {mel / args.steps * 1e3:.3f} ms/step (push {mroof['avg_launch_us']:.1f} us) vs "
+            f"fp64 {lel / args.steps * 1e3:.3f} ms/step")
+
     # ---- ensemble: 256 tubes, one graph launch per round ----
     if not args.no_ensemble:
-        result["ensemble"] = run_ensemble(args.ensemble_steps)
+        result["ensemble"] = run_ensemble(args.ensemble_steps, precision=1)
+        e64 = run_ensemble(args.ensemble_steps, precision=0)
+        result["ensemble"]["fp64"] = {k: e64[k] for k in ("value", "ms_per_step", "launch", "dtype")}
 
     if not args.no_adjoint:
         adj = run_adjoint_leg(args.adjoint_steps)
@@ -238,11 +264,11 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def run_ensemble(steps):
+def run_ensemble(steps, precision=1):
     import torch
 
     from paper_1011_6330_amd import Batch, autotune, synth
-    cfgs = synth.ensemble(n_tubes=256, seed=0, precision=1)
+    cfgs = synth.ensemble(n_tubes=256, seed=0, precision=precision)
     b = Batch([synth.tube_params(c) for c in cfgs], device="cuda:0")
     for t, c in enumerate(cfgs):
         x, u = synth.warm_start(c, seed=t)
@@ -264,13 +290,14 @@ def run_ensemble(steps):
     del b
     torch.cuda.empty_cache()
     alive = 0.5 * (n0 + n1)
-    log(f"ensemble: {el / steps * 1e3:.3f} ms/step for {alive:.3g} particles in 256 tubes, shape {cfg}")
+    log(f"ensemble ({'fp32-bulk' if precision else 'fp64'}): {el / steps * 1e3:.3f} ms/step for {alive:.3g} "
+        f"particles in 256 tubes, shape {cfg}")
     return {"value": alive * steps / el, "unit": "particle-steps/s", "ms_per_step": el / steps * 1e3,
             "tubes": 256, "cells": int(sum(c["n_cells"] for c in cfgs)), "particles": int(alive),
-            "dtype": "f32+f64", "launch": cfg, "steps": steps,
+            "dtype": "f32+f64" if precision else "f64", "launch": cfg, "steps": steps,
             "workload": "256 frame-dragging tubes, cells log-uniform 2048-65536, particles log-uniform 1e4-1e6, "
-                        "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk, one graph launch per "
-                        "16-step round"}
+                        "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk (fp64: the same tubes in FP64), "
+                        "one graph launch per 16-step round"}
 
 
 def run_adjoint_leg(steps, ckpt=50):
