@@ -518,11 +518,15 @@ pic_status pic_sync(pic_handle *h)
 
 }  // extern "C"
 
+static pic_status batch_resolve_pending(pic_handle *b);
+
 // A tube of a batch whose t = 0 solve of eq. (4) is still pending (after
-// pic_init_batch or a warm-start pic_inject) gets it now, on its own.
+// pic_init_batch or a warm-start pic_inject) gets it now, together with every
+// other pending tube of its batch (one batched Thomas launch).
 static pic_status resolve_pending(pic_handle *h)
 {
     if (!h->poisson_pending) return PIC_OK;
+    if (h->parent) return batch_resolve_pending(h->parent);
     HIP_OK(launch_poisson(h));
     HIP_OK(hipStreamSynchronize(h->stream));
     h->poisson_pending = false;
