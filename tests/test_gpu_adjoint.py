@@ -76,7 +76,7 @@ def test_adjoint_autograd_function():
     loss.backward()
     g, o = make_pair(cfg, x, u)
     L, nex, g_rho, g_rate = o.adjoint(160)
-    assert float(loss) == L
+    assert float(loss.detach()) == L
     N, K = cfg["n_cells"], 9
     z = np.arange(N + 1) * (cfg["length"] / N)
     W = np.stack([np.interp(z, np.linspace(0, cfg["length"], K), np.eye(K)[k]) for k in range(K)], axis=1)
