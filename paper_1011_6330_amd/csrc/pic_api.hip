@@ -368,24 +368,82 @@ static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t
 static pic_status batch_status(pic_handle *h);
 static void free_batch_graphs(pic_handle *h);
 
+// One step of a single tube, launched directly: push (counting the sort keys
+// on the step before a sort), field update + injection, and the sort.
+static pic_status tube_step_direct(pic_handle *h)
+{
+    const bool sort_after = h->p.sort_every > 0 && (h->step + 1) % h->p.sort_every == 0;
+    if (sort_after) HIP_OK(launch_clear_hist(h));
+    h->hist_on = sort_after;            // the step counts the sort keys of its survivors
+    hipError_t e1 = launch_push(h);
+    hipError_t e2 = e1 == hipSuccess ? launch_field_inject(h) : e1;
+    h->hist_on = false;
+    HIP_OK(e2);
+    h->fbuf ^= 1;
+    h->jbuf ^= 1;
+    h->step += 1;
+    if (sort_after) HIP_OK(launch_sort(h, true));
+    return PIC_OK;
+}
+
+// Captured rounds of a single tube are launch-shape and schedule specific.
+static void free_tube_graphs(pic_handle *h)
+{
+    for (auto &g : h->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
 pic_status pic_step(pic_handle *h, int64_t n_steps)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
     if (n_steps < 0) return fail(PIC_EINVAL, "n_steps < 0");
     if (h->parent) return fail(PIC_ESTATE, "a tube of a batch is stepped through its batch handle");
     if (h->is_batch) return batch_advance(h, n_steps, nullptr, nullptr);
-    for (int64_t s = 0; s < n_steps; ++s) {
-        const bool sort_after = h->p.sort_every > 0 && (h->step + 1) % h->p.sort_every == 0;
-        if (sort_after) HIP_OK(launch_clear_hist(h));
-        h->hist_on = sort_after;            // the step counts the sort keys of its survivors
-        hipError_t e1 = launch_push(h);
-        hipError_t e2 = e1 == hipSuccess ? launch_field_inject(h) : e1;
-        h->hist_on = false;
-        HIP_OK(e2);
-        h->fbuf ^= 1;
-        h->jbuf ^= 1;
-        h->step += 1;
-        if (sort_after) HIP_OK(launch_sort(h, true));
+    // A whole round of sort_every steps that starts on a round boundary is
+    // replayed from a graph captured once per (field, current, particle)
+    // buffer-parity state; other steps are launched one by one.  Both issue the
+    // same kernels with the same arguments.
+    const int64_t S = h->p.sort_every;
+    while (n_steps > 0) {
+        if (S > 1 && h->use_graph && h->step % S == 0 && n_steps >= S) {
+            const int key = h->fbuf | (h->jbuf << 1) | (h->pbuf << 2);
+            if (!h->graph[key]) {
+                const int fb = h->fbuf, jb = h->jbuf, pb = h->pbuf;
+                const int64_t st = h->step;
+                hipGraph_t g = nullptr;
+                bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    pic_status rc = PIC_OK;
+                    for (int64_t s = 0; s < S && rc == PIC_OK; ++s) rc = tube_step_direct(h);
+                    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+                    ok = rc == PIC_OK && e == hipSuccess && g &&
+                         hipGraphInstantiate(&h->graph[key], g, nullptr, nullptr, 0) == hipSuccess;
+                    if (g) (void)hipGraphDestroy(g);
+                }
+                // the captured round has not run yet
+                h->fbuf = fb;
+                h->jbuf = jb;
+                h->pbuf = pb;
+                h->step = st;
+                if (!ok) {
+                    (void)hipGetLastError();
+                    h->graph[key] = nullptr;
+                    h->use_graph = false;   // launch directly from now on
+                    continue;
+                }
+            }
+            HIP_OK(hipGraphLaunch(h->graph[key], h->stream));
+            h->fbuf ^= (int)(S & 1);
+            h->jbuf ^= (int)(S & 1);
+            h->pbuf ^= 1;
+            h->step += S;
+            n_steps -= S;
+        } else {
+            if (pic_status rc = tube_step_direct(h)) return rc;
+            n_steps -= 1;
+        }
     }
     return PIC_OK;
 }
@@ -502,6 +560,7 @@ pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread,
     h->push_block = block;
     h->push_ppt = per_thread;
     h->push_nt = (flags & PIC_PUSH_NONTEMPORAL) ? 1 : 0;
+    free_tube_graphs(h);
     return PIC_OK;
 }
 
@@ -715,6 +774,7 @@ pic_status pic_set_injection_schedule(pic_handle *h, const int64_t *d_counts, in
     h->d_sched = n > 0 ? d_counts : nullptr;
     h->sched_first = first_step;
     h->sched_n = n;
+    free_tube_graphs(h);
     return PIC_OK;
 }
 
@@ -920,6 +980,8 @@ pic_status pic_destroy(pic_handle *h)
     if (h->is_batch) {
         free_batch_graphs(h);
         for (pic_handle *t : h->tubes) delete t;
+    } else {
+        free_tube_graphs(h);
     }
     delete h;
     return PIC_OK;

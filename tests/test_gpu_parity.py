@@ -314,3 +314,40 @@ def test_b_steady_init_bit_identical():
     o.step(60)
     assert_state_equal(g, o, ordered=False, what="b steady init")
     g.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_rounds_equal_direct_steps(precision):
+    """pic_step replays whole sort_every rounds from captured graphs; stepping
+    one step per call launches every kernel directly.  Both give the same state,
+    bit for bit (also across a launch-shape change, which drops the graphs)."""
+    from paper_1011_6330_amd import Tube
+    N = 2048
+    cfg = dict(synth.preset("c2"), n_cells=N, q_over_m=synth.q_over_m_for(300.0), ppc=30.0,
+               warm=30 * N, capacity=int(30 * N * 1.3), sort_every=16)
+    x, u = synth.warm_start(cfg)
+    p = dict(synth.tube_params(cfg), precision=precision)
+    a, b = Tube(p), Tube(p)
+    a.inject(x, u)
+    b.inject(x, u)
+    say("graph rounds, precision", precision)
+    a.step(64)
+    for _ in range(64):
+        b.step(1)
+    a.set_push_config(64, 4 if precision else 2, True)
+    b.set_push_config(64, 4 if precision else 2, True)
+    a.step(40)
+    for _ in range(40):
+        b.step(1)
+    da = a.diagnostics(n_bins=16, fields=True, j=True)
+    db = b.diagnostics(n_bins=16, fields=True, j=True)
+    for k in ("ez", "er", "b_phi", "j_last", "prof_count", "prof_sum_lo", "prof_sum_hi"):
+        assert np.array_equal(da[k], db[k]), k
+    for k in ("step", "n_alive", "n_injected", "n_exit", "n_absorb", "exit_sum_lo", "exit_sum_hi", "w0"):
+        assert da[k] == db[k], k
+    xa, ua = a.read_particles()
+    xb, ub = b.read_particles()
+    ka, kb = np.lexsort((ua, xa)), np.lexsort((ub, xb))
+    assert np.array_equal(xa[ka], xb[kb]) and np.array_equal(ua[ka], ub[kb])
+    a.close()
+    b.close()
