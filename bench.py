@@ -258,6 +258,13 @@ def main():
                                                               "e_surf_ratio")} for r in rows]}
         log("plausibility: " + "; ".join(f"a={r['a']:g}: peak {r['gamma_peak']:.2f} vs sqrt2 a {r['gamma_paper']:.2f}, "
                                            f"ampl {r['amplitude']:.2f}" for r in rows))
+        inc = sweep.run_inclination((0.1, 0.5))
+        result["plausibility"]["inclination"] = {
+            "workload": "Fig. 6: one star (frame dragging, redshift, inclination term of eq. 6; surface density "
+                        "cos i) at i = 0.1 and 0.5 rad, a = 100, empty tubes, profiles read at front 8R",
+            "rows": [{k: r[k] for k in ("incl", "gamma_plateau", "gamma_peak", "amplitude", "front")} for r in inc]}
+        log("inclination: " + "; ".join(f"i={r['incl']:g}: plateau {r['gamma_plateau']:.1f}, peak "
+                                          f"{r['gamma_peak']:.1f}" for r in inc))
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, x, u, args.cpu_seconds)

@@ -21,6 +21,11 @@ when the front has reached 30R in every tube, as the paper does.  Per tube:
 
     python -m paper_1011_6330_amd.sweep --a 3.5 5.5 11 30
 
+run_inclination does the same for Fig. 6: one star (frame dragging, redshift
+and the inclination term of eq. (6)) at two inclinations, surface density
+scaling as cos i, profiles read when the front has crossed 8R (figures over
+1R <= z <= front - 1R).
+
 Every number comes from the GPU library; nothing here computes the method.
 """
 import argparse
@@ -46,17 +51,12 @@ def sclf_tube(a, cells_per_r, length=10.0, ppc=4.0, sort_every=16):
                 sort_every=sort_every, capacity=int(12 * ppc * n) + 8192, flags=0, precision=0)
 
 
-def run_sweep(a_values, cells_per_lambda=24.0, min_cells_per_r=50.0, front=30.0, length=40.0, n_bins=200,
-              chunk=512, max_steps=200000, device="cuda"):
-    """Run the batch until the front has crossed `front` radii in every tube
-    (the paper reads its profiles when the front reaches 30R); all tubes share
-    one grid (the finest the largest a needs), so they share the time step.
-    Returns one dict of results per value of a."""
-    from . import Batch
-    cpr = max(min_cells_per_r, cells_per_lambda * max(a_values) / (2.0 * math.pi))
-    cfgs = [sclf_tube(a, cpr, length=length) for a in a_values]
+def _measure(b, cfgs, labels, front, margin, n_bins, chunk, max_steps):
+    """Step the batch until the front has crossed `front` radii in every tube,
+    then read the profiles, fields and particles of each tube; the profile
+    figures cover margin <= z <= front - margin."""
     N = cfgs[0]["n_cells"]
-    b = Batch([synth.tube_params(c) for c in cfgs], device=device)
+    length = cfgs[0]["length"]
     ez0 = [t.diagnostics(fields=True)["ez"][0] for t in b.tubes]
     bin_r = length / n_bins
     steps = 0
@@ -72,26 +72,77 @@ def run_sweep(a_values, cells_per_lambda=24.0, min_cells_per_r=50.0, front=30.0,
             break
     b.sync()
     out = []
-    for a, c, t, e0 in zip(a_values, cfgs, b.tubes, ez0):
+    for lab, c, t, e0 in zip(labels, cfgs, b.tubes, ez0):
         d = t.diagnostics(n_bins=n_bins, fields=True)
         x, u = t.read_particles()
-        z = x / (N / c["length"])
+        z = x / (N / length)
         zf = float(np.quantile(z, 0.999)) if len(z) else 0.0
         centers = (np.arange(n_bins) + 0.5) * bin_r
-        sel = (centers >= 5.0) & (centers <= zf - 5.0) & (d["prof_count"] > 0)
+        sel = (centers >= margin) & (centers <= zf - margin) & (d["prof_count"] > 0)
         gam = np.abs(d["prof_mean"][sel])
         plateau = float(np.average(gam, weights=d["prof_count"][sel])) if sel.any() else float("nan")
         peak = float(gam.max()) if sel.any() else float("nan")
         amp = float(gam.std() / gam.mean()) if sel.sum() > 2 else float("nan")
         above = z > 1.0
         ret = float((u[above] < 0).sum() / max(above.sum(), 1))
-        out.append(dict(a=float(a), n_cells=N, steps=steps, time=steps * 0.5 * c["length"] / N,
+        out.append(dict(label=lab, n_cells=N, steps=steps, time=steps * 0.5 * length / N,
                         particles=int(d["n_alive"]), front=zf, gamma_plateau=plateau, gamma_peak=peak,
-                        gamma_sclf=gamma_sclf(a),
-                        gamma_paper=math.sqrt(2.0) * a, amplitude=amp, returning=ret,
+                        amplitude=amp, returning=ret,
                         e_surf_ratio=float(d["ez"][0] / e0) if e0 != 0 else float("nan")))
-    b.close()
     return out
+
+
+def run_sweep(a_values, cells_per_lambda=24.0, min_cells_per_r=50.0, front=30.0, length=40.0, n_bins=200,
+              chunk=512, max_steps=200000, device="cuda"):
+    """Run the batch until the front has crossed `front` radii in every tube
+    (the paper reads its profiles when the front reaches 30R); all tubes share
+    one grid (the finest the largest a needs), so they share the time step.
+    Returns one dict of results per value of a."""
+    from . import Batch
+    cpr = max(min_cells_per_r, cells_per_lambda * max(a_values) / (2.0 * math.pi))
+    cfgs = [sclf_tube(a, cpr, length=length) for a in a_values]
+    b = Batch([synth.tube_params(c) for c in cfgs], device=device)
+    rows = _measure(b, cfgs, a_values, front, 5.0, n_bins, chunk, max_steps)
+    b.close()
+    for r in rows:
+        a = r.pop("label")
+        r.update(a=float(a), gamma_sclf=gamma_sclf(a), gamma_paper=math.sqrt(2.0) * a)
+    return rows
+
+
+# The paper's standard pulsar (sec. 3): theta_p = 0.014, theta_* = 0.67 theta_p on
+# the field line varphi = 0; r_g / R_* = 0.4 for 1.4 solar masses and R_* = 10 km.
+THETA_STAR = 0.67 * 0.014
+RG_OVER_RSTAR = 0.4
+
+
+def inclination_tube(incl, a=100.0, cells_per_r=400.0, length=10.0, ppc=4.0, kappa=0.15, r_star=10.0):
+    """A cold-start tube of the whole eq. (6) background at inclination `incl`.
+
+    The surface Goldreich-Julian density scales as cos i for the same star, so
+    the amplitude is A = cos i (q/m fixed by a, the strength at A = 1); the
+    inclination term enters through (3/2) theta_* tan i cos varphi."""
+    n = int(round(cells_per_r * length))
+    return dict(n_cells=n, length=length, radius=1.0, dt_over_dz=0.5, q_over_m=-a * a / (4.0 * math.pi),
+                ppc=ppc, rho_kind=synth.RHO_GR, rho_amp=math.cos(incl), kappa=kappa, r_star=r_star,
+                incl=incl, theta_star=THETA_STAR, cos_phi=1.0, rg_over_rstar=RG_OVER_RSTAR, fp_bits=32,
+                sort_every=16, capacity=int(12 * ppc * n) + 8192, flags=0, precision=0)
+
+
+def run_inclination(incl_values=(0.1, 0.5), a=100.0, cells_per_lambda=24.0, front=8.0, length=10.0, n_bins=100,
+                    chunk=512, max_steps=200000, device="cuda"):
+    """Fig. 6: the same star at two inclinations, from empty tubes, read when
+    the front has crossed `front` radii.  A smaller inclination gives a larger
+    surface density (cos i) and accelerates the beam to higher energies."""
+    from . import Batch
+    cpr = cells_per_lambda * a / (2.0 * math.pi)
+    cfgs = [inclination_tube(i, a=a, cells_per_r=cpr, length=length) for i in incl_values]
+    b = Batch([synth.tube_params(c) for c in cfgs], device=device)
+    rows = _measure(b, cfgs, incl_values, front, 1.0, n_bins, chunk, max_steps)
+    b.close()
+    for r in rows:
+        r["incl"] = float(r.pop("label"))
+    return rows
 
 
 def main(argv=None):

@@ -22,3 +22,22 @@ def test_sclf_sweep_plausibility():
     assert hi["gamma_plateau"] > 1.5 * lo["gamma_plateau"]
     assert hi["amplitude"] > lo["amplitude"]
     assert lo["front"] >= 14.0 and hi["front"] >= 14.0
+
+
+def test_inclination_fig6():
+    """Fig. 6: the same star at i = 0.1 and 0.5 (whole eq. (6) background).  The
+    smaller inclination has the larger surface density (cos i) and accelerates
+    the beam to higher energies; the energy ratio follows cos(0.1)/cos(0.5) up to
+    the small inclination term, which favours the larger angle."""
+    import math
+
+    from paper_1011_6330_amd import sweep
+    rows = sweep.run_inclination((0.1, 0.5))
+    for r in rows:
+        say("inclination", {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()})
+    small, large = rows
+    assert small["front"] >= 8.0 and large["front"] >= 8.0
+    ratio = small["gamma_plateau"] / large["gamma_plateau"]
+    say("gamma ratio i=0.1 / i=0.5", ratio, "cos ratio", math.cos(0.1) / math.cos(0.5))
+    assert small["gamma_peak"] > large["gamma_peak"]
+    assert 1.0 < ratio < math.cos(0.1) / math.cos(0.5) * 1.05
