@@ -1,5 +1,5 @@
 // field_body.h -- per-tile body of the leap-frog field update and the SCLF
-// injection, shared by the single-tube kernel and the batched persistent kernel.
+// injection, shared by the single-tube kernel and the batched field kernel.
 #pragma once
 
 #include <math.h>

@@ -1,5 +1,5 @@
 // push_body.h -- per-tile bodies of the particle push (FP64 and FP32-bulk),
-// shared by the single-tube kernels and the batched persistent kernel so that
+// shared by the single-tube kernels and the batched push kernel so that
 // a tube computes the same bits whichever launch runs it.
 #pragma once
 
