@@ -163,6 +163,34 @@ def test_uniform_field_test_particle():
     assert u[0] == 398.5 * 10.0 / 1024     # u_n = u_0 + n K, K = (q/m) dt E0 = 10/1024
 
 
+def test_gamma_velocity_bits():
+    """The push's gamma = sqrt(1 + u^2) and v = u / gamma against the oracle's C
+    library square root and division, bit for bit.  Particles start at x = 0 in
+    a zero field, so after one step x = v / 2 exactly (dt/dz = 1/2) and each
+    stored position holds the bits of v.  u spans 2^-1074 .. 1e153, the edges
+    of the range [2^-400, 2^400] where the push skips the library's range
+    scaling, and the powers of two in between."""
+    rng = np.random.default_rng(5)
+    edges = [2.0 ** -400, 2.0 ** 400, 2.0 ** -1022]
+    special = [5e-324, 1.0, 0.5, 3.0] + edges + [np.nextafter(e, 0.0) for e in edges] + \
+              [np.nextafter(e, np.inf) for e in edges] + [2.0 ** k for k in range(-80, 80)]
+    u = np.concatenate([10.0 ** rng.uniform(-323.5, 153.0, 200000), np.array(special)])
+    x = np.zeros_like(u)
+    cfg = dict(synth.preset("c1"), flags=1 | 2, capacity=len(u) + 8)
+    g, o = make_pair(cfg, x, u)
+    ez = np.zeros(1024)
+    g.write_fields(ez=ez)
+    o.ez[:] = ez
+    g.step(1)
+    o.step(1)
+    gx, gu = g.read_particles()
+    assert len(gx) == len(u) == o.n
+    assert np.array_equal(gu, o.u[:o.n]) and np.array_equal(gu, u)
+    bad = np.flatnonzero(gx != o.x[:o.n])
+    assert bad.size == 0, f"{bad.size} positions differ, first u = {u[bad[:5]]}"
+    g.close()
+
+
 def test_exit_absorb_and_gamma_sum():
     N = 64
     cfg = dict(synth.preset("c1"), n_cells=N, length=1.0, flags=1 | 2, capacity=16)
