@@ -44,7 +44,7 @@ B_F32_HIGH = 32                # cell, offset (4 B each), u (f64)
 WORKLOADS = {
     "c1": "c1: flat-space SCLF tube, 1024 cells, cold start (~3e3 particles), dt=dz/2",
     "c2": "c2: frame-dragging tube (kappa=0.15, R*=10R, a=6878), 65536 cells, ~4.0e7 warm particles, "
-          "gamma up to ~6e6, dt=dz/2, cell sort every 16 steps",
+          "gamma up to ~6e6, dt=dz/2, cell sort every 64 steps",
     "c4": "c4: 64-knot frame-dragging tube, 4096 cells, ~1e6 warm particles",
     "c5": "c5: frame-dragging tube (a=6809), 2^20 cells, L=100R, ~2.5e8 warm particles, sort every 16",
 }

@@ -34,10 +34,10 @@ PRESETS = {
                     rho_kind=RHO_UNIFORM, rho_amp=1.0, kappa=0.0, r_star=10.0, fp_bits=32,
                     sort_every=0, capacity=1 << 17, flags=0, steps=7000, warm=0),
     # frame dragging, the paper's (R, omega_p) = (6253, 1.1) pair: a = 6878, 65,536 cells,
-    # about 4e7 particles warm-started with gamma up to ~6e6
+    # about 4e7 particles warm-started with gamma up to ~6e6, cell sort every 64 steps
     "c2": dict(n_cells=65536, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=q_over_m_for(6878.0),
                ppc=610.0, rho_kind=RHO_FRAME_DRAG, rho_amp=1.0, kappa=0.15, r_star=10.0,
-               fp_bits=32, sort_every=16, capacity=int(610 * 65536 * 1.05), flags=0, steps=20000,
+               fp_bits=32, sort_every=64, capacity=int(610 * 65536 * 1.05), flags=0, steps=20000,
                warm=610 * 65536),
     # the frame-dragging tube with the whole of eq. (6): redshift (r_g/R_* = 0.4) and the
     # inclination term of the paper's standard pulsar (i = 0.5 rad, theta_* = 0.67 theta_p,
@@ -45,7 +45,7 @@ PRESETS = {
     "c2gr": dict(n_cells=65536, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=q_over_m_for(6878.0),
                  ppc=610.0, rho_kind=RHO_GR, rho_amp=1.0, kappa=0.15, r_star=10.0, incl=0.5,
                  theta_star=0.67 * 0.014, cos_phi=1.0, rg_over_rstar=0.4,
-                 fp_bits=32, sort_every=16, capacity=int(610 * 65536 * 1.05), flags=0, steps=20000,
+                 fp_bits=32, sort_every=64, capacity=int(610 * 65536 * 1.05), flags=0, steps=20000,
                  warm=610 * 65536),
     # adjoint workload: 4096 cells, 64 knots, about 1e6 particles
     # (the macro charge is fixed at its nominal value so that it does not move with the knots)
