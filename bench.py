@@ -304,7 +304,7 @@ def run_ensemble(steps, precision=1):
             "dtype": "f32+f64" if precision else "f64", "launch": cfg, "steps": steps,
             "workload": "256 frame-dragging tubes, cells log-uniform 2048-65536, particles log-uniform 1e4-1e6, "
                         "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk (fp64: the same tubes in FP64), "
-                        "one graph launch per 16-step round"}
+                        "one graph launch per 64-step round (steps and cell sort)"}
 
 
 def run_adjoint_leg(steps, ckpt=50):

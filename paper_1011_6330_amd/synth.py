@@ -122,7 +122,7 @@ def random_particles(N, n, seed=0, u_lo=-3.0, u_hi=40.0, stream=2):
     return x, u
 
 
-def ensemble(n_tubes=256, seed=0, precision=1, sort_every=16, slack=1.3):
+def ensemble(n_tubes=256, seed=0, precision=1, sort_every=64, slack=1.3):
     """Tubes of the batched workload: per tube t, four uniforms from Philox stream
     1000 + t give N_t = round(2048 * 32^U1) cells (2,048 .. 65,536), kappa_t =
     0.05 + 0.15 U2, A_t = 0.3 * 10^U3 (0.3 .. 3), N_p,t = round(1e4 * 100^U4)
