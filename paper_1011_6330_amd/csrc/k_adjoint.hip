@@ -27,19 +27,14 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
-// dst[key] += val for every lane with `want`, one FP64 atomic per distinct key.
-__device__ __forceinline__ void wave_add_keyed_f64(double *dst, int key, double val, bool want)
+// dst[key] += val for every lane with `want`: lanes with the same key in
+// consecutive positions form a run, a segmented DPP scan sums each run, and the
+// run's last lane issues one FP64 atomic.  Wave-collective.
+__device__ __forceinline__ void wave_add_runs_f64(double *dst, int key, double val, bool want)
 {
-    unsigned long long pend = __ballot(want);
-    while (pend) {
-        const int leader = __ffsll(pend) - 1;
-        const int lk = __shfl(key, leader);
-        const bool mine = want && key == lk;
-        const double v = wave_sum_f64(mine ? val : 0.0);
-        if ((int)__lane_id() == leader && v != 0.0) atomicAdd(dst + lk, v);
-        pend &= ~__ballot(mine);
-        want = want && !mine;
-    }
+    const WaveRun r = wave_runs_i32(key, want);
+    const double s = run_sum_to_tail(want ? val : 0.0, r.rank);
+    if (want && (int)__lane_id() == r.end - 1 && s != 0.0) atomicAdd(dst + key, s);
 }
 
 __global__ __launch_bounds__(256) void k_copy_slots(const double *X, const double *U, double *Xc, double *Uc,
@@ -171,8 +166,8 @@ __global__ __launch_bounds__(256) void k_adj_particles(Consts c, AdjPartArgs a)
         a.lu[p] = 0.0;
     }
     (void)live;
-    wave_add_keyed_f64(a.lk, ka, va, wa);
-    wave_add_keyed_f64(a.lk, kb, vb, wb);
+    wave_add_runs_f64(a.lk, ka, va, wa);
+    wave_add_runs_f64(a.lk, kb, vb, wb);
     const double gs = wave_sum_f64(gr);
     if (__lane_id() == 0 && gs != 0.0) atomicAdd(a.grate, gs);
 }

@@ -191,8 +191,8 @@ __device__ __forceinline__ WaveRun wave_runs_i32(int key, bool want)
 // segmented inclusive scan on DPP, row_shr 1, 2, 4, 8 inside each row of 16
 // lanes, then row_bcast:15 (rows 0 -> 1, 2 -> 3) and row_bcast:31 (row 1 ->
 // rows 2, 3), each step taken only where the source lane lies in the same run.
-// On a run's last lane it is the run total.  Every lane must call it; values
-// are integer-valued doubles below 2^53, so every addition is exact.
+// On a run's last lane it is the run total.  Every lane must call it.  For
+// integer-valued doubles below 2^53 (the current) every addition is exact.
 __device__ __forceinline__ double run_sum_to_tail(double v, int rank)
 {
     const int lane = (int)__lane_id();
