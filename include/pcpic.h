@@ -314,8 +314,10 @@ typedef struct pic_adjoint_out {
     double backward_ms;     /* device time of the recompute + reverse sweep             */
 } pic_adjoint_out;
 
-/* Device bytes of the tape pic_run_adjoint needs (checkpoints, one segment of
- * recorded steps, adjoint arrays), 0 if the handle cannot run the adjoint. */
+/* Device bytes of the tape pic_run_adjoint needs (checkpoints, the recorded
+ * steps of two segments, adjoint arrays), 0 if the handle cannot run the
+ * adjoint.  The reverse sweep of one segment overlaps the recompute of the
+ * previous one on a second stream the call creates and destroys. */
 size_t pic_adjoint_tape_bytes(pic_handle *h, int64_t n_steps, int32_t checkpoint_every);
 
 /* Errors: PIC_EINVAL (requirements above), PIC_EWORKSPACE (tape too small or

@@ -1297,7 +1297,8 @@ struct Tape {
     int64_t T, K, nck, N, cap;
     std::vector<double *> ck_x, ck_u, ck_ez, ck_er, ck_b;   // checkpoint c: state at step c*K
     std::vector<DevCounters *> ck_ctr;
-    std::vector<double *> sg_x, sg_u, sg_ez, sg_er, sg_b;   // segment slots 1..K
+    int nsets;                                              // segment slot sets (2 when segments overlap)
+    std::vector<double *> sg_x[2], sg_u[2], sg_ez[2], sg_er[2], sg_b[2];   // segment slots 1..K
     int64_t *nslots;                                        // [T + 1]
     double *lx, *lu, *lez, *ler, *lb, *lbp, *lk, *grate, *gphi, *cp, *dp, *g_rho, *params;
     DevCounters *final_ctr;
@@ -1328,17 +1329,23 @@ Tape carve_tape(pic_handle *h, int64_t T, int64_t K, uint8_t *base)
         t.ck_b.push_back((double *)take(N * 8));
         t.ck_ctr.push_back((DevCounters *)take(sizeof(DevCounters)));
     }
-    t.sg_x.push_back(nullptr);   // slot 0 of a segment is its checkpoint
-    t.sg_u.push_back(nullptr);
-    t.sg_ez.push_back(nullptr);
-    t.sg_er.push_back(nullptr);
-    t.sg_b.push_back(nullptr);
-    for (int64_t k = 1; k <= K; ++k) {
-        t.sg_x.push_back((double *)take(cap * 8));
-        t.sg_u.push_back((double *)take(cap * 8));
-        t.sg_ez.push_back((double *)take(N * 8));
-        t.sg_er.push_back((double *)take((N + 1) * 8));
-        t.sg_b.push_back((double *)take(N * 8));
+    // two sets of segment slots when there are two segments or more: the
+    // recompute of one segment fills one set while the reverse sweep of the
+    // next reads the other
+    t.nsets = t.nck > 1 ? 2 : 1;
+    for (int q = 0; q < t.nsets; ++q) {
+        t.sg_x[q].push_back(nullptr);   // slot 0 of a segment is its checkpoint
+        t.sg_u[q].push_back(nullptr);
+        t.sg_ez[q].push_back(nullptr);
+        t.sg_er[q].push_back(nullptr);
+        t.sg_b[q].push_back(nullptr);
+        for (int64_t k = 1; k <= K; ++k) {
+            t.sg_x[q].push_back((double *)take(cap * 8));
+            t.sg_u[q].push_back((double *)take(cap * 8));
+            t.sg_ez[q].push_back((double *)take(N * 8));
+            t.sg_er[q].push_back((double *)take((N + 1) * 8));
+            t.sg_b[q].push_back((double *)take(N * 8));
+        }
     }
     t.nslots = (int64_t *)take((size_t)(T + 1) * 8);
     t.lx = (double *)take(cap * 8);
@@ -1443,6 +1450,12 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
     const int jb_final = h->jbuf;
 
     // ---- reverse sweep, one segment at a time from its checkpoint ----
+    // The recompute of segment ck-1 runs on a second stream, into the other set
+    // of segment slots, while the reverse sweep of segment ck runs on the
+    // tube's stream: the two touch disjoint memory (the recompute owns the
+    // counters, the current and the kick array; the sweep reads recorded slots,
+    // fields and slot counts and owns the adjoint arrays), and events order
+    // each recompute before its sweep and each set's reuse after its sweep.
     HIP_OK(hipEventRecord(ev[2], h->stream));
     HIP_OK(launch_zero_f64(h, t.lx, t.cap));
     HIP_OK(launch_zero_f64(h, t.lu, t.cap));
@@ -1450,32 +1463,78 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
     HIP_OK(launch_zero_f64(h, t.ler, N + 1));
     HIP_OK(launch_zero_f64(h, t.lb, N));
     HIP_OK(launch_zero_f64(h, t.grate, 1));
-    for (int64_t ck = t.nck - 1; ck >= 0; --ck) {
+    hipStream_t const main_s = h->stream;
+    hipStream_t rec_s = nullptr;
+    hipEvent_t sev[5] = {};                       // forward done; recompute done [2]; sweep done [2]
+    auto cleanup = [&]() {
+        h->stream = main_s;
+        for (auto &e : sev)
+            if (e) (void)hipEventDestroy(e);
+        if (rec_s) {
+            (void)hipStreamSynchronize(rec_s);
+            (void)hipStreamDestroy(rec_s);
+        }
+    };
+    auto fail_rev = [&](pic_status r) {
+        cleanup();
+        return done(r);
+    };
+#define REV_OK(expr)                                                                                 \
+    do {                                                                                             \
+        const hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail_rev(fail(PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+    REV_OK(hipStreamCreateWithFlags(&rec_s, hipStreamNonBlocking));
+    for (auto &e : sev) REV_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    REV_OK(hipEventRecord(sev[0], main_s));
+    REV_OK(hipStreamWaitEvent(rec_s, sev[0], 0));
+    // recompute steps s0 .. s0+m-1 of segment ck out of place on rec_s: slot k of
+    // its set holds the state before step s0+k
+    auto recompute = [&](int64_t ck) -> hipError_t {
+        const int q = t.nsets == 2 ? (int)(ck & 1) : 0;
         const int64_t s0 = ck * K, m = (T - s0) < K ? (T - s0) : K;
-        // recompute steps s0 .. s0+m-1 out of place: slot k holds the state before step s0+k
-        HIP_OK(hipMemcpyAsync(w.ctr, t.ck_ctr[ck], sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
-        HIP_OK(launch_zero_i64(h, w.j[0], N));
-        HIP_OK(launch_zero_i64(h, w.j[1], N));
-        HIP_OK(launch_kick_from(h, t.ck_ez[ck]));
-        for (int64_t k = 0; k < m; ++k) {
-            const double *xi = k == 0 ? t.ck_x[ck] : t.sg_x[(size_t)k], *ui = k == 0 ? t.ck_u[ck] : t.sg_u[(size_t)k];
-            const double *ezo = k == 0 ? t.ck_ez[ck] : t.sg_ez[(size_t)k];
-            const double *ero = k == 0 ? t.ck_er[ck] : t.sg_er[(size_t)k];
-            const double *bo = k == 0 ? t.ck_b[ck] : t.sg_b[(size_t)k];
-            if (k == m - 1) break;   // the state after the segment's last step is not needed
-            HIP_OK(launch_push_f64_ptrs(h, xi, ui, t.sg_x[(size_t)k + 1], t.sg_u[(size_t)k + 1]));
-            HIP_OK(launch_field_ptrs(h, ezo, ero, bo, t.sg_ez[(size_t)k + 1], t.sg_er[(size_t)k + 1],
-                                     t.sg_b[(size_t)k + 1], t.sg_x[(size_t)k + 1], t.sg_u[(size_t)k + 1]));
+        h->stream = rec_s;
+        hipError_t e = hipMemcpyAsync(w.ctr, t.ck_ctr[ck], sizeof(DevCounters), hipMemcpyDeviceToDevice, rec_s);
+        if (e == hipSuccess) e = launch_zero_i64(h, w.j[0], N);
+        if (e == hipSuccess) e = launch_zero_i64(h, w.j[1], N);
+        if (e == hipSuccess) e = launch_kick_from(h, t.ck_ez[ck]);
+        for (int64_t k = 0; k + 1 < m && e == hipSuccess; ++k) {
+            const double *xi = k == 0 ? t.ck_x[ck] : t.sg_x[q][(size_t)k];
+            const double *ui = k == 0 ? t.ck_u[ck] : t.sg_u[q][(size_t)k];
+            const double *ezo = k == 0 ? t.ck_ez[ck] : t.sg_ez[q][(size_t)k];
+            const double *ero = k == 0 ? t.ck_er[ck] : t.sg_er[q][(size_t)k];
+            const double *bo = k == 0 ? t.ck_b[ck] : t.sg_b[q][(size_t)k];
+            e = launch_push_f64_ptrs(h, xi, ui, t.sg_x[q][(size_t)k + 1], t.sg_u[q][(size_t)k + 1]);
+            if (e == hipSuccess)
+                e = launch_field_ptrs(h, ezo, ero, bo, t.sg_ez[q][(size_t)k + 1], t.sg_er[q][(size_t)k + 1],
+                                      t.sg_b[q][(size_t)k + 1], t.sg_x[q][(size_t)k + 1], t.sg_u[q][(size_t)k + 1]);
             h->jbuf ^= 1;
+        }
+        h->stream = main_s;
+        if (e == hipSuccess) e = hipEventRecord(sev[1 + q], rec_s);
+        return e;
+    };
+    REV_OK(recompute(t.nck - 1));
+    for (int64_t ck = t.nck - 1; ck >= 0; --ck) {
+        const int q = t.nsets == 2 ? (int)(ck & 1) : 0;
+        const int64_t s0 = ck * K, m = (T - s0) < K ? (T - s0) : K;
+        REV_OK(hipStreamWaitEvent(main_s, sev[1 + q], 0));
+        if (ck >= 1) {
+            // the other set was last read by the sweep of segment ck+1
+            if (ck + 1 <= t.nck - 1) REV_OK(hipStreamWaitEvent(rec_s, sev[3 + (q ^ 1)], 0));
+            REV_OK(recompute(ck - 1));
         }
         for (int64_t k = m - 1; k >= 0; --k) {
             const int64_t st = s0 + k;
-            AdjStepPtrs a{k == 0 ? t.ck_x[ck] : t.sg_x[(size_t)k], k == 0 ? t.ck_u[ck] : t.sg_u[(size_t)k],
-                          k == 0 ? t.ck_ez[ck] : t.sg_ez[(size_t)k], t.nslots + st, t.nslots + st + 1, n_pre, nex,
+            AdjStepPtrs a{k == 0 ? t.ck_x[ck] : t.sg_x[q][(size_t)k], k == 0 ? t.ck_u[ck] : t.sg_u[q][(size_t)k],
+                          k == 0 ? t.ck_ez[ck] : t.sg_ez[q][(size_t)k], t.nslots + st, t.nslots + st + 1, n_pre, nex,
                           t.lx, t.lu, t.lez, t.ler, t.lb, t.lbp, t.lk, t.grate};
-            HIP_OK(launch_adj_step(h, a));
+            REV_OK(launch_adj_step(h, a));
         }
+        REV_OK(hipEventRecord(sev[3 + q], main_s));
     }
+#undef REV_OK
+    cleanup();
     HIP_OK(launch_adj_finish(h, t.lez, t.ler, t.gphi, t.cp, t.dp, t.g_rho, t.params));
     HIP_OK(hipEventRecord(ev[3], h->stream));
     // restore the end state the forward left
