@@ -25,9 +25,10 @@ __global__ __launch_bounds__(BLOCK) void k_push_f32(Consts c, Push32Args a)
     const bool hi = blockIdx.x >= a.blocks_lo;
     const int64_t b = hi ? (int64_t)(blockIdx.x - a.blocks_lo) : (int64_t)blockIdx.x;
     const int64_t n = hi ? a.ctr->n_slots_hi : a.ctr->n_slots;
-    const int64_t tile0 = b * (BLOCK * 4);
+    const int64_t tile0 = b * (BLOCK * (hi ? F32_PPT_HI : F32_PPT_LO));
     if (tile0 >= n) return;                       // whole block idle (uniform)
-    push_tile_f32<BLOCK, NT>(c, a, hi, n, tile0);
+    if (hi) push_tile_hi<BLOCK, NT>(c, a, n, tile0);
+    else push_tile_lo<BLOCK, NT>(c, a, n, tile0);
 }
 
 // ------------------------------------------------------------------------
@@ -271,12 +272,13 @@ static hipError_t launch_push32_t(pic_handle *h)
 {
     const Workspace &w = h->ws;
     const int b = h->pbuf;
-    const int64_t tile = (int64_t)BLOCK * 4;
-    const unsigned nb = (unsigned)((h->c.cap + tile - 1) / tile);
+    const int64_t tlo = (int64_t)BLOCK * F32_PPT_LO, thi = (int64_t)BLOCK * F32_PPT_HI;
+    const unsigned nb = (unsigned)((h->c.cap + tlo - 1) / tlo);
+    const unsigned nbh = (unsigned)((h->c.cap + thi - 1) / thi);
     Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b], w.k32, w.k64,
                  (unsigned long long *)w.j[h->jbuf], w.ctr, nb,
                  h->hist_on ? (unsigned long long *)w.cell_count : nullptr, h->u_hi};
-    hipLaunchKernelGGL((k_push_f32<BLOCK, NT>), dim3(2 * nb), dim3(BLOCK), 0, h->stream, h->c, a);
+    hipLaunchKernelGGL((k_push_f32<BLOCK, NT>), dim3(nb + nbh), dim3(BLOCK), 0, h->stream, h->c, a);
     return hipGetLastError();
 }
 

@@ -53,6 +53,13 @@ struct Consts {
     double gr_g;      // PIC_RHO_GR: r_g / R_*
 };
 
+// Slots per thread of the two FP32-bulk push streams: the low stream loads its
+// three 4-byte fields as 16-byte vectors of 4 slots; the high stream takes 2
+// slots (8-byte cell and offset vectors, one 16-byte f64 momentum vector), which
+// keeps its registers, and so its occupancy, at those of the FP64 push.
+constexpr int F32_PPT_LO = 4;
+constexpr int F32_PPT_HI = 2;
+
 // Cell-sort keys.  A live particle's key is its cell refined into 2^sub bins
 // (so that a wave's particles sit within a small fraction of a cell and cross
 // cell edges together); in FP32-bulk mode the keys of the high stream follow
@@ -146,7 +153,8 @@ struct TubeDev {
     long long *cell_count, *cell_off, *total_lo, *blk_sum;
     double *rhs, *cp, *dp, *phi;   // Poisson solve of eq. (4)
     double u_hi;
-    int64_t push_tiles;   // push tiles per particle stream at capacity
+    int64_t push_tiles;      // push tiles at capacity (FP32-bulk: of the low stream)
+    int64_t push_tiles_hi;   // FP32-bulk: push tiles of the high stream at capacity
     int64_t sort_chunks;  // 256-slot chunks per particle stream at capacity
     int64_t n_keys;       // sort keys (N, or 2(N+1) in FP32-bulk mode)
 };

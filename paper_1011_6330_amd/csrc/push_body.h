@@ -265,129 +265,135 @@ __device__ __forceinline__ void push_one_hi(const Consts &c, const Push32Args &a
     ur = stays ? u1 : u;
 }
 
-// One tile of BLOCK*4 consecutive slots of the low (hi = false) or high stream,
-// starting at tile0 (< n): each thread 4 consecutive slots (16-byte vectors of
-// the 4-byte fields), gathers issued before the first kick, one current flush.
+// One tile of BLOCK*F32_PPT_LO consecutive slots of the low stream, starting at
+// tile0 (< n): gathers issued before the first kick, one current flush.
 // Called by every thread of the block; wave-collective.
 template <int BLOCK, int NT>
-__device__ __forceinline__ void push_tile_f32(const Consts &c, const Push32Args &a, bool hi, int64_t n,
-                                              int64_t tile0)
+__device__ __forceinline__ void push_tile_lo(const Consts &c, const Push32Args &a, int64_t n, int64_t tile0)
 {
-    constexpr int PPT = 4;
+    constexpr int PPT = F32_PPT_LO;
     const int N = (int)c.N;
     const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
     const bool full = p0 + PPT <= n;
-    int *C = hi ? a.CH : a.CL;
-    float *O = hi ? a.OH : a.OL;
-
+    int *C = a.CL;
+    float *O = a.OL;
     int cs[PPT];
-    float os[PPT];
+    float os[PPT], us[PPT];
     if (full) {
         const ivec4 cv = ld16<NT, ivec4>(C + p0);
         const fvec4 ov = ld16<NT, fvec4>(O + p0);
+        const fvec4 uv = ld16<NT, fvec4>(a.UL + p0);
         cs[0] = cv.x; cs[1] = cv.y; cs[2] = cv.z; cs[3] = cv.w;
         os[0] = ov.x; os[1] = ov.y; os[2] = ov.z; os[3] = ov.w;
+        us[0] = uv.x; us[1] = uv.y; us[2] = uv.z; us[3] = uv.w;
     } else {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             cs[k] = p0 + k < n ? C[p0 + k] : -1;
             os[k] = p0 + k < n ? O[p0 + k] : 0.0f;
+            us[k] = p0 + k < n ? a.UL[p0 + k] : 0.0f;
         }
+    }
+    float E[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        float g;
+        int j;
+        const int jc = gather_face_f32(N, cs[k], os[k], g, j);
+        const float k0 = a.K32[jc], k1 = a.K32[jc + 1];
+        const float Ei = k0 + g * (k1 - k0);
+        const float lo = j < 0 ? k0 : Ei;
+        E[k] = j >= N - 1 ? k1 : lo;
     }
     DepAcc acc;
     acc.init(a.ctr);
-
-    if (!hi) {
-        // ---------------- low stream: FP32 momentum ----------------
-        float us[PPT];
-        if (full) {
-            const fvec4 uv = ld16<NT, fvec4>(a.UL + p0);
-            us[0] = uv.x; us[1] = uv.y; us[2] = uv.z; us[3] = uv.w;
-        } else {
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) us[k] = p0 + k < n ? a.UL[p0 + k] : 0.0f;
-        }
-        float E[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            float g;
-            int j;
-            const int jc = gather_face_f32(N, cs[k], os[k], g, j);
-            const float k0 = a.K32[jc], k1 = a.K32[jc + 1];
-            const float Ei = k0 + g * (k1 - k0);
-            const float lo = j < 0 ? k0 : Ei;
-            E[k] = j >= N - 1 ? k1 : lo;
-        }
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) push_one_lo(c, a, E[k], cs[k], os[k], us[k], acc);
-        if (full) {
-            st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
-            st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
-            st16<NT, fvec4>(a.UL + p0, fvec4{us[0], us[1], us[2], us[3]});
-        } else {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UL[p0 + k] = us[k]; }
-        }
-        acc.flush_current(a.J);
-        if (a.hist) {
-            int64_t key[PPT];
-            bool live[PPT];
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                live[k] = cs[k] >= 0;
-                key[k] = live[k] ? sort_key_f32(c, cs[k], os[k], fabs((double)us[k]) >= a.u_hi) : 0;
-            }
-            hist_add<PPT>(a.hist, key, live);
-        }
+    for (int k = 0; k < PPT; ++k) push_one_lo(c, a, E[k], cs[k], os[k], us[k], acc);
+    if (full) {
+        st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
+        st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
+        st16<NT, fvec4>(a.UL + p0, fvec4{us[0], us[1], us[2], us[3]});
     } else {
-        // ---------------- high stream: FP64 momentum ----------------
-        double us[PPT];
-        if (full) {
-            const dvec2 u01 = ld16<NT, dvec2>(a.UH + p0);
-            const dvec2 u23 = ld16<NT, dvec2>(a.UH + p0 + 2);
-            us[0] = u01.x; us[1] = u01.y; us[2] = u23.x; us[3] = u23.y;
-        } else {
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) us[k] = p0 + k < n ? a.UH[p0 + k] : 0.0;
-        }
-        double E[PPT];
+        for (int k = 0; k < PPT; ++k)
+            if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UL[p0 + k] = us[k]; }
+    }
+    acc.flush_current(a.J);
+    if (a.hist) {
+        int64_t key[PPT];
+        bool live[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            float g;
-            int j;
-            const int jc = gather_face_f32(N, cs[k], os[k], g, j);
-            const double k0 = a.K64[jc], k1 = a.K64[jc + 1];
-            const double Ei = k0 + (double)g * (k1 - k0);
-            const double lo = j < 0 ? k0 : Ei;
-            E[k] = j >= N - 1 ? k1 : lo;
+            live[k] = cs[k] >= 0;
+            key[k] = live[k] ? sort_key_f32(c, cs[k], os[k], fabs((double)us[k]) >= a.u_hi) : 0;
         }
+        hist_add<PPT>(a.hist, key, live);
+    }
+}
+
+// One tile of BLOCK*F32_PPT_HI consecutive slots of the high stream (f64
+// momentum), starting at tile0 (< n).  Wave-collective, as push_tile_lo.
+template <int BLOCK, int NT>
+__device__ __forceinline__ void push_tile_hi(const Consts &c, const Push32Args &a, int64_t n, int64_t tile0)
+{
+    constexpr int PPT = F32_PPT_HI;
+    const int N = (int)c.N;
+    const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
+    const bool full = p0 + PPT <= n;
+    int *C = a.CH;
+    float *O = a.OH;
+    int cs[PPT];
+    float os[PPT];
+    double us[PPT];
+    if (full) {
+        const ivec2 cv = ld16<NT, ivec2>(C + p0);
+        const fvec2 ov = ld16<NT, fvec2>(O + p0);
+        const dvec2 uv = ld16<NT, dvec2>(a.UH + p0);
+        cs[0] = cv.x; cs[1] = cv.y;
+        os[0] = ov.x; os[1] = ov.y;
+        us[0] = uv.x; us[1] = uv.y;
+    } else {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            push_one_hi(c, a, E[k], cs[k], os[k], us[k], acc);
-            if (k == 1) __builtin_amdgcn_sched_barrier(0);
+            cs[k] = p0 + k < n ? C[p0 + k] : -1;
+            os[k] = p0 + k < n ? O[p0 + k] : 0.0f;
+            us[k] = p0 + k < n ? a.UH[p0 + k] : 0.0;
         }
-        if (full) {
-            st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
-            st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
-            st16<NT, dvec2>(a.UH + p0, dvec2{us[0], us[1]});
-            st16<NT, dvec2>(a.UH + p0 + 2, dvec2{us[2], us[3]});
-        } else {
+    }
+    double E[PPT];
 #pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UH[p0 + k] = us[k]; }
-        }
-        acc.flush_current(a.J);
-        if (a.hist) {
-            int64_t key[PPT];
-            bool live[PPT];
+    for (int k = 0; k < PPT; ++k) {
+        float g;
+        int j;
+        const int jc = gather_face_f32(N, cs[k], os[k], g, j);
+        const double k0 = a.K64[jc], k1 = a.K64[jc + 1];
+        const double Ei = k0 + (double)g * (k1 - k0);
+        const double lo = j < 0 ? k0 : Ei;
+        E[k] = j >= N - 1 ? k1 : lo;
+    }
+    DepAcc acc;
+    acc.init(a.ctr);
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                live[k] = cs[k] >= 0;
-                key[k] = live[k] ? sort_key_f32(c, cs[k], os[k], fabs(us[k]) >= a.u_hi) : 0;
-            }
-            hist_add<PPT>(a.hist, key, live);
+    for (int k = 0; k < PPT; ++k) push_one_hi(c, a, E[k], cs[k], os[k], us[k], acc);
+    if (full) {
+        st16<NT, ivec2>(C + p0, ivec2{cs[0], cs[1]});
+        st16<NT, fvec2>(O + p0, fvec2{os[0], os[1]});
+        st16<NT, dvec2>(a.UH + p0, dvec2{us[0], us[1]});
+    } else {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UH[p0 + k] = us[k]; }
+    }
+    acc.flush_current(a.J);
+    if (a.hist) {
+        int64_t key[PPT];
+        bool live[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            live[k] = cs[k] >= 0;
+            key[k] = live[k] ? sort_key_f32(c, cs[k], os[k], fabs(us[k]) >= a.u_hi) : 0;
         }
+        hist_add<PPT>(a.hist, key, live);
     }
 }
 

@@ -171,10 +171,12 @@ __device__ __forceinline__ void gamma_velocity(double u, double tt, double &gam,
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec4 __attribute__((ext_vector_type(4)));
 typedef int ivec4 __attribute__((ext_vector_type(4)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+typedef int ivec2 __attribute__((ext_vector_type(2)));
 
-// Particle-stream access of 16 bytes; NT = 1 marks it nontemporal (each value
-// is streamed once per step and should not displace the kick array and the
-// current in L2).
+// Particle-stream vector access (16 or 8 bytes, the size of V); NT = 1 marks it
+// nontemporal (each value is streamed once per step and should not displace
+// the kick array and the current in L2).
 template <int NT, typename V>
 __device__ __forceinline__ V ld16(const void *p)
 {
