@@ -38,7 +38,6 @@ template <int BLOCK, int PPT, int NT, int F32>
 __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
 {
     constexpr int TILE = BLOCK * (F32 ? F32_PPT_LO : PPT);
-    constexpr int TILE_HI = BLOCK * F32_PPT_HI;
     const int64_t it = blockIdx.x;
     if (it >= b.push_pref[b.n_tubes]) return;
     {
@@ -46,15 +45,25 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
         const TubeDev &T = b.tubes[t];
         const int64_t local = it - b.push_pref[t];
         const bool hi = F32 && local >= T.push_tiles;
-        const int64_t tile0 = hi ? (local - T.push_tiles) * TILE_HI : local * TILE;
+        // in FP32-bulk mode an item covers TILE slots of either stream: one low
+        // tile, or the high stream's tiles of BLOCK*F32_PPT_HI slots in turn
+        const int64_t tile0 = (hi ? local - T.push_tiles : local) * TILE;
         if (F32) {
             const int64_t n = hi ? T.ctr->n_slots_hi : T.ctr->n_slots;
             if (tile0 >= n) return;                   // tile past the stream's slots (uniform)
             Push32Args a{T.cl[b.pb], T.ol[b.pb], T.ul[b.pb], T.ch[b.pb], T.oh[b.pb], T.uh[b.pb], T.k32, T.k64,
                          (unsigned long long *)T.j[b.jb], T.ctr, 0u,
                          b.hist ? (unsigned long long *)T.cell_count : nullptr, T.u_hi};
-            if (hi) push_tile_hi<BLOCK, NT>(T.c, a, n, tile0);
-            else push_tile_lo<BLOCK, NT>(T.c, a, n, tile0);
+            if (!hi) {
+                push_tile_lo<BLOCK, NT>(T.c, a, n, tile0);
+            } else {
+#pragma unroll 1
+                for (int r = 0; r < F32_PPT_LO / F32_PPT_HI; ++r) {
+                    const int64_t t0 = tile0 + (int64_t)r * (BLOCK * F32_PPT_HI);
+                    if (t0 >= n) break;
+                    push_tile_hi<BLOCK, NT>(T.c, a, n, t0);
+                }
+            }
         } else {
             const int64_t n = T.ctr->n_slots;
             if (tile0 >= n) return;

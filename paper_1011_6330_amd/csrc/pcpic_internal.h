@@ -154,7 +154,7 @@ struct TubeDev {
     double *rhs, *cp, *dp, *phi;   // Poisson solve of eq. (4)
     double u_hi;
     int64_t push_tiles;      // push tiles at capacity (FP32-bulk: of the low stream)
-    int64_t push_tiles_hi;   // FP32-bulk: push tiles of the high stream at capacity
+    int64_t push_tiles_hi;   // FP32-bulk: push items of the high stream (each walks BLOCK*F32_PPT_LO slots)
     int64_t sort_chunks;  // 256-slot chunks per particle stream at capacity
     int64_t n_keys;       // sort keys (N, or 2(N+1) in FP32-bulk mode)
 };
