@@ -20,6 +20,8 @@ sort on the tube's stream.  Prints one JSON line:
   fp32_bulk      the same tube with the FP32-bulk push (f32 momentum below
                  gamma = 1e6, f64 above), with its own roofline; low_gamma: the
                  same geometry with a beam below 1e6, FP64 against FP32-bulk
+  large_tube     the 2^20-cell tube with 2.5e8 particles in FP64 and FP32-bulk,
+                 with the Gauss residual at the end
   ensemble       256 tubes of uneven size, one graph launch per round (FP32-bulk;
                  fp64: the same tubes in FP64)
   plausibility   flat-space SCLF over a = omega_p R / c (sec. 3, Table 2): gamma
@@ -54,7 +56,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def run_tube(cfg, x, u, precision, steps, warmup, push=None, tune=True):
+def run_tube(cfg, x, u, precision, steps, warmup, push=None, tune=True, diag=None):
     """Warm a tube up (tuning its push shape), then time `steps` steps."""
     import torch
 
@@ -83,8 +85,9 @@ def run_tube(cfg, x, u, precision, steps, warmup, push=None, tune=True):
     # kernel durations: `steps` more steps with HIP events around every push,
     # field update and sort, on the tube's own stream
     tim = tube.step_timed(steps)
-    d2 = tube.diagnostics(fields=False)
+    d2 = tube.diagnostics(fields=False, **(diag or {}))
     tim["alive"] = 0.5 * (d1["n_alive"] + d2["n_alive"])
+    tim["gauss_max"], tim["gauss_l2"] = d2["gauss_max"], d2["gauss_l2"]
     tim["alive_high"] = 0.5 * (d1["n_slots_high"] + d2["n_slots_high"])
     tube.close()
     del tube
@@ -148,6 +151,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 2^20-cell, 2.5e8-particle tube")
+    ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -233,6 +238,10 @@ def main():
         log(f"fp32-bulk, low gamma: {mel / args.steps * 1e3:.3f} ms/step (push {mroof['avg_launch_us']:.1f} us) vs "
             f"fp64 {lel / args.steps * 1e3:.3f} ms/step")
 
+    # ---- the large tube: 2^20 cells, 2.5e8 particles, FP64 and FP32-bulk ----
+    if not args.no_large and args.config == "c2":
+        result["large_tube"] = run_large(args.large_steps, push, push32)
+
     # ---- ensemble: 256 tubes, one graph launch per round ----
     if not args.no_ensemble:
         result["ensemble"] = run_ensemble(args.ensemble_steps, precision=1)
@@ -269,6 +278,37 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, x, u, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def run_large(steps, push, push32):
+    """C5: the 2^20-cell, L = 100R frame-dragging tube with 2.5e8 warm particles,
+    cell sort every 16 steps, in FP64 and in FP32-bulk; the Gauss residual of
+    eq. (2) at the end of each run, evaluated in FP64."""
+    import gc
+
+    from paper_1011_6330_amd import synth
+    cfg = synth.preset("c5")
+    x, u = synth.warm_start(cfg)
+    out = {"workload": WORKLOADS["c5"], "steps": steps}
+    for prec, key, shape, bpp in ((0, "fp64", push, B_FP64), (1, "fp32_bulk", push32, None)):
+        t0 = time.perf_counter()
+        d0, d1, tim, el, sh = run_tube(cfg, x, u, prec, steps, 16, push=shape, tune=False,
+                                       diag=dict(gauss=True))
+        alive = 0.5 * (d0["n_alive"] + d1["n_alive"])
+        if bpp is None:
+            nbytes = B_F32_LOW * max(tim["alive"] - tim["alive_high"], 0.0) + B_F32_HIGH * tim["alive_high"]
+        else:
+            nbytes = bpp * tim["alive"]
+        roof = roofline_of(nbytes, tim, "k_push_f64" if prec == 0 else "k_push_f32")
+        out[key] = {"value": alive * steps / el, "unit": "particle-steps/s", "ms_per_step": el / steps * 1e3,
+                    "particles": int(alive), "roofline": roof, "gauss_max": tim["gauss_max"],
+                    "gauss_l2": tim["gauss_l2"], "high_stream_fraction": tim["alive_high"] / max(tim["alive"], 1.0)}
+        log(f"large tube {key}: {el / steps * 1e3:.3f} ms/step for {alive:.3g} particles, push "
+            f"{roof['avg_launch_us']:.1f} us ({roof['achieved']:.0f} GB/s), Gauss max {tim['gauss_max']:.2e} "
+            f"({time.perf_counter() - t0:.1f} s)")
+    del x, u
+    gc.collect()
+    return out
 
 
 def run_ensemble(steps, precision=1):
