@@ -1412,32 +1412,38 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
         for (auto &e : ev) (void)hipEventDestroy(e);
         return r;
     };
+    // every failure from here on also releases the timing events
+#define ADJ_OK(expr)                                                                                  \
+    do {                                                                                              \
+        const hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return done(fail(PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
     DevCounters c0;
     s = read_counters(h, &c0);
     if (s != PIC_OK) return done(s);
     const int64_t n_pre = c0.n_slots;
 
     // ---- forward with checkpoints (the same steps as pic_step) ----
-    HIP_OK(hipEventRecord(ev[0], h->stream));
+    ADJ_OK(hipEventRecord(ev[0], h->stream));
     for (int64_t st = 0; st < T; ++st) {
         if (st % K == 0) {
             const int64_t ck = st / K;
             const int f = h->fbuf;
-            HIP_OK(launch_copy_slots(h, w.x[h->pbuf], w.u[h->pbuf], t.ck_x[ck], t.ck_u[ck]));
-            HIP_OK(hipMemcpyAsync(t.ck_ez[ck], w.ez[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
-            HIP_OK(hipMemcpyAsync(t.ck_er[ck], w.er[f], (size_t)(N + 1) * 8, hipMemcpyDeviceToDevice, h->stream));
-            HIP_OK(hipMemcpyAsync(t.ck_b[ck], w.b[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
-            HIP_OK(hipMemcpyAsync(t.ck_ctr[ck], w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+            ADJ_OK(launch_copy_slots(h, w.x[h->pbuf], w.u[h->pbuf], t.ck_x[ck], t.ck_u[ck]));
+            ADJ_OK(hipMemcpyAsync(t.ck_ez[ck], w.ez[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+            ADJ_OK(hipMemcpyAsync(t.ck_er[ck], w.er[f], (size_t)(N + 1) * 8, hipMemcpyDeviceToDevice, h->stream));
+            ADJ_OK(hipMemcpyAsync(t.ck_b[ck], w.b[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+            ADJ_OK(hipMemcpyAsync(t.ck_ctr[ck], w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
         }
-        HIP_OK(launch_record_slots(h, t.nslots + st));
-        HIP_OK(launch_push_f64(h));
-        HIP_OK(launch_field_inject(h));
+        ADJ_OK(launch_record_slots(h, t.nslots + st));
+        ADJ_OK(launch_push_f64(h));
+        ADJ_OK(launch_field_inject(h));
         h->fbuf ^= 1;
         h->jbuf ^= 1;
         h->step += 1;
     }
-    HIP_OK(launch_record_slots(h, t.nslots + T));
-    HIP_OK(hipEventRecord(ev[1], h->stream));
+    ADJ_OK(launch_record_slots(h, t.nslots + T));
+    ADJ_OK(hipEventRecord(ev[1], h->stream));
     DevCounters c1;
     s = read_counters(h, &c1);
     if (s != PIC_OK) return done(s);
@@ -1447,8 +1453,8 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
     out->loss = nex > 0 ? ldexp((double)(e1 - e0), -32) / (double)nex : 0.0;
     out->n_exit = nex;
     // keep what the recompute overwrites: counters and the last step's current
-    HIP_OK(hipMemcpyAsync(t.final_ctr, w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
-    HIP_OK(hipMemcpyAsync(t.final_jlast, w.j[1 - h->jbuf], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+    ADJ_OK(hipMemcpyAsync(t.final_ctr, w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+    ADJ_OK(hipMemcpyAsync(t.final_jlast, w.j[1 - h->jbuf], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
     const int jb_final = h->jbuf;
 
     // ---- reverse sweep, one segment at a time from its checkpoint ----
@@ -1458,13 +1464,13 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
     // counters, the current and the kick array; the sweep reads recorded slots,
     // fields and slot counts and owns the adjoint arrays), and events order
     // each recompute before its sweep and each set's reuse after its sweep.
-    HIP_OK(hipEventRecord(ev[2], h->stream));
-    HIP_OK(launch_zero_f64(h, t.lx, t.cap));
-    HIP_OK(launch_zero_f64(h, t.lu, t.cap));
-    HIP_OK(launch_zero_f64(h, t.lez, N));
-    HIP_OK(launch_zero_f64(h, t.ler, N + 1));
-    HIP_OK(launch_zero_f64(h, t.lb, N));
-    HIP_OK(launch_zero_f64(h, t.grate, 1));
+    ADJ_OK(hipEventRecord(ev[2], h->stream));
+    ADJ_OK(launch_zero_f64(h, t.lx, t.cap));
+    ADJ_OK(launch_zero_f64(h, t.lu, t.cap));
+    ADJ_OK(launch_zero_f64(h, t.lez, N));
+    ADJ_OK(launch_zero_f64(h, t.ler, N + 1));
+    ADJ_OK(launch_zero_f64(h, t.lb, N));
+    ADJ_OK(launch_zero_f64(h, t.grate, 1));
     hipStream_t const main_s = h->stream;
     hipStream_t rec_s = nullptr;
     hipEvent_t sev[5] = {};                       // forward done; recompute done [2]; sweep done [2]
@@ -1537,21 +1543,21 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
     }
 #undef REV_OK
     cleanup();
-    HIP_OK(launch_adj_finish(h, t.lez, t.ler, t.gphi, t.cp, t.dp, t.g_rho, t.params));
-    HIP_OK(hipEventRecord(ev[3], h->stream));
+    ADJ_OK(launch_adj_finish(h, t.lez, t.ler, t.gphi, t.cp, t.dp, t.g_rho, t.params));
+    ADJ_OK(hipEventRecord(ev[3], h->stream));
     // restore the end state the forward left
-    HIP_OK(hipMemcpyAsync(w.ctr, t.final_ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+    ADJ_OK(hipMemcpyAsync(w.ctr, t.final_ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
     h->jbuf = jb_final;
-    HIP_OK(launch_zero_i64(h, w.j[h->jbuf], N));
-    HIP_OK(hipMemcpyAsync(w.j[1 - h->jbuf], t.final_jlast, (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
-    HIP_OK(launch_kick(h));
+    ADJ_OK(launch_zero_i64(h, w.j[h->jbuf], N));
+    ADJ_OK(hipMemcpyAsync(w.j[1 - h->jbuf], t.final_jlast, (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+    ADJ_OK(launch_kick(h));
     // results
     std::vector<double> params((size_t)h->c.n_knots + 2);
     double grate = 0.0;
-    HIP_OK(hipMemcpyAsync(params.data(), t.params, params.size() * 8, hipMemcpyDeviceToHost, h->stream));
-    HIP_OK(hipMemcpyAsync(&grate, t.grate, 8, hipMemcpyDeviceToHost, h->stream));
-    if (out->g_rho) HIP_OK(hipMemcpyAsync(out->g_rho, t.g_rho, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
-    HIP_OK(hipStreamSynchronize(h->stream));
+    ADJ_OK(hipMemcpyAsync(params.data(), t.params, params.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    ADJ_OK(hipMemcpyAsync(&grate, t.grate, 8, hipMemcpyDeviceToHost, h->stream));
+    if (out->g_rho) ADJ_OK(hipMemcpyAsync(out->g_rho, t.g_rho, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
+    ADJ_OK(hipStreamSynchronize(h->stream));
     out->g_rate = grate;
     out->g_kappa = params[0];
     out->g_amp = params[1];
@@ -1563,6 +1569,7 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
     out->forward_ms = fms;
     out->backward_ms = bms;
     return done(PIC_OK);
+#undef ADJ_OK
 }
 
 }  // extern "C"
