@@ -42,6 +42,14 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 B_FP64 = 32                    # x, u (f64) read + written per particle-step
 B_F32_LOW = 24                 # cell, offset, u (f32)
 B_F32_HIGH = 32                # cell, offset (4 B each), u (f64)
+DEFAULT_PUSH = "128:2:nt"      # FP64 push launch shape: threads, slots per thread, nontemporal
+DEFAULT_PUSH32 = "256:4:nt"    # FP32-bulk push launch shape
+
+
+def shape_of(text):
+    """A launch shape "threads:slots[:nt]" as (threads, slots, nontemporal)."""
+    parts = text.split(":")
+    return (int(parts[0]), int(parts[1]), len(parts) > 2 and parts[2] == "nt")
 
 WORKLOADS = {
     "c1": "c1: flat-space SCLF tube, 1024 cells, cold start (~3e3 particles), dt=dz/2",
@@ -141,8 +149,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--push", default="128:2:nt", help="FP64 push shape threads:slots[:nt]")
-    ap.add_argument("--push32", default="256:4:nt", help="FP32-bulk push shape threads:4[:nt]")
+    ap.add_argument("--push", default=DEFAULT_PUSH, help="FP64 push shape threads:slots[:nt]")
+    ap.add_argument("--push32", default=DEFAULT_PUSH32, help="FP32-bulk push shape threads:4[:nt]")
     ap.add_argument("--tune", action="store_true", help="autotune the push shapes instead")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
@@ -168,9 +176,6 @@ def main():
     cfg = synth.preset(args.config)
     log("config", args.config, "cells", cfg["n_cells"], "warm particles", cfg["warm"])
     x, u = synth.warm_start(cfg)
-    def shape_of(text):
-        parts = text.split(":")
-        return (int(parts[0]), int(parts[1]), len(parts) > 2 and parts[2] == "nt")
     push = None if args.tune else shape_of(args.push)
     push32 = None if args.tune else shape_of(args.push32)
 

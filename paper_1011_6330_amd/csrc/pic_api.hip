@@ -252,6 +252,10 @@ static pic_status init_tube(const pic_params *p, void *d_workspace, size_t ws_by
     }
     h->stream = (hipStream_t)hip_stream;
     h->ws = carve(*p, (uint8_t *)d_workspace);
+    // the fastest measured push shapes (nontemporal particle streams)
+    h->push_block = p->precision == PIC_FP32_BULK ? 256 : 128;
+    h->push_ppt = p->precision == PIC_FP32_BULK ? 4 : 2;
+    h->push_nt = 1;
     {
         const double g = p->gamma_fp64 > 0.0 ? p->gamma_fp64 : 1e6;
         h->u_hi = sqrt(g * g - 1.0);   // gamma >= g  <=>  |u| >= sqrt(g^2 - 1)

@@ -128,11 +128,14 @@ def test_fp32_cold_start_c1():
 
 def test_fp32_c2_full_size():
     """The full-size frame-dragging tube (65,536 cells, ~4e7 particles, gamma up
-    to ~6e6: most of the beam in the f64-momentum stream)."""
+    to ~6e6: most of the beam in the f64-momentum stream), in the benchmark's
+    launch configuration."""
+    import bench
     cfg = synth.preset("c2")
     x, u = synth.warm_start(cfg)
-    say("fp32 c2 full size", len(x))
+    say("fp32 c2 full size", len(x), "push shape", bench.DEFAULT_PUSH32)
     g, o = _pair(cfg, x, u)
+    g.set_push_config(*bench.shape_of(bench.DEFAULT_PUSH32))
     del x, u
     g.step(10)
     o.step(10)

@@ -243,10 +243,12 @@ def test_c2_full_size_first_steps():
     """The frame-dragging tube at full size (65,536 cells, ~4e7 particles, gamma up
     to ~6e6), in the benchmark's launch configuration: every result after 3 steps
     bit-identical to the oracle."""
+    import bench
     cfg = synth.preset("c2")
     x, u = synth.warm_start(cfg)
-    say("c2 full size", len(x), "particles")
+    say("c2 full size", len(x), "particles, push shape", bench.DEFAULT_PUSH)
     g, o = make_pair(cfg, x, u)
+    g.set_push_config(*bench.shape_of(bench.DEFAULT_PUSH))
     del x, u
     g.step(3)
     o.step(3)
@@ -293,10 +295,12 @@ def test_save_load_resumes_bit_for_bit(precision):
 def test_c5_full_size_first_steps():
     """The large tube at full size (2^20 cells, L = 100R, 2.5e8 particles): two
     steps bit-identical to the oracle, sorted like the benchmark runs it."""
+    import bench
     cfg = synth.preset("c5")
     say("c5: warm start of", cfg["warm"], "particles")
     x, u = synth.warm_start(cfg)
     g, o = make_pair(cfg, x, u)
+    g.set_push_config(*bench.shape_of(bench.DEFAULT_PUSH))
     del x, u
     say("c5: stepping")
     g.step(2)
