@@ -43,33 +43,23 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
     {
         const int t = b.push_map[it];
         const TubeDev &T = b.tubes[t];
+        // the descriptor is read once, before any store, into registers
+        const Consts c = T.c;
         const int64_t local = it - b.push_pref[t];
-        const bool hi = F32 && local >= T.push_tiles;
-        // in FP32-bulk mode an item covers TILE slots of either stream: one low
-        // tile, or the high stream's tiles of BLOCK*F32_PPT_HI slots in turn
-        const int64_t tile0 = (hi ? local - T.push_tiles : local) * TILE;
         if (F32) {
-            const int64_t n = hi ? T.ctr->n_slots_hi : T.ctr->n_slots;
-            if (tile0 >= n) return;                   // tile past the stream's slots (uniform)
-            Push32Args a{T.cl[b.pb], T.ol[b.pb], T.ul[b.pb], T.ch[b.pb], T.oh[b.pb], T.uh[b.pb], T.k32, T.k64,
-                         (unsigned long long *)T.j[b.jb], T.ctr, 0u,
-                         b.hist ? (unsigned long long *)T.cell_count : nullptr, T.u_hi};
-            if (!hi) {
-                push_tile_lo<BLOCK, NT>(T.c, a, n, tile0);
-            } else {
-#pragma unroll 1
-                for (int r = 0; r < F32_PPT_LO / F32_PPT_HI; ++r) {
-                    const int64_t t0 = tile0 + (int64_t)r * (BLOCK * F32_PPT_HI);
-                    if (t0 >= n) break;
-                    push_tile_hi<BLOCK, NT>(T.c, a, n, t0);
-                }
-            }
+            Push32Args a{generic(T.cl[b.pb]), generic(T.ol[b.pb]), generic(T.ul[b.pb]), generic(T.ch[b.pb]),
+                         generic(T.oh[b.pb]), generic(T.uh[b.pb]), generic(T.k32), generic(T.k64),
+                         (unsigned long long *)generic(T.j[b.jb]), generic(T.ctr),
+                         b.hist ? (unsigned long long *)generic(T.cell_count) : nullptr, T.u_hi};
+            push_item_f32<BLOCK, NT>(c, a, local);
         } else {
+            const int64_t tile0 = local * TILE;
             const int64_t n = T.ctr->n_slots;
             if (tile0 >= n) return;
-            PushArgs a{T.x[b.pb], T.u[b.pb], T.x[b.pb], T.u[b.pb], T.k64, (unsigned long long *)T.j[b.jb], T.ctr,
-                       b.hist ? (unsigned long long *)T.cell_count : nullptr};
-            push_tile_f64<BLOCK, PPT, NT>(T.c, a, n, tile0);
+            PushArgs a{generic(T.x[b.pb]), generic(T.u[b.pb]), generic(T.x[b.pb]), generic(T.u[b.pb]),
+                       generic(T.k64), (unsigned long long *)generic(T.j[b.jb]), generic(T.ctr),
+                       b.hist ? (unsigned long long *)generic(T.cell_count) : nullptr};
+            push_tile_f64<BLOCK, PPT, NT>(c, a, n, tile0);
         }
     }
 }
@@ -83,13 +73,16 @@ __global__ __launch_bounds__(BLOCK) void k_batch_field(BatchArgs b)
     {
         const int t = b.field_map[it];
         const TubeDev &T = b.tubes[t];
+        const Consts c = T.c;
         const int64_t local = it - b.field_pref[t];
-        FieldArgs a{T.ez[fb], T.er[fb], T.b[fb], T.ez[g], T.er[g], T.b[g], T.j[jb], T.j[jb ^ 1],
-                    T.k64, F32 ? T.k32 : nullptr, F32 ? nullptr : T.x[pb], F32 ? nullptr : T.u[pb],
-                    F32 ? T.cl[pb] : nullptr, F32 ? T.ol[pb] : nullptr, F32 ? T.ul[pb] : nullptr, T.ctr,
-                    nullptr, 0, 0, b.hist ? (unsigned long long *)T.cell_count : nullptr,
-                    (F32 && 0.0 >= T.u_hi) ? sort_low_keys(T.c) : 0};
-        field_tile(T.c, a, local, BLOCK);
+        FieldArgs a{generic(T.ez[fb]), generic(T.er[fb]), generic(T.b[fb]), generic(T.ez[g]), generic(T.er[g]),
+                    generic(T.b[g]), generic(T.j[jb]), generic(T.j[jb ^ 1]), generic(T.k64),
+                    F32 ? generic(T.k32) : nullptr, F32 ? nullptr : generic(T.x[pb]),
+                    F32 ? nullptr : generic(T.u[pb]), F32 ? generic(T.cl[pb]) : nullptr,
+                    F32 ? generic(T.ol[pb]) : nullptr, F32 ? generic(T.ul[pb]) : nullptr, generic(T.ctr),
+                    nullptr, 0, 0, b.hist ? (unsigned long long *)generic(T.cell_count) : nullptr,
+                    (F32 && 0.0 >= T.u_hi) ? sort_low_keys(c) : 0};
+        field_tile(c, a, local, BLOCK);
     }
 }
 
@@ -328,30 +321,30 @@ TubeDev tube_dev(pic_handle *t)
     const Workspace &w = t->ws;
     d.c = t->c;
     for (int k = 0; k < 2; ++k) {
-        d.x[k] = w.x[k];
-        d.u[k] = w.u[k];
-        d.cl[k] = w.cl[k];
-        d.ol[k] = w.ol[k];
-        d.ul[k] = w.ul[k];
-        d.ch[k] = w.ch[k];
-        d.oh[k] = w.oh[k];
-        d.uh[k] = w.uh[k];
-        d.ez[k] = w.ez[k];
-        d.er[k] = w.er[k];
-        d.b[k] = w.b[k];
-        d.j[k] = w.j[k];
+        d.x[k] = to_global(w.x[k]);
+        d.u[k] = to_global(w.u[k]);
+        d.cl[k] = to_global(w.cl[k]);
+        d.ol[k] = to_global(w.ol[k]);
+        d.ul[k] = to_global(w.ul[k]);
+        d.ch[k] = to_global(w.ch[k]);
+        d.oh[k] = to_global(w.oh[k]);
+        d.uh[k] = to_global(w.uh[k]);
+        d.ez[k] = to_global(w.ez[k]);
+        d.er[k] = to_global(w.er[k]);
+        d.b[k] = to_global(w.b[k]);
+        d.j[k] = to_global(w.j[k]);
     }
-    d.k64 = w.k64;
-    d.k32 = w.k32;
-    d.ctr = w.ctr;
-    d.cell_count = w.cell_count;
-    d.cell_off = w.cell_off;
-    d.total_lo = w.total_lo;
-    d.blk_sum = w.blk_sum;
-    d.rhs = w.rhs;
-    d.cp = w.cp;
-    d.dp = w.dp;
-    d.phi = w.phi;
+    d.k64 = to_global(w.k64);
+    d.k32 = to_global(w.k32);
+    d.ctr = to_global(w.ctr);
+    d.cell_count = to_global(w.cell_count);
+    d.cell_off = to_global(w.cell_off);
+    d.total_lo = to_global(w.total_lo);
+    d.blk_sum = to_global(w.blk_sum);
+    d.rhs = to_global(w.rhs);
+    d.cp = to_global(w.cp);
+    d.dp = to_global(w.dp);
+    d.phi = to_global(w.phi);
     d.u_hi = t->u_hi;
     d.sort_chunks = (t->c.cap + 255) / 256;
     d.n_keys = sort_key_count(t->c, t->p.precision == PIC_FP32_BULK);

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_thomas(Consts c, const double *rhs, dou
 __global__ __launch_bounds__(256) void k_thomas_batch(const TubeDev *tubes, const int32_t *list)
 {
     const TubeDev &T = tubes[list[blockIdx.x]];
-    thomas_block(T.c, T.rhs, T.cp, T.dp, T.phi);
+    thomas_block(T.c, generic(T.rhs), generic(T.cp), generic(T.dp), generic(T.phi));
 }
 
 // Current of one drift step of the loaded beam, no kick (steady start,

@@ -22,23 +22,7 @@ namespace pcpic {
 template <int BLOCK, int NT>
 __global__ __launch_bounds__(BLOCK) void k_push_f32(Consts c, Push32Args a)
 {
-    const bool hi = blockIdx.x >= a.blocks_lo;
-    const int64_t b = hi ? (int64_t)(blockIdx.x - a.blocks_lo) : (int64_t)blockIdx.x;
-    const int64_t n = hi ? a.ctr->n_slots_hi : a.ctr->n_slots;
-    // a block covers BLOCK*F32_PPT_LO slots of either stream: one low tile, or
-    // the high stream's tiles of BLOCK*F32_PPT_HI slots one after the other
-    const int64_t span0 = b * (BLOCK * F32_PPT_LO);
-    if (span0 >= n) return;                       // whole block idle (uniform)
-    if (!hi) {
-        push_tile_lo<BLOCK, NT>(c, a, n, span0);
-        return;
-    }
-#pragma unroll 1
-    for (int r = 0; r < F32_PPT_LO / F32_PPT_HI; ++r) {
-        const int64_t tile0 = span0 + (int64_t)r * (BLOCK * F32_PPT_HI);
-        if (tile0 >= n) break;
-        push_tile_hi<BLOCK, NT>(c, a, n, tile0);
-    }
+    push_item_f32<BLOCK, NT>(c, a, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -282,13 +266,12 @@ static hipError_t launch_push32_t(pic_handle *h)
 {
     const Workspace &w = h->ws;
     const int b = h->pbuf;
-    const int64_t tlo = (int64_t)BLOCK * F32_PPT_LO;
-    const unsigned nb = (unsigned)((h->c.cap + tlo - 1) / tlo);
-    const unsigned nbh = nb;                      // a high block walks the same span in two tiles
+    const int64_t span = (int64_t)BLOCK * F32_PPT_LO;
+    const unsigned items = (unsigned)((h->c.cap + span - 1) / span + 1);   // both streams, any split
     Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b], w.k32, w.k64,
-                 (unsigned long long *)w.j[h->jbuf], w.ctr, nb,
+                 (unsigned long long *)w.j[h->jbuf], w.ctr,
                  h->hist_on ? (unsigned long long *)w.cell_count : nullptr, h->u_hi};
-    hipLaunchKernelGGL((k_push_f32<BLOCK, NT>), dim3(nb + nbh), dim3(BLOCK), 0, h->stream, h->c, a);
+    hipLaunchKernelGGL((k_push_f32<BLOCK, NT>), dim3(items), dim3(BLOCK), 0, h->stream, h->c, a);
     return hipGetLastError();
 }
 

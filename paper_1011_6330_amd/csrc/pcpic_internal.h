@@ -135,26 +135,43 @@ struct Workspace {
     size_t bytes;
 };
 
+// Pointers kept in a device-side descriptor carry the global address space:
+// a kernel that reads them from memory then issues global memory instructions,
+// as it does for pointers passed as kernel arguments, instead of flat ones
+// (which also wait on the LDS counter and cannot use a scalar base).
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__host__ __device__ __forceinline__ gptr<T> to_global(T *p)
+{
+    return (gptr<T>)p;
+}
+template <class T>
+__host__ __device__ __forceinline__ T *generic(gptr<T> p)
+{
+    return (T *)p;
+}
+
 // Device descriptor of one tube of a batch: constants and the base pointers of
 // both parities of every ping-pong array.
 struct TubeDev {
     Consts c;
-    double *x[2], *u[2];
-    int *cl[2];
-    float *ol[2], *ul[2];
-    int *ch[2];
-    float *oh[2];
-    double *uh[2];
-    double *ez[2], *er[2], *b[2];
-    int64_t *j[2];
-    double *k64;
-    float *k32;
-    DevCounters *ctr;
-    long long *cell_count, *cell_off, *total_lo, *blk_sum;
-    double *rhs, *cp, *dp, *phi;   // Poisson solve of eq. (4)
+    gptr<double> x[2], u[2];
+    gptr<int> cl[2];
+    gptr<float> ol[2], ul[2];
+    gptr<int> ch[2];
+    gptr<float> oh[2];
+    gptr<double> uh[2];
+    gptr<double> ez[2], er[2], b[2];
+    gptr<int64_t> j[2];
+    gptr<double> k64;
+    gptr<float> k32;
+    gptr<DevCounters> ctr;
+    gptr<long long> cell_count, cell_off, total_lo, blk_sum;
+    gptr<double> rhs, cp, dp, phi;   // Poisson solve of eq. (4)
     double u_hi;
-    int64_t push_tiles;      // push tiles at capacity (FP32-bulk: of the low stream)
-    int64_t push_tiles_hi;   // FP32-bulk: push items of the high stream (each walks BLOCK*F32_PPT_LO slots)
+    int64_t push_tiles;      // push tiles (FP32-bulk: spans of BLOCK*F32_PPT_LO slots) at capacity
+    int64_t push_tiles_hi;   // FP32-bulk: 1 more item, as the two streams may each end in a partial span
     int64_t sort_chunks;  // 256-slot chunks per particle stream at capacity
     int64_t n_keys;       // sort keys (N, or 2(N+1) in FP32-bulk mode)
 };

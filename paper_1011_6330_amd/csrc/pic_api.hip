@@ -1008,8 +1008,8 @@ static BatchMapSizes batch_map_sizes(const pic_params *tubes, int n)
         const pic_params &p = tubes[t];
         const bool f32 = p.precision == PIC_FP32_BULK;
         // the smallest tiles of any launch shape: 64 threads x 2 slots (FP64),
-        // 64 x 4 slots per stream (FP32-bulk)
-        m.push += f32 ? 2 * ((p.capacity + 255) / 256) : (p.capacity + 127) / 128;
+        // spans of 64 x 4 slots over both streams plus one (FP32-bulk)
+        m.push += f32 ? (p.capacity + 255) / 256 + 1 : (p.capacity + 127) / 128;
         m.field += (p.n_cells + 63) / 64;
         m.chunk += (f32 ? 2 : 1) * ((p.capacity + 255) / 256);
         const int64_t keys = (f32 ? 2 * (p.n_cells + 1) : p.n_cells) << sort_sub_log2(p);
@@ -1075,7 +1075,7 @@ static pic_status batch_configure(pic_handle *h, int block, int per_thread)
         pic_handle *s = h->tubes[(size_t)t];
         td[(size_t)t] = tube_dev(s);
         td[(size_t)t].push_tiles = (s->c.cap + tile - 1) / tile;
-        td[(size_t)t].push_tiles_hi = f32 ? td[(size_t)t].push_tiles : 0;
+        td[(size_t)t].push_tiles_hi = f32 ? 1 : 0;
         pp[(size_t)t + 1] = pp[(size_t)t] + td[(size_t)t].push_tiles + td[(size_t)t].push_tiles_hi;
         fp[(size_t)t + 1] = fp[(size_t)t] + (s->c.N + block - 1) / block;
         sp[(size_t)t + 1] = sp[(size_t)t] + (f32 ? 2 : 1) * td[(size_t)t].sort_chunks;

@@ -163,7 +163,6 @@ struct Push32Args {
     const double *__restrict__ K64;
     unsigned long long *__restrict__ J;
     DevCounters *ctr;
-    unsigned blocks_lo;     // grid blocks [0, blocks_lo) serve the low stream
     unsigned long long *hist = nullptr;   // non-null on the step before a sort: key counts of the survivors
     double u_hi = 0.0;                    // |u| from which a particle belongs to the high stream
 };
@@ -394,6 +393,30 @@ __device__ __forceinline__ void push_tile_hi(const Consts &c, const Push32Args &
             key[k] = live[k] ? sort_key_f32(c, cs[k], os[k], fabs(us[k]) >= a.u_hi) : 0;
         }
         hist_add<PPT>(a.hist, key, live);
+    }
+}
+
+// Item k of a tube's FP32-bulk push, an item being a span of BLOCK*F32_PPT_LO
+// slots: the low stream's spans come first, then the high stream's, which a
+// block walks as tiles of BLOCK*F32_PPT_HI slots one after the other.  Items
+// past both streams return at once, so launching ceil(capacity / span) + 1
+// items covers any split of the slots and leaves the idle ones at the end.
+template <int BLOCK, int NT>
+__device__ __forceinline__ void push_item_f32(const Consts &c, const Push32Args &a, int64_t k)
+{
+    constexpr int64_t SPAN = (int64_t)BLOCK * F32_PPT_LO;
+    const int64_t n_lo = a.ctr->n_slots, n_hi = a.ctr->n_slots_hi;
+    const int64_t items_lo = (n_lo + SPAN - 1) / SPAN;
+    if (k < items_lo) {
+        push_tile_lo<BLOCK, NT>(c, a, n_lo, k * SPAN);
+        return;
+    }
+    const int64_t span0 = (k - items_lo) * SPAN;
+#pragma unroll 1
+    for (int r = 0; r < F32_PPT_LO / F32_PPT_HI; ++r) {
+        const int64_t tile0 = span0 + (int64_t)r * (BLOCK * F32_PPT_HI);
+        if (tile0 >= n_hi) break;
+        push_tile_hi<BLOCK, NT>(c, a, n_hi, tile0);
     }
 }
 
