@@ -17,6 +17,7 @@
 #include "field_body.h"
 #include "pcpic_internal.h"
 #include "push_body.h"
+#include "sort_body.h"
 #include "wave.h"
 
 namespace pcpic {
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_field(BatchArgs b)
 struct BSortArgs {
     const TubeDev *tubes;
     int n_tubes;
-    const int64_t *chunk_pref;   // [n_tubes + 1] prefix of 256-slot chunks (both streams)
+    const int64_t *chunk_pref;   // [n_tubes + 1] prefix of sort items (tiles of SORT_TILE slots, sort_item)
     const int64_t *key_pref;     // [n_tubes + 1] prefix of sort keys
     const int64_t *scan_pref;    // [n_tubes + 1] prefix of scan blocks
     const int32_t *chunk_map;    // sort chunk -> tube
@@ -115,46 +116,25 @@ __global__ __launch_bounds__(256) void k_bsort_clear(BSortArgs a)
     }
 }
 
-// Slot p of the chunk item, its stream and the stream's slot count.
-__device__ __forceinline__ bool chunk_slot(const TubeDev &T, int f32, int64_t local, int64_t &p, int64_t &n)
+// A tube's particle streams of buffer parity b.
+__device__ __forceinline__ Streams tube_streams(const TubeDev &T, int b)
 {
-    const bool hi = f32 && local >= T.sort_chunks;
-    p = (hi ? local - T.sort_chunks : local) * 256 + threadIdx.x;
-    n = hi ? T.ctr->n_slots_hi : T.ctr->n_slots;
-    return hi;
+    return Streams{generic(T.cl[b]), generic(T.ol[b]), generic(T.ul[b]), generic(T.ch[b]), generic(T.oh[b]),
+                   generic(T.uh[b])};
 }
 
-// One block per chunk of 256 slots of one stream of one tube.
-__global__ __launch_bounds__(256) void k_bsort_hist(BSortArgs a)
+// One block per sort item (a tile of SORT_TILE slots of one stream) of a tube.
+__global__ __launch_bounds__(SORT_BLOCK) void k_bsort_hist(BSortArgs a)
 {
     const int64_t it = blockIdx.x;
-    {
-        const int t = a.chunk_map[it];
-        const TubeDev &T = a.tubes[t];
-        int64_t p, n;
-        const bool hi = chunk_slot(T, a.f32, it - a.chunk_pref[t], p, n);
-        bool live = false;
-        int64_t key = 0;
-        if (p < n) {
-            if (a.f32) {
-                const int cell = hi ? T.ch[a.src][p] : T.cl[a.src][p];
-                if (cell >= 0) {
-                    const double u = hi ? T.uh[a.src][p] : (double)T.ul[a.src][p];
-                    live = true;
-                    key = sort_key_f32(T.c, cell, hi ? T.oh[a.src][p] : T.ol[a.src][p], fabs(u) >= T.u_hi);
-                }
-            } else {
-                const double x = T.x[a.src][p];
-                if (x >= 0.0) {
-                    live = true;
-                    key = sort_key_f64(T.c, x);
-                }
-            }
-        }
-        const WaveRun r = wave_runs(key, live);
-        if (live && r.is_head)
-            atomicAdd((unsigned long long *)T.cell_count + key, (unsigned long long)(r.end - (int)__lane_id()));
-    }
+    const int t = a.chunk_map[it];
+    const TubeDev &T = a.tubes[t];
+    const Consts c = T.c;
+    bool hi;
+    int64_t tile0, n;
+    if (!sort_item(it - a.chunk_pref[t], a.f32 != 0, generic(T.ctr), hi, tile0, n)) return;
+    hist_tile(c, a.f32 != 0, hi, generic(T.x[a.src]), tube_streams(T, a.src), T.u_hi,
+              (unsigned long long *)generic(T.cell_count), n, tile0);
 }
 
 // Exclusive scan of every tube's key counts in three phases over blocks of
@@ -238,61 +218,25 @@ __global__ __launch_bounds__(256) void k_bscan_apply(BSortArgs a)
     }
 }
 
-__global__ __launch_bounds__(256) void k_bsort_scatter(BSortArgs a)
+__global__ __launch_bounds__(SORT_BLOCK) void k_bsort_scatter(BSortArgs a)
 {
-    const int lane = __lane_id();
     const int64_t it = blockIdx.x;
-    {
-        const int t = a.chunk_map[it];
-        const TubeDev &T = a.tubes[t];
-        int64_t p, n;
-        const bool hi = chunk_slot(T, a.f32, it - a.chunk_pref[t], p, n);
-        bool want = false;
-        int64_t key = 0;
-        int cell = 0;
-        float o = 0.0f;
-        double x = 0.0, u = 0.0;
-        if (p < n) {
-            if (a.f32) {
-                cell = hi ? T.ch[a.src][p] : T.cl[a.src][p];
-                if (cell >= 0) {
-                    o = hi ? T.oh[a.src][p] : T.ol[a.src][p];
-                    u = hi ? T.uh[a.src][p] : (double)T.ul[a.src][p];
-                    want = true;
-                    key = sort_key_f32(T.c, cell, o, fabs(u) >= T.u_hi);
-                }
-            } else {
-                x = T.x[a.src][p];
-                if (x >= 0.0) {
-                    u = T.u[a.src][p];
-                    want = true;
-                    key = sort_key_f64(T.c, x);
-                }
-            }
-        }
-        const long long tlo = a.f32 ? *T.total_lo : 0;
-        const WaveRun r = wave_runs(key, want);
-        unsigned long long f0 = 0;
-        if (want && r.is_head) f0 = atomicAdd((unsigned long long *)T.cell_off + key, (unsigned long long)(r.end - lane));
-        f0 = __shfl(f0, r.head);
-        if (want) {
-            const int64_t d = (int64_t)f0 + r.rank;
-            if (a.f32) {
-                if (key >= sort_low_keys(T.c)) {
-                    const int64_t q = d - tlo;
-                    T.ch[a.dst][q] = cell;
-                    T.oh[a.dst][q] = o;
-                    T.uh[a.dst][q] = u;
-                } else {
-                    T.cl[a.dst][d] = cell;
-                    T.ol[a.dst][d] = o;
-                    T.ul[a.dst][d] = (float)u;
-                }
-            } else {
-                T.x[a.dst][d] = x;
-                T.u[a.dst][d] = u;
-            }
-        }
+    const int t = a.chunk_map[it];
+    const TubeDev &T = a.tubes[t];
+    const Consts c = T.c;
+    bool hi;
+    int64_t tile0, n;
+    if (!sort_item(it - a.chunk_pref[t], a.f32 != 0, generic(T.ctr), hi, tile0, n)) return;
+    unsigned long long *off = (unsigned long long *)generic(T.cell_off);
+    if (a.f32) {
+        const int64_t tlo = *T.total_lo;
+        if (hi)
+            scatter_tile_f32<true>(c, tube_streams(T, a.src), tube_streams(T, a.dst), T.u_hi, tlo, off, n, tile0);
+        else
+            scatter_tile_f32<false>(c, tube_streams(T, a.src), tube_streams(T, a.dst), T.u_hi, tlo, off, n, tile0);
+    } else {
+        scatter_tile_f64(c, generic(T.x[a.src]), generic(T.u[a.src]), generic(T.x[a.dst]), generic(T.u[a.dst]), off,
+                         n, tile0);
     }
 }
 
@@ -346,7 +290,7 @@ TubeDev tube_dev(pic_handle *t)
     d.dp = to_global(w.dp);
     d.phi = to_global(w.phi);
     d.u_hi = t->u_hi;
-    d.sort_chunks = (t->c.cap + 255) / 256;
+    d.sort_chunks = (t->c.cap + SORT_TILE - 1) / SORT_TILE;
     d.n_keys = sort_key_count(t->c, t->p.precision == PIC_FP32_BULK);
     return d;
 }
@@ -444,15 +388,15 @@ hipError_t launch_batch_sort(pic_handle *h, bool hist_ready)
     if (h->batch_scan_blocks <= 0 || h->batch_scan_blocks > 0x7fffffff) return hipErrorInvalidValue;
     const unsigned sb = (unsigned)h->batch_scan_blocks;
     if (h->batch_sort_items <= 0 || h->batch_sort_items > 0x7fffffff) return hipErrorInvalidValue;
-    const unsigned g = (unsigned)h->batch_sort_items;   // one block per chunk of 256 slots
+    const unsigned g = (unsigned)h->batch_sort_items;   // one block per sort item
     if (!hist_ready) {
         hipLaunchKernelGGL(k_bsort_clear, dim3(sb), dim3(256), 0, h->stream, a);
-        hipLaunchKernelGGL(k_bsort_hist, dim3(g), dim3(256), 0, h->stream, a);
+        hipLaunchKernelGGL(k_bsort_hist, dim3(g), dim3(SORT_BLOCK), 0, h->stream, a);
     }
     hipLaunchKernelGGL(k_bscan_totals, dim3(sb), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bscan_blocks, dim3(nt), dim3(256), 0, h->stream, a);
     hipLaunchKernelGGL(k_bscan_apply, dim3(sb), dim3(256), 0, h->stream, a);
-    hipLaunchKernelGGL(k_bsort_scatter, dim3(g), dim3(256), 0, h->stream, a);
+    hipLaunchKernelGGL(k_bsort_scatter, dim3(g), dim3(SORT_BLOCK), 0, h->stream, a);
     hipLaunchKernelGGL(k_bsort_finish, dim3((nt + 63) / 64), dim3(64), 0, h->stream, a);
     return hipGetLastError();
 }

@@ -16,6 +16,7 @@
 #include "pcpic_internal.h"
 #include "push_common.h"
 #include "push_body.h"
+#include "sort_body.h"
 
 namespace pcpic {
 
@@ -28,15 +29,6 @@ __global__ __launch_bounds__(BLOCK) void k_push_f32(Consts c, Push32Args a)
 // ------------------------------------------------------------------------
 // diagnostics, sort and append for the two streams
 // ------------------------------------------------------------------------
-
-struct Streams {
-    int *CL;
-    float *OL;
-    float *UL;
-    int *CH;
-    float *OH;
-    double *UH;
-};
 
 // Blocks [0, nb_lo) walk the low stream, the rest the high stream, grid-stride.
 __device__ __forceinline__ bool stream_slot(const DevCounters *ctr, unsigned nb_lo, int64_t &first,
@@ -120,71 +112,31 @@ __global__ __launch_bounds__(256) void k_profile32(Consts c, int nb, Streams s, 
     }
 }
 
-// Destination stream of a particle: the high stream from |u| >= u_hi on.
-__device__ __forceinline__ bool goes_high(double u, double u_hi) { return fabs(u) >= u_hi; }
-
-// Histogram for the sort (sort_key_f32: the destination stream's key range).
-__global__ __launch_bounds__(256) void k_hist32(Consts c, Streams s, const DevCounters *ctr, unsigned nb_lo,
-                                                double u_hi, unsigned long long *count)
+// Histogram for the sort (sort_key_f32: the destination stream's key range),
+// one block per tile of either stream (sort_item).
+__global__ __launch_bounds__(SORT_BLOCK) void k_hist32(Consts c, Streams s, const DevCounters *ctr, double u_hi,
+                                                       unsigned long long *count)
 {
-    int64_t first, stride, n;
-    const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
-    const int *C = hi ? s.CH : s.CL;
-    const float *O = hi ? s.OH : s.OL;
-    for (int64_t base = first; base < n; base += stride) {
-        const int64_t p = base + threadIdx.x;
-        const int cell = p < n ? C[p] : -1;
-        const bool live = cell >= 0;
-        int64_t key = 0;
-        if (live) {
-            const double u = hi ? s.UH[p] : (double)s.UL[p];
-            key = sort_key_f32(c, cell, O[p], goes_high(u, u_hi));
-        }
-        const WaveRun r = wave_runs(key, live);
-        if (live && r.is_head) atomicAdd(count + key, (unsigned long long)(r.end - (int)__lane_id()));
-    }
+    bool hi;
+    int64_t tile0, n;
+    if (!sort_item(blockIdx.x, true, ctr, hi, tile0, n)) return;
+    hist_tile(c, true, hi, nullptr, s, u_hi, count, n, tile0);
 }
 
-__global__ __launch_bounds__(256) void k_scatter32(Consts c, Streams src, Streams dst, const DevCounters *ctr,
-                                                   unsigned nb_lo, double u_hi, unsigned long long *off,
-                                                   const long long *total_lo)
+// Scatter into the other buffer, one block per tile of either stream; tlo is
+// the destination low stream's slot count (the offset of the first high key).
+__global__ __launch_bounds__(SORT_BLOCK) void k_scatter32(Consts c, Streams src, Streams dst, const DevCounters *ctr,
+                                                          double u_hi, unsigned long long *off,
+                                                          const long long *total_lo)
 {
-    int64_t first, stride, n;
-    const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
-    const int *C = hi ? src.CH : src.CL;
-    const float *O = hi ? src.OH : src.OL;
-    const long long tlo = *total_lo;
-    const int lane = __lane_id();
-    for (int64_t base = first; base < n; base += stride) {
-        const int64_t p = base + threadIdx.x;
-        const int cell = p < n ? C[p] : -1;
-        const bool want = cell >= 0;
-        float o = 0.0f;
-        double u = 0.0;
-        int64_t key = 0;
-        if (want) {
-            o = O[p];
-            u = hi ? src.UH[p] : (double)src.UL[p];
-            key = sort_key_f32(c, cell, o, goes_high(u, u_hi));
-        }
-        const WaveRun r = wave_runs(key, want);
-        unsigned long long f0 = 0;
-        if (want && r.is_head) f0 = atomicAdd(off + key, (unsigned long long)(r.end - lane));
-        f0 = __shfl(f0, r.head);
-        if (want) {
-            const int64_t d = (int64_t)f0 + r.rank;
-            if (key >= sort_low_keys(c)) {
-                const int64_t q = d - tlo;
-                dst.CH[q] = cell;
-                dst.OH[q] = o;
-                dst.UH[q] = u;
-            } else {
-                dst.CL[d] = cell;
-                dst.OL[d] = o;
-                dst.UL[d] = (float)u;
-            }
-        }
-    }
+    bool hi;
+    int64_t tile0, n;
+    if (!sort_item(blockIdx.x, true, ctr, hi, tile0, n)) return;
+    const int64_t tlo = *total_lo;
+    if (hi)
+        scatter_tile_f32<true>(c, src, dst, u_hi, tlo, off, n, tile0);
+    else
+        scatter_tile_f32<false>(c, src, dst, u_hi, tlo, off, n, tile0);
 }
 
 // Low-destination total = exclusive offset of the first high key; copied before
@@ -309,22 +261,23 @@ hipError_t launch_profile32(pic_handle *h, int nbins)
     return hipGetLastError();
 }
 
+// Blocks of a pass over both streams in tiles of SORT_TILE slots (sort_item).
+static unsigned sort_items32(pic_handle *h) { return (unsigned)((h->c.cap + SORT_TILE - 1) / SORT_TILE + 1); }
+
 hipError_t launch_sort32_hist(pic_handle *h)
 {
-    const unsigned nb = (unsigned)(h->n_cu * 4);
-    hipLaunchKernelGGL(k_hist32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, streams_of(h, h->pbuf), h->ws.ctr, nb,
-                       h->u_hi, (unsigned long long *)h->ws.cell_count);
+    hipLaunchKernelGGL(k_hist32, dim3(sort_items32(h)), dim3(SORT_BLOCK), 0, h->stream, h->c, streams_of(h, h->pbuf),
+                       h->ws.ctr, h->u_hi, (unsigned long long *)h->ws.cell_count);
     return hipGetLastError();
 }
 
 hipError_t launch_sort32_scatter(pic_handle *h)
 {
-    const unsigned nb = (unsigned)(h->n_cu * 4);
     const int src = h->pbuf, dst = 1 - h->pbuf;
     hipLaunchKernelGGL(k_copy_total, dim3(1), dim3(64), 0, h->stream, (const long long *)(h->ws.cell_off + sort_low_keys(h->c)),
                        h->ws.total_lo);
-    hipLaunchKernelGGL(k_scatter32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, streams_of(h, src),
-                       streams_of(h, dst), h->ws.ctr, nb, h->u_hi, (unsigned long long *)h->ws.cell_off,
+    hipLaunchKernelGGL(k_scatter32, dim3(sort_items32(h)), dim3(SORT_BLOCK), 0, h->stream, h->c, streams_of(h, src),
+                       streams_of(h, dst), h->ws.ctr, h->u_hi, (unsigned long long *)h->ws.cell_off,
                        (const long long *)h->ws.total_lo);
     hipLaunchKernelGGL(k_sort32_finish, dim3(1), dim3(64), 0, h->stream, h->ws.ctr,
                        (const long long *)(h->ws.total_lo));

@@ -8,6 +8,7 @@
 #include <math.h>
 
 #include "pcpic_internal.h"
+#include "sort_body.h"
 #include "wave.h"
 
 namespace pcpic {
@@ -109,28 +110,16 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const long long *coun
     }
 }
 
-__global__ __launch_bounds__(256) void k_scatter(Consts c, const double *__restrict__ X, const double *__restrict__ U,
-                                                 double *__restrict__ Xo, double *__restrict__ Uo,
-                                                 const DevCounters *ctr, unsigned long long *off)
+// Scatter into the other buffer, one block per tile of SORT_TILE slots.
+__global__ __launch_bounds__(SORT_BLOCK) void k_scatter(Consts c, const double *__restrict__ X,
+                                                        const double *__restrict__ U, double *__restrict__ Xo,
+                                                        double *__restrict__ Uo, const DevCounters *ctr,
+                                                        unsigned long long *off)
 {
     const int64_t n = ctr->n_slots;
-    const int lane = __lane_id();
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
-        const int64_t p = base + threadIdx.x;
-        const double x = p < n ? X[p] : -1.0;
-        const double u = p < n ? U[p] : 0.0;
-        const bool want = x >= 0.0;
-        const int64_t key = want ? sort_key_f64(c, x) : 0;
-        const WaveRun r = wave_runs(key, want);
-        unsigned long long first = 0;
-        if (want && r.is_head) first = atomicAdd(off + key, (unsigned long long)(r.end - lane));
-        first = __shfl(first, r.head);
-        if (want) {
-            const int64_t dst = (int64_t)first + r.rank;
-            Xo[dst] = x;
-            Uo[dst] = u;
-        }
-    }
+    const int64_t tile0 = (int64_t)blockIdx.x * SORT_TILE;
+    if (tile0 >= n) return;
+    scatter_tile_f64(c, X, U, Xo, Uo, off, n, tile0);
 }
 
 __global__ void k_sort_finish(DevCounters *ctr)
@@ -180,7 +169,8 @@ hipError_t launch_sort(pic_handle *h, bool hist_ready)
         if (!hist_ready)
             hipLaunchKernelGGL(k_hist, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.ctr, w.cell_count);
         if ((e = launch_scan(h, nkeys)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_scatter, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, w.x[src], w.u[src], w.x[dst],
+        const unsigned tiles = (unsigned)((c.cap + SORT_TILE - 1) / SORT_TILE);
+        hipLaunchKernelGGL(k_scatter, dim3(tiles), dim3(SORT_BLOCK), 0, h->stream, c, w.x[src], w.u[src], w.x[dst],
                            w.u[dst], w.ctr, (unsigned long long *)w.cell_off);
         hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, h->stream, w.ctr);
     }

@@ -70,6 +70,9 @@ __host__ __device__ inline int64_t sort_key_count(const Consts &c, bool f32)
 }
 __host__ __device__ inline int64_t sort_low_keys(const Consts &c) { return (c.N + 1) << c.sub; }
 constexpr int SORT_SCAN_TILE = 1024;   // keys per block of the three-phase scan
+constexpr int SORT_BLOCK = 256;        // threads per block of the scatter and histogram passes
+constexpr int SORT_PPT = 4;            // consecutive slots per thread in those passes
+constexpr int SORT_TILE = SORT_BLOCK * SORT_PPT;
 __device__ inline int64_t sort_key_f64(const Consts &c, double x)
 {
     return (int64_t)floor(x * (double)(1 << c.sub));   // exact scaling by a power of two
@@ -172,7 +175,7 @@ struct TubeDev {
     double u_hi;
     int64_t push_tiles;      // push tiles (FP32-bulk: spans of BLOCK*F32_PPT_LO slots) at capacity
     int64_t push_tiles_hi;   // FP32-bulk: 1 more item, as the two streams may each end in a partial span
-    int64_t sort_chunks;  // 256-slot chunks per particle stream at capacity
+    int64_t sort_chunks;  // sort tiles (SORT_TILE slots) per particle stream at capacity
     int64_t n_keys;       // sort keys (N, or 2(N+1) in FP32-bulk mode)
 };
 

@@ -1011,7 +1011,7 @@ static BatchMapSizes batch_map_sizes(const pic_params *tubes, int n)
         // spans of 64 x 4 slots over both streams plus one (FP32-bulk)
         m.push += f32 ? (p.capacity + 255) / 256 + 1 : (p.capacity + 127) / 128;
         m.field += (p.n_cells + 63) / 64;
-        m.chunk += (f32 ? 2 : 1) * ((p.capacity + 255) / 256);
+        m.chunk += (p.capacity + SORT_TILE - 1) / SORT_TILE + (f32 ? 1 : 0);
         const int64_t keys = (f32 ? 2 * (p.n_cells + 1) : p.n_cells) << sort_sub_log2(p);
         m.scan += (keys + SORT_SCAN_TILE - 1) / SORT_SCAN_TILE;
     }
@@ -1078,7 +1078,7 @@ static pic_status batch_configure(pic_handle *h, int block, int per_thread)
         td[(size_t)t].push_tiles_hi = f32 ? 1 : 0;
         pp[(size_t)t + 1] = pp[(size_t)t] + td[(size_t)t].push_tiles + td[(size_t)t].push_tiles_hi;
         fp[(size_t)t + 1] = fp[(size_t)t] + (s->c.N + block - 1) / block;
-        sp[(size_t)t + 1] = sp[(size_t)t] + (f32 ? 2 : 1) * td[(size_t)t].sort_chunks;
+        sp[(size_t)t + 1] = sp[(size_t)t] + td[(size_t)t].sort_chunks + (f32 ? 1 : 0);   // sort_item
         kp[(size_t)t + 1] = kp[(size_t)t] + td[(size_t)t].n_keys;
         cp[(size_t)t + 1] = cp[(size_t)t] + (td[(size_t)t].n_keys + SORT_SCAN_TILE - 1) / SORT_SCAN_TILE;
     }
