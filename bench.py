@@ -26,7 +26,12 @@ sort on the tube's stream.  Prints one JSON line:
                  fp64: the same tubes in FP64)
   plausibility   flat-space SCLF over a = omega_p R / c (sec. 3, Table 2): gamma
                  behind the front and the oscillation amplitude per a
+  full_step      the whole step's rate against the push's 32 B per particle-step
+  diagnostics    one pic_diagnostics call (fields, Gauss residual, profile)
+  small_tubes    C1 (and C4) as time per step: cache-resident, latency-bound
   cpu_baseline   the single-threaded FP64 oracle on the same tube
+The roofline also carries the rate of torch's device copy and of the library's
+plain 16-byte nontemporal copy (the achievable stream rate, pic_stream_copy).
 """
 import argparse
 import json
@@ -64,7 +69,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def run_tube(cfg, x, u, precision, steps, warmup, push=None, tune=True, diag=None):
+def run_tube(cfg, x, u, precision, steps, warmup, push=None, tune=True, diag=None, time_diag=False):
     """Warm a tube up (tuning its push shape), then time `steps` steps."""
     import torch
 
@@ -94,6 +99,14 @@ def run_tube(cfg, x, u, precision, steps, warmup, push=None, tune=True, diag=Non
     # field update and sort, on the tube's own stream
     tim = tube.step_timed(steps)
     d2 = tube.diagnostics(fields=False, **(diag or {}))
+    if time_diag:
+        # a full diagnostics call (fields, Gauss residual, 64-bin profile, host
+        # copies included), averaged over 5 calls after an untimed one
+        tube.diagnostics(n_bins=64, gauss=True, fields=True)
+        t2 = time.perf_counter()
+        for _ in range(5):
+            tube.diagnostics(n_bins=64, gauss=True, fields=True)
+        tim["diag_ms"] = (time.perf_counter() - t2) / 5 * 1e3
     tim["alive"] = 0.5 * (d1["n_alive"] + d2["n_alive"])
     tim["gauss_max"], tim["gauss_l2"] = d2["gauss_max"], d2["gauss_l2"]
     tim["alive_high"] = 0.5 * (d1["n_slots_high"] + d2["n_slots_high"])
@@ -180,7 +193,7 @@ def main():
     push32 = None if args.tune else shape_of(args.push32)
 
     # ---- plain FP64 step: the headline value ----
-    d0, d1, tim, elapsed, shape = run_tube(cfg, x, u, 0, args.steps, args.warmup, push=push)
+    d0, d1, tim, elapsed, shape = run_tube(cfg, x, u, 0, args.steps, args.warmup, push=push, time_diag=True)
     alive = 0.5 * (d0["n_alive"] + d1["n_alive"])
     value = alive * args.steps / elapsed
     roof = roofline_of(B_FP64 * tim["alive"], tim, "k_push_f64")
@@ -205,7 +218,16 @@ def main():
         "roofline": roof,
         "breakdown_ms_per_step": {"push": tim["push_ms"] / args.steps, "field": tim["field_ms"] / args.steps,
                                   "sort": tim["sort_ms"] / args.steps},
+        # the whole step (push, field update, injection, sort) against the push's 32 B per particle-step
+        "full_step": {"achieved": B_FP64 * value / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": B_FP64 * value / 1e9 / HBM_PEAK_GBS},
+        "device": device_info(torch),
     }
+    # diagnostics (fields, Gauss residual, profile) are taken every K steps, not every step
+    result["diagnostics"] = {"ms_per_call": tim["diag_ms"], "ms_per_step_at_k100": tim["diag_ms"] / 100,
+                             "what": "pic_diagnostics on the same tube with E_z, E_r, B_phi, the Gauss residual "
+                                     "and a 64-bin signed-gamma profile, host copies included"}
+    log(f"diagnostics: {tim['diag_ms']:.2f} ms per call")
 
     # ---- FP32-bulk push on the same tube ----
     if not args.no_fp32:
@@ -260,7 +282,18 @@ def main():
 
     copy_gbs = copy_bandwidth(torch)
     result["roofline"]["torch_copy_gbs"] = copy_gbs
-    log(f"copy kernel {copy_gbs:.0f} GB/s")
+    ach = stream_copy_bandwidth(torch)
+    result["roofline"]["achievable_copy_gbs"] = ach
+    result["roofline"]["frac_of_achievable"] = result["roofline"]["achieved"] / ach
+    log(f"copy: torch {copy_gbs:.0f} GB/s, 16-byte nontemporal stream {ach:.0f} GB/s")
+
+    if args.config == "c2":
+        result["small_tubes"] = run_small()
+        if "adjoint" in result:
+            result["small_tubes"]["c4"] = {
+                "us_per_step": result["adjoint"]["plain_forward_ms"] * 1e3 / result["adjoint"]["steps"],
+                "steps": result["adjoint"]["steps"],
+                "workload": "c4 plain forward of the adjoint leg (4096 cells, ~1e6 particles, 16 MB of state)"}
 
     if not args.no_sweep:
         from paper_1011_6330_amd import sweep
@@ -411,6 +444,67 @@ def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
     del src, dst
     torch.cuda.empty_cache()
     return 2.0 * nbytes / s / 1e9
+
+
+def stream_copy_bandwidth(torch, nbytes=2 << 30, reps=20):
+    """HBM bandwidth (bytes read + written per second) of the library's plain
+    16-byte nontemporal copy kernel: the achievable rate of a simple stream."""
+    import ctypes
+
+    from paper_1011_6330_amd import _binding
+    lib = _binding.load()
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def once():
+        rc = lib.pic_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes, stream)
+        if rc != 0:
+            raise RuntimeError("pic_stream_copy: " + lib.pic_last_error().decode())
+
+    for _ in range(3):
+        once()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    if not torch.equal(src[:4096], dst[:4096]) or not torch.equal(src[-4096:], dst[-4096:]):
+        raise RuntimeError("pic_stream_copy did not copy")
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / s / 1e9
+
+
+def device_info(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "memory_gib": p.total_memory / 2 ** 30}
+
+
+def run_small(steps=2000):
+    """C1: the 1024-cell flat-space SCLF tube from empty, 2000 steps.  Its state
+    is a few hundred kB and stays in cache, so it is reported as time per step
+    (launch latency of two kernels a step), not against the HBM roofline."""
+    import torch
+
+    from paper_1011_6330_amd import Tube, synth
+    cfg = synth.preset("c1")
+    tube = Tube(synth.tube_params(cfg), device="cuda:0")
+    tube.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tube.step(steps)
+    tube.sync()
+    el = time.perf_counter() - t0
+    n = tube.diagnostics(fields=False)["n_alive"]
+    tube.close()
+    log(f"c1: {el / steps * 1e6:.1f} us/step over {steps} steps from empty, {n} particles at the end")
+    return {"c1": {"us_per_step": el / steps * 1e6, "steps": steps, "particles_end": int(n),
+                   "workload": WORKLOADS["c1"]}}
 
 
 def cpu_baseline(cfg, x, u, seconds):

@@ -353,6 +353,15 @@ pic_status pic_save(pic_handle *h, void *buf, size_t cap, size_t *bytes);
  * PIC_ESTATE for a batch or its tubes.  Synchronises the stream. */
 pic_status pic_load(pic_handle *h, const void *buf, size_t bytes);
 
+/* Measurement helper, not part of the method: copy `bytes` bytes from d_src to
+ * d_dst (device memory, both 16-byte aligned, bytes a multiple of 16, the two
+ * ranges disjoint) with one 16-byte nontemporal load and store per thread, the
+ * simplest stream the HBM can serve.  Its rate is the achievable bandwidth the
+ * particle push is compared with.  Asynchronous on hip_stream (NULL: the
+ * default stream); PIC_EINVAL for a misaligned, odd-sized or overlapping
+ * request or bytes >= 2^40. */
+pic_status pic_stream_copy(const void *d_src, void *d_dst, size_t bytes, void *hip_stream);
+
 /* Release the handle (the caller still owns workspace and stream). */
 pic_status pic_destroy(pic_handle *h);
 

@@ -98,6 +98,7 @@ SIGNATURES = {
     "pic_set_push_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_uint32]),
     "pic_sync": (ctypes.c_int32, [ctypes.c_void_p]),
+    "pic_stream_copy": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "pic_adjoint_tape_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32]),
     "pic_run_adjoint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.POINTER(PicAdjointOut)]),

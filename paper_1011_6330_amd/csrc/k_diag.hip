@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include "pcpic_internal.h"
+#include "diag_body.h"
 #include "wave.h"
 
 namespace pcpic {
@@ -46,55 +47,25 @@ __global__ __launch_bounds__(256) void k_profile_clear(int nb, long long *cnt, u
     if (i == 0) ctr->gauss_max_bits = 0;
 }
 
-// Signed gamma sign(u) sqrt(1 + u^2) binned uniformly in x.  Per bin: count,
-// 128-bit fixed-point sum in units of 2^-32 (integer part and fraction summed
-// separately, then combined exactly), min and max.
+// Signed gamma sign(u) sqrt(1 + u^2) binned uniformly in x (ProfAcc): per bin
+// count, 128-bit fixed-point sum in units of 2^-32, min and max.  Block b takes
+// a contiguous range of the slots.
 __global__ __launch_bounds__(256) void k_profile(Consts c, int nb, const double *__restrict__ X,
-                                                 const double *__restrict__ U, const DevCounters *ctr,
-                                                 long long *cnt, unsigned long long *lo, long long *hi,
-                                                 long long *mn, long long *mx)
+                                                 const double *__restrict__ U, const DevCounters *ctr, ProfOut o)
 {
-    const int64_t n = ctr->n_slots;
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+    int64_t lo, hi;
+    block_range(ctr->n_slots, gridDim.x, blockIdx.x, lo, hi);
+    ProfAcc acc;
+    for (int64_t base = lo; base < hi; base += 256) {
         const int64_t p = base + threadIdx.x;
-        const double x = p < n ? X[p] : -1.0;
-        bool want = x >= 0.0;
+        const double x = p < hi ? X[p] : -1.0;
+        const bool want = x >= 0.0;
         int64_t bin = 0, gi = 0, gf = 0;
         long long ob = 0;
-        if (want) {
-            const double u = U[p];
-            double t = u * u;
-            t = 1.0 + t;
-            const double gam = sqrt(t);
-            const double sg = u < 0.0 ? -gam : gam;
-            bin = (int64_t)floor((x * (double)nb) / (double)c.N);
-            if (bin < 0) bin = 0;
-            if (bin > nb - 1) bin = nb - 1;
-            const double fl = floor(sg);
-            gi = (int64_t)fl;
-            gf = (int64_t)rint((sg - fl) * 4294967296.0);
-            ob = ordered_bits(sg);
-        }
-        unsigned long long pend = __ballot(want);
-        while (pend) {
-            const int leader = __ffsll(pend) - 1;
-            const int64_t lb = __shfl(bin, leader);
-            const bool mine = want && bin == lb;
-            const int64_t sc = wave_sum_i64(mine ? 1 : 0);
-            const int64_t si = wave_sum_i64(mine ? gi : 0);
-            const int64_t sf = wave_sum_i64(mine ? gf : 0);
-            const long long smin = wave_min_i64(mine ? ob : 0x7fffffffffffffffLL);
-            const long long smax = wave_max_i64(mine ? ob : (long long)0x8000000000000000ULL);
-            if ((int)__lane_id() == leader) {
-                atomicAdd((unsigned long long *)&cnt[lb], (unsigned long long)sc);
-                atomic_add_i128(&lo[lb], &hi[lb], ((__int128)si << 32) + (__int128)sf);
-                atomicMin(&mn[lb], smin);
-                atomicMax(&mx[lb], smax);
-            }
-            pend &= ~__ballot(mine);
-            want = want && !mine;
-        }
+        if (want) prof_values(c, nb, x, U[p], bin, gi, gf, ob);
+        acc.add(o, want, bin, gi, gf, ob);
     }
+    acc.flush(o);
 }
 
 hipError_t launch_gauss(pic_handle *h)
@@ -119,7 +90,7 @@ hipError_t launch_profile(pic_handle *h, int nb)
     if (nb > 0 && h->p.precision == PIC_FP32_BULK) return launch_profile32(h, nb);
     if (nb > 0)
         hipLaunchKernelGGL(k_profile, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, nb, w.x[h->pbuf],
-                           w.u[h->pbuf], w.ctr, w.pcount, w.plo, w.phi128, w.pmin, w.pmax);
+                           w.u[h->pbuf], w.ctr, ProfOut{w.pcount, w.plo, w.phi128, w.pmin, w.pmax});
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 // bit-identical to an IEEE double evaluation of the same formulas.
 #include <math.h>
 
+#include "diag_body.h"
 #include "pcpic_internal.h"
 #include "wave.h"
 #include "field_body.h"
@@ -32,10 +33,12 @@ __global__ __launch_bounds__(256) void k_rho_gj(Consts c, const double *knots, d
 __global__ __launch_bounds__(256) void k_weights(Consts c, const double *__restrict__ X,
                                                  const DevCounters *ctr, unsigned long long *w)
 {
-    const int64_t n = ctr->n_slots;
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+    int64_t lo, hi;
+    block_range(ctr->n_slots, gridDim.x, blockIdx.x, lo, hi);
+    WeightAcc acc;
+    for (int64_t base = lo; base < hi; base += 256) {
         const int64_t p = base + threadIdx.x;
-        const double x = p < n ? X[p] : -1.0;
+        const double x = p < hi ? X[p] : -1.0;
         const bool live = x >= 0.0 && x < (double)c.N;
         int64_t cell = 0, F = 0;
         if (live) {
@@ -43,9 +46,9 @@ __global__ __launch_bounds__(256) void k_weights(Consts c, const double *__restr
             cell = (int64_t)cd;
             F = (int64_t)rint((x - cd) * c.twoP);
         }
-        wave_add_keyed(w, cell, c.oneP - F, live);
-        wave_add_keyed(w, cell + 1, F, live);
+        acc.add(w, live, cell, c.oneP, F);
     }
+    acc.flush(w);
 }
 
 // Right-hand side of eq. (4) times dz^2 on nodes 1..N; node N carries the

@@ -17,6 +17,7 @@
 #include "push_common.h"
 #include "push_body.h"
 #include "sort_body.h"
+#include "diag_body.h"
 
 namespace pcpic {
 
@@ -30,86 +31,68 @@ __global__ __launch_bounds__(BLOCK) void k_push_f32(Consts c, Push32Args a)
 // diagnostics, sort and append for the two streams
 // ------------------------------------------------------------------------
 
-// Blocks [0, nb_lo) walk the low stream, the rest the high stream, grid-stride.
-__device__ __forceinline__ bool stream_slot(const DevCounters *ctr, unsigned nb_lo, int64_t &first,
-                                            int64_t &stride, int64_t &n)
+// Block b's contiguous range of the slots of both streams taken end to end
+// (the low stream's, then the high stream's): [lo0, hi0) of the low stream and
+// [lo1, hi1) of the high stream, either possibly empty.
+__device__ __forceinline__ void stream_ranges(const DevCounters *ctr, int64_t &lo0, int64_t &hi0, int64_t &lo1,
+                                              int64_t &hi1)
 {
-    const bool hi = blockIdx.x >= nb_lo;
-    const int64_t b = hi ? blockIdx.x - nb_lo : blockIdx.x;
-    const int64_t nb = hi ? gridDim.x - nb_lo : nb_lo;
-    n = hi ? ctr->n_slots_hi : ctr->n_slots;
-    first = b * 256;
-    stride = nb * 256;
-    return hi;
+    const int64_t n_lo = ctr->n_slots, n_hi = ctr->n_slots_hi;
+    int64_t a, b;
+    block_range(n_lo + n_hi, gridDim.x, blockIdx.x, a, b);
+    lo0 = a < n_lo ? a : n_lo;
+    hi0 = b < n_lo ? b : n_lo;
+    lo1 = (a > n_lo ? a : n_lo) - n_lo;
+    hi1 = (b > n_lo ? b : n_lo) - n_lo;
 }
 
-__global__ __launch_bounds__(256) void k_weights32(Consts c, Streams s, const DevCounters *ctr, unsigned nb_lo,
+__global__ __launch_bounds__(256) void k_weights32(Consts c, Streams s, const DevCounters *ctr,
                                                    unsigned long long *w)
 {
-    int64_t first, stride, n;
-    const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
-    const int *C = hi ? s.CH : s.CL;
-    const float *O = hi ? s.OH : s.OL;
-    for (int64_t base = first; base < n; base += stride) {
-        const int64_t p = base + threadIdx.x;
-        const int cell = p < n ? C[p] : -1;
-        const bool live = cell >= 0;
-        int64_t F = 0;
-        if (live) F = (int64_t)rint((double)O[p] * c.twoP);
-        wave_add_keyed(w, cell, c.oneP - F, live);
-        wave_add_keyed(w, cell + 1, F, live);
+    int64_t r[4];
+    stream_ranges(ctr, r[0], r[1], r[2], r[3]);
+    WeightAcc acc;
+#pragma unroll 1
+    for (int high = 0; high < 2; ++high) {
+        const int *C = high ? s.CH : s.CL;
+        const float *O = high ? s.OH : s.OL;
+        const int64_t hi = r[2 * high + 1];
+        for (int64_t base = r[2 * high]; base < hi; base += 256) {
+            const int64_t p = base + threadIdx.x;
+            const int cell = p < hi ? C[p] : -1;
+            const bool live = cell >= 0;
+            int64_t F = 0;
+            if (live) F = (int64_t)rint((double)O[p] * c.twoP);
+            acc.add(w, live, cell, c.oneP, F);
+        }
     }
+    acc.flush(w);
 }
 
-__global__ __launch_bounds__(256) void k_profile32(Consts c, int nb, Streams s, const DevCounters *ctr,
-                                                   unsigned nb_lo, long long *cnt, unsigned long long *lo,
-                                                   long long *hi128, long long *mn, long long *mx)
+__global__ __launch_bounds__(256) void k_profile32(Consts c, int nb, Streams s, const DevCounters *ctr, ProfOut o)
 {
-    int64_t first, stride, n;
-    const bool hi = stream_slot(ctr, nb_lo, first, stride, n);
-    const int *C = hi ? s.CH : s.CL;
-    const float *O = hi ? s.OH : s.OL;
-    for (int64_t base = first; base < n; base += stride) {
-        const int64_t p = base + threadIdx.x;
-        const int cell = p < n ? C[p] : -1;
-        bool want = cell >= 0;
-        int64_t bin = 0, gi = 0, gf = 0;
-        long long ob = 0;
-        if (want) {
-            const double u = hi ? s.UH[p] : (double)s.UL[p];
-            const double x = (double)cell + (double)O[p];
-            double t = u * u;
-            t = 1.0 + t;
-            const double gam = sqrt(t);
-            const double sg = u < 0.0 ? -gam : gam;
-            bin = (int64_t)floor((x * (double)nb) / (double)c.N);
-            if (bin < 0) bin = 0;
-            if (bin > nb - 1) bin = nb - 1;
-            const double fl = floor(sg);
-            gi = (int64_t)fl;
-            gf = (int64_t)rint((sg - fl) * 4294967296.0);
-            ob = ordered_bits(sg);
-        }
-        unsigned long long pend = __ballot(want);
-        while (pend) {
-            const int leader = __ffsll(pend) - 1;
-            const int64_t lb = __shfl(bin, leader);
-            const bool mine = want && bin == lb;
-            const int64_t sc = wave_sum_i64(mine ? 1 : 0);
-            const int64_t si = wave_sum_i64(mine ? gi : 0);
-            const int64_t sf = wave_sum_i64(mine ? gf : 0);
-            const long long smin = wave_min_i64(mine ? ob : 0x7fffffffffffffffLL);
-            const long long smax = wave_max_i64(mine ? ob : (long long)0x8000000000000000ULL);
-            if ((int)__lane_id() == leader) {
-                atomicAdd((unsigned long long *)&cnt[lb], (unsigned long long)sc);
-                atomic_add_i128(&lo[lb], &hi128[lb], ((__int128)si << 32) + (__int128)sf);
-                atomicMin(&mn[lb], smin);
-                atomicMax(&mx[lb], smax);
+    int64_t r[4];
+    stream_ranges(ctr, r[0], r[1], r[2], r[3]);
+    ProfAcc acc;
+#pragma unroll 1
+    for (int high = 0; high < 2; ++high) {
+        const int *C = high ? s.CH : s.CL;
+        const float *O = high ? s.OH : s.OL;
+        const int64_t hi = r[2 * high + 1];
+        for (int64_t base = r[2 * high]; base < hi; base += 256) {
+            const int64_t p = base + threadIdx.x;
+            const int cell = p < hi ? C[p] : -1;
+            const bool want = cell >= 0;
+            int64_t bin = 0, gi = 0, gf = 0;
+            long long ob = 0;
+            if (want) {
+                const double u = high ? s.UH[p] : (double)s.UL[p];
+                prof_values(c, nb, (double)cell + (double)O[p], u, bin, gi, gf, ob);
             }
-            pend &= ~__ballot(mine);
-            want = want && !mine;
+            acc.add(o, want, bin, gi, gf, ob);
         }
     }
+    acc.flush(o);
 }
 
 // Histogram for the sort (sort_key_f32: the destination stream's key range),
@@ -246,18 +229,16 @@ hipError_t launch_push_f32(pic_handle *h)
 
 hipError_t launch_weights32(pic_handle *h, int64_t *w_out)
 {
-    const unsigned nb = (unsigned)(h->n_cu * 4);
-    hipLaunchKernelGGL(k_weights32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, streams_of(h, h->pbuf), h->ws.ctr,
-                       nb, (unsigned long long *)w_out);
+    hipLaunchKernelGGL(k_weights32, dim3(h->n_cu * 8), dim3(256), 0, h->stream, h->c, streams_of(h, h->pbuf),
+                       h->ws.ctr, (unsigned long long *)w_out);
     return hipGetLastError();
 }
 
 hipError_t launch_profile32(pic_handle *h, int nbins)
 {
     const Workspace &w = h->ws;
-    const unsigned nb = (unsigned)(h->n_cu * 4);
-    hipLaunchKernelGGL(k_profile32, dim3(2 * nb), dim3(256), 0, h->stream, h->c, nbins, streams_of(h, h->pbuf),
-                       w.ctr, nb, w.pcount, w.plo, w.phi128, w.pmin, w.pmax);
+    hipLaunchKernelGGL(k_profile32, dim3(h->n_cu * 8), dim3(256), 0, h->stream, h->c, nbins, streams_of(h, h->pbuf),
+                       w.ctr, ProfOut{w.pcount, w.plo, w.phi128, w.pmin, w.pmax});
     return hipGetLastError();
 }
 

@@ -264,6 +264,7 @@ hipError_t launch_adj_finish(pic_handle *h, const double *lez, const double *ler
 hipError_t launch_kick_from(pic_handle *h, const double *ez);
 hipError_t launch_zero_i64(pic_handle *h, int64_t *p, int64_t n);
 hipError_t launch_batch_sort(pic_handle *h, bool hist_ready);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t n16, hipStream_t stream);
 bool batch_shape_supported(pic_handle *h);
 TubeDev tube_dev(pic_handle *t);
 hipError_t launch_field_inject(pic_handle *h);

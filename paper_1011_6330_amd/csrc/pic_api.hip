@@ -976,6 +976,18 @@ pic_status pic_load(pic_handle *h, const void *buf, size_t bytes)
     return PIC_OK;
 }
 
+pic_status pic_stream_copy(const void *d_src, void *d_dst, size_t bytes, void *hip_stream)
+{
+    const uintptr_t s = (uintptr_t)d_src, d = (uintptr_t)d_dst;
+    if (!d_src || !d_dst) return fail(PIC_EINVAL, "null pointer");
+    if (s % 16 || d % 16 || bytes % 16) return fail(PIC_EINVAL, "pointers and size must be multiples of 16 bytes");
+    if (bytes >= ((size_t)1 << 40)) return fail(PIC_EINVAL, "copy of %zu bytes is too large", bytes);
+    if (s < d + bytes && d < s + bytes) return fail(PIC_EINVAL, "source and destination overlap");
+    if (bytes == 0) return PIC_OK;
+    HIP_OK(launch_stream_copy(d_src, d_dst, (int64_t)(bytes / 16), (hipStream_t)hip_stream));
+    return PIC_OK;
+}
+
 pic_status pic_destroy(pic_handle *h)
 {
     if (!h) return fail(PIC_EINVAL, "handle is NULL");

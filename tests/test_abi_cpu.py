@@ -93,3 +93,16 @@ def test_null_handle_calls(lib):
     assert lib.pic_step(None, 1) == -1
     assert lib.pic_sync(None) == -1
     assert lib.pic_destroy(None) == -1
+
+
+def test_stream_copy_validates_before_launching(lib):
+    """The benchmark's copy helper rejects bad requests on the host (these
+    addresses are never dereferenced: every case fails or is empty before any
+    HIP call)."""
+    P = ctypes.c_void_p
+    assert lib.pic_stream_copy(None, P(4096), 16, None) == -1
+    assert lib.pic_stream_copy(P(4104), P(8192), 16, None) == -1       # source not 16-byte aligned
+    assert lib.pic_stream_copy(P(4096), P(8192), 24, None) == -1       # size not a multiple of 16
+    assert lib.pic_stream_copy(P(4096), P(4160), 128, None) == -1      # ranges overlap
+    assert lib.pic_stream_copy(P(4096), P(8192), 1 << 40, None) == -1  # too large
+    assert lib.pic_stream_copy(P(4096), P(8192), 0, None) == 0         # nothing to do

@@ -383,3 +383,23 @@ def test_graph_rounds_equal_direct_steps(precision):
     assert np.array_equal(xa[ka], xb[kb]) and np.array_equal(ua[ka], ub[kb])
     a.close()
     b.close()
+
+
+def test_stream_copy_exact():
+    """The benchmark's reference copy moves every byte, including a ragged tail
+    of 16-byte vectors past the last full block."""
+    import ctypes
+
+    import torch
+
+    from paper_1011_6330_amd import _binding
+    lib = _binding.load()
+    n = 64 * 1000 + 37                       # vectors of 16 bytes
+    src = torch.randint(-2 ** 62, 2 ** 62, (2 * n + 2,), dtype=torch.int64, device="cuda:0")
+    dst = torch.zeros_like(src)
+    rc = lib.pic_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), 16 * n,
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0, lib.pic_last_error().decode()
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:2 * n], src[:2 * n])
+    assert int(dst[2 * n:].abs().sum()) == 0  # nothing written past the end
