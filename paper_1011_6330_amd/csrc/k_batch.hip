@@ -140,22 +140,6 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_bsort_hist(BSortArgs a)
 // Exclusive scan of every tube's key counts in three phases over blocks of
 // SORT_SCAN_TILE keys (a block never spans two tubes): block totals, a scan of
 // each tube's block totals (one block per tube), then the offsets.
-__device__ __forceinline__ long long bscan_block_incl(long long v, long long *s_wave)
-{
-    const int lane = __lane_id(), wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const long long o = __shfl_up(v, off);
-        if (lane >= off) v += o;
-    }
-    if (lane == 63) s_wave[wv] = v;
-    __syncthreads();
-    long long add = 0;
-    for (int q = 0; q < wv; ++q) add += s_wave[q];
-    __syncthreads();
-    return v + add;
-}
-
 __global__ __launch_bounds__(256) void k_bscan_totals(BSortArgs a)
 {
     __shared__ long long s_wave[4];
@@ -166,7 +150,7 @@ __global__ __launch_bounds__(256) void k_bscan_totals(BSortArgs a)
     long long s = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) s += base + k < T.n_keys ? T.cell_count[base + k] : 0;
-    const long long inc = bscan_block_incl(s, s_wave);
+    const long long inc = block_scan_incl(s, s_wave);
     if (threadIdx.x == 255) T.blk_sum[lb] = inc;
 }
 
@@ -181,7 +165,7 @@ __global__ __launch_bounds__(256) void k_bscan_blocks(BSortArgs a)
     for (int64_t b0 = 0; b0 < nb; b0 += 256) {
         const int64_t i = b0 + threadIdx.x;
         const long long v = i < nb ? T.blk_sum[i] : 0;
-        const long long inc = bscan_block_incl(v, s_wave);
+        const long long inc = block_scan_incl(v, s_wave);
         const long long carry = s_carry;
         if (i < nb) T.blk_sum[i] = carry + inc - v;
         __syncthreads();
@@ -205,7 +189,7 @@ __global__ __launch_bounds__(256) void k_bscan_apply(BSortArgs a)
         v[k] = base + k < T.n_keys ? T.cell_count[base + k] : 0;
         s += v[k];
     }
-    const long long inc = bscan_block_incl(s, s_wave);
+    const long long inc = block_scan_incl(s, s_wave);
     long long run = T.blk_sum[lb] + inc - s;
     const int64_t klo = a.f32 ? sort_low_keys(T.c) : -1;
 #pragma unroll

@@ -150,39 +150,84 @@ __global__ __launch_bounds__(256) void k_check_staged(Consts c, const double *X,
     if (__lane_id() == 0 && nb) atomicAdd((unsigned long long *)&ctr->bad_inputs, (unsigned long long)nb);
 }
 
-// Staged particles -> (cell, f32 offset) and the stream their gamma selects.
-__global__ __launch_bounds__(256) void k_append_staged(Consts c, const double *X, const double *U, int64_t n,
-                                                       Streams s, double u_hi, DevCounters *ctr)
+// Appending staged particles keeps their order in both streams (so a beam
+// loaded in x order needs no sort before it pushes at full rate): block b of
+// 256 staged particles counts its high-stream ones (k_stage_count), one block
+// turns the counts into exclusive offsets and advances the slot counters
+// (k_stage_offsets), and k_append_staged writes each particle at its stream's
+// old slot count + its block's offset + its rank in the block.
+__global__ __launch_bounds__(256) void k_stage_count(const double *U, int64_t n, double u_hi, long long *blk)
 {
+    __shared__ int s_w[4];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int lane = __lane_id();
-    bool want = i < n;
+    const bool high = i < n && goes_high(U[i], u_hi);
+    const int cnt = __popcll(__ballot(high));
+    if (__lane_id() == 0) s_w[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) blk[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// One block: blk[0, nblk) -> exclusive prefix sums in place; base[0], base[1] =
+// the low and high slot counts before the append, which then advance.
+__global__ __launch_bounds__(256) void k_stage_offsets(long long *blk, int64_t nblk, int64_t n, DevCounters *ctr,
+                                                       long long *base)
+{
+    __shared__ long long s_wave[4];
+    __shared__ long long s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nblk; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const long long v = i < nblk ? blk[i] : 0;
+        const long long inc = block_scan_incl(v, s_wave);
+        const long long carry = s_carry;
+        if (i < nblk) blk[i] = carry + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 255) s_carry = carry + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const long long total_hi = s_carry;
+        base[0] = ctr->n_slots;
+        base[1] = ctr->n_slots_hi;
+        ctr->n_slots += n - total_hi;
+        ctr->n_slots_hi += total_hi;
+    }
+}
+
+// Staged particles -> (cell, f32 offset) in the stream their gamma selects.
+__global__ __launch_bounds__(256) void k_append_staged(const double *X, const double *U, int64_t n, Streams s,
+                                                       double u_hi, const long long *blk, const long long *base)
+{
+    __shared__ int s_hi[4], s_lo[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = __lane_id(), wv = threadIdx.x >> 6;
+    const bool want = i < n;
     double x = 0.0, u = 0.0;
     if (want) { x = X[i]; u = U[i]; }
     const bool high = want && goes_high(u, u_hi);
-    int cell = 0;
-    float o = 0.0f;
-    if (want) {
+    const unsigned long long mh = __ballot(high), ml = __ballot(want && !high);
+    if (lane == 0) { s_hi[wv] = __popcll(mh); s_lo[wv] = __popcll(ml); }
+    __syncthreads();
+    int ph = 0, pl = 0;
+    for (int q = 0; q < wv; ++q) { ph += s_hi[q]; pl += s_lo[q]; }
+    if (!want) return;
+    int cell;
+    float o;
+    {
         const double cd = floor(x);
         cell = (int)cd;
         o = (float)(x - cd);
         if (o >= 1.0f) { o = 0.0f; cell += 1; }
     }
-    for (int sidx = 0; sidx < 2; ++sidx) {
-        const bool mine = want && (high == (sidx == 1));
-        const unsigned long long grp = __ballot(mine);
-        if (!grp) continue;
-        const int leader = __ffsll(grp) - 1;
-        unsigned long long f0 = 0;
-        if (lane == leader)
-            f0 = atomicAdd((unsigned long long *)(sidx ? &ctr->n_slots_hi : &ctr->n_slots),
-                           (unsigned long long)__popcll(grp));
-        f0 = __shfl(f0, leader);
-        if (mine) {
-            const int64_t d = (int64_t)f0 + __popcll(grp & ((1ull << lane) - 1ull));
-            if (sidx) { s.CH[d] = cell; s.OH[d] = o; s.UH[d] = u; }
-            else { s.CL[d] = cell; s.OL[d] = o; s.UL[d] = (float)u; }
-        }
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const long long hi_before = blk[blockIdx.x];                           // high particles in earlier blocks
+    if (high) {
+        const int64_t d = base[1] + hi_before + ph + __popcll(mh & below);
+        s.CH[d] = cell; s.OH[d] = o; s.UH[d] = u;
+    } else {
+        const int64_t d = base[0] + ((int64_t)blockIdx.x * 256 - hi_before) + pl + __popcll(ml & below);
+        s.CL[d] = cell; s.OL[d] = o; s.UL[d] = (float)u;
     }
 }
 
@@ -268,12 +313,17 @@ hipError_t launch_sort32_scatter(pic_handle *h)
 hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only)
 {
     const unsigned g = (unsigned)((n + 255) / 256);
-    if (check_only)
+    if (check_only) {
         hipLaunchKernelGGL(k_check_staged, dim3(g), dim3(256), 0, h->stream, h->c, h->ws.stage_x, h->ws.stage_u, n,
                            h->ws.ctr);
-    else
-        hipLaunchKernelGGL(k_append_staged, dim3(g), dim3(256), 0, h->stream, h->c, h->ws.stage_x, h->ws.stage_u, n,
-                           streams_of(h, h->pbuf), h->u_hi, h->ws.ctr);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_stage_count, dim3(g), dim3(256), 0, h->stream, h->ws.stage_u, n, h->u_hi, h->ws.stage_blk);
+    hipLaunchKernelGGL(k_stage_offsets, dim3(1), dim3(256), 0, h->stream, h->ws.stage_blk, (int64_t)g, n, h->ws.ctr,
+                       h->ws.stage_base);
+    hipLaunchKernelGGL(k_append_staged, dim3(g), dim3(256), 0, h->stream, h->ws.stage_x, h->ws.stage_u, n,
+                       streams_of(h, h->pbuf), h->u_hi, (const long long *)h->ws.stage_blk,
+                       (const long long *)h->ws.stage_base);
     return hipGetLastError();
 }
 

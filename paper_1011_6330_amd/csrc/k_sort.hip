@@ -38,24 +38,6 @@ __global__ __launch_bounds__(256) void k_hist(Consts c, const double *__restrict
     }
 }
 
-// Block-level inclusive scan of 256 values (wave scan + LDS across the 4 waves).
-__device__ __forceinline__ long long block_scan_incl(long long v, long long *s_wave)
-{
-    const int lane = __lane_id();
-    const int wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const long long o = __shfl_up(v, off);
-        if (lane >= off) v += o;
-    }
-    if (lane == 63) s_wave[wv] = v;
-    __syncthreads();
-    long long add = 0;
-    for (int k = 0; k < wv; ++k) add += s_wave[k];
-    __syncthreads();
-    return v + add;
-}
-
 // phase 1: per-block totals of SCAN_TILE cells
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_totals(const long long *count, int64_t n, long long *blk)
 {

@@ -116,6 +116,8 @@ struct Workspace {
     float *k32;             // f32 kick array (FP32-bulk low stream)
     double *stage_x, *stage_u;  // FP32-bulk: staging of injected particles
     int64_t stage_cap;
+    long long *stage_blk;       // FP32-bulk: per-256-particle block counts of a staged append
+    long long *stage_base;      // [2] slot counts of the two streams before the append
     long long *total_lo;    // FP32-bulk sort: low-destination total
     double *ez[2], *er[2], *b[2];
     int64_t *j[2];          // fixed-point current, ping-pong per step

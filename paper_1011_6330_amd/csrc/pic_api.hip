@@ -160,6 +160,8 @@ Workspace carve(const pic_params &p, uint8_t *base)
         w.stage_cap = (int64_t)(cap < ((size_t)1 << 22) ? cap : ((size_t)1 << 22));
         w.stage_x = (double *)take((size_t)w.stage_cap * 8);
         w.stage_u = (double *)take((size_t)w.stage_cap * 8);
+        w.stage_blk = (long long *)take(((size_t)w.stage_cap / 256 + 1) * 8);
+        w.stage_base = (long long *)take(16);
         w.total_lo = (long long *)take(8);
     }
     for (int k = 0; k < 2; ++k) {

@@ -213,4 +213,24 @@ __device__ __forceinline__ double run_sum_to_tail(double v, int rank)
     return v;
 }
 
+// Inclusive scan of one value per thread over a block of 256 threads (wave
+// scan, then the totals of the lower waves through LDS).  s_wave holds 4
+// entries of the caller's shared memory; every thread must call it.
+__device__ __forceinline__ long long block_scan_incl(long long v, long long *s_wave)
+{
+    const int lane = (int)__lane_id();
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) s_wave[wv] = v;
+    __syncthreads();
+    long long add = 0;
+    for (int k = 0; k < wv; ++k) add += s_wave[k];
+    __syncthreads();
+    return v + add;
+}
+
 }  // namespace pcpic

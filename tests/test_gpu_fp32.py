@@ -142,6 +142,20 @@ def test_fp32_c2_full_size():
     err = _errors(g, o)
     _gate(err, "c2 full size step 10", need_exits=True)
     assert err["n_high"] > 0.5 * err["n_alive"]
+    # the profile counts and the CIC weights come from the stored (cell, offset):
+    # after a sort (both streams in cell order), against the same pass in FP64 on
+    # the positions the FP32 path holds
+    g.step(54)                                # the round's sort: both streams in cell order
+    d = g.diagnostics(n_bins=64, weights=True, fields=False)
+    px, pu = g.read_particles()
+    N = cfg["n_cells"]
+    bins = np.clip(np.floor(px * 64 / N).astype(np.int64), 0, 63)
+    assert np.array_equal(d["prof_count"], np.bincount(bins, minlength=64))
+    cell = np.floor(px).astype(np.int64)
+    F = np.rint((px - cell) * 2.0 ** 32)
+    # per-node sums stay below 2^53, so the float64 bincount is exact
+    w = np.bincount(cell, weights=2.0 ** 32 - F, minlength=N + 1) + np.bincount(cell + 1, weights=F, minlength=N + 1)
+    assert np.array_equal(d["weights"], w.astype(np.int64))
     g.close()
 
 

@@ -254,6 +254,17 @@ def test_c2_full_size_first_steps():
     o.step(3)
     d = assert_state_equal(g, o, what="c2 full size")
     assert d["n_alive"] > 3.9e7
+    # diagnostics at full size: each wave walks long runs of one profile bin and
+    # one cell, so the per-wave partial sums carry almost every particle
+    nb = 64
+    d = g.diagnostics(n_bins=nb, gauss=True, weights=True, fields=False)
+    cnt, lo, hi, mn, mx = o.profile(nb)
+    assert np.array_equal(d["prof_count"], cnt)
+    assert np.array_equal(d["prof_sum_lo"], lo) and np.array_equal(d["prof_sum_hi"], hi)
+    assert np.array_equal(d["prof_min"], mn) and np.array_equal(d["prof_max"], mx)
+    assert np.array_equal(d["weights"], o.weights())
+    G, gmax = o.gauss()
+    assert np.array_equal(d["gauss"], G) and d["gauss_max"] == gmax
 
 
 @pytest.mark.parametrize("precision", [0, 1])
