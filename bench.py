@@ -174,6 +174,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 2^20-cell, 2.5e8-particle tube")
     ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--no-small", action="store_true", help="skip the C1 time-per-step leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -287,7 +288,7 @@ def main():
     result["roofline"]["frac_of_achievable"] = result["roofline"]["achieved"] / ach
     log(f"copy: torch {copy_gbs:.0f} GB/s, 16-byte nontemporal stream {ach:.0f} GB/s")
 
-    if args.config == "c2":
+    if args.config == "c2" and not args.no_small:
         result["small_tubes"] = run_small()
         if "adjoint" in result:
             result["small_tubes"]["c4"] = {
