@@ -1,7 +1,7 @@
 """Throughput of the polar-cap PIC step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
-                    [--push 128:2:nt] [--push32 256:4:nt] [--tune]
+                    [--push 128:2:nt] [--push32 128:4:nt] [--tune]
                     [--no-fp32] [--no-ensemble] [--no-adjoint] [--no-cpu-baseline]
 
 A step is one whole PIC cycle of the tube: push + deposit, field update +
@@ -48,7 +48,7 @@ B_FP64 = 32                    # x, u (f64) read + written per particle-step
 B_F32_LOW = 24                 # cell, offset, u (f32)
 B_F32_HIGH = 32                # cell, offset (4 B each), u (f64)
 DEFAULT_PUSH = "128:2:nt"      # FP64 push launch shape: threads, slots per thread, nontemporal
-DEFAULT_PUSH32 = "256:4:nt"    # FP32-bulk push launch shape
+DEFAULT_PUSH32 = "128:4:nt"    # FP32-bulk push launch shape
 
 
 def shape_of(text):

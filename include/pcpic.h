@@ -111,7 +111,8 @@ typedef struct pic_params {
     const double *knots;      /* host, n_knots values theta_k (PIC_RHO_KNOTS)               */
     int32_t fp_bits;          /* P, fraction bits of the fixed-point weights: 16..36         */
     int32_t sort_every;       /* cell sort + compaction period in steps (0 = never)          */
-    int64_t capacity;         /* particle capacity (live + not yet compacted)                */
+    int64_t capacity;         /* particle capacity (live + not yet compacted; FP32-bulk: both
+                                 streams together, each holds up to `capacity` slots)        */
     uint32_t flags;           /* PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS | PIC_B_STEADY_INIT  */
     int32_t max_bins;         /* largest signed-gamma profile pic_diagnostics may request    */
     double gamma_fp64;        /* PIC_FP32_BULK: gamma from which u is kept in f64 (0 = 1e6)  */
@@ -241,9 +242,9 @@ enum {
 /* Launch shape of the particle push: threads per block (64, 128, 256, 512) and
  * particle slots per thread.  FP64: 2, 4 (up to 256 threads) or 8 (up to 128
  * threads); a thread takes per_thread/2 pairs of consecutive slots, 2*block
- * slots apart.  FP32-bulk: 4 (per block of the low stream, the high stream
- * walks the same slots as two tiles of 2 per thread).  pic_init sets 128 x 2
- * (FP64) or 256 x 4 (FP32-bulk), both with PIC_PUSH_NONTEMPORAL.
+ * slots apart.  FP32-bulk: 4 (4 consecutive low-stream slots per thread; a
+ * high-stream block takes 2 per thread).  pic_init sets 128 x 2 (FP64) or
+ * 128 x 4 (FP32-bulk), both with PIC_PUSH_NONTEMPORAL.
  * Results do not depend on the choice (integer deposition); the autotuner
  * picks the fastest.  Errors: PIC_EINVAL for an unsupported shape or flag. */
 pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread, uint32_t flags);

@@ -75,6 +75,9 @@ __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, 
         // surface field from the node-0 Gauss law over the half cell [0, dz/2]
         const int64_t w0 = __hip_atomic_load(&ctr->w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int64_t slots = __hip_atomic_load(&ctr->n_slots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // FP32-bulk: the two streams together stay within the capacity, since a
+        // sort may move every particle into either one (0 in FP64 mode)
+        const int64_t slots_hi = __hip_atomic_load(&ctr->n_slots_hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double t1 = c.qmP * (double)w0;
         const double t2 = c.rho0 * c.hdz;
         const double es = s_ez0 - c.fourpi * (t1 - t2);
@@ -82,14 +85,14 @@ __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, 
         const int64_t ks = ctr->step - a.sched_first;   // index of this step in a replayed schedule
         if (a.sched && ks >= 0 && ks < a.sched_n) {
             const int64_t want = a.sched[ks] > 0 ? a.sched[ks] : 0;
-            const int64_t avail = c.cap - slots;
+            const int64_t avail = c.cap - slots - slots_hi;
             ninj = want > avail ? avail : want;
             if (want > avail) atomicOr(&ctr->status, (unsigned long long)PIC_ST_CAPACITY);
         } else if (!(c.flags & PIC_NO_AUTO_INJECT)) {
             const double ratio = es / c.fqm;
             if (ratio > 0.0) {
                 const double nf = floor(ratio);
-                const int64_t avail = c.cap - slots;
+                const int64_t avail = c.cap - slots - slots_hi;
                 if (nf > (double)avail) {
                     ninj = avail;
                     atomicOr(&ctr->status, (unsigned long long)PIC_ST_CAPACITY);

@@ -246,8 +246,8 @@ static hipError_t launch_push32_t(pic_handle *h)
 {
     const Workspace &w = h->ws;
     const int b = h->pbuf;
-    const int64_t span = (int64_t)BLOCK * F32_PPT_LO;
-    const unsigned items = (unsigned)((h->c.cap + span - 1) / span + 1);   // both streams, any split
+    const int64_t tile_hi = (int64_t)BLOCK * F32_PPT_HI;
+    const unsigned items = (unsigned)((h->c.cap + tile_hi - 1) / tile_hi + 1);   // both streams, any split
     Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b], w.k32, w.k64,
                  (unsigned long long *)w.j[h->jbuf], w.ctr,
                  h->hist_on ? (unsigned long long *)w.cell_count : nullptr, h->u_hi};

@@ -175,8 +175,8 @@ struct TubeDev {
     gptr<long long> cell_count, cell_off, total_lo, blk_sum;
     gptr<double> rhs, cp, dp, phi;   // Poisson solve of eq. (4)
     double u_hi;
-    int64_t push_tiles;      // push tiles (FP32-bulk: spans of BLOCK*F32_PPT_LO slots) at capacity
-    int64_t push_tiles_hi;   // FP32-bulk: 1 more item, as the two streams may each end in a partial span
+    int64_t push_tiles;      // push tiles at capacity (FP32-bulk: of BLOCK*F32_PPT_HI slots)
+    int64_t push_tiles_hi;   // FP32-bulk: 1 more item, as the two streams may each end in a partial tile
     int64_t sort_chunks;  // sort tiles (SORT_TILE slots) per particle stream at capacity
     int64_t n_keys;       // sort keys (N, or 2(N+1) in FP32-bulk mode)
 };

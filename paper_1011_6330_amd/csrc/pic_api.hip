@@ -255,7 +255,7 @@ static pic_status init_tube(const pic_params *p, void *d_workspace, size_t ws_by
     h->stream = (hipStream_t)hip_stream;
     h->ws = carve(*p, (uint8_t *)d_workspace);
     // the fastest measured push shapes (nontemporal particle streams)
-    h->push_block = p->precision == PIC_FP32_BULK ? 256 : 128;
+    h->push_block = 128;
     h->push_ppt = p->precision == PIC_FP32_BULK ? 4 : 2;
     h->push_nt = 1;
     {
@@ -317,8 +317,9 @@ pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u
     pic_status s = read_counters(h, &ctr);
     if (s != PIC_OK) return s;
     if (h->p.precision == PIC_FP32_BULK) {
-        // either stream may receive every particle
-        if (ctr.n_slots + n > h->c.cap || ctr.n_slots_hi + n > h->c.cap)
+        // a sort may move every particle into either stream, so both together
+        // stay within the capacity
+        if (ctr.n_slots + ctr.n_slots_hi + n > h->c.cap)
             return fail(PIC_ECAPACITY, "%lld + %lld slots used + %lld > capacity %lld", (long long)ctr.n_slots,
                         (long long)ctr.n_slots_hi, (long long)n, (long long)h->c.cap);
         const hipMemcpyKind kind = mem == 0 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -938,7 +939,7 @@ pic_status pic_load(pic_handle *h, const void *buf, size_t bytes)
     if (!same) return fail(PIC_EINVAL, "the saved tube has different parameters");
     const bool f32 = h->p.precision == PIC_FP32_BULK;
     const int64_t N = h->c.N;
-    if (hd.n_lo < 0 || hd.n_hi < 0 || hd.n_lo > h->c.cap || hd.n_hi > h->c.cap || (!f32 && hd.n_hi != 0))
+    if (hd.n_lo < 0 || hd.n_hi < 0 || hd.n_lo + hd.n_hi > h->c.cap || (!f32 && hd.n_hi != 0))
         return fail(PIC_ECAPACITY, "saved state holds %lld + %lld slots, capacity %lld", (long long)hd.n_lo,
                     (long long)hd.n_hi, (long long)h->c.cap);
     const SaveLayout L = save_layout(N, hd.n_knots, hd.n_lo, hd.n_hi, f32);
@@ -1022,8 +1023,8 @@ static BatchMapSizes batch_map_sizes(const pic_params *tubes, int n)
         const pic_params &p = tubes[t];
         const bool f32 = p.precision == PIC_FP32_BULK;
         // the smallest tiles of any launch shape: 64 threads x 2 slots (FP64),
-        // spans of 64 x 4 slots over both streams plus one (FP32-bulk)
-        m.push += f32 ? (p.capacity + 255) / 256 + 1 : (p.capacity + 127) / 128;
+        // high-stream tiles of 64 x 2 slots over both streams plus one (FP32-bulk)
+        m.push += f32 ? (p.capacity + 127) / 128 + 1 : (p.capacity + 127) / 128;
         m.field += (p.n_cells + 63) / 64;
         m.chunk += (p.capacity + SORT_TILE - 1) / SORT_TILE + (f32 ? 1 : 0);
         const int64_t keys = (f32 ? 2 * (p.n_cells + 1) : p.n_cells) << sort_sub_log2(p);
@@ -1081,7 +1082,9 @@ static pic_status batch_configure(pic_handle *h, int block, int per_thread)
         return fail(PIC_EINVAL, "unsupported batch launch shape (%d threads, %d per thread)", block, per_thread);
     }
     const int n = (int)h->tubes.size();
-    const int64_t tile = (int64_t)block * ppt;
+    // slots per push item: FP32-bulk items are tiles of the high stream's size
+    // (the low stream's are larger), push_item_f32
+    const int64_t tile = (int64_t)block * (f32 ? F32_PPT_HI : ppt);
     std::vector<TubeDev> td((size_t)n);
     std::vector<int64_t> pp((size_t)n + 1, 0), fp((size_t)n + 1, 0), sp((size_t)n + 1, 0), kp((size_t)n + 1, 0);
     std::vector<int64_t> cp((size_t)n + 1, 0);

@@ -396,11 +396,14 @@ __device__ __forceinline__ void push_tile_hi(const Consts &c, const Push32Args &
     }
 }
 
-// Item k of a tube's FP32-bulk push, an item being a span of BLOCK*F32_PPT_LO
-// slots: the low stream's spans come first, then the high stream's, which a
-// block walks as tiles of BLOCK*F32_PPT_HI slots one after the other.  Items
-// past both streams return at once, so launching ceil(capacity / span) + 1
-// items covers any split of the slots and leaves the idle ones at the end.
+// Item k of a tube's FP32-bulk push: the low stream's tiles of BLOCK*F32_PPT_LO
+// slots come first, then the high stream's tiles of BLOCK*F32_PPT_HI slots, one
+// tile per item.  Items past both streams return at once.  As the two streams
+// together hold at most `capacity` slots, ceil(capacity / (BLOCK*F32_PPT_HI)) + 1
+// items cover any split of the slots, with the idle ones at the end.  (An
+// earlier form let a block walk two high tiles in turn, so that both streams
+// had items of one size; its second tile waited on the first one's memory,
+// and the C2 push took 241 us against 221 us now.)
 template <int BLOCK, int NT>
 __device__ __forceinline__ void push_item_f32(const Consts &c, const Push32Args &a, int64_t k)
 {
@@ -411,13 +414,8 @@ __device__ __forceinline__ void push_item_f32(const Consts &c, const Push32Args 
         push_tile_lo<BLOCK, NT>(c, a, n_lo, k * SPAN);
         return;
     }
-    const int64_t span0 = (k - items_lo) * SPAN;
-#pragma unroll 1
-    for (int r = 0; r < F32_PPT_LO / F32_PPT_HI; ++r) {
-        const int64_t tile0 = span0 + (int64_t)r * (BLOCK * F32_PPT_HI);
-        if (tile0 >= n_hi) break;
-        push_tile_hi<BLOCK, NT>(c, a, n_hi, tile0);
-    }
+    const int64_t tile0 = (k - items_lo) * ((int64_t)BLOCK * F32_PPT_HI);
+    if (tile0 < n_hi) push_tile_hi<BLOCK, NT>(c, a, n_hi, tile0);
 }
 
 }  // namespace pcpic

@@ -195,6 +195,24 @@ def test_fp32_c2_20000_steps_against_fp64():
     assert a["n_exit"] == b["n_exit"]
 
 
+def test_fp32_capacity_counts_both_streams():
+    """A sort may move every particle into either stream, so the two streams
+    together must fit the capacity: an inject past it is refused even when each
+    stream alone would have room."""
+    from paper_1011_6330_amd import PicError, Tube
+    cfg = dict(synth.preset("c1"), capacity=1000, flags=1 | 2, gamma_fp64=50.0)
+    t = Tube(dict(synth.tube_params(cfg), precision=1))
+    t.inject(np.linspace(1.0, 500.0, 400), np.full(400, 2.0))        # low stream
+    t.inject(np.linspace(1.0, 500.0, 400), np.full(400, 200.0))      # high stream
+    with pytest.raises(PicError) as e:
+        t.inject(np.linspace(1.0, 500.0, 300), np.full(300, 200.0))
+    assert e.value.code == -3                                         # PIC_ECAPACITY
+    t.inject(np.linspace(1.0, 500.0, 200), np.full(200, 200.0))      # exactly full
+    d = t.diagnostics(fields=False)
+    assert d["n_alive"] == 1000 and d["n_slots_high"] == 600
+    t.close()
+
+
 def test_fp32_deterministic_under_reordering():
     """Integer deposit and integer reductions: a shuffled load and a rerun give
     identical fields and the same particle multiset."""
