@@ -76,6 +76,8 @@ def load():
         lib.orc_gauss.argtypes = [P(OrcCfg), P(OrcState), _pd, _pd]
         lib.orc_profile.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int32, _pi,
                                     P(ctypes.c_uint64), _pi, _pd, _pd]
+        lib.orc_step_par.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int64, ctypes.c_int32]
+        lib.orc_step_par.restype = ctypes.c_int
         lib.orc_adjoint.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int64, _pd, _pd, _pd, _pi]
         lib.orc_adjoint.restype = ctypes.c_int
         for f in ("orc_rho_gj", "orc_weights", "orc_init", "orc_inject", "orc_step",
@@ -153,6 +155,13 @@ class OracleTube:
         rc = self.lib.orc_step(ctypes.byref(self.ccfg), ctypes.byref(self.st), int(n))
         if rc != 0:
             raise ValueError(f"orc_step failed (rc={rc})")
+
+    def step_par(self, n=1, threads=0):
+        """n steps with the particles split over `threads` OpenMP threads (0 = the
+        default count); the same state as step(n), bit for bit."""
+        rc = self.lib.orc_step_par(ctypes.byref(self.ccfg), ctypes.byref(self.st), int(n), int(threads))
+        if rc != 0:
+            raise ValueError(f"orc_step_par failed (rc={rc})")
 
     def gauss(self):
         g = np.zeros(self.N + 1)

@@ -19,6 +19,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 /* ---- derived constants ------------------------------------------------ */
 
 typedef struct {
@@ -247,22 +251,35 @@ static void orc_add128(uint64_t *lo, int64_t *hi, int64_t v)
     *hi = (int64_t)(s >> 64);
 }
 
-static void orc_one_step(const orc_cfg *c, orc_state *st)
-{
-    orc_const k;
-    orc_consts(c, st, &k);
-    int64_t N = k.N;
-    int P = c->fp_bits;
+/* What the particle half of a step leaves behind over a range of particles. */
+typedef struct {
+    int64_t *j;           /* [N] current of the range's moves                     */
+    int64_t *j_inj;       /* [N] injected-class part of it (NULL: not kept)        */
+    int64_t w0, w0_inj;   /* node-0 weight of the survivors (all / injected class) */
+    int64_t n_exit, n_absorb, kept, status;
+    uint64_t exit_lo;     /* 128-bit sum of rint(gamma 2^32) over the exits        */
+    int64_t exit_hi;
+} orc_tally;
 
-    /* kick array from the current E_z: K = (q/m) dt E_z */
-    for (int64_t i = 0; i < N; ++i) st->k[i] = k.qmdt * st->ez[i];
+/* Start of a step: kick array K = (q/m) dt E_z from the current E_z; J cleared. */
+static void orc_step_begin(orc_state *st, const orc_const *k)
+{
+    int64_t N = k->N;
+    for (int64_t i = 0; i < N; ++i) st->k[i] = k->qmdt * st->ez[i];
     for (int64_t i = 0; i < N; ++i) st->j[i] = 0;
     if (st->j_inj)
         for (int64_t i = 0; i < N; ++i) st->j_inj[i] = 0;
-    const double rate = c->inj_rate > 0.0 ? c->inj_rate : 1.0;
+}
 
-    int64_t w0 = 0, w0_inj = 0, kept = 0;
-    for (int64_t p = 0; p < st->n; ++p) {
+/* Particles p0 .. p1-1 of the state: gather, eq. (1), the charge-conserving
+ * current, the boundaries.  Survivors are written, in order, to xo/uo/clso at
+ * index t->kept onwards (xo may be st->x itself: the write never passes the read). */
+static void orc_push_range(const orc_cfg *c, const orc_state *st, const orc_const *k, int64_t p0, int64_t p1,
+                           double *xo, double *uo, unsigned char *clso, orc_tally *t)
+{
+    int64_t N = k->N;
+    int P = c->fp_bits;
+    for (int64_t p = p0; p < p1; ++p) {
         double x = st->x[p], u = st->u[p];
         /* gather: linear interpolation of the face values, clamped at the ends */
         double s = x - 0.5, E;
@@ -277,12 +294,12 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
         }
         /* eq. (1): d(gamma m v)/dt = q E_z, dz/dt = v, with u = gamma v (c = 1) */
         double u1 = u + E;
-        double t = u1 * u1;
-        t = 1.0 + t;
-        double gam = sqrt(t);
+        double tt = u1 * u1;
+        tt = 1.0 + tt;
+        double gam = sqrt(tt);
         double v = u1 / gam;
-        double x1 = x + k.dtdz * v;
-        if (!isfinite(u1) || !isfinite(x1)) { st->status |= ORC_ST_NONFINITE; continue; }
+        double x1 = x + k->dtdz * v;
+        if (!isfinite(u1) || !isfinite(x1)) { t->status |= ORC_ST_NONFINITE; continue; }
 
         /* charge-conserving current: J_{i+1/2} += S_i(x^n) - S_i(x^{n+1}) on every face */
         int64_t c0, F0, c1, F1;
@@ -293,49 +310,67 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
         if (hi > N - 1) hi = N - 1;
         const int injected = st->cls && st->cls[p];
         for (int64_t i = lo; i <= hi; ++i) {
-            const int64_t d = orc_S(i, c0, F0, k.oneP) - orc_S(i, c1, F1, k.oneP);
-            st->j[i] += d;
-            if (injected && st->j_inj) st->j_inj[i] += d;
+            const int64_t d = orc_S(i, c0, F0, k->oneP) - orc_S(i, c1, F1, k->oneP);
+            t->j[i] += d;
+            if (injected && t->j_inj) t->j_inj[i] += d;
         }
 
         if (x1 >= (double)N) {               /* leaves through the top of the tube */
-            st->n_exit += 1;
-            orc_add128(&st->exit_sum_lo, &st->exit_sum_hi, (int64_t)rint(ldexp(gam, 32)));
+            t->n_exit += 1;
+            orc_add128(&t->exit_lo, &t->exit_hi, (int64_t)rint(ldexp(gam, 32)));
             continue;
         }
         if (x1 < 0.0) {                      /* returns to the star */
-            st->n_absorb += 1;
+            t->n_absorb += 1;
             continue;
         }
         if (c1 == 0) {                       /* node-0 weight of the survivors */
-            w0 += k.oneP - F1;
-            if (injected) w0_inj += k.oneP - F1;
+            t->w0 += k->oneP - F1;
+            if (injected) t->w0_inj += k->oneP - F1;
         }
-        st->x[kept] = x1;
-        st->u[kept] = u1;
-        if (st->cls) st->cls[kept] = st->cls[p];
-        ++kept;
+        xo[t->kept] = x1;
+        uo[t->kept] = u1;
+        if (clso) clso[t->kept] = st->cls[p];
+        t->kept += 1;
     }
-    st->n = kept;
-    st->w0 = w0;
+}
+
+/* End of a step, once every particle has moved and t holds the whole step's
+ * tallies (its current already in st->j): counters, eq. (3), the injection. */
+static void orc_step_end(const orc_cfg *c, orc_state *st, const orc_const *k, const orc_tally *t)
+{
+    int64_t N = k->N;
+    const double rate = c->inj_rate > 0.0 ? c->inj_rate : 1.0;
+    st->n = t->kept;
+    st->w0 = t->w0;
+    st->n_exit += t->n_exit;
+    st->n_absorb += t->n_absorb;
+    st->status |= t->status;
+    {
+        __int128 s = ((__int128)st->exit_sum_hi << 64) | (__int128)st->exit_sum_lo;
+        s += ((__int128)t->exit_hi << 64) | (__int128)t->exit_lo;
+        st->exit_sum_lo = (uint64_t)s;
+        st->exit_sum_hi = (int64_t)(s >> 64);
+    }
+    const int64_t w0 = t->w0, w0_inj = t->w0_inj;
 
     if (!(c->flags & ORC_FREEZE_FIELDS)) {
         /* eq. (3), leap-frog: dB/dt = -dE_r/dz - E_z/R, then dE_r/dt = -dB/dz,
          * then dE_z/dt = B/R - 4 pi j.  E_r,0 = 0 (phi = 0 at the star);
          * mirror about x = N (B odd) gives the E_r,N update. */
         for (int64_t i = 0; i < N; ++i)
-            st->b[i] = st->b[i] - (k.dtdz * (st->er[i + 1] - st->er[i]) + k.dtR * st->ez[i]);
+            st->b[i] = st->b[i] - (k->dtdz * (st->er[i + 1] - st->er[i]) + k->dtR * st->ez[i]);
         for (int64_t i = 1; i < N; ++i)
-            st->er[i] = st->er[i] - k.dtdz * (st->b[i] - st->b[i - 1]);
-        st->er[N] = st->er[N] + k.tw * st->b[N - 1];
+            st->er[i] = st->er[i] - k->dtdz * (st->b[i] - st->b[i - 1]);
+        st->er[N] = st->er[N] + k->tw * st->b[N - 1];
         if (rate == 1.0 || !st->j_inj) {
             for (int64_t i = 0; i < N; ++i)
-                st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) - k.c4 * (double)st->j[i];
+                st->ez[i] = (st->ez[i] + k->dtR * st->b[i]) - k->c4 * (double)st->j[i];
         } else {
             /* injected particles carry rate * q_m */
             for (int64_t i = 0; i < N; ++i) {
                 const double jw = (double)(st->j[i] - st->j_inj[i]) + rate * (double)st->j_inj[i];
-                st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) - k.c4 * jw;
+                st->ez[i] = (st->ez[i] + k->dtR * st->b[i]) - k->c4 * jw;
             }
         }
     }
@@ -343,10 +378,10 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
     /* SCLF injection (sec. 2): the field at the surface from the node-0 Gauss law
      * over the half cell [0, dz/2]; electrons are added at x = 0 with u = 0 until
      * the base charge cancels it (never over-injecting). */
-    double t1 = rate == 1.0 ? k.qmP * (double)w0
-                            : k.qmP * ((double)(w0 - w0_inj) + rate * (double)w0_inj);
-    double t2 = k.rho0 * k.hdz;
-    double es = st->ez[0] - k.fourpi * (t1 - t2);
+    double t1 = rate == 1.0 ? k->qmP * (double)w0
+                            : k->qmP * ((double)(w0 - w0_inj) + rate * (double)w0_inj);
+    double t2 = k->rho0 * k->hdz;
+    double es = st->ez[0] - k->fourpi * (t1 - t2);
     st->e_surf = es;
     int64_t ninj = 0;
     if (c->schedule) {                       /* frozen injection counts of a recorded run */
@@ -361,7 +396,7 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
         st->n += ninj;
         st->n_injected += ninj;
     } else if (!(c->flags & ORC_NO_AUTO_INJECT)) {
-        double ratio = es / k.fqm;
+        double ratio = es / k->fqm;
         if (ratio > 0.0) {
             double nf = floor(ratio);
             int64_t avail = c->capacity - st->n;
@@ -380,10 +415,112 @@ static void orc_one_step(const orc_cfg *c, orc_state *st)
     st->step += 1;
 }
 
+/* One PIC cycle, serially: every particle in order, survivors compacted in place. */
+static void orc_one_step(const orc_cfg *c, orc_state *st)
+{
+    orc_const k;
+    orc_consts(c, st, &k);
+    orc_step_begin(st, &k);
+    orc_tally t;
+    memset(&t, 0, sizeof t);
+    t.j = st->j;
+    t.j_inj = st->j_inj;
+    orc_push_range(c, st, &k, 0, st->n, st->x, st->u, st->cls, &t);
+    orc_step_end(c, st, &k, &t);
+}
+
 int orc_step(const orc_cfg *c, orc_state *st, int64_t n_steps)
 {
     if (orc_check(c) || !st || n_steps < 0) return -1;
     for (int64_t s = 0; s < n_steps; ++s) orc_one_step(c, st);
+    return 0;
+}
+
+/* The same steps with the particles split over threads (OpenMP), for timing the
+ * oracle on every host core.  Thread k takes the k-th contiguous slice of the
+ * particles and pushes it with orc_push_range into its own current array and
+ * tallies; the slices' survivors are then written back in slice order, the
+ * current arrays summed node by node in thread order and the tallies in thread
+ * order.  Every sum is over integers, so the state after each step is the
+ * serial oracle's, bit for bit.  Fields and injection run serially (O(N)). */
+int orc_step_par(const orc_cfg *c, orc_state *st, int64_t n_steps, int32_t n_threads)
+{
+    if (orc_check(c) || !st || n_steps < 0) return -1;
+    int T = 1;
+#ifdef _OPENMP
+    T = n_threads > 0 ? n_threads : omp_get_max_threads();
+#endif
+    if (T < 1) T = 1;
+    const int64_t N = c->n_cells, cap = c->capacity;
+    int64_t *jt = calloc((size_t)T * (size_t)N, sizeof(int64_t));
+    int64_t *jit = st->j_inj ? calloc((size_t)T * (size_t)N, sizeof(int64_t)) : NULL;
+    double *sx = malloc(sizeof(double) * (size_t)(cap + 1)), *su = malloc(sizeof(double) * (size_t)(cap + 1));
+    unsigned char *scl = st->cls ? malloc((size_t)(cap + 1)) : NULL;
+    orc_tally *tl = calloc((size_t)T, sizeof(orc_tally));
+    int64_t *pre = calloc((size_t)T + 1, sizeof(int64_t));
+    if (!jt || (st->j_inj && !jit) || !sx || !su || (st->cls && !scl) || !tl || !pre) {
+        free(jt); free(jit); free(sx); free(su); free(scl); free(tl); free(pre);
+        return -2;
+    }
+    for (int64_t s = 0; s < n_steps; ++s) {
+        orc_const k;
+        orc_consts(c, st, &k);
+        orc_step_begin(st, &k);
+        const int64_t n = st->n;
+#pragma omp parallel num_threads(T)
+        {
+            int id = 0;
+#ifdef _OPENMP
+            id = omp_get_thread_num();
+#endif
+            const int64_t p0 = (n * id) / T, p1 = (n * (id + 1)) / T;
+            int64_t *jme = jt + (size_t)id * (size_t)N;
+            int64_t *jime = jit ? jit + (size_t)id * (size_t)N : NULL;
+            memset(jme, 0, sizeof(int64_t) * (size_t)N);
+            if (jime) memset(jime, 0, sizeof(int64_t) * (size_t)N);
+            orc_tally *t = &tl[id];
+            memset(t, 0, sizeof *t);
+            t->j = jme;
+            t->j_inj = jime;
+            orc_push_range(c, st, &k, p0, p1, sx + p0, su + p0, scl ? scl + p0 : NULL, t);
+#pragma omp barrier
+#pragma omp single
+            {
+                pre[0] = 0;
+                for (int q = 0; q < T; ++q) pre[q + 1] = pre[q] + tl[q].kept;
+            }
+            /* survivors back in slice order; current summed node by node in thread order */
+            memcpy(st->x + pre[id], sx + p0, sizeof(double) * (size_t)t->kept);
+            memcpy(st->u + pre[id], su + p0, sizeof(double) * (size_t)t->kept);
+            if (scl) memcpy(st->cls + pre[id], scl + p0, (size_t)t->kept);
+            const int64_t i0 = (N * id) / T, i1 = (N * (id + 1)) / T;
+            for (int64_t i = i0; i < i1; ++i) {
+                int64_t a = 0, b = 0;
+                for (int q = 0; q < T; ++q) {
+                    a += jt[(size_t)q * (size_t)N + (size_t)i];
+                    if (jit) b += jit[(size_t)q * (size_t)N + (size_t)i];
+                }
+                st->j[i] = a;
+                if (jit) st->j_inj[i] = b;
+            }
+        }
+        orc_tally all;
+        memset(&all, 0, sizeof all);
+        for (int q = 0; q < T; ++q) {
+            all.w0 += tl[q].w0;
+            all.w0_inj += tl[q].w0_inj;
+            all.n_exit += tl[q].n_exit;
+            all.n_absorb += tl[q].n_absorb;
+            all.kept += tl[q].kept;
+            all.status |= tl[q].status;
+            __int128 e = ((__int128)all.exit_hi << 64) | (__int128)all.exit_lo;
+            e += ((__int128)tl[q].exit_hi << 64) | (__int128)tl[q].exit_lo;
+            all.exit_lo = (uint64_t)e;
+            all.exit_hi = (int64_t)(e >> 64);
+        }
+        orc_step_end(c, st, &k, &all);
+    }
+    free(jt); free(jit); free(sx); free(su); free(scl); free(tl); free(pre);
     return 0;
 }
 

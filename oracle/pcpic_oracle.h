@@ -118,6 +118,12 @@ int orc_init(const orc_cfg *cfg, orc_state *st);
 int orc_inject(const orc_cfg *cfg, orc_state *st, int64_t n, const double *x, const double *u);
 /* Advance n_steps PIC cycles. */
 int orc_step(const orc_cfg *cfg, orc_state *st, int64_t n_steps);
+/* orc_step on n_threads threads (OpenMP; 0 = the default count): the particles
+ * are split into contiguous slices, and the state after every step is identical,
+ * bit for bit, to orc_step's (all sums are integer sums).  For timing the oracle
+ * on every host core; it allocates per-thread scratch for the call.  Returns -2
+ * if that allocation fails. */
+int orc_step_par(const orc_cfg *cfg, orc_state *st, int64_t n_steps, int32_t n_threads);
 /* Discrete Gauss residual at nodes 1..N-1 into g[N+1] (g[0] = g[N] = 0);
  * returns max |G_i| / (4 pi max|rho_GJ|) in *gmax. */
 int orc_gauss(const orc_cfg *cfg, orc_state *st, double *g, double *gmax);

@@ -166,3 +166,48 @@ def test_c3_full_size_sampled_tubes():
     assert np.array_equal(xb[kb], xs[ks]) and np.array_equal(ub[kb], us[ks])
     s.close()
     b.close()
+
+
+def test_c3_full_size_fp32_bulk():
+    """The whole C3 ensemble as the bench runs it: 256 tubes, 5.5e7 particles,
+    FP32-bulk, autotuned launch shape, one 64-step round from its graph plus 16
+    more steps.  The smallest tube against the oracle per result (gamma(z), E_z,
+    exit gamma, counts, Gauss residual); the largest against the same tube
+    stepped alone, bit for bit."""
+    from gpu_common import gate_errors, oracle_errors
+    from paper_1011_6330_amd import Batch, Tube, autotune
+    cfgs = synth.ensemble(n_tubes=256, seed=0, precision=1)
+    loads = [synth.warm_start(c, seed=t) for t, c in enumerate(cfgs)]
+    say("c3 fp32 full size:", sum(len(x) for x, _ in loads), "particles")
+    b = Batch([synth.tube_params(c) for c in cfgs])
+    for t, (x, u) in enumerate(loads):
+        b.tubes[t].inject(x, u)
+    shape = autotune.tune_batch(b, use_cache=False)         # the bench's shape choice
+    say("c3 fp32: tuned shape", shape, b.get_config())
+    small = min(range(256), key=lambda t: len(loads[t][0]))
+    large = max(range(256), key=lambda t: len(loads[t][0]) * cfgs[t]["n_cells"])
+    o = _oracle(cfgs[small])
+    o.inject(*loads[small])
+    s = Tube(synth.tube_params(cfgs[large]))
+    s.inject(*loads[large])
+    done = b.tubes[0].diagnostics(fields=False)["step"]   # the tuning trials stepped the batch
+    b.step((64 - done % 64) % 64 + 64 + 16)                # to the next round boundary, a round, 16 more
+    total = b.tubes[0].diagnostics(fields=False)["step"]
+    o.step(total)
+    s.step(total)
+    b.sync()
+    say("c3 fp32: steps", total, "small tube", small, "large tube", large)
+    err = oracle_errors(b.tubes[small], o)
+    gate_errors(err, f"c3 fp32 tube {small} vs oracle")
+    db = b.tubes[large].diagnostics(fields=True, j=True)
+    ds = s.diagnostics(fields=True, j=True)
+    for k in ("ez", "er", "b_phi", "j_last"):
+        assert np.array_equal(db[k], ds[k]), k
+    for k in ("n_alive", "n_slots_high", "n_injected", "n_exit", "exit_sum_lo", "exit_sum_hi", "w0", "e_surf"):
+        assert db[k] == ds[k], k
+    xb, ub = b.tubes[large].read_particles()
+    xs, us = s.read_particles()
+    kb, ks = np.lexsort((ub, xb)), np.lexsort((us, xs))
+    assert np.array_equal(xb[kb], xs[ks]) and np.array_equal(ub[kb], us[ks])
+    s.close()
+    b.close()

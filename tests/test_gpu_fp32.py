@@ -7,18 +7,15 @@ difference of cumulative weights.  The error against the oracle is stated per
 result on the same seeded input:
 
   * gamma(z): per-bin mean gamma of bins holding more than 20 particles,
-    relative, gate GAMMA_TOL (1e-4);
-  * E_z(z): normwise relative, gate EZ_TOL;
+    relative, gate 1e-4;
+  * E_z(z): normwise relative, gate 1e-5;
   * exit gamma: mean gamma of the electrons that left through z = L, relative,
-    gate EXIT_TOL;
-  * the particle counts (alive, injected, exited) within COUNT_SLACK particles
-    or COUNT_TOL relative, whichever is larger: the injection count is the floor
-    of E_surf / (4 pi q_m), and a rounding-level change of E_surf flips it by
-    one now and then; the Gauss-deficit rule pays the difference back on the
-    next steps, so the totals stay within a couple of particles;
-  * the Gauss residual (eq. 2, evaluated in f64 on the GPU) within
-    GAUSS_FACTOR of the oracle's own residual on the same step: both come only
-    from rounding in the field accumulation, the deposited charge being exact.
+    gate 1e-4;
+  * the particle counts (alive, injected, exited) within 2 particles or 1e-3
+    relative (the injection count is a floor of the surface field);
+  * the Gauss residual within 4x of the oracle's own residual on the same step.
+
+(The gates and the error measures live in gpu_common.py.)
 
 What stays exact in f32: the discrete Gauss law (eq. 2) with the deposited
 charge (the current is a difference of the same integer weights the residual
@@ -28,63 +25,23 @@ whose kicks are exact binary fractions.
 import numpy as np
 import pytest
 
-from gpu_common import say
+from gpu_common import (GAMMA_TOL, fp32_pair, gate_errors, oracle_errors, run_errors,  # noqa: F401
+                        say)
 from paper_1011_6330_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-GAMMA_TOL = 1e-4
-EZ_TOL = 1e-5
-EXIT_TOL = 1e-4
-COUNT_TOL = 1e-3
-COUNT_SLACK = 2
-GAUSS_FACTOR = 4.0
-
 
 def _pair(cfg, x=None, u=None):
-    from oracle.oracle import OracleTube
-    from paper_1011_6330_amd import Tube
-    p = synth.tube_params(cfg)
-    g = Tube(dict(p, precision=1))
-    o = OracleTube({k: v for k, v in p.items() if k not in ("sort_every", "max_bins", "precision", "gamma_fp64")})
-    if x is not None and len(x):
-        g.inject(x, u)
-        o.inject(x, u)
-    return g, o
+    return fp32_pair(cfg, x, u)
 
 
 def _errors(g, o, nb=64):
-    from oracle.oracle import i128_to_float
-    d = g.diagnostics(n_bins=nb, fields=True, gauss=True)
-    cnt, lo, hi, _, _ = o.profile(nb)
-    om = np.array([i128_to_float(lo[k], hi[k]) / 2 ** 32 / max(cnt[k], 1) for k in range(nb)])
-    sel = (cnt > 20) & (d["prof_count"] > 20)
-    rel = np.abs(d["prof_mean"][sel] - om[sel]) / np.abs(om[sel])
-    ez = np.linalg.norm(d["ez"] - o.ez) / max(np.linalg.norm(o.ez), 1e-300)
-    c = o.counters
-    ge = d["exit_gamma_sum"] / max(d["n_exit"], 1)
-    oe = o.exit_gamma_sum() / max(c["n_exit"], 1)
-    err = dict(gamma=float(rel.max()) if rel.size else 0.0, bins=int(sel.sum()), ez=float(ez),
-               exit=abs(ge - oe) / max(oe, 1e-300) if c["n_exit"] else 0.0,
-               alive=(d["n_alive"], o.n), injected=(d["n_injected"], c["n_injected"]),
-               exited=(d["n_exit"], c["n_exit"]),
-               gauss=d["gauss_max"], gauss_oracle=o.gauss()[1], n_exit=d["n_exit"], n_high=d["n_slots_high"],
-               n_alive=d["n_alive"])
-    say("fp32 errors", {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in err.items()})
-    return err
+    return oracle_errors(g, o, nb)
 
 
 def _gate(err, what, need_exits=False):
-    assert err["gamma"] <= GAMMA_TOL, f"{what}: gamma(z) rel {err['gamma']:.3e}"
-    assert err["ez"] <= EZ_TOL, f"{what}: E_z normwise {err['ez']:.3e}"
-    assert err["exit"] <= EXIT_TOL, f"{what}: exit gamma rel {err['exit']:.3e}"
-    for k in ("alive", "injected", "exited"):
-        g, o = err[k]
-        assert abs(g - o) <= max(COUNT_SLACK, COUNT_TOL * o), f"{what}: {k} count {g} vs {o}"
-    assert err["gauss"] <= GAUSS_FACTOR * err["gauss_oracle"] + 1e-14, \
-        f"{what}: Gauss residual {err['gauss']:.3e} vs the oracle's {err['gauss_oracle']:.3e}"
-    if need_exits:
-        assert err["n_exit"] > 0
+    gate_errors(err, what, need_exits)
 
 
 def _warm_beam(N=4096, a=430.0, **over):
@@ -159,40 +116,186 @@ def test_fp32_c2_full_size():
     g.close()
 
 
-def test_fp32_c2_20000_steps_against_fp64():
-    """The full C2 run (20,000 steps) in FP32-bulk and in FP64 on the GPU (the
-    FP64 path being bit-identical to the oracle): past the first 1.25 R, gamma(z)
-    per bin within GAMMA_TOL, exit gamma within 1e-9 and the same exit count.
-    The space-charge cloud at the base is chaotic: there the two runs part by
-    ~1e-2 after 20,000 steps, as two FP64 runs do when one particle near the base
-    starts 1e-9 cells away, so the base bins are reported, not gated."""
-    import torch
+def _perturbed_near_base(x, shift=1e-9):
+    """The same load with one particle near the base moved by `shift` cells
+    (4 fixed-point units at P = 32): the particle closest to x = 0.5."""
+    xp = x.copy()
+    k = int(np.argmin(np.abs(x - 0.5)))
+    xp[k] = x[k] + shift
+    return xp
 
+
+def test_fp32_c2_20000_steps_against_fp64():
+    """The full C2 run (20,000 steps) in FP32-bulk (B), in FP64 (A, the reference:
+    the FP64 path is bit-identical to the oracle) and in FP64 from a load in which
+    one particle near the base starts 1e-9 cells away (P, the control).
+
+    * Step 1,000, before the space-charge cloud at the base mixes: every bin of
+      gamma(z) within 1e-4, E_z within 1e-5, exit gamma within 1e-4, counts as in
+      the per-result gates.
+    * Steps 5,000 and 20,000: the cloud is chaotic, and B parts from A there no
+      more than the control does, within a factor 3 (gamma(z) of the base bins
+      below 1.25 R and E_z normwise); the control itself parts by more than 1e-4,
+      which is what makes those bins a property of the dynamics, not of the
+      precision.  Past 1.25 R gamma(z) stays within 1e-4, exit gamma within 1e-9,
+      and the exit count is the same.
+    """
     from paper_1011_6330_amd import Tube
     cfg = synth.preset("c2")
     x, u = synth.warm_start(cfg)
     nb = 64
+    tubes = {}
+    for key, prec, xx in (("A", 0, x), ("P", 0, _perturbed_near_base(x)), ("B", 1, x)):
+        t = Tube(dict(synth.tube_params(cfg), precision=prec))
+        t.inject(xx, u)
+        tubes[key] = t
+    del x, u
+    away = np.arange(nb) >= 8                        # bins from z = 1.25 R on
+    done = 0
+    for horizon in (1000, 5000, 20000):
+        for t in tubes.values():
+            t.step(horizon - done)
+        done = horizon
+        d = {k: t.diagnostics(n_bins=nb, fields=True) for k, t in tubes.items()}
+        ba = run_errors(d["A"], d["B"])                   # FP32-bulk against FP64
+        pa = run_errors(d["A"], d["P"])                   # the control against FP64
+        ba_base = run_errors(d["A"], d["B"], bins=~away)
+        pa_base = run_errors(d["A"], d["P"], bins=~away)
+        ba_away = run_errors(d["A"], d["B"], bins=away)
+        say(f"c2 step {horizon}: fp32 vs fp64 gamma(z) base {ba_base['gamma']:.2e} away {ba_away['gamma']:.2e} "
+            f"E_z {ba['ez']:.2e} exit {ba['exit']:.2e} exits {ba['exited']}; control base {pa_base['gamma']:.2e} "
+            f"E_z {pa['ez']:.2e}; injected {ba['injected']} control {pa['injected'][0]}")
+        if horizon == 1000:
+            gate_errors(dict(ba, gauss=0.0, gauss_oracle=0.0), "c2 fp32 vs fp64 step 1000", need_exits=True,
+                        gauss=False)
+            assert ba["bins"] >= 60
+        else:
+            assert pa_base["gamma"] > 1e-4, "the control did not part at the base"
+            assert ba_base["gamma"] <= 3.0 * pa_base["gamma"], \
+                f"step {horizon}: base bins {ba_base['gamma']:.3e} vs control {pa_base['gamma']:.3e}"
+            assert ba["ez"] <= 3.0 * pa["ez"], f"step {horizon}: E_z {ba['ez']:.3e} vs control {pa['ez']:.3e}"
+            assert ba_away["bins"] >= 48
+            assert ba_away["gamma"] <= GAMMA_TOL
+            assert ba["exit"] <= 1e-9
+            assert ba["exited"][0] == ba["exited"][1]
+    for t in tubes.values():
+        t.close()
+
+
+def test_fp32_c5_against_fp64_200_steps():
+    """The large tube (2^20 cells, L = 100R, 2.5e8 particles, 99% of them in the
+    f64-momentum stream) over the benchmark's 200 steps, FP32-bulk against FP64
+    on the GPU (the FP64 path being bit-identical to the oracle at this size):
+    gamma(z), E_z and exit gamma at the per-result gates, the same counts."""
+    import torch
+
+    import bench
+    from paper_1011_6330_amd import Tube
+    cfg = synth.preset("c5")
+    say("fp32 vs fp64 c5: warm start")
+    x, u = synth.warm_start(cfg)
+    nb = 256
     out = []
-    for prec in (0, 1):
+    for prec, shape in ((0, bench.DEFAULT_PUSH), (1, bench.DEFAULT_PUSH32)):
+        say("c5 precision", prec, "200 steps")
         t = Tube(dict(synth.tube_params(cfg), precision=prec))
         t.inject(x, u)
-        t.step(20000)
+        t.set_push_config(*bench.shape_of(shape))
+        t.step(200)
         out.append(t.diagnostics(n_bins=nb, fields=True))
         t.close()
+        del t
         torch.cuda.empty_cache()
+    del x, u
     a, b = out
-    sel = (a["prof_count"] > 20) & (b["prof_count"] > 20)
-    with np.errstate(divide="ignore", invalid="ignore"):   # empty bins are not selected
-        rel = np.abs(b["prof_mean"] - a["prof_mean"]) / np.abs(a["prof_mean"])
-    away = sel & (np.arange(nb) >= 8)                 # bins from z = 1.25 R on
-    ea = a["exit_gamma_sum"] / a["n_exit"]
-    eb = b["exit_gamma_sum"] / b["n_exit"]
-    say("c2 20000 steps fp32 vs fp64: gamma(z) past 1.25R", f"{rel[away].max():.2e}", "base bins",
-        f"{rel[sel & ~away].max():.2e}", "exit gamma", f"{abs(eb - ea) / ea:.2e}", "exits", a["n_exit"], b["n_exit"])
-    assert away.sum() >= 48
-    assert rel[away].max() <= GAMMA_TOL
-    assert abs(eb - ea) <= 1e-9 * ea
-    assert a["n_exit"] == b["n_exit"]
+    err = run_errors(a, b)
+    say("c5 fp32 vs fp64 after 200 steps:", {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in err.items()},
+        "high stream", b["n_slots_high"])
+    gate_errors(dict(err, gauss=0.0, gauss_oracle=0.0), "c5 fp32 vs fp64 step 200", need_exits=True, gauss=False)
+    assert err["bins"] >= 250
+    assert b["n_slots_high"] > 0.9 * b["n_alive"]
+
+
+@pytest.mark.parametrize("ppc,sub", [(520.0, 4), (250.0, 3)])
+def test_fp32_sort_width_per_result(ppc, sub):
+    """FP32-bulk across sorts at the sub-cell key widths of the full-size tubes
+    (2^4 bins per cell from ppc 257 on, as in C2; 2^3 as in C4/C5): a shuffled
+    warm beam whose fast part lives in the f64-momentum stream (threshold
+    gamma = 1000), sorted every 16 steps.  Right after each sort both streams are
+    in key order (key = cell * 2^sub + floor(offset * 2^sub)) and each particle
+    sits in the stream its momentum selects; every result per result against
+    the oracle at steps 16, 32 and 40."""
+    N = 4096
+    cfg = _warm_beam(N=N, ppc=ppc, warm=int(ppc * N), capacity=int(ppc * N * 1.3), gamma_fp64=1000.0)
+    x, u = synth.warm_start(cfg)
+    perm = np.random.default_rng(11).permutation(len(x))
+    x, u = x[perm], u[perm]
+    say("fp32 sort width 2^%d:" % sub, len(x), "particles")
+    g, o = _pair(cfg, x, u)
+    del x, u
+    u_hi = np.sqrt(1000.0 ** 2 - 1.0)
+    done = 0
+    for h in (16, 32, 40):
+        g.step(h - done)
+        o.step(h - done)
+        done = h
+        err = _errors(g, o)
+        _gate(err, f"sort width 2^{sub} step {h}")
+        if h % 16 == 0:
+            d = g.diagnostics(fields=False)
+            assert d["n_slots"] == d["n_alive"]             # compacted
+            px, pu = g.read_particles()
+            n_hi = d["n_slots_high"]
+            n_lo = len(px) - n_hi
+            assert 0 < n_hi < len(px), "both streams populated"
+            key = np.floor(px * 2 ** sub)
+            assert np.all(np.diff(key[:n_lo]) >= 0) and np.all(np.diff(key[n_lo:]) >= 0)
+            assert np.all(np.abs(pu[:n_lo]) < u_hi) and np.all(np.abs(pu[n_lo:]) >= u_hi)
+    g.close()
+
+
+def test_fp32_capacity_clip_with_sort():
+    """SCLF injection against a full capacity in FP32-bulk: the high stream holds
+    most of the slots, the injection is clipped to what both streams together
+    leave free (PIC_ST_CAPACITY latched), and after every step and every sort
+    the two streams together stay within the capacity."""
+    from paper_1011_6330_amd import Tube
+    cap = 1000
+    cfg = dict(synth.preset("c1"), capacity=cap, gamma_fp64=50.0, sort_every=8)
+    t = Tube(dict(synth.tube_params(cfg), precision=1))
+    t.inject(np.linspace(600.0, 1000.0, 960), np.full(960, 200.0))   # high stream, moving up
+    d = t.diagnostics(fields=False)
+    assert d["n_slots_high"] == 960
+    exited = 0
+    for s in range(120):
+        t.step(1)
+        d = t.diagnostics(fields=False, raise_on_status=False)
+        assert d["n_slots"] <= cap, (s, d["n_slots"])
+        if s == 0:
+            assert d["status"] & 1 and d["n_slots"] == cap              # clipped to the 40 free slots
+        exited = d["n_exit"]
+    assert d["status"] & 1                                              # PIC_ST_CAPACITY stays latched
+    assert exited > 0 and d["n_injected"] > 40                          # exits made room; refilled
+    t.close()
+
+
+def test_fp32_load_rejects_more_slots_than_capacity():
+    """pic_load counts both streams against the capacity of the target tube."""
+    from paper_1011_6330_amd import PicError, Tube
+    cfg = dict(synth.preset("c1"), capacity=1000, flags=1 | 2, gamma_fp64=50.0)
+    a = Tube(dict(synth.tube_params(cfg), precision=1))
+    a.inject(np.linspace(1.0, 500.0, 500), np.full(500, 2.0))
+    a.inject(np.linspace(1.0, 500.0, 400), np.full(400, 200.0))
+    state = a.save()
+    b = Tube(dict(synth.tube_params(dict(cfg, capacity=899)), precision=1))   # 500 + 400 slots do not fit
+    with pytest.raises(PicError) as e:
+        b.load(state)
+    assert e.value.code == -3
+    c = Tube(dict(synth.tube_params(dict(cfg, capacity=900)), precision=1))   # exactly fits
+    c.load(state)
+    assert c.diagnostics(fields=False)["n_alive"] == 900
+    for t in (a, b, c):
+        t.close()
 
 
 def test_fp32_capacity_counts_both_streams():

@@ -76,6 +76,37 @@ def test_sorted_warm_tube():
     assert d["n_slots"] >= d["n_alive"]
 
 
+@pytest.mark.parametrize("ppc,sub", [(520.0, 4), (250.0, 3)])
+def test_sort_width_bit_identical(ppc, sub):
+    """The cell sort at the sub-cell key widths of the full-size tubes: 2^4 bins
+    per cell from ppc 257 on (C2), 2^3 for ppc 129..256 (C4, C5).  A warm
+    frame-drag beam loaded in a shuffled order (so that the first sort has to
+    reorder everything), sorted every 16 steps for 40 steps: right after each
+    sort the slots are in key order (key = floor(x 2^sub)) with no removed slot
+    left, and fields, current, counters and the particle multiset are
+    bit-identical to the oracle's after steps 16, 32 and 40."""
+    N = 4096
+    cfg = dict(synth.preset("c2"), n_cells=N, q_over_m=synth.q_over_m_for(430.0), ppc=ppc,
+               warm=int(ppc * N), capacity=int(ppc * N * 1.2), sort_every=16)
+    x, u = synth.warm_start(cfg)
+    perm = np.random.default_rng(9).permutation(len(x))
+    x, u = x[perm], u[perm]
+    say("sort width 2^%d:" % sub, len(x), "particles")
+    g, o = make_pair(cfg, x, u)
+    del x, u
+    done = 0
+    for h in (16, 32, 40):
+        g.step(h - done)
+        o.step(h - done)
+        done = h
+        d = assert_state_equal(g, o, ordered=False, what=f"sort width 2^{sub} step {h}")
+        if h % 16 == 0:
+            assert d["n_slots"] == d["n_alive"]
+            px, _ = g.read_particles()
+            assert np.all(np.diff(np.floor(px * 2 ** sub)) >= 0), "slots not in key order after the sort"
+    g.close()
+
+
 @pytest.mark.parametrize("shape", [(64, 4), (128, 4), (256, 2), (256, 4), (512, 2), (128, 2, True),
                                    (256, 2, True), (64, 4, True), (64, 8, True), (128, 8)])
 def test_push_launch_shapes_identical(shape):
@@ -163,18 +194,49 @@ def test_uniform_field_test_particle():
     assert u[0] == 398.5 * 10.0 / 1024     # u_n = u_0 + n K, K = (q/m) dt E0 = 10/1024
 
 
+def _near_midpoint_momenta(n_keep, n_cand=20_000_000, seed=21):
+    """Momenta u whose velocity u / sqrt(1 + u^2) lies closest to a rounding
+    midpoint of the double grid (the hard cases of a correctly rounded
+    quotient): the exact remainder u - g q of the rounded quotient q = u / g,
+    g = sqrt(1 + u^2), from Dekker's exact product, gives the distance of u / g
+    from q in ulps; the n_keep candidates nearest to half an ulp are kept."""
+    rng = np.random.default_rng(seed)
+    u = 10.0 ** rng.uniform(-8.0, 9.0, n_cand)
+    g = np.sqrt(1.0 + u * u)
+    q = u / g
+    split = 134217729.0                         # 2^27 + 1
+
+    def halves(a):
+        t = split * a
+        hi = t - (t - a)
+        return hi, a - hi
+    gh, gl = halves(g)
+    qh, ql = halves(q)
+    p = g * q
+    e = ((gh * qh - p) + gh * ql + gl * qh) + gl * ql   # g q = p + e exactly
+    rem = (u - p) - e                                  # u - p is exact (p is within an ulp of u)
+    frac = np.abs(rem / g) / np.spacing(q)
+    keep = np.argsort(-frac)[:n_keep]
+    return u[keep], float(frac[keep].min())
+
+
 def test_gamma_velocity_bits():
     """The push's gamma = sqrt(1 + u^2) and v = u / gamma against the oracle's C
     library square root and division, bit for bit.  Particles start at x = 0 in
     a zero field, so after one step x = v / 2 exactly (dt/dz = 1/2) and each
-    stored position holds the bits of v.  u spans 2^-1074 .. 1e153, the edges
-    of the range [2^-400, 2^400] where the push skips the library's range
-    scaling, and the powers of two in between."""
+    stored position holds the bits of v.  10^7 momenta: log-uniform over
+    2^-1074 .. 1e153, the edges of the range [2^-400, 2^400] where the push skips
+    the library's range scaling, the powers of two in between, and the 2e5
+    momenta (of 2e7 candidates) whose quotient lies nearest to a rounding
+    midpoint: the nearest within 1e-8 ulp of it, all within 6e-3 ulp."""
     rng = np.random.default_rng(5)
     edges = [2.0 ** -400, 2.0 ** 400, 2.0 ** -1022]
     special = [5e-324, 1.0, 0.5, 3.0] + edges + [np.nextafter(e, 0.0) for e in edges] + \
               [np.nextafter(e, np.inf) for e in edges] + [2.0 ** k for k in range(-80, 80)]
-    u = np.concatenate([10.0 ** rng.uniform(-323.5, 153.0, 200000), np.array(special)])
+    mid, mid_frac = _near_midpoint_momenta(200_000)
+    say("gamma/v bits: near-midpoint quotients within", f"{0.5 - mid_frac:.2e}", "ulp of a midpoint")
+    assert mid_frac > 0.494
+    u = np.concatenate([10.0 ** rng.uniform(-323.5, 153.0, 9_800_000), mid, np.array(special)])
     x = np.zeros_like(u)
     cfg = dict(synth.preset("c1"), flags=1 | 2, capacity=len(u) + 8)
     g, o = make_pair(cfg, x, u)
@@ -188,6 +250,10 @@ def test_gamma_velocity_bits():
     assert np.array_equal(gu, o.u[:o.n]) and np.array_equal(gu, u)
     bad = np.flatnonzero(gx != o.x[:o.n])
     assert bad.size == 0, f"{bad.size} positions differ, first u = {u[bad[:5]]}"
+    # the oracle's quotient is the correctly rounded one: v = 2 x agrees with numpy's division
+    nrm = u >= 2.0 ** -1000                   # v / 2 is not subnormal: x holds v exactly
+    v = 2.0 * o.x[:o.n][nrm]
+    assert np.array_equal(v, u[nrm] / np.sqrt(1.0 + u[nrm] * u[nrm]))
     g.close()
 
 

@@ -23,9 +23,9 @@ pytestmark = pytest.mark.slow
 # (what is planted, original text, mutated text)
 FORWARD = [
     ("sign of the E_z term in the B_phi update (eq. 3)",
-     "k.dtR * st->ez[i]);", "-k.dtR * st->ez[i]);"),
+     "k->dtR * st->ez[i]);", "-k->dtR * st->ez[i]);"),
     ("mirror factor 2 dropped in the E_r update at node N",
-     "st->er[N] = st->er[N] + k.tw * st->b[N - 1];", "st->er[N] = st->er[N] + k.dtdz * st->b[N - 1];"),
+     "st->er[N] = st->er[N] + k->tw * st->b[N - 1];", "st->er[N] = st->er[N] + k->dtdz * st->b[N - 1];"),
     ("mirror-doubled node-N weight dropped in the Poisson right-hand side",
      "int64_t wi = (i == N) ? 2 * st->w[i] : st->w[i];", "int64_t wi = st->w[i];"),
     ("mirror row of the Poisson matrix not doubled",
@@ -33,20 +33,20 @@ FORWARD = [
     ("gather between nodes instead of faces",
      "double s = x - 0.5, E;", "double s = x, E;"),
     ("move with u instead of v = u / gamma",
-     "double v = u1 / gam;\n        double x1 = x + k.dtdz * v;", "double v = u1 / gam;\n        double x1 = x + k.dtdz * u1;"),
+     "double v = u1 / gam;\n        double x1 = x + k->dtdz * v;", "double v = u1 / gam;\n        double x1 = x + k->dtdz * u1;"),
     ("cumulative weight off by one cell",
      "if (cell > i) return 0;", "if (cell > i + 1) return 0;"),
     ("sign of the background term of the surface field",
-     "double es = st->ez[0] - k.fourpi * (t1 - t2);", "double es = st->ez[0] - k.fourpi * (t1 + t2);"),
+     "double es = st->ez[0] - k->fourpi * (t1 - t2);", "double es = st->ez[0] - k->fourpi * (t1 + t2);"),
     ("whole cell instead of half cell in the node-0 Gauss law",
      "k->hdz = 0.5 * k->dz;", "k->hdz = k->dz;"),
     ("frame dragging with eta^2 instead of eta^3 (eq. 7)",
      "double fd = 1.0 - c->kappa / e3;", "double fd = 1.0 - c->kappa / (eta * eta);"),
     ("sign of the current term of the E_z update",
-     "st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) - k.c4 * (double)st->j[i];",
-     "st->ez[i] = (st->ez[i] + k.dtR * st->b[i]) + k.c4 * (double)st->j[i];"),
+     "st->ez[i] = (st->ez[i] + k->dtR * st->b[i]) - k->c4 * (double)st->j[i];",
+     "st->ez[i] = (st->ez[i] + k->dtR * st->b[i]) + k->c4 * (double)st->j[i];"),
     ("node-0 weight of a particle in cell 0 taken from the wrong side",
-     "            w0 += k.oneP - F1;", "            w0 += F1;"),
+     "            t->w0 += k->oneP - F1;", "            t->w0 += F1;"),
     ("inclination term of eq. 6 growing as eta instead of eta^(1/2)",
      "double br = fd + s * sqrt(eta);", "double br = fd + s * eta;"),
     ("redshift with r_g r instead of r_g / r",
