@@ -18,18 +18,22 @@ sort on the tube's stream.  Prints one JSON line:
                  profiles/k_push_f64_c2_hbm_traffic.txt when that summary was
                  taken on the current push sources and launch shape (else null)
   fp32_bulk      the same tube with the FP32-bulk push (f32 momentum below
-                 gamma = 1e6, f64 above), with its own roofline; low_gamma: the
+                 gamma = 1e6, f64 above), with its own roofline (traffic from
+                 profiles/k_push_f32_c2_hbm_traffic.txt); low_gamma: the
                  same geometry with a beam below 1e6, FP64 against FP32-bulk
   large_tube     the 2^20-cell tube with 2.5e8 particles in FP64 and FP32-bulk,
                  with the Gauss residual at the end
   ensemble       256 tubes of uneven size, one graph launch per round (FP32-bulk;
-                 fp64: the same tubes in FP64)
+                 fp64: the same tubes in FP64), with the roofline of the batched
+                 push (particle streams plus the kick read and current write
+                 per cell; traffic from profiles/k_batch_push_c3_hbm_traffic.txt)
   plausibility   flat-space SCLF over a = omega_p R / c (sec. 3, Table 2): gamma
                  behind the front and the oscillation amplitude per a
   full_step      the whole step's rate against the push's 32 B per particle-step
   diagnostics    one pic_diagnostics call (fields, Gauss residual, profile)
   small_tubes    C1 (and C4) as time per step: cache-resident, latency-bound
-  cpu_baseline   the single-threaded FP64 oracle on the same tube
+  cpu_baseline   the FP64 oracle on the same tube on every usable host core
+                 (threaded oracle step), with the single-threaded rate beside it
 The roofline also carries the rate of torch's device copy and of the library's
 plain 16-byte nontemporal copy (the achievable stream rate, pic_stream_copy).
 """
@@ -47,6 +51,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 B_FP64 = 32                    # x, u (f64) read + written per particle-step
 B_F32_LOW = 24                 # cell, offset, u (f32)
 B_F32_HIGH = 32                # cell, offset (4 B each), u (f64)
+B_GRID_PUSH = 16               # per cell and push: the kick (E_z) read, the current written
 DEFAULT_PUSH = "128:2:nt"      # FP64 push launch shape: threads, slots per thread, nontemporal
 DEFAULT_PUSH32 = "128:4:nt"    # FP32-bulk push launch shape
 
@@ -124,34 +129,43 @@ def roofline_of(bytes_per_launch, tim, kernel):
             "bytes_per_launch": bytes_per_launch}
 
 
-PUSH_SOURCES = ("paper_1011_6330_amd/csrc/k_push.hip", "paper_1011_6330_amd/csrc/push_body.h",
-                "paper_1011_6330_amd/csrc/push_common.h", "paper_1011_6330_amd/csrc/wave.h")
+CSRC = "paper_1011_6330_amd/csrc/"
+PUSH_SOURCES = tuple(CSRC + f for f in ("k_push.hip", "push_body.h", "push_common.h", "wave.h"))
+PUSH32_SOURCES = tuple(CSRC + f for f in ("k_push32.hip", "push_body.h", "push_common.h", "wave.h"))
+BATCH_SOURCES = tuple(CSRC + f for f in ("k_batch.hip", "push_body.h", "push_common.h", "wave.h"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_f64_c2_hbm_traffic.txt")
+TRAFFIC32_FILE = os.path.join(ROOT, "profiles", "k_push_f32_c2_hbm_traffic.txt")
+TRAFFIC_BATCH_FILE = os.path.join(ROOT, "profiles", "k_batch_push_c3_hbm_traffic.txt")
 
 
-def push_source_hash():
+def push_source_hash(sources=PUSH_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for rel in PUSH_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(shape):
-    """HBM bytes per launch of the FP64 push from the committed counter summary,
-    if it was taken on the current push sources and this launch shape; else None."""
+def shape_text(shape):
+    return f"{shape[0]}:{shape[1]}:{'nt' if shape[2] else 'plain'}" if shape else None
+
+
+def measured_traffic(shape, path=None, sources=PUSH_SOURCES, key="traffic_bytes_per_launch"):
+    """HBM bytes per launch of a kernel from a committed counter summary (default:
+    the FP64 push's), if it was taken on the current kernel sources and this
+    launch shape; else None."""
+    path = path or TRAFFIC_FILE
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
-    want = f"{shape[0]}:{shape[1]}:{'nt' if shape[2] else 'plain'}" if shape else None
-    if kv.get("source_sha256") != push_source_hash() or kv.get("push_shape") != want:
+    if kv.get("source_sha256") != push_source_hash(sources) or kv.get("push_shape") != shape_text(shape):
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
@@ -175,7 +189,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 2^20-cell, 2.5e8-particle tube")
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--no-small", action="store_true", help="skip the C1 time-per-step leg")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="seconds per CPU-baseline leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -237,6 +251,7 @@ def main():
         fhigh = 0.5 * (f0["n_slots_high"] + f1["n_slots_high"])
         froof = roofline_of(B_F32_LOW * max(ftim["alive"] - ftim["alive_high"], 0.0) + B_F32_HIGH * ftim["alive_high"],
                             ftim, "k_push_f32")
+        froof["traffic"] = measured_traffic(fshape, TRAFFIC32_FILE, PUSH32_SOURCES)
         result["fp32_bulk"] = {"value": falive * args.steps / fel, "unit": "particle-steps/s",
                                "ms_per_step": fel / args.steps * 1e3, "dtype": "f32+f64",
                                "high_stream_fraction": fhigh / max(falive, 1.0), "push_shape": list(fshape),
@@ -274,7 +289,8 @@ def main():
     if not args.no_ensemble:
         result["ensemble"] = run_ensemble(args.ensemble_steps, precision=1)
         e64 = run_ensemble(args.ensemble_steps, precision=0)
-        result["ensemble"]["fp64"] = {k: e64[k] for k in ("value", "ms_per_step", "launch", "dtype")}
+        result["ensemble"]["fp64"] = {k: e64[k] for k in ("value", "ms_per_step", "launch", "dtype", "roofline",
+                                                          "breakdown_ms_per_step")}
 
     if not args.no_adjoint:
         adj = run_adjoint_leg(args.adjoint_steps)
@@ -351,6 +367,9 @@ def run_large(steps, push, push32):
 
 
 def run_ensemble(steps, precision=1):
+    """C3: 256 tubes of uneven size, autotuned, `steps` plain steps (rounds replayed
+    from their graphs), then `steps` more with HIP events around every batched
+    kernel for the roofline of the batched push."""
     import torch
 
     from paper_1011_6330_amd import Batch, autotune, synth
@@ -370,17 +389,41 @@ def run_ensemble(steps, precision=1):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     b.sync()
-    n1 = sum(t.diagnostics(fields=False)["n_alive"] for t in b.tubes)
+    d1 = [t.diagnostics(fields=False) for t in b.tubes]
+    tim = b.step_timed(steps)
+    d2 = [t.diagnostics(fields=False) for t in b.tubes]
+    n1 = sum(d["n_alive"] for d in d1)
     cfg = b.get_config()
     b.close()
     del b
     torch.cuda.empty_cache()
     alive = 0.5 * (n0 + n1)
+    cells = int(sum(c["n_cells"] for c in cfgs))
+    # algorithmic bytes of one batched push: the particle streams (as the single-tube
+    # pushes) plus, per cell, the kick (E_z) read and the current written once
+    t_alive = 0.5 * sum(a["n_alive"] + c["n_alive"] for a, c in zip(d1, d2))
+    t_high = 0.5 * sum(a["n_slots_high"] + c["n_slots_high"] for a, c in zip(d1, d2))
+    if precision:
+        pbytes = B_F32_LOW * max(t_alive - t_high, 0.0) + B_F32_HIGH * t_high
+    else:
+        pbytes = B_FP64 * t_alive
+    gbytes = B_GRID_PUSH * cells
+    kern = f"k_batch_push<{cfg['block']}, {cfg['per_thread']}, 1, {precision}>"
+    roof = roofline_of(pbytes + gbytes, tim, kern)
+    roof["particle_bytes_per_launch"] = pbytes
+    roof["grid_bytes_per_launch"] = gbytes
+    shape = (cfg["block"], cfg["per_thread"], True)
+    roof["traffic"] = measured_traffic(shape, TRAFFIC_BATCH_FILE, BATCH_SOURCES) if precision else None
+    steps_t = max(tim["push_launches"], 1)
     log(f"ensemble ({'fp32-bulk' if precision else 'fp64'}): {el / steps * 1e3:.3f} ms/step for {alive:.3g} "
-        f"particles in 256 tubes, shape {cfg}")
+        f"particles in 256 tubes, shape {cfg}; push {roof['avg_launch_us']:.1f} us ({roof['achieved']:.0f} GB/s), "
+        f"field + work list {tim['field_ms'] / steps_t * 1e3:.1f} us per step")
     return {"value": alive * steps / el, "unit": "particle-steps/s", "ms_per_step": el / steps * 1e3,
-            "tubes": 256, "cells": int(sum(c["n_cells"] for c in cfgs)), "particles": int(alive),
-            "dtype": "f32+f64" if precision else "f64", "launch": cfg, "steps": steps,
+            "tubes": 256, "cells": cells, "particles": int(alive),
+            "dtype": "f32+f64" if precision else "f64", "launch": cfg, "steps": steps, "roofline": roof,
+            "breakdown_ms_per_step": {"push": tim["push_ms"] / steps_t, "field": tim["field_ms"] / steps_t,
+                                      "sort": tim["sort_ms"] / steps_t},
+            "high_stream_fraction": t_high / max(t_alive, 1.0),
             "workload": "256 frame-dragging tubes, cells log-uniform 2048-65536, particles log-uniform 1e4-1e6, "
                         "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk (fp64: the same tubes in FP64), "
                         "one graph launch per 64-step round (steps and cell sort)"}
@@ -508,29 +551,66 @@ def run_small(steps=2000):
                    "workload": WORKLOADS["c1"]}}
 
 
+def host_cpu():
+    """nproc, the cores this process may run on, and the CPU model of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": model}
+
+
 def cpu_baseline(cfg, x, u, seconds):
-    """The oracle, as it stands, on the same warm tube for a bounded number of steps."""
+    """The oracle on the same warm tube for a bounded number of steps: on every
+    core this process may use (orc_step_par: the oracle's own steps with the
+    particles split over OpenMP threads, bit-identical to the serial oracle),
+    and single-threaded (orc_step), each for about `seconds` seconds."""
     from oracle.oracle import OracleTube
     from paper_1011_6330_amd import synth
+    host = host_cpu()
+    threads = host["usable_cores"]
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
     p = {k: v for k, v in synth.tube_params(cfg).items()
          if k not in ("sort_every", "max_bins", "precision", "gamma_fp64")}
-    o = OracleTube(p)
-    if len(x):
-        o.inject(x, u)
-    done = 0
-    ps = 0.0
-    t0 = time.perf_counter()
-    while True:
-        n = o.n
-        o.step(1)
-        ps += 0.5 * (n + o.n)
-        done += 1
-        if time.perf_counter() - t0 > seconds and done >= 2:
-            break
-    el = time.perf_counter() - t0
-    log(f"oracle: {done} steps in {el:.1f}s")
-    return {"value": ps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"the same warm tube ({int(o.n)} particles), first {done} steps, single-threaded FP64 oracle"}
+    legs = {}
+    for key, nthreads in (("all_cores", threads), ("serial", 1)):
+        o = OracleTube(p)
+        if len(x):
+            o.inject(x, u)
+        done, ps = 0, 0.0
+        t0 = time.perf_counter()
+        while True:
+            n = o.n
+            if nthreads == 1:
+                o.step(1)
+            else:
+                o.step_par(1, nthreads)
+            ps += 0.5 * (n + o.n)
+            done += 1
+            if time.perf_counter() - t0 > seconds and done >= 2:
+                break
+        el = time.perf_counter() - t0
+        legs[key] = {"value": ps / el, "steps": done, "seconds": el, "threads": nthreads}
+        log(f"oracle ({key}, {nthreads} threads): {done} steps in {el:.1f}s, {ps / el:.3g} particle-steps/s")
+        del o
+    a = legs["all_cores"]
+    return {"value": a["value"], "unit": "particle-steps/s", "cores": a["threads"], "kind": "oracle",
+            "sample": f"the same warm tube ({len(x)} particles at the start), first {a['steps']} steps, FP64 "
+                      f"oracle on {a['threads']} threads (particles split into contiguous slices, integer sums "
+                      f"in thread order: the serial oracle's state bit for bit)",
+            "serial": {"value": legs["serial"]["value"], "cores": 1, "steps": legs["serial"]["steps"],
+                       "sample": f"first {legs['serial']['steps']} steps, single-threaded FP64 oracle"},
+            "parallel_speedup": a["value"] / legs["serial"]["value"], **host}
 
 
 if __name__ == "__main__":

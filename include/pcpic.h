@@ -253,14 +253,18 @@ pic_status pic_set_push_config(pic_handle *h, int32_t block, int32_t per_thread,
  *
  * A batch holds n_tubes tubes of any sizes (each tube's parameters as for
  * pic_init; all tubes share the precision and sort_every).  pic_step on the
- * batch handle advances every tube.  Each step is two kernels over all tubes:
- * a push kernel and a field kernel over a device list of (tube, tile) work
- * items, one block per item.  No block waits for another;
+ * batch handle advances every tube.  Each step is a push kernel and a field
+ * kernel over all tubes, over device lists of (tube, tile) work items, one
+ * block per item.  No block waits for another;
  * the kernel boundary orders the phases.  Up to sort_every steps plus a batched
  * cell sort form a round, captured once in a HIP graph and replayed with one
  * launch.  A tube of a batch computes exactly what it computes when stepped
- * alone.  pic_step_timed reports the push and field kernels of a round under
- * push_ms.  pic_sync on a batch checks every tube's status. */
+ * alone.  Before each push a one-block kernel lists the push items that hold
+ * particles, so the blocks of the push grid (sized for every tube at capacity)
+ * that find no work are the last ones.  pic_step_timed on a batch reports the
+ * batched push kernels under push_ms (push_launches of them), the field kernels
+ * and the work-list kernels under field_ms, and the sorts under sort_ms.
+ * pic_sync on a batch checks every tube's status. */
 
 /* Device bytes for a batch (header + every tube's workspace), 0 if invalid. */
 size_t pic_batch_workspace_bytes(const pic_params *tubes, int32_t n_tubes);

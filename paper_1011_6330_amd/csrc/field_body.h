@@ -13,8 +13,7 @@ struct FieldArgs {
     double *ezn, *ern, *bn;         // E^{n+1}, B^{n+1/2}
     const int64_t *j;               // J^{n+1/2} of this step
     int64_t *jnext;                 // cleared for the next step
-    double *k64;
-    float *k32;                     // FP32-bulk: f32 kick array (else null)
+    float *k32;                     // FP32-bulk: f32 kick array (q/m) dt E_z (else null)
     double *X, *U;                  // FP64: current particle buffer (injection)
     int *CL;                        // FP32-bulk: low stream of the current buffer
     float *OL, *UL;
@@ -63,9 +62,7 @@ __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, 
             ez = (a.ezo[i] + c.dtR * bi) - c.c4 * (double)a.j[i];
         }
         a.ezn[i] = ez;
-        const double kk = c.qmdt * ez;
-        a.k64[i] = kk;
-        if (a.k32) a.k32[i] = (float)kk;
+        if (a.k32) a.k32[i] = (float)(c.qmdt * ez);
         if (i == 0) s_ez0 = ez;
     }
     if (tile != 0) return;

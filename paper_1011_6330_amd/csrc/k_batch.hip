@@ -25,14 +25,48 @@ namespace pcpic {
 struct BatchArgs {
     const TubeDev *tubes;
     int n_tubes;
-    const int64_t *push_pref;    // [n_tubes + 1] prefix of push tiles (at capacity)
+    int64_t *live_pref;          // [n_tubes + 1] prefix of the push items holding particles (k_batch_plan)
     const int64_t *field_pref;   // [n_tubes + 1] prefix of cell tiles
-    const int32_t *push_map;     // push tile -> tube
     const int32_t *field_map;    // cell tile -> tube
     int fb, jb, pb;              // field, current and particle buffer parities of the step
     int hist;                    // the step before a sort: the push counts its survivors' sort keys
                                  // and the injection adds the injected particles' key
+    int tile_lo, tile_hi;        // slots per push item: FP64 tiles (tile_lo = tile_hi), or the
+                                 // FP32-bulk low- and high-stream tiles
 };
+
+// The push work list of the coming step: per tube, the items that hold
+// particles (FP64: ceil(n / tile); FP32-bulk: the low stream's tiles, then the
+// high stream's), prefix-summed over the tubes into live_pref.  One block; it
+// runs between the field update (which appends injected particles) or the
+// sort and the next push, so the counts are final.  The push grid keeps its
+// capacity-sized upper bound and every block past live_pref[n_tubes] returns at
+// once: the idle blocks come last instead of between the tubes' tiles.
+__global__ __launch_bounds__(256) void k_batch_plan(BatchArgs b)
+{
+    __shared__ long long s_wave[4];
+    __shared__ long long s_carry;
+    if (threadIdx.x == 0) {
+        s_carry = 0;
+        b.live_pref[0] = 0;
+    }
+    __syncthreads();
+    for (int t0 = 0; t0 < b.n_tubes; t0 += 256) {
+        const int t = t0 + (int)threadIdx.x;
+        long long items = 0;
+        if (t < b.n_tubes) {
+            const DevCounters *ctr = generic(b.tubes[t].ctr);
+            const int64_t n_lo = ctr->n_slots, n_hi = ctr->n_slots_hi;
+            items = (n_lo + b.tile_lo - 1) / b.tile_lo + (n_hi + b.tile_hi - 1) / b.tile_hi;
+        }
+        const long long inc = block_scan_incl(items, s_wave);
+        const long long carry = s_carry;
+        if (t < b.n_tubes) b.live_pref[t + 1] = carry + inc;
+        __syncthreads();
+        if (threadIdx.x == 255) s_carry = carry + inc;
+        __syncthreads();
+    }
+}
 
 
 template <int BLOCK, int PPT, int NT, int F32>
@@ -40,16 +74,23 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
 {
     constexpr int TILE = BLOCK * (F32 ? F32_PPT_LO : PPT);
     const int64_t it = blockIdx.x;
-    if (it >= b.push_pref[b.n_tubes]) return;
+    if (it >= b.live_pref[b.n_tubes]) return;
     {
-        const int t = b.push_map[it];
+        // the tube of item it: the last t with live_pref[t] <= it (uniform, scalar loads)
+        int lo = 0, hi = b.n_tubes;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (b.live_pref[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        const int t = lo;
         const TubeDev &T = b.tubes[t];
         // the descriptor is read once, before any store, into registers
         const Consts c = T.c;
-        const int64_t local = it - b.push_pref[t];
+        const int64_t local = it - b.live_pref[t];
         if (F32) {
             Push32Args a{generic(T.cl[b.pb]), generic(T.ol[b.pb]), generic(T.ul[b.pb]), generic(T.ch[b.pb]),
-                         generic(T.oh[b.pb]), generic(T.uh[b.pb]), generic(T.k32), generic(T.k64),
+                         generic(T.oh[b.pb]), generic(T.uh[b.pb]), generic(T.k32), generic(T.ez[b.fb]),
                          (unsigned long long *)generic(T.j[b.jb]), generic(T.ctr),
                          b.hist ? (unsigned long long *)generic(T.cell_count) : nullptr, T.u_hi};
             push_item_f32<BLOCK, NT>(c, a, local);
@@ -58,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
             const int64_t n = T.ctr->n_slots;
             if (tile0 >= n) return;
             PushArgs a{generic(T.x[b.pb]), generic(T.u[b.pb]), generic(T.x[b.pb]), generic(T.u[b.pb]),
-                       generic(T.k64), (unsigned long long *)generic(T.j[b.jb]), generic(T.ctr),
+                       generic(T.ez[b.fb]), (unsigned long long *)generic(T.j[b.jb]), generic(T.ctr),
                        b.hist ? (unsigned long long *)generic(T.cell_count) : nullptr};
             push_tile_f64<BLOCK, PPT, NT>(c, a, n, tile0);
         }
@@ -77,8 +118,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_field(BatchArgs b)
         const Consts c = T.c;
         const int64_t local = it - b.field_pref[t];
         FieldArgs a{generic(T.ez[fb]), generic(T.er[fb]), generic(T.b[fb]), generic(T.ez[g]), generic(T.er[g]),
-                    generic(T.b[g]), generic(T.j[jb]), generic(T.j[jb ^ 1]), generic(T.k64),
-                    F32 ? generic(T.k32) : nullptr, F32 ? nullptr : generic(T.x[pb]),
+                    generic(T.b[g]), generic(T.j[jb]), generic(T.j[jb ^ 1]), F32 ? generic(T.k32) : nullptr, F32 ? nullptr : generic(T.x[pb]),
                     F32 ? nullptr : generic(T.u[pb]), F32 ? generic(T.cl[pb]) : nullptr,
                     F32 ? generic(T.ol[pb]) : nullptr, F32 ? generic(T.ul[pb]) : nullptr, generic(T.ctr),
                     nullptr, 0, 0, b.hist ? (unsigned long long *)generic(T.cell_count) : nullptr,
@@ -262,7 +302,6 @@ TubeDev tube_dev(pic_handle *t)
         d.b[k] = to_global(w.b[k]);
         d.j[k] = to_global(w.j[k]);
     }
-    d.k64 = to_global(w.k64);
     d.k32 = to_global(w.k32);
     d.ctr = to_global(w.ctr);
     d.cell_count = to_global(w.cell_count);
@@ -334,10 +373,13 @@ static BSortArgs bsort_args(pic_handle *h)
                      1 - t0->pbuf};
 }
 
-// nsteps steps of every tube: a push and a field kernel per step.  With
-// hist_last, the key counts are cleared first and the last step's push counts
-// the sort keys of its survivors (the sort that follows skips its histogram).
-hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last)
+// nsteps steps of every tube: the work-list, push and field kernels per step.
+// With hist_last, the key counts are cleared first and the last step's push
+// counts the sort keys of its survivors (the sort that follows skips its
+// histogram).  With ev (timed runs), four events per step are recorded around
+// the work-list, push and field kernels (ev[4s] .. ev[4s + 3], created by the
+// caller).
+hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last, hipEvent_t *ev)
 {
     const void *kp = pick_push_kernel(h);
     const void *kf = pick_field_kernel(h);
@@ -351,15 +393,23 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last)
         hipLaunchKernelGGL(k_bsort_clear, dim3((unsigned)h->batch_scan_blocks), dim3(256), 0, h->stream,
                            bsort_args(h));
     }
+    const bool f32 = t0->p.precision == PIC_FP32_BULK;
     for (int s = 0; s < nsteps; ++s) {
-        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_push_pref, h->d_field_pref, h->d_push_map, h->d_field_map,
-                    t0->fbuf ^ (s & 1),
-                    t0->jbuf ^ (s & 1), t0->pbuf, (hist_last && s == nsteps - 1) ? 1 : 0};
+        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_live_pref, h->d_field_pref, h->d_field_map,
+                    t0->fbuf ^ (s & 1), t0->jbuf ^ (s & 1), t0->pbuf, (hist_last && s == nsteps - 1) ? 1 : 0,
+                    h->batch_block * (f32 ? F32_PPT_LO : h->batch_ppt),
+                    h->batch_block * (f32 ? F32_PPT_HI : h->batch_ppt)};
         void *args[] = {&a};
-        hipError_t e = hipLaunchKernel(kp, dim3(pgrid), dim3(h->batch_block), args, 0, h->stream);
+        hipError_t e = ev ? hipEventRecord(ev[4 * s], h->stream) : hipSuccess;
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(256), 0, h->stream, a);
+        if (ev && (e = hipEventRecord(ev[4 * s + 1], h->stream)) != hipSuccess) return e;
+        e = hipLaunchKernel(kp, dim3(pgrid), dim3(h->batch_block), args, 0, h->stream);
+        if (e != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[4 * s + 2], h->stream)) != hipSuccess) return e;
         e = hipLaunchKernel(kf, dim3(fgrid), dim3(h->batch_block), args, 0, h->stream);
         if (e != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[4 * s + 3], h->stream)) != hipSuccess) return e;
     }
     return hipSuccess;
 }

@@ -208,10 +208,10 @@ __global__ __launch_bounds__(256) void k_b_from_current(Consts c, int64_t *J, do
     }
 }
 
-// E_z = -dphi/dz at faces, E_r = phi/R at nodes, B_phi = 0, J = 0, kick array.
+// E_z = -dphi/dz at faces, E_r = phi/R at nodes, B_phi = 0, J = 0, f32 kick array.
 __global__ __launch_bounds__(256) void k_fields_from_phi(Consts c, const double *phi, double *ez,
-                                                         double *er, double *b, double *k64, float *k32,
-                                                         int64_t *j0, int64_t *j1)
+                                                         double *er, double *b, float *k32, int64_t *j0,
+                                                         int64_t *j1)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i > c.N) return;
@@ -220,9 +220,7 @@ __global__ __launch_bounds__(256) void k_fields_from_phi(Consts c, const double 
         const double e = -((phi[i + 1] - phi[i]) / c.dz);
         ez[i] = e;
         b[i] = 0.0;
-        const double kk = c.qmdt * e;
-        k64[i] = kk;
-        if (k32) k32[i] = (float)kk;
+        if (k32) k32[i] = (float)(c.qmdt * e);
         j0[i] = 0;
         j1[i] = 0;
     }
@@ -239,15 +237,11 @@ __global__ __launch_bounds__(256) void k_field_inject(Consts c, FieldArgs a)
     field_tile(c, a, blockIdx.x, 256);
 }
 
-// Kick array from E_z (after the caller overwrote the fields).
-__global__ __launch_bounds__(256) void k_kick(Consts c, const double *ez, double *k64, float *k32)
+// FP32-bulk: the f32 kick array from E_z (after the caller overwrote the fields).
+__global__ __launch_bounds__(256) void k_kick(Consts c, const double *ez, float *k32)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < c.N) {
-        const double kk = c.qmdt * ez[i];
-        k64[i] = kk;
-        if (k32) k32[i] = (float)kk;
-    }
+    if (i < c.N) k32[i] = (float)(c.qmdt * ez[i]);
 }
 
 // Check appended particles in slots [base, base + n): 0 <= x < N and u finite.
@@ -313,8 +307,8 @@ hipError_t launch_fields_from_phi(pic_handle *h)
     Workspace &w = h->ws;
     const int f = h->fbuf;
     hipLaunchKernelGGL(k_fields_from_phi, dim3(grid_for(c.N + 1, 256)), dim3(256), 0, h->stream, c,
-                       w.phi, w.ez[f], w.er[f], w.b[f], w.k64,
-                       h->p.precision == PIC_FP32_BULK ? w.k32 : nullptr, w.j[0], w.j[1]);
+                       w.phi, w.ez[f], w.er[f], w.b[f], h->p.precision == PIC_FP32_BULK ? w.k32 : nullptr,
+                       w.j[0], w.j[1]);
     if (c.flags & PIC_B_STEADY_INIT) {
         // steady start: B_phi from the current the loaded beam carries (J is clear here)
         unsigned long long *J = (unsigned long long *)w.j[h->jbuf];
@@ -357,7 +351,7 @@ hipError_t launch_field_inject(pic_handle *h)
     const bool f32 = h->p.precision == PIC_FP32_BULK;
     const int b = h->pbuf;
     FieldArgs a{w.ez[f], w.er[f], w.b[f], w.ez[g], w.er[g], w.b[g], w.j[h->jbuf], w.j[1 - h->jbuf],
-                w.k64, f32 ? w.k32 : nullptr, f32 ? nullptr : w.x[b], f32 ? nullptr : w.u[b],
+                f32 ? w.k32 : nullptr, f32 ? nullptr : w.x[b], f32 ? nullptr : w.u[b],
                 f32 ? w.cl[b] : nullptr, f32 ? w.ol[b] : nullptr, f32 ? w.ul[b] : nullptr, w.ctr,
                 h->d_sched, h->sched_first, h->sched_n,
                 h->hist_on ? (unsigned long long *)w.cell_count : nullptr,
@@ -372,7 +366,7 @@ hipError_t launch_field_ptrs(pic_handle *h, const double *ezo, const double *ero
                              double *ern, double *bn, double *X, double *U)
 {
     Workspace &w = h->ws;
-    FieldArgs a{ezo, ero, bo, ezn, ern, bn, w.j[h->jbuf], w.j[1 - h->jbuf], w.k64, nullptr, X, U,
+    FieldArgs a{ezo, ero, bo, ezn, ern, bn, w.j[h->jbuf], w.j[1 - h->jbuf], nullptr, X, U,
                 nullptr, nullptr, nullptr, w.ctr, h->d_sched, h->sched_first, h->sched_n};
     hipLaunchKernelGGL(k_field_inject, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c, a);
     return hipGetLastError();
@@ -392,12 +386,6 @@ hipError_t launch_commit_append(pic_handle *h, int64_t n)
     return hipGetLastError();
 }
 
-hipError_t launch_kick_from(pic_handle *h, const double *ez)
-{
-    hipLaunchKernelGGL(k_kick, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c, ez, h->ws.k64,
-                       h->p.precision == PIC_FP32_BULK ? h->ws.k32 : nullptr);
-    return hipGetLastError();
-}
 
 hipError_t launch_zero_i64(pic_handle *h, int64_t *p, int64_t n)
 {
@@ -406,10 +394,13 @@ hipError_t launch_zero_i64(pic_handle *h, int64_t *p, int64_t n)
     return hipGetLastError();
 }
 
+// The f32 kick array of the FP32-bulk low stream from the current E_z (the
+// FP64 path and the high stream form the kick from E_z itself: nothing to do).
 hipError_t launch_kick(pic_handle *h)
 {
-    hipLaunchKernelGGL(k_kick, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c,
-                       h->ws.ez[h->fbuf], h->ws.k64, h->p.precision == PIC_FP32_BULK ? h->ws.k32 : nullptr);
+    if (h->p.precision != PIC_FP32_BULK) return hipSuccess;
+    hipLaunchKernelGGL(k_kick, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c, h->ws.ez[h->fbuf],
+                       h->ws.k32);
     return hipGetLastError();
 }
 

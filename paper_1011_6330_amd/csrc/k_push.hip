@@ -36,7 +36,7 @@ __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
 template <int BLOCK, int PPT, int NT>
 static hipError_t launch_push_t(pic_handle *h)
 {
-    PushArgs a{h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.k64,
+    PushArgs a{h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.ez[h->fbuf],
                (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr,
                h->hist_on ? (unsigned long long *)h->ws.cell_count : nullptr};
     const int64_t tile = (int64_t)BLOCK * PPT;
@@ -54,10 +54,12 @@ static hipError_t launch_push_args_t(pic_handle *h, const PushArgs &a)
     return hipGetLastError();
 }
 
-// FP64 push reading (X, U) and writing (Xo, Uo) (used by the adjoint recompute).
-hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U, double *Xo, double *Uo)
+// FP64 push reading (X, U) and writing (Xo, Uo) in the field ez (used by the
+// adjoint recompute).
+hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U, double *Xo, double *Uo,
+                                const double *ez)
 {
-    PushArgs a{X, U, Xo, Uo, h->ws.k64, (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr};
+    PushArgs a{X, U, Xo, Uo, ez, (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr};
     return launch_push_args_t<64, 2, 1>(h, a);
 }
 

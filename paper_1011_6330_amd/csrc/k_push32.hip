@@ -9,8 +9,9 @@
 //   high stream (gamma at or above the threshold, 1e6 by default): u in f64,
 //               16 B/slot; kick, gamma and v in f64 exactly as the FP64 path.
 // The deposit takes F = rint(2^P offset) of the stored offsets, so charge
-// conservation stays exact.  Fields, the Gauss residual, E_surf and the kick
-// arrays stay FP64.  The cell sort moves particles between the streams.
+// conservation stays exact.  Fields, the Gauss residual and E_surf stay FP64;
+// the high stream's kick is (q/m) dt E_z formed in f64 from E_z itself.  The
+// cell sort moves particles between the streams.
 #include <math.h>
 
 #include "pcpic_internal.h"
@@ -248,7 +249,7 @@ static hipError_t launch_push32_t(pic_handle *h)
     const int b = h->pbuf;
     const int64_t tile_hi = (int64_t)BLOCK * F32_PPT_HI;
     const unsigned items = (unsigned)((h->c.cap + tile_hi - 1) / tile_hi + 1);   // both streams, any split
-    Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b], w.k32, w.k64,
+    Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b], w.k32, w.ez[h->fbuf],
                  (unsigned long long *)w.j[h->jbuf], w.ctr,
                  h->hist_on ? (unsigned long long *)w.cell_count : nullptr, h->u_hi};
     hipLaunchKernelGGL((k_push_f32<BLOCK, NT>), dim3(items), dim3(BLOCK), 0, h->stream, h->c, a);

@@ -113,7 +113,7 @@ struct Workspace {
     int *ch[2];
     float *oh[2];
     double *uh[2];
-    float *k32;             // f32 kick array (FP32-bulk low stream)
+    float *k32;             // f32 kick array (q/m) dt E_z (FP32-bulk low stream)
     double *stage_x, *stage_u;  // FP32-bulk: staging of injected particles
     int64_t stage_cap;
     long long *stage_blk;       // FP32-bulk: per-256-particle block counts of a staged append
@@ -121,7 +121,6 @@ struct Workspace {
     long long *total_lo;    // FP32-bulk sort: low-destination total
     double *ez[2], *er[2], *b[2];
     int64_t *j[2];          // fixed-point current, ping-pong per step
-    double *k64;            // kick array (q/m) dt E_z
     double *rho_gj;
     int64_t *w;             // CIC node weights (Poisson, diagnostics)
     double *phi, *cp, *dp, *rhs;
@@ -169,7 +168,6 @@ struct TubeDev {
     gptr<double> uh[2];
     gptr<double> ez[2], er[2], b[2];
     gptr<int64_t> j[2];
-    gptr<double> k64;
     gptr<float> k32;
     gptr<DevCounters> ctr;
     gptr<long long> cell_count, cell_off, total_lo, blk_sum;
@@ -225,9 +223,10 @@ struct pic_handle {
     pic_handle *parent = nullptr;               // set on the tubes of a batch
     std::vector<pic_handle *> tubes;
     pcpic::TubeDev *d_tubes = nullptr;
-    int64_t *d_push_pref = nullptr, *d_field_pref = nullptr, *d_sort_pref = nullptr, *d_key_pref = nullptr;
+    int64_t *d_live_pref = nullptr;             // [n + 1] prefix of the push items holding particles
+    int64_t *d_field_pref = nullptr, *d_sort_pref = nullptr, *d_key_pref = nullptr;
     int64_t *d_scan_pref = nullptr;             // [n + 1] prefix of 1024-key scan blocks
-    int32_t *d_push_map = nullptr, *d_field_map = nullptr;   // work item -> tube
+    int32_t *d_field_map = nullptr;             // cell tile -> tube
     int32_t *d_chunk_map = nullptr, *d_scan_map = nullptr;
     int batch_block = 256, batch_ppt = 2;
     int64_t batch_push_items = 0, batch_field_items = 0, batch_sort_items = 0, batch_keys = 0, batch_scan_blocks = 0;
@@ -247,7 +246,8 @@ hipError_t launch_fields_from_phi(pic_handle *h);
 hipError_t launch_thomas_batch(pic_handle *b, const int32_t *d_list, int n);
 hipError_t launch_push_f64(pic_handle *h);
 hipError_t launch_push_f32(pic_handle *h);
-hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U, double *Xo, double *Uo);
+hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U, double *Xo, double *Uo,
+                                const double *ez);
 hipError_t launch_field_ptrs(pic_handle *h, const double *ezo, const double *ero, const double *bo, double *ezn,
                              double *ern, double *bn, double *X, double *U);
 hipError_t launch_weights32(pic_handle *h, int64_t *w_out);
@@ -256,14 +256,13 @@ hipError_t launch_sort32_hist(pic_handle *h);
 hipError_t launch_sort32_scatter(pic_handle *h);
 hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only);
 hipError_t launch_scan(pic_handle *h, int64_t n_keys);
-hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last);
+hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last, hipEvent_t *ev = nullptr);
 hipError_t launch_copy_slots(pic_handle *h, const double *X, const double *U, double *Xc, double *Uc);
 hipError_t launch_record_slots(pic_handle *h, int64_t *dst);
 hipError_t launch_zero_f64(pic_handle *h, double *p, int64_t n);
 hipError_t launch_adj_step(pic_handle *h, const AdjStepPtrs &s);
 hipError_t launch_adj_finish(pic_handle *h, const double *lez, const double *ler, double *gphi, double *cp,
                              double *dp, double *g_rho, double *params);
-hipError_t launch_kick_from(pic_handle *h, const double *ez);
 hipError_t launch_zero_i64(pic_handle *h, int64_t *p, int64_t n);
 hipError_t launch_batch_sort(pic_handle *h, bool hist_ready);
 hipError_t launch_stream_copy(const void *src, void *dst, int64_t n16, hipStream_t stream);

@@ -170,7 +170,6 @@ Workspace carve(const pic_params &p, uint8_t *base)
         w.b[k] = (double *)take(N * 8);
         w.j[k] = (int64_t *)take(N * 8);
     }
-    w.k64 = (double *)take(N * 8);
     w.rho_gj = (double *)take((N + 1) * 8);
     w.w = (int64_t *)take((N + 1) * 8);
     w.phi = (double *)take((N + 1) * 8);
@@ -371,7 +370,8 @@ pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u
     return PIC_OK;
 }
 
-static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t> *ev, pic_timing *tim);
+static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t> *ev = nullptr,
+                                pic_timing *tim = nullptr, std::vector<int64_t> *round_steps = nullptr);
 static pic_status batch_status(pic_handle *h);
 static void free_batch_graphs(pic_handle *h);
 
@@ -407,7 +407,7 @@ pic_status pic_step(pic_handle *h, int64_t n_steps)
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
     if (n_steps < 0) return fail(PIC_EINVAL, "n_steps < 0");
     if (h->parent) return fail(PIC_ESTATE, "a tube of a batch is stepped through its batch handle");
-    if (h->is_batch) return batch_advance(h, n_steps, nullptr, nullptr);
+    if (h->is_batch) return batch_advance(h, n_steps);
     // A whole round of sort_every steps that starts on a round boundary is
     // replayed from a graph captured once per (field, current, particle)
     // buffer-parity state; other steps are launched one by one.  Both issue the
@@ -464,15 +464,24 @@ pic_status pic_step_timed(pic_handle *h, int64_t n_steps, pic_timing *out)
     if (n_steps == 0) return PIC_OK;
     if (h->is_batch) {
         std::vector<hipEvent_t> ev;
-        pic_status rc = batch_advance(h, n_steps, &ev, out);
+        std::vector<int64_t> rounds;
+        pic_status rc = batch_advance(h, n_steps, &ev, out, &rounds);
         if (rc == PIC_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = fail(PIC_EDEVICE, "sync failed");
         if (rc == PIC_OK) {
-            for (size_t k = 0; k + 2 < ev.size(); k += 3) {
-                float a = 0, b = 0;
-                (void)hipEventElapsedTime(&a, ev[k], ev[k + 1]);
-                (void)hipEventElapsedTime(&b, ev[k + 1], ev[k + 2]);
-                out->push_ms += a;   // push and field kernels of the round
-                out->sort_ms += b;
+            size_t k = 0;
+            for (const int64_t r : rounds) {
+                for (int64_t s = 0; s < r; ++s, k += 4) {
+                    float a = 0, b = 0, c = 0;
+                    (void)hipEventElapsedTime(&a, ev[k], ev[k + 1]);       // work list
+                    (void)hipEventElapsedTime(&b, ev[k + 1], ev[k + 2]);   // push
+                    (void)hipEventElapsedTime(&c, ev[k + 2], ev[k + 3]);   // field update + injection
+                    out->push_ms += b;
+                    out->field_ms += a + c;
+                }
+                float d = 0;
+                (void)hipEventElapsedTime(&d, ev[k], ev[k + 1]);           // the sort (0 when none)
+                out->sort_ms += d;
+                k += 2;
             }
             if (!ev.empty()) {
                 float tot = 0;
@@ -1011,20 +1020,17 @@ pic_status pic_destroy(pic_handle *h)
 // ------------------------------------------------------------------------
 
 // Entries of the work-item -> tube maps, sized for the smallest tiles any
-// launch shape uses (64 threads x 2 slots, or x 4 in FP32-bulk mode; 64 cells).
+// launch shape uses (64 cells per field tile).
 struct BatchMapSizes {
-    int64_t push, field, chunk, scan;
+    int64_t field, chunk, scan;
 };
 
 static BatchMapSizes batch_map_sizes(const pic_params *tubes, int n)
 {
-    BatchMapSizes m{0, 0, 0, 0};
+    BatchMapSizes m{0, 0, 0};
     for (int t = 0; t < n; ++t) {
         const pic_params &p = tubes[t];
         const bool f32 = p.precision == PIC_FP32_BULK;
-        // the smallest tiles of any launch shape: 64 threads x 2 slots (FP64),
-        // high-stream tiles of 64 x 2 slots over both streams plus one (FP32-bulk)
-        m.push += f32 ? (p.capacity + 127) / 128 + 1 : (p.capacity + 127) / 128;
         m.field += (p.n_cells + 63) / 64;
         m.chunk += (p.capacity + SORT_TILE - 1) / SORT_TILE + (f32 ? 1 : 0);
         const int64_t keys = (f32 ? 2 * (p.n_cells + 1) : p.n_cells) << sort_sub_log2(p);
@@ -1039,7 +1045,6 @@ static size_t batch_header_bytes(const pic_params *tubes, int n)
     size_t off = 0;
     off = align_up(off) + sizeof(TubeDev) * (size_t)n;
     for (int k = 0; k < 5; ++k) off = align_up(off) + sizeof(int64_t) * (size_t)(n + 1);
-    off = align_up(off) + 4 * (size_t)m.push;
     off = align_up(off) + 4 * (size_t)m.field;
     off = align_up(off) + 4 * (size_t)m.chunk;
     off = align_up(off) + 4 * (size_t)m.scan;
@@ -1105,21 +1110,17 @@ static pic_status batch_configure(pic_handle *h, int block, int per_thread)
     h->batch_keys = kp[(size_t)n];
     h->batch_scan_blocks = cp[(size_t)n];
     HIP_OK(hipMemcpyAsync(h->d_tubes, td.data(), sizeof(TubeDev) * (size_t)n, hipMemcpyHostToDevice, h->stream));
-    HIP_OK(hipMemcpyAsync(h->d_push_pref, pp.data(), 8 * pp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_field_pref, fp.data(), 8 * fp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_sort_pref, sp.data(), 8 * sp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_key_pref, kp.data(), 8 * kp.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_scan_pref, cp.data(), 8 * cp.size(), hipMemcpyHostToDevice, h->stream));
     // work item -> tube maps (one entry per block of the batched kernels)
-    std::vector<int32_t> pm((size_t)pp[(size_t)n]), fm((size_t)fp[(size_t)n]), sm((size_t)sp[(size_t)n]),
-        cm((size_t)cp[(size_t)n]);
+    std::vector<int32_t> fm((size_t)fp[(size_t)n]), sm((size_t)sp[(size_t)n]), cm((size_t)cp[(size_t)n]);
     for (int t = 0; t < n; ++t) {
-        for (int64_t i = pp[(size_t)t]; i < pp[(size_t)t + 1]; ++i) pm[(size_t)i] = t;
         for (int64_t i = fp[(size_t)t]; i < fp[(size_t)t + 1]; ++i) fm[(size_t)i] = t;
         for (int64_t i = sp[(size_t)t]; i < sp[(size_t)t + 1]; ++i) sm[(size_t)i] = t;
         for (int64_t i = cp[(size_t)t]; i < cp[(size_t)t + 1]; ++i) cm[(size_t)i] = t;
     }
-    HIP_OK(hipMemcpyAsync(h->d_push_map, pm.data(), 4 * pm.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_field_map, fm.data(), 4 * fm.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_chunk_map, sm.data(), 4 * sm.size(), hipMemcpyHostToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(h->d_scan_map, cm.data(), 4 * cm.size(), hipMemcpyHostToDevice, h->stream));
@@ -1158,14 +1159,13 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
         return (void *)(base + o);
     };
     h->d_tubes = (TubeDev *)take(sizeof(TubeDev) * (size_t)n_tubes);
-    h->d_push_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
+    h->d_live_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_field_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_sort_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_key_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_scan_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     {
         const BatchMapSizes m = batch_map_sizes(tubes, n_tubes);
-        h->d_push_map = (int32_t *)take(4 * (size_t)m.push);
         h->d_field_map = (int32_t *)take(4 * (size_t)m.field);
         h->d_chunk_map = (int32_t *)take(4 * (size_t)m.chunk);
         h->d_scan_map = (int32_t *)take(4 * (size_t)m.scan);
@@ -1231,7 +1231,8 @@ pic_status pic_batch_get_config(pic_handle *h, int32_t *block, int32_t *per_thre
 // period; a whole round (push and field kernels of every step, then the batched
 // sort) is replayed from a captured graph.  With `ev`, events bracket each
 // round's step kernels and its sort.
-static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t> *ev, pic_timing *tim)
+static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t> *ev, pic_timing *tim,
+                                std::vector<int64_t> *round_steps)
 {
     if (pic_status sp = batch_resolve_pending(h)) return sp;
     pic_handle *t0 = h->tubes[0];
@@ -1269,22 +1270,24 @@ static pic_status batch_advance(pic_handle *h, int64_t n, std::vector<hipEvent_t
         if (round && h->graph[key]) {
             HIP_OK(hipGraphLaunch(h->graph[key], h->stream));
         } else {
+            // timed: four events per step (work list, push, field) and two around the sort
             hipEvent_t *e = nullptr;
+            const size_t ne = ev ? (size_t)r * 4 + 2 : 0;
             if (ev) {
-                ev->resize(ev->size() + 3, nullptr);
-                e = &(*ev)[ev->size() - 3];
-                for (int k = 0; k < 3; ++k) HIP_OK(hipEventCreate(&e[k]));
-                HIP_OK(hipEventRecord(e[0], h->stream));
+                ev->resize(ev->size() + ne, nullptr);
+                e = &(*ev)[ev->size() - ne];
+                for (size_t k = 0; k < ne; ++k) HIP_OK(hipEventCreate(&e[k]));
             }
-            HIP_OK(launch_batch_steps(h, (int)r, to_sort));
-            if (e) HIP_OK(hipEventRecord(e[1], h->stream));
+            HIP_OK(launch_batch_steps(h, (int)r, to_sort, e));
+            if (e) HIP_OK(hipEventRecord(e[ne - 2], h->stream));
             if (to_sort) HIP_OK(launch_batch_sort(h, true));
-            if (e) HIP_OK(hipEventRecord(e[2], h->stream));
+            if (e) HIP_OK(hipEventRecord(e[ne - 1], h->stream));
             if (tim) {
-                tim->push_launches += 1;
+                tim->push_launches += r;
                 tim->field_launches += r;
                 if (to_sort) tim->sort_launches += 1;
             }
+            if (ev) round_steps->push_back(r);
         }
         for (pic_handle *t : h->tubes) {
             t->fbuf ^= (int)(r & 1);
@@ -1526,14 +1529,13 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
         hipError_t e = hipMemcpyAsync(w.ctr, t.ck_ctr[ck], sizeof(DevCounters), hipMemcpyDeviceToDevice, rec_s);
         if (e == hipSuccess) e = launch_zero_i64(h, w.j[0], N);
         if (e == hipSuccess) e = launch_zero_i64(h, w.j[1], N);
-        if (e == hipSuccess) e = launch_kick_from(h, t.ck_ez[ck]);
         for (int64_t k = 0; k + 1 < m && e == hipSuccess; ++k) {
             const double *xi = k == 0 ? t.ck_x[ck] : t.sg_x[q][(size_t)k];
             const double *ui = k == 0 ? t.ck_u[ck] : t.sg_u[q][(size_t)k];
             const double *ezo = k == 0 ? t.ck_ez[ck] : t.sg_ez[q][(size_t)k];
             const double *ero = k == 0 ? t.ck_er[ck] : t.sg_er[q][(size_t)k];
             const double *bo = k == 0 ? t.ck_b[ck] : t.sg_b[q][(size_t)k];
-            e = launch_push_f64_ptrs(h, xi, ui, t.sg_x[q][(size_t)k + 1], t.sg_u[q][(size_t)k + 1]);
+            e = launch_push_f64_ptrs(h, xi, ui, t.sg_x[q][(size_t)k + 1], t.sg_u[q][(size_t)k + 1], ezo);
             if (e == hipSuccess)
                 e = launch_field_ptrs(h, ezo, ero, bo, t.sg_ez[q][(size_t)k + 1], t.sg_er[q][(size_t)k + 1],
                                       t.sg_b[q][(size_t)k + 1], t.sg_x[q][(size_t)k + 1], t.sg_u[q][(size_t)k + 1]);

@@ -15,7 +15,7 @@ struct PushArgs {
     const double *__restrict__ U;
     double *__restrict__ Xo;        // slots written (== X, U for an in-place step)
     double *__restrict__ Uo;
-    const double *__restrict__ K;
+    const double *__restrict__ EZ;  // E_z^n at the faces (the kick is (q/m) dt E_z)
     unsigned long long *__restrict__ J;
     DevCounters *ctr;
     unsigned long long *hist;       // non-null on the step before a sort: key counts of the survivors
@@ -33,10 +33,11 @@ __device__ __forceinline__ void hist_add(unsigned long long *hist, const int64_t
     }
 }
 
-// Kick at x: linear interpolation between face values, clamped at the ends.
-// Also called for an empty slot (x = -1), whose face index clamps to 0, so the
-// loads of every slot can be issued together before any particle is pushed.
-__device__ __forceinline__ double gather_f64(const Consts &c, const double *__restrict__ K, double x)
+// Kick at x: linear interpolation between the face values K = (q/m) dt E_z,
+// clamped at the ends.  Also called for an empty slot (x = -1), whose face index
+// clamps to 0, so the loads of every slot can be issued together before any
+// particle is pushed.
+__device__ __forceinline__ double gather_f64(const Consts &c, const double *__restrict__ EZ, double x)
 {
     const int N = (int)c.N;
     const double Nm1 = (double)(c.N - 1);
@@ -44,7 +45,7 @@ __device__ __forceinline__ double gather_f64(const Consts &c, const double *__re
     const int jj = (int)floor(s);
     const double g = s - (double)jj;
     const int jc = jj < 0 ? 0 : (jj > N - 2 ? N - 2 : jj);
-    const double k0 = K[jc], k1 = K[jc + 1];
+    const double k0 = c.qmdt * EZ[jc], k1 = c.qmdt * EZ[jc + 1];
     const double Ei = k0 + g * (k1 - k0);
     const double lo = s < 0.0 ? k0 : Ei;
     return s >= Nm1 ? k1 : lo;
@@ -118,7 +119,7 @@ __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a
     }
     double E[PPT];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) E[k] = gather_f64(c, a.K, xs[k]);
+    for (int k = 0; k < PPT; ++k) E[k] = gather_f64(c, a.EZ, xs[k]);
 
     DepAcc acc;
     acc.init(a.ctr);
@@ -159,8 +160,8 @@ struct Push32Args {
     int *__restrict__ CH;
     float *__restrict__ OH;
     double *__restrict__ UH;
-    const float *__restrict__ K32;
-    const double *__restrict__ K64;
+    const float *__restrict__ K32;   // (float)((q/m) dt E_z) at the faces (low stream)
+    const double *__restrict__ EZ;   // E_z^n at the faces (high stream: kick (q/m) dt E_z in f64)
     unsigned long long *__restrict__ J;
     DevCounters *ctr;
     unsigned long long *hist = nullptr;   // non-null on the step before a sort: key counts of the survivors
@@ -365,7 +366,7 @@ __device__ __forceinline__ void push_tile_hi(const Consts &c, const Push32Args &
         float g;
         int j;
         const int jc = gather_face_f32(N, cs[k], os[k], g, j);
-        const double k0 = a.K64[jc], k1 = a.K64[jc + 1];
+        const double k0 = c.qmdt * a.EZ[jc], k1 = c.qmdt * a.EZ[jc + 1];
         const double Ei = k0 + (double)g * (k1 - k0);
         const double lo = j < 0 ? k0 : Ei;
         E[k] = j >= N - 1 ? k1 : lo;

@@ -41,3 +41,14 @@ def test_traffic_only_for_matching_sources_and_shape(tmp_path, monkeypatch):
     assert bench.measured_traffic((128, 2, True)) is None          # other push sources
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
     assert bench.measured_traffic((128, 2, True)) is None
+
+
+def test_traffic_files_are_keyed_by_their_own_sources(tmp_path):
+    """The FP32-bulk and batched push summaries are keyed by those kernels' sources."""
+    import bench
+    f = tmp_path / "t32.txt"
+    f.write_text(f"push_shape: 128:4:nt\nsource_sha256: {bench.push_source_hash(bench.PUSH32_SOURCES)}\n"
+                 "traffic_bytes_per_launch: 99\n")
+    assert bench.measured_traffic((128, 4, True), str(f), bench.PUSH32_SOURCES) == 99.0
+    assert bench.measured_traffic((128, 4, True), str(f), bench.BATCH_SOURCES) is None
+    assert bench.push_source_hash(bench.PUSH32_SOURCES) != bench.push_source_hash(bench.PUSH_SOURCES)
