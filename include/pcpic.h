@@ -207,6 +207,26 @@ pic_status pic_step(pic_handle *h, int64_t n_steps);
  * Returns PIC_EDEVSTATUS if a status bit is latched (out is still filled). */
 pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the signed-gamma profile of
+ * pic_diagnostics -- n_bins uniform bins over [0, N) with, per bin, the count,
+ * the 128-bit sum of sign(u) gamma in units of 2^-32 (low word, signed high
+ * word), the min and the max -- written to caller-provided device arrays of
+ * n_bins entries (any of them may be NULL).  Asynchronous on the handle's
+ * stream: it enqueues kernels only, synchronises nothing and allocates nothing;
+ * the bins accumulate in a fixed device array of the library (at most 65,536
+ * bins: 2.5 MiB per GPU, held until the process ends) instead of the
+ * workspace.  Every call on a GPU reuses that GPU's array and clears the bins
+ * it uses first: calls that overlap on one GPU (from different streams or
+ * threads) race.  The handle's device must be current.  The values equal, bit
+ * for bit, pic_diagnostics' prof_count, prof_sum_lo, prof_sum_hi, prof_min and
+ * prof_max (an empty bin has min +inf and max -inf).  Errors: PIC_EINVAL
+ * (n_bins outside [1, 65536], a batch handle), PIC_ESTATE (the t = 0 field
+ * solve of a batch tube is still pending, or another device is current),
+ * PIC_EDEVICE. */
+pic_status pic_profile_noalloc(pic_handle *h, int32_t n_bins, int64_t *d_count, uint64_t *d_sum_lo,
+                               int64_t *d_sum_hi, double *d_min, double *d_max);
+
 /* Synchronise and copy the live particles, in slot order, to host arrays of
  * `cap` entries; *n_out receives the live count (PIC_ECAPACITY if cap is short). */
 pic_status pic_read_particles(pic_handle *h, double *x, double *u, int64_t cap, int64_t *n_out);

@@ -93,6 +93,8 @@ SIGNATURES = {
     "pic_diagnostics": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(PicDiagReq),
                                          ctypes.POINTER(PicDiag)]),
     "pic_read_particles": (ctypes.c_int32, [ctypes.c_void_p, _pd, _pd, ctypes.c_int64, _pi]),
+    "pic_profile_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pic_write_fields": (ctypes.c_int32, [ctypes.c_void_p, _pd, _pd, _pd]),
     "pic_step_timed": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(PicTiming)]),
     "pic_set_push_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,

@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void k_gauss(Consts c, const double *ez, const
     if (__lane_id() == 0 && m != 0) atomicMax(&ctr->gauss_max_bits, (unsigned long long)m);
 }
 
+// Clears nb profile bins (and, with ctr, the Gauss maximum of the diagnostics).
 __global__ __launch_bounds__(256) void k_profile_clear(int nb, long long *cnt, unsigned long long *lo,
                                                        long long *hi, long long *mn, long long *mx,
                                                        DevCounters *ctr)
@@ -44,7 +45,22 @@ __global__ __launch_bounds__(256) void k_profile_clear(int nb, long long *cnt, u
         mn[i] = ordered_bits(INFINITY);
         mx[i] = ordered_bits(-INFINITY);
     }
-    if (i == 0) ctr->gauss_max_bits = 0;
+    if (i == 0 && ctr) ctr->gauss_max_bits = 0;
+}
+
+// The accumulated bins in the caller's layout: counts and the 128-bit sums as
+// they are, min and max back from their ordered bit images to doubles (an empty
+// bin gives +inf and -inf).  Any output may be null.
+__global__ __launch_bounds__(256) void k_profile_finish(int nb, ProfPtrs p, int64_t *count, uint64_t *sum_lo,
+                                                        int64_t *sum_hi, double *vmin, double *vmax)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nb) return;
+    if (count) count[i] = p.cnt[i];
+    if (sum_lo) sum_lo[i] = p.lo[i];
+    if (sum_hi) sum_hi[i] = p.hi[i];
+    if (vmin) vmin[i] = from_ordered_bits(p.mn[i]);
+    if (vmax) vmax[i] = from_ordered_bits(p.mx[i]);
 }
 
 // Signed gamma sign(u) sqrt(1 + u^2) binned uniformly in x (ProfAcc): per bin
@@ -80,17 +96,32 @@ hipError_t launch_gauss(pic_handle *h)
     return hipGetLastError();
 }
 
-hipError_t launch_profile(pic_handle *h, int nb)
+hipError_t launch_profile_into(pic_handle *h, int nb, const ProfPtrs &p, bool clear_gauss)
 {
     const Consts &c = h->c;
     Workspace &w = h->ws;
     const int nbk = nb > 0 ? nb : 1;
     hipLaunchKernelGGL(k_profile_clear, dim3((unsigned)((nbk + 255) / 256)), dim3(256), 0, h->stream, nbk,
-                       w.pcount, w.plo, w.phi128, w.pmin, w.pmax, w.ctr);
-    if (nb > 0 && h->p.precision == PIC_FP32_BULK) return launch_profile32(h, nb);
+                       p.cnt, p.lo, p.hi, p.mn, p.mx, clear_gauss ? w.ctr : nullptr);
+    if (nb > 0 && h->p.precision == PIC_FP32_BULK) return launch_profile32(h, nb, p);
     if (nb > 0)
         hipLaunchKernelGGL(k_profile, dim3(h->n_cu * 8), dim3(256), 0, h->stream, c, nb, w.x[h->pbuf],
-                           w.u[h->pbuf], w.ctr, ProfOut{w.pcount, w.plo, w.phi128, w.pmin, w.pmax});
+                           w.u[h->pbuf], w.ctr, ProfOut{p.cnt, p.lo, p.hi, p.mn, p.mx});
+    return hipGetLastError();
+}
+
+hipError_t launch_profile(pic_handle *h, int nb)
+{
+    Workspace &w = h->ws;
+    return launch_profile_into(h, nb, ProfPtrs{w.pcount, w.plo, w.phi128, w.pmin, w.pmax}, true);
+}
+
+hipError_t launch_profile_finish(pic_handle *h, int nb, const ProfPtrs &p, int64_t *count, uint64_t *sum_lo,
+                                 int64_t *sum_hi, double *vmin, double *vmax)
+{
+    if (nb > 0)
+        hipLaunchKernelGGL(k_profile_finish, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, h->stream, nb, p,
+                           count, sum_lo, sum_hi, vmin, vmax);
     return hipGetLastError();
 }
 

@@ -280,11 +280,11 @@ hipError_t launch_weights32(pic_handle *h, int64_t *w_out)
     return hipGetLastError();
 }
 
-hipError_t launch_profile32(pic_handle *h, int nbins)
+hipError_t launch_profile32(pic_handle *h, int nbins, const ProfPtrs &p)
 {
     const Workspace &w = h->ws;
     hipLaunchKernelGGL(k_profile32, dim3(h->n_cu * 8), dim3(256), 0, h->stream, h->c, nbins, streams_of(h, h->pbuf),
-                       w.ctr, ProfOut{w.pcount, w.plo, w.phi128, w.pmin, w.pmax});
+                       w.ctr, ProfOut{p.cnt, p.lo, p.hi, p.mn, p.mx});
     return hipGetLastError();
 }
 

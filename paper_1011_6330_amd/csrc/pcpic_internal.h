@@ -218,6 +218,7 @@ struct pic_handle {
     bool poisson_pending = false;       // tube of a batch: eq. (4) to be solved with the batch
     int32_t *d_pending = nullptr;       // batch: device list of tubes to solve together
     int n_cu = 256;
+    int dev = 0;        // device ordinal current at pic_init
     // batch (ensemble) handles
     bool is_batch = false;
     pic_handle *parent = nullptr;               // set on the tubes of a batch
@@ -251,7 +252,19 @@ hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U,
 hipError_t launch_field_ptrs(pic_handle *h, const double *ezo, const double *ero, const double *bo, double *ezn,
                              double *ern, double *bn, double *X, double *U);
 hipError_t launch_weights32(pic_handle *h, int64_t *w_out);
-hipError_t launch_profile32(pic_handle *h, int nbins);
+// Profile bins: count, 128-bit sum (low and high words), ordered bit images of min and max.
+struct ProfPtrs {
+    long long *cnt;
+    unsigned long long *lo;
+    long long *hi;
+    long long *mn, *mx;
+};
+hipError_t launch_profile32(pic_handle *h, int nbins, const ProfPtrs &p);
+// The profile accumulated into the bins p (cleared first; clear_gauss also clears the
+// Gauss maximum of the diagnostics), and copied out in the caller's layout.
+hipError_t launch_profile_into(pic_handle *h, int nb, const ProfPtrs &p, bool clear_gauss);
+hipError_t launch_profile_finish(pic_handle *h, int nb, const ProfPtrs &p, int64_t *count, uint64_t *sum_lo,
+                                 int64_t *sum_hi, double *vmin, double *vmax);
 hipError_t launch_sort32_hist(pic_handle *h);
 hipError_t launch_sort32_scatter(pic_handle *h);
 hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only);

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -36,6 +37,42 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
 int effective_bins(const pic_params &p) { return p.max_bins > 0 ? p.max_bins : 1024; }
+
+// ---- the scratch of pic_profile_noalloc ----------------------------------
+//
+// A fixed device array instead of the handle's workspace, so that the call
+// allocates nothing.  Each GPU the library runs on holds its own copy until the
+// process ends; every call on a GPU reuses that GPU's copy (calls overlapping on
+// one GPU race).  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current.
+constexpr int NOALLOC_MAX_BINS = 65536;
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)5 * 8 * NOALLOC_MAX_BINS;   // 2.5 MiB
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+pic_status scratch_of_current_device(int *dev_out, void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PIC_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PIC_EDEVICE, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PIC_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    if (dev_out) *dev_out = dev;
+    if (out) *out = g_scratch_dev[dev];
+    return PIC_OK;
+}
 
 pic_status validate(const pic_params *p)
 {
@@ -253,6 +290,14 @@ static pic_status init_tube(const pic_params *p, void *d_workspace, size_t ws_by
     }
     h->stream = (hipStream_t)hip_stream;
     h->ws = carve(*p, (uint8_t *)d_workspace);
+    {
+        // set-up of the fixed scratch of pic_profile_noalloc on this device
+        const pic_status ss = scratch_of_current_device(&h->dev, nullptr);
+        if (ss != PIC_OK) {
+            delete h;
+            return ss;
+        }
+    }
     // the fastest measured push shapes (nontemporal particle streams)
     h->push_block = 128;
     h->push_ppt = p->precision == PIC_FP32_BULK ? 4 : 2;
@@ -703,6 +748,36 @@ pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out
         if (out->prof_max) out->prof_max[k] = from_ordered_bits(mx[k]);
     }
     if (ctr.status) return fail(PIC_EDEVSTATUS, "device status bits 0x%llx", (unsigned long long)ctr.status);
+    return PIC_OK;
+}
+
+pic_status pic_profile_noalloc(pic_handle *h, int32_t n_bins, int64_t *d_count, uint64_t *d_sum_lo,
+                               int64_t *d_sum_hi, double *d_min, double *d_max)
+{
+    if (!h) return fail(PIC_EINVAL, "handle is NULL");
+    if (h->is_batch) return fail(PIC_EINVAL, "the profile is per tube (pic_batch_tube)");
+    if (n_bins < 1 || n_bins > NOALLOC_MAX_BINS)
+        return fail(PIC_EINVAL, "n_bins %d not in [1, %d] (the fixed scratch holds %d bins)", n_bins,
+                    NOALLOC_MAX_BINS, NOALLOC_MAX_BINS);
+    if (h->poisson_pending)
+        return fail(PIC_ESTATE, "the tube's t = 0 field solve is pending (call pic_diagnostics or pic_step first)");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->dev)
+        return fail(PIC_ESTATE, "call with the tube's device (%d) current", h->dev);
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = g_scratch_dev[dev];
+    }
+    if (!base) {
+        const pic_status s = scratch_of_current_device(nullptr, &base);
+        if (s != PIC_OK) return s;
+    }
+    long long *p = (long long *)base;
+    const size_t nb = (size_t)n_bins;
+    const ProfPtrs bins{p, (unsigned long long *)(p + nb), p + 2 * nb, p + 3 * nb, p + 4 * nb};
+    HIP_OK(launch_profile_into(h, n_bins, bins, false));
+    HIP_OK(launch_profile_finish(h, n_bins, bins, d_count, d_sum_lo, d_sum_hi, d_min, d_max));
     return PIC_OK;
 }
 
