@@ -431,11 +431,37 @@ def run_ensemble(steps, precision=1):
 
 def run_adjoint_leg(steps, ckpt=50):
     """C4: the hand-written adjoint of `steps` steps (checkpoints every `ckpt`)
-    against a plain forward of the same steps on the same tube."""
+    against a plain forward of the same steps on the same tube: the recorded
+    forward (pic_adjoint_forward) and the reverse sweep (pic_backward) timed
+    apart.  `rate_variant` is the same tube cut to its first 256 cells (same
+    cell size and density), where electrons injected during the run reach the
+    top, so that the injection-rate gradient is not 0."""
+    out = _adjoint_case(synth_preset("c4"), steps, ckpt)
+    out["workload"] = ("c4: 64-knot frame-dragging tube, 4096 cells, ~1e6 warm particles, loss = mean exit gamma, "
+                       f"{steps} steps, checkpoint every {ckpt}, FP64")
+    c = synth_preset("c4")
+    n = 256
+    c.update(n_cells=n, length=c["length"] * n / c["n_cells"], warm=int(c["ppc"] * n),
+             capacity=int(c["ppc"] * n * 8))   # the beam leaves and is replaced about twice
+    rv = _adjoint_case(c, steps, ckpt)
+    rv["workload"] = (f"the c4 tube's first 256 cells (L = {c['length']:.3f} R, same cell size and density, "
+                      f"{c['warm']} warm particles), {steps} steps, checkpoint every {ckpt}: injected electrons "
+                      "reach the top")
+    out["rate_variant"] = rv
+    log(f"adjoint rate variant: dL/drate {rv['g_rate']:.6g}, backward / plain forward "
+        f"{rv['backward_over_plain_forward']:.2f}")
+    return out
+
+
+def synth_preset(name):
+    from paper_1011_6330_amd import synth
+    return synth.preset(name)
+
+
+def _adjoint_case(cfg, steps, ckpt):
     import torch
 
     from paper_1011_6330_amd import Tube, synth
-    cfg = synth.preset("c4")
     x, u = synth.warm_start(cfg)
     p = synth.tube_params(cfg)
     # the plain forward: the same steps launched back to back, nothing recorded
@@ -453,20 +479,20 @@ def run_adjoint_leg(steps, ckpt=50):
     t.inject(x, u)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = t.run_adjoint(steps, ckpt)
+    f = t.adjoint_forward(steps, ckpt)
+    r = t.backward()
     el = time.perf_counter() - t0
     t.close()
     del t
     torch.cuda.empty_cache()
-    log(f"adjoint: plain forward {fwd:.1f} ms, checkpointed forward {r['forward_ms']:.1f} ms, "
-        f"backward {r['backward_ms']:.1f} ms, loss {r['loss']:.6g} over {r['n_exit']} exits")
-    return {"workload": "c4: 64-knot frame-dragging tube, 4096 cells, ~1e6 warm particles, loss = mean exit gamma, "
-                        f"{steps} steps, checkpoint every {ckpt}, FP64",
-            "steps": steps, "checkpoint_every": ckpt, "plain_forward_ms": fwd,
-            "checkpointed_forward_ms": r["forward_ms"], "backward_ms": r["backward_ms"],
+    log(f"adjoint: plain forward {fwd:.1f} ms, checkpointed forward {f['forward_ms']:.1f} ms, "
+        f"backward {r['backward_ms']:.1f} ms, loss {r['loss']:.6g} over {r['n_exit']} exits, "
+        f"dL/drate {r['g_rate']:.4g}")
+    return {"steps": steps, "checkpoint_every": ckpt, "plain_forward_ms": fwd,
+            "checkpointed_forward_ms": f["forward_ms"], "backward_ms": r["backward_ms"],
             "backward_over_plain_forward": r["backward_ms"] / fwd if fwd > 0 else None,
-            "backward_over_checkpointed_forward": r["backward_ms"] / r["forward_ms"] if r["forward_ms"] > 0 else None,
-            "loss": r["loss"], "n_exit": r["n_exit"], "tape_bytes": r["tape_bytes"], "wall_s": el,
+            "backward_over_checkpointed_forward": r["backward_ms"] / f["forward_ms"] if f["forward_ms"] > 0 else None,
+            "loss": r["loss"], "n_exit": r["n_exit"], "tape_bytes": f["tape_bytes"], "wall_s": el,
             "g_kappa": r["g_kappa"], "g_rate": r["g_rate"]}
 
 

@@ -318,10 +318,10 @@ pic_status pic_batch_get_config(pic_handle *batch, int32_t *block, int32_t *per_
 /* ---- hand-written adjoint ----
  *
  * Loss L = mean Lorentz factor of the electrons that leave through z = L during
- * n_steps steps.  pic_run_adjoint advances the tube by n_steps (the same steps
- * pic_step would take) while checkpointing every checkpoint_every steps into
- * the caller's device tape, then runs the reverse sweep, recomputing each
- * segment from its checkpoint, and returns dL/d(parameters).  Every discrete
+ * n_steps steps.  pic_adjoint_forward advances the tube by n_steps (the same
+ * steps pic_step would take) while checkpointing every checkpoint_every steps
+ * into the caller's device tape; pic_backward then runs the reverse sweep,
+ * recomputing each segment from its checkpoint, and returns dL/d(parameters).  Every discrete
  * decision of the run is held fixed (injection counts, exits and returns, cell
  * crossings; the fixed-point rounding is taken as the identity), and the
  * macro-particle charge is the one pic_params fixes (set macro_charge so that
@@ -341,14 +341,34 @@ typedef struct pic_adjoint_out {
     double backward_ms;     /* device time of the recompute + reverse sweep             */
 } pic_adjoint_out;
 
-/* Device bytes of the tape pic_run_adjoint needs (checkpoints, the recorded
- * steps of two segments, adjoint arrays), 0 if the handle cannot run the
- * adjoint.  The reverse sweep of one segment overlaps the recompute of the
- * previous one on a second stream the call creates and destroys. */
+/* Device bytes of the tape the adjoint needs (checkpoints, the recorded steps
+ * of two segments, adjoint arrays), 0 if the handle cannot run the adjoint.
+ * The reverse sweep of one segment overlaps the recompute of the previous one
+ * on a second stream that pic_backward creates and destroys. */
 size_t pic_adjoint_tape_bytes(pic_handle *h, int64_t n_steps, int32_t checkpoint_every);
 
-/* Errors: PIC_EINVAL (requirements above), PIC_EWORKSPACE (tape too small or
+/* The forward half: advance the tube by n_steps with a checkpoint every
+ * checkpoint_every steps in the caller's device tape (256-byte aligned,
+ * tape_bytes >= pic_adjoint_tape_bytes) and record the run on the handle; fills
+ * out->loss, out->n_exit and out->forward_ms.  Synchronises the stream.
+ * Errors: PIC_EINVAL (requirements above), PIC_EWORKSPACE (tape too small or
  * misaligned), PIC_EDEVICE. */
+pic_status pic_adjoint_forward(pic_handle *h, int64_t n_steps, int32_t checkpoint_every, void *d_tape,
+                               size_t tape_bytes, pic_adjoint_out *out);
+
+/* The reverse half: the gradient of the recorded forward, scaled by dloss (the
+ * derivative of the caller's objective with respect to L; 1 for L itself), into
+ * out (g_rate, g_kappa, g_amp, and g_rho, g_knots where non-NULL; loss, n_exit,
+ * forward_ms as recorded; backward_ms).  The tape must be the forward's and
+ * untouched since, and the tube neither stepped nor changed in between
+ * (PIC_ESTATE otherwise); it ends in the state the forward left, so the
+ * reverse sweep may be run again (the same bits each time: every sum the sweep
+ * shares between waves is an integer sum).  Synchronises the stream.
+ * Errors: PIC_EINVAL, PIC_ESTATE, PIC_EDEVICE. */
+pic_status pic_backward(pic_handle *h, double dloss, pic_adjoint_out *out);
+
+/* pic_adjoint_forward followed by pic_backward with dloss = 1.
+ * Errors: as the two. */
 pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_every, void *d_tape,
                            size_t tape_bytes, pic_adjoint_out *out);
 

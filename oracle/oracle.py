@@ -76,6 +76,15 @@ def load():
         lib.orc_gauss.argtypes = [P(OrcCfg), P(OrcState), _pd, _pd]
         lib.orc_profile.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int32, _pi,
                                     P(ctypes.c_uint64), _pi, _pd, _pd]
+        for f in ("orc_tl_fields", "orc_ad_fields"):
+            getattr(lib, f).argtypes = [P(OrcCfg), P(OrcState)] + [_pd] * 7
+        for f in ("orc_tl_push", "orc_ad_push"):
+            getattr(lib, f).argtypes = [P(OrcCfg), P(OrcState)] + [_pd] * 6
+        lib.orc_tl_poisson.argtypes = [P(OrcCfg), P(OrcState)] + [_pd] * 3
+        lib.orc_ad_poisson.argtypes = [P(OrcCfg), P(OrcState)] + [_pd] * 3
+        for f in ("orc_tl_fields", "orc_ad_fields", "orc_tl_push", "orc_ad_push", "orc_tl_poisson",
+                  "orc_ad_poisson"):
+            getattr(lib, f).restype = ctypes.c_int
         lib.orc_step_par.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int64, ctypes.c_int32]
         lib.orc_step_par.restype = ctypes.c_int
         lib.orc_adjoint.argtypes = [P(OrcCfg), P(OrcState), ctypes.c_int64, _pd, _pd, _pd, _pi]
@@ -162,6 +171,37 @@ class OracleTube:
         rc = self.lib.orc_step_par(ctypes.byref(self.ccfg), ctypes.byref(self.st), int(n), int(threads))
         if rc != 0:
             raise ValueError(f"orc_step_par failed (rc={rc})")
+
+    # -- linearised kernels (dot-product pins of the reverse sweep) ------------
+    def _lin(self, name, ins, out_sizes):
+        ins = [np.ascontiguousarray(a, np.float64) for a in ins]
+        outs = [np.zeros(n) for n in out_sizes]
+        rc = getattr(self.lib, name)(ctypes.byref(self.ccfg), ctypes.byref(self.st), *[_ptr(a) for a in ins + outs])
+        if rc != 0:
+            raise ValueError(f"{name} failed (rc={rc})")
+        return outs
+
+    def tl_fields(self, dez, der, db, dj):
+        N = self.N
+        return self._lin("orc_tl_fields", [dez, der, db, dj], [N, N + 1, N])
+
+    def ad_fields(self, lez1, ler1, lb1):
+        N = self.N
+        return self._lin("orc_ad_fields", [lez1, ler1, lb1], [N, N + 1, N, N])
+
+    def tl_push(self, dx, du, dk):
+        n = self.n
+        return self._lin("orc_tl_push", [dx, du, dk], [n, n, self.N])
+
+    def ad_push(self, lx1, lu1, lj):
+        n = self.n
+        return self._lin("orc_ad_push", [lx1, lu1, lj], [n, n, self.N])
+
+    def tl_poisson(self, drho):
+        return self._lin("orc_tl_poisson", [drho], [self.N, self.N + 1])
+
+    def ad_poisson(self, lez, ler):
+        return self._lin("orc_ad_poisson", [lez, ler], [self.N + 1])
 
     def gauss(self):
         g = np.zeros(self.N + 1)

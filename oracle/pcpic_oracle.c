@@ -596,6 +596,141 @@ static void orc_poisson_transpose(int64_t N, double bdiag, const double *g, doub
     for (int64_t i = N - 1; i >= 1; --i) y[i] = dp[i] - cp[i] * y[i + 1];
 }
 
+/* ---- the linearised kernels of one step (frozen discrete decisions) ------ */
+
+/* Adjoint of B^{s+1/2} through its uses in E_r^{s+1} and E_z^{s+1} (eq. 3):
+ * B^{s+1/2} enters E_r,i and E_r,i+1 (the mirror node N with the factor 2) and E_z. */
+static void orc_adj_b_uses(int64_t N, const orc_const *k, const double *lb, const double *lez, const double *ler,
+                           double *lbp)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        double a = lb[i] + k->dtR * lez[i];
+        if (i >= 1 && i <= N - 1) a -= k->dtdz * ler[i];
+        if (i + 1 <= N - 1) a += k->dtdz * ler[i + 1];
+        if (i == N - 1) a += k->tw * ler[N];
+        lbp[i] = a;
+    }
+}
+
+/* Adjoints of E_z^s, E_r^s and B^{s-1/2} from lbp (above) and the adjoint lk of
+ * the kick array K = (q/m) dt E_z^s, in place (E_r's update uses lbp only). */
+static void orc_adj_fields_back(int64_t N, const orc_const *k, double *lez, double *ler, double *lb,
+                                const double *lbp, const double *lk)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        const double a = lez[i] - k->dtR * lbp[i] + k->qmdt * lk[i];
+        lez[i] = a;
+    }
+    for (int64_t i = N; i >= 0; --i) {
+        double a = ler[i];
+        if (i <= N - 1) a += k->dtdz * lbp[i];
+        if (i >= 1) a -= k->dtdz * lbp[i - 1];
+        ler[i] = a;
+    }
+    for (int64_t i = 0; i < N; ++i) lb[i] = lbp[i];
+}
+
+/* The linearised push of one particle at (x, u) in the kick array K: gather,
+ * eq. (1), the move and the current J_i = S_i(x) - S_i(x1), with its cells
+ * frozen and rint taken as the identity (dS_i/dx = -2^P in cell i).  What it
+ * needs of the forward: */
+typedef struct {
+    int clamp;            /* 1: x below the first face, 2: above the last face, 0: interpolated */
+    int64_t jj;           /* lower face of the interpolation */
+    double g, dEdx;       /* interpolation weight of the upper face; K_{j+1} - K_j */
+    double u1, gam;       /* new momentum and gamma */
+    int64_t c0, c1;       /* cells before and after the move (c1 = N: left the tube; < 0: returned) */
+    int64_t F0, F1;       /* fixed-point offsets (the rate gradient's deposit) */
+    int fate;             /* 0: stays, 1: exits at the top, 2: absorbed by the star */
+} orc_lin_pt;
+
+static void orc_lin_point(int64_t N, int P, const orc_const *k, const double *kk, double x, double u, orc_lin_pt *q)
+{
+    const double sx = x - 0.5;
+    q->jj = 0;
+    q->g = 0.0;
+    q->dEdx = 0.0;
+    q->clamp = 0;
+    if (sx < 0.0) { q->clamp = 1; }
+    else if (sx >= (double)(N - 1)) { q->clamp = 2; }
+    else {
+        q->jj = (int64_t)floor(sx);
+        q->g = sx - (double)q->jj;
+        q->dEdx = kk[q->jj + 1] - kk[q->jj];
+    }
+    const double E = q->clamp == 1 ? kk[0] : (q->clamp == 2 ? kk[N - 1] : kk[q->jj] + q->g * (kk[q->jj + 1] - kk[q->jj]));
+    q->u1 = u + E;
+    double t = q->u1 * q->u1;
+    t = 1.0 + t;
+    q->gam = sqrt(t);
+    const double v = q->u1 / q->gam;
+    const double x1 = x + k->dtdz * v;
+    orc_cell(x, P, &q->c0, &q->F0);
+    orc_cell(x1, P, &q->c1, &q->F1);
+    q->fate = x1 >= (double)N ? 1 : (x1 < 0.0 ? 2 : 0);
+}
+
+/* Transpose of the linearised push of one particle: from the adjoints lx1, lu1
+ * of its new state (lu1 of an exit is the loss's seed d gamma/du / n_exit) and
+ * lj (the adjoint of the current J, already multiplied by the particle's charge
+ * factor), the adjoints of its old state and its part of lk (accumulated). */
+static void orc_adj_particle(int64_t N, const orc_const *k, const orc_lin_pt *q, double lx1, double lu1,
+                             const double *lj, double wcls, double *lx, double *lu, double *lk)
+{
+    const double twoP = k->twoP;
+    /* current: J_i = S_i(x) - S_i(x1), dS_i/dx = -2^P in cell i */
+    if (q->c1 >= 0 && q->c1 < N) lx1 += twoP * (wcls * lj[q->c1]);
+    const double lx0J = -twoP * (wcls * lj[q->c0]);
+    /* move: x1 = x + (dt/dz) u1 / gamma(u1), dv/du = 1/gamma^3 */
+    const double gam = q->gam;
+    const double lu1t = lu1 + lx1 * k->dtdz / (gam * gam * gam);
+    *lx = lx1 + lx0J + lu1t * q->dEdx;
+    *lu = lu1t;
+    /* kick: E = K_j (1 - g) + K_{j+1} g */
+    if (q->clamp == 1) lk[0] += lu1t;
+    else if (q->clamp == 2) lk[N - 1] += lu1t;
+    else { lk[q->jj] += lu1t * (1.0 - q->g); lk[q->jj + 1] += lu1t * q->g; }
+}
+
+/* The same linearised push, forward (tangent): perturbations dx, du of the old
+ * state and dk of the kick array give dx1, du1 and the particle's current
+ * perturbation (added to dj). */
+static void orc_tl_particle(int64_t N, const orc_const *k, const orc_lin_pt *q, double dx, double du, const double *dk,
+                            double *dx1, double *du1, double *dj)
+{
+    const double twoP = k->twoP;
+    double dE;
+    if (q->clamp == 1) dE = dk[0];
+    else if (q->clamp == 2) dE = dk[N - 1];
+    else dE = q->dEdx * dx + (1.0 - q->g) * dk[q->jj] + q->g * dk[q->jj + 1];
+    const double d1 = du + dE;
+    const double gam = q->gam;
+    const double dv = d1 / (gam * gam * gam);
+    *du1 = d1;
+    *dx1 = dx + k->dtdz * dv;
+    dj[q->c0] += -twoP * dx;
+    if (q->c1 >= 0 && q->c1 < N) dj[q->c1] += twoP * (*dx1);
+}
+
+/* Transposed Poisson start (eq. 4): dL/d rho_GJ at the nodes from the adjoints of
+ * the start fields E_z = -dphi/dz, E_r = phi/R, A phi = d, d_i = -cpois (rho_i - rho_GJ,i). */
+static void orc_adj_poisson(const orc_cfg *c, const orc_const *k, const double *lez, const double *ler, double *g_rho)
+{
+    const int64_t N = k->N;
+    double *gphi = calloc((size_t)(N + 1), sizeof(double)), *y = calloc((size_t)(N + 1), sizeof(double));
+    double *cp = calloc((size_t)(N + 1), sizeof(double)), *dp = calloc((size_t)(N + 1), sizeof(double));
+    for (int64_t m = 1; m <= N; ++m) {
+        double a = -lez[m - 1] / k->dz + ler[m] / c->radius;
+        if (m <= N - 1) a += lez[m] / k->dz;
+        gphi[m] = a;
+    }
+    const double rr = k->dz / c->radius;
+    orc_poisson_transpose(N, -(2.0 + rr * rr), gphi, y, cp, dp);
+    g_rho[0] = 0.0;
+    for (int64_t i = 1; i <= N; ++i) g_rho[i] = k->fourpi * (k->dz * k->dz) * y[i];
+    free(gphi); free(y); free(cp); free(dp);
+}
+
 int orc_adjoint(const orc_cfg *c, orc_state *st, int64_t T, double *g_rho, double *g_rate, double *loss,
                 int64_t *n_exit_out)
 {
@@ -606,7 +741,6 @@ int orc_adjoint(const orc_cfg *c, orc_state *st, int64_t T, double *g_rho, doubl
     const int64_t N = k.N;
     const int P = c->fp_bits;
     const double rate = c->inj_rate > 0.0 ? c->inj_rate : 1.0;
-    const double twoP = k.twoP;
 
     /* ---- forward, recording every step's starting state ---- */
     int64_t *n_at = malloc(sizeof(int64_t) * (size_t)(T + 1));
@@ -644,115 +778,159 @@ int orc_adjoint(const orc_cfg *c, orc_state *st, int64_t T, double *g_rho, doubl
     double *lez = calloc((size_t)N, sizeof(double)), *ler = calloc((size_t)(N + 1), sizeof(double));
     double *lb = calloc((size_t)N, sizeof(double)), *lbp = calloc((size_t)N, sizeof(double));
     double *lk = calloc((size_t)N, sizeof(double)), *kk = calloc((size_t)N, sizeof(double));
+    double *lj = calloc((size_t)N, sizeof(double));
     double grate = 0.0;
     for (int64_t s = T - 1; s >= 0; --s) {
         const double *ez = EZ + s * N;
         for (int64_t i = 0; i < N; ++i) { kk[i] = k.qmdt * ez[i]; lk[i] = 0.0; }
         /* adjoint of B^{s+1/2}: its own adjoint plus its uses in E_r and E_z of step s */
-        for (int64_t i = 0; i < N; ++i) {
-            double a = lb[i] + k.dtR * lez[i];
-            if (i >= 1 && i <= N - 1) a -= k.dtdz * ler[i];
-            if (i + 1 <= N - 1) a += k.dtdz * ler[i + 1];
-            if (i == N - 1) a += k.tw * ler[N];
-            lbp[i] = a;
-        }
+        orc_adj_b_uses(N, &k, lb, lez, ler, lbp);
+        /* the current enters E_z^{s+1} = ... - c4 J */
+        for (int64_t i = 0; i < N; ++i) lj[i] = -k.c4 * lez[i];
         /* particles of step s (in order; survivors keep their order at step s+1) */
         const int64_t n = n_at[s];
         double *nlx = calloc((size_t)(n + 1), sizeof(double)), *nlu = calloc((size_t)(n + 1), sizeof(double));
         int64_t jn = 0;
         for (int64_t p = 0; p < n; ++p) {
-            const double x = X[s][p], u = U[s][p];
             const double wcls = C[s][p] ? rate : 1.0;
-            const double sx = x - 0.5;
-            int64_t jj = 0;
-            double g = 0.0, dEdx = 0.0;
-            int clamp = 0;
-            if (sx < 0.0) { clamp = 1; }
-            else if (sx >= (double)(N - 1)) { clamp = 2; }
-            else {
-                jj = (int64_t)floor(sx);
-                g = sx - (double)jj;
-                dEdx = kk[jj + 1] - kk[jj];
-            }
-            const double E = clamp == 1 ? kk[0] : (clamp == 2 ? kk[N - 1] : kk[jj] + g * (kk[jj + 1] - kk[jj]));
-            const double u1 = u + E;
-            double t = u1 * u1;
-            t = 1.0 + t;
-            const double gam = sqrt(t);
-            const double v = u1 / gam;
-            const double x1 = x + k.dtdz * v;
-            int64_t c0, F0, c1, F1;
-            orc_cell(x, P, &c0, &F0);
-            orc_cell(x1, P, &c1, &F1);
+            orc_lin_pt q;
+            orc_lin_point(N, P, &k, kk, X[s][p], U[s][p], &q);
             double lx1 = 0.0, lu1 = 0.0;
-            if (x1 >= (double)N) {
-                lu1 = nex > 0 ? (u1 / gam) / (double)nex : 0.0;   /* d gamma / du = u / gamma */
-            } else if (x1 < 0.0) {
-                /* absorbed: no further influence */
-            } else {
+            if (q.fate == 1) {
+                lu1 = nex > 0 ? (q.u1 / q.gam) / (double)nex : 0.0;   /* d gamma / du = u / gamma */
+            } else if (q.fate == 0) {
                 lx1 = lx[jn];
                 lu1 = lu[jn];
                 ++jn;
-            }
-            /* current: J_i = S_i(x) - S_i(x1), dS_i/dx = -2^P in cell i, scaled by the
-             * particle's charge factor; E_z^{s+1} = ... - c4 * J */
-            if (c1 >= 0 && c1 < N) lx1 += twoP * (-k.c4 * wcls * lez[c1]);
-            const double lx0J = -twoP * (-k.c4 * wcls * lez[c0]);
+            }                                                          /* absorbed: no further influence */
             if (C[s][p]) {
-                /* dL/d rate: the particle's deposit times -c4 times the adjoint of E_z^{s+1} */
-                int64_t lo = c0 < c1 ? c0 : c1, hi = c0 < c1 ? c1 : c0;
+                /* dL/d rate: the particle's deposit times the adjoint of the current */
+                int64_t lo = q.c0 < q.c1 ? q.c0 : q.c1, hi = q.c0 < q.c1 ? q.c1 : q.c0;
                 if (lo < 0) lo = 0;
                 if (hi > N - 1) hi = N - 1;
                 for (int64_t i = lo; i <= hi; ++i)
-                    grate += (double)(orc_S(i, c0, F0, k.oneP) - orc_S(i, c1, F1, k.oneP)) * (-k.c4) * lez[i];
+                    grate += (double)(orc_S(i, q.c0, q.F0, k.oneP) - orc_S(i, q.c1, q.F1, k.oneP)) * lj[i];
             }
-            /* move: x1 = x + (dt/dz) u1 / gamma(u1), dv/du = 1/gamma^3 */
-            const double lu1t = lu1 + lx1 * k.dtdz / (gam * gam * gam);
-            nlx[p] = lx1 + lx0J + lu1t * dEdx;
-            nlu[p] = lu1t;
-            /* kick: E = K_j (1 - g) + K_{j+1} g */
-            if (clamp == 1) lk[0] += lu1t;
-            else if (clamp == 2) lk[N - 1] += lu1t;
-            else { lk[jj] += lu1t * (1.0 - g); lk[jj + 1] += lu1t * g; }
+            orc_adj_particle(N, &k, &q, lx1, lu1, lj, wcls, &nlx[p], &nlu[p], lk);
         }
         free(lx);
         free(lu);
         lx = nlx;
         lu = nlu;
         /* fields of step s: E_z^{s+1} = E_z + dtR B' - c4 J; B' = B - (dtdz (E_r,i+1 - E_r,i) + dtR E_z) */
-        for (int64_t i = 0; i < N; ++i) {
-            const double a = lez[i] - k.dtR * lbp[i] + k.qmdt * lk[i];
-            lez[i] = a;
-        }
-        double *nler = calloc((size_t)(N + 1), sizeof(double));
-        for (int64_t i = 0; i <= N; ++i) {
-            double a = ler[i];
-            if (i <= N - 1) a += k.dtdz * lbp[i];
-            if (i >= 1) a -= k.dtdz * lbp[i - 1];
-            nler[i] = a;
-        }
-        free(ler);
-        ler = nler;
-        for (int64_t i = 0; i < N; ++i) lb[i] = lbp[i];
+        orc_adj_fields_back(N, &k, lez, ler, lb, lbp, lk);
     }
-    /* Poisson start (eq. 4): E_z = -dphi/dz, E_r = phi/R, A phi = d, d_i = -cpois (rho_i - rho_GJ,i) */
-    if (g_rho) {
-        double *gphi = calloc((size_t)(N + 1), sizeof(double)), *y = calloc((size_t)(N + 1), sizeof(double));
-        double *cp = calloc((size_t)(N + 1), sizeof(double)), *dp = calloc((size_t)(N + 1), sizeof(double));
-        for (int64_t m = 1; m <= N; ++m) {
-            double a = -lez[m - 1] / k.dz + ler[m] / c->radius;
-            if (m <= N - 1) a += lez[m] / k.dz;
-            gphi[m] = a;
-        }
-        const double rr = k.dz / c->radius;
-        orc_poisson_transpose(N, -(2.0 + rr * rr), gphi, y, cp, dp);
-        g_rho[0] = 0.0;
-        for (int64_t i = 1; i <= N; ++i) g_rho[i] = k.fourpi * (k.dz * k.dz) * y[i];
-        free(gphi); free(y); free(cp); free(dp);
-    }
+    /* Poisson start (eq. 4) */
+    if (g_rho) orc_adj_poisson(c, &k, lez, ler, g_rho);
     if (g_rate) *g_rate = grate;
     for (int64_t s = 0; s < T; ++s) { free(X[s]); free(U[s]); free(C[s]); }
     free(X); free(U); free(C); free(EZ); free(ER); free(BB); free(n_at);
-    free(lx); free(lu); free(lez); free(ler); free(lb); free(lbp); free(lk); free(kk);
+    free(lx); free(lu); free(lez); free(ler); free(lb); free(lbp); free(lk); free(kk); free(lj);
+    return 0;
+}
+
+/* ---- test hooks: the linearised kernels one by one (dot-product pins) ------ */
+
+int orc_tl_fields(const orc_cfg *c, const orc_state *st, const double *dez, const double *der, const double *db,
+                  const double *dj, double *dez1, double *der1, double *db1)
+{
+    if (orc_check(c) || !st) return -1;
+    orc_const k;
+    orc_consts(c, st, &k);
+    const int64_t N = k.N;
+    for (int64_t i = 0; i < N; ++i) db1[i] = db[i] - (k.dtdz * (der[i + 1] - der[i]) + k.dtR * dez[i]);
+    der1[0] = der[0];
+    for (int64_t i = 1; i < N; ++i) der1[i] = der[i] - k.dtdz * (db1[i] - db1[i - 1]);
+    der1[N] = der[N] + k.tw * db1[N - 1];
+    for (int64_t i = 0; i < N; ++i) dez1[i] = (dez[i] + k.dtR * db1[i]) - k.c4 * dj[i];
+    return 0;
+}
+
+int orc_ad_fields(const orc_cfg *c, const orc_state *st, const double *lez1, const double *ler1, const double *lb1,
+                  double *lez, double *ler, double *lb, double *lj)
+{
+    if (orc_check(c) || !st) return -1;
+    orc_const k;
+    orc_consts(c, st, &k);
+    const int64_t N = k.N;
+    double *lbp = calloc((size_t)N, sizeof(double)), *lk = calloc((size_t)N, sizeof(double));
+    if (!lbp || !lk) { free(lbp); free(lk); return -2; }
+    orc_adj_b_uses(N, &k, lb1, lez1, ler1, lbp);
+    for (int64_t i = 0; i < N; ++i) { lez[i] = lez1[i]; lb[i] = lb1[i]; lj[i] = -k.c4 * lez1[i]; }
+    for (int64_t i = 0; i <= N; ++i) ler[i] = ler1[i];
+    orc_adj_fields_back(N, &k, lez, ler, lb, lbp, lk);
+    free(lbp);
+    free(lk);
+    return 0;
+}
+
+int orc_tl_push(const orc_cfg *c, const orc_state *st, const double *dx, const double *du, const double *dk,
+                double *dx1, double *du1, double *dj)
+{
+    if (orc_check(c) || !st) return -1;
+    orc_const k;
+    orc_consts(c, st, &k);
+    const int64_t N = k.N;
+    for (int64_t i = 0; i < N; ++i) dj[i] = 0.0;
+    for (int64_t p = 0; p < st->n; ++p) {
+        orc_lin_pt q;
+        orc_lin_point(N, c->fp_bits, &k, st->k, st->x[p], st->u[p], &q);
+        orc_tl_particle(N, &k, &q, dx[p], du[p], dk, &dx1[p], &du1[p], dj);
+    }
+    return 0;
+}
+
+int orc_ad_push(const orc_cfg *c, const orc_state *st, const double *lx1, const double *lu1, const double *lj,
+                double *lx, double *lu, double *lk)
+{
+    if (orc_check(c) || !st) return -1;
+    orc_const k;
+    orc_consts(c, st, &k);
+    const int64_t N = k.N;
+    for (int64_t i = 0; i < N; ++i) lk[i] = 0.0;
+    for (int64_t p = 0; p < st->n; ++p) {
+        orc_lin_pt q;
+        orc_lin_point(N, c->fp_bits, &k, st->k, st->x[p], st->u[p], &q);
+        orc_adj_particle(N, &k, &q, lx1[p], lu1[p], lj, 1.0, &lx[p], &lu[p], lk);
+    }
+    return 0;
+}
+
+int orc_tl_poisson(const orc_cfg *c, const orc_state *st, const double *drho, double *dez, double *der)
+{
+    if (orc_check(c) || !st) return -1;
+    orc_const k;
+    orc_consts(c, st, &k);
+    const int64_t N = k.N;
+    double *d = calloc((size_t)(N + 1), sizeof(double)), *cp = calloc((size_t)(N + 1), sizeof(double));
+    double *phi = calloc((size_t)(N + 1), sizeof(double));
+    if (!d || !cp || !phi) { free(d); free(cp); free(phi); return -2; }
+    const double rr = k.dz / c->radius;
+    const double bdiag = -(2.0 + rr * rr);
+    const double cpois = k.fourpi * (k.dz * k.dz);
+    for (int64_t i = 1; i <= N; ++i) d[i] = cpois * drho[i];   /* d_i = -cpois (rho_i - rho_GJ,i) */
+    cp[1] = 1.0 / bdiag;
+    d[1] = d[1] / bdiag;
+    for (int64_t i = 2; i <= N; ++i) {
+        const double sub = (i == N) ? 2.0 : 1.0;   /* row N: the mirror ghost doubles the sub-diagonal */
+        const double m = bdiag - sub * cp[i - 1];
+        cp[i] = 1.0 / m;
+        d[i] = (d[i] - sub * d[i - 1]) / m;
+    }
+    phi[0] = 0.0;
+    phi[N] = d[N];
+    for (int64_t i = N - 1; i >= 1; --i) phi[i] = d[i] - cp[i] * phi[i + 1];
+    for (int64_t i = 0; i < N; ++i) dez[i] = -((phi[i + 1] - phi[i]) / k.dz);
+    for (int64_t i = 0; i <= N; ++i) der[i] = phi[i] / c->radius;
+    free(d); free(cp); free(phi);
+    return 0;
+}
+
+int orc_ad_poisson(const orc_cfg *c, const orc_state *st, const double *lez, const double *ler, double *lrho)
+{
+    if (orc_check(c) || !st) return -1;
+    orc_const k;
+    orc_consts(c, st, &k);
+    orc_adj_poisson(c, &k, lez, ler, lrho);
     return 0;
 }

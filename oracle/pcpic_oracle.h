@@ -145,6 +145,27 @@ int orc_profile(const orc_cfg *cfg, const orc_state *st, int32_t nb, int64_t *co
 int orc_adjoint(const orc_cfg *cfg, orc_state *st, int64_t n_steps, double *g_rho, double *g_rate,
                 double *loss, int64_t *n_exit);
 
+/* Test hooks: the linearised kernels of one step, each as a tangent (tl) and
+ * its transpose (ad), for dot-product pins of the reverse sweep: <ad(l), d> must
+ * equal <l, tl(d)>.  The ad functions are the ones orc_adjoint applies.
+ *  fields  -- the leap-frog of eq. (3), linear: (dez, der, db, dj) -> (dez1, der1,
+ *             db1), dj the current in fixed-point units (real-valued);
+ *  push    -- gather, eq. (1), move and current of the particles of st in the kick
+ *             array st->k, every fate and cell frozen and rint taken as the
+ *             identity: (dx, du, dk) -> (dx1, du1, dj); every particle keeps its
+ *             new state as an output, including those that leave or return;
+ *  poisson -- the start fields of eq. (4) as a function of rho_GJ: drho -> (dez, der). */
+int orc_tl_fields(const orc_cfg *cfg, const orc_state *st, const double *dez, const double *der, const double *db,
+                  const double *dj, double *dez1, double *der1, double *db1);
+int orc_ad_fields(const orc_cfg *cfg, const orc_state *st, const double *lez1, const double *ler1, const double *lb1,
+                  double *lez, double *ler, double *lb, double *lj);
+int orc_tl_push(const orc_cfg *cfg, const orc_state *st, const double *dx, const double *du, const double *dk,
+                double *dx1, double *du1, double *dj);
+int orc_ad_push(const orc_cfg *cfg, const orc_state *st, const double *lx1, const double *lu1, const double *lj,
+                double *lx, double *lu, double *lk);
+int orc_tl_poisson(const orc_cfg *cfg, const orc_state *st, const double *drho, double *dez, double *der);
+int orc_ad_poisson(const orc_cfg *cfg, const orc_state *st, const double *lez, const double *ler, double *lrho);
+
 #ifdef __cplusplus
 }
 #endif

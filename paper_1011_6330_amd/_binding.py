@@ -104,6 +104,9 @@ SIGNATURES = {
     "pic_adjoint_tape_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32]),
     "pic_run_adjoint": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.POINTER(PicAdjointOut)]),
+    "pic_adjoint_forward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.POINTER(PicAdjointOut)]),
+    "pic_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(PicAdjointOut)]),
     "pic_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PicParams), ctypes.c_int32]),
     "pic_init_batch": (ctypes.c_int32, [ctypes.POINTER(PicParams), ctypes.c_int32, ctypes.c_void_p,
                                         ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -288,6 +291,37 @@ class Tube(_TubeOps):
         return dict(loss=out.loss, n_exit=out.n_exit, g_rate=out.g_rate, g_kappa=out.g_kappa, g_amp=out.g_amp,
                     g_rho=g_rho, g_knots=g_knots[:nk], forward_ms=out.forward_ms, backward_ms=out.backward_ms,
                     tape_bytes=nbytes)
+
+    def adjoint_forward(self, n_steps, checkpoint_every=50, tape=None):
+        """The checkpointed forward of the adjoint (pic_adjoint_forward): advances
+        the tube and records the run for backward(); returns loss, n_exit and the
+        forward's device time.  The tape (a torch uint8 tensor, allocated here when
+        not given) is kept on the tube until the next adjoint_forward."""
+        import torch
+        nbytes = self.lib.pic_adjoint_tape_bytes(self._h, int(n_steps), int(checkpoint_every))
+        if nbytes == 0:
+            raise PicError(-1, "pic_adjoint_tape_bytes", self.lib.pic_last_error().decode())
+        if tape is None or tape.numel() < nbytes:
+            with torch.cuda.device(self.device):
+                tape = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._tape = tape
+        out = PicAdjointOut()
+        _check(self.lib.pic_adjoint_forward(self._h, int(n_steps), int(checkpoint_every),
+                                            ctypes.c_void_p(tape.data_ptr()), nbytes, ctypes.byref(out)),
+               "pic_adjoint_forward")
+        return dict(loss=out.loss, n_exit=out.n_exit, forward_ms=out.forward_ms, tape_bytes=nbytes)
+
+    def backward(self, dloss=1.0):
+        """The reverse sweep of the recorded forward (pic_backward), scaled by dloss."""
+        out = PicAdjointOut()
+        g_rho = np.zeros(self.N + 1)
+        nk = 0 if self.cfg.get("knots") is None else len(self.cfg["knots"])
+        g_knots = np.zeros(max(nk, 1))
+        out.g_rho = _ptr(g_rho)
+        out.g_knots = _ptr(g_knots)
+        _check(self.lib.pic_backward(self._h, float(dloss), ctypes.byref(out)), "pic_backward")
+        return dict(loss=out.loss, n_exit=out.n_exit, g_rate=out.g_rate, g_kappa=out.g_kappa, g_amp=out.g_amp,
+                    g_rho=g_rho, g_knots=g_knots[:nk], forward_ms=out.forward_ms, backward_ms=out.backward_ms)
 
     def diagnostics(self, n_bins=0, gauss=False, fields=True, j=False, weights=False, rho=False,
                     raise_on_status=True):

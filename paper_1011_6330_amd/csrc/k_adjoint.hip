@@ -4,12 +4,13 @@
 //
 // One reverse step s, given the adjoints of the state after the step
 // (particles lx, lu per slot; fields lez = dL/dE_z^{s+1}, ler = dL/dE_r^{s+1},
-// lb = dL/dB^{s+1/2}) and the recorded state before it (slots X_s, U_s, fields):
-//   1. lbp = dL/dB^{s+1/2} through its uses in E_r^{s+1} and E_z^{s+1}; clear lk;
-//   2. per slot: recompute the push, route the adjoints through the move, the
+// lb = dL/dB^{s+1/2}) and the recorded state before it (slots X_s, U_s, E_z^s),
+// plus lbp = dL/dB^{s+1/2} through its uses in E_r^{s+1} and E_z^{s+1}:
+//   1. per slot: recompute the push, route the adjoints through the move, the
 //      gather (into lk, the adjoint of the kick array) and the fixed-point
 //      current (J enters E_z^{s+1} with weight -c4);
-//   3. lez, ler, lb <- adjoints of E^s, B^{s-1/2} (transposed leap-frog of eq. 3).
+//   2. lez, ler, lb <- adjoints of E^s, B^{s-1/2} (transposed leap-frog of
+//      eq. 3), and lbp of step s-1 from them.
 // After step 0 the field adjoints go through the transposed Poisson problem of
 // eq. (4) to dL/d rho_GJ.  Slots keep their particle across steps (no sort in an
 // adjoint run), so the particle adjoints are updated in place.
@@ -27,14 +28,85 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
+// ---- order-independent sums --------------------------------------------
+//
+// Several waves add to the same word (the kick adjoint of a face, the rate
+// gradient).  Each wave's partial sum is formed in a fixed lane order, then
+// rounded to a multiple of the quantum 2^(e - 60), where the exponent e of the
+// reverse step bounds every partial sum of the step by 2^e (adj_exponent), and
+// added as an integer below 2^60 split into its low 32 bits and the rest: two
+// integer atomics into an unsigned low word and a signed high word, which hold
+// the sums of up to 2^32 addends exactly.  The total does not depend on the
+// order in which the waves arrive, so the gradient is the same bits on every
+// run; the rounding is 2^-60 of the step's bound.
+
+// dst += v (|v| < 2^e) in units of 2^(e - 60), rounded to nearest.
+__device__ __forceinline__ void fixed_add(unsigned long long *lo, long long *hi, double v, int e)
+{
+    const long long t = (long long)rint(ldexp(v, 60 - e));
+    const unsigned long long tl = (unsigned long long)t & 0xffffffffull;
+    const long long th = t >> 32;
+    if (tl) atomicAdd(lo, tl);
+    if (th) atomicAdd((unsigned long long *)hi, (unsigned long long)th);
+}
+
+// The word pair (lo, hi) in units of 2^(e - 60) as a double.
+__device__ __forceinline__ double double_of(unsigned long long lo, long long hi, int e)
+{
+    return ldexp((double)hi * 0x1p32 + (double)lo, e - 60);
+}
+
+// Smallest e with b < 2^e (b >= 0), kept above the subnormal range.
+__device__ __forceinline__ int adj_exponent(double b)
+{
+    int ex = -900;
+    if (b > 0.0) (void)frexp(b, &ex);                  // b = f 2^ex, 0.5 <= f < 1
+    return ex < -900 ? -900 : ex;
+}
+
+__device__ __forceinline__ double max_of_bits(unsigned long long b) { return __builtin_bit_cast(double, b); }
+
+// Wave maximum of |v| (non-negative doubles order as their bit images) into *dst.
+__device__ __forceinline__ void wave_max_abs(unsigned long long *dst, double v)
+{
+    const long long m = wave_max_i64(__builtin_bit_cast(long long, fabs(v)));
+    if (__lane_id() == 0 && m != 0) atomicMax(dst, (unsigned long long)m);
+}
+
+// Block maximum of |a| and |b| (256 threads) into *da and *db: one atomic per
+// block and quantity, skipped when the word already holds as much (it only
+// grows, so a stale read costs at most a redundant atomic).  Every thread of
+// the block must call it.
+__device__ __forceinline__ void block_max_abs2(unsigned long long *da, unsigned long long *db, double a, double b)
+{
+    __shared__ long long s_m[2][4];
+    const long long ma = wave_max_i64(__builtin_bit_cast(long long, fabs(a)));
+    const long long mb = wave_max_i64(__builtin_bit_cast(long long, fabs(b)));
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0) {
+        s_m[0][w] = ma;
+        s_m[1][w] = mb;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        long long m = s_m[threadIdx.x][0];
+        for (int k = 1; k < 4; ++k) m = s_m[threadIdx.x][k] > m ? s_m[threadIdx.x][k] : m;
+        unsigned long long *d = threadIdx.x == 0 ? da : db;
+        if (m != 0 && (unsigned long long)m > __hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(d, (unsigned long long)m);
+    }
+}
+
 // dst[key] += val for every lane with `want`: lanes with the same key in
-// consecutive positions form a run, a segmented DPP scan sums each run, and the
-// run's last lane issues one FP64 atomic.  Wave-collective.
-__device__ __forceinline__ void wave_add_runs_f64(double *dst, int key, double val, bool want)
+// consecutive positions form a run, a segmented DPP scan sums each run in lane
+// order, and the run's last lane adds the run total in fixed point.
+// Wave-collective.
+__device__ __forceinline__ void wave_add_runs_fixed(unsigned long long *lo, long long *hi, int key, double val,
+                                                    bool want, int e)
 {
     const WaveRun r = wave_runs_i32(key, want);
     const double s = run_sum_to_tail(want ? val : 0.0, r.rank);
-    if (want && (int)__lane_id() == r.end - 1 && s != 0.0) atomicAdd(dst + key, s);
+    if (want && (int)__lane_id() == r.end - 1 && s != 0.0) fixed_add(lo + key, hi + key, s, e);
 }
 
 __global__ __launch_bounds__(256) void k_copy_slots(const double *X, const double *U, double *Xc, double *Uc,
@@ -57,20 +129,25 @@ __global__ __launch_bounds__(256) void k_fill_f64(double *p, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0;
 }
 
-// 1. adjoint of B^{s+1/2}: its own adjoint and its uses in E_r^{s+1} (nodes i,
-//    i+1; node N through the mirror term) and in E_z^{s+1}.
-__global__ __launch_bounds__(256) void k_adj_fields1(Consts c, const double *lez, const double *ler,
-                                                     const double *lb, double *lbp, double *lk)
+// The quanta of a reverse step from the maxima of the adjoints it starts from
+// (word set k, filled by the step before):
+//   |lu1t| <= max(max|lu|, 1/n_exit) + (dt/dz)(max|lx| + 2^P |c4| max|lez|)
+// bounds every particle's kick-adjoint addend (gamma >= 1), and a run of the
+// wave adds at most 64 of them; a particle's rate-gradient term is at most
+// 2 2^P |c4| max|lez|, 64 of them per wave.  Every block that needs the
+// exponents forms them from the same words, so they agree everywhere.  The
+// word sets rotate over three: step r reads set r mod 3, fills set r+1 and
+// clears set r+2.
+__device__ __forceinline__ void step_exponents(const Consts &c, const AdjScale *sc, int k, int64_t n_exit, int &e_k,
+                                               int &e_g)
 {
-    const int64_t N = c.N;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= N) return;
-    double a = lb[i] + c.dtR * lez[i];
-    if (i >= 1 && i <= N - 1) a -= c.dtdz * ler[i];
-    if (i + 1 <= N - 1) a += c.dtdz * ler[i + 1];
-    if (i == N - 1) a += c.tw * ler[N];
-    lbp[i] = a;
-    lk[i] = 0.0;
+    const double mlu = max_of_bits(sc->max_lu[k]), mlx = max_of_bits(sc->max_lx[k]);
+    const double mlez = max_of_bits(sc->max_lez[k]);
+    const double seed = n_exit > 0 ? 1.0 / (double)n_exit : 0.0;
+    const double lj = c.twoP * fabs(c.c4) * mlez;
+    const double bound = (mlu > seed ? mlu : seed) + c.dtdz * (mlx + lj);
+    e_k = adj_exponent(64.0 * bound);
+    e_g = adj_exponent(128.0 * lj);
 }
 
 struct AdjPartArgs {
@@ -82,8 +159,10 @@ struct AdjPartArgs {
     int64_t n_exit;           // exits of the whole run (loss normalisation)
     double *lx, *lu;          // slot adjoints, in place
     const double *lez;        // dL/dE_z^{s+1}
-    double *lk;               // dL/dK^s (accumulated)
-    double *grate;            // dL/d(injection charge factor) (accumulated)
+    unsigned long long *lk_lo; // dL/dK^s, 128-bit fixed point (accumulated)
+    long long *lk_hi;
+    AdjScale *sc;             // quanta of the step (word set rot); maxima of the new slot adjoints (set rot + 1)
+    int rot;
 };
 
 // 2. particles: the forward push recomputed exactly, then its transpose.
@@ -92,6 +171,9 @@ __global__ __launch_bounds__(256) void k_adj_particles(Consts c, AdjPartArgs a)
     const int64_t ns = *a.n_s, nn = *a.n_next;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int N = (int)c.N;
+    int e_k, e_g;
+    step_exponents(c, a.sc, a.rot, a.n_exit, e_k, e_g);
+    double nlx = 0.0, nlu = 0.0;              // the new slot adjoints (for the next step's maxima)
     bool live = false;
     int ka = 0, kb = 0;
     double va = 0.0, vb = 0.0, gr = 0.0;
@@ -148,13 +230,15 @@ __global__ __launch_bounds__(256) void k_adj_particles(Consts c, AdjPartArgs a)
                     d0 = -F0;
                     d1 = c1 >= 0 ? F1 - c.twoP : 0.0;
                 }
-                gr += d0 * (-c.c4) * a.lez[c0];
-                if (d1 != 0.0) gr += d1 * (-c.c4) * a.lez[c1];
+                gr += d0 * (-c.c4 * a.lez[c0]);
+                if (d1 != 0.0) gr += d1 * (-c.c4 * a.lez[c1]);
             }
             // move: x1 = x + (dt/dz) u1/gamma(u1), dv/du = 1/gamma^3
             const double lu1t = lu1 + lx1 * c.dtdz / (gam * gam * gam);
-            a.lx[p] = lx1 + lx0J + lu1t * dEdx;
-            a.lu[p] = lu1t;
+            nlx = lx1 + lx0J + lu1t * dEdx;
+            nlu = lu1t;
+            a.lx[p] = nlx;
+            a.lu[p] = nlu;
             // kick: E = K_j (1 - g) + K_{j+1} g
             if (clamp == 1) { ka = 0; va = lu1t; wa = true; }
             else if (clamp == 2) { ka = N - 1; va = lu1t; wa = true; }
@@ -166,27 +250,65 @@ __global__ __launch_bounds__(256) void k_adj_particles(Consts c, AdjPartArgs a)
         a.lu[p] = 0.0;
     }
     (void)live;
-    wave_add_runs_f64(a.lk, ka, va, wa);
-    wave_add_runs_f64(a.lk, kb, vb, wb);
+    wave_add_runs_fixed(a.lk_lo, a.lk_hi, ka, va, wa, e_k);
+    wave_add_runs_fixed(a.lk_lo, a.lk_hi, kb, vb, wb, e_k);
     const double gs = wave_sum_f64(gr);
-    if (__lane_id() == 0 && gs != 0.0) atomicAdd(a.grate, gs);
+    if (__lane_id() == 0 && gs != 0.0) fixed_add(&a.sc->g_lo, &a.sc->g_hi, gs, e_g);
+    const int nx = a.rot == 2 ? 0 : a.rot + 1;
+    block_max_abs2(&a.sc->max_lx[nx], &a.sc->max_lu[nx], nlx, nlu);
 }
 
-// 3. transposed leap-frog: adjoints of E_z^s, E_r^s, B^{s-1/2}.
-__global__ __launch_bounds__(256) void k_adj_fields2(Consts c, double *lez, double *ler, double *lb,
-                                                     const double *lbp, const double *lk)
+// 2. transposed leap-frog of step s: adjoints of E_z^s, E_r^s, B^{s-1/2}, with
+//    the kick adjoint taken out of fixed point (and cleared for the next step),
+//    then lbp of step s-1: dL/dB^{s-1/2} through its uses in E_r^s and E_z^s.
+//    E_r adjoints ping-pong (ler -> lern) since lbp needs the neighbour's new
+//    E_r adjoint, which this thread forms again from the old values; lbp
+//    ping-pongs for the same reason.  The maxima of the new E_z adjoint go to
+//    word set rot + 1, set rot + 2 is cleared for the step after, and thread 0
+//    adds the step's rate gradient to the total (one addition per step, in step
+//    order) and clears the step's sum.
+__device__ __forceinline__ double ler_next(const Consts &c, const double *ler, const double *lbp, int64_t j)
+{
+    double a = ler[j];
+    if (j <= c.N - 1) a += c.dtdz * lbp[j];
+    if (j >= 1) a -= c.dtdz * lbp[j - 1];
+    return a;
+}
+
+__global__ __launch_bounds__(256) void k_adj_fields(Consts c, double *lez, const double *ler, double *lern,
+                                                    double *lb, const double *lbp, double *lbpn,
+                                                    unsigned long long *lk_lo, long long *lk_hi, AdjScale *sc,
+                                                    int rot, int64_t n_exit)
 {
     const int64_t N = c.N;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int e_k, e_g;
+    step_exponents(c, sc, rot, n_exit, e_k, e_g);
+    const int r1 = rot == 2 ? 0 : rot + 1, r2 = r1 == 2 ? 0 : r1 + 1;
+    double nez = 0.0;
+    if (i <= N) lern[i] = ler_next(c, ler, lbp, i);
     if (i < N) {
-        lez[i] = lez[i] - c.dtR * lbp[i] + c.qmdt * lk[i];
-        lb[i] = lbp[i];
+        const double lk = double_of(lk_lo[i], lk_hi[i], e_k);
+        lk_lo[i] = 0;
+        lk_hi[i] = 0;
+        nez = lez[i] - c.dtR * lbp[i] + c.qmdt * lk;
+        lez[i] = nez;
+        const double nb = lbp[i];
+        lb[i] = nb;
+        double a = nb + c.dtR * nez;
+        if (i >= 1 && i <= N - 1) a -= c.dtdz * ler_next(c, ler, lbp, i);
+        if (i + 1 <= N - 1) a += c.dtdz * ler_next(c, ler, lbp, i + 1);
+        if (i == N - 1) a += c.tw * ler_next(c, ler, lbp, N);
+        lbpn[i] = a;
     }
-    if (i <= N) {   // each thread updates only its own node
-        double a = ler[i];
-        if (i <= N - 1) a += c.dtdz * lbp[i];
-        if (i >= 1) a -= c.dtdz * lbp[i - 1];
-        ler[i] = a;
+    wave_max_abs(&sc->max_lez[r1], nez);
+    if (i == 0) {
+        sc->grate += double_of(sc->g_lo, sc->g_hi, e_g);
+        sc->g_lo = 0;
+        sc->g_hi = 0;
+        sc->max_lu[r2] = 0;
+        sc->max_lx[r2] = 0;
+        sc->max_lez[r2] = 0;
     }
 }
 
@@ -276,8 +398,6 @@ __global__ __launch_bounds__(256) void k_adj_params(Consts c, const double *knot
     __shared__ double s_red[2][4];
     const int64_t N = c.N;
     const int K = c.n_knots;
-    for (int k = threadIdx.x; k < K + 2; k += 256) out[k] = 0.0;
-    __syncthreads();
     double gk = 0.0, ga = 0.0;
     for (int64_t i = threadIdx.x; i <= N; i += 256) {
         const double gr = g_rho[i];
@@ -305,8 +425,28 @@ __global__ __launch_bounds__(256) void k_adj_params(Consts c, const double *knot
             const double g = s - (double)kk;
             const double th = knots[kk] + g * (knots[kk + 1] - knots[kk]);
             gk += gr * (th / e3);
-            atomicAdd(&out[2 + kk], gr * (-(1.0 - g) * fd));
-            atomicAdd(&out[2 + kk + 1], gr * (-g * fd));
+        }
+    }
+    // knot k: its hat weight at the nodes of its two intervals, summed in node
+    // order by one thread
+    if (c.rho_kind == PIC_RHO_KNOTS) {
+        for (int k = threadIdx.x; k < K; k += 256) {
+            double acc = 0.0;
+            const int64_t i0 = (int64_t)floor(((double)(k - 1) * (double)N) / (double)(K - 1)) - 1;
+            const int64_t i1 = (int64_t)ceil(((double)(k + 1) * (double)N) / (double)(K - 1)) + 1;
+            for (int64_t i = (i0 > 0 ? i0 : 0); i <= (i1 < N ? i1 : N); ++i) {
+                const double z = (double)i * c.dz;
+                const double s = (z * (double)(K - 1)) / c.length;
+                int kk = (int)floor(s);
+                if (kk > K - 2) kk = K - 2;
+                if (kk < 0) kk = 0;
+                if (kk != k && kk + 1 != k) continue;
+                const double g = s - (double)kk;
+                const double eta = 1.0 + z / c.r_star;
+                const double fd = 1.0 - c.kappa / (eta * eta * eta);
+                acc += g_rho[i] * (kk == k ? -(1.0 - g) * fd : -g * fd);
+            }
+            out[2 + k] = acc;
         }
     }
     gk = wave_sum_f64(gk);
@@ -347,11 +487,11 @@ hipError_t launch_zero_f64(pic_handle *h, double *p, int64_t n)
 hipError_t launch_adj_step(pic_handle *h, const AdjStepPtrs &s)
 {
     const Consts &c = h->c;
-    hipLaunchKernelGGL(k_adj_fields1, dim3(gridn(c.N)), dim3(256), 0, h->stream, c, s.lez, s.ler, s.lb, s.lbp, s.lk);
-    AdjPartArgs a{s.X, s.U, s.ez, s.n_s, s.n_next, s.n_pre, s.n_exit, s.lx, s.lu, s.lez, s.lk, s.grate};
+    AdjPartArgs a{s.X, s.U, s.ez, s.n_s, s.n_next, s.n_pre, s.n_exit, s.lx, s.lu, s.lez, s.lk_lo, s.lk_hi,
+                  s.scale, s.rot};
     hipLaunchKernelGGL(k_adj_particles, dim3(gridn(c.cap)), dim3(256), 0, h->stream, c, a);
-    hipLaunchKernelGGL(k_adj_fields2, dim3(gridn(c.N + 1)), dim3(256), 0, h->stream, c, s.lez, s.ler, s.lb, s.lbp,
-                       s.lk);
+    hipLaunchKernelGGL(k_adj_fields, dim3(gridn(c.N + 1)), dim3(256), 0, h->stream, c, s.lez, s.ler, s.lern, s.lb,
+                       s.lbp, s.lbpn, s.lk_lo, s.lk_hi, s.scale, s.rot, s.n_exit);
     return hipGetLastError();
 }
 

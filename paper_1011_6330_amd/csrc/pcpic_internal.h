@@ -179,12 +179,31 @@ struct TubeDev {
     int64_t n_keys;       // sort keys (N, or 2(N+1) in FP32-bulk mode)
 };
 
+// Scale of the fixed-point sums of the reverse sweep (see k_adjoint.hip): the
+// maxima of the adjoints a reverse step starts from (bit images of
+// non-negative doubles, in three word sets that rotate over the steps), the
+// step's fixed-point rate-gradient sum and the running total.
+struct AdjScale {
+    unsigned long long max_lu[3], max_lx[3], max_lez[3];   // word sets rotating over the reverse steps
+    unsigned long long g_lo;          // the step's rate-gradient sum, fixed point (low 32-bit parts)
+    long long g_hi;                   //   (the rest)
+    double grate;                     // dL/d rate summed over the reverse steps done, in step order
+};
+
 // Pointers of one reverse step of the adjoint (see k_adjoint.hip).
 struct AdjStepPtrs {
     const double *X, *U, *ez;        // recorded slots and E_z before the step
     const int64_t *n_s, *n_next;     // slot counts before / after the step (device)
     int64_t n_pre, n_exit;
-    double *lx, *lu, *lez, *ler, *lb, *lbp, *lk, *grate;
+    double *lx, *lu, *lez;
+    const double *ler;               // E_r adjoint after the step; lern receives the one before it
+    double *lern, *lb;
+    const double *lbp;               // dL/dB^{s+1/2} through E^{s+1}; lbpn receives that of step s-1
+    double *lbpn;
+    unsigned long long *lk_lo;       // kick adjoint, fixed point (low 32-bit parts)
+    long long *lk_hi;                //   (the rest)
+    AdjScale *scale;
+    int rot;                         // reverse steps done, mod 3 (the word set of the step's maxima)
 };
 
 // Byte layout of the workspace (offsets from the base).  Computing it with a
@@ -196,6 +215,21 @@ Workspace carve(const pic_params &p, uint8_t *base);
 int sort_sub_log2(const pic_params &p);
 
 }  // namespace pcpic
+
+// The recorded forward of an adjoint run (pic_adjoint_forward), which
+// pic_backward reverses: the caller's tape and what the sweep needs besides it.
+struct AdjRecord {
+    bool valid = false;
+    void *tape = nullptr;
+    size_t tape_bytes = 0;
+    int64_t T = 0, K = 0;       // steps, checkpoint period
+    int64_t n_pre = 0;          // slots before the run (the injected class starts here)
+    int64_t n_exit = 0;         // exits of the run (the loss's normalisation)
+    double loss = 0.0, forward_ms = 0.0;
+    int64_t step_end = 0;       // the tube's step count after the forward
+    int64_t mut = 0;            // the tube's change count after the forward
+    int jb_final = 0;           // current buffer parity after the forward
+};
 
 struct pic_handle {
     pic_params p{};
@@ -219,6 +253,8 @@ struct pic_handle {
     int32_t *d_pending = nullptr;       // batch: device list of tubes to solve together
     int n_cu = 256;
     int dev = 0;        // device ordinal current at pic_init
+    int64_t mut = 0;    // changes of the tube's state other than steps (inject, load, field or schedule writes)
+    AdjRecord adj;      // the last recorded adjoint forward
     // batch (ensemble) handles
     bool is_batch = false;
     pic_handle *parent = nullptr;               // set on the tubes of a batch

@@ -350,6 +350,7 @@ pic_status pic_inject(pic_handle *h, int64_t n, const double *x, const double *u
     if (n < 0 || (n > 0 && (!x || !u)) || (mem != 0 && mem != 1))
         return fail(PIC_EINVAL, "bad arguments to pic_inject");
     if (n == 0) return PIC_OK;
+    h->mut += 1;
     if (mem == 0) {
         for (int64_t i = 0; i < n; ++i) {
             if (!isfinite(u[i]) || !isfinite(x[i])) return fail(PIC_ENONFINITE, "particle %lld not finite", (long long)i);
@@ -849,6 +850,7 @@ pic_status pic_write_fields(pic_handle *h, const double *ez, const double *er, c
     if (pic_status sp = resolve_pending(h)) return sp;
     const int64_t N = h->c.N;
     const int f = h->fbuf;
+    h->mut += 1;
     if (ez) HIP_OK(hipMemcpyAsync(h->ws.ez[f], ez, (size_t)N * 8, hipMemcpyHostToDevice, h->stream));
     if (er) HIP_OK(hipMemcpyAsync(h->ws.er[f], er, (size_t)(N + 1) * 8, hipMemcpyHostToDevice, h->stream));
     if (b_phi) HIP_OK(hipMemcpyAsync(h->ws.b[f], b_phi, (size_t)N * 8, hipMemcpyHostToDevice, h->stream));
@@ -862,6 +864,7 @@ pic_status pic_set_injection_schedule(pic_handle *h, const int64_t *d_counts, in
     if (!h) return fail(PIC_EINVAL, "handle is NULL");
     if (h->is_batch || h->parent) return fail(PIC_ESTATE, "injection schedules are for single tubes");
     if (n < 0 || first_step < 0 || (n > 0 && !d_counts)) return fail(PIC_EINVAL, "bad schedule arguments");
+    h->mut += 1;
     h->d_sched = n > 0 ? d_counts : nullptr;
     h->sched_first = first_step;
     h->sched_n = n;
@@ -1037,6 +1040,7 @@ pic_status pic_load(pic_handle *h, const void *buf, size_t bytes)
         return fail(PIC_EINVAL, "inconsistent saved state");
     const Workspace &w = h->ws;
     const int f = h->fbuf, b = h->pbuf;
+    h->mut += 1;
     auto h2d = [&](void *dst, size_t at, size_t n) {
         return n ? hipMemcpyAsync(dst, in + at, n, hipMemcpyHostToDevice, h->stream) : hipSuccess;
     };
@@ -1401,7 +1405,10 @@ struct Tape {
     int nsets;                                              // segment slot sets (2 when segments overlap)
     std::vector<double *> sg_x[2], sg_u[2], sg_ez[2], sg_er[2], sg_b[2];   // segment slots 1..K
     int64_t *nslots;                                        // [T + 1]
-    double *lx, *lu, *lez, *ler, *lb, *lbp, *lk, *grate, *gphi, *cp, *dp, *g_rho, *params;
+    double *lx, *lu, *lez, *ler[2], *lb, *lbp[2], *gphi, *cp, *dp, *g_rho, *params;
+    unsigned long long *lk_lo;                              // kick adjoint, 128-bit fixed point
+    long long *lk_hi;
+    AdjScale *scale;
     DevCounters *final_ctr;
     int64_t *final_jlast;
     size_t bytes;
@@ -1452,11 +1459,14 @@ Tape carve_tape(pic_handle *h, int64_t T, int64_t K, uint8_t *base)
     t.lx = (double *)take(cap * 8);
     t.lu = (double *)take(cap * 8);
     t.lez = (double *)take(N * 8);
-    t.ler = (double *)take((N + 1) * 8);
+    for (int k = 0; k < 2; ++k) {
+        t.ler[k] = (double *)take((N + 1) * 8);
+        t.lbp[k] = (double *)take(N * 8);
+    }
     t.lb = (double *)take(N * 8);
-    t.lbp = (double *)take(N * 8);
-    t.lk = (double *)take(N * 8);
-    t.grate = (double *)take(8);
+    t.lk_lo = (unsigned long long *)take(N * 8);
+    t.lk_hi = (long long *)take(N * 8);
+    t.scale = (AdjScale *)take(sizeof(AdjScale));
     t.gphi = (double *)take((N + 1) * 8);
     t.cp = (double *)take((N + 1) * 8);
     t.dp = (double *)take((N + 1) * 8);
@@ -1475,101 +1485,120 @@ pic_status adjoint_supported(pic_handle *h)
     if (h->p.precision != PIC_FP64) return fail(PIC_EINVAL, "the adjoint needs PIC_FP64");
     if (h->p.sort_every != 0) return fail(PIC_EINVAL, "the adjoint needs sort_every = 0");
     if (h->p.flags & PIC_FREEZE_FIELDS) return fail(PIC_EINVAL, "the adjoint needs evolving fields");
+    if (h->c.cap > ((int64_t)1 << 31))
+        return fail(PIC_EINVAL, "the adjoint takes at most 2^31 particle slots (its fixed-point sums)");
     return PIC_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t pic_adjoint_tape_bytes(pic_handle *h, int64_t n_steps, int32_t checkpoint_every)
+// The checkpointed forward of n_steps steps (the same steps as pic_step),
+// recorded in the tape and in h->adj for the reverse sweep.
+pic_status adjoint_forward(pic_handle *h, int64_t T, int64_t K, void *d_tape, size_t tape_bytes, pic_adjoint_out *out)
 {
-    if (adjoint_supported(h) != PIC_OK) return 0;
-    if (n_steps < 1 || checkpoint_every < 1) {
-        fail(PIC_EINVAL, "n_steps and checkpoint_every must be >= 1");
-        return 0;
-    }
-    return carve_tape(h, n_steps, checkpoint_every, nullptr).bytes;
-}
-
-pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_every, void *d_tape,
-                           size_t tape_bytes, pic_adjoint_out *out)
-{
-    pic_status s = adjoint_supported(h);
-    if (s != PIC_OK) return s;
-    if (!out || n_steps < 1 || checkpoint_every < 1) return fail(PIC_EINVAL, "bad pic_run_adjoint arguments");
-    const int64_t T = n_steps, K = checkpoint_every;
-    const size_t need = carve_tape(h, T, K, nullptr).bytes;
-    if (!d_tape || tape_bytes < need) return fail(PIC_EWORKSPACE, "tape of %zu bytes, %zu needed", tape_bytes, need);
-    if (((uintptr_t)d_tape) % ALIGN) return fail(PIC_EWORKSPACE, "tape must be %zu-byte aligned", ALIGN);
     Tape t = carve_tape(h, T, K, (uint8_t *)d_tape);
     Workspace &w = h->ws;
     const int64_t N = h->c.N;
-    hipEvent_t ev[4];
+    h->adj.valid = false;
+    hipEvent_t ev[2] = {};
     for (auto &e : ev) HIP_OK(hipEventCreate(&e));
     auto done = [&](pic_status r) {
         for (auto &e : ev) (void)hipEventDestroy(e);
         return r;
     };
-    // every failure from here on also releases the timing events
-#define ADJ_OK(expr)                                                                                  \
+#define FWD_OK(expr)                                                                                  \
     do {                                                                                              \
         const hipError_t e_ = (expr);                                                                 \
         if (e_ != hipSuccess) return done(fail(PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
     } while (0)
     DevCounters c0;
-    s = read_counters(h, &c0);
+    pic_status s = read_counters(h, &c0);
     if (s != PIC_OK) return done(s);
-    const int64_t n_pre = c0.n_slots;
-
-    // ---- forward with checkpoints (the same steps as pic_step) ----
-    ADJ_OK(hipEventRecord(ev[0], h->stream));
+    FWD_OK(hipEventRecord(ev[0], h->stream));
     for (int64_t st = 0; st < T; ++st) {
         if (st % K == 0) {
             const int64_t ck = st / K;
             const int f = h->fbuf;
-            ADJ_OK(launch_copy_slots(h, w.x[h->pbuf], w.u[h->pbuf], t.ck_x[ck], t.ck_u[ck]));
-            ADJ_OK(hipMemcpyAsync(t.ck_ez[ck], w.ez[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
-            ADJ_OK(hipMemcpyAsync(t.ck_er[ck], w.er[f], (size_t)(N + 1) * 8, hipMemcpyDeviceToDevice, h->stream));
-            ADJ_OK(hipMemcpyAsync(t.ck_b[ck], w.b[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
-            ADJ_OK(hipMemcpyAsync(t.ck_ctr[ck], w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+            FWD_OK(launch_copy_slots(h, w.x[h->pbuf], w.u[h->pbuf], t.ck_x[ck], t.ck_u[ck]));
+            FWD_OK(hipMemcpyAsync(t.ck_ez[ck], w.ez[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+            FWD_OK(hipMemcpyAsync(t.ck_er[ck], w.er[f], (size_t)(N + 1) * 8, hipMemcpyDeviceToDevice, h->stream));
+            FWD_OK(hipMemcpyAsync(t.ck_b[ck], w.b[f], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+            FWD_OK(hipMemcpyAsync(t.ck_ctr[ck], w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
         }
-        ADJ_OK(launch_record_slots(h, t.nslots + st));
-        ADJ_OK(launch_push_f64(h));
-        ADJ_OK(launch_field_inject(h));
+        FWD_OK(launch_record_slots(h, t.nslots + st));
+        FWD_OK(launch_push_f64(h));
+        FWD_OK(launch_field_inject(h));
         h->fbuf ^= 1;
         h->jbuf ^= 1;
         h->step += 1;
     }
-    ADJ_OK(launch_record_slots(h, t.nslots + T));
-    ADJ_OK(hipEventRecord(ev[1], h->stream));
+    FWD_OK(launch_record_slots(h, t.nslots + T));
+    // keep what the recompute overwrites: counters and the last step's current
+    FWD_OK(hipMemcpyAsync(t.final_ctr, w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
+    FWD_OK(hipMemcpyAsync(t.final_jlast, w.j[1 - h->jbuf], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
+    FWD_OK(hipEventRecord(ev[1], h->stream));
     DevCounters c1;
     s = read_counters(h, &c1);
     if (s != PIC_OK) return done(s);
+#undef FWD_OK
     const int64_t nex = c1.n_exit - c0.n_exit;
     const __int128 e0 = ((__int128)c0.exit_hi << 64) | (__int128)c0.exit_lo;
     const __int128 e1 = ((__int128)c1.exit_hi << 64) | (__int128)c1.exit_lo;
     out->loss = nex > 0 ? ldexp((double)(e1 - e0), -32) / (double)nex : 0.0;
     out->n_exit = nex;
-    // keep what the recompute overwrites: counters and the last step's current
-    ADJ_OK(hipMemcpyAsync(t.final_ctr, w.ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
-    ADJ_OK(hipMemcpyAsync(t.final_jlast, w.j[1 - h->jbuf], (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
-    const int jb_final = h->jbuf;
+    float fms = 0;
+    (void)hipEventElapsedTime(&fms, ev[0], ev[1]);
+    out->forward_ms = fms;
+    AdjRecord &r = h->adj;
+    r.valid = true;
+    r.tape = d_tape;
+    r.tape_bytes = tape_bytes;
+    r.T = T;
+    r.K = K;
+    r.n_pre = c0.n_slots;
+    r.n_exit = nex;
+    r.loss = out->loss;
+    r.step_end = h->step;
+    r.mut = h->mut;
+    r.jb_final = h->jbuf;
+    r.forward_ms = fms;
+    return done(PIC_OK);
+}
 
-    // ---- reverse sweep, one segment at a time from its checkpoint ----
+// The reverse sweep of the recorded forward: each segment recomputed from its
+// checkpoint (on a second stream, one segment ahead), three kernels per
+// reversed step, the transposed Poisson solve; gradients scaled by dloss.
+pic_status adjoint_backward(pic_handle *h, double dloss, pic_adjoint_out *out)
+{
+    const AdjRecord &r = h->adj;
+    Tape t = carve_tape(h, r.T, r.K, (uint8_t *)r.tape);
+    Workspace &w = h->ws;
+    const int64_t N = h->c.N, T = r.T, K = r.K, n_pre = r.n_pre, nex = r.n_exit;
+    hipEvent_t ev[2] = {};
+    for (auto &e : ev) HIP_OK(hipEventCreate(&e));
+    auto done = [&](pic_status rc) {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        return rc;
+    };
+#define ADJ_OK(expr)                                                                                  \
+    do {                                                                                              \
+        const hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return done(fail(PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
     // The recompute of segment ck-1 runs on a second stream, into the other set
     // of segment slots, while the reverse sweep of segment ck runs on the
     // tube's stream: the two touch disjoint memory (the recompute owns the
-    // counters, the current and the kick array; the sweep reads recorded slots,
-    // fields and slot counts and owns the adjoint arrays), and events order
-    // each recompute before its sweep and each set's reuse after its sweep.
-    ADJ_OK(hipEventRecord(ev[2], h->stream));
+    // counters and the current; the sweep reads recorded slots, fields and slot
+    // counts and owns the adjoint arrays), and events order each recompute
+    // before its sweep and each set's reuse after its sweep.
+    ADJ_OK(hipEventRecord(ev[0], h->stream));
     ADJ_OK(launch_zero_f64(h, t.lx, t.cap));
     ADJ_OK(launch_zero_f64(h, t.lu, t.cap));
     ADJ_OK(launch_zero_f64(h, t.lez, N));
-    ADJ_OK(launch_zero_f64(h, t.ler, N + 1));
+    ADJ_OK(launch_zero_f64(h, t.ler[0], N + 1));
     ADJ_OK(launch_zero_f64(h, t.lb, N));
-    ADJ_OK(launch_zero_f64(h, t.grate, 1));
+    ADJ_OK(launch_zero_f64(h, t.lbp[0], N));     // B adjoint of the last step: nothing depends on E^T yet
+    ADJ_OK(launch_zero_f64(h, (double *)t.lk_lo, N));
+    ADJ_OK(launch_zero_f64(h, (double *)t.lk_hi, N));
+    ADJ_OK(launch_zero_f64(h, (double *)t.scale, (int64_t)(sizeof(AdjScale) / 8)));
     hipStream_t const main_s = h->stream;
     hipStream_t rec_s = nullptr;
     hipEvent_t sev[5] = {};                       // forward done; recompute done [2]; sweep done [2]
@@ -1582,9 +1611,9 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
             (void)hipStreamDestroy(rec_s);
         }
     };
-    auto fail_rev = [&](pic_status r) {
+    auto fail_rev = [&](pic_status rc) {
         cleanup();
-        return done(r);
+        return done(rc);
     };
 #define REV_OK(expr)                                                                                 \
     do {                                                                                             \
@@ -1621,6 +1650,7 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
         return e;
     };
     REV_OK(recompute(t.nck - 1));
+    int64_t rev = 0;                              // reverse steps done (their parity picks the scale words)
     for (int64_t ck = t.nck - 1; ck >= 0; --ck) {
         const int q = t.nsets == 2 ? (int)(ck & 1) : 0;
         const int64_t s0 = ck * K, m = (T - s0) < K ? (T - s0) : K;
@@ -1630,44 +1660,102 @@ pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_ev
             if (ck + 1 <= t.nck - 1) REV_OK(hipStreamWaitEvent(rec_s, sev[3 + (q ^ 1)], 0));
             REV_OK(recompute(ck - 1));
         }
-        for (int64_t k = m - 1; k >= 0; --k) {
+        for (int64_t k = m - 1; k >= 0; --k, ++rev) {
             const int64_t st = s0 + k;
+            const int pp = (int)(rev & 1);
             AdjStepPtrs a{k == 0 ? t.ck_x[ck] : t.sg_x[q][(size_t)k], k == 0 ? t.ck_u[ck] : t.sg_u[q][(size_t)k],
                           k == 0 ? t.ck_ez[ck] : t.sg_ez[q][(size_t)k], t.nslots + st, t.nslots + st + 1, n_pre, nex,
-                          t.lx, t.lu, t.lez, t.ler, t.lb, t.lbp, t.lk, t.grate};
+                          t.lx, t.lu, t.lez, t.ler[pp], t.ler[pp ^ 1], t.lb, t.lbp[pp], t.lbp[pp ^ 1], t.lk_lo,
+                          t.lk_hi, t.scale, (int)(rev % 3)};
             REV_OK(launch_adj_step(h, a));
         }
         REV_OK(hipEventRecord(sev[3 + q], main_s));
     }
 #undef REV_OK
     cleanup();
-    ADJ_OK(launch_adj_finish(h, t.lez, t.ler, t.gphi, t.cp, t.dp, t.g_rho, t.params));
-    ADJ_OK(hipEventRecord(ev[3], h->stream));
+    ADJ_OK(launch_adj_finish(h, t.lez, t.ler[(int)(T & 1)], t.gphi, t.cp, t.dp, t.g_rho, t.params));
+    ADJ_OK(hipEventRecord(ev[1], h->stream));
     // restore the end state the forward left
     ADJ_OK(hipMemcpyAsync(w.ctr, t.final_ctr, sizeof(DevCounters), hipMemcpyDeviceToDevice, h->stream));
-    h->jbuf = jb_final;
+    h->jbuf = r.jb_final;
     ADJ_OK(launch_zero_i64(h, w.j[h->jbuf], N));
     ADJ_OK(hipMemcpyAsync(w.j[1 - h->jbuf], t.final_jlast, (size_t)N * 8, hipMemcpyDeviceToDevice, h->stream));
-    ADJ_OK(launch_kick(h));
     // results
     std::vector<double> params((size_t)h->c.n_knots + 2);
     double grate = 0.0;
     ADJ_OK(hipMemcpyAsync(params.data(), t.params, params.size() * 8, hipMemcpyDeviceToHost, h->stream));
-    ADJ_OK(hipMemcpyAsync(&grate, t.grate, 8, hipMemcpyDeviceToHost, h->stream));
+    ADJ_OK(hipMemcpyAsync(&grate, &t.scale->grate, 8, hipMemcpyDeviceToHost, h->stream));
     if (out->g_rho) ADJ_OK(hipMemcpyAsync(out->g_rho, t.g_rho, (size_t)(N + 1) * 8, hipMemcpyDeviceToHost, h->stream));
     ADJ_OK(hipStreamSynchronize(h->stream));
-    out->g_rate = grate;
-    out->g_kappa = params[0];
-    out->g_amp = params[1];
+#undef ADJ_OK
+    out->loss = r.loss;
+    out->n_exit = r.n_exit;
+    out->g_rate = dloss * grate;
+    out->g_kappa = dloss * params[0];
+    out->g_amp = dloss * params[1];
+    if (out->g_rho)
+        for (int64_t i = 0; i <= N; ++i) out->g_rho[i] *= dloss;
     if (out->g_knots)
-        for (int k = 0; k < h->c.n_knots; ++k) out->g_knots[k] = params[(size_t)k + 2];
-    float fms = 0, bms = 0;
-    (void)hipEventElapsedTime(&fms, ev[0], ev[1]);
-    (void)hipEventElapsedTime(&bms, ev[2], ev[3]);
-    out->forward_ms = fms;
+        for (int k = 0; k < h->c.n_knots; ++k) out->g_knots[k] = dloss * params[(size_t)k + 2];
+    float bms = 0;
+    (void)hipEventElapsedTime(&bms, ev[0], ev[1]);
+    out->forward_ms = r.forward_ms;
     out->backward_ms = bms;
     return done(PIC_OK);
-#undef ADJ_OK
+}
+
+pic_status check_tape(pic_handle *h, int64_t n_steps, int32_t checkpoint_every, void *d_tape, size_t tape_bytes)
+{
+    if (n_steps < 1 || checkpoint_every < 1) return fail(PIC_EINVAL, "n_steps and checkpoint_every must be >= 1");
+    const size_t need = carve_tape(h, n_steps, checkpoint_every, nullptr).bytes;
+    if (!d_tape || tape_bytes < need) return fail(PIC_EWORKSPACE, "tape of %zu bytes, %zu needed", tape_bytes, need);
+    if (((uintptr_t)d_tape) % ALIGN) return fail(PIC_EWORKSPACE, "tape must be %zu-byte aligned", ALIGN);
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pic_adjoint_tape_bytes(pic_handle *h, int64_t n_steps, int32_t checkpoint_every)
+{
+    if (adjoint_supported(h) != PIC_OK) return 0;
+    if (n_steps < 1 || checkpoint_every < 1) {
+        fail(PIC_EINVAL, "n_steps and checkpoint_every must be >= 1");
+        return 0;
+    }
+    return carve_tape(h, n_steps, checkpoint_every, nullptr).bytes;
+}
+
+pic_status pic_adjoint_forward(pic_handle *h, int64_t n_steps, int32_t checkpoint_every, void *d_tape,
+                               size_t tape_bytes, pic_adjoint_out *out)
+{
+    pic_status s = adjoint_supported(h);
+    if (s != PIC_OK) return s;
+    if (!out) return fail(PIC_EINVAL, "out is NULL");
+    if ((s = check_tape(h, n_steps, checkpoint_every, d_tape, tape_bytes)) != PIC_OK) return s;
+    if (pic_status sp = resolve_pending(h)) return sp;
+    return adjoint_forward(h, n_steps, checkpoint_every, d_tape, tape_bytes, out);
+}
+
+pic_status pic_backward(pic_handle *h, double dloss, pic_adjoint_out *out)
+{
+    pic_status s = adjoint_supported(h);
+    if (s != PIC_OK) return s;
+    if (!out) return fail(PIC_EINVAL, "out is NULL");
+    if (!isfinite(dloss)) return fail(PIC_EINVAL, "dloss must be finite");
+    if (!h->adj.valid) return fail(PIC_ESTATE, "no recorded forward (pic_adjoint_forward) on this tube");
+    if (h->step != h->adj.step_end || h->mut != h->adj.mut)
+        return fail(PIC_ESTATE, "the tube changed after its recorded forward (stepped, injected, loaded or rewritten)");
+    return adjoint_backward(h, dloss, out);
+}
+
+pic_status pic_run_adjoint(pic_handle *h, int64_t n_steps, int32_t checkpoint_every, void *d_tape,
+                           size_t tape_bytes, pic_adjoint_out *out)
+{
+    pic_status s = pic_adjoint_forward(h, n_steps, checkpoint_every, d_tape, tape_bytes, out);
+    if (s != PIC_OK) return s;
+    return adjoint_backward(h, 1.0, out);
 }
 
 }  // extern "C"

@@ -208,3 +208,69 @@ def test_adjoint_gr_background_params():
     g_kappa = float(g_rho @ (cfg["rho_amp"] / (eta ** 3 * al)))
     assert abs(r["g_amp"] - g_amp) <= 1e-8 * abs(g_amp)
     assert abs(r["g_kappa"] - g_kappa) <= 1e-8 * abs(g_kappa)
+
+
+def test_adjoint_reproducible_lazy_and_scaled():
+    """The reverse sweep shares every sum between waves as an integer sum, so
+    the gradient is the same bits on every run: two reverse sweeps of one
+    recorded forward, and a second tube's whole adjoint, agree bit for bit.
+    pic_backward scales by the incoming gradient, and refuses once the tube has
+    moved on from its recorded forward."""
+    from paper_1011_6330_amd import PicError, Tube
+    cfg, x, u = _cold_cfg()
+    T = 700
+    say("adjoint reproducible")
+    t = Tube(synth.tube_params(cfg))
+    f = t.adjoint_forward(T, 50)
+    a = t.backward()
+    b = t.backward()
+    c = t.backward(2.5)
+    assert f["loss"] == a["loss"] and f["n_exit"] == a["n_exit"] > 0
+    for k in ("g_rate", "g_kappa", "g_amp"):
+        assert a[k] == b[k], k
+        assert c[k] == 2.5 * a[k], k
+    assert np.array_equal(a["g_rho"], b["g_rho"]) and np.array_equal(a["g_knots"], b["g_knots"])
+    assert np.array_equal(c["g_rho"], 2.5 * a["g_rho"])
+    assert abs(a["g_rate"]) > 0.1
+    t2 = Tube(synth.tube_params(cfg))
+    r2 = t2.run_adjoint(T, 50)
+    for k in ("g_rate", "g_kappa", "g_amp", "loss"):
+        assert r2[k] == a[k], k
+    assert np.array_equal(r2["g_rho"], a["g_rho"]) and np.array_equal(r2["g_knots"], a["g_knots"])
+    # the tube ends where the forward left it, so the sweep can run again; once
+    # it steps on, the recorded forward is gone
+    t.step(1)
+    with pytest.raises(PicError) as e:
+        t.backward()
+    assert e.value.code == -7
+    fresh = Tube(synth.tube_params(cfg))
+    with pytest.raises(PicError) as e:
+        fresh.backward()
+    assert e.value.code == -7
+    for tt in (t, t2, fresh):
+        tt.close()
+
+
+@pytest.mark.parametrize("T", [1, 2, 5])
+def test_adjoint_few_steps_tight(T):
+    """A few reverse steps against the oracle's at 1e-12: one step exercises each
+    transposed kernel once (field update, particle push and deposit, Poisson).
+    Particles start next to the top of the tube so that some leave in the first
+    step and seed the loss."""
+    N = 128
+    cfg = dict(n_cells=N, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=synth.q_over_m_for(12.0),
+               ppc=30.0, rho_kind=2, rho_amp=1.0, kappa=0.15, r_star=10.0, knots=np.ones(9),
+               capacity=20000, warm=0, sort_every=0)
+    cfg["macro_charge"] = -(1.0 - cfg["kappa"]) * (cfg["length"] / N) / cfg["ppc"]
+    rng = np.random.default_rng(T)
+    x = np.concatenate([N - rng.uniform(0.0, 1.4, 400), rng.uniform(0.0, N, 3000)])
+    u = np.concatenate([rng.uniform(2.0, 30.0, 400), rng.uniform(-5.0, 30.0, 3000)])
+    x = np.minimum(x, np.nextafter(float(N), 0.0))
+    g, o = make_pair(cfg, x, u)
+    r = g.run_adjoint(T, 1)
+    L, nex, g_rho, g_rate = o.adjoint(T)
+    assert r["loss"] == L and r["n_exit"] == nex > 0
+    err = np.abs(r["g_rho"] - g_rho).max() / np.abs(g_rho).max()
+    say("adjoint", T, "steps: g_rho max rel", err, "g_rate", r["g_rate"], g_rate)
+    assert err <= 1e-12
+    assert abs(r["g_rate"] - g_rate) <= 1e-12 * max(abs(g_rate), 1e-300) or g_rate == r["g_rate"] == 0.0

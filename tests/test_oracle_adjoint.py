@@ -150,3 +150,109 @@ def test_gradient_is_linear_response_of_the_start(oracle_mod, run):
     mapped through the hat functions."""
     assert run["g_rho"][0] == 0.0
     assert np.abs(run["g_rho"][1:]).max() > 0
+
+
+# ---- dot-product pins of the linearised kernels (P13) --------------------------
+#
+# Each kernel of one step, linearised with its discrete decisions frozen, as a
+# tangent map d -> tl(d) and its transpose l -> ad(l) (the transpose is the code
+# the reverse sweep runs): <ad(l), d> = <l, tl(d)> for random d and l, to the
+# rounding of the sums.
+
+def _dot_rel(a, b):
+    return abs(a - b) / max(abs(a), abs(b), 1e-300)
+
+
+def _lin_tube(oracle_mod, seed=0):
+    N = 97
+    cfg = dict(n_cells=N, length=5.0, radius=1.0, dt_over_dz=0.5, q_over_m=synth.q_over_m_for(15.0), ppc=20.0,
+               rho_kind=synth.RHO_FRAME_DRAG, rho_amp=1.0, kappa=0.15, r_star=10.0, capacity=10000)
+    rng = np.random.default_rng(seed)
+    n = 3000
+    x = np.concatenate([rng.uniform(0.0, N, n - 40), rng.uniform(N - 0.6, N, 20), rng.uniform(0.0, 0.4, 20)])
+    x = np.minimum(x, np.nextafter(float(N), 0.0))
+    u = np.concatenate([rng.uniform(-20.0, 60.0, n - 40), rng.uniform(10.0, 50.0, 20), rng.uniform(-40.0, -5.0, 20)])
+    t = oracle_mod.OracleTube(cfg)
+    t.inject(x, u)
+    t.k[:] = rng.normal(0.0, 0.3, N)            # a kick array with structure on every face
+    return t, rng
+
+
+def test_dot_product_fields(oracle_mod):
+    t, rng = _lin_tube(oracle_mod, 1)
+    N = t.N
+    for _ in range(5):
+        d = [rng.normal(size=N), rng.normal(size=N + 1), rng.normal(size=N), rng.normal(size=N) * 2.0 ** 20]
+        l = [rng.normal(size=N), rng.normal(size=N + 1), rng.normal(size=N)]
+        tl = t.tl_fields(*d)
+        ad = t.ad_fields(*l)
+        lhs = sum(float(a @ b) for a, b in zip(l, tl))
+        rhs = sum(float(a @ b) for a, b in zip(ad, d))
+        assert _dot_rel(lhs, rhs) <= 1e-12, (lhs, rhs)
+
+
+def test_dot_product_push(oracle_mod):
+    t, rng = _lin_tube(oracle_mod, 2)
+    N, n = t.N, t.n
+    for _ in range(5):
+        d = [rng.normal(size=n) * 1e-3, rng.normal(size=n), rng.normal(size=N)]
+        l = [rng.normal(size=n), rng.normal(size=n), rng.normal(size=N) * 2.0 ** -20]
+        tl = t.tl_push(*d)
+        ad = t.ad_push(*l)
+        lhs = sum(float(a @ b) for a, b in zip(l, tl))
+        rhs = sum(float(a @ b) for a, b in zip(ad, d))
+        assert _dot_rel(lhs, rhs) <= 1e-12, (lhs, rhs)
+
+
+def test_push_tangent_matches_finite_differences(oracle_mod):
+    """The push's tangent against central differences of the forward step in a
+    frozen field: particles inside the tube (none leaves or returns in one
+    step), perturbed in u; x1 and u1 are smooth in u (the current is not compared:
+    a cell crossing may flip)."""
+    from oracle.oracle import FREEZE_FIELDS, NO_AUTO_INJECT, OracleTube
+    t, rng = _lin_tube(oracle_mod, 3)
+    N = t.N
+    n = 2000
+    x0 = rng.uniform(2.0, N - 2.0, n)
+    u0 = rng.uniform(-20.0, 60.0, n)
+    k0 = t.k.copy()
+    cfg = dict(t.cfg, flags=FREEZE_FIELDS | NO_AUTO_INJECT)
+
+    def tube(uu):
+        o = OracleTube(cfg)
+        o.inject(x0, uu)
+        o.ez[:] = k0 / (cfg["q_over_m"] * cfg["dt_over_dz"] * o.dz)   # the kick array is (q/m) dt E_z
+        return o
+    base = tube(u0)
+    base.k[:] = base.cfg["q_over_m"] * (base.cfg["dt_over_dz"] * base.dz) * base.ez
+    du = rng.normal(size=n)
+    dx1, du1, _ = base.tl_push(np.zeros(n), du, np.zeros(N))
+    h = 1e-7
+    cp, cm = tube(u0 + h * du), tube(u0 - h * du)
+    cp.step(1)
+    cm.step(1)
+    assert cp.n == cm.n == n
+    # the differences lose about ulp(u) / h = 1e-7 to cancellation
+    np.testing.assert_allclose((cp.u - cm.u) / (2 * h), du1, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose((cp.x - cm.x) / (2 * h), dx1, rtol=1e-5, atol=1e-6)
+
+
+def test_dot_product_poisson(oracle_mod):
+    t, rng = _lin_tube(oracle_mod, 4)
+    N = t.N
+    for _ in range(5):
+        drho = rng.normal(size=N + 1)
+        lez, ler = rng.normal(size=N), rng.normal(size=N + 1)
+        dez, der = t.tl_poisson(drho)
+        (lrho,) = t.ad_poisson(lez, ler)
+        lhs = float(lez @ dez + ler @ der)
+        rhs = float(lrho @ drho)
+        assert _dot_rel(lhs, rhs) <= 1e-12, (lhs, rhs)
+    # eq. (4) is linear in rho_GJ: the tangent is the change of the start fields of
+    # an empty tube when the uniform amplitude moves by 1 (rho_GJ = -A)
+    from oracle.oracle import OracleTube
+    a1 = OracleTube(dict(t.cfg, rho_kind=synth.RHO_UNIFORM, rho_amp=1.0))
+    a2 = OracleTube(dict(t.cfg, rho_kind=synth.RHO_UNIFORM, rho_amp=2.0))
+    dez, der = t.tl_poisson(np.full(N + 1, -1.0))
+    np.testing.assert_allclose(dez, a2.ez - a1.ez, rtol=1e-10, atol=1e-12 * np.abs(dez).max())
+    np.testing.assert_allclose(der, a2.er - a1.er, rtol=1e-10, atol=1e-12 * np.abs(der).max())

@@ -61,20 +61,20 @@ FORWARD = [
 
 REVERSE = [
     ("d v / d u taken as 1/gamma instead of 1/gamma^3",
-     "const double lu1t = lu1 + lx1 * k.dtdz / (gam * gam * gam);", "const double lu1t = lu1 + lx1 * k.dtdz / gam;"),
+     "const double lu1t = lu1 + lx1 * k->dtdz / (gam * gam * gam);", "const double lu1t = lu1 + lx1 * k->dtdz / gam;"),
     ("sign of the deposit's position adjoint",
-     "if (c1 >= 0 && c1 < N) lx1 += twoP * (-k.c4 * wcls * lez[c1]);",
-     "if (c1 >= 0 && c1 < N) lx1 -= twoP * (-k.c4 * wcls * lez[c1]);"),
+     "if (q->c1 >= 0 && q->c1 < N) lx1 += twoP * (wcls * lj[q->c1]);",
+     "if (q->c1 >= 0 && q->c1 < N) lx1 -= twoP * (wcls * lj[q->c1]);"),
     ("kick-array adjoint dropped from the E_z adjoint",
-     "const double a = lez[i] - k.dtR * lbp[i] + k.qmdt * lk[i];", "const double a = lez[i] - k.dtR * lbp[i];"),
+     "const double a = lez[i] - k->dtR * lbp[i] + k->qmdt * lk[i];", "const double a = lez[i] - k->dtR * lbp[i];"),
     ("mirror factor dropped in the transposed E_r update",
      "double c = (i <= N - 1) ? ((i == N - 1) ? 2.0 : 1.0) : 0.0;", "double c = (i <= N - 1) ? 1.0 : 0.0;"),
     ("E_r neighbour term dropped in the B adjoint",
-     "            if (i + 1 <= N - 1) a += k.dtdz * ler[i + 1];", "            if (i + 1 <= N - 1) a += 0.0 * ler[i + 1];"),
+     "        if (i + 1 <= N - 1) a += k->dtdz * ler[i + 1];", "        if (i + 1 <= N - 1) a += 0.0 * ler[i + 1];"),
     ("gather-slope term dropped from the position adjoint",
-     "nlx[p] = lx1 + lx0J + lu1t * dEdx;", "nlx[p] = lx1 + lx0J;"),
+     "*lx = lx1 + lx0J + lu1t * q->dEdx;", "*lx = lx1 + lx0J;"),
     ("loss seed d gamma / d u replaced by 1 / gamma",
-     "lu1 = nex > 0 ? (u1 / gam) / (double)nex : 0.0;", "lu1 = nex > 0 ? (1.0 / gam) / (double)nex : 0.0;"),
+     "lu1 = nex > 0 ? (q.u1 / q.gam) / (double)nex : 0.0;", "lu1 = nex > 0 ? (1.0 / q.gam) / (double)nex : 0.0;"),
 ]
 
 
