@@ -314,14 +314,19 @@ def main():
 
     if not args.no_sweep:
         from paper_1011_6330_amd import sweep
-        rows = sweep.run_sweep([3.5, 5.5, 11.0, 30.0])
-        result["plausibility"] = {"workload": "flat-space SCLF from empty tubes, L = 40R, one grid for all a, "
-                                              "profiles read when the front reaches 30R",
-                                  "rows": [{k: r[k] for k in ("a", "gamma_plateau", "gamma_peak", "gamma_sclf",
-                                                              "gamma_paper", "amplitude", "returning",
-                                                              "e_surf_ratio")} for r in rows]}
-        log("plausibility: " + "; ".join(f"a={r['a']:g}: peak {r['gamma_peak']:.2f} vs sqrt2 a {r['gamma_paper']:.2f}, "
-                                           f"ampl {r['amplitude']:.2f}" for r in rows))
+        rows = sweep.run_convergence([3.5, 5.5, 11.0, 30.0])
+        result["plausibility"] = {"workload": "flat-space SCLF from empty tubes, L = 40R, one grid for all a "
+                                              "(24 cells per plasma wavelength of the largest a, at least 50 per R), "
+                                              "profiles read at the first whole R of light travel after the front reaches 30R; the "
+                                              "same on a grid twice "
+                                              "as fine ('fine', and the relative changes)",
+                                  "rows": [{k: r[k] for k in ("a", "n_cells", "gamma_plateau", "gamma_peak",
+                                                              "gamma_sclf", "gamma_paper", "amplitude", "returning",
+                                                              "e_surf_ratio", "fine", "change_plateau",
+                                                              "change_peak")} for r in rows]}
+        log("plausibility: " + "; ".join(f"a={r['a']:g}: peak {r['gamma_peak']:.2f} (fine {r['fine']['gamma_peak']:.2f})"
+                                           f" vs sqrt2 a {r['gamma_paper']:.2f}, ampl {r['amplitude']:.2f}"
+                                           for r in rows))
         inc = sweep.run_inclination((0.1, 0.5))
         result["plausibility"]["inclination"] = {
             "workload": "Fig. 6: one star (frame dragging, redshift, inclination term of eq. 6; surface density "

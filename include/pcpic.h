@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define PCPIC_ABI_VERSION 3
+#define PCPIC_ABI_VERSION 4
 
 typedef int32_t pic_status;
 enum {
@@ -60,7 +60,10 @@ enum {
 /* Device status bits (latched; reported in pic_diag.status). */
 enum {
     PIC_ST_CAPACITY = 1,  /* SCLF injection was clipped at the capacity            */
-    PIC_ST_NONFINITE = 2  /* a particle's u or x became non-finite; it was removed */
+    PIC_ST_NONFINITE = 2, /* a particle's u or x became non-finite; it was removed */
+    PIC_ST_GAUSS = 4      /* a diagnostics call found the discrete Gauss residual of eq. (2)
+                             above its request's gauss_tol (the deposit or the field update
+                             no longer keeps the divergence equation)                     */
 };
 
 /* Arithmetic of the particle push. */
@@ -132,6 +135,8 @@ typedef struct pic_handle pic_handle;
 typedef struct pic_diag_req {
     int32_t n_bins;       /* bins of the signed-gamma profile over [0, N); 0 = none, <= max_bins */
     int32_t want_gauss;   /* compute the discrete Gauss residual at nodes 1..N-1              */
+    double gauss_tol;     /* with want_gauss: latch PIC_ST_GAUSS when gauss_max exceeds it
+                             (0 = no check)                                                 */
 } pic_diag_req;
 
 /* Diagnostics result.  Array pointers are host memory provided by the caller

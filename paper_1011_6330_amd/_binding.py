@@ -15,11 +15,11 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libpcpic.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 FP64, FP32_BULK = 0, 1
 RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS, RHO_GR = 0, 1, 2, 3
 NO_AUTO_INJECT, FREEZE_FIELDS, B_STEADY_INIT = 1, 2, 4
-ST_CAPACITY, ST_NONFINITE = 1, 2
+ST_CAPACITY, ST_NONFINITE, ST_GAUSS = 1, 2, 4
 
 STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_EWORKSPACE", -3: "PIC_ECAPACITY",
                 -4: "PIC_ENONFINITE", -5: "PIC_ECFL", -6: "PIC_EDEVICE", -7: "PIC_ESTATE",
@@ -52,7 +52,7 @@ class PicParams(ctypes.Structure):
 
 
 class PicDiagReq(ctypes.Structure):
-    _fields_ = [("n_bins", ctypes.c_int32), ("want_gauss", ctypes.c_int32)]
+    _fields_ = [("n_bins", ctypes.c_int32), ("want_gauss", ctypes.c_int32), ("gauss_tol", ctypes.c_double)]
 
 
 class PicDiag(ctypes.Structure):
@@ -324,7 +324,7 @@ class Tube(_TubeOps):
                     g_rho=g_rho, g_knots=g_knots[:nk], forward_ms=out.forward_ms, backward_ms=out.backward_ms)
 
     def diagnostics(self, n_bins=0, gauss=False, fields=True, j=False, weights=False, rho=False,
-                    raise_on_status=True):
+                    raise_on_status=True, gauss_tol=0.0):
         N = self.N
         d = PicDiag()
         out = {}
@@ -350,7 +350,7 @@ class Tube(_TubeOps):
             d.prof_count, d.prof_mean = _ptr(out["prof_count"], _pi), _ptr(out["prof_mean"])
             d.prof_min, d.prof_max = _ptr(out["prof_min"]), _ptr(out["prof_max"])
             d.prof_sum_lo, d.prof_sum_hi = _ptr(out["prof_sum_lo"], _pu), _ptr(out["prof_sum_hi"], _pi)
-        req = PicDiagReq(int(n_bins), int(bool(gauss)))
+        req = PicDiagReq(int(n_bins), int(bool(gauss)), float(gauss_tol))
         rc = self.lib.pic_diagnostics(self._h, ctypes.byref(req), ctypes.byref(d))
         if rc != 0 and (rc != -9 or raise_on_status):
             _check(rc, "pic_diagnostics")

@@ -682,6 +682,7 @@ pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out
     const int nb = req ? req->n_bins : 0;
     const bool want_gauss = req && req->want_gauss;
     if (nb < 0 || nb > effective_bins(h->p)) return fail(PIC_EINVAL, "n_bins %d > max_bins", nb);
+    if (req && !(req->gauss_tol >= 0.0)) return fail(PIC_EINVAL, "gauss_tol must be >= 0");
     const int64_t N = h->c.N;
     const Workspace &w = h->ws;
     HIP_OK(launch_profile(h, nb));   // also clears the Gauss maximum
@@ -733,6 +734,13 @@ pic_status pic_diagnostics(pic_handle *h, const pic_diag_req *req, pic_diag *out
     const double rmax = __builtin_bit_cast(double, ctr.rho_max_bits);
     const double gmax = __builtin_bit_cast(double, ctr.gauss_max_bits);
     out->gauss_max = (want_gauss || out->gauss) ? gmax / (h->c.fourpi * rmax) : 0.0;
+    if (want_gauss && req->gauss_tol > 0.0 && out->gauss_max > req->gauss_tol && !(ctr.status & PIC_ST_GAUSS)) {
+        // latch the bit in the device status word (the stream is idle here)
+        ctr.status |= PIC_ST_GAUSS;
+        HIP_OK(hipMemcpyAsync(&w.ctr->status, &ctr.status, sizeof ctr.status, hipMemcpyHostToDevice, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+        out->status = (int64_t)ctr.status;
+    }
     out->gauss_l2 = 0.0;
     if (gdst && N > 1) {
         double ss = 0.0;

@@ -93,14 +93,19 @@ def _measure(b, cfgs, labels, front, margin, n_bins, chunk, max_steps):
 
 
 def run_sweep(a_values, cells_per_lambda=24.0, min_cells_per_r=50.0, front=30.0, length=40.0, n_bins=200,
-              chunk=512, max_steps=200000, device="cuda"):
+              chunk=None, max_steps=400000, device="cuda"):
     """Run the batch until the front has crossed `front` radii in every tube
     (the paper reads its profiles when the front reaches 30R); all tubes share
     one grid (the finest the largest a needs), so they share the time step.
-    Returns one dict of results per value of a."""
+    The front is checked every `chunk` steps, by default the steps light takes
+    to cross one radius, so that grids of any resolution are read at the same
+    time to within R/c.  Returns one dict of results per value of a."""
     from . import Batch
     cpr = max(min_cells_per_r, cells_per_lambda * max(a_values) / (2.0 * math.pi))
     cfgs = [sclf_tube(a, cpr, length=length) for a in a_values]
+    if chunk is None:
+        n = cfgs[0]["n_cells"]
+        chunk = max(1, int(round(length / (0.5 * length / n) / length)))   # R / (c dt), dt = dz / 2
     b = Batch([synth.tube_params(c) for c in cfgs], device=device)
     rows = _measure(b, cfgs, a_values, front, 5.0, n_bins, chunk, max_steps)
     b.close()
@@ -108,6 +113,22 @@ def run_sweep(a_values, cells_per_lambda=24.0, min_cells_per_r=50.0, front=30.0,
         a = r.pop("label")
         r.update(a=float(a), gamma_sclf=gamma_sclf(a), gamma_paper=math.sqrt(2.0) * a)
     return rows
+
+
+def run_convergence(a_values, refine=2.0, cells_per_lambda=24.0, min_cells_per_r=50.0, **kw):
+    """run_sweep on its grid and on a grid `refine` times finer (cell size and
+    time step both shrink; the macro-particle density per cell is kept, so the
+    particle count grows with it).  Each row gets the fine grid's figures and
+    the relative changes of the plateau and the peak: what the figures still
+    owe to the resolution."""
+    coarse = run_sweep(a_values, cells_per_lambda=cells_per_lambda, min_cells_per_r=min_cells_per_r, **kw)
+    fine = run_sweep(a_values, cells_per_lambda=cells_per_lambda * refine, min_cells_per_r=min_cells_per_r * refine,
+                     **kw)
+    for c, f in zip(coarse, fine):
+        c["fine"] = {k: f[k] for k in ("n_cells", "steps", "gamma_plateau", "gamma_peak", "amplitude", "front")}
+        c["change_plateau"] = (f["gamma_plateau"] - c["gamma_plateau"]) / c["gamma_plateau"]
+        c["change_peak"] = (f["gamma_peak"] - c["gamma_peak"]) / c["gamma_peak"]
+    return coarse
 
 
 # The paper's standard pulsar (sec. 3): theta_p = 0.014, theta_* = 0.67 theta_p on

@@ -43,7 +43,7 @@ def test_exports_every_declared_symbol(lib):
 def test_abi_version(lib):
     from paper_1011_6330_amd import _binding
     m = re.search(r"#define PCPIC_ABI_VERSION (\d+)", open(os.path.join(ROOT, "include", "pcpic.h")).read())
-    assert lib.pic_abi_version() == int(m.group(1)) == _binding.ABI_VERSION == 3
+    assert lib.pic_abi_version() == int(m.group(1)) == _binding.ABI_VERSION == 4
 
 
 def _params(**kw):

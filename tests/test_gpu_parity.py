@@ -173,7 +173,7 @@ def test_diagnostics_match_oracle():
     assert d2["gauss_l2"] == 0.0
     from paper_1011_6330_amd._binding import PicDiag, PicDiagReq
     import ctypes
-    req, out = PicDiagReq(0, 1), PicDiag()
+    req, out = PicDiagReq(0, 1, 0.0), PicDiag()
     assert g.lib.pic_diagnostics(g._h, ctypes.byref(req), ctypes.byref(out)) == 0
     assert out.gauss_l2 == d["gauss_l2"] and out.gauss_max == d["gauss_max"]
 
@@ -480,3 +480,19 @@ def test_stream_copy_exact():
     torch.cuda.synchronize()
     assert torch.equal(dst[:2 * n], src[:2 * n])
     assert int(dst[2 * n:].abs().sum()) == 0  # nothing written past the end
+
+
+def test_gauss_residual_status_bit():
+    """A diagnostics call with a Gauss tolerance latches PIC_ST_GAUSS when the
+    residual of eq. (2) exceeds it, and only then."""
+    from paper_1011_6330_amd import PicError, Tube
+    t = Tube(synth.tube_params(synth.preset("c1")))
+    t.step(300)
+    d = t.diagnostics(gauss=True, fields=False, gauss_tol=1e-6)      # C1 keeps it near 1e-11
+    assert d["status"] == 0 and 0.0 < d["gauss_max"] < 1e-6
+    d = t.diagnostics(gauss=True, fields=False, gauss_tol=d["gauss_max"] / 2, raise_on_status=False)
+    assert d["status"] & 4
+    with pytest.raises(PicError) as e:
+        t.sync()                                                       # latched
+    assert e.value.code == -9
+    t.close()

@@ -41,3 +41,19 @@ def test_inclination_fig6():
     say("gamma ratio i=0.1 / i=0.5", ratio, "cos ratio", math.cos(0.1) / math.cos(0.5))
     assert small["gamma_peak"] > large["gamma_peak"]
     assert 1.0 < ratio < math.cos(0.1) / math.cos(0.5) * 1.05
+
+
+def test_sweep_resolution_small_a():
+    """Table 2's small-a rows (a = 3.5, 5.5) at 100 cells per R and on a grid
+    twice as fine: the plateau and the peak behind the front change by at most
+    5%, so the values compared with the paper's ~5 and ~8 are resolved.  (At 50
+    cells per R the plateau of a = 3.5 still moves by 5.6%.)"""
+    from paper_1011_6330_amd import sweep
+    rows = sweep.run_convergence([3.5, 5.5], min_cells_per_r=100.0, front=30.0, length=40.0)
+    for r in rows:
+        say("convergence a", r["a"], "plateau", round(r["gamma_plateau"], 4), "->", round(r["fine"]["gamma_plateau"], 4),
+            "peak", round(r["gamma_peak"], 4), "->", round(r["fine"]["gamma_peak"], 4), "cells", r["n_cells"], "->",
+            r["fine"]["n_cells"])
+        assert abs(r["change_plateau"]) <= 0.05
+        assert abs(r["change_peak"]) <= 0.05
+        assert r["fine"]["n_cells"] >= 2 * r["n_cells"] - 1
