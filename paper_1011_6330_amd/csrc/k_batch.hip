@@ -89,8 +89,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
         const Consts c = T.c;
         const int64_t local = it - b.live_pref[t];
         if (F32) {
-            Push32Args a{generic(T.cl[b.pb]), generic(T.ol[b.pb]), generic(T.ul[b.pb]), generic(T.ch[b.pb]),
-                         generic(T.oh[b.pb]), generic(T.uh[b.pb]), generic(T.k32), generic(T.ez[b.fb]),
+            Push32Args a{generic(T.cl[b.pb]), generic(T.ol[b.pb]), generic(T.ul[b.pb]), generic(T.hp[b.pb]),
+                         generic(T.hw[b.pb]), generic(T.hg[b.pb]), generic(T.uh[b.pb]), generic(T.k32),
+                         generic(T.ez[b.fb]),
                          (unsigned long long *)generic(T.j[b.jb]), generic(T.ctr),
                          b.hist ? (unsigned long long *)generic(T.cell_count) : nullptr, T.u_hi};
             push_item_f32<BLOCK, NT>(c, a, local);
@@ -159,8 +160,8 @@ __global__ __launch_bounds__(256) void k_bsort_clear(BSortArgs a)
 // A tube's particle streams of buffer parity b.
 __device__ __forceinline__ Streams tube_streams(const TubeDev &T, int b)
 {
-    return Streams{generic(T.cl[b]), generic(T.ol[b]), generic(T.ul[b]), generic(T.ch[b]), generic(T.oh[b]),
-                   generic(T.uh[b])};
+    return Streams{generic(T.cl[b]), generic(T.ol[b]), generic(T.ul[b]), generic(T.hp[b]), generic(T.hw[b]),
+                   generic(T.hg[b]), generic(T.uh[b])};
 }
 
 // One block per sort item (a tile of SORT_TILE slots of one stream) of a tube.
@@ -294,8 +295,9 @@ TubeDev tube_dev(pic_handle *t)
         d.cl[k] = to_global(w.cl[k]);
         d.ol[k] = to_global(w.ol[k]);
         d.ul[k] = to_global(w.ul[k]);
-        d.ch[k] = to_global(w.ch[k]);
-        d.oh[k] = to_global(w.oh[k]);
+        d.hp[k] = to_global(w.hp[k]);
+        d.hw[k] = to_global(w.hw[k]);
+        d.hg[k] = to_global(w.hg[k]);
         d.uh[k] = to_global(w.uh[k]);
         d.ez[k] = to_global(w.ez[k]);
         d.er[k] = to_global(w.er[k]);

@@ -11,6 +11,7 @@
 #include "pcpic_internal.h"
 #include "wave.h"
 #include "field_body.h"
+#include "sort_body.h"
 
 namespace pcpic {
 
@@ -183,18 +184,20 @@ __global__ __launch_bounds__(256) void k_drift_current_f64(Consts c, const doubl
     }
 }
 
-__global__ __launch_bounds__(256) void k_drift_current_f32(Consts c, const int *CL, const float *OL, const float *UL,
-                                                           const int *CH, const float *OH, const double *UH,
-                                                           const DevCounters *ctr, unsigned long long *J)
+__global__ __launch_bounds__(256) void k_drift_current_f32(Consts c, Streams s, const DevCounters *ctr,
+                                                           unsigned long long *J)
 {
     const int64_t nl = ctr->n_slots, nh = ctr->n_slots_hi;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nl + nh; p += (int64_t)gridDim.x * 256) {
         const bool hi = p >= nl;
         const int64_t q = hi ? p - nl : p;
-        const int cell = hi ? CH[q] : CL[q];
+        float off = 0.0f;
+        int cell;
+        if (hi) cell = hi_slot(s, q, off);
+        else { cell = s.CL[q]; off = s.OL[q]; }
         if (cell < 0) continue;
-        const double x = (double)cell + (double)(hi ? OH[q] : OL[q]);
-        drift_current(c, x, hi ? UH[q] : (double)UL[q], J);
+        const double x = (double)cell + (double)off;
+        drift_current(c, x, hi ? s.UH[q] : (double)s.UL[q], J);
     }
 }
 
@@ -315,8 +318,8 @@ hipError_t launch_fields_from_phi(pic_handle *h)
         const unsigned g = (unsigned)(h->n_cu * 8);
         const int b = h->pbuf;
         if (h->p.precision == PIC_FP32_BULK)
-            hipLaunchKernelGGL(k_drift_current_f32, dim3(g), dim3(256), 0, h->stream, c, w.cl[b], w.ol[b], w.ul[b],
-                               w.ch[b], w.oh[b], w.uh[b], w.ctr, J);
+            hipLaunchKernelGGL(k_drift_current_f32, dim3(g), dim3(256), 0, h->stream, c,
+                               Streams{w.cl[b], w.ol[b], w.ul[b], w.hp[b], w.hw[b], w.hg[b], w.uh[b]}, w.ctr, J);
         else
             hipLaunchKernelGGL(k_drift_current_f64, dim3(g), dim3(256), 0, h->stream, c, w.x[b], w.u[b], w.ctr, J);
         hipLaunchKernelGGL(k_b_from_current, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, w.j[h->jbuf],

@@ -1,13 +1,15 @@
 // k_push32.hip -- the FP32-bulk particle path.
 //
-// Particles live in two SoA streams, both positioned as (cell i32, offset f32
-// in [0, 1)) so that FP32 keeps its 24 bits of resolution inside a cell of a
-// tube of any length:
-//   low stream  (gamma below the threshold): u = gamma*beta in f32, 12 B/slot;
-//               kick from the f32 kick array, v = u * rsqrt(1 + u^2) (never
-//               formed from gamma, so nothing cancels near v = c);
-//   high stream (gamma at or above the threshold, 1e6 by default): u in f64,
-//               16 B/slot; kick, gamma and v in f64 exactly as the FP64 path.
+// Particles live in two SoA streams whose positions keep 24 bits of resolution
+// inside a cell of a tube of any length:
+//   low stream  (gamma below the threshold): cell i32, offset f32 in [0, 1),
+//               u = gamma*beta in f32, 12 B/slot; kick from the f32 kick
+//               array, v = u * rsqrt(1 + u^2) (never formed from gamma, so
+//               nothing cancels near v = c);
+//   high stream (gamma at or above the threshold, 1e6 by default): a 32-bit
+//               position word (offset in units of 2^-24, cell relative to the
+//               base cell of its group of 128 slots) and u in f64, 12 B/slot;
+//               kick, gamma and v in f64 as the FP64 path.
 // The deposit takes F = rint(2^P offset) of the stored offsets, so charge
 // conservation stays exact.  Fields, the Gauss residual and E_surf stay FP64;
 // the high stream's kick is (q/m) dt E_z formed in f64 from E_z itself.  The
@@ -55,15 +57,18 @@ __global__ __launch_bounds__(256) void k_weights32(Consts c, Streams s, const De
     WeightAcc acc;
 #pragma unroll 1
     for (int high = 0; high < 2; ++high) {
-        const int *C = high ? s.CH : s.CL;
-        const float *O = high ? s.OH : s.OL;
         const int64_t hi = r[2 * high + 1];
         for (int64_t base = r[2 * high]; base < hi; base += 256) {
             const int64_t p = base + threadIdx.x;
-            const int cell = p < hi ? C[p] : -1;
+            float off = 0.0f;
+            int cell = -1;
+            if (p < hi) {
+                if (high) cell = hi_slot(s, p, off);
+                else { cell = s.CL[p]; off = s.OL[p]; }
+            }
             const bool live = cell >= 0;
             int64_t F = 0;
-            if (live) F = (int64_t)rint((double)O[p] * c.twoP);
+            if (live) F = (int64_t)rint((double)off * c.twoP);
             acc.add(w, live, cell, c.oneP, F);
         }
     }
@@ -77,18 +82,21 @@ __global__ __launch_bounds__(256) void k_profile32(Consts c, int nb, Streams s, 
     ProfAcc acc;
 #pragma unroll 1
     for (int high = 0; high < 2; ++high) {
-        const int *C = high ? s.CH : s.CL;
-        const float *O = high ? s.OH : s.OL;
         const int64_t hi = r[2 * high + 1];
         for (int64_t base = r[2 * high]; base < hi; base += 256) {
             const int64_t p = base + threadIdx.x;
-            const int cell = p < hi ? C[p] : -1;
+            float off = 0.0f;
+            int cell = -1;
+            if (p < hi) {
+                if (high) cell = hi_slot(s, p, off);
+                else { cell = s.CL[p]; off = s.OL[p]; }
+            }
             const bool want = cell >= 0;
             int64_t bin = 0, gi = 0, gf = 0;
             long long ob = 0;
             if (want) {
                 const double u = high ? s.UH[p] : (double)s.UL[p];
-                prof_values(c, nb, (double)cell + (double)O[p], u, bin, gi, gf, ob);
+                prof_values(c, nb, (double)cell + (double)off, u, bin, gi, gf, ob);
             }
             acc.add(o, want, bin, gi, gf, ob);
         }
@@ -196,9 +204,14 @@ __global__ __launch_bounds__(256) void k_stage_offsets(long long *blk, int64_t n
     }
 }
 
-// Staged particles -> (cell, f32 offset) in the stream their gamma selects.
-__global__ __launch_bounds__(256) void k_append_staged(const double *X, const double *U, int64_t n, Streams s,
-                                                       double u_hi, const long long *blk, const long long *base)
+// Staged particles -> (cell, f32 offset) in the stream their gamma selects; the
+// high stream takes them in the wide form (offsets on its 2^-24 grid).  The
+// group that held the high stream's last slots before the append is first
+// rewritten wide by the thread that writes its first new slot: the only
+// thread that touches that group's header here.
+__global__ __launch_bounds__(256) void k_append_staged(Consts c, const double *X, const double *U, int64_t n,
+                                                       Streams s, double u_hi, const long long *blk,
+                                                       const long long *base)
 {
     __shared__ int s_hi[4], s_lo[4];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -213,20 +226,36 @@ __global__ __launch_bounds__(256) void k_append_staged(const double *X, const do
     int ph = 0, pl = 0;
     for (int q = 0; q < wv; ++q) { ph += s_hi[q]; pl += s_lo[q]; }
     if (!want) return;
-    int cell;
-    float o;
-    {
-        const double cd = floor(x);
-        cell = (int)cd;
-        o = (float)(x - cd);
-        if (o >= 1.0f) { o = 0.0f; cell += 1; }
-    }
+    // 0 <= x < N: the offset in [0, 1), on the stream's grid; one that rounds up to
+    // 1 moves into the next cell, except past the last cell, where it stays just below 1
+    const double cd = floor(x);
+    const int N = (int)c.N;
+    int cell = (int)cd;
     const unsigned long long below = (1ull << lane) - 1ull;
     const long long hi_before = blk[blockIdx.x];                           // high particles in earlier blocks
     if (high) {
+        unsigned frac;
+        hi_snap(x - cd, cell, frac);
+        if (cell >= N) { cell = N - 1; frac = HI_FRAC_MASK; }
         const int64_t d = base[1] + hi_before + ph + __popcll(mh & below);
-        s.CH[d] = cell; s.OH[d] = o; s.UH[d] = u;
+        const int64_t g0 = d & ~(int64_t)(HI_GROUP - 1);
+        if (d == base[1] && d != g0) {
+            const int hdr = s.HG[d >> HI_GROUP_LOG2];
+            if (hdr >= 0) {
+                for (int64_t q = g0; q < d; ++q) {
+                    const unsigned w = s.HP[q];
+                    if (w == HI_DEAD) continue;
+                    s.HW[q] = hi_cell(w, hdr, 0);
+                    s.HP[q] = w & HI_FRAC_MASK;
+                }
+                s.HG[d >> HI_GROUP_LOG2] = HI_WIDE;
+            }
+        }
+        hi_put_wide(s, d, cell, frac, u);
     } else {
+        float o = (float)(x - cd);
+        if (o >= 1.0f) { o = 0.0f; cell += 1; }
+        if (cell >= N) { cell = N - 1; o = 0x1.fffffep-1f; }
         const int64_t d = base[0] + ((int64_t)blockIdx.x * 256 - hi_before) + pl + __popcll(ml & below);
         s.CL[d] = cell; s.OL[d] = o; s.UL[d] = (float)u;
     }
@@ -239,7 +268,7 @@ __global__ __launch_bounds__(256) void k_append_staged(const double *X, const do
 static Streams streams_of(pic_handle *h, int b)
 {
     const Workspace &w = h->ws;
-    return Streams{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b]};
+    return Streams{w.cl[b], w.ol[b], w.ul[b], w.hp[b], w.hw[b], w.hg[b], w.uh[b]};
 }
 
 template <int BLOCK, int NT>
@@ -249,7 +278,7 @@ static hipError_t launch_push32_t(pic_handle *h)
     const int b = h->pbuf;
     const int64_t tile_hi = (int64_t)BLOCK * F32_PPT_HI;
     const unsigned items = (unsigned)((h->c.cap + tile_hi - 1) / tile_hi + 1);   // both streams, any split
-    Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.ch[b], w.oh[b], w.uh[b], w.k32, w.ez[h->fbuf],
+    Push32Args a{w.cl[b], w.ol[b], w.ul[b], w.hp[b], w.hw[b], w.hg[b], w.uh[b], w.k32, w.ez[h->fbuf],
                  (unsigned long long *)w.j[h->jbuf], w.ctr,
                  h->hist_on ? (unsigned long long *)w.cell_count : nullptr, h->u_hi};
     hipLaunchKernelGGL((k_push_f32<BLOCK, NT>), dim3(items), dim3(BLOCK), 0, h->stream, h->c, a);
@@ -322,7 +351,7 @@ hipError_t launch_append_staged(pic_handle *h, int64_t n, bool check_only)
     hipLaunchKernelGGL(k_stage_count, dim3(g), dim3(256), 0, h->stream, h->ws.stage_u, n, h->u_hi, h->ws.stage_blk);
     hipLaunchKernelGGL(k_stage_offsets, dim3(1), dim3(256), 0, h->stream, h->ws.stage_blk, (int64_t)g, n, h->ws.ctr,
                        h->ws.stage_base);
-    hipLaunchKernelGGL(k_append_staged, dim3(g), dim3(256), 0, h->stream, h->ws.stage_x, h->ws.stage_u, n,
+    hipLaunchKernelGGL(k_append_staged, dim3(g), dim3(256), 0, h->stream, h->c, h->ws.stage_x, h->ws.stage_u, n,
                        streams_of(h, h->pbuf), h->u_hi, (const long long *)h->ws.stage_blk,
                        (const long long *)h->ws.stage_base);
     return hipGetLastError();

@@ -55,10 +55,63 @@ struct Consts {
 
 // Slots per thread of the two FP32-bulk push streams: the low stream loads its
 // three 4-byte fields as 16-byte vectors of 4 slots; the high stream takes 2
-// slots (8-byte cell and offset vectors, one 16-byte f64 momentum vector), which
-// keeps its registers, and so its occupancy, at those of the FP64 push.
+// slots (an 8-byte vector of position words, one 16-byte f64 momentum vector),
+// which keeps its registers, and so its occupancy, at those of the FP64 push.
 constexpr int F32_PPT_LO = 4;
-constexpr int F32_PPT_HI = 2;
+constexpr int F32_PPT_HI = 4;
+
+// Positions of the high stream (FP32-bulk, gamma at or above the threshold):
+// 4 bytes per slot beside the 8-byte f64 momentum.  Slots form groups of
+// HI_GROUP consecutive slots (the 128 slots one wave of the push takes).  The
+// low HI_FRAC_BITS bits of a slot's word hold its offset in the cell in units
+// of 2^-24.  A narrow group (header >= 0) keeps the cell minus the header in
+// the high 8 bits; a wide group (header HI_WIDE) keeps zero there and the cell
+// in the per-slot cell array, which only wide groups touch.  HI_DEAD marks a
+// removed slot in both forms.  The push rewrites each group it moves as
+// narrow, based at its lowest live cell, when its live cells span at most
+// HI_SPAN cells, and as wide otherwise; the sort and the appends write wide
+// groups.  Offsets on the 2^-24 grid are exact in f32, so a particle moves
+// between the streams without a change of position (the low push snaps a
+// particle's offset to the grid once its momentum reaches the threshold).
+constexpr int HI_GROUP_LOG2 = 8;
+constexpr int HI_GROUP = 1 << HI_GROUP_LOG2;
+constexpr int HI_FRAC_BITS = 24;
+constexpr unsigned HI_FRAC_MASK = (1u << HI_FRAC_BITS) - 1u;
+constexpr unsigned HI_DEAD = 0xFFFFFFFFu;
+constexpr int HI_WIDE = -1;
+constexpr int HI_SPAN = 254;
+static_assert(HI_GROUP == 64 * F32_PPT_HI, "a high-stream group is the slots of one wave of the push");
+
+// The least float f with f >= v (v >= 0 finite): for a float x, |x| >= f exactly
+// when (double)|x| >= v, so an f32 test picks the same particles as the f64 one.
+__host__ __device__ inline float f32_at_least(double v)
+{
+    float f = (float)v;
+    if ((double)f < v) f = __builtin_bit_cast(float, __builtin_bit_cast(unsigned, f) + 1u);
+    return f;
+}
+
+__host__ __device__ inline int64_t hi_groups(int64_t slots) { return (slots + HI_GROUP - 1) >> HI_GROUP_LOG2; }
+// Cell of a live slot from its word, its group's header and (wide groups) the cell array.
+__host__ __device__ inline int hi_cell(unsigned w, int hdr, int wide_cell)
+{
+    return hdr >= 0 ? hdr + (int)(w >> HI_FRAC_BITS) : wide_cell;
+}
+__host__ __device__ inline float hi_offset(unsigned w) { return (float)(w & HI_FRAC_MASK) * 0x1p-24f; }
+// The word of (cell, frac) in a group with header hdr (HI_WIDE: frac alone).
+__host__ __device__ inline unsigned hi_word(int cell, unsigned frac, int hdr)
+{
+    return hdr >= 0 ? ((unsigned)(cell - hdr) << HI_FRAC_BITS) | frac : frac;
+}
+// An offset in [0, 1) on the 2^-24 grid: (cell, frac), carried into the next
+// cell when it rounds up to 1.
+__host__ __device__ inline void hi_snap(double off, int &cell, unsigned &frac)
+{
+    const double q = rint(off * 16777216.0);
+    const bool up = q >= 16777216.0;
+    cell += up ? 1 : 0;
+    frac = up ? 0u : (unsigned)q;
+}
 
 // Cell-sort keys.  A live particle's key is its cell refined into 2^sub bins
 // (so that a wave's particles sit within a small fraction of a cell and cross
@@ -107,11 +160,13 @@ struct DevCounters {
 
 struct Workspace {
     double *x[2], *u[2];    // particle double buffer (FP64)
-    // FP32-bulk streams (double-buffered): low (cell, offset, u f32), high (cell, offset, u f64)
+    // FP32-bulk streams (double-buffered): low (cell, offset, u f32); high (position
+    // word, u f64, and per group a header; cells of wide groups in hw)
     int *cl[2];
     float *ol[2], *ul[2];
-    int *ch[2];
-    float *oh[2];
+    unsigned *hp[2];
+    int *hw[2];
+    int *hg[2];
     double *uh[2];
     float *k32;             // f32 kick array (q/m) dt E_z (FP32-bulk low stream)
     double *stage_x, *stage_u;  // FP32-bulk: staging of injected particles
@@ -163,8 +218,9 @@ struct TubeDev {
     gptr<double> x[2], u[2];
     gptr<int> cl[2];
     gptr<float> ol[2], ul[2];
-    gptr<int> ch[2];
-    gptr<float> oh[2];
+    gptr<unsigned> hp[2];
+    gptr<int> hw[2];
+    gptr<int> hg[2];
     gptr<double> uh[2];
     gptr<double> ez[2], er[2], b[2];
     gptr<int64_t> j[2];

@@ -189,8 +189,9 @@ Workspace carve(const pic_params &p, uint8_t *base)
             w.cl[k] = (int *)take(cap * 4 + 16);
             w.ol[k] = (float *)take(cap * 4 + 16);
             w.ul[k] = (float *)take(cap * 4 + 16);
-            w.ch[k] = (int *)take(cap * 4 + 16);
-            w.oh[k] = (float *)take(cap * 4 + 16);
+            w.hp[k] = (unsigned *)take(cap * 4 + 16);
+            w.hw[k] = (int *)take(cap * 4 + 16);
+            w.hg[k] = (int *)take((size_t)(hi_groups((int64_t)cap) + 16) * 4);
             w.uh[k] = (double *)take(cap * 8 + 32);
         }
         w.k32 = (float *)take(N * 4);
@@ -236,6 +237,61 @@ namespace {
 hipError_t launch_push(pic_handle *h)
 {
     return h->p.precision == PIC_FP32_BULK ? launch_push_f32(h) : launch_push_f64(h);
+}
+
+// The first ns slots of the high stream of particle buffer b, decoded on the
+// host: cell (-1 for a removed slot), offset (exact in f32) and u.
+pic_status read_high_stream(pic_handle *h, int b, int64_t ns, std::vector<int> &cell, std::vector<float> &off,
+                            std::vector<double> &u)
+{
+    const Workspace &w = h->ws;
+    const size_t n = (size_t)ns, ng = (size_t)hi_groups(ns);
+    std::vector<unsigned> hp(n);
+    std::vector<int> hw(n), hg(ng);
+    cell.assign(n, -1);
+    off.assign(n, 0.0f);
+    u.assign(n, 0.0);
+    if (n == 0) return PIC_OK;
+    HIP_OK(hipMemcpyAsync(hp.data(), w.hp[b], n * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipMemcpyAsync(hw.data(), w.hw[b], n * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipMemcpyAsync(hg.data(), w.hg[b], ng * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipMemcpyAsync(u.data(), w.uh[b], n * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    for (size_t i = 0; i < n; ++i) {
+        const unsigned v = hp[i];
+        off[i] = hi_offset(v);
+        cell[i] = v == HI_DEAD ? -1 : hi_cell(v, hg[i >> HI_GROUP_LOG2], hw[i]);
+    }
+    return PIC_OK;
+}
+
+// Writes ns slots (cell, offset, u) as the high stream of particle buffer b, in
+// the wide form; offsets go onto the stream's 2^-24 grid (those it wrote are
+// on it already), a cell below 0 marks a removed slot.
+pic_status write_high_stream(pic_handle *h, int b, int64_t ns, const int *cell, const float *off, const double *u)
+{
+    const Workspace &w = h->ws;
+    const size_t n = (size_t)ns, ng = (size_t)hi_groups(ns);
+    if (n == 0) return PIC_OK;
+    std::vector<unsigned> hp(n);
+    std::vector<int> hw(n), hg(ng, HI_WIDE);
+    const int N = (int)h->c.N;
+    for (size_t i = 0; i < n; ++i) {
+        int c = cell[i];
+        unsigned frac = 0;
+        if (c >= 0) {
+            hi_snap((double)off[i], c, frac);
+            if (c >= N) { c = N - 1; frac = HI_FRAC_MASK; }
+        }
+        hw[i] = c;
+        hp[i] = c >= 0 ? frac : HI_DEAD;
+    }
+    HIP_OK(hipMemcpyAsync(w.hp[b], hp.data(), n * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(w.hw[b], hw.data(), n * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(w.hg[b], hg.data(), ng * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(w.uh[b], u, n * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return PIC_OK;
 }
 
 pic_status read_counters(pic_handle *h, DevCounters *out)
@@ -806,15 +862,12 @@ pic_status pic_read_particles(pic_handle *h, double *x, double *u, int64_t cap, 
             std::vector<int> hc((size_t)ns);
             std::vector<float> ho((size_t)ns), hul((size_t)ns);
             std::vector<double> huh((size_t)ns);
-            if (ns > 0) {
-                HIP_OK(hipMemcpyAsync(hc.data(), st ? h->ws.ch[b] : h->ws.cl[b], (size_t)ns * 4, hipMemcpyDeviceToHost,
-                                      h->stream));
-                HIP_OK(hipMemcpyAsync(ho.data(), st ? h->ws.oh[b] : h->ws.ol[b], (size_t)ns * 4, hipMemcpyDeviceToHost,
-                                      h->stream));
-                if (st)
-                    HIP_OK(hipMemcpyAsync(huh.data(), h->ws.uh[b], (size_t)ns * 8, hipMemcpyDeviceToHost, h->stream));
-                else
-                    HIP_OK(hipMemcpyAsync(hul.data(), h->ws.ul[b], (size_t)ns * 4, hipMemcpyDeviceToHost, h->stream));
+            if (st) {
+                if (pic_status e = read_high_stream(h, b, ns, hc, ho, huh)) return e;
+            } else if (ns > 0) {
+                HIP_OK(hipMemcpyAsync(hc.data(), h->ws.cl[b], (size_t)ns * 4, hipMemcpyDeviceToHost, h->stream));
+                HIP_OK(hipMemcpyAsync(ho.data(), h->ws.ol[b], (size_t)ns * 4, hipMemcpyDeviceToHost, h->stream));
+                HIP_OK(hipMemcpyAsync(hul.data(), h->ws.ul[b], (size_t)ns * 4, hipMemcpyDeviceToHost, h->stream));
                 HIP_OK(hipStreamSynchronize(h->stream));
             }
             for (int64_t i = 0; i < ns; ++i) {
@@ -1005,9 +1058,17 @@ pic_status pic_save(pic_handle *h, void *buf, size_t cap, size_t *bytes)
         HIP_OK(d2h(L.p[0], w.cl[b], (size_t)nlo * 4));
         HIP_OK(d2h(L.p[1], w.ol[b], (size_t)nlo * 4));
         HIP_OK(d2h(L.p[2], w.ul[b], (size_t)nlo * 4));
-        HIP_OK(d2h(L.p[3], w.ch[b], (size_t)nhi * 4));
-        HIP_OK(d2h(L.p[4], w.oh[b], (size_t)nhi * 4));
-        HIP_OK(d2h(L.p[5], w.uh[b], (size_t)nhi * 8));
+        HIP_OK(hipStreamSynchronize(h->stream));
+        // the high stream as (cell, offset, u), as the low stream is kept
+        std::vector<int> hc;
+        std::vector<float> ho;
+        std::vector<double> hu;
+        if (pic_status e = read_high_stream(h, b, nhi, hc, ho, hu)) return e;
+        if (nhi > 0) {
+            memcpy(o + L.p[3], hc.data(), (size_t)nhi * 4);
+            memcpy(o + L.p[4], ho.data(), (size_t)nhi * 4);
+            memcpy(o + L.p[5], hu.data(), (size_t)nhi * 8);
+        }
     }
     HIP_OK(hipStreamSynchronize(h->stream));
     return PIC_OK;
@@ -1064,9 +1125,15 @@ pic_status pic_load(pic_handle *h, const void *buf, size_t bytes)
         HIP_OK(h2d(w.cl[b], L.p[0], (size_t)hd.n_lo * 4));
         HIP_OK(h2d(w.ol[b], L.p[1], (size_t)hd.n_lo * 4));
         HIP_OK(h2d(w.ul[b], L.p[2], (size_t)hd.n_lo * 4));
-        HIP_OK(h2d(w.ch[b], L.p[3], (size_t)hd.n_hi * 4));
-        HIP_OK(h2d(w.oh[b], L.p[4], (size_t)hd.n_hi * 4));
-        HIP_OK(h2d(w.uh[b], L.p[5], (size_t)hd.n_hi * 8));
+        if (hd.n_hi > 0) {
+            std::vector<int> hc((size_t)hd.n_hi);
+            std::vector<float> ho((size_t)hd.n_hi);
+            std::vector<double> hu((size_t)hd.n_hi);
+            memcpy(hc.data(), in + L.p[3], (size_t)hd.n_hi * 4);
+            memcpy(ho.data(), in + L.p[4], (size_t)hd.n_hi * 4);
+            memcpy(hu.data(), in + L.p[5], (size_t)hd.n_hi * 8);
+            if (pic_status e = write_high_stream(h, b, hd.n_hi, hc.data(), ho.data(), hu.data())) return e;
+        }
     }
     HIP_OK(hipMemcpyAsync(w.ctr, &ctr, sizeof ctr, hipMemcpyHostToDevice, h->stream));
     HIP_OK(launch_kick(h));

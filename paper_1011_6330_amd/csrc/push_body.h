@@ -157,8 +157,9 @@ struct Push32Args {
     int *__restrict__ CL;
     float *__restrict__ OL;
     float *__restrict__ UL;
-    int *__restrict__ CH;
-    float *__restrict__ OH;
+    unsigned *__restrict__ HP;       // high stream: position words
+    int *__restrict__ HW;            //   cells of the slots of wide groups
+    int *__restrict__ HG;            //   group headers
     double *__restrict__ UH;
     const float *__restrict__ K32;   // (float)((q/m) dt E_z) at the faces (low stream)
     const double *__restrict__ EZ;   // E_z^n at the faces (high stream: kick (q/m) dt E_z in f64)
@@ -190,9 +191,11 @@ __device__ __forceinline__ int gather_face_f32(int N, int cell, float off, float
 }
 
 // One particle of the low stream (f32 momentum) with its gathered kick E, in
-// place; straight-line code with selects, as push_one_f64.
-__device__ __forceinline__ void push_one_lo(const Consts &c, const Push32Args &a, float E, int &cr, float &orf,
-                                            float &ur, DepAcc &acc)
+// place; straight-line code with selects, as push_one_f64.  A particle whose
+// |u| has reached the high stream's threshold uf (the sort will move it there)
+// lands on the 2^-24 offset grid of that stream before it deposits.
+__device__ __forceinline__ void push_one_lo(const Consts &c, const Push32Args &a, float E, float uf, int &cr,
+                                            float &orf, float &ur, DepAcc &acc)
 {
     const int N = (int)c.N;
     const int cell = cr;
@@ -205,6 +208,12 @@ __device__ __forceinline__ void push_one_lo(const Consts &c, const Push32Args &a
     float o1 = off + (float)c.dtdz * v;
     int c1 = cell;
     carry_f32(o1, c1);
+    if (fabsf(u1) >= uf) {
+        const float q = rintf(o1 * 16777216.0f);
+        const bool up = q >= 16777216.0f;
+        c1 += up ? 1 : 0;
+        o1 = up ? 0.0f : q * 0x1p-24f;
+    }
     const bool fin = isfinite(u1) && isfinite(o1);
     const bool ok = live && fin;
     const double F0 = rint((double)off * c.twoP);
@@ -226,34 +235,49 @@ __device__ __forceinline__ void push_one_lo(const Consts &c, const Push32Args &a
     ur = stays ? u1 : u;
 }
 
-// One particle of the high stream (f64 momentum, f32 offset).
-__device__ __forceinline__ void push_one_hi(const Consts &c, const Push32Args &a, double E, int &cr, float &orf,
-                                            double &ur, DepAcc &acc)
+// One particle of the high stream (f64 momentum, offset frac 2^-24 in the
+// cell): kick, gamma and v in f64; the move c dt v / dz is rounded to the
+// 2^-24 grid and added to the offset in integers (|move| < 1 cell, so the
+// carry is the sign of the sum's high bits), and the deposit takes the stored
+// positions, so that the current carries the charge exactly where it is kept.
+// BIG (the whole wave has |u| >= 2^19 after the kick): with t = 1/u^2 <=
+// 2^-38, v = sign(u) (1 - t/2) and gamma = |u| + 1/(2|u|) leave out terms
+// below 2^-77 of v and 2^-58 of gamma; 1/u comes from the hardware estimate
+// (good to about 2^-24) and one Newton step, which squares its error, so v and
+// gamma are within half an ulp plus 2^-20 of an ulp of their correctly rounded
+// values.  Otherwise gamma and v as the FP64 push forms them.  mscale =
+// (c dt / dz) 2^24, fscale = 2^(P - 24).
+// u1 is the momentum after the kick; a slot that ends removed keeps whatever
+// momentum, as nothing reads it.
+template <bool BIG>
+__device__ __forceinline__ void push_one_hi(const Consts &c, unsigned long long *J, double u1, double mscale,
+                                            double fscale, int &cr, unsigned &fr, DepAcc &acc)
 {
     const int N = (int)c.N;
     const int cell = cr;
-    const float off = orf;
-    const double u = ur;
+    const unsigned frac = fr;
     const bool live = cell >= 0;
-    const double u1 = u + E;
-    double tt = u1 * u1;
-    tt = 1.0 + tt;
     double gam, v;
-    gamma_velocity(u1, tt, gam, v);
-    const double od = (double)off + c.dtdz * v;
-    const bool up = od >= 1.0, dn = od < 0.0;
-    const double od1 = up ? od - 1.0 : (dn ? od + 1.0 : od);
-    int c1 = cell + (up ? 1 : (dn ? -1 : 0));
-    float o1 = (float)od1;
-    if (o1 >= 1.0f) {                            // rounds up to the next cell
-        o1 = 0.0f;
-        c1 += 1;
+    if (BIG) {
+        const double r0 = __builtin_amdgcn_rcp(u1);
+        const double r = fma(r0, fma(-u1, r0, 1.0), r0);
+        const double h = 0.5 * r;
+        v = copysign(fma(-h, r, 1.0), u1);
+        gam = fabs(u1) + fabs(h);
+    } else {
+        double tt = u1 * u1;
+        tt = 1.0 + tt;
+        gamma_velocity(u1, tt, gam, v);
     }
-    const bool fin = isfinite(u1) && isfinite(od);
+    const int mv = (int)rint(v * mscale);          // |mv| <= 2^24
+    const int nf = (int)frac + mv;
+    const int c1 = cell + (nf >> HI_FRAC_BITS);    // -1, 0 or +1 cells
+    const unsigned f1 = (unsigned)nf & HI_FRAC_MASK;
+    const bool fin = isfinite(u1);
     const bool ok = live && fin;
-    const double F0 = rint((double)off * c.twoP);
-    const double F1 = rint((double)o1 * c.twoP);
-    acc.deposit_sel(a.J, N, c.twoP, ok, cell, F0, c1, F1);
+    const double F0 = rint((double)frac * fscale);
+    const double F1 = rint((double)f1 * fscale);
+    acc.deposit_sel(J, N, c.twoP, ok, cell, F0, c1, F1);
     const bool exits = ok && c1 >= N, absorbed = ok && c1 < 0;
     const bool stays = ok && !exits && !absorbed;
     if (exits) acc.exit_gamma(gam);
@@ -261,8 +285,7 @@ __device__ __forceinline__ void push_one_hi(const Consts &c, const Push32Args &a
     if (stays && c1 == 0) acc.node0(c.twoP - F1);
     if (live && !fin) acc.lost();
     cr = stays ? c1 : (live ? -1 : cell);
-    orf = stays ? o1 : off;
-    ur = stays ? u1 : u;
+    fr = stays ? f1 : frac;
 }
 
 // One tile of BLOCK*F32_PPT_LO consecutive slots of the low stream, starting at
@@ -307,8 +330,9 @@ __device__ __forceinline__ void push_tile_lo(const Consts &c, const Push32Args &
     }
     DepAcc acc;
     acc.init(a.ctr);
+    const float uf = f32_at_least(a.u_hi);
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) push_one_lo(c, a, E[k], cs[k], os[k], us[k], acc);
+    for (int k = 0; k < PPT; ++k) push_one_lo(c, a, E[k], uf, cs[k], os[k], us[k], acc);
     if (full) {
         st16<NT, ivec4>(C + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
         st16<NT, fvec4>(O + p0, fvec4{os[0], os[1], os[2], os[3]});
@@ -332,7 +356,10 @@ __device__ __forceinline__ void push_tile_lo(const Consts &c, const Push32Args &
 }
 
 // One tile of BLOCK*F32_PPT_HI consecutive slots of the high stream (f64
-// momentum), starting at tile0 (< n).  Wave-collective, as push_tile_lo.
+// momentum), starting at tile0 (< n).  Wave-collective, as push_tile_lo.  Each
+// wave takes one group of HI_GROUP slots: it decodes the positions with the
+// group's header (reading the cell array only for a wide group), pushes, and
+// writes the group back narrow or wide as its new live cells allow.
 template <int BLOCK, int NT>
 __device__ __forceinline__ void push_tile_hi(const Consts &c, const Push32Args &a, int64_t n, int64_t tile0)
 {
@@ -340,50 +367,129 @@ __device__ __forceinline__ void push_tile_hi(const Consts &c, const Push32Args &
     const int N = (int)c.N;
     const int64_t p0 = tile0 + (int64_t)threadIdx.x * PPT;
     const bool full = p0 + PPT <= n;
-    int *C = a.CH;
-    float *O = a.OH;
-    int cs[PPT];
-    float os[PPT];
+    // the wave's group (tile0 is a multiple of HI_GROUP): uniform, so the header is a scalar load
+    const int grp = __builtin_amdgcn_readfirstlane((int)(p0 >> HI_GROUP_LOG2));
+    const bool has = __builtin_amdgcn_readfirstlane((int)(p0 < n)) != 0;   // the wave holds slots below n
+    const int hdr = has ? a.HG[grp] : 0;
+    unsigned ws[PPT];
+    int wc[PPT];
     double us[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) wc[k] = 0;
     if (full) {
-        const ivec2 cv = ld16<NT, ivec2>(C + p0);
-        const fvec2 ov = ld16<NT, fvec2>(O + p0);
-        const dvec2 uv = ld16<NT, dvec2>(a.UH + p0);
-        cs[0] = cv.x; cs[1] = cv.y;
-        os[0] = ov.x; os[1] = ov.y;
-        us[0] = uv.x; us[1] = uv.y;
+        if constexpr (PPT == 4) {
+            const uvec4 pv = ld16<NT, uvec4>(a.HP + p0);
+            const dvec2 ua = ld16<NT, dvec2>(a.UH + p0), ub = ld16<NT, dvec2>(a.UH + p0 + 2);
+            ws[0] = pv.x; ws[1] = pv.y; ws[2] = pv.z; ws[3] = pv.w;
+            us[0] = ua.x; us[1] = ua.y; us[2] = ub.x; us[3] = ub.y;
+            if (hdr < 0) {
+                const ivec4 cv = ld16<NT, ivec4>(a.HW + p0);
+                wc[0] = cv.x; wc[1] = cv.y; wc[2] = cv.z; wc[3] = cv.w;
+            }
+        } else {
+            const uvec2 pv = ld16<NT, uvec2>(a.HP + p0);
+            const dvec2 uv = ld16<NT, dvec2>(a.UH + p0);
+            ws[0] = pv.x; ws[1] = pv.y;
+            us[0] = uv.x; us[1] = uv.y;
+            if (hdr < 0) {
+                const ivec2 cv = ld16<NT, ivec2>(a.HW + p0);
+                wc[0] = cv.x; wc[1] = cv.y;
+            }
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            cs[k] = p0 + k < n ? C[p0 + k] : -1;
-            os[k] = p0 + k < n ? O[p0 + k] : 0.0f;
+            ws[k] = p0 + k < n ? a.HP[p0 + k] : HI_DEAD;
             us[k] = p0 + k < n ? a.UH[p0 + k] : 0.0;
+            if (hdr < 0 && p0 + k < n) wc[k] = a.HW[p0 + k];
         }
     }
-    double E[PPT];
+    int cs[PPT];
+    unsigned fs[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        cs[k] = ws[k] != HI_DEAD ? hi_cell(ws[k], hdr, wc[k]) : -1;
+        fs[k] = ws[k] & HI_FRAC_MASK;
+    }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         float g;
         int j;
-        const int jc = gather_face_f32(N, cs[k], os[k], g, j);
+        const int jc = gather_face_f32(N, cs[k], hi_offset(fs[k]), g, j);
         const double k0 = c.qmdt * a.EZ[jc], k1 = c.qmdt * a.EZ[jc + 1];
         const double Ei = k0 + (double)g * (k1 - k0);
         const double lo = j < 0 ? k0 : Ei;
-        E[k] = j >= N - 1 ? k1 : lo;
+        us[k] += j >= N - 1 ? k1 : lo;            // the kick: us holds u^{n+1/2} from here on
     }
     DepAcc acc;
     acc.init(a.ctr);
+    // the wave's old cells: when they lie in two consecutive cells, every lane
+    // takes the lower one as its current channel base, so the flush is one run
+    {
+        int lo_o = INT_MAX, hi_o = INT_MIN;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) push_one_hi(c, a, E[k], cs[k], os[k], us[k], acc);
+        for (int k = 0; k < PPT; ++k) {
+            if (cs[k] >= 0) {
+                lo_o = cs[k] < lo_o ? cs[k] : lo_o;
+                hi_o = cs[k] > hi_o ? cs[k] : hi_o;
+            }
+        }
+        lo_o = hdr >= 0 ? hdr : wave_min_i32(lo_o);
+        hi_o = wave_max_i32(hi_o);
+        if (hi_o >= lo_o && hi_o - lo_o <= 1) acc.cf = lo_o;
+    }
+    const double mscale = c.dtdz * 16777216.0, fscale = c.twoP * 0x1p-24;
+    bool big = true;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) big = big && (cs[k] < 0 || fabs(us[k]) >= 0x1p19);
+    if (__all(big)) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            push_one_hi<true>(c, a.J, us[k], mscale, fscale, cs[k], fs[k], acc);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            push_one_hi<false>(c, a.J, us[k], mscale, fscale, cs[k], fs[k], acc);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // the group's new form: narrow, based at its lowest live cell, if the live cells span <= HI_SPAN
+    int lo_c = INT_MAX, hi_c = INT_MIN;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (cs[k] >= 0) {
+            lo_c = cs[k] < lo_c ? cs[k] : lo_c;
+            hi_c = cs[k] > hi_c ? cs[k] : hi_c;
+        }
+    }
+    lo_c = wave_min_i32(lo_c);
+    hi_c = wave_max_i32(hi_c);
+    const int nh = lo_c == INT_MAX ? 0 : (hi_c - lo_c <= HI_SPAN ? lo_c : HI_WIDE);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) ws[k] = cs[k] >= 0 ? hi_word(cs[k], fs[k], nh) : HI_DEAD;
     if (full) {
-        st16<NT, ivec2>(C + p0, ivec2{cs[0], cs[1]});
-        st16<NT, fvec2>(O + p0, fvec2{os[0], os[1]});
-        st16<NT, dvec2>(a.UH + p0, dvec2{us[0], us[1]});
+        if constexpr (PPT == 4) {
+            st16<NT, uvec4>(a.HP + p0, uvec4{ws[0], ws[1], ws[2], ws[3]});
+            st16<NT, dvec2>(a.UH + p0, dvec2{us[0], us[1]});
+            st16<NT, dvec2>(a.UH + p0 + 2, dvec2{us[2], us[3]});
+            if (nh < 0) st16<NT, ivec4>(a.HW + p0, ivec4{cs[0], cs[1], cs[2], cs[3]});
+        } else {
+            st16<NT, uvec2>(a.HP + p0, uvec2{ws[0], ws[1]});
+            st16<NT, dvec2>(a.UH + p0, dvec2{us[0], us[1]});
+            if (nh < 0) st16<NT, ivec2>(a.HW + p0, ivec2{cs[0], cs[1]});
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
-            if (p0 + k < n) { C[p0 + k] = cs[k]; O[p0 + k] = os[k]; a.UH[p0 + k] = us[k]; }
+            if (p0 + k < n) {
+                a.HP[p0 + k] = ws[k];
+                a.UH[p0 + k] = us[k];
+                if (nh < 0) a.HW[p0 + k] = cs[k];
+            }
     }
+    if (__lane_id() == 0 && has) a.HG[grp] = nh;
     acc.flush_current(a.J);
     if (a.hist) {
         int64_t key[PPT];
@@ -391,7 +497,7 @@ __device__ __forceinline__ void push_tile_hi(const Consts &c, const Push32Args &
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             live[k] = cs[k] >= 0;
-            key[k] = live[k] ? sort_key_f32(c, cs[k], os[k], fabs(us[k]) >= a.u_hi) : 0;
+            key[k] = live[k] ? sort_key_f32(c, cs[k], hi_offset(fs[k]), fabs(us[k]) >= a.u_hi) : 0;
         }
         hist_add<PPT>(a.hist, key, live);
     }

@@ -6,6 +6,7 @@
 // make the result independent of the order of particles, lanes and blocks.
 #pragma once
 
+#include <limits.h>
 #include <math.h>
 
 #include "pcpic_internal.h"
@@ -173,6 +174,8 @@ typedef float fvec4 __attribute__((ext_vector_type(4)));
 typedef int ivec4 __attribute__((ext_vector_type(4)));
 typedef float fvec2 __attribute__((ext_vector_type(2)));
 typedef int ivec2 __attribute__((ext_vector_type(2)));
+typedef unsigned uvec2 __attribute__((ext_vector_type(2)));
+typedef unsigned uvec4 __attribute__((ext_vector_type(4)));
 
 // Particle-stream vector access (16 or 8 bytes, the size of V); NT = 1 marks it
 // nontemporal (each value is streamed once per step and should not displace

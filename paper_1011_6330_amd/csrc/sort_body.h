@@ -25,10 +25,32 @@ struct Streams {
     int *CL;
     float *OL;
     float *UL;
-    int *CH;
-    float *OH;
+    unsigned *HP;   // high stream: position words, cells of wide groups, group headers
+    int *HW;
+    int *HG;
     double *UH;
 };
+
+// Cell (-1 for a removed slot) and offset of high-stream slot p.
+__device__ __forceinline__ int hi_slot(const Streams &s, int64_t p, float &off)
+{
+    const unsigned w = s.HP[p];
+    off = hi_offset(w);
+    if (w == HI_DEAD) return -1;
+    const int hdr = s.HG[p >> HI_GROUP_LOG2];
+    return hdr >= 0 ? hi_cell(w, hdr, 0) : s.HW[p];
+}
+
+// Writes a live particle (cell, frac in units of 2^-24) at high-stream slot q
+// of a stream being filled in the wide form (the sort, the appends); the first
+// slot of each group sets the group's header.
+__device__ __forceinline__ void hi_put_wide(const Streams &s, int64_t q, int cell, unsigned frac, double u)
+{
+    s.HW[q] = cell;
+    s.HP[q] = frac;
+    s.UH[q] = u;
+    if ((q & (HI_GROUP - 1)) == 0) s.HG[q >> HI_GROUP_LOG2] = HI_WIDE;
+}
 
 // Destination stream of a particle: the high stream from |u| >= u_hi on.
 __device__ __forceinline__ bool goes_high(double u, double u_hi) { return fabs(u) >= u_hi; }
@@ -99,8 +121,6 @@ __device__ __forceinline__ void scatter_tile_f32(const Consts &c, const Streams 
                                                  int64_t tile0)
 {
     const int lane = (int)__lane_id();
-    const int *C = HI ? src.CH : src.CL;
-    const float *O = HI ? src.OH : src.OL;
     int cl[SORT_PPT];
     float o[SORT_PPT];
     double u[SORT_PPT];
@@ -108,9 +128,15 @@ __device__ __forceinline__ void scatter_tile_f32(const Consts &c, const Streams 
     for (int k = 0; k < SORT_PPT; ++k) {
         const int64_t p = tile0 + (int64_t)k * SORT_BLOCK + threadIdx.x;
         const bool in = p < n;
-        cl[k] = in ? __builtin_nontemporal_load(C + p) : -1;
-        o[k] = in ? __builtin_nontemporal_load(O + p) : 0.0f;
-        u[k] = in ? (HI ? __builtin_nontemporal_load(src.UH + p) : (double)__builtin_nontemporal_load(src.UL + p)) : 0.0;
+        if (HI) {
+            o[k] = 0.0f;
+            cl[k] = in ? hi_slot(src, p, o[k]) : -1;
+            u[k] = in ? __builtin_nontemporal_load(src.UH + p) : 0.0;
+        } else {
+            cl[k] = in ? __builtin_nontemporal_load(src.CL + p) : -1;
+            o[k] = in ? __builtin_nontemporal_load(src.OL + p) : 0.0f;
+            u[k] = in ? (double)__builtin_nontemporal_load(src.UL + p) : 0.0;
+        }
     }
     const int64_t klo = sort_low_keys(c);
     int64_t key[SORT_PPT];
@@ -134,10 +160,12 @@ __device__ __forceinline__ void scatter_tile_f32(const Consts &c, const Streams 
         if (want[k]) {
             const int64_t d = (int64_t)f[k] + r[k].rank;
             if (key[k] >= klo) {
-                const int64_t q = d - tlo;
-                dst.CH[q] = cl[k];
-                dst.OH[q] = o[k];
-                dst.UH[q] = u[k];
+                // a low particle reaching the threshold was put on the 2^-24 grid by its push
+                int cell = cl[k];
+                unsigned frac;
+                hi_snap((double)o[k], cell, frac);
+                if (cell >= (int)c.N) { cell = (int)c.N - 1; frac = HI_FRAC_MASK; }
+                hi_put_wide(dst, d - tlo, cell, frac, u[k]);
             } else {
                 dst.CL[d] = cl[k];
                 dst.OL[d] = o[k];
@@ -159,11 +187,12 @@ __device__ __forceinline__ void hist_tile(const Consts &c, bool f32, bool hi, co
         int64_t key = 0;
         if (p < n) {
             if (f32) {
-                const int cell = hi ? s.CH[p] : s.CL[p];
+                float off = 0.0f;
+                const int cell = hi ? hi_slot(s, p, off) : s.CL[p];
                 if (cell >= 0) {
                     const double u = hi ? s.UH[p] : (double)s.UL[p];
                     live = true;
-                    key = sort_key_f32(c, cell, hi ? s.OH[p] : s.OL[p], goes_high(u, u_hi));
+                    key = sort_key_f32(c, cell, hi ? off : s.OL[p], goes_high(u, u_hi));
                 }
             } else {
                 const double x = X[p];
