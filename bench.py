@@ -50,7 +50,7 @@ METRIC = "particle-steps/sec + % HBM roofline, FP64 plain vs FP32-bulk; adjoint/
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 B_FP64 = 32                    # x, u (f64) read + written per particle-step
 B_F32_LOW = 24                 # cell, offset, u (f32)
-B_F32_HIGH = 32                # cell, offset (4 B each), u (f64)
+B_F32_HIGH = 24                # position word (4 B), u (f64); the per-group header is 4 B per 256 slots
 B_GRID_PUSH = 16               # per cell and push: the kick (E_z) read, the current written
 DEFAULT_PUSH = "128:2:nt"      # FP64 push launch shape: threads, slots per thread, nontemporal
 DEFAULT_PUSH32 = "128:4:nt"    # FP32-bulk push launch shape

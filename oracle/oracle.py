@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PCPIC_ORACLE_LIB") or os.path.join(HERE, "libpcpic_oracle.so")
 
 RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS, RHO_GR = 0, 1, 2, 3
-NO_AUTO_INJECT, FREEZE_FIELDS, B_STEADY_INIT = 1, 2, 4
+NO_AUTO_INJECT, FREEZE_FIELDS, B_STEADY_INIT, GR_ALPHA = 1, 2, 4, 8
 ST_CAPACITY, ST_NONFINITE = 1, 2
 
 DEFAULTS = dict(n_cells=1024, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=-1.0,

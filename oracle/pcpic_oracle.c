@@ -29,6 +29,8 @@ typedef struct {
     int64_t N;
     double dz, dt, dtdz, dtR, qmdt, rho0, qm, qmP, fourpi, c4, fqm, hdz, tw, twoP;
     int64_t oneP; /* 2^P as an integer */
+    int gr;       /* ORC_GR_ALPHA */
+    double cg;    /* dt (r_g/R_*) / (2 R_*): k_g = cg / eta^2 = dt alpha alpha' */
 } orc_const;
 
 static int orc_check(const orc_cfg *c)
@@ -40,7 +42,26 @@ static int orc_check(const orc_cfg *c)
     if (c->rho_kind == ORC_RHO_GR &&
         (!(c->rg_over_rstar >= 0.0 && c->rg_over_rstar < 1.0) || !(fabs(c->incl) < 1.5) || !(c->r_star > 0)))
         return -1;
+    if ((c->flags & ORC_GR_ALPHA) && (!(c->rg_over_rstar >= 0.0 && c->rg_over_rstar < 1.0) || !(c->r_star > 0)))
+        return -1;
     return 0;
+}
+
+/* alpha^2 = 1 - r_g/r at height z (ORC_GR_ALPHA), r/R_* = eta = 1 + z/R_*. */
+static double orc_alpha2(const orc_cfg *c, double z)
+{
+    double eta = 1.0 + z / c->r_star;
+    return 1.0 - c->rg_over_rstar / eta;
+}
+
+/* alpha at node i and at face i+1/2. */
+static double orc_alpha_node(const orc_cfg *c, double dz, int64_t i)
+{
+    return sqrt(orc_alpha2(c, (double)i * dz));
+}
+static double orc_alpha_face(const orc_cfg *c, double dz, int64_t i)
+{
+    return sqrt(orc_alpha2(c, ((double)i + 0.5) * dz));
 }
 
 /* Goldreich-Julian background at node i (eqs. 5-7).
@@ -106,6 +127,8 @@ static void orc_consts(const orc_cfg *c, const orc_state *st, orc_const *k)
     k->fqm = k->fourpi * k->qm;                    /* surface-field change per injected particle */
     k->hdz = 0.5 * k->dz;
     k->tw = 2.0 * k->dtdz;
+    k->gr = (c->flags & ORC_GR_ALPHA) != 0;
+    k->cg = ((0.5 * k->dt) * c->rg_over_rstar) / c->r_star;
 }
 
 /* ---- weighting (sec. 2: linear weighting between particles and grid) --- */
@@ -162,19 +185,25 @@ static void orc_solve_fields(const orc_cfg *c, orc_state *st)
     double h2 = rr * rr;
     double bdiag = -(2.0 + h2);
     double cpois = k.fourpi * dz2;
-    /* right-hand side d_i = -4 pi dz^2 (rho_i - rho_GJ,i) */
+    /* right-hand side d_i = -4 pi dz^2 (rho_i - rho_GJ,i) (GR: rho_GJ,i / alpha_i) */
     for (int64_t i = 1; i <= N; ++i) {
         int64_t wi = (i == N) ? 2 * st->w[i] : st->w[i];
         double rho = (k.qmP * (double)wi) / k.dz;
-        double t = rho - st->rho_gj[i];
+        double rg = k.gr ? st->rho_gj[i] / orc_alpha_node(c, k.dz, i) : st->rho_gj[i];
+        double t = rho - rg;
         st->dp[i] = -(cpois * t);
     }
-    /* forward sweep: sub-diagonal 1 (2 in row N), diagonal bdiag, super-diagonal 1 */
-    st->cp[1] = 1.0 / bdiag;
-    st->dp[1] = st->dp[1] / bdiag;
+    /* forward sweep: sub-diagonal 1 (2 in row N), diagonal bdiag (GR: -(2 + h2/alpha_i^2)),
+     * super-diagonal 1 */
+    {
+        double bd = k.gr ? -(2.0 + h2 / orc_alpha2(c, k.dz)) : bdiag;
+        st->cp[1] = 1.0 / bd;
+        st->dp[1] = st->dp[1] / bd;
+    }
     for (int64_t i = 2; i <= N; ++i) {
         double a = (i == N) ? 2.0 : 1.0;
-        double m = bdiag - a * st->cp[i - 1];
+        double bd = k.gr ? -(2.0 + h2 / orc_alpha2(c, (double)i * k.dz)) : bdiag;
+        double m = bd - a * st->cp[i - 1];
         st->cp[i] = 1.0 / m;
         st->dp[i] = (st->dp[i] - a * st->dp[i - 1]) / m;
     }
@@ -183,7 +212,8 @@ static void orc_solve_fields(const orc_cfg *c, orc_state *st)
     st->phi[N] = st->dp[N];
     for (int64_t i = N - 1; i >= 1; --i) st->phi[i] = st->dp[i] - st->cp[i] * st->phi[i + 1];
     for (int64_t i = 0; i < N; ++i) st->ez[i] = -((st->phi[i + 1] - st->phi[i]) / k.dz);
-    for (int64_t i = 0; i <= N; ++i) st->er[i] = st->phi[i] / c->radius;
+    for (int64_t i = 0; i <= N; ++i)
+        st->er[i] = (k.gr ? st->phi[i] / orc_alpha_node(c, k.dz, i) : st->phi[i]) / c->radius;
     for (int64_t i = 0; i < N; ++i) { st->b[i] = 0.0; st->j[i] = 0; st->k[i] = k.qmdt * st->ez[i]; }
     if (c->flags & ORC_B_STEADY_INIT) {
         /* Steady start of eq. (3): with dE_z/dt = 0 the E_z update gives B_phi = 4 pi R j.
@@ -196,7 +226,7 @@ static void orc_solve_fields(const orc_cfg *c, orc_state *st)
             t = 1.0 + t;
             double gam = sqrt(t);
             double v = u / gam;
-            double x1 = x + k.dtdz * v;
+            double x1 = k.gr ? x + k.dtdz * (orc_alpha2(c, x * k.dz) * v) : x + k.dtdz * v;
             int64_t c0, F0, c1, F1;
             orc_cell(x, c->fp_bits, &c0, &F0);
             orc_cell(x1, c->fp_bits, &c1, &F1);
@@ -207,6 +237,7 @@ static void orc_solve_fields(const orc_cfg *c, orc_state *st)
         }
         for (int64_t i = 0; i < N; ++i) {
             st->b[i] = (k.c4 * (double)st->j[i]) / k.dtR;
+            if (k.gr) st->b[i] = st->b[i] / orc_alpha_face(c, k.dz, i);
             st->j[i] = 0;
         }
     }
@@ -293,12 +324,37 @@ static void orc_push_range(const orc_cfg *c, const orc_state *st, const orc_cons
             E = st->k[jj] + g * (st->k[jj + 1] - st->k[jj]);
         }
         /* eq. (1): d(gamma m v)/dt = q E_z, dz/dt = v, with u = gamma v (c = 1) */
-        double u1 = u + E;
-        double tt = u1 * u1;
-        tt = 1.0 + tt;
-        double gam = sqrt(tt);
-        double v = u1 / gam;
-        double x1 = x + k->dtdz * v;
+        double u1, gam, v, x1;
+        if (k->gr) {
+            /* with the lapse alpha (ORC_GR_ALPHA): du/dt = alpha (q/m) E_z - gamma alpha alpha',
+             * dz/dt = alpha^2 v; midpoint gamma for gravity, midpoint alpha^2 for the move */
+            double eta = 1.0 + (x * k->dz) / c->r_star;
+            double a2 = 1.0 - c->rg_over_rstar / eta;
+            double al = sqrt(a2);
+            double kg = k->cg / (eta * eta);
+            double t0 = u * u;
+            t0 = 1.0 + t0;
+            double g0 = sqrt(t0);
+            double uh = u + 0.5 * (al * E - kg * g0);
+            double th = uh * uh;
+            th = 1.0 + th;
+            double gh = sqrt(th);
+            u1 = u + (al * E - kg * gh);
+            double tt = u1 * u1;
+            tt = 1.0 + tt;
+            gam = sqrt(tt);
+            v = u1 / gam;
+            double xh = x + 0.5 * (k->dtdz * (a2 * v));
+            double a2h = orc_alpha2(c, xh * k->dz);
+            x1 = x + k->dtdz * (a2h * v);
+        } else {
+            u1 = u + E;
+            double tt = u1 * u1;
+            tt = 1.0 + tt;
+            gam = sqrt(tt);
+            v = u1 / gam;
+            x1 = x + k->dtdz * v;
+        }
         if (!isfinite(u1) || !isfinite(x1)) { t->status |= ORC_ST_NONFINITE; continue; }
 
         /* charge-conserving current: J_{i+1/2} += S_i(x^n) - S_i(x^{n+1}) on every face */
@@ -354,7 +410,26 @@ static void orc_step_end(const orc_cfg *c, orc_state *st, const orc_const *k, co
     }
     const int64_t w0 = t->w0, w0_inj = t->w0_inj;
 
-    if (!(c->flags & ORC_FREEZE_FIELDS)) {
+    if (!(c->flags & ORC_FREEZE_FIELDS) && k->gr) {
+        /* the same leap-frog with the lapse (ORC_GR_ALPHA): alpha at faces (af) and nodes
+         * (an) on each term of eq. (3) as in the header; the deposit's J is alpha j */
+        const double dz = k->dz;
+        for (int64_t i = 0; i < N; ++i) {
+            double af = orc_alpha_face(c, dz, i);
+            double d = orc_alpha_node(c, dz, i + 1) * st->er[i + 1] - orc_alpha_node(c, dz, i) * st->er[i];
+            st->b[i] = st->b[i] - (k->dtdz * (af * d) + k->dtR * (af * st->ez[i]));
+        }
+        for (int64_t i = 1; i < N; ++i) {
+            double d = orc_alpha_face(c, dz, i) * st->b[i] - orc_alpha_face(c, dz, i - 1) * st->b[i - 1];
+            st->er[i] = st->er[i] - k->dtdz * (orc_alpha_node(c, dz, i) * d);
+        }
+        st->er[N] = st->er[N] + k->tw * (orc_alpha_node(c, dz, N) * (orc_alpha_face(c, dz, N - 1) * st->b[N - 1]));
+        for (int64_t i = 0; i < N; ++i) {
+            const double jw = (rate == 1.0 || !st->j_inj) ? (double)st->j[i]
+                                                          : (double)(st->j[i] - st->j_inj[i]) + rate * (double)st->j_inj[i];
+            st->ez[i] = (st->ez[i] + k->dtR * (orc_alpha_face(c, dz, i) * st->b[i])) - k->c4 * jw;
+        }
+    } else if (!(c->flags & ORC_FREEZE_FIELDS)) {
         /* eq. (3), leap-frog: dB/dt = -dE_r/dz - E_z/R, then dE_r/dt = -dB/dz,
          * then dE_z/dt = B/R - 4 pi j.  E_r,0 = 0 (phi = 0 at the star);
          * mirror about x = N (B odd) gives the E_r,N update. */
@@ -381,6 +456,7 @@ static void orc_step_end(const orc_cfg *c, orc_state *st, const orc_const *k, co
     double t1 = rate == 1.0 ? k->qmP * (double)w0
                             : k->qmP * ((double)(w0 - w0_inj) + rate * (double)w0_inj);
     double t2 = k->rho0 * k->hdz;
+    if (k->gr) t2 = t2 / orc_alpha_node(c, k->dz, 0);    /* rho_GJ,0 / alpha_0 over the half cell */
     double es = st->ez[0] - k->fourpi * (t1 - t2);
     st->e_surf = es;
     int64_t ninj = 0;
@@ -540,7 +616,14 @@ int orc_gauss(const orc_cfg *c, orc_state *st, double *g, double *gmax)
     g[0] = 0.0; g[N] = 0.0;
     for (int64_t i = 1; i < N; ++i) {
         double rho = (k.qmP * (double)st->w[i]) / k.dz;
-        double d = (st->ez[i] - st->ez[i - 1]) / k.dz + st->er[i] / c->radius;
+        double dez = (st->ez[i] - st->ez[i - 1]) / k.dz;
+        if (k.gr) {
+            /* ORC_GR_ALPHA: alpha_i dE_z/dz + E_r/R = 4 pi (alpha_i lambda_i - rho_GJ,i) */
+            double an = orc_alpha_node(c, k.dz, i);
+            dez = an * dez;
+            rho = an * rho;
+        }
+        double d = dez + st->er[i] / c->radius;
         g[i] = d - k.fourpi * (rho - st->rho_gj[i]);
         m = fmax(m, fabs(g[i]));
     }
@@ -735,7 +818,7 @@ int orc_adjoint(const orc_cfg *c, orc_state *st, int64_t T, double *g_rho, doubl
                 int64_t *n_exit_out)
 {
     if (orc_check(c) || !st || T < 1 || !st->cls || !st->j_inj) return -1;
-    if (c->flags & ORC_FREEZE_FIELDS) return -1;
+    if (c->flags & (ORC_FREEZE_FIELDS | ORC_GR_ALPHA)) return -1;
     orc_const k;
     orc_consts(c, st, &k);
     const int64_t N = k.N;

@@ -42,8 +42,38 @@ enum {
 enum {
     ORC_NO_AUTO_INJECT = 1u, /* skip the SCLF injection                                  */
     ORC_FREEZE_FIELDS = 2u,  /* skip the Maxwell update: fields stay as they are           */
-    ORC_B_STEADY_INIT = 4u   /* start B_phi = 4 pi R j of the loaded beam (steady E_z)     */
+    ORC_B_STEADY_INIT = 4u,  /* start B_phi = 4 pi R j of the loaded beam (steady E_z)     */
+    ORC_GR_ALPHA = 8u        /* lapse alpha(z) in Maxwell and the equation of motion (below) */
 };
+
+/*
+ * ORC_GR_ALPHA -- the full-GR factor alpha = (1 - r_g/r)^(1/2), r = R_* + z, in
+ * Maxwell's equations and the equation of motion, which the paper names after
+ * eqs. (6)-(7) but does not write out.  Reading (3+1 split of the Schwarzschild
+ * metric, fields and momenta measured by static observers, frame dragging kept
+ * in rho_GJ only, the tube's constant radius and d/dr -> 1/R as in eq. 3; z is
+ * the radial coordinate, t the coordinate time):
+ *   (1/c) dE_z/dt = alpha B/R - 4 pi (alpha j)
+ *   (1/c) dE_r/dt = -alpha d(alpha B)/dz
+ *   (1/c) dB/dt   = -alpha d(alpha E_r)/dz - alpha E_z/R
+ *   alpha dE_z/dz + E_r/R = 4 pi (alpha lambda - rho_GJ)
+ *   du/dt = alpha (q/m) E_z - gamma alpha alpha',   dz/dt = alpha^2 u/gamma
+ * lambda is the charge per unit coordinate length (the CIC weights) and
+ * alpha j its coordinate flux, which is what the charge-conserving deposit
+ * counts, so the discrete Gauss law below is kept exactly as in flat space.
+ * alpha alpha' = (r_g/R_*) / (2 R_* eta^2), eta = r/R_*; a test particle in a
+ * static field E_z = -dPhi/dz keeps alpha gamma + (q/m) Phi.
+ * Discretisation: alpha at nodes (a_i) and faces (a_{i+1/2}) multiplies the
+ * flat leap-frog terms as written above; the push takes alpha at x^n for the
+ * kick, a midpoint gamma for the gravity term (u_h = u + (alpha K - k_g gamma(u))/2,
+ * u' = u + alpha K - k_g gamma(u_h), k_g = dt alpha alpha'), and a midpoint alpha^2
+ * for the move (x_h = x + (c dt/dz) alpha^2(x) v / 2, x' = x + (c dt/dz) alpha^2(x_h) v);
+ * the Poisson start solves d2Phi/dz2 - Phi/(alpha R)^2 = -4 pi (lambda - rho_GJ/alpha)
+ * with E_z = -dPhi/dz and E_r = Phi/(alpha R), a fixed point of the update; the
+ * surface field takes rho_GJ,0/alpha_0 in the half cell.  With r_g = 0 every
+ * factor is 1 and the step is the flat one, bit for bit.  Uses r_star and
+ * rg_over_rstar (any rho_kind); not with the reverse-mode gradient.
+ */
 
 enum {
     ORC_ST_CAPACITY = 1,     /* injection wanted more particles than the capacity allows */
@@ -64,14 +94,15 @@ typedef struct orc_cfg {
     double r_star;        /* star radius R_*                                      */
     const double *knots;  /* theta_k, k = 0..n_knots-1, uniform over [0, L]        */
     int32_t fp_bits;      /* P, fixed-point fraction bits of the weights          */
-    uint32_t flags;       /* ORC_NO_AUTO_INJECT | ORC_FREEZE_FIELDS               */
+    uint32_t flags;       /* ORC_NO_AUTO_INJECT | ORC_FREEZE_FIELDS | ORC_B_STEADY_INIT | ORC_GR_ALPHA */
     int64_t capacity;     /* particle array capacity                              */
     double macro_charge;  /* q_m; 0 = rho_GJ(0) dz / ppc                          */
     double inj_rate;      /* charge factor of particles injected during the run (0 = 1) */
     const int64_t *schedule; /* if not NULL: particles injected at step n = schedule[n]
                                 (replaces the SCLF rule; frozen decisions)         */
     int64_t n_schedule;
-    /* ORC_RHO_GR only (eq. 6): inclination i (rad), theta_* (rad), cos(varphi) and r_g / R_* */
+    /* ORC_RHO_GR (eq. 6): inclination i (rad), theta_* (rad), cos(varphi) and r_g / R_*;
+       ORC_GR_ALPHA uses r_g / R_* and r_star */
     double incl;
     double theta_star;
     double cos_phi;

@@ -26,6 +26,7 @@ struct BatchArgs {
     const TubeDev *tubes;
     int n_tubes;
     int64_t *live_pref;          // [n_tubes + 1] prefix of the push items holding particles (k_batch_plan)
+    int64_t *live_counts;        // [2 n_tubes] slots of each tube's low and high stream (FP64: n, 0)
     const int64_t *field_pref;   // [n_tubes + 1] prefix of cell tiles
     const int32_t *field_map;    // cell tile -> tube
     int fb, jb, pb;              // field, current and particle buffer parities of the step
@@ -58,6 +59,8 @@ __global__ __launch_bounds__(256) void k_batch_plan(BatchArgs b)
             const DevCounters *ctr = generic(b.tubes[t].ctr);
             const int64_t n_lo = ctr->n_slots, n_hi = ctr->n_slots_hi;
             items = (n_lo + b.tile_lo - 1) / b.tile_lo + (n_hi + b.tile_hi - 1) / b.tile_hi;
+            b.live_counts[2 * t] = n_lo;
+            b.live_counts[2 * t + 1] = n_hi;
         }
         const long long inc = block_scan_incl(items, s_wave);
         const long long carry = s_carry;
@@ -69,6 +72,26 @@ __global__ __launch_bounds__(256) void k_batch_plan(BatchArgs b)
 }
 
 
+// The last t in [0, n) with pref[t] <= it, for a non-decreasing pref with
+// pref[0] <= it: each round, the 64 lanes of the wave test 64 evenly spaced
+// entries of the range left and keep the stretch after the last one that
+// passes, so 256 tubes take two rounds of loads (one per round, all lanes at
+// once) instead of eight dependent ones.  Wave-collective; uniform result.
+__device__ __forceinline__ int find_tube(const int64_t *pref, int n, int64_t it)
+{
+    const int lane = (int)__lane_id();
+    int lo = 0, len = n;
+    while (len > 64) {
+        const int S = (len + 63) >> 6;
+        const bool le = lane * S < len && pref[lo + lane * S] <= it;
+        const int L = 63 - __builtin_clzll(__ballot(le));
+        lo += L * S;
+        len = len - L * S < S ? len - L * S : S;
+    }
+    const bool le = lane < len && pref[lo + lane] <= it;
+    return __builtin_amdgcn_readfirstlane(lo + 63 - __builtin_clzll(__ballot(le)));
+}
+
 template <int BLOCK, int PPT, int NT, int F32>
 __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
 {
@@ -76,28 +99,22 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
     const int64_t it = blockIdx.x;
     if (it >= b.live_pref[b.n_tubes]) return;
     {
-        // the tube of item it: the last t with live_pref[t] <= it (uniform, scalar loads)
-        int lo = 0, hi = b.n_tubes;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (b.live_pref[mid] <= it) lo = mid;
-            else hi = mid;
-        }
-        const int t = lo;
+        const int t = find_tube(b.live_pref, b.n_tubes, it);
         const TubeDev &T = b.tubes[t];
-        // the descriptor is read once, before any store, into registers
+        // the descriptor and the slot counts are read once, before any store, into registers
         const Consts c = T.c;
         const int64_t local = it - b.live_pref[t];
+        const int64_t n_lo = b.live_counts[2 * t], n_hi = b.live_counts[2 * t + 1];
         if (F32) {
             Push32Args a{generic(T.cl[b.pb]), generic(T.ol[b.pb]), generic(T.ul[b.pb]), generic(T.hp[b.pb]),
                          generic(T.hw[b.pb]), generic(T.hg[b.pb]), generic(T.uh[b.pb]), generic(T.k32),
                          generic(T.ez[b.fb]),
                          (unsigned long long *)generic(T.j[b.jb]), generic(T.ctr),
                          b.hist ? (unsigned long long *)generic(T.cell_count) : nullptr, T.u_hi};
-            push_item_f32<BLOCK, NT>(c, a, local);
+            push_item_f32<BLOCK, NT>(c, a, local, n_lo, n_hi);
         } else {
             const int64_t tile0 = local * TILE;
-            const int64_t n = T.ctr->n_slots;
+            const int64_t n = n_lo;
             if (tile0 >= n) return;
             PushArgs a{generic(T.x[b.pb]), generic(T.u[b.pb]), generic(T.x[b.pb]), generic(T.u[b.pb]),
                        generic(T.ez[b.fb]), (unsigned long long *)generic(T.j[b.jb]), generic(T.ctr),
@@ -397,7 +414,8 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last, hipEven
     }
     const bool f32 = t0->p.precision == PIC_FP32_BULK;
     for (int s = 0; s < nsteps; ++s) {
-        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_live_pref, h->d_field_pref, h->d_field_map,
+        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_live_pref, h->d_live_counts, h->d_field_pref,
+                    h->d_field_map,
                     t0->fbuf ^ (s & 1), t0->jbuf ^ (s & 1), t0->pbuf, (hist_last && s == nsteps - 1) ? 1 : 0,
                     h->batch_block * (f32 ? F32_PPT_LO : h->batch_ppt),
                     h->batch_block * (f32 ? F32_PPT_HI : h->batch_ppt)};

@@ -27,7 +27,7 @@ namespace pcpic {
 template <int BLOCK, int NT>
 __global__ __launch_bounds__(BLOCK) void k_push_f32(Consts c, Push32Args a)
 {
-    push_item_f32<BLOCK, NT>(c, a, blockIdx.x);
+    push_item_f32<BLOCK, NT>(c, a, blockIdx.x, a.ctr->n_slots, a.ctr->n_slots_hi);
 }
 
 // ------------------------------------------------------------------------

@@ -317,6 +317,7 @@ struct pic_handle {
     std::vector<pic_handle *> tubes;
     pcpic::TubeDev *d_tubes = nullptr;
     int64_t *d_live_pref = nullptr;             // [n + 1] prefix of the push items holding particles
+    int64_t *d_live_counts = nullptr;           // [2n] slots of each tube's two streams (FP64: n, 0)
     int64_t *d_field_pref = nullptr, *d_sort_pref = nullptr, *d_key_pref = nullptr;
     int64_t *d_scan_pref = nullptr;             // [n + 1] prefix of 1024-key scan blocks
     int32_t *d_field_map = nullptr;             // cell tile -> tube

@@ -1199,6 +1199,7 @@ static size_t batch_header_bytes(const pic_params *tubes, int n)
     size_t off = 0;
     off = align_up(off) + sizeof(TubeDev) * (size_t)n;
     for (int k = 0; k < 5; ++k) off = align_up(off) + sizeof(int64_t) * (size_t)(n + 1);
+    off = align_up(off) + sizeof(int64_t) * 2 * (size_t)n;   // per-tube slot counts of the work list
     off = align_up(off) + 4 * (size_t)m.field;
     off = align_up(off) + 4 * (size_t)m.chunk;
     off = align_up(off) + 4 * (size_t)m.scan;
@@ -1318,6 +1319,7 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
     h->d_sort_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_key_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
     h->d_scan_pref = (int64_t *)take(8 * (size_t)(n_tubes + 1));
+    h->d_live_counts = (int64_t *)take(16 * (size_t)n_tubes);
     {
         const BatchMapSizes m = batch_map_sizes(tubes, n_tubes);
         h->d_field_map = (int32_t *)take(4 * (size_t)m.field);

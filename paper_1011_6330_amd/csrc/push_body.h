@@ -503,19 +503,17 @@ __device__ __forceinline__ void push_tile_hi(const Consts &c, const Push32Args &
     }
 }
 
-// Item k of a tube's FP32-bulk push: the low stream's tiles of BLOCK*F32_PPT_LO
-// slots come first, then the high stream's tiles of BLOCK*F32_PPT_HI slots, one
-// tile per item.  Items past both streams return at once.  As the two streams
-// together hold at most `capacity` slots, ceil(capacity / (BLOCK*F32_PPT_HI)) + 1
-// items cover any split of the slots, with the idle ones at the end.  (An
-// earlier form let a block walk two high tiles in turn, so that both streams
-// had items of one size; its second tile waited on the first one's memory,
-// and the C2 push took 241 us against 221 us now.)
+// Item k of a tube's FP32-bulk push, whose streams hold n_lo and n_hi slots:
+// the low stream's tiles of BLOCK*F32_PPT_LO slots come first, then the high
+// stream's tiles of BLOCK*F32_PPT_HI slots, one tile per item.  Items past
+// both streams return at once.  As the two streams together hold at most
+// `capacity` slots, ceil(capacity / (BLOCK*F32_PPT_HI)) + 1 items cover any
+// split of the slots, with the idle ones at the end.
 template <int BLOCK, int NT>
-__device__ __forceinline__ void push_item_f32(const Consts &c, const Push32Args &a, int64_t k)
+__device__ __forceinline__ void push_item_f32(const Consts &c, const Push32Args &a, int64_t k, int64_t n_lo,
+                                              int64_t n_hi)
 {
     constexpr int64_t SPAN = (int64_t)BLOCK * F32_PPT_LO;
-    const int64_t n_lo = a.ctr->n_slots, n_hi = a.ctr->n_slots_hi;
     const int64_t items_lo = (n_lo + SPAN - 1) / SPAN;
     if (k < items_lo) {
         push_tile_lo<BLOCK, NT>(c, a, n_lo, k * SPAN);

@@ -5,7 +5,8 @@ dropped or doubled term, a wrong sign, index or factor, a transposed operand),
 builds the copy and runs the pins against it in a child process.  The pins
 that face the paper and the mathematics (test_oracle_pins.py) must catch every
 mistake in the forward step; the finite-difference pins of the gradient
-(test_oracle_adjoint.py) must catch every mistake in the reverse sweep.  The
+(test_oracle_adjoint.py) must catch every mistake in the reverse sweep; the GR
+pins (test_oracle_gr.py) every mistake in the lapse factors of the GR step.  The
 unmodified oracle passes both files in the main run.
 """
 import os
@@ -33,7 +34,7 @@ FORWARD = [
     ("gather between nodes instead of faces",
      "double s = x - 0.5, E;", "double s = x, E;"),
     ("move with u instead of v = u / gamma",
-     "double v = u1 / gam;\n        double x1 = x + k->dtdz * v;", "double v = u1 / gam;\n        double x1 = x + k->dtdz * u1;"),
+     "            v = u1 / gam;\n            x1 = x + k->dtdz * v;", "            v = u1 / gam;\n            x1 = x + k->dtdz * u1;"),
     ("cumulative weight off by one cell",
      "if (cell > i) return 0;", "if (cell > i + 1) return 0;"),
     ("sign of the background term of the surface field",
@@ -52,11 +53,40 @@ FORWARD = [
     ("redshift with r_g r instead of r_g / r",
      "double al = sqrt(1.0 - c->rg_over_rstar / eta);", "double al = sqrt(1.0 - c->rg_over_rstar * eta);"),
     ("steady start drifting with u instead of v",
-     "double v = u / gam;\n            double x1 = x + k.dtdz * v;", "double v = u / gam;\n            double x1 = x + k.dtdz * u;"),
+     "double x1 = k.gr ? x + k.dtdz * (orc_alpha2(c, x * k.dz) * v) : x + k.dtdz * v;",
+     "double x1 = k.gr ? x + k.dtdz * (orc_alpha2(c, x * k.dz) * v) : x + k.dtdz * u;"),
     ("steady start B = J / (R dt) without the 4 pi q_m 2^-P factor",
      "st->b[i] = (k.c4 * (double)st->j[i]) / k.dtR;", "st->b[i] = ((double)st->j[i]) / k.dtR;"),
     ("sin(i) instead of tan(i) after dividing eq. 6 by cos(i)",
      "((1.5 * c->theta_star) * tan(c->incl))", "((1.5 * c->theta_star) * sin(c->incl))"),
+]
+
+# the lapse alpha of the full-GR step (GR_ALPHA), against the GR pins
+GR = [
+    ("sign of the gravity term in the GR kick",
+     "u1 = u + (al * E - kg * gh);", "u1 = u + (al * E + kg * gh);"),
+    ("GR move with v instead of alpha^2 v",
+     "x1 = x + k->dtdz * (a2h * v);", "x1 = x + k->dtdz * v;"),
+    ("gravity with gamma(u) instead of the midpoint gamma",
+     "u1 = u + (al * E - kg * gh);", "u1 = u + (al * E - kg * g0);"),
+    ("surface field without rho_GJ,0 / alpha_0",
+     "if (k->gr) t2 = t2 / orc_alpha_node(c, k->dz, 0);", "if (k->gr) t2 = t2;"),
+    ("alpha_{i+1/2} dropped from the B term of the E_z update",
+     "st->ez[i] = (st->ez[i] + k->dtR * (orc_alpha_face(c, dz, i) * st->b[i])) - k->c4 * jw;",
+     "st->ez[i] = (st->ez[i] + k->dtR * st->b[i]) - k->c4 * jw;"),
+    ("alpha_i dropped from the E_r update",
+     "st->er[i] = st->er[i] - k->dtdz * (orc_alpha_node(c, dz, i) * d);", "st->er[i] = st->er[i] - k->dtdz * d;"),
+    ("alpha dropped on E_r in the B update",
+     "double d = orc_alpha_node(c, dz, i + 1) * st->er[i + 1] - orc_alpha_node(c, dz, i) * st->er[i];",
+     "double d = st->er[i + 1] - st->er[i];"),
+    ("Poisson right-hand side with rho_GJ instead of rho_GJ / alpha",
+     "double rg = k.gr ? st->rho_gj[i] / orc_alpha_node(c, k.dz, i) : st->rho_gj[i];", "double rg = st->rho_gj[i];"),
+    ("E_r = Phi / R instead of Phi / (alpha R) at the start",
+     "st->er[i] = (k.gr ? st->phi[i] / orc_alpha_node(c, k.dz, i) : st->phi[i]) / c->radius;",
+     "st->er[i] = st->phi[i] / c->radius;"),
+    ("alpha^2 on the wrong side in the Poisson diagonal",
+     "double bd = k.gr ? -(2.0 + h2 / orc_alpha2(c, (double)i * k.dz)) : bdiag;",
+     "double bd = k.gr ? -(2.0 + h2 * orc_alpha2(c, (double)i * k.dz)) : bdiag;"),
 ]
 
 REVERSE = [
@@ -97,8 +127,9 @@ def _run_case(tmp, idx, old, new, test_file):
     return r.returncode, r.stdout[-400:]
 
 
-@pytest.mark.parametrize("cases,test_file", [(FORWARD, "test_oracle_pins.py"), (REVERSE, "test_oracle_adjoint.py")],
-                         ids=["forward-step", "reverse-sweep"])
+@pytest.mark.parametrize("cases,test_file", [(FORWARD, "test_oracle_pins.py"), (REVERSE, "test_oracle_adjoint.py"),
+                                             (GR, "test_oracle_gr.py")],
+                         ids=["forward-step", "reverse-sweep", "gr-alpha"])
 def test_every_planted_mistake_fails_a_pin(tmp_path, cases, test_file):
     with ThreadPoolExecutor(max_workers=4) as ex:
         futs = [ex.submit(_run_case, str(tmp_path), k, old, new, test_file) for k, (_, old, new) in enumerate(cases)]
