@@ -90,9 +90,30 @@ enum {
 enum {
     PIC_NO_AUTO_INJECT = 1u, /* no SCLF injection (E_surf is still computed)         */
     PIC_FREEZE_FIELDS = 2u,  /* skip the Maxwell update; fields keep their values     */
-    PIC_B_STEADY_INIT = 4u   /* warm start: B_phi = 4 pi R j of the loaded beam, so that
+    PIC_B_STEADY_INIT = 4u,  /* warm start: B_phi = 4 pi R j of the loaded beam, so that
                                 dE_z/dt = 0 at t = 0 (eq. 3); j is the current of one
                                 drift step at the particles' velocities, without a kick */
+    PIC_GR_ALPHA = 8u        /* full GR: the lapse alpha = (1 - r_g/r)^(1/2), r = R_* + z,
+                                in Maxwell's equations and the equation of motion, which
+                                sec. 2 names after eqs. (6)-(7) without writing them out.
+                                Reading (3+1 Schwarzschild form, fields and momenta of
+                                static observers, z the radial coordinate):
+                                  dE_z/dt = alpha B/R - 4 pi alpha j,
+                                  dE_r/dt = -alpha d(alpha B)/dz,
+                                  dB/dt = -alpha d(alpha E_r)/dz - alpha E_z/R,
+                                  alpha dE_z/dz + E_r/R = 4 pi (alpha lambda - rho_GJ),
+                                  du/dt = alpha (q/m) E_z - gamma alpha alpha',
+                                  dz/dt = alpha^2 u/gamma,
+                                lambda the charge per coordinate length and alpha j its
+                                coordinate flux (what the deposit counts); the push takes
+                                a midpoint gamma for gravity and a midpoint alpha^2 for
+                                the move; the Poisson start solves
+                                d2Phi/dz2 - Phi/(alpha R)^2 = -4 pi (lambda - rho_GJ/alpha)
+                                with E_z = -dPhi/dz, E_r = Phi/(alpha R).  Uses r_star and
+                                rg_over_rstar with any rho_kind (r_g = 0: the flat step, bit
+                                for bit).  FP64 single tubes only: PIC_EINVAL with
+                                PIC_FP32_BULK, in a batch, and for the adjoint.  The push
+                                runs at its default launch shape.                           */
 };
 
 /* Tube description.  Copied by pic_init; the knot array is copied too. */
@@ -116,7 +137,8 @@ typedef struct pic_params {
     int32_t sort_every;       /* cell sort + compaction period in steps (0 = never)          */
     int64_t capacity;         /* particle capacity (live + not yet compacted; FP32-bulk: both
                                  streams together, each holds up to `capacity` slots)        */
-    uint32_t flags;           /* PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS | PIC_B_STEADY_INIT  */
+    uint32_t flags;           /* PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS | PIC_B_STEADY_INIT |
+                                 PIC_GR_ALPHA                                                  */
     int32_t max_bins;         /* largest signed-gamma profile pic_diagnostics may request    */
     double gamma_fp64;        /* PIC_FP32_BULK: gamma from which u is kept in f64 (0 = 1e6)  */
     double macro_charge;      /* q_m (per unit area); 0 = rho_GJ(0) dz / ppc.  A fixed value

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libpcpic.so")
 ABI_VERSION = 4
 FP64, FP32_BULK = 0, 1
 RHO_UNIFORM, RHO_FRAME_DRAG, RHO_KNOTS, RHO_GR = 0, 1, 2, 3
-NO_AUTO_INJECT, FREEZE_FIELDS, B_STEADY_INIT = 1, 2, 4
+NO_AUTO_INJECT, FREEZE_FIELDS, B_STEADY_INIT, GR_ALPHA = 1, 2, 4, 8
 ST_CAPACITY, ST_NONFINITE, ST_GAUSS = 1, 2, 4
 
 STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_EWORKSPACE", -3: "PIC_ECAPACITY",

@@ -32,8 +32,10 @@ struct FieldArgs {
 //   E_r,N      <- E_r,N + 2 (dt/dz) B_{N-1/2}           (B odd about the mirror x = N)
 //   E_z,i+1/2  <- (E_z + (dt/R) B_{i+1/2}) - 4 pi q_m 2^-P J_{i+1/2}
 // The neighbour B_{i-1/2} is recomputed from the old fields with the same
-// expression instead of being exchanged.  The block of tile 0 then applies the
-// SCLF rule.  Called by all threads of a block of bs threads.
+// expression instead of being exchanged.  PIC_GR_ALPHA puts the lapse on each
+// term (alpha B/R, alpha d(alpha E_r)/dz, alpha d(alpha B)/dz, alpha E_z/R, with
+// alpha at faces and nodes as pcpic.h states).  The block of tile 0 then applies
+// the SCLF rule.  Called by all threads of a block of bs threads.
 __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, int64_t tile, int bs)
 {
     __shared__ double s_ez0;
@@ -49,6 +51,21 @@ __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, 
             a.bn[i] = a.bo[i];
             a.ern[i] = a.ero[i];
             if (i == N - 1) a.ern[N] = a.ero[N];
+        } else if (c.flags & PIC_GR_ALPHA) {
+            // the same update with the lapse on each term (alpha at faces af, nodes an)
+            const double af = gr_alpha_face(c, i), an0 = gr_alpha_node(c, i), an1 = gr_alpha_node(c, i + 1);
+            const double bi = a.bo[i] - (c.dtdz * (af * (an1 * a.ero[i + 1] - an0 * a.ero[i])) + c.dtR * (af * a.ezo[i]));
+            a.bn[i] = bi;
+            if (i >= 1) {
+                const double afm = gr_alpha_face(c, i - 1), anm = gr_alpha_node(c, i - 1);
+                const double bm = a.bo[i - 1] - (c.dtdz * (afm * (an0 * a.ero[i] - anm * a.ero[i - 1])) +
+                                                 c.dtR * (afm * a.ezo[i - 1]));
+                a.ern[i] = a.ero[i] - c.dtdz * (an0 * (af * bi - afm * bm));
+            } else {
+                a.ern[0] = a.ero[0];
+            }
+            if (i == N - 1) a.ern[N] = a.ero[N] + c.tw * (an1 * (af * bi));
+            ez = (a.ezo[i] + c.dtR * (af * bi)) - c.c4 * (double)a.j[i];
         } else {
             const double bi = a.bo[i] - (c.dtdz * (a.ero[i + 1] - a.ero[i]) + c.dtR * a.ezo[i]);
             a.bn[i] = bi;
@@ -76,7 +93,8 @@ __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, 
         // sort may move every particle into either one (0 in FP64 mode)
         const int64_t slots_hi = __hip_atomic_load(&ctr->n_slots_hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double t1 = c.qmP * (double)w0;
-        const double t2 = c.rho0 * c.hdz;
+        double t2 = c.rho0 * c.hdz;
+        if (c.flags & PIC_GR_ALPHA) t2 = t2 / gr_alpha_node(c, 0);   // rho_GJ,0 / alpha_0 over the half cell
         const double es = s_ez0 - c.fourpi * (t1 - t2);
         int64_t ninj = 0;
         const int64_t ks = ctr->step - a.sched_first;   // index of this step in a replayed schedule

@@ -11,7 +11,8 @@
 
 namespace pcpic {
 
-// G_i = (E_z,i+1/2 - E_z,i-1/2)/dz + E_r,i/R - 4 pi (rho_i - rho_GJ,i), nodes 1..N-1.
+// G_i = (E_z,i+1/2 - E_z,i-1/2)/dz + E_r,i/R - 4 pi (rho_i - rho_GJ,i), nodes 1..N-1
+// (PIC_GR_ALPHA: the first and the rho term times alpha_i).
 __global__ __launch_bounds__(256) void k_gauss(Consts c, const double *ez, const double *er,
                                                const int64_t *w, const double *rho_gj, double *g,
                                                DevCounters *ctr)
@@ -21,8 +22,15 @@ __global__ __launch_bounds__(256) void k_gauss(Consts c, const double *ez, const
     if (i <= c.N) {
         double gi = 0.0;
         if (i >= 1 && i < c.N) {
-            const double rho = (c.qmP * (double)w[i]) / c.dz;
-            const double d = (ez[i] - ez[i - 1]) / c.dz + er[i] / c.R;
+            double rho = (c.qmP * (double)w[i]) / c.dz;
+            double dez = (ez[i] - ez[i - 1]) / c.dz;
+            if (c.flags & PIC_GR_ALPHA) {
+                // alpha_i dE_z/dz + E_r/R = 4 pi (alpha_i lambda_i - rho_GJ,i)
+                const double an = gr_alpha_node(c, i);
+                dez = an * dez;
+                rho = an * rho;
+            }
+            const double d = dez + er[i] / c.R;
             gi = d - c.fourpi * (rho - rho_gj[i]);
         }
         g[i] = gi;

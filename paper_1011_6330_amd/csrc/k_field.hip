@@ -54,6 +54,7 @@ __global__ __launch_bounds__(256) void k_weights(Consts c, const double *__restr
 
 // Right-hand side of eq. (4) times dz^2 on nodes 1..N; node N carries the
 // mirror-doubled particle weight (phi' = 0 at the tube end: phi, rho even about N).
+// PIC_GR_ALPHA: rho_GJ / alpha at the node.
 __global__ __launch_bounds__(256) void k_poisson_rhs(Consts c, const int64_t *w, const double *rho_gj,
                                                      double *rhs)
 {
@@ -61,7 +62,8 @@ __global__ __launch_bounds__(256) void k_poisson_rhs(Consts c, const int64_t *w,
     if (i > c.N) return;
     const int64_t wi = (i == c.N) ? 2 * w[i] : w[i];
     const double rho = (c.qmP * (double)wi) / c.dz;
-    const double t = rho - rho_gj[i];
+    const double rg = (c.flags & PIC_GR_ALPHA) ? rho_gj[i] / gr_alpha_node(c, i) : rho_gj[i];
+    const double t = rho - rg;
     rhs[i] = -(c.cpois * t);
 }
 
@@ -87,12 +89,14 @@ __device__ __forceinline__ void thomas_block(const Consts &c, const double *rhs,
             for (int t = 0; t < cnt; ++t) {
                 const int64_t i = base + t;
                 double ci, di;
+                // PIC_GR_ALPHA: diagonal -(2 + (dz/R)^2 / alpha_i^2)
+                const double bd = (c.flags & PIC_GR_ALPHA) ? -(2.0 + c.h2 / gr_alpha2(c, (double)i * c.dz)) : c.bdiag;
                 if (i == 1) {
-                    ci = 1.0 / c.bdiag;
-                    di = sa[t] / c.bdiag;
+                    ci = 1.0 / bd;
+                    di = sa[t] / bd;
                 } else {
                     const double a = (i == N) ? 2.0 : 1.0;
-                    const double m = c.bdiag - a * pc;
+                    const double m = bd - a * pc;
                     ci = 1.0 / m;
                     di = (sa[t] - a * pd) / m;
                 }
@@ -155,7 +159,7 @@ __device__ __forceinline__ void drift_current(const Consts &c, double x, double 
     t = 1.0 + t;
     const double gam = sqrt(t);
     const double v = u / gam;
-    const double x1 = x + c.dtdz * v;
+    const double x1 = (c.flags & PIC_GR_ALPHA) ? x + c.dtdz * (gr_alpha2(c, x * c.dz) * v) : x + c.dtdz * v;
     const double c0d = floor(x), c1d = floor(x1);
     const int64_t c0 = (int64_t)c0d, c1 = (int64_t)c1d;
     const double F0 = rint((x - c0d) * c.twoP), F1 = rint((x1 - c1d) * c.twoP);
@@ -201,24 +205,27 @@ __global__ __launch_bounds__(256) void k_drift_current_f32(Consts c, Streams s, 
     }
 }
 
-// B_phi = 4 pi R j: (dt/R) B = 4 pi q_m 2^-P J, then J is cleared.
+// B_phi = 4 pi R j: (dt/R) B = 4 pi q_m 2^-P J (PIC_GR_ALPHA: divided by alpha at
+// the face, from alpha B/R = 4 pi alpha j), then J is cleared.
 __global__ __launch_bounds__(256) void k_b_from_current(Consts c, int64_t *J, double *b)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < c.N) {
-        b[i] = (c.c4 * (double)J[i]) / c.dtR;
+        const double bi = (c.c4 * (double)J[i]) / c.dtR;
+        b[i] = (c.flags & PIC_GR_ALPHA) ? bi / gr_alpha_face(c, i) : bi;
         J[i] = 0;
     }
 }
 
-// E_z = -dphi/dz at faces, E_r = phi/R at nodes, B_phi = 0, J = 0, f32 kick array.
+// E_z = -dphi/dz at faces, E_r = phi/R at nodes (PIC_GR_ALPHA: phi/(alpha R)),
+// B_phi = 0, J = 0, f32 kick array.
 __global__ __launch_bounds__(256) void k_fields_from_phi(Consts c, const double *phi, double *ez,
                                                          double *er, double *b, float *k32, int64_t *j0,
                                                          int64_t *j1)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i > c.N) return;
-    er[i] = phi[i] / c.R;
+    er[i] = ((c.flags & PIC_GR_ALPHA) ? phi[i] / gr_alpha_node(c, i) : phi[i]) / c.R;
     if (i < c.N) {
         const double e = -((phi[i + 1] - phi[i]) / c.dz);
         ez[i] = e;

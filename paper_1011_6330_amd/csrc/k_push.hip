@@ -24,16 +24,16 @@
 
 namespace pcpic {
 
-template <int BLOCK, int PPT, int NT>
+template <int BLOCK, int PPT, int NT, int GR = 0>
 __global__ __launch_bounds__(BLOCK) void k_push_f64(Consts c, PushArgs a)
 {
     const int64_t n = a.ctr->n_slots;
     const int64_t tile0 = (int64_t)blockIdx.x * (BLOCK * PPT);
     if (tile0 >= n) return;                       // whole block idle (uniform)
-    push_tile_f64<BLOCK, PPT, NT>(c, a, n, tile0);
+    push_tile_f64<BLOCK, PPT, NT, GR>(c, a, n, tile0);
 }
 
-template <int BLOCK, int PPT, int NT>
+template <int BLOCK, int PPT, int NT, int GR = 0>
 static hipError_t launch_push_t(pic_handle *h)
 {
     PushArgs a{h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.x[h->pbuf], h->ws.u[h->pbuf], h->ws.ez[h->fbuf],
@@ -41,7 +41,7 @@ static hipError_t launch_push_t(pic_handle *h)
                h->hist_on ? (unsigned long long *)h->ws.cell_count : nullptr};
     const int64_t tile = (int64_t)BLOCK * PPT;
     const unsigned grid = (unsigned)((h->c.cap + tile - 1) / tile);
-    hipLaunchKernelGGL((k_push_f64<BLOCK, PPT, NT>), dim3(grid), dim3(BLOCK), 0, h->stream, h->c, a);
+    hipLaunchKernelGGL((k_push_f64<BLOCK, PPT, NT, GR>), dim3(grid), dim3(BLOCK), 0, h->stream, h->c, a);
     return hipGetLastError();
 }
 
@@ -65,6 +65,8 @@ hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U,
 
 hipError_t launch_push_f64(pic_handle *h)
 {
+    // PIC_GR_ALPHA: one launch shape (the default), whatever the configured one
+    if (h->c.flags & PIC_GR_ALPHA) return launch_push_t<128, 2, 1, 1>(h);
     const int B = h->push_block, P = h->push_ppt;
     if (h->push_nt) {
         if (B == 256 && P == 2) return launch_push_t<256, 2, 1>(h);

@@ -45,12 +45,14 @@ struct Consts {
     double tw;        // 2 dtdz (mirror update of E_r at node N)
     double cpois;     // fourpi dz^2 (Poisson right-hand side)
     double bdiag;     // -(2 + (dz/R)^2) (Poisson diagonal)
+    double h2;        // (dz/R)^2
     // background density
     int32_t rho_kind;
     int32_t n_knots;
     double rho_amp, kappa, r_star, length;
     double gr_s;      // PIC_RHO_GR: (3/2) theta_* tan(i) cos(varphi)
-    double gr_g;      // PIC_RHO_GR: r_g / R_*
+    double gr_g;      // PIC_RHO_GR or PIC_GR_ALPHA: r_g / R_*
+    double gr_cg;     // PIC_GR_ALPHA: dt (r_g/R_*) / (2 R_*); dt alpha alpha' = gr_cg / eta^2
 };
 
 // Slots per thread of the two FP32-bulk push streams: the low stream loads its
@@ -383,6 +385,19 @@ hipError_t launch_profile(pic_handle *h, int n_bins);
 // Counting sort; hist_ready = the key counts were accumulated by the step before.
 hipError_t launch_sort(pic_handle *h, bool hist_ready);
 hipError_t launch_clear_hist(pic_handle *h);
+
+// The lapse of PIC_GR_ALPHA: alpha^2 = 1 - r_g/r at height z, eta = r/R_* = 1 + z/R_*;
+// alpha at node i and at face i + 1/2.
+__host__ __device__ inline double gr_alpha2(const Consts &c, double z)
+{
+    const double eta = 1.0 + z / c.r_star;
+    return 1.0 - c.gr_g / eta;
+}
+__host__ __device__ inline double gr_alpha_node(const Consts &c, int64_t i) { return sqrt(gr_alpha2(c, (double)i * c.dz)); }
+__host__ __device__ inline double gr_alpha_face(const Consts &c, int64_t i)
+{
+    return sqrt(gr_alpha2(c, ((double)i + 0.5) * c.dz));
+}
 
 // Goldreich-Julian density at node i (eqs. 5-7; the three kinds are listed in
 // pcpic.h).  Used by the device fill and, at node 0, by the host to fix the

@@ -108,8 +108,12 @@ pic_status validate(const pic_params *p)
         return fail(PIC_EINVAL, "capacity %lld out of range", (long long)p->capacity);
     if (p->sort_every < 0) return fail(PIC_EINVAL, "sort_every must be >= 0");
     if (p->max_bins < 0 || p->max_bins > (1 << 20)) return fail(PIC_EINVAL, "max_bins out of range");
-    if (p->flags & ~(PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS | PIC_B_STEADY_INIT))
+    if (p->flags & ~(PIC_NO_AUTO_INJECT | PIC_FREEZE_FIELDS | PIC_B_STEADY_INIT | PIC_GR_ALPHA))
         return fail(PIC_EINVAL, "unknown flag bits");
+    if ((p->flags & PIC_GR_ALPHA) &&
+        (p->precision != PIC_FP64 || !(p->rg_over_rstar >= 0.0 && p->rg_over_rstar < 1.0) || !(p->r_star > 0) ||
+         !isfinite(p->r_star)))
+        return fail(PIC_EINVAL, "PIC_GR_ALPHA needs PIC_FP64, r_g/R_* in [0, 1) and r_star > 0");
     return PIC_OK;
 }
 
@@ -137,7 +141,8 @@ Consts make_consts(const pic_params &p, const double *knots)
     c.r_star = p.r_star;
     c.length = p.length;
     c.gr_s = p.rho_kind == PIC_RHO_GR ? ((1.5 * p.theta_star) * tan(p.incl)) * p.cos_phi : 0.0;
-    c.gr_g = p.rho_kind == PIC_RHO_GR ? p.rg_over_rstar : 0.0;
+    c.gr_g = (p.rho_kind == PIC_RHO_GR || (p.flags & PIC_GR_ALPHA)) ? p.rg_over_rstar : 0.0;
+    c.gr_cg = ((0.5 * c.dt) * c.gr_g) / p.r_star;
     c.rho0 = rho_node(c, knots, 0);
     c.qm = p.macro_charge != 0.0 ? p.macro_charge : (c.rho0 * c.dz) / p.ppc;
     c.qmP = c.qm / c.twoP;
@@ -150,6 +155,7 @@ Consts make_consts(const pic_params &p, const double *knots)
     c.cpois = c.fourpi * dz2;
     const double rr = c.dz / p.radius;
     const double h2 = rr * rr;
+    c.h2 = h2;
     c.bdiag = -(2.0 + h2);
     return c;
 }
@@ -1294,6 +1300,8 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
     for (int t = 1; t < n_tubes; ++t)
         if (tubes[t].precision != tubes[0].precision || tubes[t].sort_every != tubes[0].sort_every)
             return fail(PIC_EINVAL, "all tubes of a batch need the same precision and sort_every");
+    for (int t = 0; t < n_tubes; ++t)
+        if (tubes[t].flags & PIC_GR_ALPHA) return fail(PIC_EINVAL, "PIC_GR_ALPHA runs on single tubes only");
     if (!d_workspace || ws_bytes < need) return fail(PIC_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (((uintptr_t)d_workspace) % ALIGN) return fail(PIC_EWORKSPACE, "workspace must be %zu-byte aligned", ALIGN);
     pic_handle *h = new (std::nothrow) pic_handle();
@@ -1562,6 +1570,7 @@ pic_status adjoint_supported(pic_handle *h)
     if (h->p.precision != PIC_FP64) return fail(PIC_EINVAL, "the adjoint needs PIC_FP64");
     if (h->p.sort_every != 0) return fail(PIC_EINVAL, "the adjoint needs sort_every = 0");
     if (h->p.flags & PIC_FREEZE_FIELDS) return fail(PIC_EINVAL, "the adjoint needs evolving fields");
+    if (h->p.flags & PIC_GR_ALPHA) return fail(PIC_EINVAL, "the adjoint covers the flat step (not PIC_GR_ALPHA)");
     if (h->c.cap > ((int64_t)1 << 31))
         return fail(PIC_EINVAL, "the adjoint takes at most 2^31 particle slots (its fixed-point sums)");
     return PIC_OK;

@@ -55,6 +55,10 @@ __device__ __forceinline__ double gather_f64(const Consts &c, const double *__re
 // (eq. 1), current deposit, removal at the ends (x = -1) and the node-0 tally.
 // x < 0 marks an empty slot and is left alone.  Straight-line code with
 // selects: every lane computes the step, and the flags say what is kept.
+// GR (PIC_GR_ALPHA): du/dt = alpha (q/m) E_z - gamma alpha alpha' with a
+// midpoint gamma for the gravity term, dz/dt = alpha^2 v with a midpoint
+// alpha^2, as pcpic.h states.
+template <int GR>
 __device__ __forceinline__ void push_one_f64(const Consts &c, const PushArgs &a, double E, double &xr, double &ur,
                                              DepAcc &acc)
 {
@@ -63,12 +67,32 @@ __device__ __forceinline__ void push_one_f64(const Consts &c, const PushArgs &a,
     const double x = xr, u = ur;
     const bool live = x >= 0.0;                  // not a removed slot (-1) or past the end
     // eq. (1): u = gamma v, du/dt = (q/m) E_z, dz/dt = v
-    const double u1 = u + E;
-    double tt = u1 * u1;
-    tt = 1.0 + tt;
-    double gam, v;
-    gamma_velocity(u1, tt, gam, v);
-    const double x1 = x + c.dtdz * v;
+    double u1, gam, v, x1;
+    if (GR) {
+        const double eta = 1.0 + (x * c.dz) / c.r_star;
+        const double a2 = 1.0 - c.gr_g / eta;
+        const double al = sqrt(a2);
+        const double kg = c.gr_cg / (eta * eta);
+        double t0 = u * u;
+        t0 = 1.0 + t0;
+        const double g0 = sqrt(t0);
+        const double uh = u + 0.5 * (al * E - kg * g0);
+        double th = uh * uh;
+        th = 1.0 + th;
+        const double gh = sqrt(th);
+        u1 = u + (al * E - kg * gh);
+        double tt = u1 * u1;
+        tt = 1.0 + tt;
+        gamma_velocity(u1, tt, gam, v);
+        const double xh = x + 0.5 * (c.dtdz * (a2 * v));
+        x1 = x + c.dtdz * (gr_alpha2(c, xh * c.dz) * v);
+    } else {
+        u1 = u + E;
+        double tt = u1 * u1;
+        tt = 1.0 + tt;
+        gamma_velocity(u1, tt, gam, v);
+        x1 = x + c.dtdz * v;
+    }
     const bool fin = isfinite(u1) && isfinite(x1);
     const bool ok = live && fin;
     const double c0d = floor(x);
@@ -96,7 +120,7 @@ __device__ __forceinline__ void push_one_f64(const Consts &c, const PushArgs &a,
 // current of pair v is flushed before pair v+1 is pushed, so a flush sees the
 // few cells 128 consecutive slots span.  Called by every thread of a block of
 // BLOCK threads; wave-collective.
-template <int BLOCK, int PPT, int NT>
+template <int BLOCK, int PPT, int NT, int GR = 0>
 __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a, int64_t n, int64_t tile0)
 {
     static_assert(PPT % 2 == 0, "slots are taken in pairs");
@@ -125,8 +149,8 @@ __device__ __forceinline__ void push_tile_f64(const Consts &c, const PushArgs &a
     acc.init(a.ctr);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        push_one_f64(c, a, E[2 * v], xs[2 * v], us[2 * v], acc);
-        push_one_f64(c, a, E[2 * v + 1], xs[2 * v + 1], us[2 * v + 1], acc);
+        push_one_f64<GR>(c, a, E[2 * v], xs[2 * v], us[2 * v], acc);
+        push_one_f64<GR>(c, a, E[2 * v + 1], xs[2 * v + 1], us[2 * v + 1], acc);
         // write back (removed particles get x = -1; their u is left as it was)
         const int64_t e = tile0 + 2 * ((int64_t)v * BLOCK + threadIdx.x);
         if (e + 2 <= n) {
