@@ -182,6 +182,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=512)
+    ap.add_argument("--ensemble-dense", action="store_true",
+                    help="also run the ensemble control of 256 equal dense tubes (FP32-bulk)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -291,6 +293,10 @@ def main():
         e64 = run_ensemble(args.ensemble_steps, precision=0)
         result["ensemble"]["fp64"] = {k: e64[k] for k in ("value", "ms_per_step", "launch", "dtype", "roofline",
                                                           "breakdown_ms_per_step")}
+        if args.ensemble_dense:
+            ed = run_ensemble(args.ensemble_steps, precision=1, dense=True)
+            result["ensemble"]["dense_control"] = {k: ed[k] for k in ("value", "ms_per_step", "launch", "roofline",
+                                                                      "particles", "cells", "workload")}
 
     if not args.no_adjoint:
         adj = run_adjoint_leg(args.adjoint_steps)
@@ -371,14 +377,15 @@ def run_large(steps, push, push32):
     return out
 
 
-def run_ensemble(steps, precision=1):
+def run_ensemble(steps, precision=1, dense=False):
     """C3: 256 tubes of uneven size, autotuned, `steps` plain steps (rounds replayed
     from their graphs), then `steps` more with HIP events around every batched
-    kernel for the roofline of the batched push."""
+    kernel for the roofline of the batched push.  dense: the control of equal,
+    dense tubes (synth.ensemble)."""
     import torch
 
     from paper_1011_6330_amd import Batch, autotune, synth
-    cfgs = synth.ensemble(n_tubes=256, seed=0, precision=precision)
+    cfgs = synth.ensemble(n_tubes=256, seed=0, precision=precision, dense=dense)
     b = Batch([synth.tube_params(c) for c in cfgs], device="cuda:0")
     for t, c in enumerate(cfgs):
         x, u = synth.warm_start(c, seed=t)
@@ -420,7 +427,8 @@ def run_ensemble(steps, precision=1):
     shape = (cfg["block"], cfg["per_thread"], True)
     roof["traffic"] = measured_traffic(shape, TRAFFIC_BATCH_FILE, BATCH_SOURCES) if precision else None
     steps_t = max(tim["push_launches"], 1)
-    log(f"ensemble ({'fp32-bulk' if precision else 'fp64'}): {el / steps * 1e3:.3f} ms/step for {alive:.3g} "
+    log(f"ensemble ({'fp32-bulk' if precision else 'fp64'}{', dense control' if dense else ''}): "
+        f"{el / steps * 1e3:.3f} ms/step for {alive:.3g} "
         f"particles in 256 tubes, shape {cfg}; push {roof['avg_launch_us']:.1f} us ({roof['achieved']:.0f} GB/s), "
         f"field + work list {tim['field_ms'] / steps_t * 1e3:.1f} us per step")
     return {"value": alive * steps / el, "unit": "particle-steps/s", "ms_per_step": el / steps * 1e3,
@@ -429,9 +437,12 @@ def run_ensemble(steps, precision=1):
             "breakdown_ms_per_step": {"push": tim["push_ms"] / steps_t, "field": tim["field_ms"] / steps_t,
                                       "sort": tim["sort_ms"] / steps_t},
             "high_stream_fraction": t_high / max(t_alive, 1.0),
-            "workload": "256 frame-dragging tubes, cells log-uniform 2048-65536, particles log-uniform 1e4-1e6, "
-                        "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk (fp64: the same tubes in FP64), "
-                        "one graph launch per 64-step round (steps and cell sort)"}
+            "workload": ("256 frame-dragging tubes of 2048 cells and 2.2e5 particles each (the control: dense "
+                         "tubes, about 107 particles per cell), FP32-bulk, one graph launch per 64-step round"
+                         if dense else
+                         "256 frame-dragging tubes, cells log-uniform 2048-65536, particles log-uniform 1e4-1e6, "
+                         "kappa 0.05-0.2, rho_GJ amplitude 0.3-3, FP32-bulk (fp64: the same tubes in FP64), "
+                         "one graph launch per 64-step round (steps and cell sort)")}
 
 
 def run_adjoint_leg(steps, ckpt=50):

@@ -27,6 +27,7 @@ struct BatchArgs {
     int n_tubes;
     int64_t *live_pref;          // [n_tubes + 1] prefix of the push items holding particles (k_batch_plan)
     int64_t *live_counts;        // [2 n_tubes] slots of each tube's low and high stream (FP64: n, 0)
+    int32_t *push_map;           // push item -> tube (k_batch_map)
     const int64_t *field_pref;   // [n_tubes + 1] prefix of cell tiles
     const int32_t *field_map;    // cell tile -> tube
     int fb, jb, pb;              // field, current and particle buffer parities of the step
@@ -72,24 +73,13 @@ __global__ __launch_bounds__(256) void k_batch_plan(BatchArgs b)
 }
 
 
-// The last t in [0, n) with pref[t] <= it, for a non-decreasing pref with
-// pref[0] <= it: each round, the 64 lanes of the wave test 64 evenly spaced
-// entries of the range left and keep the stretch after the last one that
-// passes, so 256 tubes take two rounds of loads (one per round, all lanes at
-// once) instead of eight dependent ones.  Wave-collective; uniform result.
-__device__ __forceinline__ int find_tube(const int64_t *pref, int n, int64_t it)
+// The work list as a map: block t writes the tube's index over its items
+// [live_pref[t], live_pref[t+1]), so a push block finds its tube with one load.
+__global__ __launch_bounds__(256) void k_batch_map(BatchArgs b)
 {
-    const int lane = (int)__lane_id();
-    int lo = 0, len = n;
-    while (len > 64) {
-        const int S = (len + 63) >> 6;
-        const bool le = lane * S < len && pref[lo + lane * S] <= it;
-        const int L = 63 - __builtin_clzll(__ballot(le));
-        lo += L * S;
-        len = len - L * S < S ? len - L * S : S;
-    }
-    const bool le = lane < len && pref[lo + lane] <= it;
-    return __builtin_amdgcn_readfirstlane(lo + 63 - __builtin_clzll(__ballot(le)));
+    const int t = blockIdx.x;
+    const int64_t lo = b.live_pref[t], hi = b.live_pref[t + 1];
+    for (int64_t it = lo + threadIdx.x; it < hi; it += 256) b.push_map[it] = t;
 }
 
 template <int BLOCK, int PPT, int NT, int F32>
@@ -99,7 +89,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_push(BatchArgs b)
     const int64_t it = blockIdx.x;
     if (it >= b.live_pref[b.n_tubes]) return;
     {
-        const int t = find_tube(b.live_pref, b.n_tubes, it);
+        const int t = b.push_map[it];
         const TubeDev &T = b.tubes[t];
         // the descriptor and the slot counts are read once, before any store, into registers
         const Consts c = T.c;
@@ -403,7 +393,7 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last, hipEven
     const void *kp = pick_push_kernel(h);
     const void *kf = pick_field_kernel(h);
     if (!kp || !kf || h->batch_push_items <= 0 || h->batch_field_items <= 0 ||
-        h->batch_push_items > 0x7fffffff || h->batch_field_items > 0x7fffffff)
+        h->batch_push_items > 0x7fffffff || h->batch_field_items > 0x7fffffff || h->batch_push_items > h->push_map_cap)
         return hipErrorInvalidValue;
     pic_handle *t0 = h->tubes[0];
     const unsigned pgrid = (unsigned)h->batch_push_items, fgrid = (unsigned)h->batch_field_items;
@@ -414,8 +404,8 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last, hipEven
     }
     const bool f32 = t0->p.precision == PIC_FP32_BULK;
     for (int s = 0; s < nsteps; ++s) {
-        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_live_pref, h->d_live_counts, h->d_field_pref,
-                    h->d_field_map,
+        BatchArgs a{h->d_tubes, (int)h->tubes.size(), h->d_live_pref, h->d_live_counts, h->d_push_map,
+                    h->d_field_pref, h->d_field_map,
                     t0->fbuf ^ (s & 1), t0->jbuf ^ (s & 1), t0->pbuf, (hist_last && s == nsteps - 1) ? 1 : 0,
                     h->batch_block * (f32 ? F32_PPT_LO : h->batch_ppt),
                     h->batch_block * (f32 ? F32_PPT_HI : h->batch_ppt)};
@@ -423,6 +413,7 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last, hipEven
         hipError_t e = ev ? hipEventRecord(ev[4 * s], h->stream) : hipSuccess;
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(256), 0, h->stream, a);
+        hipLaunchKernelGGL(k_batch_map, dim3((unsigned)h->tubes.size()), dim3(256), 0, h->stream, a);
         if (ev && (e = hipEventRecord(ev[4 * s + 1], h->stream)) != hipSuccess) return e;
         e = hipLaunchKernel(kp, dim3(pgrid), dim3(h->batch_block), args, 0, h->stream);
         if (e != hipSuccess) return e;

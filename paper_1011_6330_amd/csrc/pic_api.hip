@@ -1182,15 +1182,17 @@ pic_status pic_destroy(pic_handle *h)
 // Entries of the work-item -> tube maps, sized for the smallest tiles any
 // launch shape uses (64 cells per field tile).
 struct BatchMapSizes {
+    int64_t push;   // push items at the smallest tile (64 threads x 2 slots), the work list's bound
     int64_t field, chunk, scan;
 };
 
 static BatchMapSizes batch_map_sizes(const pic_params *tubes, int n)
 {
-    BatchMapSizes m{0, 0, 0};
+    BatchMapSizes m{0, 0, 0, 0};
     for (int t = 0; t < n; ++t) {
         const pic_params &p = tubes[t];
         const bool f32 = p.precision == PIC_FP32_BULK;
+        m.push += (p.capacity + 127) / 128 + 2;
         m.field += (p.n_cells + 63) / 64;
         m.chunk += (p.capacity + SORT_TILE - 1) / SORT_TILE + (f32 ? 1 : 0);
         const int64_t keys = (f32 ? 2 * (p.n_cells + 1) : p.n_cells) << sort_sub_log2(p);
@@ -1207,6 +1209,7 @@ static size_t batch_header_bytes(const pic_params *tubes, int n)
     for (int k = 0; k < 5; ++k) off = align_up(off) + sizeof(int64_t) * (size_t)(n + 1);
     off = align_up(off) + sizeof(int64_t) * 2 * (size_t)n;   // per-tube slot counts of the work list
     off = align_up(off) + 4 * (size_t)m.field;
+    off = align_up(off) + 4 * (size_t)m.push;
     off = align_up(off) + 4 * (size_t)m.chunk;
     off = align_up(off) + 4 * (size_t)m.scan;
     off = align_up(off) + 4 * (size_t)n;   // tubes to solve together
@@ -1331,6 +1334,8 @@ pic_status pic_init_batch(const pic_params *tubes, int32_t n_tubes, void *d_work
     {
         const BatchMapSizes m = batch_map_sizes(tubes, n_tubes);
         h->d_field_map = (int32_t *)take(4 * (size_t)m.field);
+        h->d_push_map = (int32_t *)take(4 * (size_t)m.push);
+        h->push_map_cap = m.push;
         h->d_chunk_map = (int32_t *)take(4 * (size_t)m.chunk);
         h->d_scan_map = (int32_t *)take(4 * (size_t)m.scan);
         h->d_pending = (int32_t *)take(4 * (size_t)n_tubes);

@@ -89,12 +89,13 @@ struct DepAcc {
         }
     }
 
-    // Wave-collective: must be reached by all 64 lanes of the wave.  Lanes
-    // with the same first cell in consecutive positions form a run; the run's
-    // last lane adds the run's sums of the three channels (one atomic per face
-    // and run, however many cells the wave spans).  A wave that is one run
-    // (the common case between sorts) takes plain wave sums.  The channels
-    // start afresh.
+    // Wave-collective: must be reached by all 64 lanes of the wave.  A wave
+    // whose lanes share their first cell (the common case between sorts) takes
+    // plain wave sums, one atomic per face.  A wave whose first cells span at
+    // most 61 cells sums its channels in a per-wave LDS window with integer
+    // atomics and adds each touched face once.  Otherwise lanes with the same
+    // first cell in consecutive positions form a run, and the run's last lane
+    // adds the run's sums (segmented scans).  The channels start afresh.
     __device__ __forceinline__ void flush_current(unsigned long long *J)
     {
         const bool has = cf != -2;
@@ -113,6 +114,32 @@ struct DepAcc {
                 if (sp != 0) atomicAdd(J + cf + 1, (unsigned long long)sp);
                 if (s2 != 0) atomicAdd(J + cf + 2, (unsigned long long)s2);
             }
+        } else if (wave_max_i32(has ? cf : INT_MIN) - wave_min_i32(has ? cf : INT_MAX) <= 60) {
+            // a few cells: the faces lo-1 .. hi+2 of the wave's first cells lo .. hi
+            // in a window of 64 LDS words (word k: face lo-1+k); the lanes add their
+            // channels with LDS integer atomics, then each lane adds one face to J
+            __shared__ unsigned long long s_win[8][64];   // one window per wave (blocks up to 512)
+            unsigned long long *w = s_win[threadIdx.x >> 6];
+            const int lo = wave_min_i32(has ? cf : INT_MAX);
+            w[lane] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (has) {
+                const int k = cf - lo;
+                if (am != 0.0) atomicAdd(w + k, (unsigned long long)(long long)am);
+                if (a0 != 0.0) atomicAdd(w + k + 1, (unsigned long long)(long long)a0);
+                if (ap != 0.0) atomicAdd(w + k + 2, (unsigned long long)(long long)ap);
+                if (a2 != 0.0) atomicAdd(w + k + 3, (unsigned long long)(long long)a2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const unsigned long long v = w[lane];
+            if (v != 0) atomicAdd(J + (lo - 1 + lane), v);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         } else {
             double sm = am, s0 = a0, sp = ap, s2 = a2;
             if (__ballot(am != 0.0)) sm = run_sum_to_tail(sm, r.rank);

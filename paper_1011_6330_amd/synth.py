@@ -122,19 +122,21 @@ def random_particles(N, n, seed=0, u_lo=-3.0, u_hi=40.0, stream=2):
     return x, u
 
 
-def ensemble(n_tubes=256, seed=0, precision=1, sort_every=64, slack=1.3):
+def ensemble(n_tubes=256, seed=0, precision=1, sort_every=64, slack=1.3, dense=False):
     """Tubes of the batched workload: per tube t, four uniforms from Philox stream
     1000 + t give N_t = round(2048 * 32^U1) cells (2,048 .. 65,536), kappa_t =
     0.05 + 0.15 U2, A_t = 0.3 * 10^U3 (0.3 .. 3), N_p,t = round(1e4 * 100^U4)
     particles (1e4 .. 1e6); L = 10R, R_* = 10R and a_t = 1.05 (N_t / 10) sqrt(A_t),
-    i.e. omega_p dz / c = 1.05 in every tube, as in the frame-dragging preset."""
+    i.e. omega_p dz / c = 1.05 in every tube, as in the frame-dragging preset.
+    dense: a control with the same tube count and about the same particle total,
+    every tube 2,048 cells and 2.2e5 particles (about 107 per cell)."""
     out = []
     for t in range(n_tubes):
         U = uniform01(4, seed, stream=1000 + t)
-        N = int(round(2048 * 32.0 ** U[0]))
+        N = 2048 if dense else int(round(2048 * 32.0 ** U[0]))
         kappa = 0.05 + 0.15 * U[1]
         amp = 0.3 * 10.0 ** U[2]
-        npart = int(round(1e4 * 100.0 ** U[3]))
+        npart = 220000 if dense else int(round(1e4 * 100.0 ** U[3]))
         a = 1.05 * (N / 10.0) * math.sqrt(amp)
         out.append(dict(n_cells=N, length=10.0, radius=1.0, dt_over_dz=0.5, q_over_m=q_over_m_for(a, amp),
                         ppc=npart / N, rho_kind=RHO_FRAME_DRAG, rho_amp=amp, kappa=kappa, r_star=10.0,
