@@ -191,6 +191,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 2^20-cell, 2.5e8-particle tube")
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--no-small", action="store_true", help="skip the C1 time-per-step leg")
+    ap.add_argument("--no-gr", action="store_true", help="skip the full-GR (PIC_GR_ALPHA) leg")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="seconds per CPU-baseline leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -282,6 +283,20 @@ def main():
             "fp32_over_fp64": mval / lval}
         log(f"fp32-bulk, low gamma: {mel / args.steps * 1e3:.3f} ms/step (push {mroof['avg_launch_us']:.1f} us) vs "
             f"fp64 {lel / args.steps * 1e3:.3f} ms/step")
+
+    # ---- the same tube with the full-GR lapse factors (PIC_GR_ALPHA), FP64 ----
+    if not args.no_gr and args.config == "c2":
+        from paper_1011_6330_amd import GR_ALPHA
+        gcfg = dict(cfg, flags=int(cfg.get("flags", 0)) | GR_ALPHA, rg_over_rstar=0.4)
+        g0, g1, gtim, gel, _ = run_tube(gcfg, x, u, 0, args.steps, args.warmup, push=push)
+        gval = 0.5 * (g0["n_alive"] + g1["n_alive"]) * args.steps / gel
+        groof = roofline_of(B_FP64 * gtim["alive"], gtim, "k_push_f64<128, 2, 1, 1>")
+        result["gr_alpha"] = {"value": gval, "unit": "particle-steps/s", "ms_per_step": gel / args.steps * 1e3,
+                              "roofline": groof, "vs_flat": gval / value,
+                              "workload": "the c2 tube with the lapse alpha (r_g/R_* = 0.4) in Maxwell's equations "
+                                          "and the equation of motion (PIC_GR_ALPHA), FP64"}
+        log(f"gr alpha: {gel / args.steps * 1e3:.3f} ms/step, push {groof['avg_launch_us']:.1f} us "
+            f"({groof['achieved']:.0f} GB/s), {gval / value:.3f} of the flat step")
 
     # ---- the large tube: 2^20 cells, 2.5e8 particles, FP64 and FP32-bulk ----
     if not args.no_large and args.config == "c2":
