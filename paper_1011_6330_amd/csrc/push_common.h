@@ -90,37 +90,34 @@ struct DepAcc {
     }
 
     // Wave-collective: must be reached by all 64 lanes of the wave.  A wave
-    // whose lanes share their first cell (the common case between sorts) takes
-    // plain wave sums, one atomic per face.  A wave whose first cells span at
-    // most 61 cells sums its channels in a per-wave LDS window with integer
-    // atomics and adds each touched face once.  Otherwise lanes with the same
-    // first cell in consecutive positions form a run, and the run's last lane
-    // adds the run's sums (segmented scans).  The channels start afresh.
+    // whose lanes share their first cell (the common case between sorts) sums
+    // its four channels together (row swaps, then a scan inside each row) and
+    // adds one atomic per face.  A wave whose first cells span at most 61 cells
+    // sums its channels in a per-wave LDS window with integer atomics and adds
+    // each touched face once.  Otherwise lanes with the same first cell in
+    // consecutive positions form a run, and the run's last lane adds the run's
+    // sums (segmented scans).  The channels start afresh.
     __device__ __forceinline__ void flush_current(unsigned long long *J)
     {
         const bool has = cf != -2;
         const int lane = (int)__lane_id();
-        const WaveRun r = wave_runs_i32(cf, has);
-        const bool one_run = __ballot(r.is_head) == 1ull && __ballot(has) == ~0ull;
-        if (one_run) {
-            long long sm = 0, s0 = 0, sp = 0, s2 = 0;
-            if (__ballot(am != 0.0)) sm = wave_sum_int_f64_to63(am);
-            if (__ballot(a0 != 0.0)) s0 = wave_sum_int_f64_to63(a0);
-            if (__ballot(ap != 0.0)) sp = wave_sum_int_f64_to63(ap);
-            if (__ballot(a2 != 0.0)) s2 = wave_sum_int_f64_to63(a2);
-            if (lane == 63) {
-                if (sm != 0) atomicAdd(J + cf - 1, (unsigned long long)sm);
-                if (s0 != 0) atomicAdd(J + cf, (unsigned long long)s0);
-                if (sp != 0) atomicAdd(J + cf + 1, (unsigned long long)sp);
-                if (s2 != 0) atomicAdd(J + cf + 2, (unsigned long long)s2);
-            }
-        } else if (wave_max_i32(has ? cf : INT_MIN) - wave_min_i32(has ? cf : INT_MAX) <= 60) {
+        const int c_first = __builtin_amdgcn_readfirstlane(cf);
+        if (__ballot(has && cf == c_first) == ~0ull) {
+            // row k holds face c_first - 1 + k; its total sits in the row's last lane
+            const double s = wave_sum4_rows_f64(am, a0, ap, a2);
+            if ((lane & 15) == 15 && s != 0.0)
+                atomicAdd(J + (c_first - 1 + (lane >> 4)), (unsigned long long)(long long)s);
+            cf = -2;
+            am = a0 = ap = a2 = 0.0;
+            return;
+        }
+        const int lo = wave_min_i32(has ? cf : INT_MAX);
+        if (wave_max_i32(has ? cf : INT_MIN) - lo <= 60) {
             // a few cells: the faces lo-1 .. hi+2 of the wave's first cells lo .. hi
             // in a window of 64 LDS words (word k: face lo-1+k); the lanes add their
             // channels with LDS integer atomics, then each lane adds one face to J
             __shared__ unsigned long long s_win[8][64];   // one window per wave (blocks up to 512)
             unsigned long long *w = s_win[threadIdx.x >> 6];
-            const int lo = wave_min_i32(has ? cf : INT_MAX);
             w[lane] = 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -141,6 +138,7 @@ struct DepAcc {
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         } else {
+            const WaveRun r = wave_runs_i32(cf, has);
             double sm = am, s0 = a0, sp = ap, s2 = a2;
             if (__ballot(am != 0.0)) sm = run_sum_to_tail(sm, r.rank);
             if (__ballot(a0 != 0.0)) s0 = run_sum_to_tail(s0, r.rank);

@@ -134,6 +134,63 @@ __device__ __forceinline__ double wave_sum_f64_to63(double v)
     return v;
 }
 
+// The double of the lane n places lower in the same row of 16 lanes; the
+// first n lanes of each row read 0 (bound control, so no old value is kept).
+template <int N>
+__device__ __forceinline__ double dpp_row_shr_f64(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x110 + N, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + N, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Row swaps of a double across two registers (a row is 16 lanes; both 32-bit
+// halves move together).  swap_rows32: rows 2-3 of a trade places with rows
+// 0-1 of b, so a becomes (a0, a1, b0, b1) and b becomes (a2, a3, b2, b3).
+// swap_rows16: the odd rows of a trade places with the even rows of b, so a
+// becomes (a0, b0, a2, b2) and b becomes (a1, b1, a3, b3).
+__device__ __forceinline__ void swap_rows32_f64(double &a, double &b)
+{
+    const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+    const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
+    b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ void swap_rows16_f64(double &a, double &b)
+{
+    const unsigned long long ua = __builtin_bit_cast(unsigned long long, a);
+    const unsigned long long ub = __builtin_bit_cast(unsigned long long, b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
+    b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+
+// Sums over the 64 lanes of four values at once: on return row k (lanes
+// 16k .. 16k+15) works on the k-th argument, and lane 16k + 15 holds its
+// total.  Two row swaps fold the four rows of each value onto one row (every
+// lane then holds the sum of its four lanes of equal position in the rows),
+// and an inclusive scan inside the row (row_shr 1, 2, 4, 8) leaves the row
+// total in its last lane.  For integer-valued doubles whose sums stay below
+// 2^53 every addition is exact.
+__device__ __forceinline__ double wave_sum4_rows_f64(double v0, double v1, double v2, double v3)
+{
+    swap_rows32_f64(v0, v2);
+    swap_rows32_f64(v1, v3);
+    double s = v0 + v2;          // rows 0-1: v0 over rows (r, r+2); rows 2-3: v2
+    double t = v1 + v3;          // rows 0-1: v1; rows 2-3: v3
+    swap_rows16_f64(s, t);
+    double v = s + t;            // row k: value k summed over the four rows
+    v += dpp_row_shr_f64<1>(v);
+    v += dpp_row_shr_f64<2>(v);
+    v += dpp_row_shr_f64<4>(v);
+    v += dpp_row_shr_f64<8>(v);
+    return v;
+}
+
 // Sum over the 64 lanes of an int32, valid in lane 63, with the same DPP
 // pattern as wave_sum_f64_to63; each step is one add with a DPP operand.
 __device__ __forceinline__ int wave_sum_i32_to63(int v)
