@@ -68,16 +68,160 @@ __global__ __launch_bounds__(256) void k_poisson_rhs(Consts c, const int64_t *w,
 }
 
 // Thomas algorithm for phi_{i-1} + bdiag phi_i + phi_{i+1} = rhs_i (row N: 2 phi_{N-1}),
-// phi_0 = 0.  The recurrence is sequential: one lane runs it while the block
-// stages the operands through LDS in chunks so that no load is on the chain.
+// phi_0 = 0: c'_i = 1/m_i and d'_i = (rhs_i - a d'_{i-1})/m_i with m_i = b_i - a c'_{i-1}
+// (a = 2 on row N, else 1), then phi_i = d'_i - c'_i phi_{i+1}.  The recurrence is
+// sequential: one lane runs it while the block stages the operands through LDS in
+// chunks.  The lane takes rows in runs of TH_RUN, two register sets in turn, so the
+// next run's operands are on their way from LDS while the current run computes and
+// the chain holds only arithmetic:
+//  * the divisions use the reciprocal of m_i (hardware estimate, two Newton steps)
+//    for both quotients, each with one residual correction: the operations of the
+//    general correctly rounded division when its range scaling does not apply, so
+//    the bits are the division's; a run whose operands leave that range (ThRange)
+//    is done again with plain divisions;
+//  * without the lapse every row below N has the same diagonal, so once c'_i equals
+//    c'_{i-1} it stays fixed (m and its reciprocal too) and only d' is left to run.
 constexpr int TH_CHUNK = 2048;
+constexpr int TH_RUN = 16;
+
+__device__ __forceinline__ double th_recip(double m)
+{
+    double r = __builtin_amdgcn_rcp(m);
+    double e = fma(-m, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-m, r, 1.0);
+    return fma(r, e, r);
+}
+// n / m from r = th_recip(m)
+__device__ __forceinline__ double th_div(double n, double m, double r)
+{
+    const double q = n * r;
+    const double rem = fma(-m, q, n);
+    return fma(rem, r, q);
+}
+// The range in which the division's scaling and special-case steps do nothing:
+// denominators within [2^-300, 2^300] and numerators within [2^-600, 2^400] in
+// magnitude.  A run tracks the smallest and largest magnitudes it meets (plain
+// min/max, off the chain) and is checked once at its end; a NaN anywhere in the
+// run reaches its last d'.
+struct ThRange {
+    double nlo, nhi, mlo, mhi;
+    __device__ __forceinline__ void init() { nlo = mlo = INFINITY; nhi = mhi = 0.0; }
+    __device__ __forceinline__ void num(double n) { nlo = fmin(nlo, fabs(n)); nhi = fmax(nhi, fabs(n)); }
+    __device__ __forceinline__ void den(double m) { mlo = fmin(mlo, fabs(m)); mhi = fmax(mhi, fabs(m)); }
+    __device__ __forceinline__ bool ok(double last) const
+    {
+        return nlo >= 0x1p-600 && nhi <= 0x1p+400 && mlo >= 0x1p-300 && mhi <= 0x1p+300 && isfinite(last);
+    }
+};
+
+__device__ __forceinline__ double th_diag(const Consts &c, int64_t i)
+{
+    // PIC_GR_ALPHA: diagonal -(2 + (dz/R)^2 / alpha_i^2)
+    return (c.flags & PIC_GR_ALPHA) ? -(2.0 + c.h2 / gr_alpha2(c, (double)i * c.dz)) : c.bdiag;
+}
+
+// Lane 0's forward state: c'_{i-1}, d'_{i-1}, and once c' is fixed, m and 1/m.
+struct ThFwd {
+    double pc, pd, mst, rst;
+    bool fixed;
+};
+
+// TH_RUN rows with a = 1 (row 1 < i < N) from their operands s and diagonals bd,
+// written to od (d') and oc (c'); false (state untouched) if an operand left the
+// fast range.
+template <bool FIXED>
+__device__ __forceinline__ bool th_run_fast(const double (&s)[TH_RUN], const double (&bd)[TH_RUN], ThFwd &f,
+                                            bool gr, double *od, double *oc)
+{
+    double ci[TH_RUN], di[TH_RUN];
+    ThRange rg;
+    rg.init();
+    double pc = f.pc, pd = f.pd;
+    if (FIXED) rg.den(f.mst);
+#pragma unroll
+    for (int k = 0; k < TH_RUN; ++k) {
+        const double n = s[k] - pd;
+        rg.num(n);
+        if (FIXED) {
+            pd = th_div(n, f.mst, f.rst);
+        } else {
+            const double m = bd[k] - pc;
+            const double r = th_recip(m);
+            rg.den(m);
+            pc = fma(fma(-m, r, 1.0), r, r);
+            pd = th_div(n, m, r);
+        }
+        ci[k] = pc;
+        di[k] = pd;
+    }
+    if (!rg.ok(pd)) return false;
+#pragma unroll
+    for (int k = 0; k < TH_RUN; ++k) {
+        od[k] = di[k];
+        if (!FIXED) oc[k] = ci[k];   // a fixed c' is filled in by the block afterwards
+    }
+    if (!FIXED && !gr && ci[TH_RUN - 1] == ci[TH_RUN - 2]) {
+        f.fixed = true;
+        f.mst = bd[TH_RUN - 1] - pc;
+        f.rst = th_recip(f.mst);
+    }
+    f.pc = pc;
+    f.pd = pd;
+    return true;
+}
+
+// The same rows with plain divisions.
+__device__ __forceinline__ void th_run_plain(const double (&s)[TH_RUN], const double (&bd)[TH_RUN], ThFwd &f,
+                                             double *od, double *oc)
+{
+#pragma unroll
+    for (int k = 0; k < TH_RUN; ++k) {
+        const double m = bd[k] - f.pc;
+        f.pc = 1.0 / m;
+        f.pd = (s[k] - f.pd) / m;
+        od[k] = f.pd;
+        oc[k] = f.pc;
+    }
+}
+
+__device__ __forceinline__ void th_run(const Consts &c, const double (&s)[TH_RUN], int64_t i0, ThFwd &f,
+                                       double *od, double *oc)
+{
+    const bool gr = (c.flags & PIC_GR_ALPHA) != 0;
+    double bd[TH_RUN];
+#pragma unroll
+    for (int k = 0; k < TH_RUN; ++k) bd[k] = gr ? th_diag(c, i0 + k) : c.bdiag;
+    const bool ok = f.fixed ? th_run_fast<true>(s, bd, f, gr, od, oc) : th_run_fast<false>(s, bd, f, gr, od, oc);
+    if (!ok) th_run_plain(s, bd, f, od, oc);
+}
+
+// One row of any kind (row 1, row N, or a row outside a run), plain divisions.
+__device__ __forceinline__ void th_row(const Consts &c, int64_t i, double s, ThFwd &f, double *od, double *oc)
+{
+    const double bd = th_diag(c, i);
+    if (i == 1) {
+        f.pc = 1.0 / bd;
+        f.pd = s / bd;
+    } else {
+        const double a = (i == c.N) ? 2.0 : 1.0;
+        const double m = bd - a * f.pc;
+        f.pc = 1.0 / m;
+        f.pd = (s - a * f.pd) / m;
+    }
+    *od = f.pd;
+    *oc = f.pc;
+}
+
 __device__ __forceinline__ void thomas_block(const Consts &c, const double *rhs, double *cp, double *dp, double *phi)
 {
-    __shared__ double sa[TH_CHUNK];
-    __shared__ double sb[TH_CHUNK];
-    __shared__ double carry[2];
+    __shared__ double sa[TH_CHUNK];      // operands: rhs (forward), d' (backward)
+    __shared__ double sb[TH_CHUNK];      // c'
+    __shared__ double sd[TH_CHUNK];      // results: d' (forward), phi (backward)
+    __shared__ int s_fix[2];             // chunk rows [s_fix[0], s_fix[1]) hold the fixed c'
+    __shared__ double s_cfix;
     const int64_t N = c.N;
-    if (threadIdx.x == 0) { carry[0] = 0.0; carry[1] = 0.0; }
+    ThFwd f{0.0, 0.0, 0.0, 0.0, false};
     // forward elimination, i = 1..N
     for (int64_t base = 1; base <= N; base += TH_CHUNK) {
         const int cnt = (int)((N - base + 1) < TH_CHUNK ? (N - base + 1) : TH_CHUNK);
@@ -85,35 +229,50 @@ __device__ __forceinline__ void thomas_block(const Consts &c, const double *rhs,
         for (int t = threadIdx.x; t < cnt; t += 256) sa[t] = rhs[base + t];
         __syncthreads();
         if (threadIdx.x == 0) {
-            double pc = carry[0], pd = carry[1];
-            for (int t = 0; t < cnt; ++t) {
-                const int64_t i = base + t;
-                double ci, di;
-                // PIC_GR_ALPHA: diagonal -(2 + (dz/R)^2 / alpha_i^2)
-                const double bd = (c.flags & PIC_GR_ALPHA) ? -(2.0 + c.h2 / gr_alpha2(c, (double)i * c.dz)) : c.bdiag;
-                if (i == 1) {
-                    ci = 1.0 / bd;
-                    di = sa[t] / bd;
-                } else {
-                    const double a = (i == N) ? 2.0 : 1.0;
-                    const double m = bd - a * pc;
-                    ci = 1.0 / m;
-                    di = (sa[t] - a * pd) / m;
+            int t = 0;
+            for (; t < cnt && base + t < 2; ++t) th_row(c, base + t, sa[t], f, sd + t, sb + t);
+            // runs of rows with a = 1, two register sets in turn
+            const int tend = (int)((N - base) < (int64_t)cnt ? (N - base) : (int64_t)cnt);   // rows below N
+            double A[TH_RUN], B[TH_RUN];
+            int fix_lo = f.fixed ? t : cnt;   // first row of the runs taken with c' fixed
+            if (t + TH_RUN <= tend) {
+#pragma unroll
+                for (int k = 0; k < TH_RUN; ++k) A[k] = sa[t + k];
+                while (true) {
+                    const bool nb = t + 2 * TH_RUN <= tend;
+                    if (nb)
+#pragma unroll
+                        for (int k = 0; k < TH_RUN; ++k) B[k] = sa[t + TH_RUN + k];
+                    th_run(c, A, base + t, f, sd + t, sb + t);
+                    t += TH_RUN;
+                    if (f.fixed && fix_lo == cnt) fix_lo = t;
+                    if (!nb) break;
+                    const bool na = t + 2 * TH_RUN <= tend;
+                    if (na)
+#pragma unroll
+                        for (int k = 0; k < TH_RUN; ++k) A[k] = sa[t + TH_RUN + k];
+                    th_run(c, B, base + t, f, sd + t, sb + t);
+                    t += TH_RUN;
+                    if (f.fixed && fix_lo == cnt) fix_lo = t;
+                    if (!na) break;
                 }
-                sa[t] = di;
-                sb[t] = ci;
-                pc = ci;
-                pd = di;
             }
-            carry[0] = pc;
-            carry[1] = pd;
+            s_fix[0] = fix_lo < t ? fix_lo : cnt;
+            s_fix[1] = fix_lo < t ? t : cnt;
+            s_cfix = f.pc;
+            for (; t < cnt; ++t) th_row(c, base + t, sa[t], f, sd + t, sb + t);
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += 256) { dp[base + t] = sa[t]; cp[base + t] = sb[t]; }
+        const int flo = s_fix[0], fhi = s_fix[1];
+        const double cfix = s_cfix;
+        for (int t = threadIdx.x; t < cnt; t += 256) {
+            dp[base + t] = sd[t];
+            cp[base + t] = (t >= flo && t < fhi) ? cfix : sb[t];
+        }
     }
     __syncthreads();
     // back substitution, i = N..1
-    if (threadIdx.x == 0) carry[0] = 0.0;
+    double next = 0.0;
     for (int64_t top = N; top >= 1; top -= TH_CHUNK) {
         const int64_t lo = top - TH_CHUNK + 1 > 1 ? top - TH_CHUNK + 1 : 1;
         const int cnt = (int)(top - lo + 1);
@@ -121,17 +280,58 @@ __device__ __forceinline__ void thomas_block(const Consts &c, const double *rhs,
         for (int t = threadIdx.x; t < cnt; t += 256) { sa[t] = dp[lo + t]; sb[t] = cp[lo + t]; }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double next = carry[0];
-            for (int t = cnt - 1; t >= 0; --t) {
-                const int64_t i = lo + t;
-                const double v = (i == N) ? sa[t] : sa[t] - sb[t] * next;
-                sa[t] = v;
-                next = v;
+            int t = cnt - 1;
+            if (top == N) {
+                next = sa[t];             // phi_N = d'_N
+                sd[t] = next;
+                --t;
             }
-            carry[0] = next;
+            // runs of rows downwards, two register sets in turn
+            double DA[TH_RUN], EA[TH_RUN], DB[TH_RUN], EB[TH_RUN];
+            if (t >= TH_RUN - 1) {
+#pragma unroll
+                for (int k = 0; k < TH_RUN; ++k) {
+                    DA[k] = sa[t - k];
+                    EA[k] = sb[t - k];
+                }
+                while (true) {
+                    const bool nb = t - TH_RUN >= TH_RUN - 1;
+                    if (nb)
+#pragma unroll
+                        for (int k = 0; k < TH_RUN; ++k) {
+                            DB[k] = sa[t - TH_RUN - k];
+                            EB[k] = sb[t - TH_RUN - k];
+                        }
+#pragma unroll
+                    for (int k = 0; k < TH_RUN; ++k) {
+                        next = DA[k] - EA[k] * next;
+                        sd[t - k] = next;
+                    }
+                    t -= TH_RUN;
+                    if (!nb) break;
+                    const bool na = t - TH_RUN >= TH_RUN - 1;
+                    if (na)
+#pragma unroll
+                        for (int k = 0; k < TH_RUN; ++k) {
+                            DA[k] = sa[t - TH_RUN - k];
+                            EA[k] = sb[t - TH_RUN - k];
+                        }
+#pragma unroll
+                    for (int k = 0; k < TH_RUN; ++k) {
+                        next = DB[k] - EB[k] * next;
+                        sd[t - k] = next;
+                    }
+                    t -= TH_RUN;
+                    if (!na) break;
+                }
+            }
+            for (; t >= 0; --t) {
+                next = sa[t] - sb[t] * next;
+                sd[t] = next;
+            }
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += 256) phi[lo + t] = sa[t];
+        for (int t = threadIdx.x; t < cnt; t += 256) phi[lo + t] = sd[t];
     }
     if (threadIdx.x == 0) phi[0] = 0.0;
 }

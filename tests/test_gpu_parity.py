@@ -387,6 +387,60 @@ def test_c5_full_size_first_steps():
     g.close()
 
 
+def _first_fixed_c_prime(N, bd):
+    """First row i < N at which the forward elimination's c'_i = 1/(bd - c'_{i-1})
+    repeats c'_{i-1} exactly (Python floats: IEEE double, correctly rounded), or None."""
+    c = 1.0 / bd
+    for i in range(2, N):
+        cn = 1.0 / (bd - c)
+        if cn == c:
+            return i
+        c = cn
+    return None
+
+
+POISSON_CASES = {
+    # c' reaches a fixed point early (dz/R = 0.01): most rows take the d'-only runs
+    "fixed_c": dict(n_cells=5000, length=50.0),
+    # rho_GJ = 0 over the first knots: zero numerators, so those runs fall back to plain divisions
+    "zero_rhs": dict(n_cells=4096, length=40.96, rho_kind=synth.RHO_KNOTS, kappa=0.0,
+                     knots=np.array([0.0, 0.0, 0.0, 1.0, 1.5, 1.0, 0.5, 1.0]), macro_charge=0.01),
+    # numerators beyond 2^400 and below 2^-600: plain divisions throughout
+    "huge_rhs": dict(n_cells=3000, length=30.0, rho_amp=1e125),
+    "tiny_rhs": dict(n_cells=3000, length=30.0, rho_amp=1e-185),
+    # fewer rows than a run, and one run plus a tail
+    "small_5": dict(n_cells=5, length=0.05),
+    "small_17": dict(n_cells=17, length=0.17),
+    # several chunks with a ragged last one, a warm random load and the frame-drag background
+    "chunks_ragged": dict(n_cells=2 * 2048 + 37, length=41.33, rho_kind=synth.RHO_FRAME_DRAG, kappa=0.15,
+                          r_star=3.0, capacity=200000),
+}
+
+
+@pytest.mark.parametrize("case", sorted(POISSON_CASES))
+def test_poisson_start_bit_identical(case):
+    """The Poisson start (eq. 4) on tubes that take each path of the solver: runs
+    whose c' has stopped changing, runs that fall back to plain divisions, fewer
+    rows than a run, several chunks; E_z and E_r bit-identical to the oracle."""
+    over = POISSON_CASES[case]
+    cfg = dict(synth.preset("c1"), flags=1, **over)     # PIC_NO_AUTO_INJECT
+    N = int(cfg["n_cells"])
+    if case == "fixed_c":
+        h2 = (cfg["length"] / N / cfg["radius"]) ** 2
+        row = _first_fixed_c_prime(N, -(2.0 + h2))
+        assert row is not None and row < N - 64, row
+    x = u = None
+    if case == "chunks_ragged":
+        x, u = synth.random_particles(N, 30000, seed=11)
+    say("poisson start", case, N)
+    g, o = make_pair(cfg, x, u)
+    d = g.diagnostics()
+    assert np.array_equal(d["ez"], o.ez), f"E_z differs ({case})"
+    assert np.array_equal(d["er"], o.er), f"E_r differs ({case})"
+    assert np.all(np.isfinite(d["ez"]))
+    g.close()
+
+
 def test_gr_background_bit_identical():
     """Eq. (6) background with the redshift and the inclination term
     (i = 0.5 rad, theta_* = 0.67 theta_p, r_g/R_* = 0.4): background, start and
