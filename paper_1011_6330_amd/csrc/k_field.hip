@@ -190,8 +190,13 @@ __device__ __forceinline__ void th_run(const Consts &c, const double (&s)[TH_RUN
 {
     const bool gr = (c.flags & PIC_GR_ALPHA) != 0;
     double bd[TH_RUN];
+    if (gr) {
 #pragma unroll
-    for (int k = 0; k < TH_RUN; ++k) bd[k] = gr ? th_diag(c, i0 + k) : c.bdiag;
+        for (int k = 0; k < TH_RUN; ++k) bd[k] = th_diag(c, i0 + k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < TH_RUN; ++k) bd[k] = c.bdiag;
+    }
     const bool ok = f.fixed ? th_run_fast<true>(s, bd, f, gr, od, oc) : th_run_fast<false>(s, bd, f, gr, od, oc);
     if (!ok) th_run_plain(s, bd, f, od, oc);
 }
