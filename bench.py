@@ -184,6 +184,9 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=512)
     ap.add_argument("--ensemble-dense", action="store_true",
                     help="also run the ensemble control of 256 equal dense tubes (FP32-bulk)")
+    ap.add_argument("--ensemble-shape", default=None,
+                    help="FP32-bulk ensemble launch shape threads:slots instead of the autotuner's "
+                         "(a fixed shape for counter runs)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -304,12 +307,12 @@ def main():
 
     # ---- ensemble: 256 tubes, one graph launch per round ----
     if not args.no_ensemble:
-        result["ensemble"] = run_ensemble(args.ensemble_steps, precision=1)
+        result["ensemble"] = run_ensemble(args.ensemble_steps, precision=1, shape=args.ensemble_shape)
         e64 = run_ensemble(args.ensemble_steps, precision=0)
         result["ensemble"]["fp64"] = {k: e64[k] for k in ("value", "ms_per_step", "launch", "dtype", "roofline",
                                                           "breakdown_ms_per_step")}
         if args.ensemble_dense:
-            ed = run_ensemble(args.ensemble_steps, precision=1, dense=True)
+            ed = run_ensemble(args.ensemble_steps, precision=1, dense=True, shape=args.ensemble_shape)
             result["ensemble"]["dense_control"] = {k: ed[k] for k in ("value", "ms_per_step", "launch", "roofline",
                                                                       "particles", "cells", "workload")}
 
@@ -392,11 +395,11 @@ def run_large(steps, push, push32):
     return out
 
 
-def run_ensemble(steps, precision=1, dense=False):
+def run_ensemble(steps, precision=1, dense=False, shape=None):
     """C3: 256 tubes of uneven size, autotuned, `steps` plain steps (rounds replayed
     from their graphs), then `steps` more with HIP events around every batched
     kernel for the roofline of the batched push.  dense: the control of equal,
-    dense tubes (synth.ensemble)."""
+    dense tubes (synth.ensemble).  shape: "threads:slots" in place of the tuner."""
     import torch
 
     from paper_1011_6330_amd import Batch, autotune, synth
@@ -406,7 +409,11 @@ def run_ensemble(steps, precision=1, dense=False):
         x, u = synth.warm_start(c, seed=t)
         b.tubes[t].inject(x, u)
     log("ensemble loaded")
-    bb, bp, _ = autotune.tune_batch(b, use_cache=False)
+    if shape:
+        blk, ppt = (int(v) for v in shape.split(":")[:2])
+        b.set_config(blk, ppt)
+    else:
+        autotune.tune_batch(b, use_cache=False)
     b.step(32)
     b.sync()
     n0 = sum(t.diagnostics(fields=False)["n_alive"] for t in b.tubes)
