@@ -571,7 +571,7 @@ hipError_t launch_field_inject(pic_handle *h)
                 h->d_sched, h->sched_first, h->sched_n,
                 h->hist_on ? (unsigned long long *)w.cell_count : nullptr,
                 f32 && 0.0 >= h->u_hi ? sort_low_keys(c) : 0};
-    hipLaunchKernelGGL(k_field_inject, dim3(grid_for(c.N, 256)), dim3(256), 0, h->stream, c, a);
+    hipLaunchKernelGGL(k_field_inject, dim3(grid_for(c.N, 256 * FIELD_CPT)), dim3(256), 0, h->stream, c, a);
     return hipGetLastError();
 }
 
@@ -583,7 +583,7 @@ hipError_t launch_field_ptrs(pic_handle *h, const double *ezo, const double *ero
     Workspace &w = h->ws;
     FieldArgs a{ezo, ero, bo, ezn, ern, bn, w.j[h->jbuf], w.j[1 - h->jbuf], nullptr, X, U,
                 nullptr, nullptr, nullptr, w.ctr, h->d_sched, h->sched_first, h->sched_n};
-    hipLaunchKernelGGL(k_field_inject, dim3(grid_for(h->c.N, 256)), dim3(256), 0, h->stream, h->c, a);
+    hipLaunchKernelGGL(k_field_inject, dim3(grid_for(h->c.N, 256 * FIELD_CPT)), dim3(256), 0, h->stream, h->c, a);
     return hipGetLastError();
 }
 

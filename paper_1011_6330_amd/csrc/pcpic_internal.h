@@ -77,6 +77,9 @@ constexpr int F32_PPT_HI = 4;
 // particle's offset to the grid once its momentum reaches the threshold).
 constexpr int HI_GROUP_LOG2 = 8;
 constexpr int HI_GROUP = 1 << HI_GROUP_LOG2;
+// Faces per thread of the field update (field_body.h).
+constexpr int FIELD_CPT = 4;
+
 constexpr int HI_FRAC_BITS = 24;
 constexpr unsigned HI_FRAC_MASK = (1u << HI_FRAC_BITS) - 1u;
 constexpr unsigned HI_DEAD = 0xFFFFFFFFu;

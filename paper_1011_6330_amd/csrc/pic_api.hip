@@ -1263,7 +1263,7 @@ static pic_status batch_configure(pic_handle *h, int block, int per_thread)
         td[(size_t)t].push_tiles = (s->c.cap + tile - 1) / tile;
         td[(size_t)t].push_tiles_hi = f32 ? 1 : 0;
         pp[(size_t)t + 1] = pp[(size_t)t] + td[(size_t)t].push_tiles + td[(size_t)t].push_tiles_hi;
-        fp[(size_t)t + 1] = fp[(size_t)t] + (s->c.N + block - 1) / block;
+        fp[(size_t)t + 1] = fp[(size_t)t] + (s->c.N + block * FIELD_CPT - 1) / (block * FIELD_CPT);
         sp[(size_t)t + 1] = sp[(size_t)t] + td[(size_t)t].sort_chunks + (f32 ? 1 : 0);   // sort_item
         kp[(size_t)t + 1] = kp[(size_t)t] + td[(size_t)t].n_keys;
         cp[(size_t)t + 1] = cp[(size_t)t] + (td[(size_t)t].n_keys + SORT_SCAN_TILE - 1) / SORT_SCAN_TILE;
