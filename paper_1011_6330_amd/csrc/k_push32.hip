@@ -8,7 +8,7 @@
 //               nothing cancels near v = c);
 //   high stream (gamma at or above the threshold, 1e6 by default): a 32-bit
 //               position word (offset in units of 2^-24, cell relative to the
-//               base cell of its group of 128 slots) and u in f64, 12 B/slot;
+//               base cell of its group of 256 slots) and u in f64, 12 B/slot;
 //               kick, gamma and v in f64 as the FP64 path.
 // The deposit takes F = rint(2^P offset) of the stored offsets, so charge
 // conservation stays exact.  Fields, the Gauss residual and E_surf stay FP64;

@@ -56,15 +56,15 @@ struct Consts {
 };
 
 // Slots per thread of the two FP32-bulk push streams: the low stream loads its
-// three 4-byte fields as 16-byte vectors of 4 slots; the high stream takes 2
-// slots (an 8-byte vector of position words, one 16-byte f64 momentum vector),
-// which keeps its registers, and so its occupancy, at those of the FP64 push.
+// three 4-byte fields as 16-byte vectors of 4 slots; the high stream takes 4
+// slots too (a 16-byte vector of position words, two 16-byte f64 momentum
+// vectors), so that one wave covers one group of HI_GROUP slots.
 constexpr int F32_PPT_LO = 4;
 constexpr int F32_PPT_HI = 4;
 
 // Positions of the high stream (FP32-bulk, gamma at or above the threshold):
 // 4 bytes per slot beside the 8-byte f64 momentum.  Slots form groups of
-// HI_GROUP consecutive slots (the 128 slots one wave of the push takes).  The
+// HI_GROUP consecutive slots (the 256 slots one wave of the push takes).  The
 // low HI_FRAC_BITS bits of a slot's word hold its offset in the cell in units
 // of 2^-24.  A narrow group (header >= 0) keeps the cell minus the header in
 // the high 8 bits; a wide group (header HI_WIDE) keeps zero there and the cell
