@@ -668,13 +668,47 @@ def cpu_baseline(cfg, x, u, seconds):
         log(f"oracle ({key}, {nthreads} threads): {done} steps in {el:.1f}s, {ps / el:.3g} particle-steps/s")
         del o
     a = legs["all_cores"]
+    adj = cpu_adjoint_ratio()
     return {"value": a["value"], "unit": "particle-steps/s", "cores": a["threads"], "kind": "oracle",
+            "adjoint": adj,
             "sample": f"the same warm tube ({len(x)} particles at the start), first {a['steps']} steps, FP64 "
                       f"oracle on {a['threads']} threads (particles split into contiguous slices, integer sums "
                       f"in thread order: the serial oracle's state bit for bit)",
             "serial": {"value": legs["serial"]["value"], "cores": 1, "steps": legs["serial"]["steps"],
                        "sample": f"first {legs['serial']['steps']} steps, single-threaded FP64 oracle"},
             "parallel_speedup": a["value"] / legs["serial"]["value"], **host}
+
+
+def cpu_adjoint_ratio(steps=200):
+    """The adjoint/forward time ratio of the oracle on a 1e5-particle downscale of
+    the adjoint workload (4096 cells, 24.4 particles per base cell-charge, the same
+    density relative to rho_GJ): a plain serial forward of `steps` steps, and the
+    oracle's adjoint (the same steps recorded whole, then the reverse sweep)."""
+    from oracle.oracle import OracleTube
+    from paper_1011_6330_amd import synth
+    ppc = 24.4
+    cfg = synth.preset("c4", ppc=ppc, warm=int(ppc * 4096), capacity=int(ppc * 4096 * 1.3),
+                       macro_charge=-(1.0 - 0.15) * (10.0 / 4096) / ppc)
+    x, u = synth.warm_start(cfg)
+    p = {k: v for k, v in synth.tube_params(cfg).items()
+         if k not in ("sort_every", "max_bins", "precision", "gamma_fp64")}
+    o = OracleTube(p)
+    o.inject(x, u)
+    t0 = time.perf_counter()
+    o.step(steps)
+    fwd = time.perf_counter() - t0
+    o = OracleTube(p)
+    o.inject(x, u)
+    t0 = time.perf_counter()
+    loss, nex, _, _ = o.adjoint(steps)
+    adj = time.perf_counter() - t0
+    del o
+    log(f"oracle adjoint ({len(x)} particles, {steps} steps): plain forward {fwd * 1e3:.0f} ms, recorded forward "
+        f"and reverse sweep {adj * 1e3:.0f} ms")
+    return {"workload": f"c4 downscaled to {len(x)} particles (4096 cells, ppc {ppc}), {steps} steps, serial FP64 oracle",
+            "plain_forward_s": fwd, "adjoint_s": adj, "adjoint_over_plain_forward": adj / fwd,
+            "backward_over_plain_forward": (adj - fwd) / fwd, "loss": loss, "n_exit": nex,
+            "note": "the oracle records every step (no checkpoints); backward = adjoint run minus a plain forward"}
 
 
 if __name__ == "__main__":

@@ -66,11 +66,11 @@ __device__ __forceinline__ int adj_exponent(double b)
 
 __device__ __forceinline__ double max_of_bits(unsigned long long b) { return __builtin_bit_cast(double, b); }
 
-// Wave maximum of |v| (non-negative doubles order as their bit images) into *dst.
+// Wave maximum of |v| into *dst (non-negative doubles order as their bit images).
 __device__ __forceinline__ void wave_max_abs(unsigned long long *dst, double v)
 {
-    const long long m = wave_max_i64(__builtin_bit_cast(long long, fabs(v)));
-    if (__lane_id() == 0 && m != 0) atomicMax(dst, (unsigned long long)m);
+    const long long m = __builtin_bit_cast(long long, wave_max_f64_to63(fabs(v)));
+    if (__lane_id() == 63 && m != 0) atomicMax(dst, (unsigned long long)m);
 }
 
 // Block maximum of |a| and |b| (256 threads) into *da and *db: one atomic per
@@ -80,10 +80,10 @@ __device__ __forceinline__ void wave_max_abs(unsigned long long *dst, double v)
 __device__ __forceinline__ void block_max_abs2(unsigned long long *da, unsigned long long *db, double a, double b)
 {
     __shared__ long long s_m[2][4];
-    const long long ma = wave_max_i64(__builtin_bit_cast(long long, fabs(a)));
-    const long long mb = wave_max_i64(__builtin_bit_cast(long long, fabs(b)));
+    const long long ma = __builtin_bit_cast(long long, wave_max_f64_to63(fabs(a)));
+    const long long mb = __builtin_bit_cast(long long, wave_max_f64_to63(fabs(b)));
     const int w = threadIdx.x >> 6;
-    if (__lane_id() == 0) {
+    if (__lane_id() == 63) {
         s_m[0][w] = ma;
         s_m[1][w] = mb;
     }
@@ -252,8 +252,11 @@ __global__ __launch_bounds__(256) void k_adj_particles(Consts c, AdjPartArgs a)
     (void)live;
     wave_add_runs_fixed(a.lk_lo, a.lk_hi, ka, va, wa, e_k);
     wave_add_runs_fixed(a.lk_lo, a.lk_hi, kb, vb, wb, e_k);
-    const double gs = wave_sum_f64(gr);
-    if (__lane_id() == 0 && gs != 0.0) fixed_add(&a.sc->g_lo, &a.sc->g_hi, gs, e_g);
+    // the rate gradient: only lanes of the injected class have a term
+    if (__ballot(gr != 0.0)) {
+        const double gs = wave_sum_f64_to63(gr);
+        if (__lane_id() == 63 && gs != 0.0) fixed_add(&a.sc->g_lo, &a.sc->g_hi, gs, e_g);
+    }
     const int nx = a.rot == 2 ? 0 : a.rot + 1;
     block_max_abs2(&a.sc->max_lx[nx], &a.sc->max_lu[nx], nlx, nlu);
 }

@@ -191,6 +191,20 @@ __device__ __forceinline__ double wave_sum4_rows_f64(double v0, double v1, doubl
     return v;
 }
 
+// Maximum over the 64 lanes of non-negative doubles, valid in lane 63: the DPP
+// pattern of wave_sum_f64_to63 with max in place of the sum (a lane without a
+// source reads 0, which no non-negative value is below).
+__device__ __forceinline__ double wave_max_f64_to63(double v)
+{
+    v = fmax(v, dpp_f64<0x111, 0xf>(v));
+    v = fmax(v, dpp_f64<0x112, 0xf>(v));
+    v = fmax(v, dpp_f64<0x114, 0xf>(v));
+    v = fmax(v, dpp_f64<0x118, 0xf>(v));
+    v = fmax(v, dpp_f64<0x142, 0xa>(v));
+    v = fmax(v, dpp_f64<0x143, 0xc>(v));
+    return v;
+}
+
 // Sum over the 64 lanes of an int32, valid in lane 63, with the same DPP
 // pattern as wave_sum_f64_to63; each step is one add with a DPP operand.
 __device__ __forceinline__ int wave_sum_i32_to63(int v)
