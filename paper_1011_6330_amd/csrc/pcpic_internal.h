@@ -25,7 +25,7 @@ struct Consts {
     int32_t P;        // fixed-point fraction bits
     uint32_t flags;   // PIC_* flags
     int32_t sub;      // log2 of the sort key's bins per cell
-    int32_t pad0;
+    int32_t gr_fast;  // PIC_GR_ALPHA: the lapse constants lie where the push's short division and square root apply
     int64_t oneP;     // 2^P
     double twoP;      // 2^P as a double
     double dz;        // L / N

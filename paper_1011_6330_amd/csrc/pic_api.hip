@@ -143,6 +143,13 @@ Consts make_consts(const pic_params &p, const double *knots)
     c.gr_s = p.rho_kind == PIC_RHO_GR ? ((1.5 * p.theta_star) * tan(p.incl)) * p.cos_phi : 0.0;
     c.gr_g = (p.rho_kind == PIC_RHO_GR || (p.flags & PIC_GR_ALPHA)) ? p.rg_over_rstar : 0.0;
     c.gr_cg = ((0.5 * c.dt) * c.gr_g) / p.r_star;
+    {
+        // the GR push's short forms need its fixed operands where the general
+        // division's scaling steps do nothing (push_common.h, nr_div)
+        auto num_ok = [](double v) { return v == 0.0 || (fabs(v) >= 0x1p-600 && fabs(v) <= 0x1p+400); };
+        auto den_ok = [](double v) { return fabs(v) >= 0x1p-300 && fabs(v) <= 0x1p+300; };
+        c.gr_fast = (num_ok(c.gr_g) && num_ok(c.gr_cg) && den_ok(p.r_star) && den_ok(c.dz)) ? 1 : 0;
+    }
     c.rho0 = rho_node(c, knots, 0);
     c.qm = p.macro_charge != 0.0 ? p.macro_charge : (c.rho0 * c.dz) / p.ppc;
     c.qmP = c.qm / c.twoP;

@@ -69,23 +69,46 @@ __device__ __forceinline__ void push_one_f64(const Consts &c, const PushArgs &a,
     // eq. (1): u = gamma v, du/dt = (q/m) E_z, dz/dt = v
     double u1, gam, v, x1;
     if (GR) {
-        const double eta = 1.0 + (x * c.dz) / c.r_star;
-        const double a2 = 1.0 - c.gr_g / eta;
-        const double al = sqrt(a2);
-        const double kg = c.gr_cg / (eta * eta);
+        // the divisions and square roots take their short forms (nr_div,
+        // gs_sqrt: the same bits) when every live lane's operands allow them
+        const double zx = x * c.dz;
+        const bool fast = c.gr_fast && __all(!live || nr_num_ok(zx));
+        double eta, a2, al, kg, g0, gh;
         double t0 = u * u;
         t0 = 1.0 + t0;
-        const double g0 = sqrt(t0);
+        if (fast) {
+            const double rr = nr_recip(c.r_star);
+            eta = 1.0 + nr_div(zx, c.r_star, rr);
+            a2 = 1.0 - nr_div(c.gr_g, eta, nr_recip(eta));
+            al = gs_sqrt(a2);
+            const double e2 = eta * eta;
+            kg = nr_div(c.gr_cg, e2, nr_recip(e2));
+            g0 = gs_sqrt(t0);
+        } else {
+            eta = 1.0 + zx / c.r_star;
+            a2 = 1.0 - c.gr_g / eta;
+            al = sqrt(a2);
+            kg = c.gr_cg / (eta * eta);
+            g0 = sqrt(t0);
+        }
         const double uh = u + 0.5 * (al * E - kg * g0);
         double th = uh * uh;
         th = 1.0 + th;
-        const double gh = sqrt(th);
+        gh = fast ? gs_sqrt(th) : sqrt(th);
         u1 = u + (al * E - kg * gh);
         double tt = u1 * u1;
         tt = 1.0 + tt;
         gamma_velocity(u1, tt, gam, v);
         const double xh = x + 0.5 * (c.dtdz * (a2 * v));
-        x1 = x + c.dtdz * (gr_alpha2(c, xh * c.dz) * v);
+        const double zh = xh * c.dz;
+        double a2h;
+        if (fast && __all(!live || nr_num_ok(zh))) {
+            const double eh = 1.0 + nr_div(zh, c.r_star, nr_recip(c.r_star));
+            a2h = 1.0 - nr_div(c.gr_g, eh, nr_recip(eh));
+        } else {
+            a2h = gr_alpha2(c, zh);
+        }
+        x1 = x + c.dtdz * (a2h * v);
     } else {
         u1 = u + E;
         double tt = u1 * u1;
