@@ -496,40 +496,51 @@ def synth_preset(name):
     return synth.preset(name)
 
 
-def _adjoint_case(cfg, steps, ckpt):
+def _adjoint_case(cfg, steps, ckpt, reps=3):
+    """Plain forward, and recorded forward + reverse sweep, `reps` times each on
+    fresh tubes; the medians are reported (the reverse sweep's two streams make
+    single runs vary by tens of percent on these short kernels)."""
+    import statistics
+
     import torch
 
     from paper_1011_6330_amd import Tube, synth
     x, u = synth.warm_start(cfg)
     p = synth.tube_params(cfg)
-    # the plain forward: the same steps launched back to back, nothing recorded
-    # between them, timed from the host around a device synchronisation
-    t = Tube(p, device="cuda:0")
-    t.inject(x, u)
-    t.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    t.step(steps)
-    t.sync()
-    fwd = (time.perf_counter() - t0) * 1e3
-    t.close()
-    t = Tube(p, device="cuda:0")
-    t.inject(x, u)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f = t.adjoint_forward(steps, ckpt)
-    r = t.backward()
-    el = time.perf_counter() - t0
-    t.close()
-    del t
-    torch.cuda.empty_cache()
-    log(f"adjoint: plain forward {fwd:.1f} ms, checkpointed forward {f['forward_ms']:.1f} ms, "
-        f"backward {r['backward_ms']:.1f} ms, loss {r['loss']:.6g} over {r['n_exit']} exits, "
-        f"dL/drate {r['g_rate']:.4g}")
+    fwds, recs, bwds = [], [], []
+    for _ in range(reps):
+        # the plain forward: the same steps launched back to back, nothing recorded
+        # between them, timed from the host around a device synchronisation
+        t = Tube(p, device="cuda:0")
+        t.inject(x, u)
+        t.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.step(steps)
+        t.sync()
+        fwds.append((time.perf_counter() - t0) * 1e3)
+        t.close()
+        t = Tube(p, device="cuda:0")
+        t.inject(x, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = t.adjoint_forward(steps, ckpt)
+        r = t.backward()
+        el = time.perf_counter() - t0
+        recs.append(f["forward_ms"])
+        bwds.append(r["backward_ms"])
+        t.close()
+        del t
+        torch.cuda.empty_cache()
+    fwd, rec, bwd = statistics.median(fwds), statistics.median(recs), statistics.median(bwds)
+    log(f"adjoint: plain forward {fwd:.1f} ms, checkpointed forward {rec:.1f} ms, "
+        f"backward {bwd:.1f} ms (medians of {reps}; backward runs {', '.join(f'{b:.1f}' for b in bwds)} ms), "
+        f"loss {r['loss']:.6g} over {r['n_exit']} exits, dL/drate {r['g_rate']:.4g}")
     return {"steps": steps, "checkpoint_every": ckpt, "plain_forward_ms": fwd,
-            "checkpointed_forward_ms": f["forward_ms"], "backward_ms": r["backward_ms"],
-            "backward_over_plain_forward": r["backward_ms"] / fwd if fwd > 0 else None,
-            "backward_over_checkpointed_forward": r["backward_ms"] / f["forward_ms"] if f["forward_ms"] > 0 else None,
+            "checkpointed_forward_ms": rec, "backward_ms": bwd, "repeats": reps,
+            "backward_ms_runs": bwds, "plain_forward_ms_runs": fwds,
+            "backward_over_plain_forward": bwd / fwd if fwd > 0 else None,
+            "backward_over_checkpointed_forward": bwd / rec if rec > 0 else None,
             "loss": r["loss"], "n_exit": r["n_exit"], "tape_bytes": f["tape_bytes"], "wall_s": el,
             "g_kappa": r["g_kappa"], "g_rate": r["g_rate"]}
 
