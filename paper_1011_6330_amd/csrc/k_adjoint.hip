@@ -21,6 +21,8 @@
 
 namespace pcpic {
 
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ double wave_sum_f64(double v)
 {
 #pragma unroll
@@ -133,8 +135,8 @@ __global__ __launch_bounds__(256) void k_fill_f64(double *p, int64_t n)
 // (word set k, filled by the step before):
 //   |lu1t| <= max(max|lu|, 1/n_exit) + (dt/dz)(max|lx| + 2^P |c4| max|lez|)
 // bounds every particle's kick-adjoint addend (gamma >= 1), and a run of the
-// wave adds at most 64 of them; a particle's rate-gradient term is at most
-// 2 2^P |c4| max|lez|, 64 of them per wave.  Every block that needs the
+// wave adds at most 128 of them (two slots per lane); a particle's
+// rate-gradient term is at most 2 2^P |c4| max|lez|, 128 of them per wave.  Every block that needs the
 // exponents forms them from the same words, so they agree everywhere.  The
 // word sets rotate over three: step r reads set r mod 3, fills set r+1 and
 // clears set r+2.
@@ -146,8 +148,8 @@ __device__ __forceinline__ void step_exponents(const Consts &c, const AdjScale *
     const double seed = n_exit > 0 ? 1.0 / (double)n_exit : 0.0;
     const double lj = c.twoP * fabs(c.c4) * mlez;
     const double bound = (mlu > seed ? mlu : seed) + c.dtdz * (mlx + lj);
-    e_k = adj_exponent(64.0 * bound);
-    e_g = adj_exponent(128.0 * lj);
+    e_k = adj_exponent(128.0 * bound);
+    e_g = adj_exponent(256.0 * lj);
 }
 
 struct AdjPartArgs {
@@ -165,100 +167,152 @@ struct AdjPartArgs {
     int rot;
 };
 
-// 2. particles: the forward push recomputed exactly, then its transpose.
+// One slot's reverse step: the forward push recomputed exactly, then its
+// transpose.  lx_in, lu_in: the slot's adjoints after the step.  The new slot
+// adjoints, the kick-adjoint terms (faces ka, kb) and the rate-gradient term.
+struct AdjSlot {
+    double nlx, nlu, va, vb, gr;
+    int ka, kb;
+    bool wa, wb;
+};
+
+__device__ __forceinline__ AdjSlot adj_slot(const Consts &c, const AdjPartArgs &a, int64_t p, double x, double u,
+                                            double lx_in, double lu_in)
+{
+    const int N = (int)c.N;
+    AdjSlot o{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, false, false};
+    const double s = x - 0.5;
+    int clamp = 0, jj = 0;
+    double g = 0.0, dEdx = 0.0;
+    const double kN1 = c.qmdt * a.ez[N - 1], k0 = c.qmdt * a.ez[0];
+    double kj = 0.0, kj1 = 0.0;
+    if (s < 0.0) {
+        clamp = 1;
+    } else if (s >= (double)(N - 1)) {
+        clamp = 2;
+    } else {
+        jj = (int)floor(s);
+        g = s - (double)jj;
+        kj = c.qmdt * a.ez[jj];
+        kj1 = c.qmdt * a.ez[jj + 1];
+        dEdx = kj1 - kj;
+    }
+    const double E = clamp == 1 ? k0 : (clamp == 2 ? kN1 : kj + g * (kj1 - kj));
+    const double u1 = u + E;
+    double t = u1 * u1;
+    t = 1.0 + t;
+    const double gam = sqrt(t);
+    const double v = u1 / gam;
+    const double x1 = x + c.dtdz * v;
+    const double c0d = floor(x), c1d = floor(x1);
+    const int c0 = (int)c0d, c1 = (int)c1d;
+    double lx1 = 0.0, lu1 = 0.0;
+    if (x1 >= (double)N) {
+        lu1 = a.n_exit > 0 ? (u1 / gam) / (double)a.n_exit : 0.0;   // d gamma/du = u/gamma
+    } else if (x1 >= 0.0) {
+        lx1 = lx_in;
+        lu1 = lu_in;
+    }
+    // current: J_i = S_i(x) - S_i(x1), dS_i/dx = -2^P in cell i; E_z^{s+1} -= c4 J
+    if (c1 >= 0 && c1 < N) lx1 += c.twoP * (-c.c4 * a.lez[c1]);
+    const double lx0J = -c.twoP * (-c.c4 * a.lez[c0]);
+    if (p >= a.n_pre) {
+        // injected class: its deposit times -c4 times the adjoint of E_z^{s+1}
+        const double F0 = rint((x - c0d) * c.twoP), F1 = rint((x1 - c1d) * c.twoP);
+        double d0, d1 = 0.0;
+        if (c1 == c0) {
+            d0 = F1 - F0;
+        } else if (c1 > c0) {
+            d0 = c.twoP - F0;
+            d1 = c1 < N ? F1 : 0.0;
+        } else {
+            d0 = -F0;
+            d1 = c1 >= 0 ? F1 - c.twoP : 0.0;
+        }
+        o.gr += d0 * (-c.c4 * a.lez[c0]);
+        if (d1 != 0.0) o.gr += d1 * (-c.c4 * a.lez[c1]);
+    }
+    // move: x1 = x + (dt/dz) u1/gamma(u1), dv/du = 1/gamma^3
+    const double lu1t = lu1 + lx1 * c.dtdz / (gam * gam * gam);
+    o.nlx = lx1 + lx0J + lu1t * dEdx;
+    o.nlu = lu1t;
+    // kick: E = K_j (1 - g) + K_{j+1} g
+    if (clamp == 1) { o.ka = 0; o.va = lu1t; o.wa = true; }
+    else if (clamp == 2) { o.ka = N - 1; o.va = lu1t; o.wa = true; }
+    else { o.ka = jj; o.va = lu1t * (1.0 - g); o.kb = jj + 1; o.vb = lu1t * g; o.wa = true; o.wb = true; }
+    return o;
+}
+
+// 2. particles: two consecutive slots per thread (16-byte accesses).  A slot
+// removed before the step keeps its adjoints; a slot injected at the end of
+// the step (n_s <= p < n_next: created at rest, no dependence) gets 0.  The
+// two slots' kick-adjoint terms are merged where they fall on the same face
+// (the usual case, as consecutive slots sit in the same or the next cell), so
+// the wave usually sums two keyed terms per thread instead of four.
 __global__ __launch_bounds__(256) void k_adj_particles(Consts c, AdjPartArgs a)
 {
     const int64_t ns = *a.n_s, nn = *a.n_next;
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int N = (int)c.N;
+    if ((int64_t)blockIdx.x * 512 >= nn) return;      // a block past every slot (uniform): nothing to add
+    const int64_t p0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
     int e_k, e_g;
     step_exponents(c, a.sc, a.rot, a.n_exit, e_k, e_g);
-    double nlx = 0.0, nlu = 0.0;              // the new slot adjoints (for the next step's maxima)
-    bool live = false;
-    int ka = 0, kb = 0;
-    double va = 0.0, vb = 0.0, gr = 0.0;
-    bool wa = false, wb = false;
-    if (p < ns) {
-        const double x = a.X[p], u = a.U[p];
-        if (x >= 0.0) {
-            live = true;
-            const double s = x - 0.5;
-            int clamp = 0, jj = 0;
-            double g = 0.0, dEdx = 0.0;
-            const double kN1 = c.qmdt * a.ez[N - 1], k0 = c.qmdt * a.ez[0];
-            double kj = 0.0, kj1 = 0.0;
-            if (s < 0.0) {
-                clamp = 1;
-            } else if (s >= (double)(N - 1)) {
-                clamp = 2;
-            } else {
-                jj = (int)floor(s);
-                g = s - (double)jj;
-                kj = c.qmdt * a.ez[jj];
-                kj1 = c.qmdt * a.ez[jj + 1];
-                dEdx = kj1 - kj;
-            }
-            const double E = clamp == 1 ? k0 : (clamp == 2 ? kN1 : kj + g * (kj1 - kj));
-            const double u1 = u + E;
-            double t = u1 * u1;
-            t = 1.0 + t;
-            const double gam = sqrt(t);
-            const double v = u1 / gam;
-            const double x1 = x + c.dtdz * v;
-            const double c0d = floor(x), c1d = floor(x1);
-            const int c0 = (int)c0d, c1 = (int)c1d;
-            double lx1 = 0.0, lu1 = 0.0;
-            if (x1 >= (double)N) {
-                lu1 = a.n_exit > 0 ? (u1 / gam) / (double)a.n_exit : 0.0;   // d gamma/du = u/gamma
-            } else if (x1 >= 0.0) {
-                lx1 = a.lx[p];
-                lu1 = a.lu[p];
-            }
-            // current: J_i = S_i(x) - S_i(x1), dS_i/dx = -2^P in cell i; E_z^{s+1} -= c4 J
-            if (c1 >= 0 && c1 < N) lx1 += c.twoP * (-c.c4 * a.lez[c1]);
-            const double lx0J = -c.twoP * (-c.c4 * a.lez[c0]);
-            if (p >= a.n_pre) {
-                // injected class: its deposit times -c4 times the adjoint of E_z^{s+1}
-                const double F0 = rint((x - c0d) * c.twoP), F1 = rint((x1 - c1d) * c.twoP);
-                double d0, d1 = 0.0;
-                if (c1 == c0) {
-                    d0 = F1 - F0;
-                } else if (c1 > c0) {
-                    d0 = c.twoP - F0;
-                    d1 = c1 < N ? F1 : 0.0;
-                } else {
-                    d0 = -F0;
-                    d1 = c1 >= 0 ? F1 - c.twoP : 0.0;
-                }
-                gr += d0 * (-c.c4 * a.lez[c0]);
-                if (d1 != 0.0) gr += d1 * (-c.c4 * a.lez[c1]);
-            }
-            // move: x1 = x + (dt/dz) u1/gamma(u1), dv/du = 1/gamma^3
-            const double lu1t = lu1 + lx1 * c.dtdz / (gam * gam * gam);
-            nlx = lx1 + lx0J + lu1t * dEdx;
-            nlu = lu1t;
-            a.lx[p] = nlx;
-            a.lu[p] = nlu;
-            // kick: E = K_j (1 - g) + K_{j+1} g
-            if (clamp == 1) { ka = 0; va = lu1t; wa = true; }
-            else if (clamp == 2) { ka = N - 1; va = lu1t; wa = true; }
-            else { ka = jj; va = lu1t * (1.0 - g); kb = jj + 1; vb = lu1t * g; wa = true; wb = true; }
-        }
-    } else if (p < nn) {
-        // injected at the end of step s: created at rest, no dependence
-        a.lx[p] = 0.0;
-        a.lu[p] = 0.0;
+    double x[2] = {-1.0, -1.0}, u[2] = {0.0, 0.0}, lxi[2] = {0.0, 0.0}, lui[2] = {0.0, 0.0};
+    const bool pair = p0 + 2 <= nn;
+    if (pair) {
+        const dvec2 xv = *(const dvec2 *)(a.X + p0), uv = *(const dvec2 *)(a.U + p0);
+        const dvec2 lxv = *(const dvec2 *)(a.lx + p0), luv = *(const dvec2 *)(a.lu + p0);
+        x[0] = xv.x; x[1] = xv.y; u[0] = uv.x; u[1] = uv.y;
+        lxi[0] = lxv.x; lxi[1] = lxv.y; lui[0] = luv.x; lui[1] = luv.y;
+    } else if (p0 < nn) {
+        x[0] = a.X[p0]; u[0] = a.U[p0]; lxi[0] = a.lx[p0]; lui[0] = a.lu[p0];
     }
-    (void)live;
-    wave_add_runs_fixed(a.lk_lo, a.lk_hi, ka, va, wa, e_k);
-    wave_add_runs_fixed(a.lk_lo, a.lk_hi, kb, vb, wb, e_k);
-    // the rate gradient: only lanes of the injected class have a term
+    AdjSlot o[2];
+    double nlx[2], nlu[2], mlx = 0.0, mlu = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int64_t p = p0 + k;
+        o[k] = AdjSlot{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, false, false};
+        nlx[k] = lxi[k];
+        nlu[k] = lui[k];
+        if (p < ns) {
+            if (x[k] >= 0.0) {
+                o[k] = adj_slot(c, a, p, x[k], u[k], lxi[k], lui[k]);
+                nlx[k] = o[k].nlx;
+                nlu[k] = o[k].nlu;
+                mlx = fmax(mlx, fabs(o[k].nlx));
+                mlu = fmax(mlu, fabs(o[k].nlu));
+            }
+        } else {
+            nlx[k] = 0.0;
+            nlu[k] = 0.0;
+        }
+    }
+    if (pair) {
+        *(dvec2 *)(a.lx + p0) = dvec2{nlx[0], nlx[1]};
+        *(dvec2 *)(a.lu + p0) = dvec2{nlu[0], nlu[1]};
+    } else if (p0 < nn) {
+        a.lx[p0] = nlx[0];
+        a.lu[p0] = nlu[0];
+    }
+    // the second slot's terms join the first slot's where the face is the same
+    AdjSlot &f = o[0], &h = o[1];
+    if (h.wa && !f.wa) { f.ka = h.ka; f.va = h.va; f.wa = true; h.wa = false; }
+    if (h.wb && !f.wb && !(f.wa && h.wb && h.kb == f.ka)) { f.kb = h.kb; f.vb = h.vb; f.wb = true; h.wb = false; }
+    if (h.wa && h.ka == f.ka) { f.va += h.va; h.wa = false; }
+    else if (h.wa && f.wb && h.ka == f.kb) { f.vb += h.va; h.wa = false; }
+    if (h.wb && f.wb && h.kb == f.kb) { f.vb += h.vb; h.wb = false; }
+    wave_add_runs_fixed(a.lk_lo, a.lk_hi, f.ka, f.va, f.wa, e_k);
+    wave_add_runs_fixed(a.lk_lo, a.lk_hi, f.kb, f.vb, f.wb, e_k);
+    if (__ballot(h.wa)) wave_add_runs_fixed(a.lk_lo, a.lk_hi, h.ka, h.va, h.wa, e_k);
+    if (__ballot(h.wb)) wave_add_runs_fixed(a.lk_lo, a.lk_hi, h.kb, h.vb, h.wb, e_k);
+    // the rate gradient: only slots of the injected class have a term
+    const double gr = o[0].gr + o[1].gr;
     if (__ballot(gr != 0.0)) {
         const double gs = wave_sum_f64_to63(gr);
         if (__lane_id() == 63 && gs != 0.0) fixed_add(&a.sc->g_lo, &a.sc->g_hi, gs, e_g);
     }
     const int nx = a.rot == 2 ? 0 : a.rot + 1;
-    block_max_abs2(&a.sc->max_lx[nx], &a.sc->max_lu[nx], nlx, nlu);
+    block_max_abs2(&a.sc->max_lx[nx], &a.sc->max_lu[nx], mlx, mlu);
 }
 
 // 2. transposed leap-frog of step s: adjoints of E_z^s, E_r^s, B^{s-1/2}, with
@@ -492,7 +546,7 @@ hipError_t launch_adj_step(pic_handle *h, const AdjStepPtrs &s)
     const Consts &c = h->c;
     AdjPartArgs a{s.X, s.U, s.ez, s.n_s, s.n_next, s.n_pre, s.n_exit, s.lx, s.lu, s.lez, s.lk_lo, s.lk_hi,
                   s.scale, s.rot};
-    hipLaunchKernelGGL(k_adj_particles, dim3(gridn(c.cap)), dim3(256), 0, h->stream, c, a);
+    hipLaunchKernelGGL(k_adj_particles, dim3((unsigned)((c.cap + 511) / 512)), dim3(256), 0, h->stream, c, a);
     hipLaunchKernelGGL(k_adj_fields, dim3(gridn(c.N + 1)), dim3(256), 0, h->stream, c, s.lez, s.ler, s.lern, s.lb,
                        s.lbp, s.lbpn, s.lk_lo, s.lk_hi, s.scale, s.rot, s.n_exit);
     return hipGetLastError();

@@ -9,13 +9,13 @@
 // wave's pair v being 128 consecutive slots, each pair one 16-byte vector per
 // stream.  Between cell sorts consecutive slots sit in the same cell, so a
 // thread's current contributions land on the faces around the one or two
-// cells of its pair and are summed in four register channels (DepAcc); one
-// DPP reduction per wave and pair (segmented when the wave spans several
-// cells) then issues a single int64 atomic per face and run of lanes in the
-// same cell.  The particle arithmetic is straight-line code with selects, so
-// lanes that stay in their cell and lanes that cross a face share one
-// instruction stream; the rare boundary events (exit, return, node-0 tally)
-// are added by the lanes that have them.
+// cells of its pair and are summed in four register channels (DepAcc); per
+// wave and pair the channels are summed (all four together for a wave in one
+// cell, through a per-wave LDS window for a few cells, by segmented scans
+// otherwise) into one int64 atomic per face.  The particle arithmetic is
+// straight-line code with selects, so lanes that stay in their cell and lanes
+// that cross a face share one instruction stream; the rare boundary events
+// (exit, return, node-0 tally) are added by the lanes that have them.
 #include <math.h>
 
 #include "pcpic_internal.h"
@@ -55,12 +55,12 @@ static hipError_t launch_push_args_t(pic_handle *h, const PushArgs &a)
 }
 
 // FP64 push reading (X, U) and writing (Xo, Uo) in the field ez (used by the
-// adjoint recompute).
+// adjoint recompute), at the default launch shape.
 hipError_t launch_push_f64_ptrs(pic_handle *h, const double *X, const double *U, double *Xo, double *Uo,
                                 const double *ez)
 {
     PushArgs a{X, U, Xo, Uo, ez, (unsigned long long *)h->ws.j[h->jbuf], h->ws.ctr};
-    return launch_push_args_t<64, 2, 1>(h, a);
+    return launch_push_args_t<128, 2, 1>(h, a);
 }
 
 hipError_t launch_push_f64(pic_handle *h)
