@@ -130,9 +130,9 @@ def roofline_of(bytes_per_launch, tim, kernel):
 
 
 CSRC = "paper_1011_6330_amd/csrc/"
-PUSH_SOURCES = tuple(CSRC + f for f in ("k_push.hip", "push_body.h", "push_common.h", "wave.h"))
-PUSH32_SOURCES = tuple(CSRC + f for f in ("k_push32.hip", "push_body.h", "push_common.h", "wave.h"))
-BATCH_SOURCES = tuple(CSRC + f for f in ("k_batch.hip", "push_body.h", "push_common.h", "wave.h"))
+PUSH_SOURCES = tuple(CSRC + f for f in ("k_push.hip", "push_body.h", "push_common.h", "short_math.h", "wave.h"))
+PUSH32_SOURCES = tuple(CSRC + f for f in ("k_push32.hip", "push_body.h", "push_common.h", "short_math.h", "wave.h"))
+BATCH_SOURCES = tuple(CSRC + f for f in ("k_batch.hip", "push_body.h", "push_common.h", "short_math.h", "wave.h"))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_f64_c2_hbm_traffic.txt")
 TRAFFIC32_FILE = os.path.join(ROOT, "profiles", "k_push_f32_c2_hbm_traffic.txt")
 TRAFFIC_BATCH_FILE = os.path.join(ROOT, "profiles", "k_batch_push_c3_hbm_traffic.txt")

@@ -9,6 +9,7 @@
 
 #include "diag_body.h"
 #include "pcpic_internal.h"
+#include "short_math.h"
 #include "wave.h"
 #include "field_body.h"
 #include "sort_body.h"
@@ -84,21 +85,6 @@ __global__ __launch_bounds__(256) void k_poisson_rhs(Consts c, const int64_t *w,
 constexpr int TH_CHUNK = 2048;
 constexpr int TH_RUN = 16;
 
-__device__ __forceinline__ double th_recip(double m)
-{
-    double r = __builtin_amdgcn_rcp(m);
-    double e = fma(-m, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-m, r, 1.0);
-    return fma(r, e, r);
-}
-// n / m from r = th_recip(m)
-__device__ __forceinline__ double th_div(double n, double m, double r)
-{
-    const double q = n * r;
-    const double rem = fma(-m, q, n);
-    return fma(rem, r, q);
-}
 // The range in which the division's scaling and special-case steps do nothing:
 // denominators within [2^-300, 2^300] and numerators within [2^-600, 2^400] in
 // magnitude.  A run tracks the smallest and largest magnitudes it meets (plain
@@ -144,13 +130,13 @@ __device__ __forceinline__ bool th_run_fast(const double (&s)[TH_RUN], const dou
         const double n = s[k] - pd;
         rg.num(n);
         if (FIXED) {
-            pd = th_div(n, f.mst, f.rst);
+            pd = nr_div(n, f.mst, f.rst);
         } else {
             const double m = bd[k] - pc;
-            const double r = th_recip(m);
+            const double r = nr_recip(m);
             rg.den(m);
             pc = fma(fma(-m, r, 1.0), r, r);
-            pd = th_div(n, m, r);
+            pd = nr_div(n, m, r);
         }
         ci[k] = pc;
         di[k] = pd;
@@ -164,7 +150,7 @@ __device__ __forceinline__ bool th_run_fast(const double (&s)[TH_RUN], const dou
     if (!FIXED && !gr && ci[TH_RUN - 1] == ci[TH_RUN - 2]) {
         f.fixed = true;
         f.mst = bd[TH_RUN - 1] - pc;
-        f.rst = th_recip(f.mst);
+        f.rst = nr_recip(f.mst);
     }
     f.pc = pc;
     f.pd = pd;

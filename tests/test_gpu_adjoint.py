@@ -57,6 +57,15 @@ def test_adjoint_warm_matches_oracle(ckpt):
     assert abs(r["g_kappa"] - g_kappa) <= 1e-8 * abs(g_kappa)
 
 
+def test_adjoint_odd_slot_count_matches_oracle():
+    """An odd number of slots (the particle kernel takes two per thread, so the last
+    thread holds one): the gradient still matches the oracle's."""
+    cfg, x, u = _warm_cfg(n=2001)
+    assert len(x) == 2001
+    say("adjoint odd slot count")
+    _compare(cfg, x, u, 120, 7)
+
+
 def test_adjoint_cold_rate_matches_oracle():
     cfg, x, u = _cold_cfg()
     say("adjoint cold")
