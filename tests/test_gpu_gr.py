@@ -67,6 +67,22 @@ def test_gr_alpha_c2_full_size_first_steps():
     g.close()
 
 
+@pytest.mark.parametrize("rg", [0.05, 0.95])
+def test_gr_alpha_strong_and_weak_lapse_bit_identical(rg):
+    """The lapse at r_g/R_* = 0.05 and 0.95 (alpha^2 down to 0.05 at the surface): a
+    sorted warm beam, 80 steps, every result bit-identical to the oracle."""
+    N = 2048
+    cfg = dict(synth.preset("c2"), n_cells=N, q_over_m=synth.q_over_m_for(300.0), ppc=30.0, warm=30 * N,
+               capacity=int(30 * N * 1.3), sort_every=16, flags=GR_ALPHA, rg_over_rstar=rg)
+    x, u = synth.warm_start(cfg)
+    say("gr alpha lapse", rg, N, len(x))
+    g, o = make_pair(cfg, x, u)
+    g.step(80)
+    o.step(80)
+    assert_state_equal(g, o, ordered=False, what=f"gr alpha r_g/R_* = {rg}")
+    g.close()
+
+
 def test_gr_alpha_zero_rg_equals_flat_on_gpu():
     """r_g = 0: the GR kernels give the flat step's bits (200 steps of the C1 tube)."""
     cfg = dict(synth.preset("c1"), rho_kind=synth.RHO_FRAME_DRAG, kappa=0.15, r_star=10.0)
