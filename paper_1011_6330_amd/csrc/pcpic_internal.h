@@ -77,6 +77,10 @@ constexpr int F32_PPT_HI = 4;
 // particle's offset to the grid once its momentum reaches the threshold).
 constexpr int HI_GROUP_LOG2 = 8;
 constexpr int HI_GROUP = 1 << HI_GROUP_LOG2;
+// Steps per captured round of a tube that never sorts (even: the field and
+// current buffers end a round in the parity they started it in).
+constexpr int64_t GRAPH_ROUND = 32;
+
 // Faces per thread of the field update (field_body.h).
 constexpr int FIELD_CPT = 4;
 

@@ -526,8 +526,11 @@ pic_status pic_step(pic_handle *h, int64_t n_steps)
     // A whole round of sort_every steps that starts on a round boundary is
     // replayed from a graph captured once per (field, current, particle)
     // buffer-parity state; other steps are launched one by one.  Both issue the
-    // same kernels with the same arguments.
-    const int64_t S = h->p.sort_every;
+    // same kernels with the same arguments.  A tube that never sorts takes
+    // rounds of GRAPH_ROUND steps the same way (an even count, so a round ends
+    // in the parity state it started from).
+    const bool sorts = h->p.sort_every > 0;
+    const int64_t S = sorts ? h->p.sort_every : GRAPH_ROUND;
     while (n_steps > 0) {
         if (S > 1 && h->use_graph && h->step % S == 0 && n_steps >= S) {
             const int key = h->fbuf | (h->jbuf << 1) | (h->pbuf << 2);
@@ -559,7 +562,7 @@ pic_status pic_step(pic_handle *h, int64_t n_steps)
             HIP_OK(hipGraphLaunch(h->graph[key], h->stream));
             h->fbuf ^= (int)(S & 1);
             h->jbuf ^= (int)(S & 1);
-            h->pbuf ^= 1;
+            if (sorts) h->pbuf ^= 1;
             h->step += S;
             n_steps -= S;
         } else {
