@@ -680,14 +680,50 @@ def cpu_baseline(cfg, x, u, seconds):
         del o
     a = legs["all_cores"]
     adj = cpu_adjoint_ratio()
+    others = cpu_other_configs(threads)
     return {"value": a["value"], "unit": "particle-steps/s", "cores": a["threads"], "kind": "oracle",
-            "adjoint": adj,
+            "adjoint": adj, "other_configs": others,
             "sample": f"the same warm tube ({len(x)} particles at the start), first {a['steps']} steps, FP64 "
                       f"oracle on {a['threads']} threads (particles split into contiguous slices, integer sums "
                       f"in thread order: the serial oracle's state bit for bit)",
             "serial": {"value": legs["serial"]["value"], "cores": 1, "steps": legs["serial"]["steps"],
                        "sample": f"first {legs['serial']['steps']} steps, single-threaded FP64 oracle"},
             "parallel_speedup": a["value"] / legs["serial"]["value"], **host}
+
+
+def cpu_other_configs(threads, ens_steps=2):
+    """The oracle on the small tube (C1 from empty, all 2000 steps, serial: a time per
+    step) and on the ensemble (every tube of C3 from its warm start, `ens_steps`
+    steps on `threads` threads: particle-steps/s)."""
+    from oracle.oracle import OracleTube
+    from paper_1011_6330_amd import synth
+    out = {}
+    c1 = synth.preset("c1")
+    p = {k: v for k, v in synth.tube_params(c1).items()
+         if k not in ("sort_every", "max_bins", "precision", "gamma_fp64")}
+    o = OracleTube(p)
+    t0 = time.perf_counter()
+    o.step(2000)
+    el = time.perf_counter() - t0
+    out["c1"] = {"us_per_step": el / 2000 * 1e6, "steps": 2000, "threads": 1, "particles_end": int(o.n)}
+    log(f"oracle c1: {el / 2000 * 1e6:.1f} us/step over 2000 steps (serial)")
+    ps, el = 0.0, 0.0
+    for t, c in enumerate(synth.ensemble(n_tubes=256, seed=0, precision=0)):
+        x, u = synth.warm_start(c, seed=t)
+        p = {k: v for k, v in synth.tube_params(c).items()
+             if k not in ("sort_every", "max_bins", "precision", "gamma_fp64")}
+        o = OracleTube(p)
+        o.inject(x, u)
+        n = o.n
+        t0 = time.perf_counter()
+        o.step_par(ens_steps, threads)
+        el += time.perf_counter() - t0
+        ps += 0.5 * (n + o.n) * ens_steps
+        del o
+    out["c3"] = {"value": ps / el, "unit": "particle-steps/s", "steps": ens_steps, "threads": threads,
+                 "sample": f"all 256 tubes, {ens_steps} steps each from the warm start (tube set-up not timed)"}
+    log(f"oracle c3: {ps / el:.3g} particle-steps/s on {threads} threads ({ens_steps} steps of all 256 tubes)")
+    return out
 
 
 def cpu_adjoint_ratio(steps=200):
