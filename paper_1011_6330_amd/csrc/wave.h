@@ -61,19 +61,6 @@ __device__ __forceinline__ WaveRun wave_runs(long long key, bool want)
     return r;
 }
 
-// Sum of v over [lane, end) (Hillis-Steele suffix scan inside contiguous runs);
-// on a run's head lane it is the run total.  Every lane must call it.
-__device__ __forceinline__ double run_sum_to_head(double v, int end)
-{
-    const int lane = (int)__lane_id();
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_down(v, (unsigned)off);
-        if (lane + off < end) v += t;
-    }
-    return v;
-}
-
 // Add `val` to dst[key] for every lane with `want`, one global atomic per
 // distinct key present in the wave: lanes sharing the leader's key are summed
 // with a butterfly, the leader lane issues the atomic, and the loop repeats
@@ -121,8 +108,8 @@ __device__ __forceinline__ double dpp_f64(double v)
 
 // Sum over the 64 lanes, valid in lane 63: inclusive scan inside each row of
 // 16 lanes (row_shr 1, 2, 4, 8), then row 0 -> row 1 and row 2 -> row 3
-// (row_bcast:15), then rows 0-1 -> rows 2-3 (row_bcast:31).  Used on
-// integer-valued doubles below 2^53, where every addition is exact.
+// (row_bcast:15), then rows 0-1 -> rows 2-3 (row_bcast:31).  The additions
+// come in a fixed order (exact for integer-valued doubles below 2^53).
 __device__ __forceinline__ double wave_sum_f64_to63(double v)
 {
     v += dpp_f64<0x111, 0xf>(v);
@@ -205,36 +192,9 @@ __device__ __forceinline__ double wave_max_f64_to63(double v)
     return v;
 }
 
-// Sum over the 64 lanes of an int32, valid in lane 63, with the same DPP
-// pattern as wave_sum_f64_to63; each step is one add with a DPP operand.
-__device__ __forceinline__ int wave_sum_i32_to63(int v)
-{
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
-    return v;
-}
-
-// Sum over the 64 lanes of integer-valued doubles with |v| < 2^40, exact,
-// valid in lane 63: each value is split into 2^16 v_hi + v_lo with
-// 0 <= v_lo < 2^16, and the two int32 parts are summed apart (no part sum can
-// reach 2^31), which is cheaper than summing the doubles.
-__device__ __forceinline__ long long wave_sum_int_f64_to63(double v)
-{
-    const double hd = floor(v * 0x1p-16);
-    const int hi = (int)hd;
-    const int lo = (int)fma(hd, -65536.0, v);
-    const int hs = wave_sum_i32_to63(hi);
-    const int ls = wave_sum_i32_to63(lo);
-    return (long long)hs * 65536 + (long long)ls;
-}
-
 // Minimum (maximum) of an int32 over the 64 lanes, returned in every lane: the
-// DPP pattern of wave_sum_i32_to63 with min (max) in place of the sum, where a
-// lane without a DPP source keeps its own value, then lane 63 read back.
+// DPP pattern of wave_sum_f64_to63 on int32 with min (max) in place of the sum,
+// where a lane without a DPP source keeps its own value, then lane 63 read back.
 __device__ __forceinline__ int wave_min_i32(int v)
 {
     v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xf, 0xf, false));
