@@ -21,6 +21,9 @@ sort on the tube's stream.  Prints one JSON line:
                  gamma = 1e6, f64 above), with its own roofline (traffic from
                  profiles/k_push_f32_c2_hbm_traffic.txt); low_gamma: the
                  same geometry with a beam below 1e6, FP64 against FP32-bulk
+  gr_alpha       the same tube with the full-GR lapse (PIC_GR_ALPHA), FP64, with
+                 the push's VALU busy time from
+                 profiles/k_push_f64_gr_c2_sq_counters.txt (same source rule)
   large_tube     the 2^20-cell tube with 2.5e8 particles in FP64 and FP32-bulk,
                  with the Gauss residual at the end
   ensemble       256 tubes of uneven size, one graph launch per round (FP32-bulk;
@@ -136,6 +139,7 @@ BATCH_SOURCES = tuple(CSRC + f for f in ("k_batch.hip", "push_body.h", "push_com
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_f64_c2_hbm_traffic.txt")
 TRAFFIC32_FILE = os.path.join(ROOT, "profiles", "k_push_f32_c2_hbm_traffic.txt")
 TRAFFIC_BATCH_FILE = os.path.join(ROOT, "profiles", "k_batch_push_c3_hbm_traffic.txt")
+GR_SQ_FILE = os.path.join(ROOT, "profiles", "k_push_f64_gr_c2_sq_counters.txt")
 
 
 def push_source_hash(sources=PUSH_SOURCES):
@@ -298,6 +302,13 @@ def main():
                               "roofline": groof, "vs_flat": gval / value,
                               "workload": "the c2 tube with the lapse alpha (r_g/R_* = 0.4) in Maxwell's equations "
                                           "and the equation of motion (PIC_GR_ALPHA), FP64"}
+        # the full-GR push is launched at 128 x 2 whatever the configured shape
+        busy = measured_traffic((128, 2, True), GR_SQ_FILE, PUSH_SOURCES, key="valu_busy_us")
+        if busy is not None:
+            result["gr_alpha"]["valu"] = {
+                "busy_us": busy, "frac_of_push": busy / groof["avg_launch_us"],
+                "source": "SQ_ACTIVE_INST_VALU x 4 cycles over 1024 SIMDs at 2.4 GHz, from "
+                          "profiles/k_push_f64_gr_c2_sq_counters.txt (taken on these kernel sources)"}
         log(f"gr alpha: {gel / args.steps * 1e3:.3f} ms/step, push {groof['avg_launch_us']:.1f} us "
             f"({groof['achieved']:.0f} GB/s), {gval / value:.3f} of the flat step")
 
