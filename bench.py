@@ -212,8 +212,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="seconds per CPU-baseline leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(how the step would shard is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(no sharding of a tube across GPUs, no collectives)", file=sys.stderr)
         sys.exit(2)
 
     import torch
