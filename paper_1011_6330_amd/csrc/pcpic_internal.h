@@ -57,8 +57,9 @@ struct Consts {
 
 // Slots per thread of the two FP32-bulk push streams: the low stream loads its
 // three 4-byte fields as 16-byte vectors of 4 slots; the high stream takes 4
-// slots too (a 16-byte vector of position words, two 16-byte f64 momentum
-// vectors), so that one wave covers one group of HI_GROUP slots.
+// slots too, as two pairs 128 slots apart (an 8-byte vector of position words
+// and a 16-byte f64 momentum vector per pair, so that each access instruction
+// covers one contiguous span), and one wave covers one group of HI_GROUP slots.
 constexpr int F32_PPT_LO = 4;
 constexpr int F32_PPT_HI = 4;
 
