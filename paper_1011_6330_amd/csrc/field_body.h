@@ -76,69 +76,115 @@ __device__ __forceinline__ double field_cell(const Consts &c, const FieldArgs &a
     return ez;
 }
 
-// The flat update (no lapse, fields not frozen) of the four faces i0 .. i0+3
-// (i0 a multiple of 4, i0 + 4 <= N) with 16-byte accesses; each face's B is
-// computed once and serves as B_{i-1/2} of the next face, with the same
-// expressions as field_cell.  Returns the new E_z of face i0.
-__device__ __forceinline__ double field_cells4_flat(const Consts &c, const FieldArgs &a, int64_t i0)
+// Value of lane + 1 (lane 63 reads 0) and of lane - 1 (lane 0 reads 0) of a
+// double: DPP wave_shl:1 and wave_shr:1 on its two halves.
+__device__ __forceinline__ double lane_next_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_prev_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// The flat update (no lapse, fields not frozen) of the 4*64 faces [w0, w0 + 256)
+// of one wave (w0 a multiple of 256, w0 + 256 <= N), wave-collective.  Lane L
+// takes the face pairs w0 + 2L and w0 + 128 + 2L, so that each 16-byte access
+// covers one contiguous span of 128 faces.  A pair's new B at its first face
+// serves as B_{i-1/2} of its second; B_{i-1/2} of its first face is the new B
+// of the previous lane's second face (moved across lanes), of the first pairs'
+// last lane for lane 0's second pair, and is recomputed with field_cell's
+// expression only at face w0 - 1; E_r after a pair likewise comes from the
+// next lane.  Every value has the expression, and so the bits, of field_cell.
+// Returns the new E_z of face w0 + 2L.
+__device__ __forceinline__ double field_wave_pairs(const Consts &c, const FieldArgs &a, int64_t w0)
 {
     typedef double d2 __attribute__((ext_vector_type(2)));
     typedef long long l2 __attribute__((ext_vector_type(2)));
-    typedef float f4 __attribute__((ext_vector_type(4)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const int lane = (int)__lane_id();
     const int64_t N = c.N;
-    const d2 ez01 = *(const d2 *)(a.ezo + i0), ez23 = *(const d2 *)(a.ezo + i0 + 2);
-    const d2 er01 = *(const d2 *)(a.ero + i0), er23 = *(const d2 *)(a.ero + i0 + 2);
-    const d2 bo01 = *(const d2 *)(a.bo + i0), bo23 = *(const d2 *)(a.bo + i0 + 2);
-    const l2 j01 = *(const l2 *)(a.j + i0), j23 = *(const l2 *)(a.j + i0 + 2);
-    const double er4 = a.ero[i0 + 4];
-    const double ez[4] = {ez01.x, ez01.y, ez23.x, ez23.y};
-    const double er[5] = {er01.x, er01.y, er23.x, er23.y, er4};
-    const double bo[4] = {bo01.x, bo01.y, bo23.x, bo23.y};
-    const long long jj[4] = {j01.x, j01.y, j23.x, j23.y};
-    double b[5];
-    b[0] = 0.0;
-    if (i0 >= 1) b[0] = a.bo[i0 - 1] - (c.dtdz * (er[0] - a.ero[i0 - 1]) + c.dtR * a.ezo[i0 - 1]);
+    d2 ez[2], er[2], bo[2];
+    l2 jj[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) b[k + 1] = bo[k] - (c.dtdz * (er[k + 1] - er[k]) + c.dtR * ez[k]);
-    double ern[4], ezn[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        ern[k] = (i0 + k >= 1) ? er[k] - c.dtdz * (b[k + 1] - b[k]) : er[0];
-        ezn[k] = (ez[k] + c.dtR * b[k + 1]) - c.c4 * (double)jj[k];
+    for (int p = 0; p < 2; ++p) {
+        const int64_t f = w0 + 128 * p + 2 * lane;
+        ez[p] = *(const d2 *)(a.ezo + f);
+        er[p] = *(const d2 *)(a.ero + f);
+        bo[p] = *(const d2 *)(a.bo + f);
+        jj[p] = *(const l2 *)(a.j + f);
     }
-    *(d2 *)(a.bn + i0) = d2{b[1], b[2]};
-    *(d2 *)(a.bn + i0 + 2) = d2{b[3], b[4]};
-    *(d2 *)(a.ern + i0) = d2{ern[0], ern[1]};
-    *(d2 *)(a.ern + i0 + 2) = d2{ern[2], ern[3]};
-    *(d2 *)(a.ezn + i0) = d2{ezn[0], ezn[1]};
-    *(d2 *)(a.ezn + i0 + 2) = d2{ezn[2], ezn[3]};
-    *(l2 *)(a.jnext + i0) = l2{0, 0};
-    *(l2 *)(a.jnext + i0 + 2) = l2{0, 0};
-    if (a.k32)
-        *(f4 *)(a.k32 + i0) = f4{(float)(c.qmdt * ezn[0]), (float)(c.qmdt * ezn[1]), (float)(c.qmdt * ezn[2]),
-                                 (float)(c.qmdt * ezn[3])};
-    if (i0 + 4 == N) a.ern[N] = a.ero[N] + c.tw * b[4];
-    return ezn[0];
+    // E_r at the face after each pair
+    double err[2];
+    err[0] = lane_next_f64(er[0].x);
+    err[1] = lane_next_f64(er[1].x);
+    const double er_next0 = readlane_f64(er[1].x, 0);
+    if (lane == 63) {
+        err[0] = er_next0;
+        err[1] = a.ero[w0 + 256];
+    }
+    double b1[2], b2[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        b1[p] = bo[p].x - (c.dtdz * (er[p].y - er[p].x) + c.dtR * ez[p].x);
+        b2[p] = bo[p].y - (c.dtdz * (err[p] - er[p].y) + c.dtR * ez[p].y);
+    }
+    // B_{i-1/2} of each pair's first face
+    double bl[2];
+    bl[0] = lane_prev_f64(b2[0]);
+    bl[1] = lane_prev_f64(b2[1]);
+    const double b_last0 = readlane_f64(b2[0], 63);
+    if (lane == 0) {
+        bl[1] = b_last0;
+        bl[0] = w0 >= 1 ? a.bo[w0 - 1] - (c.dtdz * (er[0].x - a.ero[w0 - 1]) + c.dtR * a.ezo[w0 - 1]) : 0.0;
+    }
+    double ez_first = 0.0;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int64_t f = w0 + 128 * p + 2 * lane;
+        const double ern1 = f >= 1 ? er[p].x - c.dtdz * (b1[p] - bl[p]) : er[p].x;
+        const double ern2 = er[p].y - c.dtdz * (b2[p] - b1[p]);
+        const double ezn1 = (ez[p].x + c.dtR * b1[p]) - c.c4 * (double)jj[p].x;
+        const double ezn2 = (ez[p].y + c.dtR * b2[p]) - c.c4 * (double)jj[p].y;
+        *(d2 *)(a.bn + f) = d2{b1[p], b2[p]};
+        *(d2 *)(a.ern + f) = d2{ern1, ern2};
+        *(d2 *)(a.ezn + f) = d2{ezn1, ezn2};
+        *(l2 *)(a.jnext + f) = l2{0, 0};
+        if (a.k32) *(f2 *)(a.k32 + f) = f2{(float)(c.qmdt * ezn1), (float)(c.qmdt * ezn2)};
+        if (p == 0) ez_first = ezn1;
+    }
+    if (lane == 63 && w0 + 256 == N) a.ern[N] = a.ero[N] + c.tw * b2[1];
+    return ez_first;
 }
 
-// The field update of the faces [tile*bs*4, (tile+1)*bs*4), FIELD_CPT consecutive
-// faces per thread (field_cells4_flat where it applies, else field_cell face by
-// face); the block of tile 0 then applies the SCLF rule.  Called by all threads
-// of a block of bs threads.
+// The field update of the faces [tile*bs*4, (tile+1)*bs*4), 256 faces per wave:
+// field_wave_pairs where the flat update applies to the wave's whole span, else
+// FIELD_CPT consecutive faces per thread with field_cell face by face; the
+// block of tile 0 then applies the SCLF rule.  Called by all threads of a block
+// of bs threads (a multiple of 64).
 __device__ __forceinline__ void field_tile(const Consts &c, const FieldArgs &a, int64_t tile, int bs)
 {
     __shared__ double s_ez0;
     __shared__ long long s_base, s_n;
     const int64_t N = c.N;
     const int64_t i0 = (tile * bs + threadIdx.x) * FIELD_CPT;
-    if (i0 < N) {
-        double ez;
-        if (!(c.flags & (PIC_FREEZE_FIELDS | PIC_GR_ALPHA)) && i0 + FIELD_CPT <= N) {
-            ez = field_cells4_flat(c, a, i0);
-        } else {
-            ez = field_cell(c, a, i0);
-            for (int k = 1; k < FIELD_CPT && i0 + k < N; ++k) field_cell(c, a, i0 + k);
-        }
+    const int64_t w0 = (tile * bs + (threadIdx.x & ~63)) * FIELD_CPT;   // the wave's first face (uniform)
+    static_assert(FIELD_CPT == 4, "a wave takes 256 faces");
+    if (!(c.flags & (PIC_FREEZE_FIELDS | PIC_GR_ALPHA)) && w0 + 256 <= N) {
+        const double ez = field_wave_pairs(c, a, w0);
+        if (w0 + 2 * (int)__lane_id() == 0) s_ez0 = ez;
+    } else if (i0 < N) {
+        const double ez = field_cell(c, a, i0);
+        for (int k = 1; k < FIELD_CPT && i0 + k < N; ++k) field_cell(c, a, i0 + k);
         if (i0 == 0) s_ez0 = ez;
     }
     if (tile != 0) return;

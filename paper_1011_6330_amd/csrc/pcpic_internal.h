@@ -82,7 +82,8 @@ constexpr int HI_GROUP = 1 << HI_GROUP_LOG2;
 // current buffers end a round in the parity they started it in).
 constexpr int64_t GRAPH_ROUND = 32;
 
-// Faces per thread of the field update (field_body.h).
+// Faces per thread of the field update (field_body.h): a wave takes 256 faces,
+// as two pairs per lane where the flat update applies.
 constexpr int FIELD_CPT = 4;
 
 constexpr int HI_FRAC_BITS = 24;
