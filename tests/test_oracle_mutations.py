@@ -84,6 +84,8 @@ GR = [
     ("E_r = Phi / R instead of Phi / (alpha R) at the start",
      "st->er[i] = (k.gr ? st->phi[i] / orc_alpha_node(c, k.dz, i) : st->phi[i]) / c->radius;",
      "st->er[i] = st->phi[i] / c->radius;"),
+    ("alpha at faces taken at the node below (half a cell off)",
+     "    return sqrt(orc_alpha2(c, ((double)i + 0.5) * dz));", "    return sqrt(orc_alpha2(c, (double)i * dz));"),
     ("alpha^2 on the wrong side in the Poisson diagonal",
      "double bd = k.gr ? -(2.0 + h2 / orc_alpha2(c, (double)i * k.dz)) : bdiag;",
      "double bd = k.gr ? -(2.0 + h2 * orc_alpha2(c, (double)i * k.dz)) : bdiag;"),
