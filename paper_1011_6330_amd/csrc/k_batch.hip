@@ -25,9 +25,9 @@ namespace pcpic {
 struct BatchArgs {
     const TubeDev *tubes;
     int n_tubes;
-    int64_t *live_pref;          // [n_tubes + 1] prefix of the push items holding particles (k_batch_plan)
+    int64_t *live_pref;          // [n_tubes + 1] prefix of the push items holding particles (k_batch_worklist)
     int64_t *live_counts;        // [2 n_tubes] slots of each tube's low and high stream (FP64: n, 0)
-    int32_t *push_map;           // push item -> tube (k_batch_map)
+    int32_t *push_map;           // push item -> tube (k_batch_worklist)
     const int64_t *field_pref;   // [n_tubes + 1] prefix of cell tiles
     const int32_t *field_map;    // cell tile -> tube
     int fb, jb, pb;              // field, current and particle buffer parities of the step
@@ -37,49 +37,45 @@ struct BatchArgs {
                                  // FP32-bulk low- and high-stream tiles
 };
 
-// The push work list of the coming step: per tube, the items that hold
-// particles (FP64: ceil(n / tile); FP32-bulk: the low stream's tiles, then the
-// high stream's), prefix-summed over the tubes into live_pref.  One block; it
-// runs between the field update (which appends injected particles) or the
-// sort and the next push, so the counts are final.  The push grid keeps its
-// capacity-sized upper bound and every block past live_pref[n_tubes] returns at
-// once: the idle blocks come last instead of between the tubes' tiles.
-__global__ __launch_bounds__(256) void k_batch_plan(BatchArgs b)
+// Push items of tube t that hold particles (FP64: ceil(n / tile); FP32-bulk:
+// the low stream's tiles, then the high stream's).
+__device__ __forceinline__ long long tube_items(const BatchArgs &b, int t, int64_t &n_lo, int64_t &n_hi)
 {
-    __shared__ long long s_wave[4];
-    __shared__ long long s_carry;
-    if (threadIdx.x == 0) {
-        s_carry = 0;
-        b.live_pref[0] = 0;
-    }
-    __syncthreads();
-    for (int t0 = 0; t0 < b.n_tubes; t0 += 256) {
-        const int t = t0 + (int)threadIdx.x;
-        long long items = 0;
-        if (t < b.n_tubes) {
-            const DevCounters *ctr = generic(b.tubes[t].ctr);
-            const int64_t n_lo = ctr->n_slots, n_hi = ctr->n_slots_hi;
-            items = (n_lo + b.tile_lo - 1) / b.tile_lo + (n_hi + b.tile_hi - 1) / b.tile_hi;
-            b.live_counts[2 * t] = n_lo;
-            b.live_counts[2 * t + 1] = n_hi;
-        }
-        const long long inc = block_scan_incl(items, s_wave);
-        const long long carry = s_carry;
-        if (t < b.n_tubes) b.live_pref[t + 1] = carry + inc;
-        __syncthreads();
-        if (threadIdx.x == 255) s_carry = carry + inc;
-        __syncthreads();
-    }
+    const DevCounters *ctr = generic(b.tubes[t].ctr);
+    n_lo = ctr->n_slots;
+    n_hi = ctr->n_slots_hi;
+    return (n_lo + b.tile_lo - 1) / b.tile_lo + (n_hi + b.tile_hi - 1) / b.tile_hi;
 }
 
-
-// The work list as a map: block t writes the tube's index over its items
-// [live_pref[t], live_pref[t+1]), so a push block finds its tube with one load.
-__global__ __launch_bounds__(256) void k_batch_map(BatchArgs b)
+// The push work list of the coming step, one block per tube t: the block sums
+// the items of the tubes below t from their counters (every block recounts
+// them; the counters sit in L2), writes the prefix live_pref[t + 1] and t's
+// slot counts, and t's index over its items [live_pref[t], live_pref[t + 1])
+// of push_map, so a push block finds its tube with one load.  It runs between
+// the field update (which appends injected particles) or the sort and the
+// next push, so the counts are final.  The push grid keeps its capacity-sized
+// upper bound and every block past live_pref[n_tubes] returns at once: the
+// idle blocks come last instead of between the tubes' tiles.
+__global__ __launch_bounds__(256) void k_batch_worklist(BatchArgs b)
 {
+    __shared__ long long s_wave[4];
     const int t = blockIdx.x;
-    const int64_t lo = b.live_pref[t], hi = b.live_pref[t + 1];
-    for (int64_t it = lo + threadIdx.x; it < hi; it += 256) b.push_map[it] = t;
+    int64_t n_lo, n_hi;
+    long long below = 0;
+    for (int s = (int)threadIdx.x; s < t; s += 256) below += tube_items(b, s, n_lo, n_hi);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
+    if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = below;
+    __syncthreads();
+    below = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    const long long mine = tube_items(b, t, n_lo, n_hi);
+    if (threadIdx.x == 0) {
+        if (t == 0) b.live_pref[0] = 0;
+        b.live_pref[t + 1] = below + mine;
+        b.live_counts[2 * t] = n_lo;
+        b.live_counts[2 * t + 1] = n_hi;
+    }
+    for (long long it = below + threadIdx.x; it < below + mine; it += 256) b.push_map[it] = t;
 }
 
 template <int BLOCK, int PPT, int NT, int F32>
@@ -412,8 +408,7 @@ hipError_t launch_batch_steps(pic_handle *h, int nsteps, bool hist_last, hipEven
         void *args[] = {&a};
         hipError_t e = ev ? hipEventRecord(ev[4 * s], h->stream) : hipSuccess;
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(256), 0, h->stream, a);
-        hipLaunchKernelGGL(k_batch_map, dim3((unsigned)h->tubes.size()), dim3(256), 0, h->stream, a);
+        hipLaunchKernelGGL(k_batch_worklist, dim3((unsigned)h->tubes.size()), dim3(256), 0, h->stream, a);
         if (ev && (e = hipEventRecord(ev[4 * s + 1], h->stream)) != hipSuccess) return e;
         e = hipLaunchKernel(kp, dim3(pgrid), dim3(h->batch_block), args, 0, h->stream);
         if (e != hipSuccess) return e;

@@ -329,7 +329,7 @@ struct pic_handle {
     pcpic::TubeDev *d_tubes = nullptr;
     int64_t *d_live_pref = nullptr;             // [n + 1] prefix of the push items holding particles
     int64_t *d_live_counts = nullptr;           // [2n] slots of each tube's two streams (FP64: n, 0)
-    int32_t *d_push_map = nullptr;              // push item -> tube of the coming step (k_batch_map)
+    int32_t *d_push_map = nullptr;              // push item -> tube of the coming step (k_batch_worklist)
     int64_t push_map_cap = 0;                   // entries of d_push_map (at least the push grid)
     int64_t *d_field_pref = nullptr, *d_sort_pref = nullptr, *d_key_pref = nullptr;
     int64_t *d_scan_pref = nullptr;             // [n + 1] prefix of 1024-key scan blocks
