@@ -40,10 +40,13 @@ def test_vacuum_stays_fixed():
     assert_state_equal(g, o, what="vacuum")
 
 
-@pytest.mark.parametrize("N,n", [(777, 3 * 1024 + 123), (1000, 1), (256, 0), (2048, 20000)])
+@pytest.mark.parametrize("N,n", [(777, 3 * 1024 + 123), (1000, 1), (256, 0), (2048, 20000), (257, 900), (511, 1700),
+                                 (255, 800)])
 def test_ragged_grid_and_tail_stepwise(N, n):
-    """Grids that are not a multiple of the 256-thread field block, particle counts
-    with a ragged last tile; J of every step bit-exact, frame-drag background."""
+    """Grids that are not a multiple of the 256 faces a wave of the field update takes
+    (a whole last span, one face past it, a span short by one, a grid shorter than
+    one span), particle counts with a ragged last tile; J of every step bit-exact,
+    frame-drag background."""
     cfg = dict(synth.preset("c1"), n_cells=N, length=N / 100.0, q_over_m=-40.0, ppc=6.0,
                rho_kind=synth.RHO_FRAME_DRAG, kappa=0.15, r_star=3.0, capacity=200000)
     x, u = synth.random_particles(N, n, seed=7)
