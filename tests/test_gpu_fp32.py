@@ -425,11 +425,13 @@ def _snap24(x):
 
 
 def test_fp32_high_stream_narrow_and_wide_groups():
-    """The high stream keeps its positions per group of 128 slots: relative to
+    """The high stream keeps its positions per group of 256 slots: relative to
     the group's lowest cell while its cells span at most 254 cells, absolute
-    otherwise.  A beam with a dense head (narrow groups) and a sparse tail (wide
-    groups), sorted every 16 steps, against the oracle per result; both forms
-    occur (the high stream read back in slot order, with no particle lost)."""
+    otherwise.  A beam with a dense head (narrow groups, one or two cells per
+    group) and a sparse tail (wide groups, whose waves flush their current after
+    their first slot pairs), sorted every 16 steps, against the oracle per
+    result; both forms occur (the high stream read back in slot order, with no
+    particle lost)."""
     N = 4096
     cfg = _warm_beam(N=N, gamma_fp64=1000.0, flags=1, capacity=200000, q_over_m=synth.q_over_m_for(10.0))
     rng = np.random.default_rng(11)
@@ -445,7 +447,7 @@ def test_fp32_high_stream_narrow_and_wide_groups():
     d = g.diagnostics(fields=False)
     assert d["n_alive"] == len(x) and d["n_slots_high"] == len(x)
     px, _ = g.read_particles()
-    spans = [np.ptp(np.floor(px[k:k + 128])) for k in range(0, len(px), 128)]
+    spans = [np.ptp(np.floor(px[k:k + 256])) for k in range(0, len(px), 256)]
     say("high-stream groups", len(spans), "narrow", sum(s <= 254 for s in spans), "wide", sum(s > 254 for s in spans))
     assert sum(s <= 254 for s in spans) > 100 and sum(s > 254 for s in spans) >= 2
     g.close()
