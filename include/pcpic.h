@@ -289,8 +289,8 @@ enum {
 /* Launch shape of the particle push: threads per block (64, 128, 256, 512) and
  * particle slots per thread.  FP64: 2, 4 (up to 256 threads) or 8 (up to 128
  * threads); a thread takes per_thread/2 pairs of consecutive slots, 2*block
- * slots apart.  FP32-bulk: 4 (4 consecutive low-stream slots per thread; a
- * high-stream block takes 2 per thread).  pic_init sets 128 x 2 (FP64) or
+ * slots apart.  FP32-bulk: 4 (4 consecutive low-stream slots per thread; in
+ * the high stream two pairs of slots 128 apart).  pic_init sets 128 x 2 (FP64) or
  * 128 x 4 (FP32-bulk), both with PIC_PUSH_NONTEMPORAL.
  * Results do not depend on the choice (integer deposition); the autotuner
  * picks the fastest.  Errors: PIC_EINVAL for an unsupported shape or flag. */
